@@ -1,0 +1,198 @@
+"""Benchmark: FGMRES + MGR time-to-1e-8 on one MI355X.
+
+Workload: the hybrid mimetic single-phase system on a 64^3 hex grid (cell
+pressures + face multipliers, 1,060,864 unknowns, 12,070,912 nonzeros,
+lognormal diagonal permeability with sigma = 2), one MGR level eliminating the
+cells exactly (F = cells, Jacobi), AMG V-cycle on the face system, FGMRES(50)
+to a relative residual of 1e-8.  One step = MGR/AMG setup + solve, with the
+matrix already resident in HBM.  The FP64 apply is the headline; the same steps
+with the FP32 MGR apply are reported beside it (FP32-vs-FP64 speedup).
+
+Prints one JSON line (stdout).  Progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def spmv_bytes(n, nnz, s=8):
+    """Algorithmic bytes of one CSR SpMV y = A x: values + column indices +
+    row pointers once, x once, y once."""
+    return nnz * (s + 4) + 4 * (n + 1) + 2 * n * 8
+
+
+def time_kernel(fn, stream, reps, flush_buf):
+    """Average duration of fn() (one kernel launch) with HIP events on `stream`,
+    flushing the 256 MB Infinity Cache with a 512 MB write between launches."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        flush_buf.fill_(1.0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    return statistics.mean(ts), ts
+
+
+def run_steps(P, s, vals, rhs, precision, steps, warmup):
+    import torch
+    solver = P.Solver(s["b"], s["rp"], s["ci"], vals, s["field"], s["levels"], precision=precision)
+    stream = torch.cuda.current_stream()
+    rec = []
+    X = info = None
+    for it in range(warmup + steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solver.setup(vals)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        X, [info] = solver.solve(rhs)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if it >= warmup:
+            rec.append((t1 - t0, t2 - t1, info.iterations, info.rel_res_true))
+        log(f"  fp{precision} step {it} ({'warmup' if it < warmup else 'timed'}): setup {t1 - t0:.4f} s, "
+            f"solve {t2 - t1:.4f} s, iters {info.iterations}, true rel res {info.rel_res_true:.2e}")
+    return solver, rec, X, info, stream
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--grid", type=int, default=64, help="grid size per axis of the mimetic system")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not part of "
+              f"this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2101_11649_amd as P
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    g = args.grid
+    log(f"generating hybrid mimetic {g}^3 ...")
+    s = W.hybrid_mimetic(g, g, g, seed=1)
+    n, nnz = s["n"], len(s["ci"])
+    log(f"n = {n}, nnz = {nnz}")
+    vals = torch.tensor(s["vals"], device="cuda")
+    rhs = torch.tensor(s["rhs"], device="cuda")
+    torch.cuda.synchronize()
+
+    # ---- FP64 apply (headline) and FP32 apply, K timed steps each
+    solver, rec64, X64, info64, stream = run_steps(P, s, vals, rhs, 64, args.steps, args.warmup)
+    solver32, rec32, X32, info32, _ = run_steps(P, s, vals, rhs, 32, args.steps, args.warmup)
+
+    tot64 = [a + b for a, b, _, _ in rec64]
+    tot32 = [a + b for a, b, _, _ in rec32]
+    value = statistics.mean(tot64)
+
+    # ---- roofline of the dominant kernel: the FGMRES CSR SpMV on A (FP64)
+    flush = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    xv = torch.randn(n, dtype=torch.float64, device="cuda")
+    yv = torch.empty_like(xv)
+    lib = P.lib()
+    import ctypes
+    fn = lambda: lib.mgr_matvec(solver._h, 0, ctypes.c_void_p(xv.data_ptr()), ctypes.c_void_p(yv.data_ptr()))
+    fn()
+    t_spmv, _ = time_kernel(fn, stream, 50, flush)
+    nbytes = spmv_bytes(n, nnz)
+    achieved = nbytes / t_spmv / 1e9
+
+    # per-apply FP64 vs FP32 (cache flushed between launches; an apply is several kernels)
+    v = torch.randn(n, dtype=torch.float64, device="cuda")
+    z = torch.empty_like(v)
+    ap64 = lambda: lib.mgr_apply(solver._h, ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(z.data_ptr()))
+    ap32 = lambda: lib.mgr_apply(solver32._h, ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(z.data_ptr()))
+    ap64(); ap32()
+    t_ap64, _ = time_kernel(ap64, stream, 20, flush)
+    t_ap32, _ = time_kernel(ap32, stream, 20, flush)
+
+    # ---- FP64 oracle on the machine's host cores (bounded sample: one full setup + solve of this workload)
+    cpu = None
+    x_err64 = x_err32 = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        log("oracle (CPU, single thread): one setup + solve of the same workload ...")
+        t0 = time.perf_counter()
+        om = O.MGR(s["b"], s["rp"], s["ci"], s["vals"], s["field"], [O.LevelOpts(**l) for l in s["levels"]])
+        t1 = time.perf_counter()
+        xo, io = om.solve(s["rhs"])
+        t2 = time.perf_counter()
+        log(f"  oracle setup {t1 - t0:.2f} s, solve {t2 - t1:.2f} s, iters {io.iterations}")
+        cpu = {"value": round(t2 - t0, 4), "unit": "s", "cores": 1, "kind": "oracle",
+               "sample": f"one full setup + FGMRES solve to 1e-8 of the {g}^3 mimetic system "
+                         f"(setup {t1 - t0:.2f} s, solve {t2 - t1:.2f} s, {io.iterations} iterations)"}
+        nx = np.linalg.norm(xo)
+        x_err64 = float(np.linalg.norm(X64.cpu().numpy() - xo) / nx)
+        x_err32 = float(np.linalg.norm(X32.cpu().numpy() - xo) / nx)
+
+    out = {
+        "metric": "FGMRES+MGR time-to-1e-8 (s), HBM GB/s; FP32-vs-FP64 apply speedup",
+        "value": round(value, 6),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * value, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"hybrid_mimetic_consistent_{g}x{g}x{g}", "n": n, "nnz": nnz,
+                   "mgr": "1 level, F = cells (Jacobi), C = faces -> AMG V(1,1)", "rtol": 1e-8,
+                   "restart": 50},
+        "setup_s": round(statistics.mean(a for a, _, _, _ in rec64), 6),
+        "solve_s": round(statistics.mean(b for _, b, _, _ in rec64), 6),
+        "iterations": rec64[-1][2],
+        "rel_res_true": rec64[-1][3],
+        "x_rel_err_vs_oracle": x_err64,
+        "fp32_apply": {
+            "time_to_tol_s": round(statistics.mean(tot32), 6),
+            "setup_s": round(statistics.mean(a for a, _, _, _ in rec32), 6),
+            "solve_s": round(statistics.mean(b for _, b, _, _ in rec32), 6),
+            "iterations": rec32[-1][2],
+            "rel_res_true": rec32[-1][3],
+            "x_rel_err_vs_oracle": x_err32,
+            "speedup_time_to_tol": round(value / statistics.mean(tot32), 4),
+            "apply_ms_fp64": round(1e3 * t_ap64, 4),
+            "apply_ms_fp32": round(1e3 * t_ap32, 4),
+            "speedup_per_apply": round(t_ap64 / t_ap32, 4),
+        },
+        "roofline": {"kernel": "k_spmv<double> (FGMRES matvec, CSR, FP64)", "bound": "hbm",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": nbytes, "avg_launch_us": round(1e6 * t_spmv, 2)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    solver.close()
+    solver32.close()
+
+
+if __name__ == "__main__":
+    main()

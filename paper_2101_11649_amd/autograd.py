@@ -1,0 +1,40 @@
+"""torch.autograd.Function around solve(A, b) with an adjoint backward.
+
+Forward: X = A^{-1} B by MGR-preconditioned FGMRES (optionally with the FP32
+MGR apply).  Backward, for an upstream gradient G = dL/dX: Lambda = A^{-T} G by
+FGMRES on A^T right-preconditioned with the exact transpose M^{-T} of the MGR
+cycle; then dL/dB = Lambda and dL/dA_ij = -sum_k Lambda_k[i] X_k[j] on A's
+sparsity pattern (the adjoint of a linear solve).  Both steps run in the HIP
+library; this module only passes tensors through.
+"""
+from __future__ import annotations
+
+import torch
+
+
+class MGRSolve(torch.autograd.Function):
+    """X = MGRSolve.apply(values, B, structure) with structure a dict of
+    b, rp, ci, field, levels and solver keyword options (precision, rtol, ...).
+    values: (nnzb*b*b,) float64 CUDA tensor; B: (n,) or (nrhs, n)."""
+
+    @staticmethod
+    def forward(ctx, values, B, structure):
+        from . import Solver
+        opts = dict(structure.get("opts", {}))
+        solver = Solver(structure["b"], structure["rp"], structure["ci"], values.detach(), structure["field"],
+                        structure["levels"], **opts)
+        X, infos = solver.solve(B.detach())
+        ctx.solver = solver
+        ctx.infos = infos
+        ctx.save_for_backward(X)
+        return X
+
+    @staticmethod
+    def backward(ctx, G):
+        (X,) = ctx.saved_tensors
+        solver = ctx.solver
+        lam, infos_t = solver.solve(G.contiguous(), transpose=True)
+        ctx.infos_adjoint = infos_t
+        grad_values = solver.grad_values(lam, X)
+        solver.close()
+        return grad_values, lam, None

@@ -1,0 +1,85 @@
+// apply.hpp -- launchers of the solve-phase kernels (k_apply.hip).
+#pragma once
+
+#include "common.hpp"
+
+namespace mgr {
+
+// Number of per-block partial sums used by the Krylov reductions (a fixed grid
+// so that every reduction is formed in the same order on every call).
+constexpr int KRYLOV_PARTS = 2048;
+
+// Read-only view of a CSR operator in value type T with its SpMV group size
+// (lanes per row, chosen from the average row length).
+template <typename T>
+struct SpOp {
+    int nr = 0, nc = 0;
+    long nnz = 0;
+    const int* rp = nullptr;
+    const int* ci = nullptr;
+    const T* v = nullptr;
+    int group = 1;
+};
+
+int spmv_group(int nr, long nnz);
+
+template <typename T>
+inline SpOp<T> view(const DCsr& A);
+template <>
+inline SpOp<double> view<double>(const DCsr& A) {
+    SpOp<double> o;
+    o.nr = A.nr; o.nc = A.nc; o.nnz = A.nnz; o.rp = A.rp.p; o.ci = A.ci.p; o.v = A.v.p;
+    o.group = spmv_group(A.nr, A.nnz);
+    return o;
+}
+template <>
+inline SpOp<float> view<float>(const DCsr& A) {
+    SpOp<float> o;
+    o.nr = A.nr; o.nc = A.nc; o.nnz = A.nnz; o.rp = A.rp.p; o.ci = A.ci.p; o.v = A.vf.p;
+    o.group = spmv_group(A.nr, A.nnz);
+    return o;
+}
+
+// y = alpha * A [x | x2] + beta * w: columns >= split read x2[c - split];
+// pass x2 = nullptr and split = INT_MAX for a single source, w = nullptr for beta = 0.
+template <typename MT, typename XT, typename X2T, typename YT, typename WT>
+void spmv(const SpOp<MT>& A, const XT* x, const X2T* x2, int split, const WT* w, YT* y, MT alpha, MT beta,
+          hipStream_t s);
+// y = x + dinv .* (b - A x)  (out of place)
+template <typename T>
+void jacobi_sweep(const SpOp<T>& A, const T* dinv, const T* b, const T* x, T* y, hipStream_t s);
+// x = dinv .* b ; r = b - A x
+template <typename T>
+void presmooth(const SpOp<T>& A, const T* dinv, const T* b, T* x, T* r, hipStream_t s);
+// block-CSR y = alpha A x + beta w (FP64)
+void bsr_spmv(int bsize, int nbr, const int* rp, const int* ci, const double* v, long nnzb, const double* x,
+              const double* w, double* y, double alpha, double beta, hipStream_t s);
+template <typename T, typename XT>
+void dense_gemv(int n, const T* m, const XT* x, T* y, hipStream_t s);
+template <typename S, typename D>
+void gather(int n, const int* map, const S* src, D* dst, hipStream_t s);
+template <typename S, typename D>
+void scatter(int n, const int* map, const S* src, D* dst, hipStream_t s);
+template <typename T>
+void axpby(long n, T a, const T* x, T b, T* y, hipStream_t s);
+template <typename T>
+void mul(long n, const T* d, const T* x, T* y, T w, hipStream_t s);
+template <typename T>
+void addmul(long n, const T* d, const T* x, T* y, T w, hipStream_t s);
+template <typename S, typename D>
+void copy(long n, const S* src, D* dst, hipStream_t s);
+template <typename T>
+void set(long n, T* dst, T v, hipStream_t s);
+void scale(long n, double a, double* x, hipStream_t s);
+
+int krylov_parts(long n);
+// out[i] = <V_i, w> for i < nvec (V column-major with leading dimension ldv);
+// part needs nvec * KRYLOV_PARTS doubles.
+void mdot(long n, const double* V, long ldv, int nvec, const double* w, double* part, double* out, hipStream_t s);
+// w -= hscale * sum_i h[i] V_i; if norm2_out, *norm2_out = ||w_new||^2.
+void maxpy(long n, const double* V, long ldv, int nvec, const double* h, double hscale, double* w, double* part,
+           double* norm2_out, hipStream_t s);
+void grad_values(int b, int nbr, const int* rp, const int* ci, long nnzb, int nrhs, const double* lam,
+                 const double* x, double* dv, hipStream_t s);
+
+}  // namespace mgr

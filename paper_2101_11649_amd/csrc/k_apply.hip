@@ -1,0 +1,502 @@
+// k_apply.hip -- solve-phase kernels for gfx950: CSR / block-CSR SpMV variants
+// (FGMRES matvec, MGR restriction / interpolation, AMG residual, transfer and
+// L1-Jacobi smoothing), the coarsest dense apply, the FGMRES vector kernels
+// (multi-dot, multi-axpy, norms) and the adjoint gradient.
+//
+// Every solve-phase kernel is bound by HBM bandwidth (about 0.1-0.3 flop per
+// byte), so the designs favour coalesced streaming of the matrix arrays,
+// sub-wavefront row groups sized to the row length and fused vector updates;
+// there is no dense contraction here that the matrix cores could speed up.
+#include <climits>
+
+#include "apply.hpp"
+
+namespace mgr {
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int WAVE = 64;
+
+template <typename T>
+__device__ inline T group_sum(T v, int G) {
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+    return v;
+}
+
+// Sum over the row with G lanes of the group: lanes take entries lane, lane+G, ...
+// The x operand is either one vector, or two concatenated ones ([x | x2] with
+// column c >= split reading x2[c - split]).
+template <typename MT, typename XT, typename X2T, int G>
+__device__ inline MT row_dot(int p0, int p1, int lane, const int* __restrict__ ci, const MT* __restrict__ v,
+                             const XT* __restrict__ x, const X2T* __restrict__ x2, int split) {
+    MT s = MT(0);
+    for (int p = p0 + lane; p < p1; p += G) {
+        int c = ci[p];
+        MT xv = (c < split) ? (MT)x[c] : (MT)x2[c - split];
+        s += v[p] * xv;
+    }
+    return group_sum<MT>(s, G);
+}
+
+// y = alpha * A [x | x2] + beta * w   (w may be null; w may alias y: each row
+// reads w[row] before writing y[row])
+template <typename MT, typename XT, typename X2T, typename YT, typename WT, int G>
+__global__ __launch_bounds__(TPB) void k_spmv(int nr, const int* __restrict__ rp, const int* __restrict__ ci,
+                                              const MT* __restrict__ v, const XT* __restrict__ x,
+                                              const X2T* __restrict__ x2, int split, const WT* w, YT* y,
+                                              MT alpha, MT beta) {
+    long gid = (long)blockIdx.x * TPB + threadIdx.x;
+    int row = (int)(gid / G), lane = (int)(gid % G);
+    if (row >= nr) return;
+    MT s = row_dot<MT, XT, X2T, G>(rp[row], rp[row + 1], lane, ci, v, x, x2, split);
+    if (lane == 0) {
+        MT r = alpha * s;
+        if (w) r += beta * (MT)w[row];
+        y[row] = (YT)r;
+    }
+}
+
+// One L1-Jacobi sweep, out of place: y = x + dinv .* (b - A x).
+template <typename T, int G>
+__global__ __launch_bounds__(TPB) void k_jacobi(int nr, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                const T* __restrict__ v, const T* __restrict__ dinv,
+                                                const T* __restrict__ b, const T* __restrict__ x,
+                                                T* __restrict__ y) {
+    long gid = (long)blockIdx.x * TPB + threadIdx.x;
+    int row = (int)(gid / G), lane = (int)(gid % G);
+    if (row >= nr) return;
+    T s = row_dot<T, T, T, G>(rp[row], rp[row + 1], lane, ci, v, x, x, INT_MAX);
+    if (lane == 0) y[row] = x[row] + dinv[row] * (b[row] - s);
+}
+
+// First L1-Jacobi sweep from zero fused with the residual:
+// x = dinv .* b,  r = b - A x  (x_j recomputed on the fly from b_j and dinv_j).
+template <typename T, int G>
+__global__ __launch_bounds__(TPB) void k_presmooth(int nr, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                   const T* __restrict__ v, const T* __restrict__ dinv,
+                                                   const T* __restrict__ b, T* __restrict__ x,
+                                                   T* __restrict__ r) {
+    long gid = (long)blockIdx.x * TPB + threadIdx.x;
+    int row = (int)(gid / G), lane = (int)(gid % G);
+    if (row >= nr) return;
+    T s = T(0);
+    for (int p = rp[row] + lane; p < rp[row + 1]; p += G) {
+        int c = ci[p];
+        s += v[p] * (dinv[c] * b[c]);
+    }
+    s = group_sum<T>(s, G);
+    if (lane == 0) {
+        T bi = b[row];
+        x[row] = dinv[row] * bi;
+        r[row] = bi - s;
+    }
+}
+
+// Block-CSR SpMV, b x b row-major blocks, G lanes per block row:
+// y = alpha * A x + beta * w.
+template <int B, int G>
+__global__ __launch_bounds__(TPB) void k_bsr_spmv(int nbr, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                  const double* __restrict__ v, const double* __restrict__ x,
+                                                  const double* w, double* y, double alpha, double beta) {
+    long gid = (long)blockIdx.x * TPB + threadIdx.x;
+    int I = (int)(gid / G), lane = (int)(gid % G);
+    if (I >= nbr) return;
+    double s[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) s[r] = 0.0;
+    for (int p = rp[I] + lane; p < rp[I + 1]; p += G) {
+        int J = ci[p];
+        const double* blk = v + (long)p * B * B;
+        double xv[B];
+#pragma unroll
+        for (int c = 0; c < B; ++c) xv[c] = x[(long)J * B + c];
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int c = 0; c < B; ++c) s[r] += blk[r * B + c] * xv[c];
+    }
+#pragma unroll
+    for (int r = 0; r < B; ++r) s[r] = group_sum<double>(s[r], G);
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+        if (r % G == lane) {
+            long i = (long)I * B + r;
+            double o = alpha * s[r];
+            if (w) o += beta * w[i];
+            y[i] = o;
+        }
+}
+
+// Coarsest level: y = Minv x with a dense n x n inverse, one wavefront per row.
+template <typename T, typename XT>
+__global__ __launch_bounds__(TPB) void k_dense_gemv(int n, const T* __restrict__ m, const XT* __restrict__ x,
+                                                    T* __restrict__ y) {
+    int row = blockIdx.x * (TPB / WAVE) + threadIdx.x / WAVE;
+    int lane = threadIdx.x & (WAVE - 1);
+    if (row >= n) return;
+    T s = T(0);
+    for (int j = lane; j < n; j += WAVE) s += m[(long)row * n + j] * (T)x[j];
+    s = group_sum<T>(s, WAVE);
+    if (lane == 0) y[row] = s;
+}
+
+template <typename S, typename D>
+__global__ void k_gather(int n, const int* __restrict__ map, const S* __restrict__ src, D* __restrict__ dst) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (D)src[map[i]];
+}
+
+template <typename S, typename D>
+__global__ void k_scatter(int n, const int* __restrict__ map, const S* __restrict__ src, D* __restrict__ dst) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[map[i]] = (D)src[i];
+}
+
+template <typename T>
+__global__ void k_axpby(long n, T a, const T* __restrict__ x, T b, T* __restrict__ y) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (b == T(0)) ? a * x[i] : a * x[i] + b * y[i];
+}
+
+template <typename T>
+__global__ void k_mul(long n, const T* __restrict__ d, const T* __restrict__ x, T* __restrict__ y, T w) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = w * (d[i] * x[i]);
+}
+
+template <typename T>
+__global__ void k_addmul(long n, const T* __restrict__ d, const T* __restrict__ x, T* __restrict__ y, T w) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += w * (d[i] * x[i]);
+}
+
+template <typename S, typename D>
+__global__ void k_copy(long n, const S* __restrict__ s, D* __restrict__ d) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = (D)s[i];
+}
+
+template <typename T>
+__global__ void k_set(long n, T* __restrict__ d, T v) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = v;
+}
+
+__global__ void k_scale(long n, double a, double* __restrict__ x) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] *= a;
+}
+
+// ---------------------------------------------------------------- Krylov reductions
+template <int NB>
+__device__ inline void block_reduce_write(double (&acc)[NB], double* __restrict__ out, int stride) {
+    __shared__ double sh[NB][TPB / WAVE];
+    int wid = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+        double v = group_sum<double>(acc[t], WAVE);
+        if (lane == 0) sh[t][wid] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < NB) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < TPB / WAVE; ++q) s += sh[threadIdx.x][q];
+        out[(long)threadIdx.x * stride] = s;
+    }
+}
+
+// part[(i0+t) * gridDim.x + block] = partial of <V_{i0+t}, w>
+template <int NB>
+__global__ __launch_bounds__(TPB) void k_mdot(long n, const double* __restrict__ V, long ldv, int nvec,
+                                              const double* __restrict__ w, double* __restrict__ part) {
+    int i0 = blockIdx.y * NB;
+    double acc[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) acc[t] = 0.0;
+    long stride = (long)gridDim.x * TPB;
+    for (long r = (long)blockIdx.x * TPB + threadIdx.x; r < n; r += stride) {
+        double wr = w[r];
+#pragma unroll
+        for (int t = 0; t < NB; ++t)
+            if (i0 + t < nvec) acc[t] += V[(long)(i0 + t) * ldv + r] * wr;
+    }
+    __shared__ double sh[NB][TPB / WAVE];
+    int wid = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+        double v = group_sum<double>(acc[t], WAVE);
+        if (lane == 0) sh[t][wid] = v;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < NB && i0 + (int)threadIdx.x < nvec) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < TPB / WAVE; ++q) s += sh[threadIdx.x][q];
+        part[(long)(i0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// out[i] = sum over the nparts partials of vector i, in a fixed tree order.
+__global__ __launch_bounds__(TPB) void k_reduce_parts(int nparts, const double* __restrict__ part,
+                                                      double* __restrict__ out) {
+    __shared__ double sh[TPB];
+    const double* p = part + (long)blockIdx.x * nparts;
+    double s = 0.0;
+    for (int q = threadIdx.x; q < nparts; q += TPB) s += p[q];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = TPB / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+}
+
+// w -= sum_i h[i] V_i  (h on the device); optionally partial sums of w_new^2.
+__global__ __launch_bounds__(TPB) void k_maxpy(long n, const double* __restrict__ V, long ldv, int nvec,
+                                               const double* __restrict__ h, double hscale, double* __restrict__ w,
+                                               double* __restrict__ normpart) {
+    __shared__ double hs[64];
+    if ((int)threadIdx.x < nvec) hs[threadIdx.x] = hscale * h[threadIdx.x];
+    __syncthreads();
+    double acc = 0.0;
+    long stride = (long)gridDim.x * TPB;
+    for (long r = (long)blockIdx.x * TPB + threadIdx.x; r < n; r += stride) {
+        double s = 0.0;
+        for (int i = 0; i < nvec; ++i) s += hs[i] * V[(long)i * ldv + r];
+        double wn = w[r] - s;
+        w[r] = wn;
+        acc += wn * wn;
+    }
+    if (normpart) {
+        double a[1] = {acc};
+        block_reduce_write<1>(a, normpart + blockIdx.x, 0);
+    }
+}
+
+// Adjoint gradient on the block pattern: dv[p,r,c] = -sum_k lam_k[I b + r] x_k[J b + c].
+__global__ void k_grad(long nnzb, int b, int nbr, const int* __restrict__ rp, const int* __restrict__ ci, long n,
+                       int nrhs, const double* __restrict__ lam, const double* __restrict__ x,
+                       double* __restrict__ dv) {
+    long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nnzb) return;
+    int lo = 0, hi = nbr;  // find I with rp[I] <= p < rp[I+1]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (rp[mid] <= p) lo = mid;
+        else hi = mid;
+    }
+    int I = lo, J = ci[p];
+    for (int r = 0; r < b; ++r)
+        for (int c = 0; c < b; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < nrhs; ++k) s += lam[k * n + (long)I * b + r] * x[k * n + (long)J * b + c];
+            dv[p * b * b + r * b + c] = -s;
+        }
+}
+
+inline int nblk(long n, int t = TPB) { return (int)((n + t - 1) / t); }
+
+int pick_group(double avg) {
+    if (avg <= 1.5) return 1;
+    if (avg <= 3.0) return 2;
+    if (avg <= 6.0) return 4;
+    if (avg <= 14.0) return 8;
+    if (avg <= 28.0) return 16;
+    if (avg <= 56.0) return 32;
+    return 64;
+}
+
+}  // namespace
+
+int spmv_group(int nr, long nnz) { return pick_group(nr > 0 ? (double)nnz / nr : 1.0); }
+
+#define MGR_DISPATCH_G(G, ...)                          \
+    switch (G) {                                        \
+        case 1: { constexpr int GG = 1; __VA_ARGS__; } break;   \
+        case 2: { constexpr int GG = 2; __VA_ARGS__; } break;   \
+        case 4: { constexpr int GG = 4; __VA_ARGS__; } break;   \
+        case 8: { constexpr int GG = 8; __VA_ARGS__; } break;   \
+        case 16: { constexpr int GG = 16; __VA_ARGS__; } break; \
+        case 32: { constexpr int GG = 32; __VA_ARGS__; } break; \
+        default: { constexpr int GG = 64; __VA_ARGS__; } break; \
+    }
+
+template <typename MT, typename XT, typename X2T, typename YT, typename WT>
+void spmv(const SpOp<MT>& A, const XT* x, const X2T* x2, int split, const WT* w, YT* y, MT alpha, MT beta,
+          hipStream_t s) {
+    if (A.nr <= 0) return;
+    int G = A.group;
+    long threads = (long)A.nr * G;
+    MGR_DISPATCH_G(G, (k_spmv<MT, XT, X2T, YT, WT, GG><<<nblk(threads), TPB, 0, s>>>(
+                              A.nr, A.rp, A.ci, A.v, x, x2, split, w, y, alpha, beta)));
+    MGR_LAUNCH_CHECK();
+}
+
+template <typename T>
+void jacobi_sweep(const SpOp<T>& A, const T* dinv, const T* b, const T* x, T* y, hipStream_t s) {
+    if (A.nr <= 0) return;
+    int G = A.group;
+    long threads = (long)A.nr * G;
+    MGR_DISPATCH_G(G, (k_jacobi<T, GG><<<nblk(threads), TPB, 0, s>>>(A.nr, A.rp, A.ci, A.v, dinv, b, x, y)));
+    MGR_LAUNCH_CHECK();
+}
+
+template <typename T>
+void presmooth(const SpOp<T>& A, const T* dinv, const T* b, T* x, T* r, hipStream_t s) {
+    if (A.nr <= 0) return;
+    int G = A.group;
+    long threads = (long)A.nr * G;
+    MGR_DISPATCH_G(G, (k_presmooth<T, GG><<<nblk(threads), TPB, 0, s>>>(A.nr, A.rp, A.ci, A.v, dinv, b, x, r)));
+    MGR_LAUNCH_CHECK();
+}
+
+void bsr_spmv(int bsize, int nbr, const int* rp, const int* ci, const double* v, long nnzb, const double* x,
+              const double* w, double* y, double alpha, double beta, hipStream_t s) {
+    if (nbr <= 0) return;
+    int G = pick_group((double)nnzb / nbr);
+    long threads = (long)nbr * G;
+    switch (bsize) {
+        case 2: MGR_DISPATCH_G(G, (k_bsr_spmv<2, GG><<<nblk(threads), TPB, 0, s>>>(nbr, rp, ci, v, x, w, y, alpha, beta))); break;
+        case 3: MGR_DISPATCH_G(G, (k_bsr_spmv<3, GG><<<nblk(threads), TPB, 0, s>>>(nbr, rp, ci, v, x, w, y, alpha, beta))); break;
+        case 4: MGR_DISPATCH_G(G, (k_bsr_spmv<4, GG><<<nblk(threads), TPB, 0, s>>>(nbr, rp, ci, v, x, w, y, alpha, beta))); break;
+        default: throw Error(-6, "block size not supported by the block SpMV");
+    }
+    MGR_LAUNCH_CHECK();
+}
+
+template <typename T, typename XT>
+void dense_gemv(int n, const T* m, const XT* x, T* y, hipStream_t s) {
+    if (n <= 0) return;
+    k_dense_gemv<T, XT><<<ceil_div(n, TPB / WAVE), TPB, 0, s>>>(n, m, x, y);
+    MGR_LAUNCH_CHECK();
+}
+
+template <typename S, typename D>
+void gather(int n, const int* map, const S* src, D* dst, hipStream_t s) {
+    if (n <= 0) return;
+    k_gather<S, D><<<nblk(n), TPB, 0, s>>>(n, map, src, dst);
+    MGR_LAUNCH_CHECK();
+}
+
+template <typename S, typename D>
+void scatter(int n, const int* map, const S* src, D* dst, hipStream_t s) {
+    if (n <= 0) return;
+    k_scatter<S, D><<<nblk(n), TPB, 0, s>>>(n, map, src, dst);
+    MGR_LAUNCH_CHECK();
+}
+
+template <typename T>
+void axpby(long n, T a, const T* x, T b, T* y, hipStream_t s) {
+    if (n <= 0) return;
+    k_axpby<T><<<nblk(n), TPB, 0, s>>>(n, a, x, b, y);
+    MGR_LAUNCH_CHECK();
+}
+
+template <typename T>
+void mul(long n, const T* d, const T* x, T* y, T w, hipStream_t s) {
+    if (n <= 0) return;
+    k_mul<T><<<nblk(n), TPB, 0, s>>>(n, d, x, y, w);
+    MGR_LAUNCH_CHECK();
+}
+
+template <typename T>
+void addmul(long n, const T* d, const T* x, T* y, T w, hipStream_t s) {
+    if (n <= 0) return;
+    k_addmul<T><<<nblk(n), TPB, 0, s>>>(n, d, x, y, w);
+    MGR_LAUNCH_CHECK();
+}
+
+template <typename S, typename D>
+void copy(long n, const S* src, D* dst, hipStream_t s) {
+    if (n <= 0) return;
+    k_copy<S, D><<<nblk(n), TPB, 0, s>>>(n, src, dst);
+    MGR_LAUNCH_CHECK();
+}
+
+template <typename T>
+void set(long n, T* dst, T v, hipStream_t s) {
+    if (n <= 0) return;
+    k_set<T><<<nblk(n), TPB, 0, s>>>(n, dst, v);
+    MGR_LAUNCH_CHECK();
+}
+
+void scale(long n, double a, double* x, hipStream_t s) {
+    if (n <= 0) return;
+    k_scale<<<nblk(n), TPB, 0, s>>>(n, a, x);
+    MGR_LAUNCH_CHECK();
+}
+
+int krylov_parts(long n) {
+    long b = (n + TPB - 1) / TPB;
+    return (int)(b < KRYLOV_PARTS ? (b > 0 ? b : 1) : KRYLOV_PARTS);
+}
+
+void mdot(long n, const double* V, long ldv, int nvec, const double* w, double* part, double* out, hipStream_t s) {
+    if (nvec <= 0) return;
+    int np = krylov_parts(n);
+    constexpr int NB = 8;
+    dim3 grid(np, ceil_div(nvec, NB));
+    k_mdot<NB><<<grid, TPB, 0, s>>>(n, V, ldv, nvec, w, part);
+    k_reduce_parts<<<nvec, TPB, 0, s>>>(np, part, out);
+    MGR_LAUNCH_CHECK();
+}
+
+void maxpy(long n, const double* V, long ldv, int nvec, const double* h, double hscale, double* w, double* part,
+           double* norm2_out, hipStream_t s) {
+    if (nvec > 64) throw Error(-1, "maxpy: at most 64 vectors");
+    int np = krylov_parts(n);
+    if (nvec <= 0 && !norm2_out) return;
+    k_maxpy<<<np, TPB, 0, s>>>(n, V, ldv, nvec, h, hscale, w, norm2_out ? part : nullptr);
+    if (norm2_out) k_reduce_parts<<<1, TPB, 0, s>>>(np, part, norm2_out);
+    MGR_LAUNCH_CHECK();
+}
+
+void grad_values(int b, int nbr, const int* rp, const int* ci, long nnzb, int nrhs, const double* lam,
+                 const double* x, double* dv, hipStream_t s) {
+    if (nnzb <= 0) return;
+    k_grad<<<nblk(nnzb), TPB, 0, s>>>(nnzb, b, nbr, rp, ci, (long)nbr * b, nrhs, lam, x, dv);
+    MGR_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- explicit instantiations
+#define INST_SPMV(MT, XT, X2T, YT, WT) \
+    template void spmv<MT, XT, X2T, YT, WT>(const SpOp<MT>&, const XT*, const X2T*, int, const WT*, YT*, MT, MT, hipStream_t);
+INST_SPMV(double, double, double, double, double)
+INST_SPMV(float, float, float, float, float)
+INST_SPMV(float, double, double, float, float)
+INST_SPMV(float, double, double, float, double)
+INST_SPMV(float, float, double, double, double)
+INST_SPMV(float, float, double, double, float)
+INST_SPMV(float, float, float, double, double)
+INST_SPMV(double, double, double, float, float)
+
+template void jacobi_sweep<double>(const SpOp<double>&, const double*, const double*, const double*, double*, hipStream_t);
+template void jacobi_sweep<float>(const SpOp<float>&, const float*, const float*, const float*, float*, hipStream_t);
+template void presmooth<double>(const SpOp<double>&, const double*, const double*, double*, double*, hipStream_t);
+template void presmooth<float>(const SpOp<float>&, const float*, const float*, float*, float*, hipStream_t);
+template void dense_gemv<double, double>(int, const double*, const double*, double*, hipStream_t);
+template void dense_gemv<float, float>(int, const float*, const float*, float*, hipStream_t);
+template void dense_gemv<float, double>(int, const float*, const double*, float*, hipStream_t);
+template void gather<double, double>(int, const int*, const double*, double*, hipStream_t);
+template void gather<double, float>(int, const int*, const double*, float*, hipStream_t);
+template void gather<float, float>(int, const int*, const float*, float*, hipStream_t);
+template void scatter<double, double>(int, const int*, const double*, double*, hipStream_t);
+template void scatter<float, double>(int, const int*, const float*, double*, hipStream_t);
+template void scatter<float, float>(int, const int*, const float*, float*, hipStream_t);
+template void axpby<double>(long, double, const double*, double, double*, hipStream_t);
+template void axpby<float>(long, float, const float*, float, float*, hipStream_t);
+template void mul<double>(long, const double*, const double*, double*, double, hipStream_t);
+template void mul<float>(long, const float*, const float*, float*, float, hipStream_t);
+template void addmul<double>(long, const double*, const double*, double*, double, hipStream_t);
+template void addmul<float>(long, const float*, const float*, float*, float, hipStream_t);
+template void copy<double, double>(long, const double*, double*, hipStream_t);
+template void copy<double, float>(long, const double*, float*, hipStream_t);
+template void copy<float, double>(long, const float*, double*, hipStream_t);
+template void copy<float, float>(long, const float*, float*, hipStream_t);
+template void set<double>(long, double*, double, hipStream_t);
+template void set<float>(long, float*, float, hipStream_t);
+
+}  // namespace mgr

@@ -1,0 +1,1074 @@
+// k_setup.hip -- setup kernels for gfx950: block extraction by C/F split,
+// F-relaxation operators, SpGEMM / sparse add / transpose (Petrov-Galerkin
+// coarse operators of MGR and Galerkin products of AMG), PMIS coarsening,
+// direct interpolation and the coarsest dense inverse.
+//
+// Built with -ffp-contract=off: the coarse values feed the strength-of-
+// connection test of the next AMG level, so every sum is formed exactly in the
+// order written (a separate multiply and add, no fused multiply-add).
+#include <climits>
+
+#include "kernels.hpp"
+
+namespace mgr {
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int WAVE = 64;
+constexpr int SCAN_T = 256;
+constexpr int SCAN_I = 8;
+constexpr int SCAN_B = SCAN_T * SCAN_I;
+
+inline int nblk(long n, int t = TPB) { return (int)((n + t - 1) / t); }
+
+__device__ inline int wave_min_int(int v) {
+    for (int off = WAVE / 2; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, WAVE));
+    return v;
+}
+
+__device__ inline void set_flag(int* flag, int code) { atomicMax(flag, code); }
+
+// ------------------------------------------------------------------ scan
+__global__ void k_scan_reduce(const int* __restrict__ in, int n, long long* __restrict__ bsum) {
+    __shared__ long long sh[SCAN_T];
+    long long s = 0;
+    int base = blockIdx.x * SCAN_B;
+    for (int t = 0; t < SCAN_I; ++t) {
+        int i = base + t * SCAN_T + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = SCAN_T / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = sh[0];
+}
+
+__global__ void k_scan_blocks(long long* __restrict__ bsum, int nb, int* __restrict__ out_last,
+                              long long* __restrict__ total) {
+    __shared__ long long sh[1024];
+    int chunk = (nb + 1023) / 1024;
+    int b0 = threadIdx.x * chunk, b1 = min(nb, b0 + chunk);
+    long long s = 0;
+    for (int b = b0; b < b1; ++b) s += bsum[b];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        long long t = ((int)threadIdx.x >= off) ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    long long run = threadIdx.x ? sh[threadIdx.x - 1] : 0;
+    for (int b = b0; b < b1; ++b) {
+        long long v = bsum[b];
+        bsum[b] = run;
+        run += v;
+    }
+    if (threadIdx.x == 1023) {
+        *total = sh[1023];
+        *out_last = (sh[1023] > INT_MAX) ? INT_MAX : (int)sh[1023];
+    }
+}
+
+__global__ void k_scan_apply(const int* __restrict__ in, int n, const long long* __restrict__ boff,
+                             int* __restrict__ out) {
+    __shared__ int sh[SCAN_T];
+    int base = blockIdx.x * SCAN_B + threadIdx.x * SCAN_I;
+    int v[SCAN_I];
+    int s = 0;
+    for (int t = 0; t < SCAN_I; ++t) {
+        int i = base + t;
+        v[t] = (i < n) ? in[i] : 0;
+        s += v[t];
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < SCAN_T; off <<= 1) {
+        int t = ((int)threadIdx.x >= off) ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    long long off = boff[blockIdx.x] + (threadIdx.x ? sh[threadIdx.x - 1] : 0);
+    for (int t = 0; t < SCAN_I; ++t) {
+        int i = base + t;
+        if (i < n) out[i] = (int)off;
+        off += v[t];
+    }
+}
+
+// ------------------------------------------------------------------ misc
+__global__ void k_fill_int(int* p, int v, long n) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_to_float(const double* __restrict__ s, float* __restrict__ d, long n) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = (float)s[i];
+}
+
+__global__ void k_negate(double* v, long n) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = -v[i];
+}
+
+__global__ void k_iota_div(int n, int b, int* __restrict__ out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = i / b;
+}
+
+__global__ void k_gather_int(int n, const int* __restrict__ map, const int* __restrict__ src, int* __restrict__ dst) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[map[i]];
+}
+
+// ------------------------------------------------------------------ block layout
+// Scalar row i = I*b + r holds, for each block of block row I in order, the b
+// entries of block row r: the same order the block values are stored in.
+__global__ void k_bsr_expand(int b, int nbr, const int* __restrict__ brp, const int* __restrict__ bci,
+                             const double* __restrict__ bv, int* __restrict__ rp, int* __restrict__ ci,
+                             double* __restrict__ v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int n = nbr * b;
+    if (i >= n) return;
+    int I = i / b, r = i - I * b;
+    int p0 = brp[I], p1 = brp[I + 1];
+    long o = (long)p0 * b * b + (long)r * (p1 - p0) * b;
+    rp[i] = (int)o;
+    if (i == n - 1) rp[n] = (int)((long)brp[nbr] * b * b);
+    for (int p = p0; p < p1; ++p) {
+        int J = bci[p];
+        const double* blk = bv + (long)p * b * b + r * b;
+        for (int c = 0; c < b; ++c) {
+            ci[o] = J * b + c;
+            v[o] = blk[c];
+            ++o;
+        }
+    }
+}
+
+__global__ void k_bsr_tcount(long nnzb, const int* __restrict__ ci, int* __restrict__ cnt) {
+    long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nnzb) atomicAdd(&cnt[ci[p]], 1);
+}
+
+__global__ void k_bsr_tscatter(int nbr, const int* __restrict__ rp, const int* __restrict__ ci,
+                               int* __restrict__ cursor, int* __restrict__ tci, int* __restrict__ src) {
+    int I = blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= nbr) return;
+    for (int p = rp[I]; p < rp[I + 1]; ++p) {
+        int q = atomicAdd(&cursor[ci[p]], 1);
+        tci[q] = I;
+        src[q] = p;
+    }
+}
+
+__global__ void k_bsr_tsort(int nbr, const int* __restrict__ trp, int* __restrict__ tci, int* __restrict__ src) {
+    int J = blockIdx.x * blockDim.x + threadIdx.x;
+    if (J >= nbr) return;
+    int q0 = trp[J], q1 = trp[J + 1];
+    for (int q = q0 + 1; q < q1; ++q) {
+        int key = tci[q], s = src[q], t = q - 1;
+        while (t >= q0 && tci[t] > key) { tci[t + 1] = tci[t]; src[t + 1] = src[t]; --t; }
+        tci[t + 1] = key;
+        src[t + 1] = s;
+    }
+}
+
+__global__ void k_bsr_tvalues(long nnzb, int b, const int* __restrict__ src, const double* __restrict__ v,
+                              double* __restrict__ tv) {
+    long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nnzb) return;
+    const double* a = v + (long)src[q] * b * b;
+    double* t = tv + q * b * b;
+    for (int r = 0; r < b; ++r)
+        for (int c = 0; c < b; ++c) t[r * b + c] = a[c * b + r];
+}
+
+// ------------------------------------------------------------------ C/F split and block extraction
+__global__ void k_cf_flags(int n, const int* __restrict__ field, uint32_t mask, int* __restrict__ isF,
+                           int* __restrict__ flag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int f = field[i];
+    if (f < 0 || f >= 32) { set_flag(flag, 5); isF[i] = 0; return; }
+    isF[i] = (int)((mask >> f) & 1u);
+}
+
+__global__ void k_cf_maps(int n, const int* __restrict__ isF, const int* __restrict__ fpos, int* __restrict__ lmap,
+                          int* __restrict__ fmap, int* __restrict__ cmap) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (isF[i]) { int k = fpos[i]; lmap[i] = k; fmap[k] = i; }
+    else { int c = i - fpos[i]; lmap[i] = c; cmap[c] = i; }
+}
+
+__global__ void k_extract_count(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                 const int* __restrict__ isF, const int* __restrict__ lmap, int* cFF, int* cFC,
+                                 int* cCF, int* cCC) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int f = 0, c = 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        if (isF[ci[p]]) ++f;
+        else ++c;
+    }
+    int l = lmap[i];
+    if (isF[i]) { cFF[l] = f; cFC[l] = c; }
+    else { cCF[l] = f; cCC[l] = c; }
+}
+
+__global__ void k_extract_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                               const double* __restrict__ v, const int* __restrict__ isF,
+                               const int* __restrict__ lmap, const int* __restrict__ rpFF, int* ciFF, double* vFF,
+                               const int* __restrict__ rpFC, int* ciFC, double* vFC, const int* __restrict__ rpCF,
+                               int* ciCF, double* vCF, const int* __restrict__ rpCC, int* ciCC, double* vCC) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int l = lmap[i];
+    int oF, oC;
+    int *cF, *cC;
+    double *vF, *vC;
+    if (isF[i]) { oF = rpFF[l]; oC = rpFC[l]; cF = ciFF; vF = vFF; cC = ciFC; vC = vFC; }
+    else { oF = rpCF[l]; oC = rpCC[l]; cF = ciCF; vF = vCF; cC = ciCC; vC = vCC; }
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        int j = ci[p];
+        if (isF[j]) { cF[oF] = lmap[j]; vF[oF] = v[p]; ++oF; }
+        else { cC[oC] = lmap[j]; vC[oC] = v[p]; ++oC; }
+    }
+}
+
+// ------------------------------------------------------------------ F-relaxation operator
+__global__ void k_frelax_flags(int nF, const int* __restrict__ bid, int* __restrict__ flagk) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nF) return;
+    flagk[k] = (bid == nullptr || k == 0 || bid[k] != bid[k - 1]) ? 1 : 0;
+}
+
+__global__ void k_frelax_starts(int nF, const int* __restrict__ flagk, const int* __restrict__ excl,
+                                int* __restrict__ bstart, int* __restrict__ bnum) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nF) return;
+    int b = excl[k] + flagk[k] - 1;
+    bnum[k] = b;
+    if (flagk[k]) bstart[b] = k;
+    if (k == nF - 1) bstart[excl[nF]] = nF;
+}
+
+__global__ void k_frelax_len(int nF, const int* __restrict__ bnum, const int* __restrict__ bstart,
+                             int* __restrict__ len) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nF) return;
+    int b = bnum[k];
+    len[k] = bstart[b + 1] - bstart[b];
+}
+
+// Gauss-Jordan inverse with partial pivoting (ties to the lower row): scale the
+// pivot row by 1/pivot, then subtract f times it from every other row.
+__global__ void k_frelax_fill(int nb, const int* __restrict__ bstart, const int* __restrict__ arp,
+                              const int* __restrict__ aci, const double* __restrict__ av,
+                              const int* __restrict__ mrp, int* __restrict__ mci, double* __restrict__ mv,
+                              int* __restrict__ flag) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nb) return;
+    int s0 = bstart[t], bs = bstart[t + 1] - s0;
+    if (bs > 4) { set_flag(flag, 6); return; }
+    double a[16], e[16];
+    for (int r = 0; r < bs; ++r)
+        for (int c = 0; c < bs; ++c) { a[r * bs + c] = 0.0; e[r * bs + c] = (r == c) ? 1.0 : 0.0; }
+    for (int r = 0; r < bs; ++r)
+        for (int p = arp[s0 + r]; p < arp[s0 + r + 1]; ++p) {
+            int c = aci[p] - s0;
+            if (c >= 0 && c < bs) a[r * bs + c] = av[p];
+        }
+    for (int c = 0; c < bs; ++c) {
+        int pv = c;
+        double best = fabs(a[c * bs + c]);
+        for (int r = c + 1; r < bs; ++r)
+            if (fabs(a[r * bs + c]) > best) { best = fabs(a[r * bs + c]); pv = r; }
+        if (!(best > 0.0) || !isfinite(best)) { set_flag(flag, 3); return; }
+        if (pv != c)
+            for (int k = 0; k < bs; ++k) {
+                double x = a[c * bs + k]; a[c * bs + k] = a[pv * bs + k]; a[pv * bs + k] = x;
+                x = e[c * bs + k]; e[c * bs + k] = e[pv * bs + k]; e[pv * bs + k] = x;
+            }
+        double ip = 1.0 / a[c * bs + c];
+        for (int k = 0; k < bs; ++k) { a[c * bs + k] = a[c * bs + k] * ip; e[c * bs + k] = e[c * bs + k] * ip; }
+        for (int r = 0; r < bs; ++r) {
+            if (r == c) continue;
+            double f = a[r * bs + c];
+            for (int k = 0; k < bs; ++k) {
+                a[r * bs + k] = a[r * bs + k] - f * a[c * bs + k];
+                e[r * bs + k] = e[r * bs + k] - f * e[c * bs + k];
+            }
+        }
+    }
+    for (int r = 0; r < bs; ++r) {
+        int o = mrp[s0 + r];
+        for (int c = 0; c < bs; ++c) { mci[o + c] = s0 + c; mv[o + c] = e[r * bs + c]; }
+    }
+}
+
+// ------------------------------------------------------------------ sparse products
+__global__ void k_max_row(int n, const int* __restrict__ rp, int* __restrict__ out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicMax(out, rp[i + 1] - rp[i]);
+}
+
+// C = A B, one wavefront per output row.  Each lane owns up to NH entries p of
+// row i of A (p = a0 + lane + 64 t) and walks row aci[p] of B: a k-way merge
+// whose current minimum column is found by a wave-wide min.  Every output
+// value starts at 0.0 and adds a_ip * b_pj over the contributing p in
+// ascending order (t-major, then lane), i.e. Gustavson's order.
+template <int NH, bool FILL>
+__global__ __launch_bounds__(TPB) void k_spgemm(int nr, const int* __restrict__ arp, const int* __restrict__ aci,
+                                                const double* __restrict__ av, const int* __restrict__ brp,
+                                                const int* __restrict__ bci, const double* __restrict__ bv,
+                                                const int* __restrict__ crp, int* __restrict__ cci,
+                                                double* __restrict__ cv, int* __restrict__ cnt,
+                                                int* __restrict__ flag) {
+    int row = blockIdx.x * (TPB / WAVE) + threadIdx.x / WAVE;
+    int lane = threadIdx.x & (WAVE - 1);
+    if (row >= nr) return;
+    int a0 = arp[row], a1 = arp[row + 1];
+    if (a1 - a0 > NH * WAVE) {
+        if (lane == 0) set_flag(flag, 6);
+        return;
+    }
+    int h[NH], e[NH], c[NH];
+    double a[NH];
+#pragma unroll
+    for (int t = 0; t < NH; ++t) {
+        int p = a0 + lane + WAVE * t;
+        c[t] = INT_MAX;
+        h[t] = 0;
+        e[t] = 0;
+        a[t] = 0.0;
+        if (p < a1) {
+            int k = aci[p];
+            h[t] = brp[k];
+            e[t] = brp[k + 1];
+            a[t] = FILL ? av[p] : 0.0;
+            if (h[t] < e[t]) c[t] = bci[h[t]];
+        }
+    }
+    int count = 0;
+    int o = FILL ? crp[row] : 0;
+    for (;;) {
+        int mn = c[0];
+#pragma unroll
+        for (int t = 1; t < NH; ++t) mn = min(mn, c[t]);
+        mn = wave_min_int(mn);
+        if (mn == INT_MAX) break;
+        if (FILL) {
+            double acc = 0.0;
+#pragma unroll
+            for (int t = 0; t < NH; ++t) {
+                bool m = (c[t] == mn);
+                double prod = m ? a[t] * bv[h[t]] : 0.0;
+                unsigned long long mask = __ballot(m);
+                while (mask) {
+                    int l = __ffsll((unsigned long long)mask) - 1;
+                    acc = acc + __shfl(prod, l, WAVE);
+                    mask &= mask - 1;
+                }
+            }
+            if (lane == 0) {
+                cci[o + count] = mn;
+                cv[o + count] = acc;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NH; ++t)
+            if (c[t] == mn) {
+                ++h[t];
+                c[t] = (h[t] < e[t]) ? bci[h[t]] : INT_MAX;
+            }
+        ++count;
+    }
+    if (!FILL && lane == 0) cnt[row] = count;
+}
+
+__global__ void k_add_count(int nr, const int* __restrict__ arp, const int* __restrict__ aci,
+                            const int* __restrict__ brp, const int* __restrict__ bci, int* __restrict__ cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    int p = arp[i], pe = arp[i + 1], q = brp[i], qe = brp[i + 1], n = 0;
+    while (p < pe || q < qe) {
+        if (q >= qe || (p < pe && aci[p] < bci[q])) ++p;
+        else if (p >= pe || bci[q] < aci[p]) ++q;
+        else { ++p; ++q; }
+        ++n;
+    }
+    cnt[i] = n;
+}
+
+__global__ void k_add_fill(int nr, const int* __restrict__ arp, const int* __restrict__ aci,
+                           const double* __restrict__ av, const int* __restrict__ brp, const int* __restrict__ bci,
+                           const double* __restrict__ bv, const int* __restrict__ crp, int* __restrict__ cci,
+                           double* __restrict__ cv) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    int p = arp[i], pe = arp[i + 1], q = brp[i], qe = brp[i + 1], o = crp[i];
+    while (p < pe || q < qe) {
+        if (q >= qe || (p < pe && aci[p] < bci[q])) { cci[o] = aci[p]; cv[o] = av[p]; ++p; }
+        else if (p >= pe || bci[q] < aci[p]) { cci[o] = bci[q]; cv[o] = bv[q]; ++q; }
+        else { cci[o] = aci[p]; cv[o] = av[p] + bv[q]; ++p; ++q; }
+        ++o;
+    }
+}
+
+__global__ void k_transpose_count(long nnz, const int* __restrict__ ci, int* __restrict__ cnt) {
+    long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nnz) atomicAdd(&cnt[ci[p]], 1);
+}
+
+__global__ void k_transpose_scatter(int nr, const int* __restrict__ rp, const int* __restrict__ ci,
+                                    const double* __restrict__ v, int* __restrict__ cursor, int* __restrict__ tci,
+                                    double* __restrict__ tv) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        int q = atomicAdd(&cursor[ci[p]], 1);
+        tci[q] = i;
+        if (tv) tv[q] = v[p];
+    }
+}
+
+// Sort each transposed row by source row (an insertion sort: rows are short).
+__global__ void k_transpose_sort(int nr, const int* __restrict__ rp, int* __restrict__ ci, double* __restrict__ v) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nr) return;
+    int q0 = rp[i], q1 = rp[i + 1];
+    for (int q = q0 + 1; q < q1; ++q) {
+        int key = ci[q];
+        double val = v ? v[q] : 0.0;
+        int t = q - 1;
+        while (t >= q0 && ci[t] > key) {
+            ci[t + 1] = ci[t];
+            if (v) v[t + 1] = v[t];
+            --t;
+        }
+        ci[t + 1] = key;
+        if (v) v[t + 1] = val;
+    }
+}
+
+// ------------------------------------------------------------------ AMG setup
+// j in S_i iff j != i (same label under the unknown-based option) and
+// -a_ij >= theta * max_k(-a_ik); S_i empty when that max is not positive.
+__global__ void k_strength(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                           const double* __restrict__ v, double theta, const int* __restrict__ label,
+                           unsigned char* __restrict__ strong) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double mx = 0.0;
+    bool have = false;
+    int li = label ? label[i] : 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        int j = ci[p];
+        if (j == i || (label && label[j] != li)) continue;
+        double t = -v[p];
+        if (!have || t > mx) { mx = t; have = true; }
+    }
+    double thr = theta * mx;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        int j = ci[p];
+        unsigned char s = 0;
+        if (have && mx > 0.0 && j != i && !(label && label[j] != li) && -v[p] >= thr) s = 1;
+        strong[p] = s;
+    }
+}
+
+__global__ void k_lambda(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                         const unsigned char* __restrict__ strong, int* __restrict__ lam) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+        if (strong[p]) atomicAdd(&lam[ci[p]], 1);
+}
+
+__global__ void k_scount(int n, const int* __restrict__ rp, const unsigned char* __restrict__ strong,
+                         int* __restrict__ cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) c += strong[p];
+    cnt[i] = c;
+}
+
+__global__ void k_sfill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                        const unsigned char* __restrict__ strong, const int* __restrict__ srp, int* __restrict__ sci) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int o = srp[i];
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+        if (strong[p]) sci[o++] = ci[p];
+}
+
+// splitmix64 (Steele, Lea, Flood 2014): output k of the stream seeded with
+// `seed` is mix(seed + k * 0x9E3779B97F4A7C15).
+__device__ inline uint64_t splitmix64(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + k * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+__global__ void k_pmis_init(int n, const int* __restrict__ lam, uint64_t seed, int level, double* __restrict__ w,
+                            int* __restrict__ cf) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t k = ((uint64_t)(unsigned)level << 32) + (uint64_t)(unsigned)i + 1ULL;
+    double u = (double)(splitmix64(seed, k) >> 11) * (1.0 / 9007199254740992.0);
+    w[i] = (double)lam[i] + u;
+    cf[i] = (lam[i] == 0) ? -1 : 0;
+}
+
+// An undecided point becomes C when its (w, index) beats every undecided
+// neighbour in S_i and S^T_i (decided on the state at the start of the round).
+__global__ void k_pmis_select(int n, const int* __restrict__ srp, const int* __restrict__ sci,
+                              const int* __restrict__ trp, const int* __restrict__ tci, const double* __restrict__ w,
+                              const int* __restrict__ cf, unsigned char* __restrict__ newc) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (cf[i] != 0) { newc[i] = 0; return; }
+    double wi = w[i];
+    bool best = true;
+    for (int q = srp[i]; q < srp[i + 1] && best; ++q) {
+        int j = sci[q];
+        if (cf[j] == 0 && (w[j] > wi || (w[j] == wi && j > i))) best = false;
+    }
+    for (int q = trp[i]; q < trp[i + 1] && best; ++q) {
+        int j = tci[q];
+        if (cf[j] == 0 && (w[j] > wi || (w[j] == wi && j > i))) best = false;
+    }
+    newc[i] = best ? 1 : 0;
+}
+
+// New C-points are set; an undecided point that strongly depends on a new
+// C-point becomes F.  Counts what is still undecided.
+__global__ void k_pmis_update(int n, const int* __restrict__ srp, const int* __restrict__ sci,
+                              const unsigned char* __restrict__ newc, int* __restrict__ cf,
+                              int* __restrict__ undecided) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (newc[i]) { cf[i] = 1; return; }
+    if (cf[i] != 0) return;
+    for (int q = srp[i]; q < srp[i + 1]; ++q)
+        if (newc[sci[q]]) { cf[i] = -1; return; }
+    atomicAdd(undecided, 1);
+}
+
+__global__ void k_is_c(int n, const int* __restrict__ cf, int* __restrict__ isC) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) isC[i] = (cf[i] == 1) ? 1 : 0;
+}
+
+__global__ void k_interp_count(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                               const unsigned char* __restrict__ strong, const int* __restrict__ cf,
+                               int* __restrict__ cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (cf[i] == 1) { cnt[i] = 1; return; }
+    int c = 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+        if (strong[p] && cf[ci[p]] == 1) ++c;
+    cnt[i] = c;
+}
+
+// Direct interpolation with positive off-diagonals lumped into the diagonal
+// (Stueben 2001): w_ij = -(alpha_i a_ij) / atilde_ii, alpha_i = neg_i / cs_i.
+__global__ void k_interp_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                              const double* __restrict__ v, const unsigned char* __restrict__ strong,
+                              const int* __restrict__ cf, const int* __restrict__ cidx, const int* __restrict__ label,
+                              const int* __restrict__ prp, int* __restrict__ pci, double* __restrict__ pv,
+                              int* __restrict__ flag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int o = prp[i];
+    if (cf[i] == 1) { pci[o] = cidx[i]; pv[o] = 1.0; return; }
+    if (prp[i + 1] == o) return;
+    int li = label ? label[i] : 0;
+    double aii = 0.0, neg = 0.0, pos = 0.0, cs = 0.0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        int k = ci[p];
+        double a = v[p];
+        if (k == i) { aii = a; continue; }
+        if (label && label[k] != li) continue;
+        if (a < 0.0) neg = neg + a;
+        else if (a > 0.0) pos = pos + a;
+        if (strong[p] && cf[k] == 1) cs = cs + a;
+    }
+    double atil = aii + pos;
+    if (!(atil > 0.0)) set_flag(flag, 6);
+    double alpha = neg / cs;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        int k = ci[p];
+        if (strong[p] && cf[k] == 1) {
+            pci[o] = cidx[k];
+            pv[o] = -(alpha * v[p]) / atil;
+            ++o;
+        }
+    }
+}
+
+__global__ void k_l1_dinv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                          const double* __restrict__ v, double* __restrict__ dinv, int* __restrict__ flag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0, aii = 0.0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        if (ci[p] == i) aii = v[p];
+        else s = s + fabs(v[p]);
+    }
+    double d = aii + s;
+    if (!(d > 0.0)) { set_flag(flag, 6); d = 1.0; }
+    dinv[i] = 1.0 / d;
+}
+
+__global__ void k_densify(int n, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ v,
+                          double* __restrict__ dense) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int j = 0; j < n; ++j) dense[(long)i * n + j] = 0.0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) dense[(long)i * n + ci[p]] = v[p];
+}
+
+// Gauss-Jordan inverse with partial pivoting of the coarsest AMG matrix, one
+// workgroup (n <= 2048): a and inv are n x n row-major in global memory.
+__global__ __launch_bounds__(1024) void k_dense_inverse(int n, double* __restrict__ a, double* __restrict__ inv,
+                                                        double* __restrict__ fcol, int* __restrict__ flag) {
+    __shared__ double sv[1024];
+    __shared__ int si[1024];
+    int tid = threadIdx.x, nt = blockDim.x;
+    for (long q = tid; q < (long)n * n; q += nt) inv[q] = ((q / n) == (q % n)) ? 1.0 : 0.0;
+    __syncthreads();
+    for (int c = 0; c < n; ++c) {
+        double best = -1.0;
+        int bi = n;
+        for (int r = c + tid; r < n; r += nt) {
+            double t = fabs(a[(long)r * n + c]);
+            if (t > best || (t == best && r < bi)) { best = t; bi = r; }
+        }
+        sv[tid] = best;
+        si[tid] = bi;
+        __syncthreads();
+        for (int off = nt / 2; off > 0; off >>= 1) {
+            if (tid < off) {
+                double o = sv[tid + off];
+                int oi = si[tid + off];
+                if (o > sv[tid] || (o == sv[tid] && oi < si[tid])) { sv[tid] = o; si[tid] = oi; }
+            }
+            __syncthreads();
+        }
+        int pv = si[0];
+        double pbest = sv[0];
+        __syncthreads();
+        if (!(pbest > 0.0) || !isfinite(pbest)) {
+            if (tid == 0) set_flag(flag, 3);
+            return;
+        }
+        if (pv != c)
+            for (int k = tid; k < n; k += nt) {
+                double x = a[(long)c * n + k]; a[(long)c * n + k] = a[(long)pv * n + k]; a[(long)pv * n + k] = x;
+                x = inv[(long)c * n + k]; inv[(long)c * n + k] = inv[(long)pv * n + k]; inv[(long)pv * n + k] = x;
+            }
+        __syncthreads();
+        double ip = 1.0 / a[(long)c * n + c];
+        __syncthreads();
+        for (int k = tid; k < n; k += nt) {
+            a[(long)c * n + k] = a[(long)c * n + k] * ip;
+            inv[(long)c * n + k] = inv[(long)c * n + k] * ip;
+        }
+        for (int r = tid; r < n; r += nt) fcol[r] = a[(long)r * n + c];
+        __syncthreads();
+        for (long q = tid; q < (long)n * n; q += nt) {
+            int r = (int)(q / n), k = (int)(q % n);
+            if (r == c) continue;
+            double f = fcol[r];
+            a[q] = a[q] - f * a[(long)c * n + k];
+            inv[q] = inv[q] - f * inv[(long)c * n + k];
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ fused-apply operators
+// R = [X (F columns mapped to global) | I at cmap[i]], X scaled by `scale`.
+__global__ void k_rj_count(int nC, const int* __restrict__ xrp, int* __restrict__ len) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nC) len[i] = xrp[i + 1] - xrp[i] + 1;
+}
+
+__global__ void k_rj_fill(int nC, const int* __restrict__ xrp, const int* __restrict__ xci,
+                          const double* __restrict__ xv, double scale, const int* __restrict__ fmap,
+                          const int* __restrict__ cmap, const int* __restrict__ rrp, int* __restrict__ rci,
+                          double* __restrict__ rv) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nC) return;
+    int o = rrp[i];
+    int g = cmap[i];
+    bool placed = false;
+    for (int p = xrp[i]; p < xrp[i + 1]; ++p) {
+        int col = fmap[xci[p]];
+        if (!placed && col > g) { rci[o] = g; rv[o] = 1.0; ++o; placed = true; }
+        rci[o] = col;
+        rv[o] = scale * xv[p];
+        ++o;
+    }
+    if (!placed) { rci[o] = g; rv[o] = 1.0; }
+}
+
+// P = [[Y (coarse columns) , M (columns nC + fmap)] on F rows ; unit rows on C rows]
+__global__ void k_pj_count(int n, const int* __restrict__ isF, const int* __restrict__ lmap,
+                           const int* __restrict__ yrp, const int* __restrict__ mrp, int* __restrict__ len) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    if (!isF[g]) { len[g] = 1; return; }
+    int k = lmap[g];
+    len[g] = (yrp[k + 1] - yrp[k]) + (mrp[k + 1] - mrp[k]);
+}
+
+__global__ void k_pj_fill(int n, int nC, const int* __restrict__ isF, const int* __restrict__ lmap,
+                          const int* __restrict__ yrp, const int* __restrict__ yci, const double* __restrict__ yv,
+                          double yscale, const int* __restrict__ mrp, const int* __restrict__ mci,
+                          const double* __restrict__ mv, double mscale, const int* __restrict__ fmap,
+                          const int* __restrict__ prp,
+                          int* __restrict__ pci, double* __restrict__ pv) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n) return;
+    int o = prp[g];
+    int k = lmap[g];
+    if (!isF[g]) { pci[o] = k; pv[o] = 1.0; return; }
+    for (int p = yrp[k]; p < yrp[k + 1]; ++p) { pci[o] = yci[p]; pv[o] = yscale * yv[p]; ++o; }
+    for (int p = mrp[k]; p < mrp[k + 1]; ++p) { pci[o] = nC + fmap[mci[p]]; pv[o] = mscale * mv[p]; ++o; }
+}
+
+}  // namespace
+
+// ====================================================================== launchers
+void scan_exclusive_async(const int* in, int* out, int n, hipStream_t s) {
+    int nb = ceil_div(n > 0 ? n : 1, SCAN_B);
+    DArr<long long> bsum((size_t)nb + 1, s);
+    long long* total = bsum.p + nb;
+    k_scan_reduce<<<nb, SCAN_T, 0, s>>>(in, n, bsum.p);
+    k_scan_blocks<<<1, 1024, 0, s>>>(bsum.p, nb, out + n, total);
+    k_scan_apply<<<nb, SCAN_T, 0, s>>>(in, n, bsum.p, out);
+    MGR_LAUNCH_CHECK();
+}
+
+long scan_exclusive(const int* in, int* out, int n, hipStream_t s) {
+    int nb = ceil_div(n > 0 ? n : 1, SCAN_B);
+    DArr<long long> bsum((size_t)nb + 1, s);
+    long long* total = bsum.p + nb;
+    k_scan_reduce<<<nb, SCAN_T, 0, s>>>(in, n, bsum.p);
+    k_scan_blocks<<<1, 1024, 0, s>>>(bsum.p, nb, out + n, total);
+    k_scan_apply<<<nb, SCAN_T, 0, s>>>(in, n, bsum.p, out);
+    MGR_LAUNCH_CHECK();
+    long long h = 0;
+    MGR_HIP(hipMemcpyAsync(&h, total, sizeof(h), hipMemcpyDeviceToHost, s));
+    MGR_HIP(hipStreamSynchronize(s));
+    if (h > INT_MAX) throw Error(-6, "prefix sum exceeds the int32 index range");
+    return (long)h;
+}
+
+int read_int(const int* dptr, hipStream_t s) {
+    int h = 0;
+    MGR_HIP(hipMemcpyAsync(&h, dptr, sizeof(int), hipMemcpyDeviceToHost, s));
+    MGR_HIP(hipStreamSynchronize(s));
+    return h;
+}
+
+void flag_clear(int* flag, hipStream_t s) { fill_int(flag, 0, 1, s); }
+int flag_read(const int* flag, hipStream_t s) { return read_int(flag, s); }
+
+void fill_int(int* p, int v, long n, hipStream_t s) {
+    if (n <= 0) return;
+    k_fill_int<<<nblk(n), TPB, 0, s>>>(p, v, n);
+    MGR_LAUNCH_CHECK();
+}
+
+void to_float(const double* src, float* dst, long n, hipStream_t s) {
+    if (n <= 0) return;
+    k_to_float<<<nblk(n), TPB, 0, s>>>(src, dst, n);
+    MGR_LAUNCH_CHECK();
+}
+
+void negate(double* v, long n, hipStream_t s) {
+    if (n <= 0) return;
+    k_negate<<<nblk(n), TPB, 0, s>>>(v, n);
+    MGR_LAUNCH_CHECK();
+}
+
+void gather_int(int n, const int* map, const int* src, int* dst, hipStream_t s) {
+    if (n <= 0) return;
+    k_gather_int<<<nblk(n), TPB, 0, s>>>(n, map, src, dst);
+    MGR_LAUNCH_CHECK();
+}
+
+void iota_div(int n, int b, int* out, hipStream_t s) {
+    if (n <= 0) return;
+    k_iota_div<<<nblk(n), TPB, 0, s>>>(n, b, out);
+    MGR_LAUNCH_CHECK();
+}
+
+void bsr_expand(int b, int nbr, const int* brp, const int* bci, const double* bv, int* rp, int* ci, double* v,
+                hipStream_t s) {
+    int n = nbr * b;
+    if (n <= 0) return;
+    k_bsr_expand<<<nblk(n), TPB, 0, s>>>(b, nbr, brp, bci, bv, rp, ci, v);
+    MGR_LAUNCH_CHECK();
+}
+
+void bsr_transpose_blocks(int b, int nbr, const int* rp, const int* ci, const double* v, int* trp, int* tci,
+                          double* tv, hipStream_t s) {
+    int nnzb = read_int(rp + nbr, s);
+    DArr<int> cnt((size_t)nbr + 1, s), cursor((size_t)nbr + 1, s), src((size_t)(nnzb > 0 ? nnzb : 1), s);
+    fill_int(cnt.p, 0, nbr + 1, s);
+    if (nnzb > 0) k_bsr_tcount<<<nblk(nnzb), TPB, 0, s>>>(nnzb, ci, cnt.p);
+    scan_exclusive_async(cnt.p, trp, nbr, s);
+    MGR_HIP(hipMemcpyAsync(cursor.p, trp, sizeof(int) * (nbr + 1), hipMemcpyDeviceToDevice, s));
+    k_bsr_tscatter<<<nblk(nbr), TPB, 0, s>>>(nbr, rp, ci, cursor.p, tci, src.p);
+    k_bsr_tsort<<<nblk(nbr), TPB, 0, s>>>(nbr, trp, tci, src.p);
+    if (nnzb > 0) k_bsr_tvalues<<<nblk(nnzb), TPB, 0, s>>>(nnzb, b, src.p, v, tv);
+    MGR_LAUNCH_CHECK();
+}
+
+void cf_flags(int n, const int* field, uint32_t mask, int* isF, int* flag, hipStream_t s) {
+    if (n <= 0) return;
+    k_cf_flags<<<nblk(n), TPB, 0, s>>>(n, field, mask, isF, flag);
+    MGR_LAUNCH_CHECK();
+}
+
+void cf_maps(int n, const int* isF, const int* fpos, int* lmap, int* fmap, int* cmap, hipStream_t s) {
+    if (n <= 0) return;
+    k_cf_maps<<<nblk(n), TPB, 0, s>>>(n, isF, fpos, lmap, fmap, cmap);
+    MGR_LAUNCH_CHECK();
+}
+
+void extract_count(const DCsr& A, const int* isF, const int* lmap, int* cFF, int* cFC, int* cCF, int* cCC,
+                   hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_extract_count<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, isF, lmap, cFF, cFC, cCF, cCC);
+    MGR_LAUNCH_CHECK();
+}
+
+void extract_fill(const DCsr& A, const int* isF, const int* lmap, DCsr& FF, DCsr& FC, DCsr& CF, DCsr& CC,
+                  hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_extract_fill<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, isF, lmap, FF.rp.p, FF.ci.p, FF.v.p,
+                                              FC.rp.p, FC.ci.p, FC.v.p, CF.rp.p, CF.ci.p, CF.v.p, CC.rp.p, CC.ci.p,
+                                              CC.v.p);
+    MGR_LAUNCH_CHECK();
+}
+
+void frelax_block_flags(int nF, const int* bid, int* flagk, hipStream_t s) {
+    if (nF <= 0) return;
+    k_frelax_flags<<<nblk(nF), TPB, 0, s>>>(nF, bid, flagk);
+    MGR_LAUNCH_CHECK();
+}
+
+void frelax_block_starts(int nF, const int* flagk, const int* excl, int* bstart, int* bnum, hipStream_t s) {
+    if (nF <= 0) return;
+    k_frelax_starts<<<nblk(nF), TPB, 0, s>>>(nF, flagk, excl, bstart, bnum);
+    MGR_LAUNCH_CHECK();
+}
+
+void frelax_row_len(int nF, const int* bnum, const int* bstart, int* len, hipStream_t s) {
+    if (nF <= 0) return;
+    k_frelax_len<<<nblk(nF), TPB, 0, s>>>(nF, bnum, bstart, len);
+    MGR_LAUNCH_CHECK();
+}
+
+void frelax_fill(int nb, const int* bstart, const DCsr& AFF, DCsr& M, int* flag, hipStream_t s) {
+    if (nb <= 0) return;
+    k_frelax_fill<<<nblk(nb), TPB, 0, s>>>(nb, bstart, AFF.rp.p, AFF.ci.p, AFF.v.p, M.rp.p, M.ci.p, M.v.p, flag);
+    MGR_LAUNCH_CHECK();
+}
+
+int max_row_len(const DCsr& A, hipStream_t s) {
+    if (A.nr <= 0) return 0;
+    DArr<int> m(1, s);
+    fill_int(m.p, 0, 1, s);
+    k_max_row<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, m.p);
+    MGR_LAUNCH_CHECK();
+    return read_int(m.p, s);
+}
+
+template <bool FILL>
+static void spgemm_launch(const DCsr& A, const DCsr& B, int max_row, const int* crp, int* cci, double* cv, int* cnt,
+                          int* flag, hipStream_t s) {
+    if (A.nr <= 0) return;
+    int grid = ceil_div(A.nr, TPB / WAVE);
+    if (max_row <= WAVE)
+        k_spgemm<1, FILL><<<grid, TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p, B.v.p, crp, cci, cv,
+                                                cnt, flag);
+    else if (max_row <= 4 * WAVE)
+        k_spgemm<4, FILL><<<grid, TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p, B.v.p, crp, cci, cv,
+                                                cnt, flag);
+    else if (max_row <= 16 * WAVE)
+        k_spgemm<16, FILL><<<grid, TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p, B.v.p, crp, cci, cv,
+                                                 cnt, flag);
+    else
+        throw Error(-6, "SpGEMM: a row of the left factor has more than 1024 entries");
+    MGR_LAUNCH_CHECK();
+}
+
+void spgemm_count(const DCsr& A, const DCsr& B, int max_row, int* cnt, int* flag, hipStream_t s) {
+    spgemm_launch<false>(A, B, max_row, nullptr, nullptr, nullptr, cnt, flag, s);
+}
+
+void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, hipStream_t s) {
+    spgemm_launch<true>(A, B, max_row, C.rp.p, C.ci.p, C.v.p, nullptr, nullptr, s);
+}
+
+void add_count(const DCsr& A, const DCsr& B, int* cnt, hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_add_count<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, B.rp.p, B.ci.p, cnt);
+    MGR_LAUNCH_CHECK();
+}
+
+void add_fill(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_add_fill<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p, B.v.p, C.rp.p, C.ci.p,
+                                          C.v.p);
+    MGR_LAUNCH_CHECK();
+}
+
+void transpose_count(const DCsr& A, int* cnt, hipStream_t s) {
+    if (A.nnz <= 0) return;
+    k_transpose_count<<<nblk(A.nnz), TPB, 0, s>>>(A.nnz, A.ci.p, cnt);
+    MGR_LAUNCH_CHECK();
+}
+
+void transpose_fill(const DCsr& A, DCsr& T, int* cursor, hipStream_t s) {
+    if (A.nr > 0)
+        k_transpose_scatter<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, cursor, T.ci.p, T.v.p);
+    if (T.nr > 0) k_transpose_sort<<<nblk(T.nr), TPB, 0, s>>>(T.nr, T.rp.p, T.ci.p, T.v.p);
+    MGR_LAUNCH_CHECK();
+}
+
+void amg_strength(const DCsr& A, double theta, const int* label, unsigned char* strong, hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_strength<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, theta, label, strong);
+    MGR_LAUNCH_CHECK();
+}
+
+void amg_lambda(const DCsr& A, const unsigned char* strong, int* lam, hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_lambda<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, strong, lam);
+    MGR_LAUNCH_CHECK();
+}
+
+void strength_compact_count(const DCsr& A, const unsigned char* strong, int* cnt, hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_scount<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, strong, cnt);
+    MGR_LAUNCH_CHECK();
+}
+
+void strength_compact_fill(const DCsr& A, const unsigned char* strong, const int* srp, int* sci, hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_sfill<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, strong, srp, sci);
+    MGR_LAUNCH_CHECK();
+}
+
+void pattern_transpose_fill(int nr, const int* rp, const int* ci, const int* trp, int* cursor, int* tci,
+                            hipStream_t s) {
+    (void)trp;
+    if (nr <= 0) return;
+    k_transpose_scatter<<<nblk(nr), TPB, 0, s>>>(nr, rp, ci, nullptr, cursor, tci, nullptr);
+    MGR_LAUNCH_CHECK();
+}
+
+void pmis_init(int n, const int* lam, uint64_t seed, int level, double* w, int* cf, hipStream_t s) {
+    if (n <= 0) return;
+    k_pmis_init<<<nblk(n), TPB, 0, s>>>(n, lam, seed, level, w, cf);
+    MGR_LAUNCH_CHECK();
+}
+
+void pmis_select(int n, const int* srp, const int* sci, const int* trp, const int* tci, const double* w,
+                 const int* cf, unsigned char* newc, hipStream_t s) {
+    if (n <= 0) return;
+    k_pmis_select<<<nblk(n), TPB, 0, s>>>(n, srp, sci, trp, tci, w, cf, newc);
+    MGR_LAUNCH_CHECK();
+}
+
+void pmis_update(int n, const int* srp, const int* sci, const unsigned char* newc, int* cf, int* undecided,
+                 hipStream_t s) {
+    if (n <= 0) return;
+    k_pmis_update<<<nblk(n), TPB, 0, s>>>(n, srp, sci, newc, cf, undecided);
+    MGR_LAUNCH_CHECK();
+}
+
+void cf_is_c(int n, const int* cf, int* isC, hipStream_t s) {
+    if (n <= 0) return;
+    k_is_c<<<nblk(n), TPB, 0, s>>>(n, cf, isC);
+    MGR_LAUNCH_CHECK();
+}
+
+void interp_count(const DCsr& A, const unsigned char* strong, const int* cf, int* cnt, hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_interp_count<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, strong, cf, cnt);
+    MGR_LAUNCH_CHECK();
+}
+
+void interp_fill(const DCsr& A, const unsigned char* strong, const int* cf, const int* cidx, const int* label,
+                 DCsr& P, int* flag, hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_interp_fill<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, strong, cf, cidx, label, P.rp.p, P.ci.p,
+                                             P.v.p, flag);
+    MGR_LAUNCH_CHECK();
+}
+
+void l1_dinv(const DCsr& A, double* dinv, int* flag, hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_l1_dinv<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, dinv, flag);
+    MGR_LAUNCH_CHECK();
+}
+
+void densify(const DCsr& A, double* dense, hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_densify<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, dense);
+    MGR_LAUNCH_CHECK();
+}
+
+void dense_inverse(int n, double* a, double* inv, int* flag, hipStream_t s) {
+    if (n <= 0) return;
+    DArr<double> fcol((size_t)n, s);
+    k_dense_inverse<<<1, 1024, 0, s>>>(n, a, inv, fcol.p, flag);
+    MGR_LAUNCH_CHECK();
+}
+
+void rj_count(int nC, const DCsr& X, int* len, hipStream_t s) {
+    if (nC <= 0) return;
+    k_rj_count<<<nblk(nC), TPB, 0, s>>>(nC, X.rp.p, len);
+    MGR_LAUNCH_CHECK();
+}
+
+void rj_fill(int nC, const DCsr& X, double scale, const int* fmap, const int* cmap, DCsr& R, hipStream_t s) {
+    if (nC <= 0) return;
+    k_rj_fill<<<nblk(nC), TPB, 0, s>>>(nC, X.rp.p, X.ci.p, X.v.p, scale, fmap, cmap, R.rp.p, R.ci.p, R.v.p);
+    MGR_LAUNCH_CHECK();
+}
+
+void pj_count(int n, const int* isF, const int* lmap, const DCsr& Y, const DCsr& M, int* len, hipStream_t s) {
+    if (n <= 0) return;
+    k_pj_count<<<nblk(n), TPB, 0, s>>>(n, isF, lmap, Y.rp.p, M.rp.p, len);
+    MGR_LAUNCH_CHECK();
+}
+
+void pj_fill(int n, int nC, const int* isF, const int* lmap, const DCsr& Y, double yscale, const DCsr& M,
+             double mscale, const int* fmap, DCsr& P, hipStream_t s) {
+    if (n <= 0) return;
+    k_pj_fill<<<nblk(n), TPB, 0, s>>>(n, nC, isF, lmap, Y.rp.p, Y.ci.p, Y.v.p, yscale, M.rp.p, M.ci.p, M.v.p,
+                                      mscale, fmap, P.rp.p, P.ci.p, P.v.p);
+    MGR_LAUNCH_CHECK();
+}
+
+}  // namespace mgr

@@ -1,0 +1,87 @@
+// kernels.hpp -- host-side launchers of the gfx950 kernels.  Setup kernels
+// live in k_setup.hip (built with -ffp-contract=off so that every coarse value
+// is rounded exactly as the sums are written); apply / Krylov kernels live in
+// k_apply.hip.  All launchers are asynchronous on the given stream unless they
+// return a host value.
+#pragma once
+
+#include "common.hpp"
+
+namespace mgr {
+
+// ---------------------------------------------------------------- setup
+// out[0..n] = exclusive prefix sum of in[0..n), out[n] = total.  Returns the
+// total (synchronises the stream).  Throws UNSUPPORTED if the total exceeds int32.
+long scan_exclusive(const int* in, int* out, int n, hipStream_t s);
+// Same, without reading the total back.
+void scan_exclusive_async(const int* in, int* out, int n, hipStream_t s);
+int read_int(const int* dptr, hipStream_t s);
+
+// Device-wide error flag helpers (a single int in device memory, 0 = ok).
+void flag_clear(int* flag, hipStream_t s);
+int flag_read(const int* flag, hipStream_t s);
+
+void bsr_expand(int b, int nbr, const int* brp, const int* bci, const double* bv, int* rp, int* ci, double* v,
+                hipStream_t s);
+void bsr_transpose_blocks(int b, int nbr, const int* rp, const int* ci, const double* v, int* trp, int* tci,
+                          double* tv, hipStream_t s);
+
+// isF[i] = bit field[i] of mask; flag set to 1 if a label is outside [0,32).
+void cf_flags(int n, const int* field, uint32_t mask, int* isF, int* flag, hipStream_t s);
+// fpos = exclusive scan of isF; lmap[i] = local index in F or C; fmap / cmap.
+void cf_maps(int n, const int* isF, const int* fpos, int* lmap, int* fmap, int* cmap, hipStream_t s);
+void iota_div(int n, int b, int* out, hipStream_t s);
+void gather_int(int n, const int* map, const int* src, int* dst, hipStream_t s);
+// row counts of the four blocks A_FF, A_FC (F rows), A_CF, A_CC (C rows)
+void extract_count(const DCsr& A, const int* isF, const int* lmap, int* cFF, int* cFC, int* cCF, int* cCC,
+                   hipStream_t s);
+void extract_fill(const DCsr& A, const int* isF, const int* lmap, DCsr& FF, DCsr& FC, DCsr& CF, DCsr& CC,
+                  hipStream_t s);
+
+// F-relaxation operator: blocks = runs of consecutive F-points with equal block id
+// (Jacobi: every point its own block).  bstart gets nb+1 entries.
+void frelax_block_flags(int nF, const int* bid, int* flagk, hipStream_t s);
+void frelax_block_starts(int nF, const int* flagk, const int* excl, int* bstart, int* bnum, hipStream_t s);
+void frelax_row_len(int nF, const int* bnum, const int* bstart, int* len, hipStream_t s);
+void frelax_fill(int nb, const int* bstart, const DCsr& AFF, DCsr& M, int* flag, hipStream_t s);
+
+int max_row_len(const DCsr& A, hipStream_t s);
+void spgemm_count(const DCsr& A, const DCsr& B, int max_row, int* cnt, int* flag, hipStream_t s);
+void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, hipStream_t s);
+void add_count(const DCsr& A, const DCsr& B, int* cnt, hipStream_t s);
+void add_fill(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s);
+void negate(double* v, long n, hipStream_t s);
+void transpose_count(const DCsr& A, int* cnt, hipStream_t s);
+void transpose_fill(const DCsr& A, DCsr& T, int* cursor, hipStream_t s);
+
+// AMG setup
+void amg_strength(const DCsr& A, double theta, const int* label, unsigned char* strong, hipStream_t s);
+void amg_lambda(const DCsr& A, const unsigned char* strong, int* lam, hipStream_t s);
+void strength_compact_count(const DCsr& A, const unsigned char* strong, int* cnt, hipStream_t s);
+void strength_compact_fill(const DCsr& A, const unsigned char* strong, const int* srp, int* sci, hipStream_t s);
+void pattern_transpose_fill(int nr, const int* rp, const int* ci, const int* trp, int* cursor, int* tci,
+                            hipStream_t s);
+void pmis_init(int n, const int* lam, uint64_t seed, int level, double* w, int* cf, hipStream_t s);
+void pmis_select(int n, const int* srp, const int* sci, const int* trp, const int* tci, const double* w,
+                 const int* cf, unsigned char* newc, hipStream_t s);
+void pmis_update(int n, const int* srp, const int* sci, const unsigned char* newc, int* cf, int* undecided,
+                 hipStream_t s);
+void cf_is_c(int n, const int* cf, int* isC, hipStream_t s);
+void interp_count(const DCsr& A, const unsigned char* strong, const int* cf, int* cnt, hipStream_t s);
+void interp_fill(const DCsr& A, const unsigned char* strong, const int* cf, const int* cidx, const int* label,
+                 DCsr& P, int* flag, hipStream_t s);
+void l1_dinv(const DCsr& A, double* dinv, int* flag, hipStream_t s);
+void densify(const DCsr& A, double* dense, hipStream_t s);
+void dense_inverse(int n, double* a, double* inv, int* flag, hipStream_t s);
+
+// MGR apply operators of the fused one-sweep path
+void rj_count(int nC, const DCsr& X, int* len, hipStream_t s);
+void rj_fill(int nC, const DCsr& X, double scale, const int* fmap, const int* cmap, DCsr& R, hipStream_t s);
+void pj_count(int n, const int* isF, const int* lmap, const DCsr& Y, const DCsr& M, int* len, hipStream_t s);
+void pj_fill(int n, int nC, const int* isF, const int* lmap, const DCsr& Y, double yscale, const DCsr& M,
+             double mscale, const int* fmap, DCsr& P, hipStream_t s);
+
+void to_float(const double* src, float* dst, long n, hipStream_t s);
+void fill_int(int* p, int v, long n, hipStream_t s);
+
+}  // namespace mgr

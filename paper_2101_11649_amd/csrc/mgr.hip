@@ -1,0 +1,1138 @@
+// mgr.hip -- host orchestration of the MGR + FGMRES library and its C-ABI.
+//
+// Method: Bui et al., arXiv 2101.11649.  Setup builds, per MGR level, the C/F
+// split by field, the F-relaxation operator M, the Jacobi interpolation
+// P = [-M A_FC; I] (Sec. 2, eq. (4)), the restriction (injection, eq. (4), or
+// Jacobi, eq. (5)) and the Petrov-Galerkin coarse operator R A P, then a
+// classical AMG hierarchy on the last coarse system (Sec. 4.1).  The apply is
+// Algorithm 1 from z = 0 without global relaxation; FGMRES uses it as a right
+// preconditioner (Sec. 4.1).  Every numeric step runs in the kernels of
+// k_setup.hip / k_apply.hip; this file only sequences launches and sizes.
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "apply.hpp"
+#include "kernels.hpp"
+#include "mgr.h"
+
+namespace mgr {
+
+// ====================================================================== sparse helpers
+static DCsr csr_from_counts(int nr, int nc, const int* counts, hipStream_t s) {
+    DCsr C;
+    C.nr = nr;
+    C.nc = nc;
+    C.rp.alloc((size_t)nr + 1, s);
+    C.nnz = scan_exclusive(counts, C.rp.p, nr, s);
+    C.ci.alloc((size_t)(C.nnz > 0 ? C.nnz : 1), s);
+    C.v.alloc((size_t)(C.nnz > 0 ? C.nnz : 1), s);
+    return C;
+}
+
+static void check_flag(int* flag, hipStream_t s, const char* what) {
+    int f = flag_read(flag, s);
+    if (f == 0) return;
+    flag_clear(flag, s);
+    std::string m = std::string(what) + ": ";
+    if (f == 3) throw Error(MGR_ERR_ZERO_PIVOT, m + "zero or non-finite pivot");
+    if (f == 5) throw Error(MGR_ERR_BAD_LABELS, m + "field label outside [0, 32)");
+    throw Error(MGR_ERR_UNSUPPORTED, m + "unsupported input (row too long, block larger than 4, or a_ii <= 0)");
+}
+
+static DCsr spgemm(const DCsr& A, const DCsr& B, int* flag, hipStream_t s) {
+    if (A.nc != B.nr) throw Error(MGR_ERR_ARG, "spgemm: inner dimensions differ");
+    int mr = max_row_len(A, s);
+    DArr<int> cnt((size_t)A.nr + 1, s);
+    spgemm_count(A, B, mr, cnt.p, flag, s);
+    check_flag(flag, s, "SpGEMM");
+    DCsr C = csr_from_counts(A.nr, B.nc, cnt.p, s);
+    spgemm_fill(A, B, mr, C, s);
+    return C;
+}
+
+static DCsr csr_add(const DCsr& A, const DCsr& B, hipStream_t s) {
+    DArr<int> cnt((size_t)A.nr + 1, s);
+    add_count(A, B, cnt.p, s);
+    DCsr C = csr_from_counts(A.nr, A.nc, cnt.p, s);
+    add_fill(A, B, C, s);
+    return C;
+}
+
+static DCsr csr_transpose(const DCsr& A, hipStream_t s) {
+    DArr<int> cnt((size_t)A.nc + 1, s);
+    fill_int(cnt.p, 0, A.nc + 1, s);
+    transpose_count(A, cnt.p, s);
+    DCsr T = csr_from_counts(A.nc, A.nr, cnt.p, s);
+    DArr<int> cursor((size_t)A.nc + 1, s);
+    MGR_HIP(hipMemcpyAsync(cursor.p, T.rp.p, sizeof(int) * ((size_t)A.nc + 1), hipMemcpyDeviceToDevice, s));
+    transpose_fill(A, T, cursor.p, s);
+    return T;
+}
+
+static DCsr csr_copy(const DCsr& A, hipStream_t s) {
+    DCsr C;
+    C.alloc(A.nr, A.nc, A.nnz, s);
+    MGR_HIP(hipMemcpyAsync(C.rp.p, A.rp.p, sizeof(int) * ((size_t)A.nr + 1), hipMemcpyDeviceToDevice, s));
+    if (A.nnz > 0) {
+        MGR_HIP(hipMemcpyAsync(C.ci.p, A.ci.p, sizeof(int) * A.nnz, hipMemcpyDeviceToDevice, s));
+        MGR_HIP(hipMemcpyAsync(C.v.p, A.v.p, sizeof(double) * A.nnz, hipMemcpyDeviceToDevice, s));
+    }
+    return C;
+}
+
+static void make_float(DCsr& A, hipStream_t s) {
+    if (A.vf.p || A.nr == 0) return;
+    A.vf.alloc((size_t)(A.nnz > 0 ? A.nnz : 1), s);
+    to_float(A.v.p, A.vf.p, A.nnz, s);
+}
+
+// ====================================================================== AMG
+struct AmgLevel {
+    int n = 0;
+    DCsr A, P, R, AT;        // R = P^T; AT = A^T for the transposed cycle
+    DArr<int> cf, label;
+    DArr<double> dinv;
+    DArr<float> dinvf;
+    DArr<double> rd, td, bd, xd;
+    DArr<float> rf, tf, bf, xf;
+};
+
+struct Amg {
+    std::vector<AmgLevel> lv;
+    DArr<double> cinv, cinvT;
+    DArr<float> cinvf, cinvTf;
+    int nc = 0, nu_pre = 1, nu_post = 1;
+    bool have_float = false, have_trans = false;
+};
+
+// Classical AMG setup (the coarse solver of Sec. 4.1, with PMIS coarsening,
+// direct interpolation and L1-Jacobi smoothing; see the oracle for the
+// definitions): stops at n <= max_coarse, at max_levels, or when coarsening
+// stalls (no C-point or n_c > 0.9 n).  The coarsest matrix is inverted densely.
+static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o, uint64_t seed, int* flag,
+                      hipStream_t s) {
+    H.lv.clear();
+    H.nu_pre = o.nu_pre;
+    H.nu_post = o.nu_post;
+    H.lv.emplace_back();
+    int n0 = A0.nr;
+    H.lv[0].A = std::move(A0);
+    H.lv[0].n = n0;
+    if (label0) {
+        H.lv[0].label.alloc((size_t)n0, s);
+        MGR_HIP(hipMemcpyAsync(H.lv[0].label.p, label0, sizeof(int) * n0, hipMemcpyDeviceToDevice, s));
+    }
+    int k = 0;
+    for (;;) {
+        AmgLevel& L = H.lv[k];
+        const DCsr& A = L.A;
+        int n = A.nr;
+        if (n <= o.max_coarse || k + 1 >= o.max_levels) break;
+        DArr<unsigned char> strong((size_t)(A.nnz > 0 ? A.nnz : 1), s);
+        amg_strength(A, o.theta, L.label.p, strong.p, s);
+        DArr<int> lam((size_t)n + 1, s);
+        fill_int(lam.p, 0, n + 1, s);
+        amg_lambda(A, strong.p, lam.p, s);
+        // strength graph S (rows = i, cols = j in S_i) and its transpose
+        DArr<int> scnt((size_t)n + 1, s), srp((size_t)n + 1, s), trp((size_t)n + 1, s), cursor((size_t)n + 1, s);
+        strength_compact_count(A, strong.p, scnt.p, s);
+        long ns = scan_exclusive(scnt.p, srp.p, n, s);
+        DArr<int> sci((size_t)(ns > 0 ? ns : 1), s), tci((size_t)(ns > 0 ? ns : 1), s);
+        strength_compact_fill(A, strong.p, srp.p, sci.p, s);
+        scan_exclusive_async(lam.p, trp.p, n, s);
+        MGR_HIP(hipMemcpyAsync(cursor.p, trp.p, sizeof(int) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
+        pattern_transpose_fill(n, srp.p, sci.p, trp.p, cursor.p, tci.p, s);
+        // PMIS rounds
+        DArr<double> w((size_t)n, s);
+        DArr<int> cf((size_t)n, s), und(1, s);
+        DArr<unsigned char> newc((size_t)n, s);
+        pmis_init(n, lam.p, seed, k, w.p, cf.p, s);
+        for (int round = 0; round < 10000; ++round) {
+            fill_int(und.p, 0, 1, s);
+            pmis_select(n, srp.p, sci.p, trp.p, tci.p, w.p, cf.p, newc.p, s);
+            pmis_update(n, srp.p, sci.p, newc.p, cf.p, und.p, s);
+            if (read_int(und.p, s) == 0) break;
+        }
+        DArr<int> isC((size_t)n + 1, s), cidx((size_t)n + 1, s);
+        cf_is_c(n, cf.p, isC.p, s);
+        long nc = scan_exclusive(isC.p, cidx.p, n, s);
+        if (nc == 0 || (double)nc > 0.9 * (double)n) break;
+        // direct interpolation, P^T, Galerkin product P^T (A P)
+        DArr<int> pcnt((size_t)n + 1, s);
+        interp_count(A, strong.p, cf.p, pcnt.p, s);
+        DCsr P = csr_from_counts(n, (int)nc, pcnt.p, s);
+        interp_fill(A, strong.p, cf.p, cidx.p, L.label.p, P, flag, s);
+        check_flag(flag, s, "AMG interpolation");
+        DCsr R = csr_transpose(P, s);
+        DCsr AP = spgemm(A, P, flag, s);
+        DCsr Ac = spgemm(R, AP, flag, s);
+        AP = DCsr();
+        L.dinv.alloc((size_t)n, s);
+        l1_dinv(A, L.dinv.p, flag, s);
+        check_flag(flag, s, "AMG L1 diagonal");
+        L.P = std::move(P);
+        L.R = std::move(R);
+        L.cf = std::move(cf);
+        AmgLevel next;
+        next.n = (int)nc;
+        next.A = std::move(Ac);
+        if (L.label.p) {
+            DArr<int> lmap((size_t)n, s), cmap((size_t)nc, s), dummy((size_t)n, s);
+            cf_maps(n, isC.p, cidx.p, lmap.p, cmap.p, dummy.p, s);
+            next.label.alloc((size_t)nc, s);
+            gather_int((int)nc, cmap.p, L.label.p, next.label.p, s);
+        }
+        H.lv.push_back(std::move(next));
+        ++k;
+    }
+    AmgLevel& Lc = H.lv.back();
+    H.nc = Lc.n;
+    if (H.nc > 2048) throw Error(MGR_ERR_UNSUPPORTED, "AMG: coarsest level has more than 2048 unknowns");
+    int nc = H.nc;
+    DArr<double> dense((size_t)nc * nc + 1, s);
+    H.cinv.alloc((size_t)nc * nc + 1, s);
+    densify(Lc.A, dense.p, s);
+    dense_inverse(nc, dense.p, H.cinv.p, flag, s);
+    check_flag(flag, s, "AMG coarsest inverse");
+    // work vectors
+    for (size_t l = 0; l < H.lv.size(); ++l) {
+        AmgLevel& L = H.lv[l];
+        L.rd.alloc((size_t)L.n + 1, s);
+        L.td.alloc((size_t)L.n + 1, s);
+        if (l > 0) { L.bd.alloc((size_t)L.n + 1, s); L.xd.alloc((size_t)L.n + 1, s); }
+    }
+    H.have_float = false;
+    H.have_trans = false;
+}
+
+static void amg_make_float(Amg& H, hipStream_t s) {
+    if (H.have_float) return;
+    for (size_t l = 0; l < H.lv.size(); ++l) {
+        AmgLevel& L = H.lv[l];
+        make_float(L.A, s);
+        if (l + 1 < H.lv.size()) {
+            make_float(L.P, s);
+            make_float(L.R, s);
+            L.dinvf.alloc((size_t)L.n, s);
+            to_float(L.dinv.p, L.dinvf.p, L.n, s);
+        }
+        if (H.have_trans && L.AT.nr) make_float(L.AT, s);
+        L.rf.alloc((size_t)L.n + 1, s);
+        L.tf.alloc((size_t)L.n + 1, s);
+        if (l > 0) { L.bf.alloc((size_t)L.n + 1, s); L.xf.alloc((size_t)L.n + 1, s); }
+    }
+    long nn = (long)H.nc * H.nc;
+    H.cinvf.alloc((size_t)nn + 1, s);
+    to_float(H.cinv.p, H.cinvf.p, nn, s);
+    if (H.have_trans) {
+        H.cinvTf.alloc((size_t)nn + 1, s);
+        to_float(H.cinvT.p, H.cinvTf.p, nn, s);
+    }
+    H.have_float = true;
+}
+
+static void amg_make_trans(Amg& H, hipStream_t s) {
+    if (H.have_trans) return;
+    for (size_t l = 0; l + 1 < H.lv.size(); ++l) {
+        H.lv[l].AT = csr_transpose(H.lv[l].A, s);
+        if (H.have_float) make_float(H.lv[l].AT, s);
+    }
+    int nc = H.nc;
+    std::vector<double> h((size_t)nc * nc), t((size_t)nc * nc);
+    MGR_HIP(hipMemcpyAsync(h.data(), H.cinv.p, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+    MGR_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < nc; ++i)
+        for (int j = 0; j < nc; ++j) t[(size_t)j * nc + i] = h[(size_t)i * nc + j];
+    H.cinvT.alloc((size_t)nc * nc + 1, s);
+    MGR_HIP(hipMemcpyAsync(H.cinvT.p, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice, s));
+    if (H.have_float) {
+        H.cinvTf.alloc((size_t)nc * nc + 1, s);
+        to_float(H.cinvT.p, H.cinvTf.p, (long)nc * nc, s);
+    }
+    MGR_HIP(hipStreamSynchronize(s));
+    H.have_trans = true;
+}
+
+template <typename T> struct Prec;
+template <> struct Prec<double> {
+    static double* r(AmgLevel& L) { return L.rd.p; }
+    static double* t(AmgLevel& L) { return L.td.p; }
+    static double* b(AmgLevel& L) { return L.bd.p; }
+    static double* x(AmgLevel& L) { return L.xd.p; }
+    static const double* dinv(AmgLevel& L) { return L.dinv.p; }
+    static const double* cinv(Amg& H, bool tr) { return tr ? H.cinvT.p : H.cinv.p; }
+};
+template <> struct Prec<float> {
+    static float* r(AmgLevel& L) { return L.rf.p; }
+    static float* t(AmgLevel& L) { return L.tf.p; }
+    static float* b(AmgLevel& L) { return L.bf.p; }
+    static float* x(AmgLevel& L) { return L.xf.p; }
+    static const float* dinv(AmgLevel& L) { return L.dinvf.p; }
+    static const float* cinv(Amg& H, bool tr) { return tr ? H.cinvTf.p : H.cinvf.p; }
+};
+
+// V(nu_pre, nu_post) cycle from x = 0 with L1-Jacobi smoothing; the transposed
+// cycle uses A^T on every level, swaps the sweep counts and applies the
+// transposed coarsest inverse (the exact adjoint of the forward cycle).
+template <typename T>
+static void amg_vcycle(Amg& H, int k, const T* b, T* x, bool tr, hipStream_t s) {
+    AmgLevel& L = H.lv[k];
+    int n = L.n;
+    if (k + 1 == (int)H.lv.size()) {
+        dense_gemv<T, T>(n, Prec<T>::cinv(H, tr), b, x, s);
+        return;
+    }
+    SpOp<T> A = view<T>(tr ? L.AT : L.A);
+    const T* dinv = Prec<T>::dinv(L);
+    T* r = Prec<T>::r(L);
+    T* t = Prec<T>::t(L);
+    int npre = tr ? H.nu_post : H.nu_pre, npost = tr ? H.nu_pre : H.nu_post;
+    if (npre >= 1) {
+        presmooth<T>(A, dinv, b, x, r, s);
+        if (npre > 1) {
+            for (int q = 1; q < npre; ++q) {
+                jacobi_sweep<T>(A, dinv, b, x, t, s);
+                copy<T, T>(n, t, x, s);
+            }
+            spmv<T, T, T, T, T>(A, x, (const T*)nullptr, INT_MAX, b, r, T(-1), T(1), s);
+        }
+    } else {
+        set<T>(n, x, T(0), s);
+        copy<T, T>(n, b, r, s);
+    }
+    AmgLevel& Lc = H.lv[k + 1];
+    T* bc = Prec<T>::b(Lc);
+    T* xc = Prec<T>::x(Lc);
+    spmv<T, T, T, T, T>(view<T>(L.R), r, (const T*)nullptr, INT_MAX, (const T*)nullptr, bc, T(1), T(0), s);
+    amg_vcycle<T>(H, k + 1, bc, xc, tr, s);
+    SpOp<T> P = view<T>(L.P);
+    if (npost == 0) {
+        spmv<T, T, T, T, T>(P, xc, (const T*)nullptr, INT_MAX, x, x, T(1), T(1), s);
+        return;
+    }
+    // prolongate into the buffer from which an odd/even number of out-of-place
+    // sweeps ends in x
+    T* src = (npost % 2 == 1) ? t : x;
+    spmv<T, T, T, T, T>(P, xc, (const T*)nullptr, INT_MAX, x, src, T(1), T(1), s);
+    T* other = (src == x) ? t : x;
+    for (int q = 0; q < npost; ++q) {
+        jacobi_sweep<T>(A, dinv, b, src, other, s);
+        std::swap(src, other);
+    }
+}
+
+// ====================================================================== MGR levels
+struct MgrLevel {
+    int n = 0, nF = 0, nC = 0;
+    mgr_level_opts o{};
+    bool fused = false;
+    DArr<int> isF, lmap, fmap, cmap;
+    DCsr AFF, AFC, ACF, ACC, M, PF, RF, W;   // W = A_CF M
+    DCsr RJ, PJ, RJt, PJt;                   // operators of the fused one-sweep apply
+    DCsr Aout;                               // coarse operator (input of the next level; the
+                                             // last level's is owned by the coarse AMG)
+    DCsr AFFt, ACFt, PFt, RFt, Mt;           // general transposed apply
+    bool have_float = false, have_trans = false;
+    std::unique_ptr<Amg> famg;
+    // level vectors: coarse input / output (the next level's v and z)
+    DArr<double> rcd, ecd, vFd, vCd, zFd, rFd, tFd;
+    DArr<float> rcf, ecf, vFf, vCf, zFf, rFf, tFf;
+};
+
+struct Ctx {
+    hipStream_t s = nullptr;
+    mgr_opts o{};
+    std::string err;
+    bool ready = false;
+    int b = 1, nbr = 0, n = 0;
+    long nnzb = 0;
+    DArr<int> Arp, Aci, ATrp, ATci;
+    DArr<double> Av, ATv;
+    DCsr A0, A0t;      // scalar level-0 operator (b = 1: the CSR input)
+    bool have_At = false;
+    std::vector<MgrLevel> L;
+    Amg camg;
+    DArr<int> flag;
+    // Krylov workspace
+    int kr_m = 0;
+    long kr_n = 0;
+    DArr<double> V, Z, hbuf, part, yd;
+    DArr<double> apply_tmp;
+};
+
+static bool fused_ok(const mgr_level_opts& o) {
+    return o.sweeps == 1 && o.restrict_type == MGR_RESTRICT_INJECTION &&
+           (o.frelax == MGR_FRELAX_JACOBI || o.frelax == MGR_FRELAX_BLOCK_JACOBI);
+}
+
+// One MGR level (Sec. 2): C/F split by field, blocks A_FF, A_FC, A_CF, A_CC,
+// F-relaxation operator M, P_F = -M A_FC, R_F = -A_CF M (Jacobi restriction),
+// coarse operator A_c = A_CC + A_CF P_F (+ R_F A_FC + R_F (A_FF P_F)).
+static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr& A, const int* field, const int* block,
+                            const mgr_level_opts& o, int lev) {
+    hipStream_t s = c.s;
+    int n = A.nr;
+    l.n = n;
+    l.o = o;
+    l.isF.alloc((size_t)n + 1, s);
+    l.lmap.alloc((size_t)n + 1, s);
+    DArr<int> fpos((size_t)n + 1, s);
+    cf_flags(n, field, o.f_field_mask, l.isF.p, c.flag.p, s);
+    check_flag(c.flag.p, s, "C/F split");
+    long nF = scan_exclusive(l.isF.p, fpos.p, n, s);
+    l.nF = (int)nF;
+    l.nC = n - l.nF;
+    if (l.nF == 0 || l.nC == 0)
+        throw Error(MGR_ERR_BAD_LABELS, "MGR level " + std::to_string(lev) + ": empty F or C set");
+    l.fmap.alloc((size_t)l.nF, s);
+    l.cmap.alloc((size_t)l.nC, s);
+    cf_maps(n, l.isF.p, fpos.p, l.lmap.p, l.fmap.p, l.cmap.p, s);
+    // block extraction
+    DArr<int> cFF((size_t)l.nF + 1, s), cFC((size_t)l.nF + 1, s), cCF((size_t)l.nC + 1, s), cCC((size_t)l.nC + 1, s);
+    extract_count(A, l.isF.p, l.lmap.p, cFF.p, cFC.p, cCF.p, cCC.p, s);
+    l.AFF = csr_from_counts(l.nF, l.nF, cFF.p, s);
+    l.AFC = csr_from_counts(l.nF, l.nC, cFC.p, s);
+    l.ACF = csr_from_counts(l.nC, l.nF, cCF.p, s);
+    l.ACC = csr_from_counts(l.nC, l.nC, cCC.p, s);
+    extract_fill(A, l.isF.p, l.lmap.p, l.AFF, l.AFC, l.ACF, l.ACC, s);
+    // F-relaxation operator (Jacobi: 1x1 blocks; block-Jacobi: F-points of one block row)
+    {
+        DArr<int> bid, flagk((size_t)l.nF + 1, s), excl((size_t)l.nF + 1, s), bnum((size_t)l.nF, s),
+            len((size_t)l.nF + 1, s);
+        const int* bidp = nullptr;
+        if (o.frelax == MGR_FRELAX_BLOCK_JACOBI) {
+            bid.alloc((size_t)l.nF, s);
+            gather_int(l.nF, l.fmap.p, block, bid.p, s);
+            bidp = bid.p;
+        }
+        frelax_block_flags(l.nF, bidp, flagk.p, s);
+        long nb = scan_exclusive(flagk.p, excl.p, l.nF, s);
+        DArr<int> bstart((size_t)nb + 1, s);
+        frelax_block_starts(l.nF, flagk.p, excl.p, bstart.p, bnum.p, s);
+        frelax_row_len(l.nF, bnum.p, bstart.p, len.p, s);
+        l.M = csr_from_counts(l.nF, l.nF, len.p, s);
+        frelax_fill((int)nb, bstart.p, l.AFF, l.M, c.flag.p, s);
+        check_flag(c.flag.p, s, "F-relaxation operator");
+    }
+    if (o.frelax == MGR_FRELAX_ILU0)
+        throw Error(MGR_ERR_UNSUPPORTED, "ILU(0) F-relaxation is not available in the GPU library");
+    if (o.frelax == MGR_FRELAX_AMG) {
+        l.famg.reset(new Amg());
+        mgr_amg_opts fo = c.o.amg;
+        fo.unknown_based = o.amg_unknown_based;
+        DArr<int> flab;
+        if (o.amg_unknown_based) {
+            flab.alloc((size_t)l.nF, s);
+            gather_int(l.nF, l.fmap.p, field, flab.p, s);
+        }
+        amg_setup(*l.famg, csr_copy(l.AFF, s), o.amg_unknown_based ? flab.p : nullptr, fo,
+                  c.o.amg.seed + 0x1000193ULL * (uint64_t)(lev + 1), c.flag.p, s);
+    }
+    // transfer operators and coarse operator (Petrov-Galerkin R A P)
+    l.PF = spgemm(l.M, l.AFC, c.flag.p, s);
+    negate(l.PF.v.p, l.PF.nnz, s);
+    l.W = spgemm(l.ACF, l.M, c.flag.p, s);
+    if (o.restrict_type == MGR_RESTRICT_JACOBI) {
+        l.RF = csr_copy(l.W, s);
+        negate(l.RF.v.p, l.RF.nnz, s);
+    }
+    DCsr T1 = spgemm(l.ACF, l.PF, c.flag.p, s);
+    DCsr Ac = csr_add(l.ACC, T1, s);
+    T1 = DCsr();
+    if (o.restrict_type == MGR_RESTRICT_JACOBI) {
+        DCsr T2 = spgemm(l.RF, l.AFC, c.flag.p, s);
+        DCsr S2 = csr_add(Ac, T2, s);
+        T2 = DCsr();
+        DCsr FFP = spgemm(l.AFF, l.PF, c.flag.p, s);
+        DCsr T3 = spgemm(l.RF, FFP, c.flag.p, s);
+        FFP = DCsr();
+        Ac = csr_add(S2, T3, s);
+    }
+    // fused one-sweep apply: r_c = [-omega A_CF M | I] v ; z = [P_F | omega M] [e_c ; v]
+    l.fused = fused_ok(o);
+    if (l.fused) {
+        DArr<int> len((size_t)n + 1, s);
+        rj_count(l.nC, l.W, len.p, s);
+        l.RJ = csr_from_counts(l.nC, n, len.p, s);
+        rj_fill(l.nC, l.W, -o.omega, l.fmap.p, l.cmap.p, l.RJ, s);
+        pj_count(n, l.isF.p, l.lmap.p, l.PF, l.M, len.p, s);
+        l.PJ = csr_from_counts(n, l.nC + n, len.p, s);
+        pj_fill(n, l.nC, l.isF.p, l.lmap.p, l.PF, 1.0, l.M, o.omega, l.fmap.p, l.PJ, s);
+    }
+    // level vectors
+    l.rcd.alloc((size_t)l.nC + 1, s);
+    l.ecd.alloc((size_t)l.nC + 1, s);
+    if (!l.fused) {
+        l.vFd.alloc((size_t)l.nF + 1, s); l.vCd.alloc((size_t)l.nC + 1, s);
+        l.zFd.alloc((size_t)l.nF + 1, s); l.rFd.alloc((size_t)l.nF + 1, s); l.tFd.alloc((size_t)l.nF + 1, s);
+    }
+    return Ac;
+}
+
+static void mgr_level_make_trans(Ctx& c, MgrLevel& l) {
+    if (l.have_trans) return;
+    hipStream_t s = c.s;
+    if (l.o.sweeps != 1)
+        throw Error(MGR_ERR_UNSUPPORTED, "transposed MGR apply needs one F-relaxation sweep per level");
+    if (l.fused) {
+        // r_c = [P_F^T | I] u ; z = [-omega W^T | omega M^T] [e ; u]
+        DCsr PFt = csr_transpose(l.PF, s);
+        DCsr Wt = csr_transpose(l.W, s);
+        DCsr Mt = csr_transpose(l.M, s);
+        DArr<int> len((size_t)l.n + 1, s);
+        rj_count(l.nC, PFt, len.p, s);
+        l.RJt = csr_from_counts(l.nC, l.n, len.p, s);
+        rj_fill(l.nC, PFt, 1.0, l.fmap.p, l.cmap.p, l.RJt, s);
+        pj_count(l.n, l.isF.p, l.lmap.p, Wt, Mt, len.p, s);
+        l.PJt = csr_from_counts(l.n, l.nC + l.n, len.p, s);
+        pj_fill(l.n, l.nC, l.isF.p, l.lmap.p, Wt, -l.o.omega, Mt, l.o.omega, l.fmap.p, l.PJt, s);
+        if (l.have_float) { make_float(l.RJt, s); make_float(l.PJt, s); }
+    } else {
+        l.AFFt = csr_transpose(l.AFF, s);
+        l.ACFt = csr_transpose(l.ACF, s);
+        l.PFt = csr_transpose(l.PF, s);
+        l.Mt = csr_transpose(l.M, s);
+        if (l.o.restrict_type == MGR_RESTRICT_JACOBI) l.RFt = csr_transpose(l.RF, s);
+        if (l.have_float) {
+            make_float(l.AFFt, s); make_float(l.ACFt, s); make_float(l.PFt, s); make_float(l.Mt, s);
+            if (l.RFt.nr) make_float(l.RFt, s);
+        }
+    }
+    if (l.famg) amg_make_trans(*l.famg, s);
+    l.have_trans = true;
+}
+
+static void mgr_level_make_float(Ctx& c, MgrLevel& l) {
+    if (l.have_float) return;
+    hipStream_t s = c.s;
+    if (l.fused) {
+        make_float(l.RJ, s); make_float(l.PJ, s);
+        if (l.have_trans) { make_float(l.RJt, s); make_float(l.PJt, s); }
+    } else {
+        make_float(l.AFF, s); make_float(l.ACF, s); make_float(l.PF, s); make_float(l.M, s);
+        if (l.RF.nr) make_float(l.RF, s);
+        if (l.have_trans) {
+            make_float(l.AFFt, s); make_float(l.ACFt, s); make_float(l.PFt, s); make_float(l.Mt, s);
+            if (l.RFt.nr) make_float(l.RFt, s);
+        }
+        l.vFf.alloc((size_t)l.nF + 1, s); l.vCf.alloc((size_t)l.nC + 1, s);
+        l.zFf.alloc((size_t)l.nF + 1, s); l.rFf.alloc((size_t)l.nF + 1, s); l.tFf.alloc((size_t)l.nF + 1, s);
+    }
+    l.rcf.alloc((size_t)l.nC + 1, s);
+    l.ecf.alloc((size_t)l.nC + 1, s);
+    if (l.famg) amg_make_float(*l.famg, s);
+    l.have_float = true;
+}
+
+template <typename T> struct LV;
+template <> struct LV<double> {
+    static double* rc(MgrLevel& l) { return l.rcd.p; }
+    static double* ec(MgrLevel& l) { return l.ecd.p; }
+    static double* vF(MgrLevel& l) { return l.vFd.p; }
+    static double* vC(MgrLevel& l) { return l.vCd.p; }
+    static double* zF(MgrLevel& l) { return l.zFd.p; }
+    static double* rF(MgrLevel& l) { return l.rFd.p; }
+    static double* tF(MgrLevel& l) { return l.tFd.p; }
+};
+template <> struct LV<float> {
+    static float* rc(MgrLevel& l) { return l.rcf.p; }
+    static float* ec(MgrLevel& l) { return l.ecf.p; }
+    static float* vF(MgrLevel& l) { return l.vFf.p; }
+    static float* vC(MgrLevel& l) { return l.vCf.p; }
+    static float* zF(MgrLevel& l) { return l.zFf.p; }
+    static float* rF(MgrLevel& l) { return l.rFf.p; }
+    static float* tF(MgrLevel& l) { return l.tFf.p; }
+};
+
+// tF = M_FF^{-1} rF (trans: M_FF^{-T}) for Jacobi / block-Jacobi / AMG F-relaxation
+template <typename T>
+static void frelax_apply(MgrLevel& l, const T* rF, T* tF, bool tr, hipStream_t s) {
+    if (l.o.frelax == MGR_FRELAX_AMG) {
+        amg_vcycle<T>(*l.famg, 0, rF, tF, tr, s);
+        return;
+    }
+    spmv<T, T, T, T, T>(view<T>(tr ? l.Mt : l.M), rF, (const T*)nullptr, INT_MAX, (const T*)nullptr, tF, T(1),
+                        T(0), s);
+}
+
+template <typename T>
+static void mgr_apply_rec(Ctx& c, int lev, const void* vin, void* zout, bool tr);
+
+// Algorithm 1 at level `lev` with working precision T; VT is the type of v and
+// z at this level (FP64 at level 0, T below).
+template <typename T, typename VT>
+static void mgr_level_apply(Ctx& c, int lev, const VT* v, VT* z, bool tr) {
+    hipStream_t s = c.s;
+    MgrLevel& l = c.L[lev];
+    T* rc = LV<T>::rc(l);
+    T* ec = LV<T>::ec(l);
+    if (l.fused) {
+        SpOp<T> R = view<T>(tr ? l.RJt : l.RJ);
+        SpOp<T> P = view<T>(tr ? l.PJt : l.PJ);
+        spmv<T, VT, VT, T, T>(R, v, (const VT*)nullptr, INT_MAX, (const T*)nullptr, rc, T(1), T(0), s);
+        mgr_apply_rec<T>(c, lev + 1, rc, ec, tr);
+        spmv<T, T, VT, VT, VT>(P, ec, v, l.nC, (const VT*)nullptr, z, T(1), T(0), s);
+        return;
+    }
+    T* vF = LV<T>::vF(l);
+    T* vC = LV<T>::vC(l);
+    T* zF = LV<T>::zF(l);
+    T* rF = LV<T>::rF(l);
+    T* tF = LV<T>::tF(l);
+    T om = (T)l.o.omega;
+    gather<VT, T>(l.nF, l.fmap.p, v, vF, s);
+    gather<VT, T>(l.nC, l.cmap.p, v, vC, s);
+    if (!tr) {
+        // F-relaxation sweeps from z = 0 (the C part of z stays 0 meanwhile)
+        for (int q = 0; q < l.o.sweeps; ++q) {
+            const T* res = vF;
+            if (q > 0) {
+                spmv<T, T, T, T, T>(view<T>(l.AFF), zF, (const T*)nullptr, INT_MAX, vF, rF, T(-1), T(1), s);
+                res = rF;
+            }
+            frelax_apply<T>(l, res, tF, false, s);
+            axpby<T>(l.nF, om, tF, q == 0 ? T(0) : T(1), zF, s);
+        }
+        // restriction: r_c = v_C - A_CF z_F (+ R_F (v_F - A_FF z_F))
+        spmv<T, T, T, T, T>(view<T>(l.ACF), zF, (const T*)nullptr, INT_MAX, vC, rc, T(-1), T(1), s);
+        if (l.o.restrict_type == MGR_RESTRICT_JACOBI) {
+            spmv<T, T, T, T, T>(view<T>(l.AFF), zF, (const T*)nullptr, INT_MAX, vF, rF, T(-1), T(1), s);
+            spmv<T, T, T, T, T>(view<T>(l.RF), rF, (const T*)nullptr, INT_MAX, rc, rc, T(1), T(1), s);
+        }
+        mgr_apply_rec<T>(c, lev + 1, rc, ec, false);
+        // interpolation and correction: z_F += P_F e_c ; z_C = e_c
+        spmv<T, T, T, T, T>(view<T>(l.PF), ec, (const T*)nullptr, INT_MAX, zF, zF, T(1), T(1), s);
+    } else {
+        // u_c = v_C + P_F^T v_F ; e = C^T u_c ; y_F = R_F^T e ;
+        // z_F = y_F + omega M^T (v_F - A_FF^T y_F - A_CF^T e) ; z_C = e
+        spmv<T, T, T, T, T>(view<T>(l.PFt), vF, (const T*)nullptr, INT_MAX, vC, rc, T(1), T(1), s);
+        mgr_apply_rec<T>(c, lev + 1, rc, ec, true);
+        spmv<T, T, T, T, T>(view<T>(l.ACFt), ec, (const T*)nullptr, INT_MAX, vF, rF, T(-1), T(1), s);
+        bool jr = (l.o.restrict_type == MGR_RESTRICT_JACOBI);
+        if (jr) {
+            spmv<T, T, T, T, T>(view<T>(l.RFt), ec, (const T*)nullptr, INT_MAX, (const T*)nullptr, zF, T(1), T(0), s);
+            spmv<T, T, T, T, T>(view<T>(l.AFFt), zF, (const T*)nullptr, INT_MAX, rF, rF, T(-1), T(1), s);
+        }
+        frelax_apply<T>(l, rF, tF, true, s);
+        axpby<T>(l.nF, om, tF, jr ? T(1) : T(0), zF, s);
+    }
+    scatter<T, VT>(l.nF, l.fmap.p, zF, z, s);
+    scatter<T, VT>(l.nC, l.cmap.p, ec, z, s);
+}
+
+template <typename T>
+static void mgr_apply_rec(Ctx& c, int lev, const void* vin, void* zout, bool tr) {
+    if (lev == (int)c.L.size()) {
+        amg_vcycle<T>(c.camg, 0, (const T*)vin, (T*)zout, tr, c.s);
+        return;
+    }
+    if (lev == 0)
+        mgr_level_apply<T, double>(c, 0, (const double*)vin, (double*)zout, tr);
+    else
+        mgr_level_apply<T, T>(c, lev, (const T*)vin, (T*)zout, tr);
+}
+
+// z = M^{-1} v (or M^{-T} v), FP64 in and out whatever the apply precision.
+static void mgr_apply_top(Ctx& c, const double* v, double* z, bool tr) {
+    if (!c.ready) throw Error(MGR_ERR_ARG, "apply before setup");
+    if (tr) {
+        for (auto& l : c.L) mgr_level_make_trans(c, l);
+        amg_make_trans(c.camg, c.s);
+    }
+    bool f32 = (c.o.apply_precision == 32);
+    if (f32) {
+        for (auto& l : c.L) mgr_level_make_float(c, l);
+        amg_make_float(c.camg, c.s);
+    }
+    if (c.L.empty()) {
+        // no reduction level: the preconditioner is the AMG cycle on A itself
+        if (f32) {
+            if (!c.apply_tmp.p) c.apply_tmp.alloc((size_t)c.n * 2 + 2, c.s);
+            float* vf = reinterpret_cast<float*>(c.apply_tmp.p);
+            float* zf = vf + c.n + 1;
+            copy<double, float>(c.n, v, vf, c.s);
+            amg_vcycle<float>(c.camg, 0, vf, zf, tr, c.s);
+            copy<float, double>(c.n, zf, z, c.s);
+        } else {
+            amg_vcycle<double>(c.camg, 0, v, z, tr, c.s);
+        }
+        return;
+    }
+    if (f32) mgr_apply_rec<float>(c, 0, v, z, tr);
+    else mgr_apply_rec<double>(c, 0, v, z, tr);
+}
+
+static void ensure_At(Ctx& c) {
+    if (c.have_At) return;
+    hipStream_t s = c.s;
+    if (c.b == 1) {
+        c.A0t = csr_transpose(c.A0, s);
+    } else {
+        c.ATrp.alloc((size_t)c.nbr + 1, s);
+        c.ATci.alloc((size_t)(c.nnzb > 0 ? c.nnzb : 1), s);
+        c.ATv.alloc((size_t)(c.nnzb > 0 ? c.nnzb : 1) * c.b * c.b, s);
+        bsr_transpose_blocks(c.b, c.nbr, c.Arp.p, c.Aci.p, c.Av.p, c.ATrp.p, c.ATci.p, c.ATv.p, s);
+    }
+    MGR_HIP(hipStreamSynchronize(s));
+    c.have_At = true;
+}
+
+// y = alpha * op(A) x + beta * w in FP64 (block SpMV on the input layout)
+static void matvec(Ctx& c, bool tr, const double* x, const double* w, double* y, double alpha, double beta) {
+    if (tr) ensure_At(c);
+    if (c.b == 1) {
+        spmv<double, double, double, double, double>(view<double>(tr ? c.A0t : c.A0), x, (const double*)nullptr,
+                                                     INT_MAX, w, y, alpha, beta, c.s);
+    } else {
+        bsr_spmv(c.b, c.nbr, tr ? c.ATrp.p : c.Arp.p, tr ? c.ATci.p : c.Aci.p, tr ? c.ATv.p : c.Av.p, c.nnzb, x, w,
+                 y, alpha, beta, c.s);
+    }
+}
+
+// ====================================================================== FGMRES
+static void ensure_krylov(Ctx& c) {
+    int m = c.o.restart;
+    if (c.kr_m == m && c.kr_n == c.n && c.V.p) return;
+    hipStream_t s = c.s;
+    c.V.alloc((size_t)(m + 1) * c.n, s);
+    c.Z.alloc((size_t)m * c.n, s);
+    c.hbuf.alloc(256, s);
+    c.part.alloc((size_t)(m + 2) * KRYLOV_PARTS, s);
+    c.yd.alloc(64, s);
+    c.kr_m = m;
+    c.kr_n = c.n;
+}
+
+// Flexible GMRES(m) with right preconditioning (Saad 1993): x0 = 0, CGS2
+// Arnoldi, Givens rotations on the host, stop when |g_{j+1}| <= rtol ||b||,
+// then the true residual ||b - A x|| is checked and the cycle restarted if needed.
+static int fgmres(Ctx& c, bool tr, const double* b, double* x, mgr_solve_info* info) {
+    hipStream_t s = c.s;
+    ensure_krylov(c);
+    const long n = c.n;
+    const int m = c.o.restart;
+    double* V = c.V.p;
+    double* Z = c.Z.p;
+    double* hb = c.hbuf.p;  // [0,64): h1, [64,128): h2, [128]: ||w||^2, [129]: scratch
+    double hh[130];
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    set<double>(n, x, 0.0, s);
+    mdot(n, b, n, 1, b, c.part.p, hb + 129, s);
+    MGR_HIP(hipMemcpyAsync(hh + 129, hb + 129, sizeof(double), hipMemcpyDeviceToHost, s));
+    MGR_HIP(hipStreamSynchronize(s));
+    double bnorm = std::sqrt(hh[129]);
+    mgr_solve_info inf{};
+    if (bnorm == 0.0) {
+        inf.status = MGR_OK;
+        if (info) *info = inf;
+        return MGR_OK;
+    }
+    int iters = 0;
+    bool converged = false;
+    double est = 1.0, truer = 1.0;
+    bool first = true;
+    for (int cycle = 0;; ++cycle) {
+        // V_0 = b - A x
+        if (first) copy<double, double>(n, b, V, s);
+        else matvec(c, tr, x, b, V, -1.0, 1.0);
+        first = false;
+        mdot(n, V, n, 1, V, c.part.p, hb + 129, s);
+        MGR_HIP(hipMemcpyAsync(hh + 129, hb + 129, sizeof(double), hipMemcpyDeviceToHost, s));
+        MGR_HIP(hipStreamSynchronize(s));
+        double beta = std::sqrt(hh[129]);
+        if (beta <= c.o.rtol * bnorm) {
+            converged = true;
+            est = truer = beta / bnorm;
+            break;
+        }
+        if (cycle > 0) inf.restarts++;
+        scale(n, 1.0 / beta, V, s);
+        std::fill(g.begin(), g.end(), 0.0);
+        std::fill(H.begin(), H.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        for (int j = 0; j < m; ++j) {
+            double* vj = V + (long)j * n;
+            double* zj = Z + (long)j * n;
+            double* w = V + (long)(j + 1) * n;
+            mgr_apply_top(c, vj, zj, tr);
+            matvec(c, tr, zj, nullptr, w, 1.0, 0.0);
+            // classical Gram-Schmidt, twice
+            mdot(n, V, n, j + 1, w, c.part.p, hb, s);
+            maxpy(n, V, n, j + 1, hb, 1.0, w, c.part.p, nullptr, s);
+            mdot(n, V, n, j + 1, w, c.part.p, hb + 64, s);
+            maxpy(n, V, n, j + 1, hb + 64, 1.0, w, c.part.p, hb + 128, s);
+            MGR_HIP(hipMemcpyAsync(hh, hb, sizeof(double) * 129, hipMemcpyDeviceToHost, s));
+            MGR_HIP(hipStreamSynchronize(s));
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[64 + i];
+            double hn = std::sqrt(hh[128]);
+            H[(size_t)(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                double a0 = H[(size_t)i * m + j], a1 = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a0 + sn[i] * a1;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a0 + cs[i] * a1;
+            }
+            double a0 = H[(size_t)j * m + j], a1 = H[(size_t)(j + 1) * m + j];
+            double den = std::sqrt(a0 * a0 + a1 * a1);
+            if (den == 0.0) { cs[j] = 1.0; sn[j] = 0.0; }
+            else { cs[j] = a0 / den; sn[j] = a1 / den; }
+            H[(size_t)j * m + j] = cs[j] * a0 + sn[j] * a1;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++iters;
+            k = j + 1;
+            est = std::fabs(g[j + 1]) / bnorm;
+            if (hn == 0.0) break;
+            scale(n, 1.0 / hn, w, s);
+            if (std::fabs(g[j + 1]) <= c.o.rtol * bnorm || iters >= c.o.maxiter) break;
+        }
+        for (int i = k - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int q = i + 1; q < k; ++q) t -= H[(size_t)i * m + q] * y[q];
+            y[i] = t / H[(size_t)i * m + i];
+        }
+        MGR_HIP(hipMemcpyAsync(c.yd.p, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+        maxpy(n, Z, n, k, c.yd.p, -1.0, x, c.part.p, nullptr, s);
+        // true residual
+        double* r = V;
+        matvec(c, tr, x, b, r, -1.0, 1.0);
+        mdot(n, r, n, 1, r, c.part.p, hb + 129, s);
+        MGR_HIP(hipMemcpyAsync(hh + 129, hb + 129, sizeof(double), hipMemcpyDeviceToHost, s));
+        MGR_HIP(hipStreamSynchronize(s));
+        truer = std::sqrt(hh[129]) / bnorm;
+        if (truer <= c.o.rtol) { converged = true; break; }
+        if (iters >= c.o.maxiter) break;
+        first = false;
+    }
+    inf.iterations = iters;
+    inf.rel_res_est = est;
+    inf.rel_res_true = truer;
+    inf.status = converged ? MGR_OK : MGR_NOT_CONVERGED;
+    if (info) *info = inf;
+    return inf.status;
+}
+
+// ====================================================================== setup
+static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nlevels, const mgr_level_opts* lvl) {
+    hipStream_t s = c.s;
+    if (!A || !field) throw Error(MGR_ERR_ARG, "null matrix or field array");
+    if (A->block_size < 1 || A->block_size > 4) throw Error(MGR_ERR_ARG, "block_size must be 1..4");
+    if (A->n_block_rows <= 0 || !A->row_ptr || !A->col_idx || !A->values) throw Error(MGR_ERR_ARG, "empty matrix");
+    if (nlevels < 0 || nlevels > 8 || (nlevels > 0 && !lvl)) throw Error(MGR_ERR_ARG, "nlevels must be 0..8");
+    if (c.o.restart < 1 || c.o.restart > 63) throw Error(MGR_ERR_ARG, "restart must be 1..63");
+    for (int l = 0; l < nlevels; ++l) {
+        if (lvl[l].sweeps < 1) throw Error(MGR_ERR_ARG, "sweeps must be >= 1");
+        if (lvl[l].frelax < 0 || lvl[l].frelax > 3) throw Error(MGR_ERR_ARG, "unknown F-relaxation");
+        if (lvl[l].restrict_type < 0 || lvl[l].restrict_type > 1) throw Error(MGR_ERR_ARG, "unknown restriction");
+        if (lvl[l].f_field_mask == 0) throw Error(MGR_ERR_BAD_LABELS, "empty F-field mask");
+    }
+    c.ready = false;
+    c.L.clear();
+    c.camg = Amg();
+    c.have_At = false;
+    c.b = A->block_size;
+    c.nbr = A->n_block_rows;
+    c.n = c.b * c.nbr;
+    c.Arp.alloc((size_t)c.nbr + 1, s);
+    MGR_HIP(hipMemcpyAsync(c.Arp.p, A->row_ptr, sizeof(int) * ((size_t)c.nbr + 1), hipMemcpyDeviceToDevice, s));
+    c.nnzb = read_int(c.Arp.p + c.nbr, s);
+    if (c.nnzb <= 0) throw Error(MGR_ERR_ARG, "matrix has no entries");
+    long bb = (long)c.b * c.b;
+    c.Aci.alloc((size_t)c.nnzb, s);
+    c.Av.alloc((size_t)c.nnzb * bb, s);
+    MGR_HIP(hipMemcpyAsync(c.Aci.p, A->col_idx, sizeof(int) * c.nnzb, hipMemcpyDeviceToDevice, s));
+    MGR_HIP(hipMemcpyAsync(c.Av.p, A->values, sizeof(double) * c.nnzb * bb, hipMemcpyDeviceToDevice, s));
+    if (c.nnzb * bb > INT_MAX) throw Error(MGR_ERR_UNSUPPORTED, "more than 2^31 scalar entries");
+    // scalar operator of level 0
+    c.A0.alloc(c.n, c.n, c.nnzb * bb, s);
+    if (c.b == 1) {
+        MGR_HIP(hipMemcpyAsync(c.A0.rp.p, c.Arp.p, sizeof(int) * ((size_t)c.n + 1), hipMemcpyDeviceToDevice, s));
+        MGR_HIP(hipMemcpyAsync(c.A0.ci.p, c.Aci.p, sizeof(int) * c.nnzb, hipMemcpyDeviceToDevice, s));
+        MGR_HIP(hipMemcpyAsync(c.A0.v.p, c.Av.p, sizeof(double) * c.nnzb, hipMemcpyDeviceToDevice, s));
+    } else {
+        bsr_expand(c.b, c.nbr, c.Arp.p, c.Aci.p, c.Av.p, c.A0.rp.p, c.A0.ci.p, c.A0.v.p, s);
+    }
+    DArr<int> fld((size_t)c.n, s), blk((size_t)c.n, s);
+    MGR_HIP(hipMemcpyAsync(fld.p, field, sizeof(int) * c.n, hipMemcpyDeviceToDevice, s));
+    iota_div(c.n, c.b, blk.p, s);
+    const DCsr* cur = &c.A0;
+    DCsr next;
+    c.L.resize(nlevels);
+    for (int l = 0; l < nlevels; ++l) {
+        DCsr Ac = mgr_setup_level(c, c.L[l], *cur, fld.p, blk.p, lvl[l], l);
+        MgrLevel& L = c.L[l];
+        DArr<int> f2((size_t)L.nC, s), b2((size_t)L.nC, s);
+        gather_int(L.nC, L.cmap.p, fld.p, f2.p, s);
+        gather_int(L.nC, L.cmap.p, blk.p, b2.p, s);
+        fld = std::move(f2);
+        blk = std::move(b2);
+        if (l + 1 < nlevels) {
+            L.Aout = std::move(Ac);
+            cur = &L.Aout;
+        } else {
+            next = std::move(Ac);
+            cur = &next;
+        }
+    }
+    amg_setup(c.camg, nlevels > 0 ? std::move(next) : csr_copy(c.A0, s), c.o.amg.unknown_based ? fld.p : nullptr,
+              c.o.amg, c.o.amg.seed, c.flag.p, s);
+    if (c.o.apply_precision == 32) {
+        for (auto& l : c.L) mgr_level_make_float(c, l);
+        amg_make_float(c.camg, s);
+    }
+    MGR_HIP(hipStreamSynchronize(s));
+    c.ready = true;
+}
+
+// ====================================================================== export
+static void export_csr(const DCsr& A, int64_t* sizes, void* b0, void* b1, void* b2, hipStream_t s) {
+    sizes[0] = A.nr;
+    sizes[1] = A.nc;
+    sizes[2] = A.nnz;
+    if (b0 && A.rp.p) MGR_HIP(hipMemcpyAsync(b0, A.rp.p, sizeof(int) * ((size_t)A.nr + 1), hipMemcpyDeviceToHost, s));
+    if (b1 && A.nnz > 0) MGR_HIP(hipMemcpyAsync(b1, A.ci.p, sizeof(int) * A.nnz, hipMemcpyDeviceToHost, s));
+    if (b2 && A.nnz > 0) MGR_HIP(hipMemcpyAsync(b2, A.v.p, sizeof(double) * A.nnz, hipMemcpyDeviceToHost, s));
+    MGR_HIP(hipStreamSynchronize(s));
+}
+
+static int do_export(Ctx& c, int kind, int level, int what, int sub, int64_t* sizes, void* b0, void* b1,
+                     void* b2) {
+    hipStream_t s = c.s;
+    if (!c.ready) throw Error(MGR_ERR_ARG, "export before setup");
+    if (kind == 0) {
+        if (level < 0 || level >= (int)c.L.size()) throw Error(MGR_ERR_ARG, "no such MGR level");
+        MgrLevel& l = c.L[level];
+        if (what == 0) {
+            sizes[0] = l.n; sizes[1] = 0; sizes[2] = 0;
+            if (b0) {
+                std::vector<int> t(l.n);
+                MGR_HIP(hipMemcpyAsync(t.data(), l.isF.p, sizeof(int) * l.n, hipMemcpyDeviceToHost, s));
+                MGR_HIP(hipStreamSynchronize(s));
+                int* o = (int*)b0;
+                for (int i = 0; i < l.n; ++i) o[i] = t[i] ? 0 : 1;
+            }
+            return MGR_OK;
+        }
+        const DCsr* A = nullptr;
+        if (what == 1) A = (level + 1 < (int)c.L.size()) ? &l.Aout : &c.camg.lv[0].A;
+        if (what == 2) A = &l.PF;
+        if (what == 3) A = &l.RF;
+        if (what == 4) A = &l.AFF;
+        if (what == 5) A = &l.M;
+        if (!A) throw Error(MGR_ERR_ARG, "unknown export item");
+        export_csr(*A, sizes, b0, b1, b2, s);
+        return MGR_OK;
+    }
+    Amg* H = (kind == 1) ? &c.camg : ((sub >= 0 && sub < (int)c.L.size()) ? c.L[sub].famg.get() : nullptr);
+    if (!H || level < 0 || level >= (int)H->lv.size()) throw Error(MGR_ERR_ARG, "no such AMG level");
+    AmgLevel& L = H->lv[level];
+    if (what == 0) {
+        if (level + 1 >= (int)H->lv.size()) throw Error(MGR_ERR_ARG, "coarsest AMG level has no C/F split");
+        sizes[0] = L.n; sizes[1] = 0; sizes[2] = 0;
+        if (b0) {
+            MGR_HIP(hipMemcpyAsync(b0, L.cf.p, sizeof(int) * L.n, hipMemcpyDeviceToHost, s));
+            MGR_HIP(hipStreamSynchronize(s));
+        }
+        return MGR_OK;
+    }
+    if (what == 1) { export_csr(L.A, sizes, b0, b1, b2, s); return MGR_OK; }
+    if (what == 2 && level + 1 < (int)H->lv.size()) { export_csr(L.P, sizes, b0, b1, b2, s); return MGR_OK; }
+    throw Error(MGR_ERR_ARG, "unknown export item");
+}
+
+}  // namespace mgr
+
+// ====================================================================== C-ABI
+struct mgr_ctx {
+    mgr::Ctx c;
+};
+
+using mgr::Error;
+
+template <typename F>
+static int guarded(mgr_handle h, F&& f) {
+    if (!h) return MGR_ERR_ARG;
+    try {
+        h->c.err.clear();
+        return f();
+    } catch (const Error& e) {
+        h->c.err = e.what();
+        return e.code;
+    } catch (const std::exception& e) {
+        h->c.err = e.what();
+        return MGR_ERR_HIP;
+    }
+}
+
+extern "C" {
+
+void mgr_default_opts(mgr_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->apply_precision = 64;
+    o->restart = 50;
+    o->maxiter = 1000;
+    o->rtol = 1e-8;
+    o->ortho = MGR_ORTHO_CGS2;
+    o->amg.theta = 0.25;
+    o->amg.max_levels = 25;
+    o->amg.max_coarse = 128;
+    o->amg.nu_pre = 1;
+    o->amg.nu_post = 1;
+    o->amg.unknown_based = 0;
+    o->amg.seed = 12345;
+}
+
+static int check_opts(const mgr_opts* o) {
+    if (o->apply_precision != 32 && o->apply_precision != 64) return MGR_ERR_ARG;
+    if (o->restart < 1 || o->restart > 63 || o->maxiter < 1 || !(o->rtol >= 0.0)) return MGR_ERR_ARG;
+    if (o->amg.max_levels < 1 || o->amg.max_coarse < 1 || o->amg.nu_pre < 0 || o->amg.nu_post < 0) return MGR_ERR_ARG;
+    return MGR_OK;
+}
+
+int mgr_create(mgr_handle* h, const mgr_opts* o, void* hip_stream) {
+    if (!h) return MGR_ERR_ARG;
+    *h = nullptr;
+    mgr_opts d;
+    mgr_default_opts(&d);
+    if (o) {
+        if (check_opts(o) != MGR_OK) return MGR_ERR_ARG;
+        d = *o;
+    }
+    mgr_ctx* c = new (std::nothrow) mgr_ctx();
+    if (!c) return MGR_ERR_OOM;
+    c->c.s = (hipStream_t)hip_stream;
+    c->c.o = d;
+    try {
+        c->c.flag.alloc(1, c->c.s);
+        mgr::flag_clear(c->c.flag.p, c->c.s);
+        hipError_t e = hipStreamSynchronize(c->c.s);
+        if (e != hipSuccess) throw Error(MGR_ERR_HIP, hipGetErrorString(e));
+    } catch (...) {
+        delete c;
+        return MGR_ERR_HIP;
+    }
+    *h = c;
+    return MGR_OK;
+}
+
+int mgr_set_opts(mgr_handle h, const mgr_opts* o) {
+    return guarded(h, [&]() {
+        if (!o || check_opts(o) != MGR_OK) throw Error(MGR_ERR_ARG, "invalid options");
+        h->c.o = *o;
+        return MGR_OK;
+    });
+}
+
+int mgr_setup(mgr_handle h, const mgr_matrix* A, const int32_t* field_of_dof, int32_t nlevels,
+              const mgr_level_opts* lvl) {
+    return guarded(h, [&]() {
+        mgr::setup(h->c, A, field_of_dof, nlevels, lvl);
+        return MGR_OK;
+    });
+}
+
+int mgr_apply(mgr_handle h, const double* r, double* z) {
+    return guarded(h, [&]() {
+        if (!r || !z) throw Error(MGR_ERR_ARG, "null vector");
+        mgr::mgr_apply_top(h->c, r, z, false);
+        return MGR_OK;
+    });
+}
+
+int mgr_apply_transpose(mgr_handle h, const double* r, double* z) {
+    return guarded(h, [&]() {
+        if (!r || !z) throw Error(MGR_ERR_ARG, "null vector");
+        mgr::mgr_apply_top(h->c, r, z, true);
+        return MGR_OK;
+    });
+}
+
+int mgr_matvec(mgr_handle h, int32_t trans, const double* x, double* y) {
+    return guarded(h, [&]() {
+        if (!h->c.ready) throw Error(MGR_ERR_ARG, "matvec before setup");
+        if (!x || !y) throw Error(MGR_ERR_ARG, "null vector");
+        mgr::matvec(h->c, trans != 0, x, nullptr, y, 1.0, 0.0);
+        return MGR_OK;
+    });
+}
+
+static int solve_impl(mgr_handle h, bool tr, int32_t nrhs, const double* B, double* X, mgr_solve_info* info) {
+    return guarded(h, [&]() {
+        if (!h->c.ready) throw Error(MGR_ERR_ARG, "solve before setup");
+        if (nrhs < 1 || !B || !X) throw Error(MGR_ERR_ARG, "bad right-hand sides");
+        int st = MGR_OK;
+        for (int k = 0; k < nrhs; ++k) {
+            mgr_solve_info inf{};
+            int r = mgr::fgmres(h->c, tr, B + (long)k * h->c.n, X + (long)k * h->c.n, &inf);
+            if (info) info[k] = inf;
+            if (r != MGR_OK) st = r;
+        }
+        return st;
+    });
+}
+
+int mgr_solve(mgr_handle h, int32_t nrhs, const double* B, double* X, mgr_solve_info* info) {
+    return solve_impl(h, false, nrhs, B, X, info);
+}
+
+int mgr_solve_transpose(mgr_handle h, int32_t nrhs, const double* B, double* X, mgr_solve_info* info) {
+    return solve_impl(h, true, nrhs, B, X, info);
+}
+
+int mgr_grad_values(mgr_handle h, int32_t nrhs, const double* Lam, const double* X, double* dvalues) {
+    return guarded(h, [&]() {
+        mgr::Ctx& c = h->c;
+        if (!c.ready) throw Error(MGR_ERR_ARG, "grad before setup");
+        if (nrhs < 1 || !Lam || !X || !dvalues) throw Error(MGR_ERR_ARG, "bad arguments");
+        mgr::grad_values(c.b, c.nbr, c.Arp.p, c.Aci.p, c.nnzb, nrhs, Lam, X, dvalues, c.s);
+        return MGR_OK;
+    });
+}
+
+int mgr_hierarchy_info(mgr_handle h, int64_t* out, int32_t cap) {
+    return guarded(h, [&]() {
+        mgr::Ctx& c = h->c;
+        if (!c.ready) throw Error(MGR_ERR_ARG, "info before setup");
+        if (!out || cap < 2) throw Error(MGR_ERR_ARG, "bad buffer");
+        int o = 0;
+        out[o++] = (int64_t)c.L.size();
+        out[o++] = (int64_t)c.camg.lv.size();
+        for (size_t l = 0; l < c.L.size() && o + 4 <= cap; ++l) {
+            out[o++] = c.L[l].n;
+            out[o++] = c.L[l].nF;
+            out[o++] = c.L[l].nC;
+            out[o++] = (l + 1 < c.L.size()) ? c.L[l].Aout.nnz : c.camg.lv[0].A.nnz;
+        }
+        for (size_t k = 0; k < c.camg.lv.size() && o + 2 <= cap; ++k) {
+            out[o++] = c.camg.lv[k].n;
+            out[o++] = c.camg.lv[k].A.nnz;
+        }
+        return o;
+    });
+}
+
+int mgr_export(mgr_handle h, int32_t kind, int32_t level, int32_t what, int32_t sub, int64_t* sizes, void* b0,
+               void* b1, void* b2) {
+    return guarded(h, [&]() {
+        if (!sizes) throw Error(MGR_ERR_ARG, "null sizes");
+        return mgr::do_export(h->c, kind, level, what, sub, sizes, b0, b1, b2);
+    });
+}
+
+const char* mgr_last_error(mgr_handle h) { return h ? h->c.err.c_str() : "null handle"; }
+
+void mgr_destroy(mgr_handle h) {
+    if (!h) return;
+    hipStream_t s = h->c.s;
+    (void)hipStreamSynchronize(s);
+    delete h;
+    (void)hipStreamSynchronize(s);
+}
+
+}  // extern "C"

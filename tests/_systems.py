@@ -1,0 +1,38 @@
+"""Shared test helpers: seeded systems and builders for the oracle and the GPU solver."""
+import numpy as np
+
+import oracle as O
+import workloads as W
+
+SMALL = {
+    # ragged sizes (not multiples of any tile), several AMG levels each
+    "tpfa_7x6x5": lambda: W.two_field_tpfa(7, 6, 5, seed=11),
+    "tpfa_16^3": lambda: W.two_field_tpfa(16, 16, 16, seed=0),
+    "mimetic_9x7x6": lambda: W.hybrid_mimetic(9, 7, 6, seed=3),
+    "mimetic_tpfa_sym_6^3": lambda: W.hybrid_mimetic(6, 6, 6, seed=4, consistent=False, upwind=False),
+    "mimetic_20^3": lambda: W.hybrid_mimetic(20, 20, 20, seed=5),
+}
+
+
+def oracle_mgr(s, levels=None, **kw):
+    lv = [O.LevelOpts(**l) for l in (levels if levels is not None else s["levels"])]
+    m = O.MGR(s["b"], s["rp"], s["ci"], s["vals"], s["field"], lv, **kw)
+    assert m.status == 0, m.status
+    return m
+
+
+def gpu_solver(s, levels=None, **kw):
+    import paper_2101_11649_amd as P
+    return P.Solver(s["b"], s["rp"], s["ci"], s["vals"], s["field"],
+                    levels if levels is not None else s["levels"], **kw)
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    d = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (d if d > 0 else 1.0)
+
+
+def say(*args):
+    print(*args, flush=True)
