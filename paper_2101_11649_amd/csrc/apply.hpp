@@ -8,6 +8,9 @@ namespace mgr {
 // Number of per-block partial sums used by the Krylov reductions (a fixed grid
 // so that every reduction is formed in the same order on every call).
 constexpr int KRYLOV_PARTS = 2048;
+// CSR-stream SpMV: nominal nonzeros per row block, and the LDS stage size.
+constexpr int SPMV_CHUNK = 1024;
+constexpr int SPMV_LDS = 2048;
 
 // Read-only view of a CSR operator in value type T with its SpMV group size
 // (lanes per row, chosen from the average row length).
@@ -18,10 +21,13 @@ struct SpOp {
     const int* rp = nullptr;
     const int* ci = nullptr;
     const T* v = nullptr;
-    int group = 1;
+    const int* blk = nullptr;  // row-block boundaries (nblk + 1)
+    int nblk = 0;
 };
 
-int spmv_group(int nr, long nnz);
+// number of row blocks of an operator with nnz entries, and their boundaries
+int rowblock_count(long nnz);
+void rowblocks(int nr, long nnz, const int* rp, int* blk, hipStream_t s);
 
 template <typename T>
 inline SpOp<T> view(const DCsr& A);
@@ -29,22 +35,24 @@ template <>
 inline SpOp<double> view<double>(const DCsr& A) {
     SpOp<double> o;
     o.nr = A.nr; o.nc = A.nc; o.nnz = A.nnz; o.rp = A.rp.p; o.ci = A.ci.p; o.v = A.v.p;
-    o.group = spmv_group(A.nr, A.nnz);
+    o.blk = A.blk.p; o.nblk = A.nblk;
     return o;
 }
 template <>
 inline SpOp<float> view<float>(const DCsr& A) {
     SpOp<float> o;
     o.nr = A.nr; o.nc = A.nc; o.nnz = A.nnz; o.rp = A.rp.p; o.ci = A.ci.p; o.v = A.vf.p;
-    o.group = spmv_group(A.nr, A.nnz);
+    o.blk = A.blk.p; o.nblk = A.nblk;
     return o;
 }
 
 // y = alpha * A [x | x2] + beta * w: columns >= split read x2[c - split];
 // pass x2 = nullptr and split = INT_MAX for a single source, w = nullptr for beta = 0.
+// tag = 1 selects a separately named kernel instance (the FGMRES matvec), so that
+// profiles report it on its own.
 template <typename MT, typename XT, typename X2T, typename YT, typename WT>
 void spmv(const SpOp<MT>& A, const XT* x, const X2T* x2, int split, const WT* w, YT* y, MT alpha, MT beta,
-          hipStream_t s);
+          hipStream_t s, int tag = 0);
 // y = x + dinv .* (b - A x)  (out of place)
 template <typename T>
 void jacobi_sweep(const SpOp<T>& A, const T* dinv, const T* b, const T* x, T* y, hipStream_t s);

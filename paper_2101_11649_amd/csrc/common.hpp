@@ -68,6 +68,9 @@ struct DCsr {
     DArr<int> rp, ci;
     DArr<double> v;
     DArr<float> vf;
+    DArr<int> blk;   // row-block boundaries of the CSR-stream SpMV
+    int nblk = 0;
+    int max_row = -1;  // longest row (-1 = not known yet)
     bool empty() const { return nr == 0 && nnz == 0; }
     void alloc(int rows, int cols, long nz, hipStream_t s) {
         nr = rows;
@@ -77,6 +80,9 @@ struct DCsr {
         ci.alloc((size_t)(nz > 0 ? nz : 1), s);
         v.alloc((size_t)(nz > 0 ? nz : 1), s);
         vf.reset();
+        blk.reset();
+        nblk = 0;
+        max_row = -1;
     }
 };
 

@@ -24,73 +24,124 @@ __device__ inline T group_sum(T v, int G) {
     return v;
 }
 
-// Sum over the row with G lanes of the group: lanes take entries lane, lane+G, ...
-// The x operand is either one vector, or two concatenated ones ([x | x2] with
-// column c >= split reading x2[c - split]).
-template <typename MT, typename XT, typename X2T, int G>
-__device__ inline MT row_dot(int p0, int p1, int lane, const int* __restrict__ ci, const MT* __restrict__ v,
-                             const XT* __restrict__ x, const X2T* __restrict__ x2, int split) {
-    MT s = MT(0);
-    for (int p = p0 + lane; p < p1; p += G) {
-        int c = ci[p];
-        MT xv = (c < split) ? (MT)x[c] : (MT)x2[c - split];
-        s += v[p] * xv;
+// ---------------------------------------------------------------- CSR-stream SpMV
+// Rows are partitioned into row blocks whose first entries fall in one chunk of
+// SPMV_CHUNK nonzeros (rowblocks(), computed once per operator at setup).  A
+// workgroup streams its block's nonzeros with fully coalesced loads of the
+// values and column indices, forms the products in LDS, then reduces the rows:
+// one thread per row when the block holds many short rows, a power-of-two lane
+// group per row otherwise.  A block whose nonzeros exceed the LDS stage (a
+// long row) is reduced row by row across the whole workgroup.
+//
+// The product and the row epilogue are supplied by an operation class:
+//   SpmvOp     y = alpha * A [x | x2] + beta * w   (w may alias y)
+//   JacobiOp   y = x + dinv .* (b - A x)          (one L1-Jacobi sweep, out of place)
+//   PreOp      x = dinv .* b,  r = b - A x        (first sweep from zero + residual)
+template <typename MT, typename XT, typename X2T, typename YT, typename WT>
+struct SpmvOp {
+    const XT* x; const X2T* x2; int split; const WT* w; YT* y; MT alpha, beta;
+    __device__ MT xval(int c) const { return (c < split) ? (MT)x[c] : (MT)x2[c - split]; }
+    __device__ void done(int r, MT s) const {
+        MT o = alpha * s;
+        if (w) o += beta * (MT)w[r];
+        y[r] = (YT)o;
     }
-    return group_sum<MT>(s, G);
+};
+
+template <typename T>
+struct JacobiOp {
+    const T* dinv; const T* b; const T* x; T* y;
+    __device__ T xval(int c) const { return x[c]; }
+    __device__ void done(int r, T s) const { y[r] = x[r] + dinv[r] * (b[r] - s); }
+};
+
+template <typename T>
+struct PreOp {
+    const T* dinv; const T* b; T* x; T* r_;
+    __device__ T xval(int c) const { return dinv[c] * b[c]; }
+    __device__ void done(int r, T s) const {
+        T bi = b[r];
+        x[r] = dinv[r] * bi;
+        r_[r] = bi - s;
+    }
+};
+
+template <typename MT, int TAG, class Op>
+__global__ __launch_bounds__(TPB) void k_spmv_stream(const int* __restrict__ blk, const int* __restrict__ rp,
+                                                     const int* __restrict__ ci, const MT* __restrict__ v, Op op) {
+    __shared__ MT sh[SPMV_LDS];
+    __shared__ MT red[TPB / WAVE];
+    const int tid = threadIdx.x;
+    const int r0 = blk[blockIdx.x], r1 = blk[blockIdx.x + 1];
+    if (r0 >= r1) return;
+    const int p0 = rp[r0], p1 = rp[r1];
+    const int nnz = p1 - p0;
+    if (nnz <= SPMV_LDS) {
+        // issue every index and value load of this thread before the gathers
+        constexpr int PER = SPMV_LDS / TPB;
+        int cc[PER];
+        MT vv[PER];
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            int q = tid + t * TPB;
+            if (q < nnz) { cc[t] = ci[p0 + q]; vv[t] = v[p0 + q]; }
+        }
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            int q = tid + t * TPB;
+            if (q < nnz) sh[q] = vv[t] * op.xval(cc[t]);
+        }
+        __syncthreads();
+        const int nrows = r1 - r0;
+        if (nrows > TPB / 4) {
+            for (int r = r0 + tid; r < r1; r += TPB) {
+                MT s = MT(0);
+                int qe = rp[r + 1] - p0;
+                for (int q = rp[r] - p0; q < qe; ++q) s += sh[q];
+                op.done(r, s);
+            }
+        } else {
+            int G = 64;
+            while (G > 1 && G * nrows > TPB) G >>= 1;
+            int rl = tid / G, lane = tid & (G - 1);
+            int r = r0 + rl;
+            MT s = MT(0);
+            if (rl < nrows) {
+                int qe = rp[r + 1] - p0;
+                for (int q = rp[r] - p0 + lane; q < qe; q += G) s += sh[q];
+            }
+            for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, WAVE);
+            if (rl < nrows && lane == 0) op.done(r, s);
+        }
+        return;
+    }
+    for (int r = r0; r < r1; ++r) {
+        MT s = MT(0);
+        for (int p = rp[r] + tid; p < rp[r + 1]; p += TPB) s += v[p] * op.xval(ci[p]);
+        for (int off = WAVE / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, WAVE);
+        if ((tid & (WAVE - 1)) == 0) red[tid / WAVE] = s;
+        __syncthreads();
+        if (tid == 0) {
+            MT t = MT(0);
+            for (int q = 0; q < TPB / WAVE; ++q) t += red[q];
+            op.done(r, t);
+        }
+        __syncthreads();
+    }
 }
 
-// y = alpha * A [x | x2] + beta * w   (w may be null; w may alias y: each row
-// reads w[row] before writing y[row])
-template <typename MT, typename XT, typename X2T, typename YT, typename WT, int G>
-__global__ __launch_bounds__(TPB) void k_spmv(int nr, const int* __restrict__ rp, const int* __restrict__ ci,
-                                              const MT* __restrict__ v, const XT* __restrict__ x,
-                                              const X2T* __restrict__ x2, int split, const WT* w, YT* y,
-                                              MT alpha, MT beta) {
-    long gid = (long)blockIdx.x * TPB + threadIdx.x;
-    int row = (int)(gid / G), lane = (int)(gid % G);
-    if (row >= nr) return;
-    MT s = row_dot<MT, XT, X2T, G>(rp[row], rp[row + 1], lane, ci, v, x, x2, split);
-    if (lane == 0) {
-        MT r = alpha * s;
-        if (w) r += beta * (MT)w[row];
-        y[row] = (YT)r;
+__global__ void k_rowblocks(int nr, int nb, const int* __restrict__ rp, int* __restrict__ blk) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > nb) return;
+    if (b == nb) { blk[b] = nr; return; }
+    long target = (long)b * SPMV_CHUNK;
+    int lo = 0, hi = nr;  // first row r in [0, nr] with rp[r] >= target
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (rp[mid] < target) lo = mid + 1;
+        else hi = mid;
     }
-}
-
-// One L1-Jacobi sweep, out of place: y = x + dinv .* (b - A x).
-template <typename T, int G>
-__global__ __launch_bounds__(TPB) void k_jacobi(int nr, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                const T* __restrict__ v, const T* __restrict__ dinv,
-                                                const T* __restrict__ b, const T* __restrict__ x,
-                                                T* __restrict__ y) {
-    long gid = (long)blockIdx.x * TPB + threadIdx.x;
-    int row = (int)(gid / G), lane = (int)(gid % G);
-    if (row >= nr) return;
-    T s = row_dot<T, T, T, G>(rp[row], rp[row + 1], lane, ci, v, x, x, INT_MAX);
-    if (lane == 0) y[row] = x[row] + dinv[row] * (b[row] - s);
-}
-
-// First L1-Jacobi sweep from zero fused with the residual:
-// x = dinv .* b,  r = b - A x  (x_j recomputed on the fly from b_j and dinv_j).
-template <typename T, int G>
-__global__ __launch_bounds__(TPB) void k_presmooth(int nr, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                   const T* __restrict__ v, const T* __restrict__ dinv,
-                                                   const T* __restrict__ b, T* __restrict__ x,
-                                                   T* __restrict__ r) {
-    long gid = (long)blockIdx.x * TPB + threadIdx.x;
-    int row = (int)(gid / G), lane = (int)(gid % G);
-    if (row >= nr) return;
-    T s = T(0);
-    for (int p = rp[row] + lane; p < rp[row + 1]; p += G) {
-        int c = ci[p];
-        s += v[p] * (dinv[c] * b[c]);
-    }
-    s = group_sum<T>(s, G);
-    if (lane == 0) {
-        T bi = b[row];
-        x[row] = dinv[row] * bi;
-        r[row] = bi - s;
-    }
+    blk[b] = lo;
 }
 
 // Block-CSR SpMV, b x b row-major blocks, G lanes per block row:
@@ -311,8 +362,6 @@ int pick_group(double avg) {
 
 }  // namespace
 
-int spmv_group(int nr, long nnz) { return pick_group(nr > 0 ? (double)nnz / nr : 1.0); }
-
 #define MGR_DISPATCH_G(G, ...)                          \
     switch (G) {                                        \
         case 1: { constexpr int GG = 1; __VA_ARGS__; } break;   \
@@ -324,32 +373,40 @@ int spmv_group(int nr, long nnz) { return pick_group(nr > 0 ? (double)nnz / nr :
         default: { constexpr int GG = 64; __VA_ARGS__; } break; \
     }
 
+int rowblock_count(long nnz) { return nnz > 0 ? (int)((nnz + SPMV_CHUNK - 1) / SPMV_CHUNK) : 1; }
+
+void rowblocks(int nr, long nnz, const int* rp, int* blk, hipStream_t s) {
+    int nb = rowblock_count(nnz);
+    k_rowblocks<<<nblk(nb + 1), TPB, 0, s>>>(nr, nb, rp, blk);
+    MGR_LAUNCH_CHECK();
+}
+
 template <typename MT, typename XT, typename X2T, typename YT, typename WT>
 void spmv(const SpOp<MT>& A, const XT* x, const X2T* x2, int split, const WT* w, YT* y, MT alpha, MT beta,
-          hipStream_t s) {
+          hipStream_t s, int tag) {
     if (A.nr <= 0) return;
-    int G = A.group;
-    long threads = (long)A.nr * G;
-    MGR_DISPATCH_G(G, (k_spmv<MT, XT, X2T, YT, WT, GG><<<nblk(threads), TPB, 0, s>>>(
-                              A.nr, A.rp, A.ci, A.v, x, x2, split, w, y, alpha, beta)));
+    if (!A.blk) throw Error(-1, "spmv: operator without row blocks");
+    SpmvOp<MT, XT, X2T, YT, WT> op{x, x2, split, w, y, alpha, beta};
+    if (tag == 1)
+        k_spmv_stream<MT, 1><<<A.nblk, TPB, 0, s>>>(A.blk, A.rp, A.ci, A.v, op);
+    else
+        k_spmv_stream<MT, 0><<<A.nblk, TPB, 0, s>>>(A.blk, A.rp, A.ci, A.v, op);
     MGR_LAUNCH_CHECK();
 }
 
 template <typename T>
 void jacobi_sweep(const SpOp<T>& A, const T* dinv, const T* b, const T* x, T* y, hipStream_t s) {
     if (A.nr <= 0) return;
-    int G = A.group;
-    long threads = (long)A.nr * G;
-    MGR_DISPATCH_G(G, (k_jacobi<T, GG><<<nblk(threads), TPB, 0, s>>>(A.nr, A.rp, A.ci, A.v, dinv, b, x, y)));
+    JacobiOp<T> op{dinv, b, x, y};
+    k_spmv_stream<T, 0><<<A.nblk, TPB, 0, s>>>(A.blk, A.rp, A.ci, A.v, op);
     MGR_LAUNCH_CHECK();
 }
 
 template <typename T>
 void presmooth(const SpOp<T>& A, const T* dinv, const T* b, T* x, T* r, hipStream_t s) {
     if (A.nr <= 0) return;
-    int G = A.group;
-    long threads = (long)A.nr * G;
-    MGR_DISPATCH_G(G, (k_presmooth<T, GG><<<nblk(threads), TPB, 0, s>>>(A.nr, A.rp, A.ci, A.v, dinv, b, x, r)));
+    PreOp<T> op{dinv, b, x, r};
+    k_spmv_stream<T, 0><<<A.nblk, TPB, 0, s>>>(A.blk, A.rp, A.ci, A.v, op);
     MGR_LAUNCH_CHECK();
 }
 
@@ -463,7 +520,7 @@ void grad_values(int b, int nbr, const int* rp, const int* ci, long nnzb, int nr
 
 // ---------------------------------------------------------------- explicit instantiations
 #define INST_SPMV(MT, XT, X2T, YT, WT) \
-    template void spmv<MT, XT, X2T, YT, WT>(const SpOp<MT>&, const XT*, const X2T*, int, const WT*, YT*, MT, MT, hipStream_t);
+    template void spmv<MT, XT, X2T, YT, WT>(const SpOp<MT>&, const XT*, const X2T*, int, const WT*, YT*, MT, MT, hipStream_t, int);
 INST_SPMV(double, double, double, double, double)
 INST_SPMV(float, float, float, float, float)
 INST_SPMV(float, double, double, float, float)

@@ -30,36 +30,50 @@ __device__ inline int wave_min_int(int v) {
 __device__ inline void set_flag(int* flag, int code) { atomicMax(flag, code); }
 
 // ------------------------------------------------------------------ scan
-__global__ void k_scan_reduce(const int* __restrict__ in, int n, long long* __restrict__ bsum) {
+// Exclusive prefix sum in three passes (block sums, scan of block sums, block
+// scans + offsets).  The scan also reports the total and the largest input
+// value (the longest row when the inputs are row counts) into a device slot.
+__global__ void k_scan_reduce(const int* __restrict__ in, int n, long long* __restrict__ bsum,
+                              long long* __restrict__ bmax) {
     __shared__ long long sh[SCAN_T];
+    __shared__ int sm[SCAN_T];
     long long s = 0;
+    int m = 0;
     int base = blockIdx.x * SCAN_B;
     for (int t = 0; t < SCAN_I; ++t) {
         int i = base + t * SCAN_T + threadIdx.x;
-        if (i < n) s += in[i];
+        if (i < n) { int v = in[i]; s += v; m = max(m, v); }
     }
     sh[threadIdx.x] = s;
+    sm[threadIdx.x] = m;
     __syncthreads();
     for (int off = SCAN_T / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+        if ((int)threadIdx.x < off) {
+            sh[threadIdx.x] += sh[threadIdx.x + off];
+            sm[threadIdx.x] = max(sm[threadIdx.x], sm[threadIdx.x + off]);
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) bsum[blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) { bsum[blockIdx.x] = sh[0]; bmax[blockIdx.x] = sm[0]; }
 }
 
-__global__ void k_scan_blocks(long long* __restrict__ bsum, int nb, int* __restrict__ out_last,
-                              long long* __restrict__ total) {
+__global__ void k_scan_blocks(long long* __restrict__ bsum, const long long* __restrict__ bmax, int nb,
+                              int* __restrict__ out_last, long long* __restrict__ slot) {
     __shared__ long long sh[1024];
+    __shared__ long long sm[1024];
     int chunk = (nb + 1023) / 1024;
     int b0 = threadIdx.x * chunk, b1 = min(nb, b0 + chunk);
-    long long s = 0;
-    for (int b = b0; b < b1; ++b) s += bsum[b];
+    long long s = 0, m = 0;
+    for (int b = b0; b < b1; ++b) { s += bsum[b]; m = max(m, bmax[b]); }
     sh[threadIdx.x] = s;
+    sm[threadIdx.x] = m;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
         long long t = ((int)threadIdx.x >= off) ? sh[threadIdx.x - off] : 0;
+        long long u = ((int)threadIdx.x >= off) ? sm[threadIdx.x - off] : 0;
         __syncthreads();
         sh[threadIdx.x] += t;
+        sm[threadIdx.x] = max(sm[threadIdx.x], u);
         __syncthreads();
     }
     long long run = threadIdx.x ? sh[threadIdx.x - 1] : 0;
@@ -69,8 +83,8 @@ __global__ void k_scan_blocks(long long* __restrict__ bsum, int nb, int* __restr
         run += v;
     }
     if (threadIdx.x == 1023) {
-        *total = sh[1023];
         *out_last = (sh[1023] > INT_MAX) ? INT_MAX : (int)sh[1023];
+        if (slot) { slot[0] = sh[1023]; slot[1] = sm[1023]; }
     }
 }
 
@@ -99,6 +113,11 @@ __global__ void k_scan_apply(const int* __restrict__ in, int n, const long long*
         if (i < n) out[i] = (int)off;
         off += v[t];
     }
+}
+
+__global__ void k_fill_ll(long long* p, long long v, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 // ------------------------------------------------------------------ misc
@@ -316,8 +335,15 @@ __global__ void k_frelax_fill(int nb, const int* __restrict__ bstart, const int*
 
 // ------------------------------------------------------------------ sparse products
 __global__ void k_max_row(int n, const int* __restrict__ rp, int* __restrict__ out) {
+    __shared__ int sh[TPB];
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) atomicMax(out, rp[i + 1] - rp[i]);
+    sh[threadIdx.x] = (i < n) ? rp[i + 1] - rp[i] : 0;
+    __syncthreads();
+    for (int off = TPB / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, sh[0]);
 }
 
 // C = A B, one wavefront per output row.  Each lane owns up to NH entries p of
@@ -337,7 +363,12 @@ __global__ __launch_bounds__(TPB) void k_spgemm(int nr, const int* __restrict__ 
     if (row >= nr) return;
     int a0 = arp[row], a1 = arp[row + 1];
     if (a1 - a0 > NH * WAVE) {
-        if (lane == 0) set_flag(flag, 6);
+        // too long for this variant: reported through *flag so the caller reruns
+        // the product with more heads per lane
+        if (lane == 0) {
+            if (!FILL) cnt[row] = 0;
+            if (flag) atomicMax(flag, 1);
+        }
         return;
     }
     int h[NH], e[NH], c[NH];
@@ -392,6 +423,81 @@ __global__ __launch_bounds__(TPB) void k_spgemm(int nr, const int* __restrict__ 
         ++count;
     }
     if (!FILL && lane == 0) cnt[row] = count;
+}
+
+// The same product with a lane group of G (<= 32) lanes per row, several rows
+// per wavefront, for left factors whose rows have at most G entries.  Control
+// flow is kept uniform across the wavefront (groups that are done idle), and
+// each output value still adds its products in the order of the entries of the
+// row of A (lane order inside the group).
+template <int G, bool FILL>
+__global__ __launch_bounds__(TPB) void k_spgemm_g(int nr, const int* __restrict__ arp, const int* __restrict__ aci,
+                                                  const double* __restrict__ av, const int* __restrict__ brp,
+                                                  const int* __restrict__ bci, const double* __restrict__ bv,
+                                                  const int* __restrict__ crp, int* __restrict__ cci,
+                                                  double* __restrict__ cv, int* __restrict__ cnt,
+                                                  int* __restrict__ flag) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int gl = lane & (G - 1);
+    const int gbase = lane - gl;
+    const unsigned long long gmask_all = (G >= 64) ? ~0ULL : ((1ULL << G) - 1ULL);
+    const int row = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    bool valid = row < nr;
+    int a0 = 0, a1 = 0;
+    if (valid) {
+        a0 = arp[row];
+        a1 = arp[row + 1];
+        if (a1 - a0 > G) {
+            if (gl == 0) {
+                if (!FILL) cnt[row] = 0;
+                if (flag) atomicMax(flag, 1);
+            }
+            valid = false;
+        }
+    }
+    int h = 0, e = 0, c = INT_MAX;
+    double a = 0.0;
+    const int p = a0 + gl;
+    if (valid && p < a1) {
+        int k = aci[p];
+        h = brp[k];
+        e = brp[k + 1];
+        if (FILL) a = av[p];
+        if (h < e) c = bci[h];
+    }
+    int count = 0;
+    const int o = (FILL && valid) ? crp[row] : 0;
+    for (;;) {
+        int mn = c;
+        for (int off = G / 2; off > 0; off >>= 1) mn = min(mn, __shfl_xor(mn, off, WAVE));
+        if (!__any(mn != INT_MAX)) break;
+        const bool m = (mn != INT_MAX) && (c == mn);
+        if (FILL) {
+            double prod = m ? a * bv[h] : 0.0;
+            unsigned long long gm = (__ballot(m) >> gbase) & gmask_all;
+            int nb = __popcll(gm);
+            for (int off = WAVE / 2; off > 0; off >>= 1) nb = max(nb, __shfl_xor(nb, off, WAVE));
+            double acc = 0.0;
+            for (int it = 0; it < nb; ++it) {
+                int src = gbase + (gm ? (__ffsll((unsigned long long)gm) - 1) : 0);
+                double v = __shfl(prod, src, WAVE);
+                if (gm) {
+                    acc = acc + v;
+                    gm &= gm - 1;
+                }
+            }
+            if (gl == 0 && mn != INT_MAX) {
+                cci[o + count] = mn;
+                cv[o + count] = acc;
+            }
+        }
+        if (m) {
+            ++h;
+            c = (h < e) ? bci[h] : INT_MAX;
+        }
+        if (mn != INT_MAX) ++count;
+    }
+    if (!FILL && valid && gl == 0) cnt[row] = count;
 }
 
 __global__ void k_add_count(int nr, const int* __restrict__ arp, const int* __restrict__ aci,
@@ -753,29 +859,31 @@ __global__ void k_pj_fill(int n, int nC, const int* __restrict__ isF, const int*
 }  // namespace
 
 // ====================================================================== launchers
-void scan_exclusive_async(const int* in, int* out, int n, hipStream_t s) {
+void scan_async(const int* in, int* out, int n, long long* slot, hipStream_t s) {
     int nb = ceil_div(n > 0 ? n : 1, SCAN_B);
-    DArr<long long> bsum((size_t)nb + 1, s);
-    long long* total = bsum.p + nb;
-    k_scan_reduce<<<nb, SCAN_T, 0, s>>>(in, n, bsum.p);
-    k_scan_blocks<<<1, 1024, 0, s>>>(bsum.p, nb, out + n, total);
-    k_scan_apply<<<nb, SCAN_T, 0, s>>>(in, n, bsum.p, out);
+    DArr<long long> tmp((size_t)2 * nb + 2, s);
+    k_scan_reduce<<<nb, SCAN_T, 0, s>>>(in, n, tmp.p, tmp.p + nb);
+    k_scan_blocks<<<1, 1024, 0, s>>>(tmp.p, tmp.p + nb, nb, out + n, slot);
+    k_scan_apply<<<nb, SCAN_T, 0, s>>>(in, n, tmp.p, out);
     MGR_LAUNCH_CHECK();
 }
 
+void scan_exclusive_async(const int* in, int* out, int n, hipStream_t s) { scan_async(in, out, n, nullptr, s); }
+
 long scan_exclusive(const int* in, int* out, int n, hipStream_t s) {
-    int nb = ceil_div(n > 0 ? n : 1, SCAN_B);
-    DArr<long long> bsum((size_t)nb + 1, s);
-    long long* total = bsum.p + nb;
-    k_scan_reduce<<<nb, SCAN_T, 0, s>>>(in, n, bsum.p);
-    k_scan_blocks<<<1, 1024, 0, s>>>(bsum.p, nb, out + n, total);
-    k_scan_apply<<<nb, SCAN_T, 0, s>>>(in, n, bsum.p, out);
-    MGR_LAUNCH_CHECK();
-    long long h = 0;
-    MGR_HIP(hipMemcpyAsync(&h, total, sizeof(h), hipMemcpyDeviceToHost, s));
+    DArr<long long> slot(2, s);
+    scan_async(in, out, n, slot.p, s);
+    long long h[2] = {0, 0};
+    MGR_HIP(hipMemcpyAsync(h, slot.p, sizeof(h), hipMemcpyDeviceToHost, s));
     MGR_HIP(hipStreamSynchronize(s));
-    if (h > INT_MAX) throw Error(-6, "prefix sum exceeds the int32 index range");
-    return (long)h;
+    if (h[0] > INT_MAX) throw Error(-6, "prefix sum exceeds the int32 index range");
+    return (long)h[0];
+}
+
+void fill_ll(long long* p, long long v, int n, hipStream_t s) {
+    if (n <= 0) return;
+    k_fill_ll<<<nblk(n), TPB, 0, s>>>(p, v, n);
+    MGR_LAUNCH_CHECK();
 }
 
 int read_int(const int* dptr, hipStream_t s) {
@@ -904,9 +1012,26 @@ int max_row_len(const DCsr& A, hipStream_t s) {
 template <bool FILL>
 static void spgemm_launch(const DCsr& A, const DCsr& B, int max_row, const int* crp, int* cci, double* cv, int* cnt,
                           int* flag, hipStream_t s) {
+    // max_row selects the variant: <= 64 entries per row of A -> one head per lane
     if (A.nr <= 0) return;
     int grid = ceil_div(A.nr, TPB / WAVE);
-    if (max_row <= WAVE)
+    if (max_row <= 32) {
+        int G = 1;
+        while (G < max_row) G <<= 1;
+        int g2 = ceil_div((long)A.nr * G, TPB);
+#define MGR_SPGEMM_G(GG)                                                                                         \
+    k_spgemm_g<GG, FILL><<<g2, TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p, B.v.p, crp, cci, cv, cnt, \
+                                           flag)
+        switch (G) {
+            case 1: MGR_SPGEMM_G(1); break;
+            case 2: MGR_SPGEMM_G(2); break;
+            case 4: MGR_SPGEMM_G(4); break;
+            case 8: MGR_SPGEMM_G(8); break;
+            case 16: MGR_SPGEMM_G(16); break;
+            default: MGR_SPGEMM_G(32); break;
+        }
+#undef MGR_SPGEMM_G
+    } else if (max_row <= WAVE)
         k_spgemm<1, FILL><<<grid, TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p, B.v.p, crp, cci, cv,
                                                 cnt, flag);
     else if (max_row <= 4 * WAVE)

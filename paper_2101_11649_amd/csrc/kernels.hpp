@@ -15,6 +15,9 @@ namespace mgr {
 long scan_exclusive(const int* in, int* out, int n, hipStream_t s);
 // Same, without reading the total back.
 void scan_exclusive_async(const int* in, int* out, int n, hipStream_t s);
+// Asynchronous scan that also stores {total, max input} into slot[0..1] (device).
+void scan_async(const int* in, int* out, int n, long long* slot, hipStream_t s);
+void fill_ll(long long* p, long long v, int n, hipStream_t s);
 int read_int(const int* dptr, hipStream_t s);
 
 // Device-wide error flag helpers (a single int in device memory, 0 = ok).
@@ -46,6 +49,8 @@ void frelax_row_len(int nF, const int* bnum, const int* bstart, int* len, hipStr
 void frelax_fill(int nb, const int* bstart, const DCsr& AFF, DCsr& M, int* flag, hipStream_t s);
 
 int max_row_len(const DCsr& A, hipStream_t s);
+// C = A B counts; rows of A longer than the variant chosen by max_row get a zero
+// count and set *flag (an int in device memory) to 1.
 void spgemm_count(const DCsr& A, const DCsr& B, int max_row, int* cnt, int* flag, hipStream_t s);
 void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, hipStream_t s);
 void add_count(const DCsr& A, const DCsr& B, int* cnt, hipStream_t s);

@@ -22,54 +22,175 @@
 namespace mgr {
 
 // ====================================================================== sparse helpers
-static DCsr csr_from_counts(int nr, int nc, const int* counts, hipStream_t s) {
-    DCsr C;
+// Device-produced values the host needs during setup (prefix-sum totals,
+// longest rows, counters, error flags) land in a small slot array that is read
+// back with ONE pinned copy per sync point, so a whole setup needs a few tens of
+// host synchronisations instead of one per scan.
+struct Slots {
+    static constexpr int N = 64;
+    static constexpr int FLAG = N - 1;   // int error flag kept in the last slot
+    DArr<long long> d;
+    long long* h = nullptr;
+    int next = 0;
+    hipStream_t s = nullptr;
+    void init(hipStream_t st) {
+        s = st;
+        d.alloc(N, s);
+        fill_ll(d.p, 0, N, s);
+        MGR_HIP(hipHostMalloc(reinterpret_cast<void**>(&h), sizeof(long long) * N, hipHostMallocDefault));
+        std::memset(h, 0, sizeof(long long) * N);
+    }
+    ~Slots() {
+        if (h) (void)hipHostFree(h);
+    }
+    long long* take(int k) {
+        if (next + k > FLAG) throw Error(MGR_ERR_ARG, "internal: too many pending setup values");
+        long long* p = d.p + next;
+        next += k;
+        return p;
+    }
+    int* flag() { return reinterpret_cast<int*>(d.p + FLAG); }
+    void sync(const char* what) {
+        MGR_HIP(hipMemcpyAsync(h, d.p, sizeof(long long) * N, hipMemcpyDeviceToHost, s));
+        MGR_HIP(hipStreamSynchronize(s));
+        next = 0;
+        int f = (int)(h[FLAG] & 0xffffffffLL);
+        if (f != 0) {
+            fill_ll(d.p + FLAG, 0, 1, s);
+            std::string m = std::string(what) + ": ";
+            if (f == 3) throw Error(MGR_ERR_ZERO_PIVOT, m + "zero or non-finite pivot");
+            if (f == 5) throw Error(MGR_ERR_BAD_LABELS, m + "field label outside [0, 32)");
+            throw Error(MGR_ERR_UNSUPPORTED,
+                        m + "unsupported input (row too long, block larger than 4, or a_ii <= 0)");
+        }
+    }
+    long long val(const long long* p) const { return h[p - d.p]; }
+};
+
+static void make_rowblocks(DCsr& C, hipStream_t s) {
+    C.nblk = rowblock_count(C.nnz);
+    C.blk.alloc((size_t)C.nblk + 1, s);
+    rowblocks(C.nr, C.nnz, C.rp.p, C.blk.p, s);
+}
+
+// Two-phase construction from row counts: begin() scans asynchronously, the
+// caller syncs the slots, finish() allocates the entries.
+struct Pend {
+    DCsr* C = nullptr;
+    long long* slot = nullptr;
+};
+
+static Pend csr_begin(DCsr& C, int nr, int nc, const int* counts, Slots& S) {
+    C = DCsr();
     C.nr = nr;
     C.nc = nc;
-    C.rp.alloc((size_t)nr + 1, s);
-    C.nnz = scan_exclusive(counts, C.rp.p, nr, s);
-    C.ci.alloc((size_t)(C.nnz > 0 ? C.nnz : 1), s);
-    C.v.alloc((size_t)(C.nnz > 0 ? C.nnz : 1), s);
+    C.rp.alloc((size_t)nr + 1, S.s);
+    Pend p{&C, S.take(2)};
+    scan_async(counts, C.rp.p, nr, p.slot, S.s);
+    return p;
+}
+
+static void csr_finish(const Pend& p, Slots& S) {
+    DCsr& C = *p.C;
+    long long nnz = S.val(p.slot);
+    if (nnz > INT_MAX) throw Error(MGR_ERR_UNSUPPORTED, "operator exceeds the int32 index range");
+    C.nnz = (long)nnz;
+    C.max_row = (int)S.val(p.slot + 1);
+    C.ci.alloc((size_t)(C.nnz > 0 ? C.nnz : 1), S.s);
+    C.v.alloc((size_t)(C.nnz > 0 ? C.nnz : 1), S.s);
+    make_rowblocks(C, S.s);
+}
+
+static DCsr csr_from_counts(int nr, int nc, const int* counts, Slots& S, const char* what) {
+    DCsr C;
+    Pend p = csr_begin(C, nr, nc, counts, S);
+    S.sync(what);
+    csr_finish(p, S);
     return C;
 }
 
-static void check_flag(int* flag, hipStream_t s, const char* what) {
-    int f = flag_read(flag, s);
-    if (f == 0) return;
-    flag_clear(flag, s);
-    std::string m = std::string(what) + ": ";
-    if (f == 3) throw Error(MGR_ERR_ZERO_PIVOT, m + "zero or non-finite pivot");
-    if (f == 5) throw Error(MGR_ERR_BAD_LABELS, m + "field label outside [0, 32)");
-    throw Error(MGR_ERR_UNSUPPORTED, m + "unsupported input (row too long, block larger than 4, or a_ii <= 0)");
-}
+// C = A B in two phases around a sync point (symbolic count, then numeric fill).
+struct Spgemm {
+    const DCsr* A = nullptr;
+    const DCsr* B = nullptr;
+    DCsr* C = nullptr;
+    DArr<int> cnt;
+    long long* lr = nullptr;
+    Pend pend;
+};
 
-static DCsr spgemm(const DCsr& A, const DCsr& B, int* flag, hipStream_t s) {
+static void spgemm_begin(Spgemm& j, const DCsr& A, const DCsr& B, DCsr& C, Slots& S) {
     if (A.nc != B.nr) throw Error(MGR_ERR_ARG, "spgemm: inner dimensions differ");
-    int mr = max_row_len(A, s);
-    DArr<int> cnt((size_t)A.nr + 1, s);
-    spgemm_count(A, B, mr, cnt.p, flag, s);
-    check_flag(flag, s, "SpGEMM");
-    DCsr C = csr_from_counts(A.nr, B.nc, cnt.p, s);
-    spgemm_fill(A, B, mr, C, s);
+    if (A.max_row < 0) throw Error(MGR_ERR_ARG, "internal: spgemm left factor without a known row length");
+    j.A = &A;
+    j.B = &B;
+    j.C = &C;
+    j.cnt.alloc((size_t)A.nr + 1, S.s);
+    j.lr = S.take(1);
+    fill_ll(j.lr, 0, 1, S.s);
+    spgemm_count(A, B, A.max_row, j.cnt.p, reinterpret_cast<int*>(j.lr), S.s);
+    j.pend = csr_begin(C, A.nr, B.nc, j.cnt.p, S);
+}
+
+static void spgemm_finish(Spgemm& j, Slots& S) {
+    if (S.val(j.lr) != 0) throw Error(MGR_ERR_ARG, "internal: spgemm row longer than its recorded length");
+    csr_finish(j.pend, S);
+    spgemm_fill(*j.A, *j.B, j.A->max_row, *j.C, S.s);
+    j.cnt.reset();
+}
+
+static DCsr spgemm(const DCsr& A, const DCsr& B, Slots& S) {
+    DCsr C;
+    Spgemm j;
+    spgemm_begin(j, A, B, C, S);
+    S.sync("SpGEMM");
+    spgemm_finish(j, S);
     return C;
 }
 
-static DCsr csr_add(const DCsr& A, const DCsr& B, hipStream_t s) {
-    DArr<int> cnt((size_t)A.nr + 1, s);
-    add_count(A, B, cnt.p, s);
-    DCsr C = csr_from_counts(A.nr, A.nc, cnt.p, s);
-    add_fill(A, B, C, s);
+static DCsr csr_add(const DCsr& A, const DCsr& B, Slots& S) {
+    DArr<int> cnt((size_t)A.nr + 1, S.s);
+    add_count(A, B, cnt.p, S.s);
+    DCsr C = csr_from_counts(A.nr, A.nc, cnt.p, S, "sparse add");
+    add_fill(A, B, C, S.s);
     return C;
 }
 
-static DCsr csr_transpose(const DCsr& A, hipStream_t s) {
+// Transpose: the entry count is known, so no sync is needed; the longest row of
+// the result is recorded in a slot (read at the caller's next sync point).
+struct Transp {
+    DCsr* T = nullptr;
+    long long* slot = nullptr;
+};
+
+static Transp csr_transpose_begin(const DCsr& A, DCsr& T, Slots& S) {
+    hipStream_t s = S.s;
     DArr<int> cnt((size_t)A.nc + 1, s);
     fill_int(cnt.p, 0, A.nc + 1, s);
     transpose_count(A, cnt.p, s);
-    DCsr T = csr_from_counts(A.nc, A.nr, cnt.p, s);
+    T = DCsr();
+    T.nr = A.nc;
+    T.nc = A.nr;
+    T.nnz = A.nnz;
+    T.rp.alloc((size_t)A.nc + 1, s);
+    Transp t{&T, S.take(2)};
+    scan_async(cnt.p, T.rp.p, A.nc, t.slot, s);
+    T.ci.alloc((size_t)(A.nnz > 0 ? A.nnz : 1), s);
+    T.v.alloc((size_t)(A.nnz > 0 ? A.nnz : 1), s);
     DArr<int> cursor((size_t)A.nc + 1, s);
     MGR_HIP(hipMemcpyAsync(cursor.p, T.rp.p, sizeof(int) * ((size_t)A.nc + 1), hipMemcpyDeviceToDevice, s));
     transpose_fill(A, T, cursor.p, s);
+    make_rowblocks(T, s);
+    return t;
+}
+
+static void csr_transpose_finish(const Transp& t, Slots& S) { t.T->max_row = (int)S.val(t.slot + 1); }
+
+static DCsr csr_transpose(const DCsr& A, Slots& S) {
+    DCsr T;
+    Transp t = csr_transpose_begin(A, T, S);
+    S.sync("transpose");
+    csr_transpose_finish(t, S);
     return T;
 }
 
@@ -81,6 +202,8 @@ static DCsr csr_copy(const DCsr& A, hipStream_t s) {
         MGR_HIP(hipMemcpyAsync(C.ci.p, A.ci.p, sizeof(int) * A.nnz, hipMemcpyDeviceToDevice, s));
         MGR_HIP(hipMemcpyAsync(C.v.p, A.v.p, sizeof(double) * A.nnz, hipMemcpyDeviceToDevice, s));
     }
+    C.max_row = A.max_row;
+    make_rowblocks(C, s);
     return C;
 }
 
@@ -113,8 +236,9 @@ struct Amg {
 // direct interpolation and L1-Jacobi smoothing; see the oracle for the
 // definitions): stops at n <= max_coarse, at max_levels, or when coarsening
 // stalls (no C-point or n_c > 0.9 n).  The coarsest matrix is inverted densely.
-static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o, uint64_t seed, int* flag,
-                      hipStream_t s) {
+// Host synchronisation: about three sync points per level.
+static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o, uint64_t seed, Slots& S) {
+    hipStream_t s = S.s;
     H.lv.clear();
     H.nu_pre = o.nu_pre;
     H.nu_post = o.nu_post;
@@ -132,48 +256,67 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
         const DCsr& A = L.A;
         int n = A.nr;
         if (n <= o.max_coarse || k + 1 >= o.max_levels) break;
-        DArr<unsigned char> strong((size_t)(A.nnz > 0 ? A.nnz : 1), s);
+        size_t nz = (size_t)(A.nnz > 0 ? A.nnz : 1);
+        DArr<unsigned char> strong(nz, s);
         amg_strength(A, o.theta, L.label.p, strong.p, s);
         DArr<int> lam((size_t)n + 1, s);
         fill_int(lam.p, 0, n + 1, s);
         amg_lambda(A, strong.p, lam.p, s);
-        // strength graph S (rows = i, cols = j in S_i) and its transpose
+        // strength graph S (row i lists S_i) and its transpose; both fit in nnz(A)
         DArr<int> scnt((size_t)n + 1, s), srp((size_t)n + 1, s), trp((size_t)n + 1, s), cursor((size_t)n + 1, s);
+        DArr<int> sci(nz, s), tci(nz, s);
         strength_compact_count(A, strong.p, scnt.p, s);
-        long ns = scan_exclusive(scnt.p, srp.p, n, s);
-        DArr<int> sci((size_t)(ns > 0 ? ns : 1), s), tci((size_t)(ns > 0 ? ns : 1), s);
+        scan_exclusive_async(scnt.p, srp.p, n, s);
         strength_compact_fill(A, strong.p, srp.p, sci.p, s);
         scan_exclusive_async(lam.p, trp.p, n, s);
         MGR_HIP(hipMemcpyAsync(cursor.p, trp.p, sizeof(int) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
         pattern_transpose_fill(n, srp.p, sci.p, trp.p, cursor.p, tci.p, s);
-        // PMIS rounds
+        // PMIS rounds, run in batches between checks of the undecided count
         DArr<double> w((size_t)n, s);
-        DArr<int> cf((size_t)n, s), und(1, s);
+        DArr<int> cf((size_t)n, s), isC((size_t)n + 1, s), cidx((size_t)n + 1, s), pcnt((size_t)n + 1, s);
         DArr<unsigned char> newc((size_t)n, s);
         pmis_init(n, lam.p, seed, k, w.p, cf.p, s);
-        for (int round = 0; round < 10000; ++round) {
-            fill_int(und.p, 0, 1, s);
-            pmis_select(n, srp.p, sci.p, trp.p, tci.p, w.p, cf.p, newc.p, s);
-            pmis_update(n, srp.p, sci.p, newc.p, cf.p, und.p, s);
-            if (read_int(und.p, s) == 0) break;
+        DCsr P;
+        Pend pp;
+        long long* sc = nullptr;
+        int batch = 5;
+        for (int total = 0;; total += batch, batch = 2) {
+            if (total > 100000) throw Error(MGR_ERR_UNSUPPORTED, "PMIS did not terminate");
+            long long* und = S.take(1);
+            for (int r = 0; r < batch; ++r) {
+                fill_ll(und, 0, 1, s);
+                pmis_select(n, srp.p, sci.p, trp.p, tci.p, w.p, cf.p, newc.p, s);
+                pmis_update(n, srp.p, sci.p, newc.p, cf.p, reinterpret_cast<int*>(und), s);
+            }
+            // speculative: C numbering and interpolation row counts for this state
+            cf_is_c(n, cf.p, isC.p, s);
+            sc = S.take(2);
+            scan_async(isC.p, cidx.p, n, sc, s);
+            interp_count(A, strong.p, cf.p, pcnt.p, s);
+            pp = csr_begin(P, n, 0, pcnt.p, S);
+            S.sync("PMIS");
+            if ((S.val(und) & 0xffffffffLL) == 0) break;
         }
-        DArr<int> isC((size_t)n + 1, s), cidx((size_t)n + 1, s);
-        cf_is_c(n, cf.p, isC.p, s);
-        long nc = scan_exclusive(isC.p, cidx.p, n, s);
+        long nc = (long)S.val(sc);
         if (nc == 0 || (double)nc > 0.9 * (double)n) break;
-        // direct interpolation, P^T, Galerkin product P^T (A P)
-        DArr<int> pcnt((size_t)n + 1, s);
-        interp_count(A, strong.p, cf.p, pcnt.p, s);
-        DCsr P = csr_from_counts(n, (int)nc, pcnt.p, s);
-        interp_fill(A, strong.p, cf.p, cidx.p, L.label.p, P, flag, s);
-        check_flag(flag, s, "AMG interpolation");
-        DCsr R = csr_transpose(P, s);
-        DCsr AP = spgemm(A, P, flag, s);
-        DCsr Ac = spgemm(R, AP, flag, s);
-        AP = DCsr();
+        P.nc = (int)nc;
+        csr_finish(pp, S);
+        interp_fill(A, strong.p, cf.p, cidx.p, L.label.p, P, S.flag(), s);
+        // R = P^T and A P, then P^T (A P)
+        DCsr R, AP, Ac;
+        Transp tr = csr_transpose_begin(P, R, S);
+        Spgemm j1;
+        spgemm_begin(j1, A, P, AP, S);
+        S.sync("AMG interpolation");
+        csr_transpose_finish(tr, S);
+        spgemm_finish(j1, S);
+        Spgemm j2;
+        spgemm_begin(j2, R, AP, Ac, S);
         L.dinv.alloc((size_t)n, s);
-        l1_dinv(A, L.dinv.p, flag, s);
-        check_flag(flag, s, "AMG L1 diagonal");
+        l1_dinv(A, L.dinv.p, S.flag(), s);
+        S.sync("AMG Galerkin product");
+        spgemm_finish(j2, S);
+        AP = DCsr();
         L.P = std::move(P);
         L.R = std::move(R);
         L.cf = std::move(cf);
@@ -196,8 +339,7 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
     DArr<double> dense((size_t)nc * nc + 1, s);
     H.cinv.alloc((size_t)nc * nc + 1, s);
     densify(Lc.A, dense.p, s);
-    dense_inverse(nc, dense.p, H.cinv.p, flag, s);
-    check_flag(flag, s, "AMG coarsest inverse");
+    dense_inverse(nc, dense.p, H.cinv.p, S.flag(), s);
     // work vectors
     for (size_t l = 0; l < H.lv.size(); ++l) {
         AmgLevel& L = H.lv[l];
@@ -205,6 +347,7 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
         L.td.alloc((size_t)L.n + 1, s);
         if (l > 0) { L.bd.alloc((size_t)L.n + 1, s); L.xd.alloc((size_t)L.n + 1, s); }
     }
+    S.sync("AMG coarsest inverse");
     H.have_float = false;
     H.have_trans = false;
 }
@@ -235,10 +378,11 @@ static void amg_make_float(Amg& H, hipStream_t s) {
     H.have_float = true;
 }
 
-static void amg_make_trans(Amg& H, hipStream_t s) {
+static void amg_make_trans(Amg& H, Slots& S) {
+    hipStream_t s = S.s;
     if (H.have_trans) return;
     for (size_t l = 0; l + 1 < H.lv.size(); ++l) {
-        H.lv[l].AT = csr_transpose(H.lv[l].A, s);
+        H.lv[l].AT = csr_transpose(H.lv[l].A, S);
         if (H.have_float) make_float(H.lv[l].AT, s);
     }
     int nc = H.nc;
@@ -356,7 +500,7 @@ struct Ctx {
     bool have_At = false;
     std::vector<MgrLevel> L;
     Amg camg;
-    DArr<int> flag;
+    Slots slots;
     // Krylov workspace
     int kr_m = 0;
     long kr_n = 0;
@@ -375,49 +519,51 @@ static bool fused_ok(const mgr_level_opts& o) {
 static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr& A, const int* field, const int* block,
                             const mgr_level_opts& o, int lev) {
     hipStream_t s = c.s;
+    Slots& S = c.slots;
     int n = A.nr;
     l.n = n;
     l.o = o;
     l.isF.alloc((size_t)n + 1, s);
     l.lmap.alloc((size_t)n + 1, s);
     DArr<int> fpos((size_t)n + 1, s);
-    cf_flags(n, field, o.f_field_mask, l.isF.p, c.flag.p, s);
-    check_flag(c.flag.p, s, "C/F split");
-    long nF = scan_exclusive(l.isF.p, fpos.p, n, s);
-    l.nF = (int)nF;
+    cf_flags(n, field, o.f_field_mask, l.isF.p, S.flag(), s);
+    long long* sF = S.take(2);
+    scan_async(l.isF.p, fpos.p, n, sF, s);
+    S.sync("C/F split");
+    l.nF = (int)S.val(sF);
     l.nC = n - l.nF;
     if (l.nF == 0 || l.nC == 0)
         throw Error(MGR_ERR_BAD_LABELS, "MGR level " + std::to_string(lev) + ": empty F or C set");
     l.fmap.alloc((size_t)l.nF, s);
     l.cmap.alloc((size_t)l.nC, s);
     cf_maps(n, l.isF.p, fpos.p, l.lmap.p, l.fmap.p, l.cmap.p, s);
-    // block extraction
+    // block extraction and the F-relaxation block structure (Jacobi: 1x1 blocks;
+    // block-Jacobi: the F-points of one block row)
     DArr<int> cFF((size_t)l.nF + 1, s), cFC((size_t)l.nF + 1, s), cCF((size_t)l.nC + 1, s), cCC((size_t)l.nC + 1, s);
     extract_count(A, l.isF.p, l.lmap.p, cFF.p, cFC.p, cCF.p, cCC.p, s);
-    l.AFF = csr_from_counts(l.nF, l.nF, cFF.p, s);
-    l.AFC = csr_from_counts(l.nF, l.nC, cFC.p, s);
-    l.ACF = csr_from_counts(l.nC, l.nF, cCF.p, s);
-    l.ACC = csr_from_counts(l.nC, l.nC, cCC.p, s);
-    extract_fill(A, l.isF.p, l.lmap.p, l.AFF, l.AFC, l.ACF, l.ACC, s);
-    // F-relaxation operator (Jacobi: 1x1 blocks; block-Jacobi: F-points of one block row)
-    {
-        DArr<int> bid, flagk((size_t)l.nF + 1, s), excl((size_t)l.nF + 1, s), bnum((size_t)l.nF, s),
-            len((size_t)l.nF + 1, s);
-        const int* bidp = nullptr;
-        if (o.frelax == MGR_FRELAX_BLOCK_JACOBI) {
-            bid.alloc((size_t)l.nF, s);
-            gather_int(l.nF, l.fmap.p, block, bid.p, s);
-            bidp = bid.p;
-        }
-        frelax_block_flags(l.nF, bidp, flagk.p, s);
-        long nb = scan_exclusive(flagk.p, excl.p, l.nF, s);
-        DArr<int> bstart((size_t)nb + 1, s);
-        frelax_block_starts(l.nF, flagk.p, excl.p, bstart.p, bnum.p, s);
-        frelax_row_len(l.nF, bnum.p, bstart.p, len.p, s);
-        l.M = csr_from_counts(l.nF, l.nF, len.p, s);
-        frelax_fill((int)nb, bstart.p, l.AFF, l.M, c.flag.p, s);
-        check_flag(c.flag.p, s, "F-relaxation operator");
+    Pend pFF = csr_begin(l.AFF, l.nF, l.nF, cFF.p, S);
+    Pend pFC = csr_begin(l.AFC, l.nF, l.nC, cFC.p, S);
+    Pend pCF = csr_begin(l.ACF, l.nC, l.nF, cCF.p, S);
+    Pend pCC = csr_begin(l.ACC, l.nC, l.nC, cCC.p, S);
+    DArr<int> bid, flagk((size_t)l.nF + 1, s), excl((size_t)l.nF + 1, s), bnum((size_t)l.nF, s),
+        len((size_t)l.nF + 1, s), bstart((size_t)l.nF + 1, s);
+    const int* bidp = nullptr;
+    if (o.frelax == MGR_FRELAX_BLOCK_JACOBI) {
+        bid.alloc((size_t)l.nF, s);
+        gather_int(l.nF, l.fmap.p, block, bid.p, s);
+        bidp = bid.p;
     }
+    frelax_block_flags(l.nF, bidp, flagk.p, s);
+    long long* sB = S.take(2);
+    scan_async(flagk.p, excl.p, l.nF, sB, s);
+    frelax_block_starts(l.nF, flagk.p, excl.p, bstart.p, bnum.p, s);
+    frelax_row_len(l.nF, bnum.p, bstart.p, len.p, s);
+    Pend pM = csr_begin(l.M, l.nF, l.nF, len.p, S);
+    S.sync("block extraction");
+    csr_finish(pFF, S); csr_finish(pFC, S); csr_finish(pCF, S); csr_finish(pCC, S); csr_finish(pM, S);
+    long nb = (long)S.val(sB);
+    extract_fill(A, l.isF.p, l.lmap.p, l.AFF, l.AFC, l.ACF, l.ACC, s);
+    frelax_fill((int)nb, bstart.p, l.AFF, l.M, S.flag(), s);
     if (o.frelax == MGR_FRELAX_ILU0)
         throw Error(MGR_ERR_UNSUPPORTED, "ILU(0) F-relaxation is not available in the GPU library");
     if (o.frelax == MGR_FRELAX_AMG) {
@@ -430,38 +576,53 @@ static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr& A, const int* field
             gather_int(l.nF, l.fmap.p, field, flab.p, s);
         }
         amg_setup(*l.famg, csr_copy(l.AFF, s), o.amg_unknown_based ? flab.p : nullptr, fo,
-                  c.o.amg.seed + 0x1000193ULL * (uint64_t)(lev + 1), c.flag.p, s);
+                  c.o.amg.seed + 0x1000193ULL * (uint64_t)(lev + 1), S);
     }
-    // transfer operators and coarse operator (Petrov-Galerkin R A P)
-    l.PF = spgemm(l.M, l.AFC, c.flag.p, s);
+    // transfer operators and the Petrov-Galerkin coarse operator R A P
+    Spgemm jP, jW;
+    spgemm_begin(jP, l.M, l.AFC, l.PF, S);
+    spgemm_begin(jW, l.ACF, l.M, l.W, S);
+    S.sync("MGR transfer operators");
+    spgemm_finish(jP, S);
     negate(l.PF.v.p, l.PF.nnz, s);
-    l.W = spgemm(l.ACF, l.M, c.flag.p, s);
+    spgemm_finish(jW, S);
     if (o.restrict_type == MGR_RESTRICT_JACOBI) {
         l.RF = csr_copy(l.W, s);
         negate(l.RF.v.p, l.RF.nnz, s);
     }
-    DCsr T1 = spgemm(l.ACF, l.PF, c.flag.p, s);
-    DCsr Ac = csr_add(l.ACC, T1, s);
-    T1 = DCsr();
-    if (o.restrict_type == MGR_RESTRICT_JACOBI) {
-        DCsr T2 = spgemm(l.RF, l.AFC, c.flag.p, s);
-        DCsr S2 = csr_add(Ac, T2, s);
-        T2 = DCsr();
-        DCsr FFP = spgemm(l.AFF, l.PF, c.flag.p, s);
-        DCsr T3 = spgemm(l.RF, FFP, c.flag.p, s);
-        FFP = DCsr();
-        Ac = csr_add(S2, T3, s);
-    }
+    DCsr T1;
+    Spgemm j1;
+    spgemm_begin(j1, l.ACF, l.PF, T1, S);
     // fused one-sweep apply: r_c = [-omega A_CF M | I] v ; z = [P_F | omega M] [e_c ; v]
     l.fused = fused_ok(o);
+    DArr<int> lenR, lenP;
+    Pend pR, pP;
     if (l.fused) {
-        DArr<int> len((size_t)n + 1, s);
-        rj_count(l.nC, l.W, len.p, s);
-        l.RJ = csr_from_counts(l.nC, n, len.p, s);
+        lenR.alloc((size_t)l.nC + 1, s);
+        lenP.alloc((size_t)n + 1, s);
+        rj_count(l.nC, l.W, lenR.p, s);
+        pj_count(n, l.isF.p, l.lmap.p, l.PF, l.M, lenP.p, s);
+        pR = csr_begin(l.RJ, l.nC, n, lenR.p, S);
+        pP = csr_begin(l.PJ, n, l.nC + n, lenP.p, S);
+    }
+    S.sync("MGR coarse product");
+    spgemm_finish(j1, S);
+    if (l.fused) {
+        csr_finish(pR, S);
+        csr_finish(pP, S);
         rj_fill(l.nC, l.W, -o.omega, l.fmap.p, l.cmap.p, l.RJ, s);
-        pj_count(n, l.isF.p, l.lmap.p, l.PF, l.M, len.p, s);
-        l.PJ = csr_from_counts(n, l.nC + n, len.p, s);
         pj_fill(n, l.nC, l.isF.p, l.lmap.p, l.PF, 1.0, l.M, o.omega, l.fmap.p, l.PJ, s);
+    }
+    DCsr Ac = csr_add(l.ACC, T1, S);
+    T1 = DCsr();
+    if (o.restrict_type == MGR_RESTRICT_JACOBI) {
+        DCsr T2 = spgemm(l.RF, l.AFC, S);
+        DCsr S2 = csr_add(Ac, T2, S);
+        T2 = DCsr();
+        DCsr FFP = spgemm(l.AFF, l.PF, S);
+        DCsr T3 = spgemm(l.RF, FFP, S);
+        FFP = DCsr();
+        Ac = csr_add(S2, T3, S);
     }
     // level vectors
     l.rcd.alloc((size_t)l.nC + 1, s);
@@ -476,33 +637,34 @@ static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr& A, const int* field
 static void mgr_level_make_trans(Ctx& c, MgrLevel& l) {
     if (l.have_trans) return;
     hipStream_t s = c.s;
+    Slots& S = c.slots;
     if (l.o.sweeps != 1)
         throw Error(MGR_ERR_UNSUPPORTED, "transposed MGR apply needs one F-relaxation sweep per level");
     if (l.fused) {
         // r_c = [P_F^T | I] u ; z = [-omega W^T | omega M^T] [e ; u]
-        DCsr PFt = csr_transpose(l.PF, s);
-        DCsr Wt = csr_transpose(l.W, s);
-        DCsr Mt = csr_transpose(l.M, s);
+        DCsr PFt = csr_transpose(l.PF, S);
+        DCsr Wt = csr_transpose(l.W, S);
+        DCsr Mt = csr_transpose(l.M, S);
         DArr<int> len((size_t)l.n + 1, s);
         rj_count(l.nC, PFt, len.p, s);
-        l.RJt = csr_from_counts(l.nC, l.n, len.p, s);
+        l.RJt = csr_from_counts(l.nC, l.n, len.p, S, "transposed restriction");
         rj_fill(l.nC, PFt, 1.0, l.fmap.p, l.cmap.p, l.RJt, s);
         pj_count(l.n, l.isF.p, l.lmap.p, Wt, Mt, len.p, s);
-        l.PJt = csr_from_counts(l.n, l.nC + l.n, len.p, s);
+        l.PJt = csr_from_counts(l.n, l.nC + l.n, len.p, S, "transposed interpolation");
         pj_fill(l.n, l.nC, l.isF.p, l.lmap.p, Wt, -l.o.omega, Mt, l.o.omega, l.fmap.p, l.PJt, s);
         if (l.have_float) { make_float(l.RJt, s); make_float(l.PJt, s); }
     } else {
-        l.AFFt = csr_transpose(l.AFF, s);
-        l.ACFt = csr_transpose(l.ACF, s);
-        l.PFt = csr_transpose(l.PF, s);
-        l.Mt = csr_transpose(l.M, s);
-        if (l.o.restrict_type == MGR_RESTRICT_JACOBI) l.RFt = csr_transpose(l.RF, s);
+        l.AFFt = csr_transpose(l.AFF, S);
+        l.ACFt = csr_transpose(l.ACF, S);
+        l.PFt = csr_transpose(l.PF, S);
+        l.Mt = csr_transpose(l.M, S);
+        if (l.o.restrict_type == MGR_RESTRICT_JACOBI) l.RFt = csr_transpose(l.RF, S);
         if (l.have_float) {
             make_float(l.AFFt, s); make_float(l.ACFt, s); make_float(l.PFt, s); make_float(l.Mt, s);
             if (l.RFt.nr) make_float(l.RFt, s);
         }
     }
-    if (l.famg) amg_make_trans(*l.famg, s);
+    if (l.famg) amg_make_trans(*l.famg, S);
     l.have_trans = true;
 }
 
@@ -641,7 +803,7 @@ static void mgr_apply_top(Ctx& c, const double* v, double* z, bool tr) {
     if (!c.ready) throw Error(MGR_ERR_ARG, "apply before setup");
     if (tr) {
         for (auto& l : c.L) mgr_level_make_trans(c, l);
-        amg_make_trans(c.camg, c.s);
+        amg_make_trans(c.camg, c.slots);
     }
     bool f32 = (c.o.apply_precision == 32);
     if (f32) {
@@ -670,7 +832,7 @@ static void ensure_At(Ctx& c) {
     if (c.have_At) return;
     hipStream_t s = c.s;
     if (c.b == 1) {
-        c.A0t = csr_transpose(c.A0, s);
+        c.A0t = csr_transpose(c.A0, c.slots);
     } else {
         c.ATrp.alloc((size_t)c.nbr + 1, s);
         c.ATci.alloc((size_t)(c.nnzb > 0 ? c.nnzb : 1), s);
@@ -686,7 +848,7 @@ static void matvec(Ctx& c, bool tr, const double* x, const double* w, double* y,
     if (tr) ensure_At(c);
     if (c.b == 1) {
         spmv<double, double, double, double, double>(view<double>(tr ? c.A0t : c.A0), x, (const double*)nullptr,
-                                                     INT_MAX, w, y, alpha, beta, c.s);
+                                                     INT_MAX, w, y, alpha, beta, c.s, 1);
     } else {
         bsr_spmv(c.b, c.nbr, tr ? c.ATrp.p : c.Arp.p, tr ? c.ATci.p : c.Aci.p, tr ? c.ATv.p : c.Av.p, c.nnzb, x, w,
                  y, alpha, beta, c.s);
@@ -857,6 +1019,8 @@ static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nle
     } else {
         bsr_expand(c.b, c.nbr, c.Arp.p, c.Aci.p, c.Av.p, c.A0.rp.p, c.A0.ci.p, c.A0.v.p, s);
     }
+    make_rowblocks(c.A0, s);
+    c.A0.max_row = max_row_len(c.A0, s);
     DArr<int> fld((size_t)c.n, s), blk((size_t)c.n, s);
     MGR_HIP(hipMemcpyAsync(fld.p, field, sizeof(int) * c.n, hipMemcpyDeviceToDevice, s));
     iota_div(c.n, c.b, blk.p, s);
@@ -880,7 +1044,7 @@ static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nle
         }
     }
     amg_setup(c.camg, nlevels > 0 ? std::move(next) : csr_copy(c.A0, s), c.o.amg.unknown_based ? fld.p : nullptr,
-              c.o.amg, c.o.amg.seed, c.flag.p, s);
+              c.o.amg, c.o.amg.seed, c.slots);
     if (c.o.apply_precision == 32) {
         for (auto& l : c.L) mgr_level_make_float(c, l);
         amg_make_float(c.camg, s);
@@ -1009,8 +1173,15 @@ int mgr_create(mgr_handle* h, const mgr_opts* o, void* hip_stream) {
     c->c.s = (hipStream_t)hip_stream;
     c->c.o = d;
     try {
-        c->c.flag.alloc(1, c->c.s);
-        mgr::flag_clear(c->c.flag.p, c->c.s);
+        // keep freed blocks in the stream-ordered pool across synchronisations:
+        // a setup re-allocates the same sizes every time it runs
+        int dev = 0;
+        MGR_HIP(hipGetDevice(&dev));
+        hipMemPool_t pool;
+        MGR_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+        uint64_t thr = UINT64_MAX;
+        MGR_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+        c->c.slots.init(c->c.s);
         hipError_t e = hipStreamSynchronize(c->c.s);
         if (e != hipSuccess) throw Error(MGR_ERR_HIP, hipGetErrorString(e));
     } catch (...) {
