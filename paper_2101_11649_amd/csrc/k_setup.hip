@@ -288,7 +288,10 @@ __global__ void k_frelax_len(int nF, const int* __restrict__ bnum, const int* __
 }
 
 // Gauss-Jordan inverse with partial pivoting (ties to the lower row): scale the
-// pivot row by 1/pivot, then subtract f times it from every other row.
+// pivot row by 1/pivot, then subtract f times it from every other row.  On a
+// failure (block larger than 4, zero or non-finite pivot) the flag is raised
+// and the rows are still written, with valid column indices and zero values,
+// so that no later kernel reads an unwritten index.
 __global__ void k_frelax_fill(int nb, const int* __restrict__ bstart, const int* __restrict__ arp,
                               const int* __restrict__ aci, const double* __restrict__ av,
                               const int* __restrict__ mrp, int* __restrict__ mci, double* __restrict__ mv,
@@ -296,40 +299,50 @@ __global__ void k_frelax_fill(int nb, const int* __restrict__ bstart, const int*
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nb) return;
     int s0 = bstart[t], bs = bstart[t + 1] - s0;
-    if (bs > 4) { set_flag(flag, 6); return; }
+    bool ok = bs <= 4;
+    if (!ok) set_flag(flag, 6);
     double a[16], e[16];
-    for (int r = 0; r < bs; ++r)
-        for (int c = 0; c < bs; ++c) { a[r * bs + c] = 0.0; e[r * bs + c] = (r == c) ? 1.0 : 0.0; }
-    for (int r = 0; r < bs; ++r)
-        for (int p = arp[s0 + r]; p < arp[s0 + r + 1]; ++p) {
-            int c = aci[p] - s0;
-            if (c >= 0 && c < bs) a[r * bs + c] = av[p];
-        }
-    for (int c = 0; c < bs; ++c) {
-        int pv = c;
-        double best = fabs(a[c * bs + c]);
-        for (int r = c + 1; r < bs; ++r)
-            if (fabs(a[r * bs + c]) > best) { best = fabs(a[r * bs + c]); pv = r; }
-        if (!(best > 0.0) || !isfinite(best)) { set_flag(flag, 3); return; }
-        if (pv != c)
-            for (int k = 0; k < bs; ++k) {
-                double x = a[c * bs + k]; a[c * bs + k] = a[pv * bs + k]; a[pv * bs + k] = x;
-                x = e[c * bs + k]; e[c * bs + k] = e[pv * bs + k]; e[pv * bs + k] = x;
+    if (ok) {
+        for (int r = 0; r < bs; ++r)
+            for (int c = 0; c < bs; ++c) { a[r * bs + c] = 0.0; e[r * bs + c] = (r == c) ? 1.0 : 0.0; }
+        for (int r = 0; r < bs; ++r)
+            for (int p = arp[s0 + r]; p < arp[s0 + r + 1]; ++p) {
+                int c = aci[p] - s0;
+                if (c >= 0 && c < bs) a[r * bs + c] = av[p];
             }
-        double ip = 1.0 / a[c * bs + c];
-        for (int k = 0; k < bs; ++k) { a[c * bs + k] = a[c * bs + k] * ip; e[c * bs + k] = e[c * bs + k] * ip; }
-        for (int r = 0; r < bs; ++r) {
-            if (r == c) continue;
-            double f = a[r * bs + c];
-            for (int k = 0; k < bs; ++k) {
-                a[r * bs + k] = a[r * bs + k] - f * a[c * bs + k];
-                e[r * bs + k] = e[r * bs + k] - f * e[c * bs + k];
+        for (int c = 0; c < bs && ok; ++c) {
+            int pv = c;
+            double best = fabs(a[c * bs + c]);
+            for (int r = c + 1; r < bs; ++r)
+                if (fabs(a[r * bs + c]) > best) { best = fabs(a[r * bs + c]); pv = r; }
+            if (!(best > 0.0) || !isfinite(best)) {
+                set_flag(flag, 3);
+                ok = false;
+                break;
+            }
+            if (pv != c)
+                for (int k = 0; k < bs; ++k) {
+                    double x = a[c * bs + k]; a[c * bs + k] = a[pv * bs + k]; a[pv * bs + k] = x;
+                    x = e[c * bs + k]; e[c * bs + k] = e[pv * bs + k]; e[pv * bs + k] = x;
+                }
+            double ip = 1.0 / a[c * bs + c];
+            for (int k = 0; k < bs; ++k) { a[c * bs + k] = a[c * bs + k] * ip; e[c * bs + k] = e[c * bs + k] * ip; }
+            for (int r = 0; r < bs; ++r) {
+                if (r == c) continue;
+                double f = a[r * bs + c];
+                for (int k = 0; k < bs; ++k) {
+                    a[r * bs + k] = a[r * bs + k] - f * a[c * bs + k];
+                    e[r * bs + k] = e[r * bs + k] - f * e[c * bs + k];
+                }
             }
         }
     }
     for (int r = 0; r < bs; ++r) {
         int o = mrp[s0 + r];
-        for (int c = 0; c < bs; ++c) { mci[o + c] = s0 + c; mv[o + c] = e[r * bs + c]; }
+        for (int c = 0; c < bs; ++c) {
+            mci[o + c] = s0 + c;
+            mv[o + c] = ok ? e[r * bs + c] : 0.0;
+        }
     }
 }
 

@@ -564,6 +564,8 @@ static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr& A, const int* field
     long nb = (long)S.val(sB);
     extract_fill(A, l.isF.p, l.lmap.p, l.AFF, l.AFC, l.ACF, l.ACC, s);
     frelax_fill((int)nb, bstart.p, l.AFF, l.M, S.flag(), s);
+    // nothing may consume M before its pivots are known to be valid
+    S.sync("F-relaxation operator");
     if (o.frelax == MGR_FRELAX_ILU0)
         throw Error(MGR_ERR_UNSUPPORTED, "ILU(0) F-relaxation is not available in the GPU library");
     if (o.frelax == MGR_FRELAX_AMG) {

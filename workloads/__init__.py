@@ -203,6 +203,109 @@ def hybrid_mimetic(nx=64, ny=64, nz=64, seed=1, consistent=True, upwind=True, nr
                    f"hybrid_mimetic_{'consistent' if consistent else 'tpfa'}_{nx}x{ny}x{nz}", **extra)
 
 
+def compositional_wells(nx=128, ny=128, nz=64, seed=2, wells_per_axis=4, nperf=3, margin_p=1.1, margin_rho=2.0):
+    """Compositional-style system: 4 unknowns per cell -- pressure (field 0) and
+    three component densities (fields 1-3) -- as interleaved 4x4 blocks on the
+    7-point stencil, plus vertical wells (well-pressure equation, field 4) each
+    stored as one extra block row whose other three unknowns are identity
+    padding (field 5).
+
+    Off-diagonal block (c, d) = -T_cd W with W_00 = 1, W_{p,rho} and W_{rho,p}
+    ~ U[0, 0.5], and W_{rho,rho'} ~ U[0, 0.5] only when d is upwind of c (random
+    upwind direction per face); T_cd harmonic, log10 k ~ N(0,1).  Diagonal block:
+    1.1 times the absolute row sum of the off-diagonal blocks plus an
+    accumulation term U[0.1, 1] on the diagonal, intra-cell off-diagonals
+    U[-0.1, 0.1] times the row's diagonal.  Wells sit at the centres of a
+    wells_per_axis^2 lattice in (x, y), perforated in layers k = 0..nperf-1 with
+    WI = 10^N(0,1) k_c: each equation e of a perforated cell gets -WI m_e in the
+    well column and +WI m_e in its pressure column (m_e ~ U[0.5, 1]); the well
+    row has sum(WI) + 1e-3 on the diagonal and -WI at each perforated pressure.
+    Reduction order: components (+ padding) by block-Jacobi, then wells by
+    Jacobi, then AMG on the cell pressures."""
+    g = _rngs(seed)
+    ncell = nx * ny * nz
+    k = 10.0 ** g["perm"].standard_normal(ncell)
+    acc = g["accum"].uniform(0.1, 1.0, (ncell, 4))
+    kz, ky, kx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    kx, ky, kz = kx.ravel(), ky.ravel(), kz.ravel()
+    cells = np.arange(ncell)
+    offs = np.array([-nx * ny, -nx, -1, 0, 1, nx, nx * ny])
+    exist = np.stack([kz > 0, ky > 0, kx > 0, np.ones(ncell, bool), kx < nx - 1, ky < ny - 1, kz < nz - 1], 1)
+    # face flow direction for the + faces of every cell (x, y, z); >= 0 means from c to c+off
+    gface = g["upwind"].standard_normal((ncell, 3))
+    blocks = np.zeros((ncell, 8, 4, 4))
+    for sl in (0, 1, 2, 4, 5, 6):
+        m = exist[:, sl]
+        c = cells[m]
+        d = c + offs[sl]
+        T = 2.0 * k[c] * k[d] / (k[c] + k[d])
+        axis = {0: 2, 1: 1, 2: 0, 4: 0, 5: 1, 6: 2}[sl]
+        if sl > 3:
+            d_upwind = gface[c, axis] < 0.0       # flow from d to c
+        else:
+            d_upwind = gface[d, axis] >= 0.0      # flow from d (lower index) to c
+        W = np.zeros((len(c), 4, 4))
+        W[:, 0, 0] = 1.0
+        W[:, 0, 1:] = g["noise"].uniform(0.0, 0.5, (len(c), 3))
+        W[:, 1:, 0] = g["noise"].uniform(0.0, 0.5, (len(c), 3))
+        W[:, 1:, 1:] = g["noise"].uniform(0.0, 0.5, (len(c), 3, 3)) * d_upwind[:, None, None]
+        blocks[m, sl] = -T[:, None, None] * W
+    rowabs = np.abs(blocks).sum(axis=(1, 3))            # (ncell, 4): off-diagonal blocks only so far
+    diag = np.array([margin_p, margin_rho, margin_rho, margin_rho])[None, :] * rowabs + acc
+    intra = g["noise"].uniform(-0.1, 0.1, (ncell, 4, 4)) * diag[:, :, None]
+    intra[:, np.arange(4), np.arange(4)] = diag
+    blocks[:, 3] = intra
+    # wells
+    pos = [(2 * m + 1) * nx // (2 * wells_per_axis) for m in range(wells_per_axis)]
+    posy = [(2 * m + 1) * ny // (2 * wells_per_axis) for m in range(wells_per_axis)]
+    wells = [(i, j) for j in posy for i in pos]
+    nw = len(wells)
+    nperf = min(nperf, nz)
+    perf_cells = np.array([[i + nx * (j + ny * kk) for kk in range(nperf)] for (i, j) in wells])   # (nw, nperf)
+    WI = (10.0 ** g["wells"].standard_normal((nw, nperf))) * k[perf_cells]
+    me = g["wells"].uniform(0.5, 1.0, (nw, nperf, 4))
+    wblk_cell = np.zeros((nw, nperf, 4, 4))       # block (cell, well): column 0 = well pressure
+    wblk_cell[:, :, :, 0] = -WI[:, :, None] * me
+    for w in range(nw):
+        for q in range(nperf):
+            blocks[perf_cells[w, q], 3, :, 0] += WI[w, q] * me[w, q]
+    exist8 = np.concatenate([exist, np.zeros((ncell, 1), bool)], 1)
+    has_well = np.zeros(ncell, np.int64) - 1
+    for w in range(nw):
+        for q in range(nperf):
+            c = perf_cells[w, q]
+            has_well[c] = w
+            exist8[c, 7] = True
+            blocks[c, 7] = wblk_cell[w, q]
+    # block-CSR: cell rows (slots ascending by column), then well rows
+    cnt = exist8.sum(1)
+    well_cnt = np.full(nw, nperf + 1)
+    rp = np.concatenate([[0], np.cumsum(np.concatenate([cnt, well_cnt]))]).astype(np.int64)
+    colmat = cells[:, None] + np.concatenate([offs, [0]])[None, :]
+    colmat[:, 7] = ncell + np.maximum(has_well, 0)
+    ci_cells = colmat[exist8]
+    vals_cells = blocks[exist8]
+    del blocks
+    ci_w, v_w = [], []
+    for w in range(nw):
+        for q in range(nperf):
+            b = np.zeros((4, 4))
+            b[0, 0] = -WI[w, q]
+            ci_w.append(perf_cells[w, q]); v_w.append(b)
+        b = np.eye(4)
+        b[0, 0] = WI[w].sum() + 1e-3
+        ci_w.append(ncell + w); v_w.append(b)
+    ci = np.concatenate([ci_cells, np.array(ci_w, np.int64)]).astype(np.int32)
+    vals = np.concatenate([vals_cells.reshape(-1), np.array(v_w).reshape(-1)])
+    field = np.concatenate([np.tile(np.arange(4, dtype=np.int32), ncell),
+                            np.tile(np.array([4, 5, 5, 5], np.int32), nw)])
+    rhs = g["rhs"].standard_normal(4 * (ncell + nw))
+    rhs[field == 5] = 0.0
+    levels = [level((1 << 1) | (1 << 2) | (1 << 3) | (1 << 5), "block_jacobi"), level(1 << 4, "jacobi")]
+    return _system(4, rp.astype(np.int32), ci, vals, field, rhs, levels,
+                   f"compositional_wells_{nx}x{ny}x{nz}", grid=(nx, ny, nz), nwells=nw, ncell=ncell)
+
+
 def csr_of(system):
     """Scalar scipy CSR view of a generated system (block layout expanded)."""
     b = system["b"]
@@ -216,6 +319,7 @@ def csr_of(system):
 CONFIGS = {
     0: lambda: two_field_tpfa(16, 16, 16, seed=0),
     1: lambda: hybrid_mimetic(64, 64, 64, seed=1),
+    2: lambda: compositional_wells(128, 128, 64, seed=2),
 }
 
 
