@@ -35,11 +35,13 @@ def spmv_bytes(n, nnz, s=8):
 
 def time_kernel(fn, stream, reps, flush_buf):
     """Average duration of fn() (one kernel launch) with HIP events on `stream`,
-    flushing the 256 MB Infinity Cache with a 512 MB write between launches."""
+    evicting the 256 MB Infinity Cache between launches by reading a 512 MB
+    buffer (a read leaves no dirty lines whose write-back would land in the
+    timed launch)."""
     import torch
     ts = []
     for _ in range(reps):
-        flush_buf.fill_(1.0)
+        flush_buf.sum()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -48,6 +50,26 @@ def time_kernel(fn, stream, reps, flush_buf):
         e1.synchronize()
         ts.append(e0.elapsed_time(e1) * 1e-3)
     return statistics.mean(ts), ts
+
+
+def kernel_traffic(name):
+    """HBM bytes per launch of `name` from the committed rocprofv3 counter summary
+    (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None if the summary
+    is missing or the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", name)
+    src = os.path.join(ROOT, "paper_2101_11649_amd", "csrc", "k_apply.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if fields.get("k_apply.hip sha256") != sha or "traffic bytes per launch" not in fields:
+        return None
+    return int(float(fields["traffic bytes per launch"]))
 
 
 def run_steps(P, s, vals, rhs, precision, steps, warmup):
@@ -79,6 +101,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--grid", type=int, default=64, help="grid size per axis of the mimetic system")
+    ap.add_argument("--comp-steps", type=int, default=2,
+                    help="timed steps of the secondary compositional workload (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not part of "
@@ -111,7 +135,10 @@ def main():
     value = statistics.mean(tot64)
 
     # ---- roofline of the dominant kernel: the FGMRES CSR SpMV on A (FP64)
-    flush = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    flush = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
+    # calibration launch for the byte counters: a plain 512 MB device copy
+    calib = torch.empty_like(flush)
+    calib.copy_(flush)
     xv = torch.randn(n, dtype=torch.float64, device="cuda")
     yv = torch.empty_like(xv)
     lib = P.lib()
@@ -130,6 +157,38 @@ def main():
     ap64(); ap32()
     t_ap64, _ = time_kernel(ap64, stream, 20, flush)
     t_ap32, _ = time_kernel(ap32, stream, 20, flush)
+
+    # ---- secondary: the compositional system with wells (128x128x64, 4 unknowns per
+    # cell, 16 wells; 2-level MGR), FP64 vs FP32 apply inside FP64 FGMRES
+    comp = None
+    if args.comp_steps > 0:
+        log("generating compositional 128x128x64 + 16 wells ...")
+        c2 = W.compositional_wells(seed=2)
+        v2 = torch.tensor(c2["vals"], device="cuda")
+        b2 = torch.tensor(c2["rhs"], device="cuda")
+        s64, r64, _, _, _ = run_steps(P, c2, v2, b2, 64, args.comp_steps, 1)
+        s32, r32, _, _, _ = run_steps(P, c2, v2, b2, 32, args.comp_steps, 1)
+        t64 = statistics.mean(a + b for a, b, _, _ in r64)
+        t32 = statistics.mean(a + b for a, b, _, _ in r32)
+        vv = torch.randn(c2["n"], dtype=torch.float64, device="cuda")
+        zz = torch.empty_like(vv)
+        a64 = lambda: lib.mgr_apply(s64._h, ctypes.c_void_p(vv.data_ptr()), ctypes.c_void_p(zz.data_ptr()))
+        a32 = lambda: lib.mgr_apply(s32._h, ctypes.c_void_p(vv.data_ptr()), ctypes.c_void_p(zz.data_ptr()))
+        a64(); a32()
+        ta64, _ = time_kernel(a64, stream, 10, flush)
+        ta32, _ = time_kernel(a32, stream, 10, flush)
+        comp = {"workload": "compositional_wells_128x128x64", "n": c2["n"], "nnz": int(len(c2["ci"]) * 16),
+                "mgr": "L1 F = components (block-Jacobi), L2 F = wells (Jacobi), coarse pressure AMG",
+                "fp64": {"time_to_tol_s": round(t64, 6), "setup_s": round(statistics.mean(a for a, _, _, _ in r64), 6),
+                         "solve_s": round(statistics.mean(b for _, b, _, _ in r64), 6), "iterations": r64[-1][2],
+                         "rel_res_true": r64[-1][3], "apply_ms": round(1e3 * ta64, 4)},
+                "fp32": {"time_to_tol_s": round(t32, 6), "setup_s": round(statistics.mean(a for a, _, _, _ in r32), 6),
+                         "solve_s": round(statistics.mean(b for _, b, _, _ in r32), 6), "iterations": r32[-1][2],
+                         "rel_res_true": r32[-1][3], "apply_ms": round(1e3 * ta32, 4)},
+                "speedup_time_to_tol": round(t64 / t32, 4), "speedup_per_apply": round(ta64 / ta32, 4)}
+        s64.close()
+        s32.close()
+        del c2, v2, b2
 
     # ---- FP64 oracle on the machine's host cores (bounded sample: one full setup + solve of this workload)
     cpu = None
@@ -183,10 +242,12 @@ def main():
             "apply_ms_fp32": round(1e3 * t_ap32, 4),
             "speedup_per_apply": round(t_ap64 / t_ap32, 4),
         },
-        "roofline": {"kernel": "k_spmv<double> (FGMRES matvec, CSR, FP64)", "bound": "hbm",
-                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "roofline": {"kernel": "k_spmv_stream<double, 1, SpmvOp> (FGMRES matvec y = A x, CSR, FP64)",
+                     "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": kernel_traffic("k_spmv_fgmres_mimetic64.md"),
                      "bytes_per_launch": nbytes, "avg_launch_us": round(1e6 * t_spmv, 2)},
+        "secondary_compositional": comp,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
