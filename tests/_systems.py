@@ -14,11 +14,22 @@ SMALL = {
     # 4x4 blocks + wells, two MGR levels (block-Jacobi, then Jacobi on wells)
     "comp_8x8x6": lambda: W.compositional_wells(8, 8, 6, seed=7),
     "comp_20x18x10": lambda: W.compositional_wells(20, 18, 10, seed=8, wells_per_axis=3),
+    # elasticity (3x3 blocks) + fracture pressures; F-relaxation = unknown-based AMG V-cycle
+    "frac_12^3": lambda: W.fracturing(12, seed=5),
+    "frac_18^3": lambda: W.fracturing(18, seed=6),
 }
+
+
+def _opts(s, kw):
+    o = dict(s.get("solver_opts", {}))
+    o.update(kw)
+    return o
 
 
 def oracle_mgr(s, levels=None, **kw):
     lv = [O.LevelOpts(**l) for l in (levels if levels is not None else s["levels"])]
+    kw = {k: v for k, v in _opts(s, kw).items() if k in ("theta", "max_levels", "max_coarse", "nu_pre", "nu_post",
+                                                         "coarse_unknown_based", "seed")}
     m = O.MGR(s["b"], s["rp"], s["ci"], s["vals"], s["field"], lv, **kw)
     assert m.status == 0, m.status
     return m
@@ -27,7 +38,7 @@ def oracle_mgr(s, levels=None, **kw):
 def gpu_solver(s, levels=None, **kw):
     import paper_2101_11649_amd as P
     return P.Solver(s["b"], s["rp"], s["ci"], s["vals"], s["field"],
-                    levels if levels is not None else s["levels"], **kw)
+                    levels if levels is not None else s["levels"], **_opts(s, kw))
 
 
 def rel(a, b):

@@ -63,6 +63,25 @@ def test_hierarchy_bit_exact(built, name):
             assert np.array_equal(gs.export(1, k, 0), om.export(1, k, 0)), f"AMG level {k} C/F"
             bitwise.append(_compare_csr(gs.export(1, k, 2), om.export(1, k, 2), f"AMG{k} P"))
         bitwise.append(_compare_csr(gs.export(1, k, 1), om.export(1, k, 1), f"AMG{k} A"))
+    # AMG hierarchies used as F-relaxation (MGR_FRELAX_AMG levels)
+    for l, lv in enumerate(s["levels"]):
+        if lv.get("frelax") != "amg":
+            continue
+        k = 0
+        while True:
+            try:
+                o = om.export(2, k, 1, sub=l)
+            except KeyError:
+                break
+            bitwise.append(_compare_csr(gs.export(2, k, 1, sub=l), o, f"F-AMG{k} A"))
+            try:
+                ocf = om.export(2, k, 0, sub=l)
+            except KeyError:
+                break
+            assert np.array_equal(gs.export(2, k, 0, sub=l), ocf), f"F-relaxation AMG level {k} C/F"
+            bitwise.append(_compare_csr(gs.export(2, k, 2, sub=l), om.export(2, k, 2, sub=l), f"F-AMG{k} P"))
+            k += 1
+        assert k >= 2
     say(f"{name}: values bitwise equal in {sum(bitwise)}/{len(bitwise)} operators")
     assert all(bitwise)
 

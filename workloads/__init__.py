@@ -306,6 +306,149 @@ def compositional_wells(nx=128, ny=128, nz=64, seed=2, wells_per_axis=4, nperf=3
                    f"compositional_wells_{nx}x{ny}x{nz}", grid=(nx, ny, nz), nwells=nw, ncell=ncell)
 
 
+def _q1_reference_stiffness(nu):
+    """24x24 stiffness of the unit trilinear hex for E = 1 (2x2x2 Gauss points),
+    dofs ordered (node a, component c) -> 3a + c, nodes in (x fastest) order."""
+    lam = nu / ((1 + nu) * (1 - 2 * nu))
+    mu = 1.0 / (2 * (1 + nu))
+    D = np.zeros((6, 6))
+    D[:3, :3] = lam
+    D[np.arange(3), np.arange(3)] += 2 * mu
+    D[np.arange(3, 6), np.arange(3, 6)] = mu
+    corners = np.array([[(a >> 0) & 1, (a >> 1) & 1, (a >> 2) & 1] for a in range(8)], float)
+    gp = np.array([0.5 - 0.5 / np.sqrt(3), 0.5 + 0.5 / np.sqrt(3)])
+    K = np.zeros((24, 24))
+    for x in gp:
+        for y in gp:
+            for z in gp:
+                q = np.array([x, y, z])
+                dN = np.zeros((8, 3))
+                for a in range(8):
+                    f = np.where(corners[a] == 1, q, 1 - q)
+                    sgn = np.where(corners[a] == 1, 1.0, -1.0)
+                    dN[a] = [sgn[0] * f[1] * f[2], f[0] * sgn[1] * f[2], f[0] * f[1] * sgn[2]]
+                B = np.zeros((6, 24))
+                for a in range(8):
+                    B[0, 3 * a] = dN[a, 0]; B[1, 3 * a + 1] = dN[a, 1]; B[2, 3 * a + 2] = dN[a, 2]
+                    B[3, 3 * a] = dN[a, 1]; B[3, 3 * a + 1] = dN[a, 0]
+                    B[4, 3 * a + 1] = dN[a, 2]; B[4, 3 * a + 2] = dN[a, 1]
+                    B[5, 3 * a] = dN[a, 2]; B[5, 3 * a + 2] = dN[a, 0]
+                K += B.T @ D @ B / 8.0
+    return K, corners.astype(int)
+
+
+def fracturing(nn=96, seed=3, nu=0.25, cs=0.1, storage=1e-2):
+    """Hydraulic-fracturing-style system (Sec. 3.3, App. C): Q1 hexahedral
+    elasticity on an nn^3 node grid (3 displacement unknowns per node, fields
+    0-2), Young's modulus per element with ln E ~ N(0,1), Poisson ratio 0.25,
+    Dirichlet outer boundary (identity rows, couplings removed), coupled to a
+    planar fracture of nn x nn cells on the node plane y = nn/2 (one pressure
+    per cell, field 3, grouped three per 3x3 block row).
+
+    Fracture flow: 5-point cubic-law stencil with T = harmonic mean of w^3/12
+    (aperture ln w ~ N(0, 0.5^2), unit viscosity) plus a storage term 1e-2.
+    Coupling at the node tied to each interior cell: -1 from pressure into the
+    node's u_y equation (traction) and +cs from u_y into the cell's mass balance
+    (aperture storage), so the pressure Schur complement gains a positive term.
+    Reduction (MGR_U): F = displacements, F-relaxation one unknown-based AMG
+    V-cycle on A_uu, Jacobi interpolation, injection; AMG on the coarse system."""
+    if (nn * nn) % 3:
+        raise ValueError("nn^2 must be a multiple of 3 (pressures are grouped three per block row)")
+    g = _rngs(seed)
+    ne = nn - 1
+    nnode = nn ** 3
+    E = np.exp(g["perm"].standard_normal(ne ** 3))
+    K0, corners = _q1_reference_stiffness(nu)
+    ez, ey, ex = np.meshgrid(np.arange(ne), np.arange(ne), np.arange(ne), indexing="ij")
+    ex, ey, ez = ex.ravel(), ey.ravel(), ez.ravel()
+    nid = lambda x, y, z: x + nn * (y + nn * z)
+    # 27-slot layout: slot of offset (dx,dy,dz) = (dx+1) + 3(dy+1) + 9(dz+1); ascending slot = ascending column
+    blocks = np.zeros((nnode, 27, 3, 3))
+    for a in range(8):
+        na = nid(ex + corners[a, 0], ey + corners[a, 1], ez + corners[a, 2])
+        for b in range(8):
+            d = corners[b] - corners[a]
+            slot = (d[0] + 1) + 3 * (d[1] + 1) + 9 * (d[2] + 1)
+            blocks[na, slot] += E[:, None, None] * K0[3 * a:3 * a + 3, 3 * b:3 * b + 3][None]
+    kz, ky, kx = np.meshgrid(np.arange(nn), np.arange(nn), np.arange(nn), indexing="ij")
+    kx, ky, kz = kx.ravel(), ky.ravel(), kz.ravel()
+    interior = (kx > 0) & (kx < nn - 1) & (ky > 0) & (ky < nn - 1) & (kz > 0) & (kz < nn - 1)
+    exist = np.zeros((nnode, 28), bool)
+    cols = np.zeros((nnode, 28), np.int64)
+    for slot in range(27):
+        dx, dy, dz = slot % 3 - 1, (slot // 3) % 3 - 1, slot // 9 - 1
+        x, y, z = kx + dx, ky + dy, kz + dz
+        inside = (x >= 0) & (x < nn) & (y >= 0) & (y < nn) & (z >= 0) & (z < nn)
+        nb = np.where(inside, nid(np.clip(x, 0, nn - 1), np.clip(y, 0, nn - 1), np.clip(z, 0, nn - 1)), 0)
+        exist[:, slot] = interior & inside & interior[nb]
+        cols[:, slot] = nb
+    # Dirichlet boundary nodes: identity diagonal block only
+    bnd = ~interior
+    blocks[bnd] = 0.0
+    blocks[bnd, 13] = np.eye(3)
+    exist[bnd, 13] = True
+    # fracture
+    jf = nn // 2
+    ncell = nn * nn
+    w = np.exp(0.5 * g["noise"].standard_normal(ncell))
+    tw = w ** 3 / 12.0
+    ci_, ck_ = np.meshgrid(np.arange(nn), np.arange(nn), indexing="ij")   # cell q = i + nn k
+    ci_, ck_ = ci_.T.ravel(), ck_.T.ravel()
+    q_of = lambda i, k: i + nn * k
+    node_of_cell = nid(ci_, np.full(ncell, jf), ck_)
+    coupled = interior[node_of_cell]
+    pr0 = nnode            # block row of the first pressure triple
+    # node rows: one extra block in the node's row for its cell's pressure triple
+    qc = np.arange(ncell)[coupled]
+    mc = node_of_cell[coupled]
+    exist[mc, 27] = True
+    cols[mc, 27] = pr0 + qc // 3
+    extra = np.zeros((nnode, 3, 3))
+    extra[mc, 1, qc % 3] = -1.0
+    # pressure rows as block triplets
+    trip_r, trip_c, trip_i, trip_j, trip_v = [], [], [], [], []
+    def addp(qa, col_block, i_in, j_in, v):
+        trip_r.append(qa // 3); trip_c.append(col_block); trip_i.append(qa % 3); trip_j.append(j_in); trip_v.append(v)
+    diag = np.full(ncell, storage)
+    for (di, dk) in ((1, 0), (0, 1)):
+        m = (ci_ + di < nn) & (ck_ + dk < nn)
+        qa = np.arange(ncell)[m]
+        qb = q_of(ci_[m] + di, ck_[m] + dk)
+        T = 2 * tw[qa] * tw[qb] / (tw[qa] + tw[qb])
+        np.add.at(diag, qa, T); np.add.at(diag, qb, T)
+        addp(qa, pr0 + qb // 3, None, qb % 3, -T)
+        addp(qb, pr0 + qa // 3, None, qa % 3, -T)
+    q = np.arange(ncell)
+    addp(q, pr0 + q // 3, None, q % 3, diag)
+    addp(qc, mc, None, np.full(len(qc), 1), np.full(len(qc), cs))
+    R = np.concatenate(trip_r); C = np.concatenate(trip_c); I = np.concatenate(trip_i)
+    J = np.concatenate([np.broadcast_to(j, np.shape(r)) for j, r in zip(trip_j, trip_r)])
+    V = np.concatenate(trip_v)
+    npr = ncell // 3
+    key = R.astype(np.int64) * (nnode + npr) + C
+    ukey, inv = np.unique(key, return_inverse=True)
+    pvals = np.zeros((len(ukey), 3, 3))
+    np.add.at(pvals, (inv, I, J), V)
+    prow = ukey // (nnode + npr)
+    pcol = ukey % (nnode + npr)
+    # assemble
+    cnt_nodes = exist.sum(1)
+    cnt_p = np.bincount(prow, minlength=npr)
+    rp = np.concatenate([[0], np.cumsum(np.concatenate([cnt_nodes, cnt_p]))])
+    allblocks = np.concatenate([blocks, extra[:, None]], axis=1)
+    del blocks
+    vals = np.concatenate([allblocks[exist].reshape(-1), pvals.reshape(-1)])
+    ci = np.concatenate([cols[exist], pcol]).astype(np.int32)
+    del allblocks
+    field = np.concatenate([np.tile(np.arange(3, dtype=np.int32), nnode), np.full(ncell, 3, np.int32)])
+    rhs = g["rhs"].standard_normal(3 * nnode + ncell)
+    rhs[:3 * nnode][np.repeat(bnd, 3)] = 0.0
+    levels = [level((1 << 0) | (1 << 1) | (1 << 2), "amg", amg_unknown_based=True)]
+    # two L1-Jacobi sweeps per side stand in for the paper's hybrid L1 Gauss-Seidel
+    return _system(3, rp.astype(np.int32), ci, vals, field, rhs, levels, f"fracturing_{nn}^3",
+                   nnode=nnode, ncell=ncell, solver_opts=dict(nu_pre=2, nu_post=2))
+
+
 def csr_of(system):
     """Scalar scipy CSR view of a generated system (block layout expanded)."""
     b = system["b"]
@@ -320,6 +463,7 @@ CONFIGS = {
     0: lambda: two_field_tpfa(16, 16, 16, seed=0),
     1: lambda: hybrid_mimetic(64, 64, 64, seed=1),
     2: lambda: compositional_wells(128, 128, 64, seed=2),
+    3: lambda: fracturing(96, seed=3),
 }
 
 
