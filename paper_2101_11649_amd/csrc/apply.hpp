@@ -87,6 +87,10 @@ void mdot(long n, const double* V, long ldv, int nvec, const double* w, double* 
 // w -= hscale * sum_i h[i] V_i; if norm2_out, *norm2_out = ||w_new||^2.
 void maxpy(long n, const double* V, long ldv, int nvec, const double* h, double hscale, double* w, double* part,
            double* norm2_out, hipStream_t s);
+// rows[0..cnt) of one level of a triangular solve with matrix A: x_i = (b_i - sum_{j!=i} a_ij x_j) / a_ii
+// (unit: diagonal 1 and not stored).  b may alias x.
+template <typename T>
+void trsv_level(int cnt, const int* rows, const SpOp<T>& A, const T* b, T* x, bool unit, hipStream_t s);
 void grad_values(int b, int nbr, const int* rp, const int* ci, long nnzb, int nrhs, const double* lam,
                  const double* x, double* dv, hipStream_t s);
 

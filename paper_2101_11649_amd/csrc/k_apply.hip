@@ -327,6 +327,23 @@ __global__ __launch_bounds__(TPB) void k_maxpy(long n, const double* __restrict_
     }
 }
 
+// One level of a triangular solve: for the rows of this level,
+// x_i = (b_i - sum_{j != i} t_ij x_j) / t_ii (unit: no division, no diagonal stored).
+template <typename T>
+__global__ void k_trsv_level(int cnt, const int* __restrict__ rows, const int* __restrict__ rp,
+                             const int* __restrict__ ci, const T* __restrict__ v, const T* b, T* x, int unit) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt) return;
+    int i = rows[t];
+    T s = b[i], d = T(1);
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        int j = ci[p];
+        if (j == i) d = v[p];
+        else s -= v[p] * x[j];
+    }
+    x[i] = unit ? s : s / d;
+}
+
 // Adjoint gradient on the block pattern: dv[p,r,c] = -sum_k lam_k[I b + r] x_k[J b + c].
 __global__ void k_grad(long nnzb, int b, int nbr, const int* __restrict__ rp, const int* __restrict__ ci, long n,
                        int nrhs, const double* __restrict__ lam, const double* __restrict__ x,
@@ -510,6 +527,15 @@ void maxpy(long n, const double* V, long ldv, int nvec, const double* h, double 
     if (norm2_out) k_reduce_parts<<<1, TPB, 0, s>>>(np, part, norm2_out);
     MGR_LAUNCH_CHECK();
 }
+
+template <typename T>
+void trsv_level(int cnt, const int* rows, const SpOp<T>& A, const T* b, T* x, bool unit, hipStream_t s) {
+    if (cnt <= 0) return;
+    k_trsv_level<T><<<nblk(cnt), TPB, 0, s>>>(cnt, rows, A.rp, A.ci, A.v, b, x, unit ? 1 : 0);
+    MGR_LAUNCH_CHECK();
+}
+template void trsv_level<double>(int, const int*, const SpOp<double>&, const double*, double*, bool, hipStream_t);
+template void trsv_level<float>(int, const int*, const SpOp<float>&, const float*, float*, bool, hipStream_t);
 
 void grad_values(int b, int nbr, const int* rp, const int* ci, long nnzb, int nrhs, const double* lam,
                  const double* x, double* dv, hipStream_t s) {

@@ -818,6 +818,116 @@ __global__ __launch_bounds__(1024) void k_dense_inverse(int n, double* __restric
     }
 }
 
+// ------------------------------------------------------------------ ILU(0) of A_FF
+// Level of a row in a triangular dependency graph: rows with no dependency are
+// level 0, otherwise 1 + the largest level they depend on.  Computed by
+// monotone relaxation sweeps (levels only grow toward the fixed point, so stale
+// reads of a neighbour's level during a sweep are harmless).  fwd: row i
+// depends on the columns k < i of its row; !fwd: on the columns k > i.
+__global__ void k_level_sweep(int n, const int* __restrict__ rp, const int* __restrict__ ci, int fwd,
+                              int* lev, int* __restrict__ changed) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int m = 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        int k = ci[p];
+        if ((fwd && k < i) || (!fwd && k > i)) m = max(m, ((volatile int*)lev)[k] + 1);
+    }
+    if (m > lev[i]) {
+        lev[i] = m;
+        *changed = 1;
+    }
+}
+
+__global__ void k_level_max(int n, const int* __restrict__ lev, int* __restrict__ out) {
+    __shared__ int sh[TPB];
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    sh[threadIdx.x] = (i < n) ? lev[i] : 0;
+    __syncthreads();
+    for (int off = TPB / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, sh[0]);
+}
+
+__global__ void k_level_count(int n, const int* __restrict__ lev, int* __restrict__ cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[lev[i]], 1);
+}
+
+__global__ void k_level_scatter(int n, const int* __restrict__ lev, int* __restrict__ cursor, int* __restrict__ order) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) order[atomicAdd(&cursor[lev[i]], 1)] = i;
+}
+
+__global__ void k_diag_pos(int n, const int* __restrict__ rp, const int* __restrict__ ci, int* __restrict__ dpos,
+                           int* __restrict__ flag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int d = -1;
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+        if (ci[p] == i) d = p;
+    dpos[i] = d;
+    if (d < 0) set_flag(flag, 3);
+}
+
+// ILU(0) of one level of rows (Saad, Iterative Methods, ILU(0) in IKJ order):
+// for each k < i in row i, in column order: l = a_ik / u_kk; a_ik = l; then
+// a_ij -= l * u_kj for the entries j > k of row k present in row i.  Every
+// row of an earlier level is final, so the arithmetic equals the sequential one.
+__global__ void k_ilu_level(int cnt, const int* __restrict__ rows, const int* __restrict__ rp,
+                            const int* __restrict__ ci, const int* __restrict__ dpos, double* lu,
+                            int* __restrict__ flag) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cnt) return;
+    int i = rows[t];
+    int p0 = rp[i], p1 = rp[i + 1];
+    for (int p = p0; p < p1; ++p) {
+        int k = ci[p];
+        if (k >= i) break;
+        double ukk = lu[dpos[k]];
+        if (ukk == 0.0) { set_flag(flag, 3); continue; }
+        double l = lu[p] / ukk;
+        lu[p] = l;
+        int q = dpos[k] + 1, qe = rp[k + 1], r = p + 1;
+        while (q < qe && r < p1) {
+            int cq = ci[q], cr = ci[r];
+            if (cq == cr) { lu[r] = lu[r] - l * lu[q]; ++q; ++r; }
+            else if (cq < cr) ++q;
+            else ++r;
+        }
+    }
+    double d = lu[dpos[i]];
+    if (d == 0.0 || !isfinite(d)) set_flag(flag, 3);
+}
+
+// split the factors: L = strict lower part (unit diagonal implied), U = diagonal and upper part
+__global__ void k_split_count(int n, const int* __restrict__ rp, const int* __restrict__ ci, int* __restrict__ nl,
+                              int* __restrict__ nu) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int a = 0, b = 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        if (ci[p] < i) ++a;
+        else ++b;
+    }
+    nl[i] = a;
+    nu[i] = b;
+}
+
+__global__ void k_split_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ v,
+                             const int* __restrict__ lrp, int* __restrict__ lci, double* __restrict__ lv,
+                             const int* __restrict__ urp, int* __restrict__ uci, double* __restrict__ uv) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int a = lrp[i], b = urp[i];
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+        if (ci[p] < i) { lci[a] = ci[p]; lv[a] = v[p]; ++a; }
+        else { uci[b] = ci[p]; uv[b] = v[p]; ++b; }
+    }
+}
+
 // ------------------------------------------------------------------ fused-apply operators
 // R = [X (F columns mapped to global) | I at cmap[i]], X scaled by `scale`.
 __global__ void k_rj_count(int nC, const int* __restrict__ xrp, int* __restrict__ len) {
@@ -1180,6 +1290,49 @@ void dense_inverse(int n, double* a, double* inv, int* flag, hipStream_t s) {
     if (n <= 0) return;
     DArr<double> fcol((size_t)n, s);
     k_dense_inverse<<<1, 1024, 0, s>>>(n, a, inv, fcol.p, flag);
+    MGR_LAUNCH_CHECK();
+}
+
+void level_sweep(const DCsr& A, bool fwd, int* lev, int* changed, hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_level_sweep<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, fwd ? 1 : 0, lev, changed);
+    MGR_LAUNCH_CHECK();
+}
+
+void level_max(int n, const int* lev, int* out, hipStream_t s) {
+    if (n <= 0) return;
+    k_level_max<<<nblk(n), TPB, 0, s>>>(n, lev, out);
+    MGR_LAUNCH_CHECK();
+}
+
+void level_bucket(int n, const int* lev, int* cnt, int* cursor, int* order, hipStream_t s, bool scatter) {
+    if (n <= 0) return;
+    if (!scatter) k_level_count<<<nblk(n), TPB, 0, s>>>(n, lev, cnt);
+    else k_level_scatter<<<nblk(n), TPB, 0, s>>>(n, lev, cursor, order);
+    MGR_LAUNCH_CHECK();
+}
+
+void diag_pos(const DCsr& A, int* dpos, int* flag, hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_diag_pos<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, dpos, flag);
+    MGR_LAUNCH_CHECK();
+}
+
+void ilu_level(int cnt, const int* rows, DCsr& LU, const int* dpos, int* flag, hipStream_t s) {
+    if (cnt <= 0) return;
+    k_ilu_level<<<nblk(cnt), TPB, 0, s>>>(cnt, rows, LU.rp.p, LU.ci.p, dpos, LU.v.p, flag);
+    MGR_LAUNCH_CHECK();
+}
+
+void split_count(const DCsr& A, int* nl, int* nu, hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_split_count<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, nl, nu);
+    MGR_LAUNCH_CHECK();
+}
+
+void split_fill(const DCsr& A, DCsr& L, DCsr& U, hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_split_fill<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, L.rp.p, L.ci.p, L.v.p, U.rp.p, U.ci.p, U.v.p);
     MGR_LAUNCH_CHECK();
 }
 

@@ -79,6 +79,17 @@ void l1_dinv(const DCsr& A, double* dinv, int* flag, hipStream_t s);
 void densify(const DCsr& A, double* dense, hipStream_t s);
 void dense_inverse(int n, double* a, double* inv, int* flag, hipStream_t s);
 
+// ILU(0): level analysis (fwd: dependencies on columns < i; else > i), bucketing
+// of rows by level, factorization of one level, split into L (strict lower) and
+// U (diagonal + upper)
+void level_sweep(const DCsr& A, bool fwd, int* lev, int* changed, hipStream_t s);
+void level_max(int n, const int* lev, int* out, hipStream_t s);
+void level_bucket(int n, const int* lev, int* cnt, int* cursor, int* order, hipStream_t s, bool scatter);
+void diag_pos(const DCsr& A, int* dpos, int* flag, hipStream_t s);
+void ilu_level(int cnt, const int* rows, DCsr& LU, const int* dpos, int* flag, hipStream_t s);
+void split_count(const DCsr& A, int* nl, int* nu, hipStream_t s);
+void split_fill(const DCsr& A, DCsr& L, DCsr& U, hipStream_t s);
+
 // MGR apply operators of the fused one-sweep path
 void rj_count(int nC, const DCsr& X, int* len, hipStream_t s);
 void rj_fill(int nC, const DCsr& X, double scale, const int* fmap, const int* cmap, DCsr& R, hipStream_t s);

@@ -469,6 +469,53 @@ static void amg_vcycle(Amg& H, int k, const T* b, T* x, bool tr, hipStream_t s) 
     }
 }
 
+// ====================================================================== triangular schedules
+// Rows of a triangular matrix grouped by dependency level (rows of one level
+// are independent once the earlier levels are solved).
+struct Sched {
+    DArr<int> order;           // rows, level by level
+    std::vector<int> off;      // level offsets into order (host), nlev + 1
+};
+
+static Sched level_schedule(const DCsr& T, bool fwd, Slots& S) {
+    hipStream_t s = S.s;
+    int n = T.nr;
+    Sched sc;
+    DArr<int> lev((size_t)n + 1, s);
+    fill_int(lev.p, 0, n + 1, s);
+    for (int it = 0;; it += 8) {
+        if (it > 8 * (n + 8)) throw Error(MGR_ERR_UNSUPPORTED, "level analysis did not converge");
+        long long* ch = S.take(1);
+        fill_ll(ch, 0, 1, s);
+        for (int q = 0; q < 8; ++q) level_sweep(T, fwd, lev.p, reinterpret_cast<int*>(ch), s);
+        S.sync("level analysis");
+        if (S.val(ch) == 0) break;
+    }
+    long long* mx = S.take(1);
+    fill_ll(mx, 0, 1, s);
+    level_max(n, lev.p, reinterpret_cast<int*>(mx), s);
+    S.sync("level analysis");
+    int nlev = (int)(S.val(mx) & 0xffffffffLL) + 1;
+    DArr<int> cnt((size_t)nlev + 1, s), off((size_t)nlev + 1, s), cursor((size_t)nlev + 1, s);
+    fill_int(cnt.p, 0, nlev + 1, s);
+    level_bucket(n, lev.p, cnt.p, nullptr, nullptr, s, false);
+    scan_exclusive_async(cnt.p, off.p, nlev, s);
+    MGR_HIP(hipMemcpyAsync(cursor.p, off.p, sizeof(int) * ((size_t)nlev + 1), hipMemcpyDeviceToDevice, s));
+    sc.order.alloc((size_t)n + 1, s);
+    level_bucket(n, lev.p, nullptr, cursor.p, sc.order.p, s, true);
+    sc.off.resize((size_t)nlev + 1);
+    MGR_HIP(hipMemcpyAsync(sc.off.data(), off.p, sizeof(int) * ((size_t)nlev + 1), hipMemcpyDeviceToHost, s));
+    MGR_HIP(hipStreamSynchronize(s));
+    return sc;
+}
+
+template <typename T>
+static void trsv(const Sched& sc, const DCsr& A, const T* b, T* x, bool unit, hipStream_t s) {
+    SpOp<T> op = view<T>(A);
+    for (size_t k = 0; k + 1 < sc.off.size(); ++k)
+        trsv_level<T>(sc.off[k + 1] - sc.off[k], sc.order.p + sc.off[k], op, b, x, unit, s);
+}
+
 // ====================================================================== MGR levels
 struct MgrLevel {
     int n = 0, nF = 0, nC = 0;
@@ -482,6 +529,10 @@ struct MgrLevel {
     DCsr AFFt, ACFt, PFt, RFt, Mt;           // general transposed apply
     bool have_float = false, have_trans = false;
     std::unique_ptr<Amg> famg;
+    // ILU(0) F-relaxation: L (unit, strict lower), U (diagonal + upper), their
+    // transposes, and the level schedules of the four triangular solves
+    DCsr iluL, iluU, iluLt, iluUt;
+    Sched schL, schU, schLt, schUt;
     // level vectors: coarse input / output (the next level's v and z)
     DArr<double> rcd, ecd, vFd, vCd, zFd, rFd, tFd;
     DArr<float> rcf, ecf, vFf, vCf, zFf, rFf, tFf;
@@ -566,8 +617,25 @@ static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr& A, const int* field
     frelax_fill((int)nb, bstart.p, l.AFF, l.M, S.flag(), s);
     // nothing may consume M before its pivots are known to be valid
     S.sync("F-relaxation operator");
-    if (o.frelax == MGR_FRELAX_ILU0)
-        throw Error(MGR_ERR_UNSUPPORTED, "ILU(0) F-relaxation is not available in the GPU library");
+    if (o.frelax == MGR_FRELAX_ILU0) {
+        // ILU(0) on the pattern of A_FF in the natural order, one level of rows at a time
+        DCsr LU = csr_copy(l.AFF, s);
+        DArr<int> dpos((size_t)l.nF + 1, s);
+        diag_pos(LU, dpos.p, S.flag(), s);
+        S.sync("ILU(0) diagonal");
+        l.schL = level_schedule(LU, true, S);
+        for (size_t k = 0; k + 1 < l.schL.off.size(); ++k)
+            ilu_level(l.schL.off[k + 1] - l.schL.off[k], l.schL.order.p + l.schL.off[k], LU, dpos.p, S.flag(), s);
+        DArr<int> nl((size_t)l.nF + 1, s), nu((size_t)l.nF + 1, s);
+        split_count(LU, nl.p, nu.p, s);
+        Pend pL = csr_begin(l.iluL, l.nF, l.nF, nl.p, S);
+        Pend pU = csr_begin(l.iluU, l.nF, l.nF, nu.p, S);
+        S.sync("ILU(0) factorization");
+        csr_finish(pL, S);
+        csr_finish(pU, S);
+        split_fill(LU, l.iluL, l.iluU, s);
+        l.schU = level_schedule(l.iluU, false, S);
+    }
     if (o.frelax == MGR_FRELAX_AMG) {
         l.famg.reset(new Amg());
         mgr_amg_opts fo = c.o.amg;
@@ -661,9 +729,16 @@ static void mgr_level_make_trans(Ctx& c, MgrLevel& l) {
         l.PFt = csr_transpose(l.PF, S);
         l.Mt = csr_transpose(l.M, S);
         if (l.o.restrict_type == MGR_RESTRICT_JACOBI) l.RFt = csr_transpose(l.RF, S);
+        if (l.o.frelax == MGR_FRELAX_ILU0) {
+            l.iluLt = csr_transpose(l.iluL, S);
+            l.iluUt = csr_transpose(l.iluU, S);
+            l.schUt = level_schedule(l.iluUt, true, S);
+            l.schLt = level_schedule(l.iluLt, false, S);
+        }
         if (l.have_float) {
             make_float(l.AFFt, s); make_float(l.ACFt, s); make_float(l.PFt, s); make_float(l.Mt, s);
             if (l.RFt.nr) make_float(l.RFt, s);
+            if (l.iluLt.nr) { make_float(l.iluLt, s); make_float(l.iluUt, s); }
         }
     }
     if (l.famg) amg_make_trans(*l.famg, S);
@@ -679,6 +754,8 @@ static void mgr_level_make_float(Ctx& c, MgrLevel& l) {
     } else {
         make_float(l.AFF, s); make_float(l.ACF, s); make_float(l.PF, s); make_float(l.M, s);
         if (l.RF.nr) make_float(l.RF, s);
+        if (l.iluL.nr) { make_float(l.iluL, s); make_float(l.iluU, s); }
+        if (l.have_trans && l.iluLt.nr) { make_float(l.iluLt, s); make_float(l.iluUt, s); }
         if (l.have_trans) {
             make_float(l.AFFt, s); make_float(l.ACFt, s); make_float(l.PFt, s); make_float(l.Mt, s);
             if (l.RFt.nr) make_float(l.RFt, s);
@@ -715,6 +792,17 @@ template <> struct LV<float> {
 // tF = M_FF^{-1} rF (trans: M_FF^{-T}) for Jacobi / block-Jacobi / AMG F-relaxation
 template <typename T>
 static void frelax_apply(MgrLevel& l, const T* rF, T* tF, bool tr, hipStream_t s) {
+    if (l.o.frelax == MGR_FRELAX_ILU0) {
+        // (LU)^{-1} r: L y = r (unit lower), U z = y; (LU)^{-T} r: U^T y = r, L^T z = y
+        if (!tr) {
+            trsv<T>(l.schL, l.iluL, rF, tF, true, s);
+            trsv<T>(l.schU, l.iluU, tF, tF, false, s);
+        } else {
+            trsv<T>(l.schUt, l.iluUt, rF, tF, false, s);
+            trsv<T>(l.schLt, l.iluLt, tF, tF, true, s);
+        }
+        return;
+    }
     if (l.o.frelax == MGR_FRELAX_AMG) {
         amg_vcycle<T>(*l.famg, 0, rF, tF, tr, s);
         return;

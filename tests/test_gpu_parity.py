@@ -134,6 +134,8 @@ VARIANTS = {
     "jacobi_restriction": dict(restrict="jacobi"),
     "two_sweeps_omega": dict(sweeps=2, omega=0.8),
     "amg_frelax": dict(frelax="amg"),
+    "ilu0_frelax": dict(frelax="ilu0"),
+    "ilu0_two_sweeps_jacobi_r": dict(frelax="ilu0", sweeps=2, restrict="jacobi"),
 }
 
 
@@ -226,3 +228,23 @@ def test_multi_rhs_solve_and_gradient():
     loss.backward()
     assert rel(vals.grad.cpu().numpy(), go) <= 1e-8
     assert rel(Bt.grad.cpu().numpy(), Lam) <= 1e-8
+
+
+def test_ilu0_on_compositional_components():
+    # ILU(0) F-relaxation of the three component densities (the paper recommends
+    # incomplete factorizations for such transport blocks)
+    s = W.compositional_wells(12, 10, 8, seed=9)
+    lv = [dict(s["levels"][0], frelax="ilu0"), s["levels"][1]]
+    say("[ilu0] compositional 12x10x8")
+    om = oracle_mgr(s, levels=lv)
+    gs = gpu_solver(s, levels=lv)
+    v = np.random.default_rng(8).standard_normal(s["n"])
+    assert rel(gs.apply(v).cpu().numpy(), om.apply(v)) <= 1e-10
+    assert rel(gs.apply(v, transpose=True).cpu().numpy(), om.apply(v, trans=True)) <= 1e-10
+    X, [ig] = gs.solve(s["rhs"])
+    xo, io = om.solve(s["rhs"])
+    say(f"[ilu0] iterations gpu {ig.iterations} oracle {io.iterations}")
+    assert abs(ig.iterations - io.iterations) <= 1 and rel(X.cpu().numpy(), xo) <= 1e-8
+    gs.set_opts(precision=32)
+    X32, [i32] = gs.solve(s["rhs"])
+    assert i32.status == 0 and rel(X32.cpu().numpy(), xo) <= 1e-7
