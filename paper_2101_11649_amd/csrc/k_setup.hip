@@ -928,6 +928,401 @@ __global__ void k_split_fill(int n, const int* __restrict__ rp, const int* __res
     }
 }
 
+// ------------------------------------------------------------------ lane-group-per-row variants
+// The kernels below give each row a group of G lanes (G a power of two <= 64,
+// chosen from the longest row) so that the row's entries are read with
+// coalesced loads.  Compaction keeps the entries' order (ballot + prefix
+// popcount); every reduction that feeds a bit-exact result is exact (counts,
+// maxima) or kept strictly sequential (interpolation sums).
+template <int G>
+struct Grp {
+    int lane, gl, gbase;
+    unsigned long long gmask;
+    __device__ Grp() {
+        lane = threadIdx.x & (WAVE - 1);
+        gl = lane & (G - 1);
+        gbase = lane - gl;
+        gmask = (G >= 64) ? ~0ULL : ((1ULL << G) - 1ULL);
+    }
+    __device__ unsigned long long bits(bool pred) const { return (__ballot(pred) >> gbase) & gmask; }
+    __device__ int below(unsigned long long b) const { return __popcll(b & ((1ULL << gl) - 1ULL)); }
+    __device__ int sum(int v) const {
+        for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+        return v;
+    }
+    __device__ double sumd(double v) const {
+        for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+        return v;
+    }
+};
+
+__device__ inline int wave_max_int(int v) {
+    for (int off = WAVE / 2; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, WAVE));
+    return v;
+}
+
+template <int G>
+__global__ __launch_bounds__(TPB) void k_extract_count_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                         const int* __restrict__ isF, const int* __restrict__ lmap,
+                                                         int* cFF, int* cFC, int* cCF, int* cCC) {
+    Grp<G> g;
+    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    int f = 0, c = 0;
+    if (i < n)
+        for (int p = rp[i] + g.gl; p < rp[i + 1]; p += G) {
+            if (isF[ci[p]]) ++f;
+            else ++c;
+        }
+    f = g.sum(f);
+    c = g.sum(c);
+    if (i < n && g.gl == 0) {
+        int l = lmap[i];
+        if (isF[i]) { cFF[l] = f; cFC[l] = c; }
+        else { cCF[l] = f; cCC[l] = c; }
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(TPB) void k_extract_fill_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                        const double* __restrict__ v, const int* __restrict__ isF,
+                                                        const int* __restrict__ lmap, const int* __restrict__ rpFF,
+                                                        int* ciFF, double* vFF, const int* __restrict__ rpFC,
+                                                        int* ciFC, double* vFC, const int* __restrict__ rpCF,
+                                                        int* ciCF, double* vCF, const int* __restrict__ rpCC,
+                                                        int* ciCC, double* vCC) {
+    Grp<G> g;
+    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    bool valid = i < n;
+    int p0 = valid ? rp[i] : 0, len = valid ? rp[i + 1] - p0 : 0;
+    int maxlen = wave_max_int(len);
+    int oF = 0, oC = 0;
+    int *cF = nullptr, *cC = nullptr;
+    double *vF = nullptr, *vC = nullptr;
+    if (valid) {
+        int l = lmap[i];
+        if (isF[i]) { oF = rpFF[l]; oC = rpFC[l]; cF = ciFF; vF = vFF; cC = ciFC; vC = vFC; }
+        else { oF = rpCF[l]; oC = rpCC[l]; cF = ciCF; vF = vCF; cC = ciCC; vC = vCC; }
+    }
+    for (int base = 0; base < maxlen; base += G) {
+        int q = base + g.gl;
+        bool act = q < len;
+        int j = act ? ci[p0 + q] : 0;
+        bool f = act && isF[j];
+        bool c = act && !isF[j];
+        unsigned long long bf = g.bits(f), bc = g.bits(c);
+        if (f) { int o = oF + g.below(bf); cF[o] = lmap[j]; vF[o] = v[p0 + q]; }
+        if (c) { int o = oC + g.below(bc); cC[o] = lmap[j]; vC[o] = v[p0 + q]; }
+        oF += __popcll(bf);
+        oC += __popcll(bc);
+    }
+}
+
+// scalar row i = I*b + r of a block row: G lanes take the row's blocks
+template <int G>
+__global__ __launch_bounds__(TPB) void k_bsr_expand_g(int b, int nbr, const int* __restrict__ brp,
+                                                      const int* __restrict__ bci, const double* __restrict__ bv,
+                                                      int* __restrict__ rp, int* __restrict__ ci, double* __restrict__ v) {
+    Grp<G> g;
+    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    int n = nbr * b;
+    if (i >= n) return;
+    int I = i / b, r = i - I * b;
+    int p0 = brp[I], p1 = brp[I + 1];
+    long o = (long)p0 * b * b + (long)r * (p1 - p0) * b;
+    if (g.gl == 0) {
+        rp[i] = (int)o;
+        if (i == n - 1) rp[n] = (int)((long)brp[nbr] * b * b);
+    }
+    for (int p = p0 + g.gl; p < p1; p += G) {
+        int J = bci[p];
+        const double* blk = bv + (long)p * b * b + r * b;
+        long q = o + (long)(p - p0) * b;
+        for (int c = 0; c < b; ++c) { ci[q + c] = J * b + c; v[q + c] = blk[c]; }
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(TPB) void k_strength_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                    const double* __restrict__ v, double theta,
+                                                    const int* __restrict__ label, unsigned char* __restrict__ strong,
+                                                    int* __restrict__ scnt) {
+    Grp<G> g;
+    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    bool valid = i < n;
+    int li = (valid && label) ? label[i] : 0;
+    double mx = 0.0;
+    int have = 0;
+    if (valid)
+        for (int p = rp[i] + g.gl; p < rp[i + 1]; p += G) {
+            int j = ci[p];
+            if (j == i || (label && label[j] != li)) continue;
+            double t = -v[p];
+            if (!have || t > mx) { mx = t; have = 1; }
+        }
+    for (int off = G / 2; off > 0; off >>= 1) {
+        double om = __shfl_xor(mx, off, WAVE);
+        int oh = __shfl_xor(have, off, WAVE);
+        if (oh && (!have || om > mx)) mx = om;
+        have |= oh;
+    }
+    int c = 0;
+    if (valid) {
+        double thr = theta * mx;
+        for (int p = rp[i] + g.gl; p < rp[i + 1]; p += G) {
+            int j = ci[p];
+            unsigned char sflag = 0;
+            if (have && mx > 0.0 && j != i && !(label && label[j] != li) && -v[p] >= thr) sflag = 1;
+            strong[p] = sflag;
+            c += sflag;
+        }
+    }
+    c = g.sum(c);
+    if (valid && g.gl == 0) scnt[i] = c;
+}
+
+template <int G>
+__global__ __launch_bounds__(TPB) void k_lambda_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                  const unsigned char* __restrict__ strong, int* __restrict__ lam) {
+    Grp<G> g;
+    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    if (i >= n) return;
+    for (int p = rp[i] + g.gl; p < rp[i + 1]; p += G)
+        if (strong[p]) atomicAdd(&lam[ci[p]], 1);
+}
+
+template <int G>
+__global__ __launch_bounds__(TPB) void k_sfill_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                 const unsigned char* __restrict__ strong, const int* __restrict__ srp,
+                                                 int* __restrict__ sci) {
+    Grp<G> g;
+    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    bool valid = i < n;
+    int p0 = valid ? rp[i] : 0, len = valid ? rp[i + 1] - p0 : 0;
+    int maxlen = wave_max_int(len);
+    int o = valid ? srp[i] : 0;
+    for (int base = 0; base < maxlen; base += G) {
+        int q = base + g.gl;
+        bool st = q < len && strong[p0 + q];
+        unsigned long long bs = g.bits(st);
+        if (st) sci[o + g.below(bs)] = ci[p0 + q];
+        o += __popcll(bs);
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(TPB) void k_interp_count_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                        const unsigned char* __restrict__ strong,
+                                                        const int* __restrict__ cf, int* __restrict__ cnt) {
+    Grp<G> g;
+    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    bool valid = i < n;
+    int c = 0;
+    if (valid && cf[i] != 1)
+        for (int p = rp[i] + g.gl; p < rp[i + 1]; p += G)
+            if (strong[p] && cf[ci[p]] == 1) ++c;
+    c = g.sum(c);
+    if (valid && g.gl == 0) cnt[i] = (cf[i] == 1) ? 1 : c;
+}
+
+// Direct interpolation: the row sums are formed strictly left to right (each
+// chunk's values are broadcast lane by lane), exactly as the thread-per-row
+// version and the oracle do.
+template <int G>
+__global__ __launch_bounds__(TPB) void k_interp_fill_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                       const double* __restrict__ v,
+                                                       const unsigned char* __restrict__ strong,
+                                                       const int* __restrict__ cf, const int* __restrict__ cidx,
+                                                       const int* __restrict__ label, const int* __restrict__ prp,
+                                                       int* __restrict__ pci, double* __restrict__ pv,
+                                                       int* __restrict__ flag) {
+    Grp<G> g;
+    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    bool valid = i < n;
+    bool frow = valid && cf[i] != 1 && prp[i + 1] > prp[i];
+    if (valid && cf[i] == 1 && g.gl == 0) { pci[prp[i]] = cidx[i]; pv[prp[i]] = 1.0; }
+    int p0 = valid ? rp[i] : 0, len = frow ? rp[i + 1] - p0 : 0;
+    int maxlen = wave_max_int(len);
+    int li = (frow && label) ? label[i] : 0;
+    double aii = 0.0, neg = 0.0, pos = 0.0, cs = 0.0;
+    for (int base = 0; base < maxlen; base += G) {
+        int q = base + g.gl;
+        bool act = q < len;
+        int k = act ? ci[p0 + q] : -1;
+        double a = act ? v[p0 + q] : 0.0;
+        int kind = 0;  // 1 diag, 2 same-label off-diagonal, 0 other / inactive
+        bool sc = false;
+        if (act) {
+            if (k == i) kind = 1;
+            else if (!(label && label[k] != li)) {
+                kind = 2;
+                sc = strong[p0 + q] && cf[k] == 1;
+            }
+        }
+        for (int t = 0; t < G; ++t) {
+            double at = __shfl(a, g.gbase + t, WAVE);
+            int kt = __shfl(kind, g.gbase + t, WAVE);
+            int st = __shfl((int)sc, g.gbase + t, WAVE);
+            if (kt == 1) aii = at;
+            else if (kt == 2) {
+                if (at < 0.0) neg = neg + at;
+                else if (at > 0.0) pos = pos + at;
+                if (st) cs = cs + at;
+            }
+        }
+    }
+    double atil = aii + pos;
+    if (frow && g.gl == 0 && !(atil > 0.0)) set_flag(flag, 6);
+    double alpha = neg / cs;
+    int o = frow ? prp[i] : 0;
+    for (int base = 0; base < maxlen; base += G) {
+        int q = base + g.gl;
+        bool act = q < len;
+        int k = act ? ci[p0 + q] : 0;
+        bool w = act && strong[p0 + q] && cf[k] == 1;
+        unsigned long long bw = g.bits(w);
+        if (w) {
+            int oo = o + g.below(bw);
+            pci[oo] = cidx[k];
+            pv[oo] = -(alpha * v[p0 + q]) / atil;
+        }
+        o += __popcll(bw);
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(TPB) void k_l1_dinv_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                   const double* __restrict__ v, double* __restrict__ dinv,
+                                                   int* __restrict__ flag) {
+    Grp<G> g;
+    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    bool valid = i < n;
+    double s = 0.0, aii = 0.0;
+    if (valid)
+        for (int p = rp[i] + g.gl; p < rp[i + 1]; p += G) {
+            if (ci[p] == i) aii = v[p];
+            else s += fabs(v[p]);
+        }
+    s = g.sumd(s);
+    aii = g.sumd(aii);
+    if (valid && g.gl == 0) {
+        double d = aii + s;
+        if (!(d > 0.0)) { set_flag(flag, 6); d = 1.0; }
+        dinv[i] = 1.0 / d;
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(TPB) void k_transpose_scatter_g(int nr, const int* __restrict__ rp,
+                                                             const int* __restrict__ ci, const double* __restrict__ v,
+                                                             int* __restrict__ cursor, int* __restrict__ tci,
+                                                             double* __restrict__ tv) {
+    Grp<G> g;
+    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    if (i >= nr) return;
+    for (int p = rp[i] + g.gl; p < rp[i + 1]; p += G) {
+        int q = atomicAdd(&cursor[ci[p]], 1);
+        tci[q] = i;
+        if (tv) tv[q] = v[p];
+    }
+}
+
+// Coarsest-level inverse for n <= 128, kept in registers: 1024 threads, thread
+// t owns row t/8 and the 32 columns (t%8)*32.. of the augmented matrix [A | I];
+// Gauss-Jordan with partial pivoting (ties to the lower row), same steps as the
+// global-memory version.
+__global__ __launch_bounds__(1024) void k_dense_inverse_small(int n, const double* __restrict__ a,
+                                                              double* __restrict__ inv, int* __restrict__ flag) {
+    __shared__ double prow[256];
+    __shared__ double fcol[128];
+    __shared__ double pv[128];
+    __shared__ int pi[128];
+    __shared__ double rowc[256], rowp[256];
+    __shared__ int piv_sh;
+    const int t = threadIdx.x;
+    const int r = t >> 3, c0 = (t & 7) * 32;
+    double m[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        int c = c0 + k;
+        double x = 0.0;
+        if (r < n) {
+            if (c < n) x = a[(long)r * n + c];
+            else if (c < 2 * n && c - n == r) x = 1.0;
+        }
+        m[k] = x;
+    }
+    for (int c = 0; c < n; ++c) {
+        const int owner = c >> 5, ck = c & 31;
+        double mine = 0.0;
+#pragma unroll
+        for (int k = 0; k < 32; ++k)
+            if (k == ck) mine = m[k];
+        if ((t & 7) == owner && r < n) { fcol[r] = mine; pv[r] = (r >= c) ? fabs(mine) : -1.0; pi[r] = r; }
+        __syncthreads();
+        if (t < 64) {
+            double bv = -1.0;
+            int bi = n;
+            for (int q = t; q < n; q += 64) {
+                double x = pv[q];
+                if (x > bv || (x == bv && q < bi)) { bv = x; bi = q; }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                double ov = __shfl_xor(bv, off, 64);
+                int oi = __shfl_xor(bi, off, 64);
+                if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+            }
+            if (t == 0) {
+                piv_sh = (bv > 0.0 && isfinite(bv)) ? bi : -1;
+                if (piv_sh < 0) set_flag(flag, 3);
+            }
+        }
+        __syncthreads();
+        const int p = piv_sh;
+        if (p < 0) return;
+        // swap rows c and p (through LDS), then scale the pivot row
+        if (r == c || r == p) {
+#pragma unroll
+            for (int k = 0; k < 32; ++k) (r == c ? rowc : rowp)[c0 + k] = m[k];
+        }
+        __syncthreads();
+        if (p != c) {
+            if (r == c) {
+#pragma unroll
+                for (int k = 0; k < 32; ++k) m[k] = rowp[c0 + k];
+            } else if (r == p) {
+#pragma unroll
+                for (int k = 0; k < 32; ++k) m[k] = rowc[c0 + k];
+            }
+        }
+        double piv = (p != c) ? rowp[c] : rowc[c];
+        double ip = 1.0 / piv;
+        if (r == c) {
+#pragma unroll
+            for (int k = 0; k < 32; ++k) { m[k] = m[k] * ip; prow[c0 + k] = m[k]; }
+        }
+        // the multipliers: column c of every row after the swap
+        if (r < n && (t & 7) == owner) {
+            double f = 0.0;
+#pragma unroll
+            for (int k = 0; k < 32; ++k)
+                if (k == ck) f = m[k];
+            fcol[r] = f;
+        }
+        __syncthreads();
+        if (r < n && r != c) {
+            double f = fcol[r];
+#pragma unroll
+            for (int k = 0; k < 32; ++k) m[k] = m[k] - f * prow[c0 + k];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < 32; ++k) {
+        int c = c0 + k;
+        if (r < n && c >= n && c < 2 * n) inv[(long)r * n + (c - n)] = m[k];
+    }
+}
+
 // ------------------------------------------------------------------ fused-apply operators
 // R = [X (F columns mapped to global) | I at cmap[i]], X scaled by `scale`.
 __global__ void k_rj_count(int nC, const int* __restrict__ xrp, int* __restrict__ len) {
@@ -982,6 +1377,24 @@ __global__ void k_pj_fill(int n, int nC, const int* __restrict__ isF, const int*
 }  // namespace
 
 // ====================================================================== launchers
+static int group_for(int max_row) {
+    if (max_row < 0) return 64;
+    int G = 4;
+    while (G < max_row && G < 64) G <<= 1;
+    return G;
+}
+
+#define MGR_DISPATCH_G4(G, ...)                                  \
+    switch (G) {                                                 \
+        case 4: { constexpr int GG = 4; __VA_ARGS__; } break;    \
+        case 8: { constexpr int GG = 8; __VA_ARGS__; } break;    \
+        case 16: { constexpr int GG = 16; __VA_ARGS__; } break;  \
+        case 32: { constexpr int GG = 32; __VA_ARGS__; } break;  \
+        default: { constexpr int GG = 64; __VA_ARGS__; } break;  \
+    }
+
+static int grid_for(long rows, int G) { return (int)((rows * G + TPB - 1) / TPB); }
+
 void scan_async(const int* in, int* out, int n, long long* slot, hipStream_t s) {
     int nb = ceil_div(n > 0 ? n : 1, SCAN_B);
     DArr<long long> tmp((size_t)2 * nb + 2, s);
@@ -1049,11 +1462,12 @@ void iota_div(int n, int b, int* out, hipStream_t s) {
     MGR_LAUNCH_CHECK();
 }
 
-void bsr_expand(int b, int nbr, const int* brp, const int* bci, const double* bv, int* rp, int* ci, double* v,
-                hipStream_t s) {
+void bsr_expand(int b, int nbr, long nnzb, const int* brp, const int* bci, const double* bv, int* rp, int* ci,
+                double* v, hipStream_t s) {
     int n = nbr * b;
     if (n <= 0) return;
-    k_bsr_expand<<<nblk(n), TPB, 0, s>>>(b, nbr, brp, bci, bv, rp, ci, v);
+    int G = group_for((int)((nnzb + nbr - 1) / nbr));
+    MGR_DISPATCH_G4(G, (k_bsr_expand_g<GG><<<grid_for(n, GG), TPB, 0, s>>>(b, nbr, brp, bci, bv, rp, ci, v)));
     MGR_LAUNCH_CHECK();
 }
 
@@ -1086,16 +1500,19 @@ void cf_maps(int n, const int* isF, const int* fpos, int* lmap, int* fmap, int* 
 void extract_count(const DCsr& A, const int* isF, const int* lmap, int* cFF, int* cFC, int* cCF, int* cCC,
                    hipStream_t s) {
     if (A.nr <= 0) return;
-    k_extract_count<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, isF, lmap, cFF, cFC, cCF, cCC);
+    int G = group_for(A.max_row);
+    MGR_DISPATCH_G4(G, (k_extract_count_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, isF, lmap, cFF,
+                                                                                   cFC, cCF, cCC)));
     MGR_LAUNCH_CHECK();
 }
 
 void extract_fill(const DCsr& A, const int* isF, const int* lmap, DCsr& FF, DCsr& FC, DCsr& CF, DCsr& CC,
                   hipStream_t s) {
     if (A.nr <= 0) return;
-    k_extract_fill<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, isF, lmap, FF.rp.p, FF.ci.p, FF.v.p,
-                                              FC.rp.p, FC.ci.p, FC.v.p, CF.rp.p, CF.ci.p, CF.v.p, CC.rp.p, CC.ci.p,
-                                              CC.v.p);
+    int G = group_for(A.max_row);
+    MGR_DISPATCH_G4(G, (k_extract_fill_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(
+                           A.nr, A.rp.p, A.ci.p, A.v.p, isF, lmap, FF.rp.p, FF.ci.p, FF.v.p, FC.rp.p, FC.ci.p, FC.v.p,
+                           CF.rp.p, CF.ci.p, CF.v.p, CC.rp.p, CC.ci.p, CC.v.p)));
     MGR_LAUNCH_CHECK();
 }
 
@@ -1196,21 +1613,27 @@ void transpose_count(const DCsr& A, int* cnt, hipStream_t s) {
 }
 
 void transpose_fill(const DCsr& A, DCsr& T, int* cursor, hipStream_t s) {
-    if (A.nr > 0)
-        k_transpose_scatter<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, cursor, T.ci.p, T.v.p);
+    if (A.nr > 0) {
+        int G = group_for(A.max_row);
+        MGR_DISPATCH_G4(G, (k_transpose_scatter_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(
+                               A.nr, A.rp.p, A.ci.p, A.v.p, cursor, T.ci.p, T.v.p)));
+    }
     if (T.nr > 0) k_transpose_sort<<<nblk(T.nr), TPB, 0, s>>>(T.nr, T.rp.p, T.ci.p, T.v.p);
     MGR_LAUNCH_CHECK();
 }
 
-void amg_strength(const DCsr& A, double theta, const int* label, unsigned char* strong, hipStream_t s) {
+void amg_strength(const DCsr& A, double theta, const int* label, unsigned char* strong, int* scnt, hipStream_t s) {
     if (A.nr <= 0) return;
-    k_strength<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, theta, label, strong);
+    int G = group_for(A.max_row);
+    MGR_DISPATCH_G4(G, (k_strength_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, theta, label,
+                                                                              strong, scnt)));
     MGR_LAUNCH_CHECK();
 }
 
 void amg_lambda(const DCsr& A, const unsigned char* strong, int* lam, hipStream_t s) {
     if (A.nr <= 0) return;
-    k_lambda<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, strong, lam);
+    int G = group_for(A.max_row);
+    MGR_DISPATCH_G4(G, (k_lambda_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, strong, lam)));
     MGR_LAUNCH_CHECK();
 }
 
@@ -1222,7 +1645,8 @@ void strength_compact_count(const DCsr& A, const unsigned char* strong, int* cnt
 
 void strength_compact_fill(const DCsr& A, const unsigned char* strong, const int* srp, int* sci, hipStream_t s) {
     if (A.nr <= 0) return;
-    k_sfill<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, strong, srp, sci);
+    int G = group_for(A.max_row);
+    MGR_DISPATCH_G4(G, (k_sfill_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, strong, srp, sci)));
     MGR_LAUNCH_CHECK();
 }
 
@@ -1262,21 +1686,24 @@ void cf_is_c(int n, const int* cf, int* isC, hipStream_t s) {
 
 void interp_count(const DCsr& A, const unsigned char* strong, const int* cf, int* cnt, hipStream_t s) {
     if (A.nr <= 0) return;
-    k_interp_count<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, strong, cf, cnt);
+    int G = group_for(A.max_row);
+    MGR_DISPATCH_G4(G, (k_interp_count_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, strong, cf, cnt)));
     MGR_LAUNCH_CHECK();
 }
 
 void interp_fill(const DCsr& A, const unsigned char* strong, const int* cf, const int* cidx, const int* label,
                  DCsr& P, int* flag, hipStream_t s) {
     if (A.nr <= 0) return;
-    k_interp_fill<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, strong, cf, cidx, label, P.rp.p, P.ci.p,
-                                             P.v.p, flag);
+    int G = group_for(A.max_row);
+    MGR_DISPATCH_G4(G, (k_interp_fill_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(
+                           A.nr, A.rp.p, A.ci.p, A.v.p, strong, cf, cidx, label, P.rp.p, P.ci.p, P.v.p, flag)));
     MGR_LAUNCH_CHECK();
 }
 
 void l1_dinv(const DCsr& A, double* dinv, int* flag, hipStream_t s) {
     if (A.nr <= 0) return;
-    k_l1_dinv<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, dinv, flag);
+    int G = group_for(A.max_row);
+    MGR_DISPATCH_G4(G, (k_l1_dinv_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, dinv, flag)));
     MGR_LAUNCH_CHECK();
 }
 
@@ -1288,6 +1715,11 @@ void densify(const DCsr& A, double* dense, hipStream_t s) {
 
 void dense_inverse(int n, double* a, double* inv, int* flag, hipStream_t s) {
     if (n <= 0) return;
+    if (n <= 128) {
+        k_dense_inverse_small<<<1, 1024, 0, s>>>(n, a, inv, flag);
+        MGR_LAUNCH_CHECK();
+        return;
+    }
     DArr<double> fcol((size_t)n, s);
     k_dense_inverse<<<1, 1024, 0, s>>>(n, a, inv, fcol.p, flag);
     MGR_LAUNCH_CHECK();

@@ -24,8 +24,8 @@ int read_int(const int* dptr, hipStream_t s);
 void flag_clear(int* flag, hipStream_t s);
 int flag_read(const int* flag, hipStream_t s);
 
-void bsr_expand(int b, int nbr, const int* brp, const int* bci, const double* bv, int* rp, int* ci, double* v,
-                hipStream_t s);
+void bsr_expand(int b, int nbr, long nnzb, const int* brp, const int* bci, const double* bv, int* rp, int* ci,
+                double* v, hipStream_t s);
 void bsr_transpose_blocks(int b, int nbr, const int* rp, const int* ci, const double* v, int* trp, int* tci,
                           double* tv, hipStream_t s);
 
@@ -60,7 +60,8 @@ void transpose_count(const DCsr& A, int* cnt, hipStream_t s);
 void transpose_fill(const DCsr& A, DCsr& T, int* cursor, hipStream_t s);
 
 // AMG setup
-void amg_strength(const DCsr& A, double theta, const int* label, unsigned char* strong, hipStream_t s);
+// strength flags per entry and the number of strong entries per row (scnt)
+void amg_strength(const DCsr& A, double theta, const int* label, unsigned char* strong, int* scnt, hipStream_t s);
 void amg_lambda(const DCsr& A, const unsigned char* strong, int* lam, hipStream_t s);
 void strength_compact_count(const DCsr& A, const unsigned char* strong, int* cnt, hipStream_t s);
 void strength_compact_fill(const DCsr& A, const unsigned char* strong, const int* srp, int* sci, hipStream_t s);

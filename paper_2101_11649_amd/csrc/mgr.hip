@@ -258,14 +258,13 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
         if (n <= o.max_coarse || k + 1 >= o.max_levels) break;
         size_t nz = (size_t)(A.nnz > 0 ? A.nnz : 1);
         DArr<unsigned char> strong(nz, s);
-        amg_strength(A, o.theta, L.label.p, strong.p, s);
+        DArr<int> scnt((size_t)n + 1, s), srp((size_t)n + 1, s), trp((size_t)n + 1, s), cursor((size_t)n + 1, s);
+        amg_strength(A, o.theta, L.label.p, strong.p, scnt.p, s);
         DArr<int> lam((size_t)n + 1, s);
         fill_int(lam.p, 0, n + 1, s);
         amg_lambda(A, strong.p, lam.p, s);
         // strength graph S (row i lists S_i) and its transpose; both fit in nnz(A)
-        DArr<int> scnt((size_t)n + 1, s), srp((size_t)n + 1, s), trp((size_t)n + 1, s), cursor((size_t)n + 1, s);
         DArr<int> sci(nz, s), tci(nz, s);
-        strength_compact_count(A, strong.p, scnt.p, s);
         scan_exclusive_async(scnt.p, srp.p, n, s);
         strength_compact_fill(A, strong.p, srp.p, sci.p, s);
         scan_exclusive_async(lam.p, trp.p, n, s);
@@ -1107,7 +1106,7 @@ static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nle
         MGR_HIP(hipMemcpyAsync(c.A0.ci.p, c.Aci.p, sizeof(int) * c.nnzb, hipMemcpyDeviceToDevice, s));
         MGR_HIP(hipMemcpyAsync(c.A0.v.p, c.Av.p, sizeof(double) * c.nnzb, hipMemcpyDeviceToDevice, s));
     } else {
-        bsr_expand(c.b, c.nbr, c.Arp.p, c.Aci.p, c.Av.p, c.A0.rp.p, c.A0.ci.p, c.A0.v.p, s);
+        bsr_expand(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, c.Av.p, c.A0.rp.p, c.A0.ci.p, c.A0.v.p, s);
     }
     make_rowblocks(c.A0, s);
     c.A0.max_row = max_row_len(c.A0, s);
