@@ -79,6 +79,8 @@ void copy(long n, const S* src, D* dst, hipStream_t s);
 template <typename T>
 void set(long n, T* dst, T v, hipStream_t s);
 void scale(long n, double a, double* x, hipStream_t s);
+// x /= sqrt(*norm2), norm2 in device memory
+void scale_by_norm(long n, const double* norm2, double* x, hipStream_t s);
 
 int krylov_parts(long n);
 // out[i] = <V_i, w> for i < nvec (V column-major with leading dimension ldv);

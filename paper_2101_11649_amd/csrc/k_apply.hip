@@ -239,6 +239,15 @@ __global__ void k_scale(long n, double a, double* __restrict__ x) {
     if (i < n) x[i] *= a;
 }
 
+// x /= sqrt(*norm2) with the norm read on the device (x is left at zero when the
+// norm is zero, which only happens at an Arnoldi breakdown).
+__global__ void k_scale_by_norm(long n, const double* __restrict__ norm2, double* __restrict__ x) {
+    double q = *norm2;
+    double a = q > 0.0 ? 1.0 / sqrt(q) : 0.0;
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = x[i] * a;
+}
+
 // ---------------------------------------------------------------- Krylov reductions
 template <int NB>
 __device__ inline void block_reduce_write(double (&acc)[NB], double* __restrict__ out, int stride) {
@@ -500,6 +509,12 @@ void set(long n, T* dst, T v, hipStream_t s) {
 void scale(long n, double a, double* x, hipStream_t s) {
     if (n <= 0) return;
     k_scale<<<nblk(n), TPB, 0, s>>>(n, a, x);
+    MGR_LAUNCH_CHECK();
+}
+
+void scale_by_norm(long n, const double* norm2, double* x, hipStream_t s) {
+    if (n <= 0) return;
+    k_scale_by_norm<<<nblk(n), TPB, 0, s>>>(n, norm2, x);
     MGR_LAUNCH_CHECK();
 }
 

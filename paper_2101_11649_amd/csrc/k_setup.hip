@@ -513,6 +513,104 @@ __global__ __launch_bounds__(TPB) void k_spgemm_g(int nr, const int* __restrict_
     if (!FILL && valid && gl == 0) cnt[row] = count;
 }
 
+// The same product for a right factor with few columns (<= SPGEMM_DENSE): one
+// wavefront per output row accumulates into a dense LDS row.  The entries of
+// the row of A are taken one after another and, for each, the lanes add the
+// products of the distinct columns of the matching row of B, so every output
+// value still starts at 0.0 and adds its products in the order of A's entries
+// (Gustavson's order).  Row data for four entries of A is loaded ahead, so the
+// wave waits on global memory once per four entries; the pattern is the set of
+// touched columns (structural, like the merge variants), compacted in column
+// order at the end.
+constexpr int SPGEMM_DENSE = SPGEMM_DENSE_COLS;
+// rows x columns above which clearing and compacting the dense rows costs more
+// than the merge
+constexpr long SPGEMM_DENSE_WORK = 64L * 1024 * 1024;
+
+template <bool FILL>
+__global__ __launch_bounds__(WAVE) void k_spgemm_dw(int nr, const int* __restrict__ arp, const int* __restrict__ aci,
+                                                    const double* __restrict__ av, const int* __restrict__ brp,
+                                                    const int* __restrict__ bci, const double* __restrict__ bv,
+                                                    int ncols, const int* __restrict__ crp, int* __restrict__ cci,
+                                                    double* __restrict__ cv, int* __restrict__ cnt) {
+    __shared__ double acc[FILL ? SPGEMM_DENSE : 1];
+    __shared__ unsigned char hit[SPGEMM_DENSE];
+    const int row = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (row >= nr) return;
+    for (int c = lane; c < ncols; c += WAVE) {
+        hit[c] = 0;
+        if (FILL) acc[c] = 0.0;
+    }
+    const int a0 = arp[row], a1 = arp[row + 1];
+    for (int base = a0; base < a1; base += WAVE) {
+        // lane t holds entry base + t of the row of A and the extent of its row of B
+        int kb0 = 0, kb1 = 0;
+        double ka = 0.0;
+        if (base + lane < a1) {
+            int k = aci[base + lane];
+            kb0 = brp[k];
+            kb1 = brp[k + 1];
+            if (FILL) ka = av[base + lane];
+        }
+        const int cnt_here = min(WAVE, a1 - base);
+        for (int t0 = 0; t0 < cnt_here; t0 += 4) {
+            int jj[4], b0[4], b1[4];
+            double vv[4], aa[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                int t = min(t0 + u, cnt_here - 1);
+                b0[u] = __shfl(kb0, t, WAVE);
+                b1[u] = __shfl(kb1, t, WAVE);
+                aa[u] = __shfl(ka, t, WAVE);
+                int q = b0[u] + lane;
+                jj[u] = -1;
+                vv[u] = 0.0;
+                if (t0 + u < cnt_here && q < b1[u]) {
+                    jj[u] = bci[q];
+                    if (FILL) vv[u] = bv[q];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (t0 + u < cnt_here) {
+                    if (jj[u] >= 0) {
+                        hit[jj[u]] = 1;
+                        if (FILL) acc[jj[u]] = acc[jj[u]] + aa[u] * vv[u];
+                    }
+                    // rows of B longer than a wavefront
+                    for (int q = b0[u] + WAVE + lane; q < b1[u]; q += WAVE) {
+                        int j = bci[q];
+                        hit[j] = 1;
+                        if (FILL) acc[j] = acc[j] + aa[u] * bv[q];
+                    }
+                }
+            }
+        }
+    }
+    // compaction in column order: lane l scans columns [l*chunk, (l+1)*chunk)
+    const int chunk = (ncols + WAVE - 1) / WAVE;
+    const int c0 = min(lane * chunk, ncols), c1 = min(c0 + chunk, ncols);
+    int mine = 0;
+    for (int c = c0; c < c1; ++c) mine += hit[c];
+    int incl = mine;
+    for (int off = 1; off < WAVE; off <<= 1) {
+        int o = __shfl_up(incl, off, WAVE);
+        if (lane >= off) incl += o;
+    }
+    if (!FILL) {
+        if (lane == WAVE - 1) cnt[row] = incl;
+        return;
+    }
+    int o = crp[row] + incl - mine;
+    for (int c = c0; c < c1; ++c)
+        if (hit[c]) {
+            cci[o] = c;
+            cv[o] = acc[c];
+            ++o;
+        }
+}
+
 __global__ void k_add_count(int nr, const int* __restrict__ arp, const int* __restrict__ aci,
                             const int* __restrict__ brp, const int* __restrict__ bci, int* __restrict__ cnt) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1227,7 +1325,8 @@ __global__ __launch_bounds__(TPB) void k_transpose_scatter_g(int nr, const int* 
 }
 
 // Coarsest-level inverse for n <= 128, kept in registers: 1024 threads, thread
-// t owns row t/8 and the 32 columns (t%8)*32.. of the augmented matrix [A | I];
+// t owns row t/8 and the 32 columns t%8 + 8k of the augmented matrix [A | I]
+// (interleaved so that the eight column groups read different LDS banks);
 // Gauss-Jordan with partial pivoting (ties to the lower row), same steps as the
 // global-memory version.
 __global__ __launch_bounds__(1024) void k_dense_inverse_small(int n, const double* __restrict__ a,
@@ -1239,11 +1338,11 @@ __global__ __launch_bounds__(1024) void k_dense_inverse_small(int n, const doubl
     __shared__ double rowc[256], rowp[256];
     __shared__ int piv_sh;
     const int t = threadIdx.x;
-    const int r = t >> 3, c0 = (t & 7) * 32;
+    const int r = t >> 3, cg = t & 7;   // columns cg, cg + 8, ... (no LDS bank conflicts)
     double m[32];
 #pragma unroll
     for (int k = 0; k < 32; ++k) {
-        int c = c0 + k;
+        int c = cg + 8 * k;
         double x = 0.0;
         if (r < n) {
             if (c < n) x = a[(long)r * n + c];
@@ -1252,7 +1351,7 @@ __global__ __launch_bounds__(1024) void k_dense_inverse_small(int n, const doubl
         m[k] = x;
     }
     for (int c = 0; c < n; ++c) {
-        const int owner = c >> 5, ck = c & 31;
+        const int owner = c & 7, ck = c >> 3;
         double mine = 0.0;
 #pragma unroll
         for (int k = 0; k < 32; ++k)
@@ -1282,23 +1381,23 @@ __global__ __launch_bounds__(1024) void k_dense_inverse_small(int n, const doubl
         // swap rows c and p (through LDS), then scale the pivot row
         if (r == c || r == p) {
 #pragma unroll
-            for (int k = 0; k < 32; ++k) (r == c ? rowc : rowp)[c0 + k] = m[k];
+            for (int k = 0; k < 32; ++k) (r == c ? rowc : rowp)[cg + 8 * k] = m[k];
         }
         __syncthreads();
         if (p != c) {
             if (r == c) {
 #pragma unroll
-                for (int k = 0; k < 32; ++k) m[k] = rowp[c0 + k];
+                for (int k = 0; k < 32; ++k) m[k] = rowp[cg + 8 * k];
             } else if (r == p) {
 #pragma unroll
-                for (int k = 0; k < 32; ++k) m[k] = rowc[c0 + k];
+                for (int k = 0; k < 32; ++k) m[k] = rowc[cg + 8 * k];
             }
         }
         double piv = (p != c) ? rowp[c] : rowc[c];
         double ip = 1.0 / piv;
         if (r == c) {
 #pragma unroll
-            for (int k = 0; k < 32; ++k) { m[k] = m[k] * ip; prow[c0 + k] = m[k]; }
+            for (int k = 0; k < 32; ++k) { m[k] = m[k] * ip; prow[cg + 8 * k] = m[k]; }
         }
         // the multipliers: column c of every row after the swap
         if (r < n && (t & 7) == owner) {
@@ -1312,13 +1411,13 @@ __global__ __launch_bounds__(1024) void k_dense_inverse_small(int n, const doubl
         if (r < n && r != c) {
             double f = fcol[r];
 #pragma unroll
-            for (int k = 0; k < 32; ++k) m[k] = m[k] - f * prow[c0 + k];
+            for (int k = 0; k < 32; ++k) m[k] = m[k] - f * prow[cg + 8 * k];
         }
         __syncthreads();
     }
 #pragma unroll
     for (int k = 0; k < 32; ++k) {
-        int c = c0 + k;
+        int c = cg + 8 * k;
         if (r < n && c >= n && c < 2 * n) inv[(long)r * n + (c - n)] = m[k];
     }
 }
@@ -1372,6 +1471,106 @@ __global__ void k_pj_fill(int n, int nC, const int* __restrict__ isF, const int*
     if (!isF[g]) { pci[o] = k; pv[o] = 1.0; return; }
     for (int p = yrp[k]; p < yrp[k + 1]; ++p) { pci[o] = yci[p]; pv[o] = yscale * yv[p]; ++o; }
     for (int p = mrp[k]; p < mrp[k + 1]; ++p) { pci[o] = nC + fmap[mci[p]]; pv[o] = mscale * mv[p]; ++o; }
+}
+
+// ---------------------------------------------------------------- composed two-grid operators
+// For one L1-Jacobi V(1,1) level (pre-sweep from zero, restriction, coarse
+// correction, post-sweep) the output is linear in the level's right-hand side b
+// and the coarse correction x_c:  b_c = G b  and  x = W b + Q x_c  with
+//   W = 2 D^-1 - D^-1 A D^-1,  Q = P - D^-1 (A P),  G = R - (R A) D^-1.
+// These kernels form W, Q, G on the patterns of A, A P and R A; every entry of
+// P (of R) must appear in the pattern of A P (of R A), which holds when every
+// row of A stores its diagonal.  A missing diagonal or entry sets *bad.
+
+// W on the pattern of A.
+template <int G>
+__global__ __launch_bounds__(TPB) void k_compose_w_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                     const double* __restrict__ v, const double* __restrict__ dinv,
+                                                     double* __restrict__ w, int* __restrict__ bad) {
+    Grp<G> g;
+    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    bool valid = i < n;
+    int diag = 0;
+    if (valid) {
+        double di = dinv[i];
+        for (int p = rp[i] + g.gl; p < rp[i + 1]; p += G) {
+            int j = ci[p];
+            double t = di * v[p];
+            t = t * dinv[j];
+            double o = -t;
+            if (j == i) {
+                o = 2.0 * di - t;
+                ++diag;
+            }
+            w[p] = o;
+        }
+    }
+    diag = g.sum(diag);
+    if (valid && g.gl == 0 && diag != 1) atomicMax(bad, 1);
+}
+
+// out = X - S Y on the pattern of Y, with S = diag(rs) from the left (rs != null)
+// or diag(cs) from the right.  Row i of X must be contained in row i of Y.
+template <int G>
+__global__ __launch_bounds__(TPB) void k_compose_sub_g(int nr, const int* __restrict__ xrp, const int* __restrict__ xci,
+                                                       const double* __restrict__ xv, const int* __restrict__ yrp,
+                                                       const int* __restrict__ yci, const double* __restrict__ yv,
+                                                       const double* __restrict__ rs, const double* __restrict__ cs,
+                                                       double* __restrict__ out, int* __restrict__ bad) {
+    Grp<G> g;
+    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    bool valid = i < nr;
+    int found = 0, xlen = 0;
+    if (valid) {
+        int x0 = xrp[i], x1 = xrp[i + 1];
+        xlen = x1 - x0;
+        double ri = rs ? rs[i] : 0.0;
+        for (int p = yrp[i] + g.gl; p < yrp[i + 1]; p += G) {
+            int j = yci[p];
+            double t = (rs ? ri : cs[j]) * yv[p];
+            // binary search for column j in row i of X (columns ascending)
+            int lo = x0, hi = x1;
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (xci[mid] < j) lo = mid + 1;
+                else hi = mid;
+            }
+            double o = -t;
+            if (lo < x1 && xci[lo] == j) {
+                o = xv[lo] - t;
+                ++found;
+            }
+            out[p] = o;
+        }
+    }
+    found = g.sum(found);
+    if (valid && g.gl == 0 && found != xlen) atomicMax(bad, 1);
+}
+
+// C = [A | B] row by row (columns of B shifted by off); C's row pointers are
+// the sums of A's and B's.
+template <int G>
+__global__ __launch_bounds__(TPB) void k_concat_g(int nr, const int* __restrict__ arp, const int* __restrict__ aci,
+                                                  const double* __restrict__ av, const int* __restrict__ brp,
+                                                  const int* __restrict__ bci, const double* __restrict__ bv, int off,
+                                                  int* __restrict__ crp, int* __restrict__ cci,
+                                                  double* __restrict__ cv) {
+    Grp<G> g;
+    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    if (i > nr) return;
+    int a0 = arp[i], b0 = brp[i];
+    int o = a0 + b0;
+    if (g.gl == 0) crp[i] = o;
+    if (i == nr) return;
+    int la = arp[i + 1] - a0, lb = brp[i + 1] - b0;
+    for (int q = g.gl; q < la; q += G) {
+        cci[o + q] = aci[a0 + q];
+        cv[o + q] = av[a0 + q];
+    }
+    for (int q = g.gl; q < lb; q += G) {
+        cci[o + la + q] = bci[b0 + q] + off;
+        cv[o + la + q] = bv[b0 + q];
+    }
 }
 
 }  // namespace
@@ -1554,6 +1753,12 @@ static void spgemm_launch(const DCsr& A, const DCsr& B, int max_row, const int* 
                           int* flag, hipStream_t s) {
     // max_row selects the variant: <= 64 entries per row of A -> one head per lane
     if (A.nr <= 0) return;
+    if (B.nc <= SPGEMM_DENSE && (long)A.nr * B.nc <= SPGEMM_DENSE_WORK) {
+        k_spgemm_dw<FILL><<<A.nr, WAVE, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p, B.v.p, B.nc, crp, cci,
+                                                cv, cnt);
+        MGR_LAUNCH_CHECK();
+        return;
+    }
     int grid = ceil_div(A.nr, TPB / WAVE);
     if (max_row <= 32) {
         int G = 1;
@@ -1791,6 +1996,34 @@ void pj_fill(int n, int nC, const int* isF, const int* lmap, const DCsr& Y, doub
     if (n <= 0) return;
     k_pj_fill<<<nblk(n), TPB, 0, s>>>(n, nC, isF, lmap, Y.rp.p, Y.ci.p, Y.v.p, yscale, M.rp.p, M.ci.p, M.v.p,
                                       mscale, fmap, P.rp.p, P.ci.p, P.v.p);
+    MGR_LAUNCH_CHECK();
+}
+
+void compose_w(const DCsr& A, const double* dinv, double* w, int* bad, hipStream_t s) {
+    if (A.nr <= 0) return;
+    int G = group_for(A.max_row);
+    MGR_DISPATCH_G4(G, (k_compose_w_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, dinv, w,
+                                                                             bad)));
+    MGR_LAUNCH_CHECK();
+}
+
+void compose_sub(const DCsr& X, const DCsr& Y, const double* rs, const double* cs, double* out, int* bad,
+                 hipStream_t s) {
+    if (Y.nr <= 0) return;
+    if (X.nr != Y.nr || X.nc != Y.nc) throw Error(-6, "internal: composed operator shapes differ");
+    int G = group_for(Y.max_row);
+    MGR_DISPATCH_G4(G, (k_compose_sub_g<GG><<<grid_for(Y.nr, GG), TPB, 0, s>>>(
+                           Y.nr, X.rp.p, X.ci.p, X.v.p, Y.rp.p, Y.ci.p, Y.v.p, rs, cs, out, bad)));
+    MGR_LAUNCH_CHECK();
+}
+
+void concat_rows(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s) {
+    if (A.nr != B.nr) throw Error(-6, "internal: concatenated operators differ in rows");
+    C.alloc(A.nr, A.nc + B.nc, A.nnz + B.nnz, s);
+    C.max_row = A.max_row + B.max_row;
+    int G = group_for(C.max_row);
+    MGR_DISPATCH_G4(G, (k_concat_g<GG><<<grid_for((long)A.nr + 1, GG), TPB, 0, s>>>(
+                           A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p, B.v.p, A.nc, C.rp.p, C.ci.p, C.v.p)));
     MGR_LAUNCH_CHECK();
 }
 

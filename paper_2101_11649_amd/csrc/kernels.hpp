@@ -51,6 +51,9 @@ void frelax_fill(int nb, const int* bstart, const DCsr& AFF, DCsr& M, int* flag,
 int max_row_len(const DCsr& A, hipStream_t s);
 // C = A B counts; rows of A longer than the variant chosen by max_row get a zero
 // count and set *flag (an int in device memory) to 1.
+// Right factors with at most SPGEMM_DENSE_COLS columns (and few enough rows x
+// columns) use a dense-row accumulator per output row instead of the merge.
+constexpr int SPGEMM_DENSE_COLS = 4096;
 void spgemm_count(const DCsr& A, const DCsr& B, int max_row, int* cnt, int* flag, hipStream_t s);
 void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, hipStream_t s);
 void add_count(const DCsr& A, const DCsr& B, int* cnt, hipStream_t s);
@@ -77,6 +80,14 @@ void interp_count(const DCsr& A, const unsigned char* strong, const int* cf, int
 void interp_fill(const DCsr& A, const unsigned char* strong, const int* cf, const int* cidx, const int* label,
                  DCsr& P, int* flag, hipStream_t s);
 void l1_dinv(const DCsr& A, double* dinv, int* flag, hipStream_t s);
+// Composed operators of one L1-Jacobi V(1,1) level (b_c = G b, x = W b + Q x_c):
+// w = 2 D^-1 - D^-1 A D^-1 on A's pattern; out = X - S Y on Y's pattern with
+// S = diag(rs) on the left or diag(cs) on the right; C = [A | B].  *bad is set
+// when a row of A stores no diagonal or X is not contained in Y.
+void compose_w(const DCsr& A, const double* dinv, double* w, int* bad, hipStream_t s);
+void compose_sub(const DCsr& X, const DCsr& Y, const double* rs, const double* cs, double* out, int* bad,
+                 hipStream_t s);
+void concat_rows(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s);
 void densify(const DCsr& A, double* dense, hipStream_t s);
 void dense_inverse(int n, double* a, double* inv, int* flag, hipStream_t s);
 

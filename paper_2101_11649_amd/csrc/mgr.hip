@@ -217,6 +217,12 @@ static void make_float(DCsr& A, hipStream_t s) {
 struct AmgLevel {
     int n = 0;
     DCsr A, P, R, AT;        // R = P^T; AT = A^T for the transposed cycle
+    // composed form of a V(1,1) level: b_c = G b, x = [W | Q] [b; x_c]; the
+    // transposed cycle uses b_c = Q^T b, x = [W^T | G^T] [b; x_c]
+    bool composed = false;
+    DCsr G, W, Q, WQ, Qt, WGt;
+    DCsr AP, RA;             // setup temporaries of the composed form
+    long long* bad = nullptr;
     DArr<int> cf, label;
     DArr<double> dinv;
     DArr<float> dinvf;
@@ -231,6 +237,41 @@ struct Amg {
     int nc = 0, nu_pre = 1, nu_post = 1;
     bool have_float = false, have_trans = false;
 };
+
+// Levels whose matrix has at most this many entries (and at most
+// SPGEMM_DENSE_COLS rows, so that R A is a cheap product) are applied in
+// composed form: there a launch costs more than the extra entries the composed
+// operators read.
+constexpr long AMG_COMPOSE_NNZ = 1L << 20;
+
+// Forms W, Q = P - D^-1 (A P) (in place over A P) and G = R - (R A) D^-1 (in
+// place over R A) and [W | Q]; validity is read back at the next sync.
+static void amg_compose_begin(AmgLevel& L, Slots& S) {
+    hipStream_t s = S.s;
+    L.bad = S.take(1);
+    fill_ll(L.bad, 0, 1, s);
+    int* bad = reinterpret_cast<int*>(L.bad);
+    L.W = csr_copy(L.A, s);
+    compose_w(L.A, L.dinv.p, L.W.v.p, bad, s);
+    compose_sub(L.P, L.AP, L.dinv.p, nullptr, L.AP.v.p, bad, s);
+    L.Q = std::move(L.AP);
+    compose_sub(L.R, L.RA, nullptr, L.dinv.p, L.RA.v.p, bad, s);
+    L.G = std::move(L.RA);
+    concat_rows(L.W, L.Q, L.WQ, s);
+    make_rowblocks(L.WQ, s);
+}
+
+static void amg_compose_finish(AmgLevel& L, Slots& S) {
+    if (S.val(L.bad) != 0) {
+        // a row without a stored diagonal: keep the plain four-SpMV form
+        L.composed = false;
+        L.G = DCsr();
+        L.W = DCsr();
+        L.Q = DCsr();
+        L.WQ = DCsr();
+    }
+    L.bad = nullptr;
+}
 
 // Classical AMG setup (the coarse solver of Sec. 4.1, with PMIS coarsening,
 // direct interpolation and L1-Jacobi smoothing; see the oracle for the
@@ -309,12 +350,19 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
         S.sync("AMG interpolation");
         csr_transpose_finish(tr, S);
         spgemm_finish(j1, S);
-        Spgemm j2;
+        Spgemm j2, j3;
         spgemm_begin(j2, R, AP, Ac, S);
+        // small V(1,1) levels are applied in composed form (two SpMVs instead of four)
+        L.composed = H.nu_pre == 1 && H.nu_post == 1 && A.nnz <= AMG_COMPOSE_NNZ && n <= SPGEMM_DENSE_COLS;
+        if (L.composed) spgemm_begin(j3, R, A, L.RA, S);
         L.dinv.alloc((size_t)n, s);
         l1_dinv(A, L.dinv.p, S.flag(), s);
         S.sync("AMG Galerkin product");
         spgemm_finish(j2, S);
+        if (L.composed) {
+            spgemm_finish(j3, S);
+            L.AP = std::move(AP);
+        }
         AP = DCsr();
         L.P = std::move(P);
         L.R = std::move(R);
@@ -331,6 +379,9 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
         H.lv.push_back(std::move(next));
         ++k;
     }
+    H.lv.back().composed = false;
+    for (size_t l = 0; l + 1 < H.lv.size(); ++l)
+        if (H.lv[l].composed) amg_compose_begin(H.lv[l], S);
     AmgLevel& Lc = H.lv.back();
     H.nc = Lc.n;
     if (H.nc > 2048) throw Error(MGR_ERR_UNSUPPORTED, "AMG: coarsest level has more than 2048 unknowns");
@@ -347,6 +398,8 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
         if (l > 0) { L.bd.alloc((size_t)L.n + 1, s); L.xd.alloc((size_t)L.n + 1, s); }
     }
     S.sync("AMG coarsest inverse");
+    for (size_t l = 0; l + 1 < H.lv.size(); ++l)
+        if (H.lv[l].composed) amg_compose_finish(H.lv[l], S);
     H.have_float = false;
     H.have_trans = false;
 }
@@ -355,14 +408,23 @@ static void amg_make_float(Amg& H, hipStream_t s) {
     if (H.have_float) return;
     for (size_t l = 0; l < H.lv.size(); ++l) {
         AmgLevel& L = H.lv[l];
-        make_float(L.A, s);
-        if (l + 1 < H.lv.size()) {
+        if (L.composed) {
+            make_float(L.G, s);
+            make_float(L.WQ, s);
+            if (H.have_trans) {
+                make_float(L.Qt, s);
+                make_float(L.WGt, s);
+            }
+        } else {
+            make_float(L.A, s);
+        }
+        if (l + 1 < H.lv.size() && !L.composed) {
             make_float(L.P, s);
             make_float(L.R, s);
             L.dinvf.alloc((size_t)L.n, s);
             to_float(L.dinv.p, L.dinvf.p, L.n, s);
         }
-        if (H.have_trans && L.AT.nr) make_float(L.AT, s);
+        if (H.have_trans && L.AT.nr && !L.composed) make_float(L.AT, s);
         L.rf.alloc((size_t)L.n + 1, s);
         L.tf.alloc((size_t)L.n + 1, s);
         if (l > 0) { L.bf.alloc((size_t)L.n + 1, s); L.xf.alloc((size_t)L.n + 1, s); }
@@ -381,8 +443,26 @@ static void amg_make_trans(Amg& H, Slots& S) {
     hipStream_t s = S.s;
     if (H.have_trans) return;
     for (size_t l = 0; l + 1 < H.lv.size(); ++l) {
-        H.lv[l].AT = csr_transpose(H.lv[l].A, S);
-        if (H.have_float) make_float(H.lv[l].AT, s);
+        AmgLevel& L = H.lv[l];
+        if (L.composed) {
+            DCsr Wt, Gt;
+            Transp t1 = csr_transpose_begin(L.Q, L.Qt, S);
+            Transp t2 = csr_transpose_begin(L.W, Wt, S);
+            Transp t3 = csr_transpose_begin(L.G, Gt, S);
+            S.sync("transpose of a composed level");
+            csr_transpose_finish(t1, S);
+            csr_transpose_finish(t2, S);
+            csr_transpose_finish(t3, S);
+            concat_rows(Wt, Gt, L.WGt, s);
+            make_rowblocks(L.WGt, s);
+            if (H.have_float) {
+                make_float(L.Qt, s);
+                make_float(L.WGt, s);
+            }
+            continue;
+        }
+        L.AT = csr_transpose(L.A, S);
+        if (H.have_float) make_float(L.AT, s);
     }
     int nc = H.nc;
     std::vector<double> h((size_t)nc * nc), t((size_t)nc * nc);
@@ -427,6 +507,16 @@ static void amg_vcycle(Amg& H, int k, const T* b, T* x, bool tr, hipStream_t s) 
     int n = L.n;
     if (k + 1 == (int)H.lv.size()) {
         dense_gemv<T, T>(n, Prec<T>::cinv(H, tr), b, x, s);
+        return;
+    }
+    if (L.composed) {
+        AmgLevel& Lc = H.lv[k + 1];
+        T* bc = Prec<T>::b(Lc);
+        T* xc = Prec<T>::x(Lc);
+        spmv<T, T, T, T, T>(view<T>(tr ? L.Qt : L.G), b, (const T*)nullptr, INT_MAX, (const T*)nullptr, bc, T(1),
+                            T(0), s);
+        amg_vcycle<T>(H, k + 1, bc, xc, tr, s);
+        spmv<T, T, T, T, T>(view<T>(tr ? L.WGt : L.WQ), b, xc, n, (const T*)nullptr, x, T(1), T(0), s);
         return;
     }
     SpOp<T> A = view<T>(tr ? L.AT : L.A);
@@ -556,6 +646,15 @@ struct Ctx {
     long kr_n = 0;
     DArr<double> V, Z, hbuf, part, yd;
     DArr<double> apply_tmp;
+    // pinned copies of the Arnoldi coefficients, one row of HROW per iteration,
+    // and the event that marks each copy
+    static constexpr int HROW = 130;
+    double* hpin = nullptr;
+    std::vector<hipEvent_t> hev;
+    ~Ctx() {
+        for (hipEvent_t e : hev) (void)hipEventDestroy(e);
+        if (hpin) (void)hipHostFree(hpin);
+    }
 };
 
 static bool fused_ok(const mgr_level_opts& o) {
@@ -954,6 +1053,15 @@ static void ensure_krylov(Ctx& c) {
     c.hbuf.alloc(256, s);
     c.part.alloc((size_t)(m + 2) * KRYLOV_PARTS, s);
     c.yd.alloc(64, s);
+    if (c.hpin) (void)hipHostFree(c.hpin);
+    c.hpin = nullptr;
+    MGR_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.hpin), sizeof(double) * Ctx::HROW * (m + 1),
+                          hipHostMallocDefault));
+    while ((int)c.hev.size() < m) {
+        hipEvent_t e;
+        MGR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        c.hev.push_back(e);
+    }
     c.kr_m = m;
     c.kr_n = c.n;
 }
@@ -961,6 +1069,13 @@ static void ensure_krylov(Ctx& c) {
 // Flexible GMRES(m) with right preconditioning (Saad 1993): x0 = 0, CGS2
 // Arnoldi, Givens rotations on the host, stop when |g_{j+1}| <= rtol ||b||,
 // then the true residual ||b - A x|| is checked and the cycle restarted if needed.
+//
+// The basis vector is normalised on the device, so iteration j+1 can be queued
+// before the host has seen the coefficients of iteration j: the host processes
+// column j-1 while the GPU runs iteration j.  When the residual estimate
+// predicts convergence within the next column, the host waits for the current
+// column instead, so that no iteration is queued past convergence in the usual
+// case (one queued past it is only wasted work: it never enters the solution).
 static int fgmres(Ctx& c, bool tr, const double* b, double* x, mgr_solve_info* info) {
     hipStream_t s = c.s;
     ensure_krylov(c);
@@ -969,19 +1084,20 @@ static int fgmres(Ctx& c, bool tr, const double* b, double* x, mgr_solve_info* i
     double* V = c.V.p;
     double* Z = c.Z.p;
     double* hb = c.hbuf.p;  // [0,64): h1, [64,128): h2, [128]: ||w||^2, [129]: scratch
-    double hh[130];
+    double* hscr = c.hpin + (size_t)Ctx::HROW * m;   // host row for the scalar reads
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
     set<double>(n, x, 0.0, s);
     mdot(n, b, n, 1, b, c.part.p, hb + 129, s);
-    MGR_HIP(hipMemcpyAsync(hh + 129, hb + 129, sizeof(double), hipMemcpyDeviceToHost, s));
+    MGR_HIP(hipMemcpyAsync(hscr + 129, hb + 129, sizeof(double), hipMemcpyDeviceToHost, s));
     MGR_HIP(hipStreamSynchronize(s));
-    double bnorm = std::sqrt(hh[129]);
+    double bnorm = std::sqrt(hscr[129]);
     mgr_solve_info inf{};
     if (bnorm == 0.0) {
         inf.status = MGR_OK;
         if (info) *info = inf;
         return MGR_OK;
     }
+    const double tol = c.o.rtol * bnorm;
     int iters = 0;
     bool converged = false;
     double est = 1.0, truer = 1.0;
@@ -992,10 +1108,10 @@ static int fgmres(Ctx& c, bool tr, const double* b, double* x, mgr_solve_info* i
         else matvec(c, tr, x, b, V, -1.0, 1.0);
         first = false;
         mdot(n, V, n, 1, V, c.part.p, hb + 129, s);
-        MGR_HIP(hipMemcpyAsync(hh + 129, hb + 129, sizeof(double), hipMemcpyDeviceToHost, s));
+        MGR_HIP(hipMemcpyAsync(hscr + 129, hb + 129, sizeof(double), hipMemcpyDeviceToHost, s));
         MGR_HIP(hipStreamSynchronize(s));
-        double beta = std::sqrt(hh[129]);
-        if (beta <= c.o.rtol * bnorm) {
+        double beta = std::sqrt(hscr[129]);
+        if (beta <= tol) {
             converged = true;
             est = truer = beta / bnorm;
             break;
@@ -1005,20 +1121,14 @@ static int fgmres(Ctx& c, bool tr, const double* b, double* x, mgr_solve_info* i
         std::fill(g.begin(), g.end(), 0.0);
         std::fill(H.begin(), H.end(), 0.0);
         g[0] = beta;
-        int k = 0;
-        for (int j = 0; j < m; ++j) {
-            double* vj = V + (long)j * n;
-            double* zj = Z + (long)j * n;
-            double* w = V + (long)(j + 1) * n;
-            mgr_apply_top(c, vj, zj, tr);
-            matvec(c, tr, zj, nullptr, w, 1.0, 0.0);
-            // classical Gram-Schmidt, twice
-            mdot(n, V, n, j + 1, w, c.part.p, hb, s);
-            maxpy(n, V, n, j + 1, hb, 1.0, w, c.part.p, nullptr, s);
-            mdot(n, V, n, j + 1, w, c.part.p, hb + 64, s);
-            maxpy(n, V, n, j + 1, hb + 64, 1.0, w, c.part.p, hb + 128, s);
-            MGR_HIP(hipMemcpyAsync(hh, hb, sizeof(double) * 129, hipMemcpyDeviceToHost, s));
-            MGR_HIP(hipStreamSynchronize(s));
+        const int jmax = std::min(m, c.o.maxiter - iters);
+        int k = 0;          // columns processed on the host
+        bool stop = false;  // converged, broke down, or out of iterations
+        double rate = 1.0;  // last ratio |g_{j+1}| / |g_j|
+        // Givens update of column j from its pinned coefficients
+        auto process = [&](int j) {
+            MGR_HIP(hipEventSynchronize(c.hev[j]));
+            const double* hh = c.hpin + (size_t)Ctx::HROW * j;
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[64 + i];
             double hn = std::sqrt(hh[128]);
             H[(size_t)(j + 1) * m + j] = hn;
@@ -1033,15 +1143,37 @@ static int fgmres(Ctx& c, bool tr, const double* b, double* x, mgr_solve_info* i
             else { cs[j] = a0 / den; sn[j] = a1 / den; }
             H[(size_t)j * m + j] = cs[j] * a0 + sn[j] * a1;
             H[(size_t)(j + 1) * m + j] = 0.0;
+            double gprev = std::fabs(g[j]);
             g[j + 1] = -sn[j] * g[j];
             g[j] = cs[j] * g[j];
             ++iters;
             k = j + 1;
             est = std::fabs(g[j + 1]) / bnorm;
-            if (hn == 0.0) break;
-            scale(n, 1.0 / hn, w, s);
-            if (std::fabs(g[j + 1]) <= c.o.rtol * bnorm || iters >= c.o.maxiter) break;
+            if (gprev > 0.0) rate = std::min(1.0, std::max(0.05, std::fabs(g[j + 1]) / gprev));
+            if (hn == 0.0 || std::fabs(g[j + 1]) <= tol || iters >= c.o.maxiter) stop = true;
+        };
+        for (int j = 0; j < jmax && !stop; ++j) {
+            double* vj = V + (long)j * n;
+            double* zj = Z + (long)j * n;
+            double* w = V + (long)(j + 1) * n;
+            mgr_apply_top(c, vj, zj, tr);
+            matvec(c, tr, zj, nullptr, w, 1.0, 0.0);
+            // classical Gram-Schmidt, twice; then w /= ||w|| on the device
+            mdot(n, V, n, j + 1, w, c.part.p, hb, s);
+            maxpy(n, V, n, j + 1, hb, 1.0, w, c.part.p, nullptr, s);
+            mdot(n, V, n, j + 1, w, c.part.p, hb + 64, s);
+            maxpy(n, V, n, j + 1, hb + 64, 1.0, w, c.part.p, hb + 128, s);
+            scale_by_norm(n, hb + 128, w, s);
+            MGR_HIP(hipMemcpyAsync(c.hpin + (size_t)Ctx::HROW * j, hb, sizeof(double) * 129, hipMemcpyDeviceToHost,
+                                   s));
+            MGR_HIP(hipEventRecord(c.hev[j], s));
+            // wait for this column if convergence looks near (predicted from the
+            // last processed column), else for the previous one
+            double pred = std::fabs(g[k]) * std::pow(rate, (double)(j + 1 - k));
+            int upto = (j + 1 == jmax || pred <= 4.0 * tol) ? j : j - 1;
+            while (k <= upto && !stop) process(k);
         }
+        while (!stop && k < jmax) process(k);
         for (int i = k - 1; i >= 0; --i) {
             double t = g[i];
             for (int q = i + 1; q < k; ++q) t -= H[(size_t)i * m + q] * y[q];
@@ -1053,9 +1185,9 @@ static int fgmres(Ctx& c, bool tr, const double* b, double* x, mgr_solve_info* i
         double* r = V;
         matvec(c, tr, x, b, r, -1.0, 1.0);
         mdot(n, r, n, 1, r, c.part.p, hb + 129, s);
-        MGR_HIP(hipMemcpyAsync(hh + 129, hb + 129, sizeof(double), hipMemcpyDeviceToHost, s));
+        MGR_HIP(hipMemcpyAsync(hscr + 129, hb + 129, sizeof(double), hipMemcpyDeviceToHost, s));
         MGR_HIP(hipStreamSynchronize(s));
-        truer = std::sqrt(hh[129]) / bnorm;
+        truer = std::sqrt(hscr[129]) / bnorm;
         if (truer <= c.o.rtol) { converged = true; break; }
         if (iters >= c.o.maxiter) break;
         first = false;
