@@ -6,9 +6,11 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <stdexcept>
 #include <string>
 #include <utility>
+#include <vector>
 
 namespace mgr {
 
@@ -29,19 +31,75 @@ struct Error : public std::runtime_error {
 
 #define MGR_LAUNCH_CHECK() MGR_HIP(hipGetLastError())
 
-// Stream-ordered device array (hipMallocAsync / hipFreeAsync on one stream).
+// Stream-ordered block cache of one solver context.  A setup makes hundreds of
+// short-lived device arrays; handing their blocks back to a free list (by size
+// class) and out again to later allocations on the same stream costs a map
+// lookup instead of a runtime call.  Reuse needs no synchronisation because all
+// of a context's device work is ordered on its one stream.  The blocks stay
+// with the context until it is destroyed.
+struct BlockCache {
+    hipStream_t s = nullptr;
+    std::multimap<size_t, void*> free_;
+    std::vector<void*> owned_;
+    // 256-byte granules up to 4 KiB, then four classes per power of two
+    static size_t size_class(size_t bytes) {
+        if (bytes <= 4096) return (bytes + 255) & ~size_t(255);
+        size_t p = 4096;
+        while (p * 2 < bytes) p *= 2;
+        size_t step = p / 4;
+        return (bytes + step - 1) / step * step;
+    }
+    void* get(size_t bytes, size_t& cls) {
+        cls = size_class(bytes);
+        auto it = free_.find(cls);
+        if (it != free_.end()) {
+            void* q = it->second;
+            free_.erase(it);
+            return q;
+        }
+        void* q = nullptr;
+        MGR_HIP(hipMallocAsync(&q, cls, s));
+        owned_.push_back(q);
+        return q;
+    }
+    void put(void* q, size_t cls) { free_.emplace(cls, q); }
+    // every block goes back to the runtime (the caller has synchronised s)
+    void release() {
+        for (void* q : owned_) (void)hipFreeAsync(q, s);
+        owned_.clear();
+        free_.clear();
+    }
+    ~BlockCache() { release(); }
+};
+
+// The cache that device arrays allocated by the current thread draw from (set
+// for the duration of a library call on a context; null elsewhere).
+inline thread_local BlockCache* tl_cache = nullptr;
+
+// Stream-ordered device array: from the current context's block cache when one
+// is active on this stream, else hipMallocAsync / hipFreeAsync.
 template <typename T>
 struct DArr {
     T* p = nullptr;
     size_t n = 0;
     hipStream_t s = nullptr;
+    BlockCache* cache = nullptr;
+    size_t cls = 0;
     DArr() = default;
     DArr(size_t count, hipStream_t st) { alloc(count, st); }
     DArr(const DArr&) = delete;
     DArr& operator=(const DArr&) = delete;
-    DArr(DArr&& o) noexcept : p(o.p), n(o.n), s(o.s) { o.p = nullptr; o.n = 0; }
+    DArr(DArr&& o) noexcept : p(o.p), n(o.n), s(o.s), cache(o.cache), cls(o.cls) {
+        o.p = nullptr;
+        o.n = 0;
+        o.cache = nullptr;
+    }
     DArr& operator=(DArr&& o) noexcept {
-        if (this != &o) { reset(); p = o.p; n = o.n; s = o.s; o.p = nullptr; o.n = 0; }
+        if (this != &o) {
+            reset();
+            p = o.p; n = o.n; s = o.s; cache = o.cache; cls = o.cls;
+            o.p = nullptr; o.n = 0; o.cache = nullptr;
+        }
         return *this;
     }
     ~DArr() { reset(); }
@@ -49,12 +107,22 @@ struct DArr {
         reset();
         s = st;
         n = count;
-        if (count) MGR_HIP(hipMallocAsync(reinterpret_cast<void**>(&p), count * sizeof(T), st));
+        if (!count) return;
+        if (tl_cache && tl_cache->s == st) {
+            cache = tl_cache;
+            p = static_cast<T*>(cache->get(count * sizeof(T), cls));
+        } else {
+            MGR_HIP(hipMallocAsync(reinterpret_cast<void**>(&p), count * sizeof(T), st));
+        }
     }
     void reset() {
-        if (p) (void)hipFreeAsync(p, s);
+        if (p) {
+            if (cache) cache->put(p, cls);
+            else (void)hipFreeAsync(p, s);
+        }
         p = nullptr;
         n = 0;
+        cache = nullptr;
     }
     T* get() const { return p; }
     size_t bytes() const { return n * sizeof(T); }

@@ -115,6 +115,62 @@ __global__ void k_scan_apply(const int* __restrict__ in, int n, const long long*
     }
 }
 
+// Whole scan in one workgroup for n <= SCAN_SMALL: thread t owns up to 16
+// consecutive inputs; wavefront scans, then a scan of the 16 wave totals.
+constexpr int SCAN_SMALL = 1024 * 16;
+
+__global__ __launch_bounds__(1024) void k_scan_small(const int* __restrict__ in, int n, int* __restrict__ out,
+                                                     long long* __restrict__ slot) {
+    __shared__ long long wsum[16];
+    __shared__ int wmax[16];
+    const int t = threadIdx.x, lane = t & (WAVE - 1), wid = t / WAVE;
+    const int chunk = (n + 1023) / 1024;
+    const int b0 = t * chunk;
+    int v[16];
+    long long sum = 0;
+    int m = 0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        int i = b0 + u;
+        v[u] = (u < chunk && i < n) ? in[i] : 0;
+        sum += v[u];
+        m = max(m, v[u]);
+    }
+    long long inc = sum;
+    for (int off = 1; off < WAVE; off <<= 1) {
+        long long o = __shfl_up(inc, off, WAVE);
+        if (lane >= off) inc += o;
+    }
+    for (int off = WAVE / 2; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, WAVE));
+    if (lane == WAVE - 1) wsum[wid] = inc;
+    if (lane == 0) wmax[wid] = m;
+    __syncthreads();
+    if (wid == 0) {
+        long long x = lane < 16 ? wsum[lane] : 0;
+        int y = lane < 16 ? wmax[lane] : 0;
+        for (int off = 1; off < 16; off <<= 1) {
+            long long o = __shfl_up(x, off, WAVE);
+            if (lane >= off) x += o;
+        }
+        for (int off = 8; off > 0; off >>= 1) y = max(y, __shfl_xor(y, off, WAVE));
+        if (lane < 16) wsum[lane] = x;
+        if (lane == 0) wmax[0] = y;
+    }
+    __syncthreads();
+    long long run = (wid ? wsum[wid - 1] : 0) + inc - sum;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        int i = b0 + u;
+        if (u < chunk && i < n) out[i] = (int)run;
+        run += v[u];
+    }
+    if (t == 0) {
+        long long total = wsum[15];
+        out[n] = (total > INT_MAX) ? INT_MAX : (int)total;
+        if (slot) { slot[0] = total; slot[1] = wmax[0]; }
+    }
+}
+
 __global__ void k_fill_ll(long long* p, long long v, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -1595,6 +1651,11 @@ static int group_for(int max_row) {
 static int grid_for(long rows, int G) { return (int)((rows * G + TPB - 1) / TPB); }
 
 void scan_async(const int* in, int* out, int n, long long* slot, hipStream_t s) {
+    if (n <= SCAN_SMALL) {
+        k_scan_small<<<1, 1024, 0, s>>>(in, n < 0 ? 0 : n, out, slot);
+        MGR_LAUNCH_CHECK();
+        return;
+    }
     int nb = ceil_div(n > 0 ? n : 1, SCAN_B);
     DArr<long long> tmp((size_t)2 * nb + 2, s);
     k_scan_reduce<<<nb, SCAN_T, 0, s>>>(in, n, tmp.p, tmp.p + nb);

@@ -628,6 +628,9 @@ struct MgrLevel {
 };
 
 struct Ctx {
+    // declared first so that it is destroyed last, after every array has
+    // returned its block
+    BlockCache cache;
     hipStream_t s = nullptr;
     mgr_opts o{};
     std::string err;
@@ -1342,6 +1345,12 @@ using mgr::Error;
 template <typename F>
 static int guarded(mgr_handle h, F&& f) {
     if (!h) return MGR_ERR_ARG;
+    // device arrays made during the call come from the context's block cache
+    struct CacheScope {
+        mgr::BlockCache* prev;
+        explicit CacheScope(mgr::BlockCache* c) : prev(mgr::tl_cache) { mgr::tl_cache = c; }
+        ~CacheScope() { mgr::tl_cache = prev; }
+    } scope(&h->c.cache);
     try {
         h->c.err.clear();
         return f();
@@ -1392,6 +1401,7 @@ int mgr_create(mgr_handle* h, const mgr_opts* o, void* hip_stream) {
     mgr_ctx* c = new (std::nothrow) mgr_ctx();
     if (!c) return MGR_ERR_OOM;
     c->c.s = (hipStream_t)hip_stream;
+    c->c.cache.s = c->c.s;
     c->c.o = d;
     try {
         // keep freed blocks in the stream-ordered pool across synchronisations:
