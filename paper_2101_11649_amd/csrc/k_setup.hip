@@ -667,35 +667,6 @@ __global__ __launch_bounds__(WAVE) void k_spgemm_dw(int nr, const int* __restric
         }
 }
 
-__global__ void k_add_count(int nr, const int* __restrict__ arp, const int* __restrict__ aci,
-                            const int* __restrict__ brp, const int* __restrict__ bci, int* __restrict__ cnt) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nr) return;
-    int p = arp[i], pe = arp[i + 1], q = brp[i], qe = brp[i + 1], n = 0;
-    while (p < pe || q < qe) {
-        if (q >= qe || (p < pe && aci[p] < bci[q])) ++p;
-        else if (p >= pe || bci[q] < aci[p]) ++q;
-        else { ++p; ++q; }
-        ++n;
-    }
-    cnt[i] = n;
-}
-
-__global__ void k_add_fill(int nr, const int* __restrict__ arp, const int* __restrict__ aci,
-                           const double* __restrict__ av, const int* __restrict__ brp, const int* __restrict__ bci,
-                           const double* __restrict__ bv, const int* __restrict__ crp, int* __restrict__ cci,
-                           double* __restrict__ cv) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nr) return;
-    int p = arp[i], pe = arp[i + 1], q = brp[i], qe = brp[i + 1], o = crp[i];
-    while (p < pe || q < qe) {
-        if (q >= qe || (p < pe && aci[p] < bci[q])) { cci[o] = aci[p]; cv[o] = av[p]; ++p; }
-        else if (p >= pe || bci[q] < aci[p]) { cci[o] = bci[q]; cv[o] = bv[q]; ++q; }
-        else { cci[o] = aci[p]; cv[o] = av[p] + bv[q]; ++p; ++q; }
-        ++o;
-    }
-}
-
 __global__ void k_transpose_count(long nnz, const int* __restrict__ ci, int* __restrict__ cnt) {
     long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p < nnz) atomicAdd(&cnt[ci[p]], 1);
@@ -713,22 +684,30 @@ __global__ void k_transpose_scatter(int nr, const int* __restrict__ rp, const in
     }
 }
 
-// Sort each transposed row by source row (an insertion sort: rows are short).
-__global__ void k_transpose_sort(int nr, const int* __restrict__ rp, int* __restrict__ ci, double* __restrict__ v) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Row i of the transpose, scattered in arbitrary order into tci / tv, is
+// written to ci / v in ascending column order: one wavefront per row, the
+// position of each entry is the number of smaller keys in the row (keys of a
+// row are distinct).
+__global__ __launch_bounds__(TPB) void k_transpose_rank(int nr, const int* __restrict__ rp,
+                                                        const int* __restrict__ tci, const double* __restrict__ tv,
+                                                        int* __restrict__ ci, double* __restrict__ v) {
+    const int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / WAVE);
+    const int lane = threadIdx.x & (WAVE - 1);
     if (i >= nr) return;
-    int q0 = rp[i], q1 = rp[i + 1];
-    for (int q = q0 + 1; q < q1; ++q) {
-        int key = ci[q];
-        double val = v ? v[q] : 0.0;
-        int t = q - 1;
-        while (t >= q0 && ci[t] > key) {
-            ci[t + 1] = ci[t];
-            if (v) v[t + 1] = v[t];
-            --t;
+    const int q0 = rp[i], q1 = rp[i + 1];
+    for (int u0 = q0; u0 < q1; u0 += WAVE) {
+        const int q = u0 + lane;
+        const int key = (q < q1) ? tci[q] : INT_MAX;
+        int rank = 0;
+        for (int base = q0; base < q1; base += WAVE) {
+            int kk = (base + lane < q1) ? tci[base + lane] : INT_MAX;
+            const int lim = min(WAVE, q1 - base);
+            for (int t = 0; t < lim; ++t) rank += (__shfl(kk, t, WAVE) < key) ? 1 : 0;
         }
-        ci[t + 1] = key;
-        if (v) v[t + 1] = val;
+        if (q < q1) {
+            ci[q0 + rank] = key;
+            if (v) v[q0 + rank] = tv[q];
+        }
     }
 }
 
@@ -1115,6 +1094,83 @@ __device__ inline int wave_max_int(int v) {
     return v;
 }
 
+// C = A + B with a lane group of G lanes per row.  An entry of A with column c
+// lands at (its index in A's row) + (entries of B's row below c) - (columns
+// below c present in both), found by binary search in the other row and a
+// group prefix count of the shared columns; entries of B present in A are
+// added to A's value (a + b), the others placed the same way.
+__device__ inline int lower_bound_int(const int* __restrict__ a, int len, int key) {
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <int G, bool FILL>
+__global__ __launch_bounds__(TPB) void k_add_g(int nr, const int* __restrict__ arp, const int* __restrict__ aci,
+                                               const double* __restrict__ av, const int* __restrict__ brp,
+                                               const int* __restrict__ bci, const double* __restrict__ bv,
+                                               const int* __restrict__ crp, int* __restrict__ cci,
+                                               double* __restrict__ cv, int* __restrict__ cnt) {
+    Grp<G> g;
+    const int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    const bool valid = i < nr;
+    int a0 = 0, la = 0, b0 = 0, lb = 0, o = 0;
+    if (valid) {
+        a0 = arp[i];
+        la = arp[i + 1] - a0;
+        b0 = brp[i];
+        lb = brp[i + 1] - b0;
+        if (FILL) o = crp[i];
+    }
+    const int wla = wave_max_int(la), wlb = wave_max_int(lb);
+    int mA = 0;
+    for (int base = 0; base < wla; base += G) {
+        const int ia = base + g.gl;
+        const bool act = ia < la;
+        int ca = 0, rb = 0;
+        bool eq = false;
+        if (act) {
+            ca = aci[a0 + ia];
+            rb = lower_bound_int(bci + b0, lb, ca);
+            eq = rb < lb && bci[b0 + rb] == ca;
+        }
+        const unsigned long long bits = g.bits(eq);
+        if (FILL && act) {
+            int pos = o + ia + rb - (mA + g.below(bits));
+            cci[pos] = ca;
+            cv[pos] = eq ? av[a0 + ia] + bv[b0 + rb] : av[a0 + ia];
+        }
+        mA += __popcll(bits);
+    }
+    if (!FILL) {
+        if (valid && g.gl == 0) cnt[i] = la + lb - mA;
+        return;
+    }
+    int mB = 0;
+    for (int base = 0; base < wlb; base += G) {
+        const int jb = base + g.gl;
+        const bool act = jb < lb;
+        int cb = 0, ra = 0;
+        bool eq = false;
+        if (act) {
+            cb = bci[b0 + jb];
+            ra = lower_bound_int(aci + a0, la, cb);
+            eq = ra < la && aci[a0 + ra] == cb;
+        }
+        const unsigned long long bits = g.bits(eq);
+        if (act && !eq) {
+            int pos = o + jb + ra - (mB + g.below(bits));
+            cci[pos] = cb;
+            cv[pos] = bv[b0 + jb];
+        }
+        mB += __popcll(bits);
+    }
+}
+
 template <int G>
 __global__ __launch_bounds__(TPB) void k_extract_count_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                          const int* __restrict__ isF, const int* __restrict__ lmap,
@@ -1312,7 +1368,8 @@ __global__ __launch_bounds__(TPB) void k_interp_fill_g(int n, const int* __restr
                 sc = strong[p0 + q] && cf[k] == 1;
             }
         }
-        for (int t = 0; t < G; ++t) {
+        const int lim = min(G, maxlen - base);
+        for (int t = 0; t < lim; ++t) {
             double at = __shfl(a, g.gbase + t, WAVE);
             int kt = __shfl(kind, g.gbase + t, WAVE);
             int st = __shfl((int)sc, g.gbase + t, WAVE);
@@ -1381,100 +1438,116 @@ __global__ __launch_bounds__(TPB) void k_transpose_scatter_g(int nr, const int* 
 }
 
 // Coarsest-level inverse for n <= 128, kept in registers: 1024 threads, thread
-// t owns row t/8 and the 32 columns t%8 + 8k of the augmented matrix [A | I]
-// (interleaved so that the eight column groups read different LDS banks);
-// Gauss-Jordan with partial pivoting (ties to the lower row), same steps as the
-// global-memory version.
+// t owns rows 4(t/32) .. 4(t/32)+3 and the eight columns t%32 + 32k of the
+// augmented matrix [A | I] (eight pivot-row values and four multipliers read
+// from LDS per step).  Gauss-Jordan with partial pivoting in place: the pivot
+// of column c is the largest |entry| among rows not yet used as pivots (ties
+// to the lower row); no rows are swapped, so at the end row p of the right
+// half is row c of the inverse when p was the pivot row of column c.
 __global__ __launch_bounds__(1024) void k_dense_inverse_small(int n, const double* __restrict__ a,
                                                               double* __restrict__ inv, int* __restrict__ flag) {
     __shared__ double prow[256];
     __shared__ double fcol[128];
     __shared__ double pv[128];
-    __shared__ int pi[128];
-    __shared__ double rowc[256], rowp[256];
+    __shared__ int used[128];
+    __shared__ int pos[128];
     __shared__ int piv_sh;
     const int t = threadIdx.x;
-    const int r = t >> 3, cg = t & 7;   // columns cg, cg + 8, ... (no LDS bank conflicts)
-    double m[32];
+    const int rb = t >> 5, cb = t & 31;
+    double m[4][8];
 #pragma unroll
-    for (int k = 0; k < 32; ++k) {
-        int c = cg + 8 * k;
-        double x = 0.0;
-        if (r < n) {
-            if (c < n) x = a[(long)r * n + c];
-            else if (c < 2 * n && c - n == r) x = 1.0;
+    for (int i = 0; i < 4; ++i) {
+        int r = rb * 4 + i;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            int c = cb + 32 * k;
+            double x = 0.0;
+            if (r < n) {
+                if (c < n) x = a[(long)r * n + c];
+                else if (c < 2 * n && c - n == r) x = 1.0;
+            }
+            m[i][k] = x;
         }
-        m[k] = x;
     }
+    if (t < 128) used[t] = 0;
+    __syncthreads();
     for (int c = 0; c < n; ++c) {
-        const int owner = c & 7, ck = c >> 3;
-        double mine = 0.0;
+        const int kc = c >> 5;
+        if (cb == (c & 31)) {
 #pragma unroll
-        for (int k = 0; k < 32; ++k)
-            if (k == ck) mine = m[k];
-        if ((t & 7) == owner && r < n) { fcol[r] = mine; pv[r] = (r >= c) ? fabs(mine) : -1.0; pi[r] = r; }
+            for (int i = 0; i < 4; ++i) {
+                int r = rb * 4 + i;
+                double x = 0.0;
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    if (k == kc) x = m[i][k];
+                if (r < n) {
+                    fcol[r] = x;
+                    pv[r] = used[r] ? -1.0 : fabs(x);
+                }
+            }
+        }
         __syncthreads();
-        if (t < 64) {
+        if (t < WAVE) {
             double bv = -1.0;
             int bi = n;
-            for (int q = t; q < n; q += 64) {
+            for (int q = t; q < n; q += WAVE) {
                 double x = pv[q];
                 if (x > bv || (x == bv && q < bi)) { bv = x; bi = q; }
             }
-            for (int off = 32; off > 0; off >>= 1) {
-                double ov = __shfl_xor(bv, off, 64);
-                int oi = __shfl_xor(bi, off, 64);
+            for (int off = WAVE / 2; off > 0; off >>= 1) {
+                double ov = __shfl_xor(bv, off, WAVE);
+                int oi = __shfl_xor(bi, off, WAVE);
                 if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
             }
             if (t == 0) {
-                piv_sh = (bv > 0.0 && isfinite(bv)) ? bi : -1;
-                if (piv_sh < 0) set_flag(flag, 3);
+                int p = (bv > 0.0 && isfinite(bv)) ? bi : -1;
+                piv_sh = p;
+                if (p < 0) set_flag(flag, 3);
+                else { used[p] = 1; pos[p] = c; }
             }
         }
         __syncthreads();
         const int p = piv_sh;
         if (p < 0) return;
-        // swap rows c and p (through LDS), then scale the pivot row
-        if (r == c || r == p) {
+        const double ip = 1.0 / fcol[p];
+        if (rb == (p >> 2)) {
+            const int ip4 = p & 3;
 #pragma unroll
-            for (int k = 0; k < 32; ++k) (r == c ? rowc : rowp)[cg + 8 * k] = m[k];
+            for (int i = 0; i < 4; ++i)
+                if (i == ip4) {
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        m[i][k] = m[i][k] * ip;
+                        prow[cb + 32 * k] = m[i][k];
+                    }
+                }
         }
         __syncthreads();
-        if (p != c) {
-            if (r == c) {
+        double pr[8];
 #pragma unroll
-                for (int k = 0; k < 32; ++k) m[k] = rowp[cg + 8 * k];
-            } else if (r == p) {
+        for (int k = 0; k < 8; ++k) pr[k] = prow[cb + 32 * k];
 #pragma unroll
-                for (int k = 0; k < 32; ++k) m[k] = rowc[cg + 8 * k];
+        for (int i = 0; i < 4; ++i) {
+            int r = rb * 4 + i;
+            if (r < n && r != p) {
+                double f = fcol[r];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) m[i][k] = m[i][k] - f * pr[k];
             }
-        }
-        double piv = (p != c) ? rowp[c] : rowc[c];
-        double ip = 1.0 / piv;
-        if (r == c) {
-#pragma unroll
-            for (int k = 0; k < 32; ++k) { m[k] = m[k] * ip; prow[cg + 8 * k] = m[k]; }
-        }
-        // the multipliers: column c of every row after the swap
-        if (r < n && (t & 7) == owner) {
-            double f = 0.0;
-#pragma unroll
-            for (int k = 0; k < 32; ++k)
-                if (k == ck) f = m[k];
-            fcol[r] = f;
-        }
-        __syncthreads();
-        if (r < n && r != c) {
-            double f = fcol[r];
-#pragma unroll
-            for (int k = 0; k < 32; ++k) m[k] = m[k] - f * prow[cg + 8 * k];
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int k = 0; k < 32; ++k) {
-        int c = cg + 8 * k;
-        if (r < n && c >= n && c < 2 * n) inv[(long)r * n + (c - n)] = m[k];
+    for (int i = 0; i < 4; ++i) {
+        int r = rb * 4 + i;
+        if (r >= n) continue;
+        int row = pos[r];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            int c = cb + 32 * k;
+            if (c >= n && c < 2 * n) inv[(long)row * n + (c - n)] = m[i][k];
+        }
     }
 }
 
@@ -1859,16 +1932,24 @@ void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, hipStream_t
     spgemm_launch<true>(A, B, max_row, C.rp.p, C.ci.p, C.v.p, nullptr, nullptr, s);
 }
 
+static int add_group(const DCsr& A, const DCsr& B) {
+    if (A.max_row < 0 || B.max_row < 0) return 64;
+    return group_for(A.max_row > B.max_row ? A.max_row : B.max_row);
+}
+
 void add_count(const DCsr& A, const DCsr& B, int* cnt, hipStream_t s) {
     if (A.nr <= 0) return;
-    k_add_count<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, B.rp.p, B.ci.p, cnt);
+    int G = add_group(A, B);
+    MGR_DISPATCH_G4(G, (k_add_g<GG, false><<<grid_for(A.nr, GG), TPB, 0, s>>>(
+                           A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p, B.v.p, nullptr, nullptr, nullptr, cnt)));
     MGR_LAUNCH_CHECK();
 }
 
 void add_fill(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s) {
     if (A.nr <= 0) return;
-    k_add_fill<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p, B.v.p, C.rp.p, C.ci.p,
-                                          C.v.p);
+    int G = add_group(A, B);
+    MGR_DISPATCH_G4(G, (k_add_g<GG, true><<<grid_for(A.nr, GG), TPB, 0, s>>>(
+                           A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p, B.v.p, C.rp.p, C.ci.p, C.v.p, nullptr)));
     MGR_LAUNCH_CHECK();
 }
 
@@ -1879,12 +1960,18 @@ void transpose_count(const DCsr& A, int* cnt, hipStream_t s) {
 }
 
 void transpose_fill(const DCsr& A, DCsr& T, int* cursor, hipStream_t s) {
+    if (A.nnz <= 0) return;
+    // scatter into temporaries, then order each row while copying it out
+    DArr<int> tci((size_t)A.nnz, s);
+    DArr<double> tv(A.v.p ? (size_t)A.nnz : 0, s);
     if (A.nr > 0) {
         int G = group_for(A.max_row);
         MGR_DISPATCH_G4(G, (k_transpose_scatter_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(
-                               A.nr, A.rp.p, A.ci.p, A.v.p, cursor, T.ci.p, T.v.p)));
+                               A.nr, A.rp.p, A.ci.p, A.v.p, cursor, tci.p, A.v.p ? tv.p : nullptr)));
     }
-    if (T.nr > 0) k_transpose_sort<<<nblk(T.nr), TPB, 0, s>>>(T.nr, T.rp.p, T.ci.p, T.v.p);
+    if (T.nr > 0)
+        k_transpose_rank<<<grid_for(T.nr, WAVE), TPB, 0, s>>>(T.nr, T.rp.p, tci.p, tv.p, T.ci.p,
+                                                              A.v.p ? T.v.p : nullptr);
     MGR_LAUNCH_CHECK();
 }
 
@@ -1960,7 +2047,9 @@ void interp_count(const DCsr& A, const unsigned char* strong, const int* cf, int
 void interp_fill(const DCsr& A, const unsigned char* strong, const int* cf, const int* cidx, const int* label,
                  DCsr& P, int* flag, hipStream_t s) {
     if (A.nr <= 0) return;
-    int G = group_for(A.max_row);
+    // the row sums run lane by lane through each chunk of G entries, so the
+    // group is sized to the average row, not the longest
+    int G = group_for((int)((A.nnz + A.nr - 1) / A.nr));
     MGR_DISPATCH_G4(G, (k_interp_fill_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(
                            A.nr, A.rp.p, A.ci.p, A.v.p, strong, cf, cidx, label, P.rp.p, P.ci.p, P.v.p, flag)));
     MGR_LAUNCH_CHECK();
