@@ -52,6 +52,13 @@ def time_kernel(fn, stream, reps, flush_buf):
     return statistics.mean(ts), ts
 
 
+def bsr_spmv_bytes(b, nbr, nnzb, s=8):
+    """Algorithmic bytes of one block-CSR SpMV: b x b value blocks + block column
+    indices + block row pointers once, x once, y once."""
+    n = b * nbr
+    return nnzb * (b * b * s + 4) + 4 * (nbr + 1) + 2 * n * 8
+
+
 def kernel_traffic(name):
     """HBM bytes per launch of `name` from the committed rocprofv3 counter summary
     (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None if the summary
@@ -72,9 +79,9 @@ def kernel_traffic(name):
     return int(float(fields["traffic bytes per launch"]))
 
 
-def run_steps(P, s, vals, rhs, precision, steps, warmup):
+def run_steps(P, s, vals, rhs, precision, steps, warmup, **opts):
     import torch
-    solver = P.Solver(s["b"], s["rp"], s["ci"], vals, s["field"], s["levels"], precision=precision)
+    solver = P.Solver(s["b"], s["rp"], s["ci"], vals, s["field"], s["levels"], precision=precision, **opts)
     stream = torch.cuda.current_stream()
     rec = []
     X = info = None
@@ -103,6 +110,8 @@ def main():
     ap.add_argument("--grid", type=int, default=64, help="grid size per axis of the mimetic system")
     ap.add_argument("--comp-steps", type=int, default=2,
                     help="timed steps of the secondary compositional workload (0 = skip)")
+    ap.add_argument("--frac-steps", type=int, default=1,
+                    help="timed steps of the secondary fracturing workload (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not part of "
@@ -177,6 +186,18 @@ def main():
         a64(); a32()
         ta64, _ = time_kernel(a64, stream, 10, flush)
         ta32, _ = time_kernel(a32, stream, 10, flush)
+        # roofline of its FGMRES matvec: block-CSR (4 x 4) SpMV in FP64, an operator
+        # of about 1 GB, four times the Infinity Cache
+        mv = lambda: lib.mgr_matvec(s64._h, 0, ctypes.c_void_p(vv.data_ptr()), ctypes.c_void_p(zz.data_ptr()))
+        mv()
+        t_bsr, _ = time_kernel(mv, stream, 20, flush)
+        nbr2, nnzb2 = len(c2["rp"]) - 1, len(c2["ci"])
+        bb = bsr_spmv_bytes(4, nbr2, nnzb2)
+        comp_roof = {"kernel": "k_bsr_spmv<4, 8> (FGMRES matvec y = A x, 4 x 4 block CSR, FP64)", "bound": "hbm",
+                     "achieved": round(bb / t_bsr / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(bb / t_bsr / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": kernel_traffic("k_bsr_spmv_compositional.md"),
+                     "bytes_per_launch": bb, "avg_launch_us": round(1e6 * t_bsr, 2)}
         comp = {"workload": "compositional_wells_128x128x64", "n": c2["n"], "nnz": int(len(c2["ci"]) * 16),
                 "mgr": "L1 F = components (block-Jacobi), L2 F = wells (Jacobi), coarse pressure AMG",
                 "fp64": {"time_to_tol_s": round(t64, 6), "setup_s": round(statistics.mean(a for a, _, _, _ in r64), 6),
@@ -185,10 +206,44 @@ def main():
                 "fp32": {"time_to_tol_s": round(t32, 6), "setup_s": round(statistics.mean(a for a, _, _, _ in r32), 6),
                          "solve_s": round(statistics.mean(b for _, b, _, _ in r32), 6), "iterations": r32[-1][2],
                          "rel_res_true": r32[-1][3], "apply_ms": round(1e3 * ta32, 4)},
-                "speedup_time_to_tol": round(t64 / t32, 4), "speedup_per_apply": round(ta64 / ta32, 4)}
+                "speedup_time_to_tol": round(t64 / t32, 4), "speedup_per_apply": round(ta64 / ta32, 4),
+                "roofline": comp_roof}
         s64.close()
         s32.close()
-        del c2, v2, b2
+        del c2, v2, b2, vv, zz
+
+    # ---- secondary: the fracturing system (Q1 elasticity on 96^3 nodes + a 96 x 96
+    # planar fracture; MGR_U with an unknown-based AMG V-cycle as F-relaxation)
+    frac = None
+    if args.frac_steps > 0:
+        log("generating fracturing 96^3 ...")
+        f3 = W.fracturing(96, seed=3)
+        v3 = torch.tensor(f3["vals"], device="cuda")
+        b3 = torch.tensor(f3["rhs"], device="cuda")
+        o3 = f3.get("solver_opts", {})
+        f64s, q64, _, _, _ = run_steps(P, f3, v3, b3, 64, args.frac_steps, 1, **o3)
+        f32s, q32, _, _, _ = run_steps(P, f3, v3, b3, 32, args.frac_steps, 1, **o3)
+        t64 = statistics.mean(a + b for a, b, _, _ in q64)
+        t32 = statistics.mean(a + b for a, b, _, _ in q32)
+        vv = torch.randn(f3["n"], dtype=torch.float64, device="cuda")
+        zz = torch.empty_like(vv)
+        a64 = lambda: lib.mgr_apply(f64s._h, ctypes.c_void_p(vv.data_ptr()), ctypes.c_void_p(zz.data_ptr()))
+        a32 = lambda: lib.mgr_apply(f32s._h, ctypes.c_void_p(vv.data_ptr()), ctypes.c_void_p(zz.data_ptr()))
+        a64(); a32()
+        ta64, _ = time_kernel(a64, stream, 5, flush)
+        ta32, _ = time_kernel(a32, stream, 5, flush)
+        frac = {"workload": "fracturing_96x96x96", "n": f3["n"], "nnz": int(len(f3["ci"]) * 9),
+                "mgr": "F = displacements (unknown-based AMG V(2,2) F-relaxation), C = fracture pressures -> AMG",
+                "fp64": {"time_to_tol_s": round(t64, 6), "setup_s": round(statistics.mean(a for a, _, _, _ in q64), 6),
+                         "solve_s": round(statistics.mean(b for _, b, _, _ in q64), 6), "iterations": q64[-1][2],
+                         "rel_res_true": q64[-1][3], "apply_ms": round(1e3 * ta64, 4)},
+                "fp32": {"time_to_tol_s": round(t32, 6), "setup_s": round(statistics.mean(a for a, _, _, _ in q32), 6),
+                         "solve_s": round(statistics.mean(b for _, b, _, _ in q32), 6), "iterations": q32[-1][2],
+                         "rel_res_true": q32[-1][3], "apply_ms": round(1e3 * ta32, 4)},
+                "speedup_time_to_tol": round(t64 / t32, 4), "speedup_per_apply": round(ta64 / ta32, 4)}
+        f64s.close()
+        f32s.close()
+        del f3, v3, b3, vv, zz
 
     # ---- FP64 oracle on the machine's host cores (bounded sample: one full setup + solve of this workload)
     cpu = None
@@ -248,6 +303,7 @@ def main():
                      "traffic": kernel_traffic("k_spmv_fgmres_mimetic64.md"),
                      "bytes_per_launch": nbytes, "avg_launch_us": round(1e6 * t_spmv, 2)},
         "secondary_compositional": comp,
+        "secondary_fracturing": frac,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -31,8 +31,19 @@ void rowblocks(int nr, long nnz, const int* rp, int* blk, hipStream_t s);
 
 template <typename T>
 inline SpOp<T> view(const DCsr& A);
+// The row-block partition of an operator is made on its first use by an SpMV
+// (on the operator's stream), so setup temporaries never pay for one.
+inline void ensure_rowblocks(const DCsr& A) {
+    if (A.blk.p || A.nr <= 0) return;
+    DCsr& M = const_cast<DCsr&>(A);
+    M.nblk = rowblock_count(M.nnz);
+    M.blk.alloc((size_t)M.nblk + 1, M.rp.s);
+    rowblocks(M.nr, M.nnz, M.rp.p, M.blk.p, M.rp.s);
+}
+
 template <>
 inline SpOp<double> view<double>(const DCsr& A) {
+    ensure_rowblocks(A);
     SpOp<double> o;
     o.nr = A.nr; o.nc = A.nc; o.nnz = A.nnz; o.rp = A.rp.p; o.ci = A.ci.p; o.v = A.v.p;
     o.blk = A.blk.p; o.nblk = A.nblk;
@@ -40,6 +51,7 @@ inline SpOp<double> view<double>(const DCsr& A) {
 }
 template <>
 inline SpOp<float> view<float>(const DCsr& A) {
+    ensure_rowblocks(A);
     SpOp<float> o;
     o.nr = A.nr; o.nc = A.nc; o.nnz = A.nnz; o.rp = A.rp.p; o.ci = A.ci.p; o.v = A.vf.p;
     o.blk = A.blk.p; o.nblk = A.nblk;

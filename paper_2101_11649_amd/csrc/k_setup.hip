@@ -814,7 +814,7 @@ __global__ void k_pmis_update(int n, const int* __restrict__ srp, const int* __r
     if (cf[i] != 0) return;
     for (int q = srp[i]; q < srp[i + 1]; ++q)
         if (newc[sci[q]]) { cf[i] = -1; return; }
-    atomicAdd(undecided, 1);
+    if (undecided) atomicAdd(undecided, 1);
 }
 
 __global__ void k_is_c(int n, const int* __restrict__ cf, int* __restrict__ isC) {
@@ -1422,16 +1422,20 @@ __global__ __launch_bounds__(TPB) void k_l1_dinv_g(int n, const int* __restrict_
     }
 }
 
+// Scatter of A's entries into the rows of its transpose: row j of the
+// transpose has cnt[j] slots from trp[j]; each entry takes one by decrementing
+// cnt[j] (which ends at zero), so the order inside a row is arbitrary.
 template <int G>
 __global__ __launch_bounds__(TPB) void k_transpose_scatter_g(int nr, const int* __restrict__ rp,
                                                              const int* __restrict__ ci, const double* __restrict__ v,
-                                                             int* __restrict__ cursor, int* __restrict__ tci,
-                                                             double* __restrict__ tv) {
+                                                             const int* __restrict__ trp, int* __restrict__ cnt,
+                                                             int* __restrict__ tci, double* __restrict__ tv) {
     Grp<G> g;
     int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
     if (i >= nr) return;
     for (int p = rp[i] + g.gl; p < rp[i + 1]; p += G) {
-        int q = atomicAdd(&cursor[ci[p]], 1);
+        int j = ci[p];
+        int q = trp[j] + atomicSub(&cnt[j], 1) - 1;
         tci[q] = i;
         if (tv) tv[q] = v[p];
     }
@@ -1959,7 +1963,7 @@ void transpose_count(const DCsr& A, int* cnt, hipStream_t s) {
     MGR_LAUNCH_CHECK();
 }
 
-void transpose_fill(const DCsr& A, DCsr& T, int* cursor, hipStream_t s) {
+void transpose_fill(const DCsr& A, DCsr& T, int* cnt, hipStream_t s) {
     if (A.nnz <= 0) return;
     // scatter into temporaries, then order each row while copying it out
     DArr<int> tci((size_t)A.nnz, s);
@@ -1967,7 +1971,7 @@ void transpose_fill(const DCsr& A, DCsr& T, int* cursor, hipStream_t s) {
     if (A.nr > 0) {
         int G = group_for(A.max_row);
         MGR_DISPATCH_G4(G, (k_transpose_scatter_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(
-                               A.nr, A.rp.p, A.ci.p, A.v.p, cursor, tci.p, A.v.p ? tv.p : nullptr)));
+                               A.nr, A.rp.p, A.ci.p, A.v.p, T.rp.p, cnt, tci.p, A.v.p ? tv.p : nullptr)));
     }
     if (T.nr > 0)
         k_transpose_rank<<<grid_for(T.nr, WAVE), TPB, 0, s>>>(T.nr, T.rp.p, tci.p, tv.p, T.ci.p,

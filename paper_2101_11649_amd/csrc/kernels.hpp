@@ -60,7 +60,9 @@ void add_count(const DCsr& A, const DCsr& B, int* cnt, hipStream_t s);
 void add_fill(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s);
 void negate(double* v, long n, hipStream_t s);
 void transpose_count(const DCsr& A, int* cnt, hipStream_t s);
-void transpose_fill(const DCsr& A, DCsr& T, int* cursor, hipStream_t s);
+// T's row pointers must be the exclusive scan of cnt (the column counts of A);
+// cnt is consumed (decremented to zero).
+void transpose_fill(const DCsr& A, DCsr& T, int* cnt, hipStream_t s);
 
 // AMG setup
 // strength flags per entry and the number of strong entries per row (scnt)

@@ -50,9 +50,12 @@ struct Slots {
         return p;
     }
     int* flag() { return reinterpret_cast<int*>(d.p + FLAG); }
+    // Reads every slot back; the value slots are then cleared on the stream, so
+    // slots handed out by take() start at zero.
     void sync(const char* what) {
         MGR_HIP(hipMemcpyAsync(h, d.p, sizeof(long long) * N, hipMemcpyDeviceToHost, s));
         MGR_HIP(hipStreamSynchronize(s));
+        if (next > 0) fill_ll(d.p, 0, next, s);
         next = 0;
         int f = (int)(h[FLAG] & 0xffffffffLL);
         if (f != 0) {
@@ -66,12 +69,6 @@ struct Slots {
     }
     long long val(const long long* p) const { return h[p - d.p]; }
 };
-
-static void make_rowblocks(DCsr& C, hipStream_t s) {
-    C.nblk = rowblock_count(C.nnz);
-    C.blk.alloc((size_t)C.nblk + 1, s);
-    rowblocks(C.nr, C.nnz, C.rp.p, C.blk.p, s);
-}
 
 // Two-phase construction from row counts: begin() scans asynchronously, the
 // caller syncs the slots, finish() allocates the entries.
@@ -98,7 +95,6 @@ static void csr_finish(const Pend& p, Slots& S) {
     C.max_row = (int)S.val(p.slot + 1);
     C.ci.alloc((size_t)(C.nnz > 0 ? C.nnz : 1), S.s);
     C.v.alloc((size_t)(C.nnz > 0 ? C.nnz : 1), S.s);
-    make_rowblocks(C, S.s);
 }
 
 static DCsr csr_from_counts(int nr, int nc, const int* counts, Slots& S, const char* what) {
@@ -127,7 +123,6 @@ static void spgemm_begin(Spgemm& j, const DCsr& A, const DCsr& B, DCsr& C, Slots
     j.C = &C;
     j.cnt.alloc((size_t)A.nr + 1, S.s);
     j.lr = S.take(1);
-    fill_ll(j.lr, 0, 1, S.s);
     spgemm_count(A, B, A.max_row, j.cnt.p, reinterpret_cast<int*>(j.lr), S.s);
     j.pend = csr_begin(C, A.nr, B.nc, j.cnt.p, S);
 }
@@ -177,10 +172,7 @@ static Transp csr_transpose_begin(const DCsr& A, DCsr& T, Slots& S) {
     scan_async(cnt.p, T.rp.p, A.nc, t.slot, s);
     T.ci.alloc((size_t)(A.nnz > 0 ? A.nnz : 1), s);
     T.v.alloc((size_t)(A.nnz > 0 ? A.nnz : 1), s);
-    DArr<int> cursor((size_t)A.nc + 1, s);
-    MGR_HIP(hipMemcpyAsync(cursor.p, T.rp.p, sizeof(int) * ((size_t)A.nc + 1), hipMemcpyDeviceToDevice, s));
-    transpose_fill(A, T, cursor.p, s);
-    make_rowblocks(T, s);
+    transpose_fill(A, T, cnt.p, s);   // consumes the column counts
     return t;
 }
 
@@ -203,7 +195,6 @@ static DCsr csr_copy(const DCsr& A, hipStream_t s) {
         MGR_HIP(hipMemcpyAsync(C.v.p, A.v.p, sizeof(double) * A.nnz, hipMemcpyDeviceToDevice, s));
     }
     C.max_row = A.max_row;
-    make_rowblocks(C, s);
     return C;
 }
 
@@ -249,7 +240,6 @@ constexpr long AMG_COMPOSE_NNZ = 1L << 20;
 static void amg_compose_begin(AmgLevel& L, Slots& S) {
     hipStream_t s = S.s;
     L.bad = S.take(1);
-    fill_ll(L.bad, 0, 1, s);
     int* bad = reinterpret_cast<int*>(L.bad);
     L.W = csr_copy(L.A, s);
     compose_w(L.A, L.dinv.p, L.W.v.p, bad, s);
@@ -258,7 +248,6 @@ static void amg_compose_begin(AmgLevel& L, Slots& S) {
     compose_sub(L.R, L.RA, nullptr, L.dinv.p, L.RA.v.p, bad, s);
     L.G = std::move(L.RA);
     concat_rows(L.W, L.Q, L.WQ, s);
-    make_rowblocks(L.WQ, s);
 }
 
 static void amg_compose_finish(AmgLevel& L, Slots& S) {
@@ -324,9 +313,10 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
             if (total > 100000) throw Error(MGR_ERR_UNSUPPORTED, "PMIS did not terminate");
             long long* und = S.take(1);
             for (int r = 0; r < batch; ++r) {
-                fill_ll(und, 0, 1, s);
                 pmis_select(n, srp.p, sci.p, trp.p, tci.p, w.p, cf.p, newc.p, s);
-                pmis_update(n, srp.p, sci.p, newc.p, cf.p, reinterpret_cast<int*>(und), s);
+                // the undecided points are counted after the last round of the batch
+                pmis_update(n, srp.p, sci.p, newc.p, cf.p, r + 1 == batch ? reinterpret_cast<int*>(und) : nullptr,
+                            s);
             }
             // speculative: C numbering and interpolation row counts for this state
             cf_is_c(n, cf.p, isC.p, s);
@@ -454,7 +444,6 @@ static void amg_make_trans(Amg& H, Slots& S) {
             csr_transpose_finish(t2, S);
             csr_transpose_finish(t3, S);
             concat_rows(Wt, Gt, L.WGt, s);
-            make_rowblocks(L.WGt, s);
             if (H.have_float) {
                 make_float(L.Qt, s);
                 make_float(L.WGt, s);
@@ -575,13 +564,11 @@ static Sched level_schedule(const DCsr& T, bool fwd, Slots& S) {
     for (int it = 0;; it += 8) {
         if (it > 8 * (n + 8)) throw Error(MGR_ERR_UNSUPPORTED, "level analysis did not converge");
         long long* ch = S.take(1);
-        fill_ll(ch, 0, 1, s);
         for (int q = 0; q < 8; ++q) level_sweep(T, fwd, lev.p, reinterpret_cast<int*>(ch), s);
         S.sync("level analysis");
         if (S.val(ch) == 0) break;
     }
     long long* mx = S.take(1);
-    fill_ll(mx, 0, 1, s);
     level_max(n, lev.p, reinterpret_cast<int*>(mx), s);
     S.sync("level analysis");
     int nlev = (int)(S.val(mx) & 0xffffffffLL) + 1;
@@ -1243,7 +1230,6 @@ static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nle
     } else {
         bsr_expand(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, c.Av.p, c.A0.rp.p, c.A0.ci.p, c.A0.v.p, s);
     }
-    make_rowblocks(c.A0, s);
     c.A0.max_row = max_row_len(c.A0, s);
     DArr<int> fld((size_t)c.n, s), blk((size_t)c.n, s);
     MGR_HIP(hipMemcpyAsync(fld.p, field, sizeof(int) * c.n, hipMemcpyDeviceToDevice, s));
