@@ -71,6 +71,12 @@ void jacobi_sweep(const SpOp<T>& A, const T* dinv, const T* b, const T* x, T* y,
 // x = dinv .* b ; r = b - A x
 template <typename T>
 void presmooth(const SpOp<T>& A, const T* dinv, const T* b, T* x, T* r, hipStream_t s);
+// the same with bd = dinv .* b formed beforehand (one gathered vector per entry)
+template <typename T>
+void presmooth_scaled(const SpOp<T>& A, const T* bd, const T* b, T* x, T* r, hipStream_t s);
+// y = A x and yd = dsc .* y (a restriction that also forms the next level's D^-1 b)
+template <typename T>
+void restrict_scaled(const SpOp<T>& A, const T* x, const T* dsc, T* y, T* yd, hipStream_t s);
 // block-CSR y = alpha A x + beta w (FP64)
 void bsr_spmv(int bsize, int nbr, const int* rp, const int* ci, const double* v, long nnzb, const double* x,
               const double* w, double* y, double alpha, double beta, hipStream_t s);
@@ -98,6 +104,10 @@ int krylov_parts(long n);
 // out[i] = <V_i, w> for i < nvec (V column-major with leading dimension ldv);
 // part needs nvec * KRYLOV_PARTS doubles.
 void mdot(long n, const double* V, long ldv, int nvec, const double* w, double* part, double* out, hipStream_t s);
+// w -= sum_i h[i] V_i, then out[i] = <V_i, w_new>, in one pass over V; only for
+// nvec <= 16 (returns false otherwise, and does nothing).
+bool maxpy_mdot(long n, const double* V, long ldv, int nvec, const double* h, double* w, double* part,
+                double* out, hipStream_t s);
 // w -= hscale * sum_i h[i] V_i; if norm2_out, *norm2_out = ||w_new||^2.
 void maxpy(long n, const double* V, long ldv, int nvec, const double* h, double hscale, double* w, double* part,
            double* norm2_out, hipStream_t s);

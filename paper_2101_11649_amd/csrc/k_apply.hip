@@ -66,6 +66,28 @@ struct PreOp {
     }
 };
 
+// RestrictOp  y = A x  and  yd = dsc .* y  (the next level's D^-1 b)
+template <typename T>
+struct RestrictOp {
+    const T* x; const T* dsc; T* y; T* yd;
+    __device__ T xval(int c) const { return x[c]; }
+    __device__ void done(int r, T s) const {
+        y[r] = s;
+        yd[r] = dsc[r] * s;
+    }
+};
+
+// PreOpD  x = bd,  r = b - A bd  with bd = dinv .* b already formed
+template <typename T>
+struct PreOpD {
+    const T* bd; const T* b; T* x; T* r_;
+    __device__ T xval(int c) const { return bd[c]; }
+    __device__ void done(int r, T s) const {
+        x[r] = bd[r];
+        r_[r] = b[r] - s;
+    }
+};
+
 template <typename MT, int TAG, class Op>
 __global__ __launch_bounds__(TPB) void k_spmv_stream(const int* __restrict__ blk, const int* __restrict__ rp,
                                                      const int* __restrict__ ci, const MT* __restrict__ v, Op op) {
@@ -298,6 +320,54 @@ __global__ __launch_bounds__(TPB) void k_mdot(long n, const double* __restrict__
     }
 }
 
+// First Gram-Schmidt correction fused with the products of the second pass
+// (nvec <= NV <= 16, where the row of V stays in registers): w -= sum_i h[i] V_i,
+// then part[i * gridDim.x + block] = partial of <V_i, w_new>.  The per-row sum
+// and the per-thread accumulations run in the same order as the separate
+// maxpy and mdot kernels.
+template <int NV>
+__global__ __launch_bounds__(TPB) void k_maxpy_mdot(long n, const double* __restrict__ V, long ldv, int nvec,
+                                                    const double* __restrict__ h, double* __restrict__ w,
+                                                    double* __restrict__ part) {
+    __shared__ double hs[NV];
+    __shared__ double sh[NV][TPB / WAVE];
+    if ((int)threadIdx.x < nvec) hs[threadIdx.x] = h[threadIdx.x];
+    __syncthreads();
+    double acc[NV];
+#pragma unroll
+    for (int t = 0; t < NV; ++t) acc[t] = 0.0;
+    long stride = (long)gridDim.x * TPB;
+    for (long r = (long)blockIdx.x * TPB + threadIdx.x; r < n; r += stride) {
+        double vv[NV];
+        double sum = 0.0;
+#pragma unroll
+        for (int t = 0; t < NV; ++t) {
+            vv[t] = (t < nvec) ? V[(long)t * ldv + r] : 0.0;
+            if (t < nvec) sum += hs[t] * vv[t];
+        }
+        double wn = w[r] - sum;
+        w[r] = wn;
+#pragma unroll
+        for (int t = 0; t < NV; ++t)
+            if (t < nvec) acc[t] += vv[t] * wn;
+    }
+    int wid = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int t = 0; t < NV; ++t) {
+        if (t < nvec) {
+            double v = group_sum<double>(acc[t], WAVE);
+            if (lane == 0) sh[t][wid] = v;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nvec) {
+        double sacc = 0.0;
+#pragma unroll
+        for (int q = 0; q < TPB / WAVE; ++q) sacc += sh[threadIdx.x][q];
+        part[(long)threadIdx.x * gridDim.x + blockIdx.x] = sacc;
+    }
+}
+
 // out[i] = sum over the nparts partials of vector i, in a fixed tree order.
 __global__ __launch_bounds__(TPB) void k_reduce_parts(int nparts, const double* __restrict__ part,
                                                       double* __restrict__ out) {
@@ -436,6 +506,24 @@ void presmooth(const SpOp<T>& A, const T* dinv, const T* b, T* x, T* r, hipStrea
     MGR_LAUNCH_CHECK();
 }
 
+template <typename T>
+void presmooth_scaled(const SpOp<T>& A, const T* bd, const T* b, T* x, T* r, hipStream_t s) {
+    if (A.nr <= 0) return;
+    if (!A.blk) throw Error(-1, "presmooth: operator without row blocks");
+    PreOpD<T> op{bd, b, x, r};
+    k_spmv_stream<T, 0><<<A.nblk, TPB, 0, s>>>(A.blk, A.rp, A.ci, A.v, op);
+    MGR_LAUNCH_CHECK();
+}
+
+template <typename T>
+void restrict_scaled(const SpOp<T>& A, const T* x, const T* dsc, T* y, T* yd, hipStream_t s) {
+    if (A.nr <= 0) return;
+    if (!A.blk) throw Error(-1, "restrict: operator without row blocks");
+    RestrictOp<T> op{x, dsc, y, yd};
+    k_spmv_stream<T, 0><<<A.nblk, TPB, 0, s>>>(A.blk, A.rp, A.ci, A.v, op);
+    MGR_LAUNCH_CHECK();
+}
+
 void bsr_spmv(int bsize, int nbr, const int* rp, const int* ci, const double* v, long nnzb, const double* x,
               const double* w, double* y, double alpha, double beta, hipStream_t s) {
     if (nbr <= 0) return;
@@ -533,6 +621,17 @@ void mdot(long n, const double* V, long ldv, int nvec, const double* w, double* 
     MGR_LAUNCH_CHECK();
 }
 
+bool maxpy_mdot(long n, const double* V, long ldv, int nvec, const double* h, double* w, double* part,
+                double* out, hipStream_t s) {
+    if (nvec <= 0 || nvec > 16) return false;
+    int np = krylov_parts(n);
+    if (nvec <= 8) k_maxpy_mdot<8><<<np, TPB, 0, s>>>(n, V, ldv, nvec, h, w, part);
+    else k_maxpy_mdot<16><<<np, TPB, 0, s>>>(n, V, ldv, nvec, h, w, part);
+    k_reduce_parts<<<nvec, TPB, 0, s>>>(np, part, out);
+    MGR_LAUNCH_CHECK();
+    return true;
+}
+
 void maxpy(long n, const double* V, long ldv, int nvec, const double* h, double hscale, double* w, double* part,
            double* norm2_out, hipStream_t s) {
     if (nvec > 64) throw Error(-1, "maxpy: at most 64 vectors");
@@ -575,6 +674,12 @@ template void jacobi_sweep<double>(const SpOp<double>&, const double*, const dou
 template void jacobi_sweep<float>(const SpOp<float>&, const float*, const float*, const float*, float*, hipStream_t);
 template void presmooth<double>(const SpOp<double>&, const double*, const double*, double*, double*, hipStream_t);
 template void presmooth<float>(const SpOp<float>&, const float*, const float*, float*, float*, hipStream_t);
+template void presmooth_scaled<double>(const SpOp<double>&, const double*, const double*, double*, double*,
+                                       hipStream_t);
+template void presmooth_scaled<float>(const SpOp<float>&, const float*, const float*, float*, float*, hipStream_t);
+template void restrict_scaled<double>(const SpOp<double>&, const double*, const double*, double*, double*,
+                                      hipStream_t);
+template void restrict_scaled<float>(const SpOp<float>&, const float*, const float*, float*, float*, hipStream_t);
 template void dense_gemv<double, double>(int, const double*, const double*, double*, hipStream_t);
 template void dense_gemv<float, float>(int, const float*, const float*, float*, hipStream_t);
 template void dense_gemv<float, double>(int, const float*, const double*, float*, hipStream_t);

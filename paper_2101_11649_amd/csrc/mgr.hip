@@ -217,8 +217,8 @@ struct AmgLevel {
     DArr<int> cf, label;
     DArr<double> dinv;
     DArr<float> dinvf;
-    DArr<double> rd, td, bd, xd;
-    DArr<float> rf, tf, bf, xf;
+    DArr<double> rd, td, bd, xd, sd;   // sd = D^-1 b, formed by the restriction from the level above
+    DArr<float> rf, tf, bf, xf, sf;
 };
 
 struct Amg {
@@ -385,7 +385,11 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
         AmgLevel& L = H.lv[l];
         L.rd.alloc((size_t)L.n + 1, s);
         L.td.alloc((size_t)L.n + 1, s);
-        if (l > 0) { L.bd.alloc((size_t)L.n + 1, s); L.xd.alloc((size_t)L.n + 1, s); }
+        if (l > 0) {
+            L.bd.alloc((size_t)L.n + 1, s);
+            L.xd.alloc((size_t)L.n + 1, s);
+            L.sd.alloc((size_t)L.n + 1, s);
+        }
     }
     S.sync("AMG coarsest inverse");
     for (size_t l = 0; l + 1 < H.lv.size(); ++l)
@@ -417,7 +421,11 @@ static void amg_make_float(Amg& H, hipStream_t s) {
         if (H.have_trans && L.AT.nr && !L.composed) make_float(L.AT, s);
         L.rf.alloc((size_t)L.n + 1, s);
         L.tf.alloc((size_t)L.n + 1, s);
-        if (l > 0) { L.bf.alloc((size_t)L.n + 1, s); L.xf.alloc((size_t)L.n + 1, s); }
+        if (l > 0) {
+            L.bf.alloc((size_t)L.n + 1, s);
+            L.xf.alloc((size_t)L.n + 1, s);
+            L.sf.alloc((size_t)L.n + 1, s);
+        }
     }
     long nn = (long)H.nc * H.nc;
     H.cinvf.alloc((size_t)nn + 1, s);
@@ -475,6 +483,7 @@ template <> struct Prec<double> {
     static double* t(AmgLevel& L) { return L.td.p; }
     static double* b(AmgLevel& L) { return L.bd.p; }
     static double* x(AmgLevel& L) { return L.xd.p; }
+    static double* sb(AmgLevel& L) { return L.sd.p; }
     static const double* dinv(AmgLevel& L) { return L.dinv.p; }
     static const double* cinv(Amg& H, bool tr) { return tr ? H.cinvT.p : H.cinv.p; }
 };
@@ -483,15 +492,17 @@ template <> struct Prec<float> {
     static float* t(AmgLevel& L) { return L.tf.p; }
     static float* b(AmgLevel& L) { return L.bf.p; }
     static float* x(AmgLevel& L) { return L.xf.p; }
+    static float* sb(AmgLevel& L) { return L.sf.p; }
     static const float* dinv(AmgLevel& L) { return L.dinvf.p; }
     static const float* cinv(Amg& H, bool tr) { return tr ? H.cinvTf.p : H.cinvf.p; }
 };
 
 // V(nu_pre, nu_post) cycle from x = 0 with L1-Jacobi smoothing; the transposed
 // cycle uses A^T on every level, swaps the sweep counts and applies the
-// transposed coarsest inverse (the exact adjoint of the forward cycle).
+// transposed coarsest inverse (the exact adjoint of the forward cycle).  bd,
+// when given, is D^-1 b of this level (formed by the restriction above it).
 template <typename T>
-static void amg_vcycle(Amg& H, int k, const T* b, T* x, bool tr, hipStream_t s) {
+static void amg_vcycle(Amg& H, int k, const T* b, T* x, bool tr, hipStream_t s, const T* bd = nullptr) {
     AmgLevel& L = H.lv[k];
     int n = L.n;
     if (k + 1 == (int)H.lv.size()) {
@@ -514,7 +525,8 @@ static void amg_vcycle(Amg& H, int k, const T* b, T* x, bool tr, hipStream_t s) 
     T* t = Prec<T>::t(L);
     int npre = tr ? H.nu_post : H.nu_pre, npost = tr ? H.nu_pre : H.nu_post;
     if (npre >= 1) {
-        presmooth<T>(A, dinv, b, x, r, s);
+        if (bd) presmooth_scaled<T>(A, bd, b, x, r, s);
+        else presmooth<T>(A, dinv, b, x, r, s);
         if (npre > 1) {
             for (int q = 1; q < npre; ++q) {
                 jacobi_sweep<T>(A, dinv, b, x, t, s);
@@ -529,8 +541,15 @@ static void amg_vcycle(Amg& H, int k, const T* b, T* x, bool tr, hipStream_t s) 
     AmgLevel& Lc = H.lv[k + 1];
     T* bc = Prec<T>::b(Lc);
     T* xc = Prec<T>::x(Lc);
-    spmv<T, T, T, T, T>(view<T>(L.R), r, (const T*)nullptr, INT_MAX, (const T*)nullptr, bc, T(1), T(0), s);
-    amg_vcycle<T>(H, k + 1, bc, xc, tr, s);
+    // a plain (not composed, not coarsest) next level gets D^-1 b_c from the restriction
+    if (npre >= 1 && !Lc.composed && k + 2 < (int)H.lv.size()) {
+        T* sc = Prec<T>::sb(Lc);
+        restrict_scaled<T>(view<T>(L.R), r, Prec<T>::dinv(Lc), bc, sc, s);
+        amg_vcycle<T>(H, k + 1, bc, xc, tr, s, sc);
+    } else {
+        spmv<T, T, T, T, T>(view<T>(L.R), r, (const T*)nullptr, INT_MAX, (const T*)nullptr, bc, T(1), T(0), s);
+        amg_vcycle<T>(H, k + 1, bc, xc, tr, s);
+    }
     SpOp<T> P = view<T>(L.P);
     if (npost == 0) {
         spmv<T, T, T, T, T>(P, xc, (const T*)nullptr, INT_MAX, x, x, T(1), T(1), s);
@@ -1150,8 +1169,10 @@ static int fgmres(Ctx& c, bool tr, const double* b, double* x, mgr_solve_info* i
             matvec(c, tr, zj, nullptr, w, 1.0, 0.0);
             // classical Gram-Schmidt, twice; then w /= ||w|| on the device
             mdot(n, V, n, j + 1, w, c.part.p, hb, s);
-            maxpy(n, V, n, j + 1, hb, 1.0, w, c.part.p, nullptr, s);
-            mdot(n, V, n, j + 1, w, c.part.p, hb + 64, s);
+            if (!maxpy_mdot(n, V, n, j + 1, hb, w, c.part.p, hb + 64, s)) {
+                maxpy(n, V, n, j + 1, hb, 1.0, w, c.part.p, nullptr, s);
+                mdot(n, V, n, j + 1, w, c.part.p, hb + 64, s);
+            }
             maxpy(n, V, n, j + 1, hb + 64, 1.0, w, c.part.p, hb + 128, s);
             scale_by_norm(n, hb + 128, w, s);
             MGR_HIP(hipMemcpyAsync(c.hpin + (size_t)Ctx::HROW * j, hb, sizeof(double) * 129, hipMemcpyDeviceToHost,
