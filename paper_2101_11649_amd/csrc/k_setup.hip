@@ -343,11 +343,82 @@ __global__ void k_frelax_len(int nF, const int* __restrict__ bnum, const int* __
     len[k] = bstart[b + 1] - bstart[b];
 }
 
-// Gauss-Jordan inverse with partial pivoting (ties to the lower row): scale the
-// pivot row by 1/pivot, then subtract f times it from every other row.  On a
-// failure (block larger than 4, zero or non-finite pivot) the flag is raised
-// and the rows are still written, with valid column indices and zero values,
-// so that no later kernel reads an unwritten index.
+// Inverse of one BS x BS diagonal block by Gauss-Jordan with partial pivoting
+// (ties keep the row with the lower index): scale the pivot row by 1/pivot,
+// then subtract f times it from every other row.  Every index is static so the
+// block stays in registers.  Returns false on a zero or non-finite pivot.
+template <int BS>
+__device__ inline bool frelax_block_inverse(int s0, const int* __restrict__ arp, const int* __restrict__ aci,
+                                            const double* __restrict__ av, double (&e)[BS][BS]) {
+    double a[BS][BS];
+#pragma unroll
+    for (int r = 0; r < BS; ++r)
+#pragma unroll
+        for (int c = 0; c < BS; ++c) { a[r][c] = 0.0; e[r][c] = (r == c) ? 1.0 : 0.0; }
+#pragma unroll
+    for (int r = 0; r < BS; ++r)
+        for (int p = arp[s0 + r]; p < arp[s0 + r + 1]; ++p) {
+            int c = aci[p] - s0;
+            double v = av[p];
+#pragma unroll
+            for (int cc = 0; cc < BS; ++cc)
+                if (c == cc) a[r][cc] = v;
+        }
+#pragma unroll
+    for (int c = 0; c < BS; ++c) {
+        int pv = c;
+        double best = fabs(a[c][c]);
+#pragma unroll
+        for (int r = c + 1; r < BS; ++r)
+            if (fabs(a[r][c]) > best) { best = fabs(a[r][c]); pv = r; }
+        if (!(best > 0.0) || !isfinite(best)) return false;
+#pragma unroll
+        for (int r = c + 1; r < BS; ++r)
+            if (r == pv)
+#pragma unroll
+                for (int k = 0; k < BS; ++k) {
+                    double x = a[c][k]; a[c][k] = a[r][k]; a[r][k] = x;
+                    x = e[c][k]; e[c][k] = e[r][k]; e[r][k] = x;
+                }
+        double ip = 1.0 / a[c][c];
+#pragma unroll
+        for (int k = 0; k < BS; ++k) { a[c][k] = a[c][k] * ip; e[c][k] = e[c][k] * ip; }
+#pragma unroll
+        for (int r = 0; r < BS; ++r) {
+            if (r == c) continue;
+            double f = a[r][c];
+#pragma unroll
+            for (int k = 0; k < BS; ++k) {
+                a[r][k] = a[r][k] - f * a[c][k];
+                e[r][k] = e[r][k] - f * e[c][k];
+            }
+        }
+    }
+    return true;
+}
+
+template <int BS>
+__device__ inline void frelax_block(int s0, const int* __restrict__ arp, const int* __restrict__ aci,
+                                    const double* __restrict__ av, const int* __restrict__ mrp, int* __restrict__ mci,
+                                    double* __restrict__ mv, int* __restrict__ flag) {
+    double e[BS][BS];
+    bool ok = frelax_block_inverse<BS>(s0, arp, aci, av, e);
+    if (!ok) set_flag(flag, 3);
+#pragma unroll
+    for (int r = 0; r < BS; ++r) {
+        int o = mrp[s0 + r];
+#pragma unroll
+        for (int c = 0; c < BS; ++c) {
+            mci[o + c] = s0 + c;
+            mv[o + c] = ok ? e[r][c] : 0.0;
+        }
+    }
+}
+
+// M = block-diagonal inverse of A_FF over the blocks [bstart[t], bstart[t+1]).
+// On a failure (block larger than 4, zero or non-finite pivot) the flag is
+// raised and the rows are still written, with valid column indices and zero
+// values, so that no later kernel reads an unwritten index.
 __global__ void k_frelax_fill(int nb, const int* __restrict__ bstart, const int* __restrict__ arp,
                               const int* __restrict__ aci, const double* __restrict__ av,
                               const int* __restrict__ mrp, int* __restrict__ mci, double* __restrict__ mv,
@@ -355,49 +426,21 @@ __global__ void k_frelax_fill(int nb, const int* __restrict__ bstart, const int*
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nb) return;
     int s0 = bstart[t], bs = bstart[t + 1] - s0;
-    bool ok = bs <= 4;
-    if (!ok) set_flag(flag, 6);
-    double a[16], e[16];
-    if (ok) {
-        for (int r = 0; r < bs; ++r)
-            for (int c = 0; c < bs; ++c) { a[r * bs + c] = 0.0; e[r * bs + c] = (r == c) ? 1.0 : 0.0; }
-        for (int r = 0; r < bs; ++r)
-            for (int p = arp[s0 + r]; p < arp[s0 + r + 1]; ++p) {
-                int c = aci[p] - s0;
-                if (c >= 0 && c < bs) a[r * bs + c] = av[p];
-            }
-        for (int c = 0; c < bs && ok; ++c) {
-            int pv = c;
-            double best = fabs(a[c * bs + c]);
-            for (int r = c + 1; r < bs; ++r)
-                if (fabs(a[r * bs + c]) > best) { best = fabs(a[r * bs + c]); pv = r; }
-            if (!(best > 0.0) || !isfinite(best)) {
-                set_flag(flag, 3);
-                ok = false;
-                break;
-            }
-            if (pv != c)
-                for (int k = 0; k < bs; ++k) {
-                    double x = a[c * bs + k]; a[c * bs + k] = a[pv * bs + k]; a[pv * bs + k] = x;
-                    x = e[c * bs + k]; e[c * bs + k] = e[pv * bs + k]; e[pv * bs + k] = x;
-                }
-            double ip = 1.0 / a[c * bs + c];
-            for (int k = 0; k < bs; ++k) { a[c * bs + k] = a[c * bs + k] * ip; e[c * bs + k] = e[c * bs + k] * ip; }
+    switch (bs) {
+        case 1: frelax_block<1>(s0, arp, aci, av, mrp, mci, mv, flag); break;
+        case 2: frelax_block<2>(s0, arp, aci, av, mrp, mci, mv, flag); break;
+        case 3: frelax_block<3>(s0, arp, aci, av, mrp, mci, mv, flag); break;
+        case 4: frelax_block<4>(s0, arp, aci, av, mrp, mci, mv, flag); break;
+        default: {
+            // larger blocks are not supported: flagged, structure written with zeros
+            set_flag(flag, 6);
             for (int r = 0; r < bs; ++r) {
-                if (r == c) continue;
-                double f = a[r * bs + c];
-                for (int k = 0; k < bs; ++k) {
-                    a[r * bs + k] = a[r * bs + k] - f * a[c * bs + k];
-                    e[r * bs + k] = e[r * bs + k] - f * e[c * bs + k];
+                int o = mrp[s0 + r];
+                for (int c = 0; c < bs; ++c) {
+                    mci[o + c] = s0 + c;
+                    mv[o + c] = 0.0;
                 }
             }
-        }
-    }
-    for (int r = 0; r < bs; ++r) {
-        int o = mrp[s0 + r];
-        for (int c = 0; c < bs; ++c) {
-            mci[o + c] = s0 + c;
-            mv[o + c] = ok ? e[r * bs + c] : 0.0;
         }
     }
 }
@@ -582,6 +625,8 @@ constexpr int SPGEMM_DENSE = SPGEMM_DENSE_COLS;
 // rows x columns above which clearing and compacting the dense rows costs more
 // than the merge
 constexpr long SPGEMM_DENSE_WORK = 64L * 1024 * 1024;
+// a workgroup per output row: beyond this many rows the short merge variants win
+constexpr int SPGEMM_DENSE_ROWS = 65536;
 
 template <bool FILL>
 __global__ __launch_bounds__(WAVE) void k_spgemm_dw(int nr, const int* __restrict__ arp, const int* __restrict__ aci,
@@ -1562,25 +1607,6 @@ __global__ void k_rj_count(int nC, const int* __restrict__ xrp, int* __restrict_
     if (i < nC) len[i] = xrp[i + 1] - xrp[i] + 1;
 }
 
-__global__ void k_rj_fill(int nC, const int* __restrict__ xrp, const int* __restrict__ xci,
-                          const double* __restrict__ xv, double scale, const int* __restrict__ fmap,
-                          const int* __restrict__ cmap, const int* __restrict__ rrp, int* __restrict__ rci,
-                          double* __restrict__ rv) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nC) return;
-    int o = rrp[i];
-    int g = cmap[i];
-    bool placed = false;
-    for (int p = xrp[i]; p < xrp[i + 1]; ++p) {
-        int col = fmap[xci[p]];
-        if (!placed && col > g) { rci[o] = g; rv[o] = 1.0; ++o; placed = true; }
-        rci[o] = col;
-        rv[o] = scale * xv[p];
-        ++o;
-    }
-    if (!placed) { rci[o] = g; rv[o] = 1.0; }
-}
-
 // P = [[Y (coarse columns) , M (columns nC + fmap)] on F rows ; unit rows on C rows]
 __global__ void k_pj_count(int n, const int* __restrict__ isF, const int* __restrict__ lmap,
                            const int* __restrict__ yrp, const int* __restrict__ mrp, int* __restrict__ len) {
@@ -1591,19 +1617,73 @@ __global__ void k_pj_count(int n, const int* __restrict__ isF, const int* __rest
     len[g] = (yrp[k + 1] - yrp[k]) + (mrp[k + 1] - mrp[k]);
 }
 
-__global__ void k_pj_fill(int n, int nC, const int* __restrict__ isF, const int* __restrict__ lmap,
-                          const int* __restrict__ yrp, const int* __restrict__ yci, const double* __restrict__ yv,
-                          double yscale, const int* __restrict__ mrp, const int* __restrict__ mci,
-                          const double* __restrict__ mv, double mscale, const int* __restrict__ fmap,
-                          const int* __restrict__ prp,
-                          int* __restrict__ pci, double* __restrict__ pv) {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n) return;
-    int o = prp[g];
-    int k = lmap[g];
-    if (!isF[g]) { pci[o] = k; pv[o] = 1.0; return; }
-    for (int p = yrp[k]; p < yrp[k + 1]; ++p) { pci[o] = yci[p]; pv[o] = yscale * yv[p]; ++o; }
-    for (int p = mrp[k]; p < mrp[k + 1]; ++p) { pci[o] = nC + fmap[mci[p]]; pv[o] = mscale * mv[p]; ++o; }
+// Lane-group versions of the two fills above.  In a row of R the unit entry
+// goes before the first column above g, so entry p of X lands at
+// (p - row start) + (col > g) and the unit after the columns below g.
+template <int G>
+__global__ __launch_bounds__(TPB) void k_rj_fill_g(int nC, const int* __restrict__ xrp, const int* __restrict__ xci,
+                                                   const double* __restrict__ xv, double scale,
+                                                   const int* __restrict__ fmap, const int* __restrict__ cmap,
+                                                   const int* __restrict__ rrp, int* __restrict__ rci,
+                                                   double* __restrict__ rv) {
+    Grp<G> g;
+    const int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    const bool valid = i < nC;
+    int p0 = 0, len = 0, o = 0, gc = 0;
+    if (valid) {
+        p0 = xrp[i];
+        len = xrp[i + 1] - p0;
+        o = rrp[i];
+        gc = cmap[i];
+    }
+    const int wl = wave_max_int(len);
+    int nless = 0;
+    for (int base = 0; base < wl; base += G) {
+        const int q = base + g.gl;
+        const bool act = q < len;
+        int col = 0;
+        if (act) {
+            col = fmap[xci[p0 + q]];
+            int pos = o + q + (col > gc ? 1 : 0);
+            rci[pos] = col;
+            rv[pos] = scale * xv[p0 + q];
+        }
+        nless += __popcll(g.bits(act && col < gc));
+    }
+    if (valid && g.gl == 0) {
+        rci[o + nless] = gc;
+        rv[o + nless] = 1.0;
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(TPB) void k_pj_fill_g(int n, int nC, const int* __restrict__ isF,
+                                                   const int* __restrict__ lmap, const int* __restrict__ yrp,
+                                                   const int* __restrict__ yci, const double* __restrict__ yv,
+                                                   double yscale, const int* __restrict__ mrp,
+                                                   const int* __restrict__ mci, const double* __restrict__ mv,
+                                                   double mscale, const int* __restrict__ fmap,
+                                                   const int* __restrict__ prp, int* __restrict__ pci,
+                                                   double* __restrict__ pv) {
+    Grp<G> g;
+    const int r = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    if (r >= n) return;
+    const int o = prp[r];
+    const int k = lmap[r];
+    if (!isF[r]) {
+        if (g.gl == 0) { pci[o] = k; pv[o] = 1.0; }
+        return;
+    }
+    const int y0 = yrp[k], ylen = yrp[k + 1] - y0;
+    for (int q = g.gl; q < ylen; q += G) {
+        pci[o + q] = yci[y0 + q];
+        pv[o + q] = yscale * yv[y0 + q];
+    }
+    const int m0 = mrp[k], mlen = mrp[k + 1] - m0;
+    for (int q = g.gl; q < mlen; q += G) {
+        pci[o + ylen + q] = nC + fmap[mci[m0 + q]];
+        pv[o + ylen + q] = mscale * mv[m0 + q];
+    }
 }
 
 // ---------------------------------------------------------------- composed two-grid operators
@@ -1891,7 +1971,7 @@ static void spgemm_launch(const DCsr& A, const DCsr& B, int max_row, const int* 
                           int* flag, hipStream_t s) {
     // max_row selects the variant: <= 64 entries per row of A -> one head per lane
     if (A.nr <= 0) return;
-    if (B.nc <= SPGEMM_DENSE && (long)A.nr * B.nc <= SPGEMM_DENSE_WORK) {
+    if (B.nc <= SPGEMM_DENSE && A.nr <= SPGEMM_DENSE_ROWS && (long)A.nr * B.nc <= SPGEMM_DENSE_WORK) {
         k_spgemm_dw<FILL><<<A.nr, WAVE, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p, B.v.p, B.nc, crp, cci,
                                                 cv, cnt);
         MGR_LAUNCH_CHECK();
@@ -2135,7 +2215,9 @@ void rj_count(int nC, const DCsr& X, int* len, hipStream_t s) {
 
 void rj_fill(int nC, const DCsr& X, double scale, const int* fmap, const int* cmap, DCsr& R, hipStream_t s) {
     if (nC <= 0) return;
-    k_rj_fill<<<nblk(nC), TPB, 0, s>>>(nC, X.rp.p, X.ci.p, X.v.p, scale, fmap, cmap, R.rp.p, R.ci.p, R.v.p);
+    int G = group_for(X.max_row);
+    MGR_DISPATCH_G4(G, (k_rj_fill_g<GG><<<grid_for(nC, GG), TPB, 0, s>>>(nC, X.rp.p, X.ci.p, X.v.p, scale, fmap,
+                                                                          cmap, R.rp.p, R.ci.p, R.v.p)));
     MGR_LAUNCH_CHECK();
 }
 
@@ -2148,8 +2230,10 @@ void pj_count(int n, const int* isF, const int* lmap, const DCsr& Y, const DCsr&
 void pj_fill(int n, int nC, const int* isF, const int* lmap, const DCsr& Y, double yscale, const DCsr& M,
              double mscale, const int* fmap, DCsr& P, hipStream_t s) {
     if (n <= 0) return;
-    k_pj_fill<<<nblk(n), TPB, 0, s>>>(n, nC, isF, lmap, Y.rp.p, Y.ci.p, Y.v.p, yscale, M.rp.p, M.ci.p, M.v.p,
-                                      mscale, fmap, P.rp.p, P.ci.p, P.v.p);
+    int G = group_for(Y.max_row < 0 || M.max_row < 0 ? -1 : Y.max_row + M.max_row);
+    MGR_DISPATCH_G4(G, (k_pj_fill_g<GG><<<grid_for(n, GG), TPB, 0, s>>>(n, nC, isF, lmap, Y.rp.p, Y.ci.p, Y.v.p,
+                                                                         yscale, M.rp.p, M.ci.p, M.v.p, mscale,
+                                                                         fmap, P.rp.p, P.ci.p, P.v.p)));
     MGR_LAUNCH_CHECK();
 }
 
