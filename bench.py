@@ -167,83 +167,69 @@ def main():
     t_ap64, _ = time_kernel(ap64, stream, 20, flush)
     t_ap32, _ = time_kernel(ap32, stream, 20, flush)
 
-    # ---- secondary: the compositional system with wells (128x128x64, 4 unknowns per
-    # cell, 16 wells; 2-level MGR), FP64 vs FP32 apply inside FP64 FGMRES
-    comp = None
-    if args.comp_steps > 0:
-        log("generating compositional 128x128x64 + 16 wells ...")
-        c2 = W.compositional_wells(seed=2)
-        v2 = torch.tensor(c2["vals"], device="cuda")
-        b2 = torch.tensor(c2["rhs"], device="cuda")
-        s64, r64, _, _, _ = run_steps(P, c2, v2, b2, 64, args.comp_steps, 1)
-        s32, r32, _, _, _ = run_steps(P, c2, v2, b2, 32, args.comp_steps, 1)
+    def secondary(sysd, steps, mgr_desc, apply_reps, roof=None):
+        """FP64 and FP32 apply on one more workload: time to 1e-8, per-apply time
+        (cache flushed), and optionally the roofline of its FGMRES matvec."""
+        vv_ = torch.tensor(sysd["vals"], device="cuda")
+        bb_ = torch.tensor(sysd["rhs"], device="cuda")
+        o = sysd.get("solver_opts", {})
+        s64, r64, _, _, _ = run_steps(P, sysd, vv_, bb_, 64, steps, 1, **o)
+        s32, r32, _, _, _ = run_steps(P, sysd, vv_, bb_, 32, steps, 1, **o)
         t64 = statistics.mean(a + b for a, b, _, _ in r64)
         t32 = statistics.mean(a + b for a, b, _, _ in r32)
-        vv = torch.randn(c2["n"], dtype=torch.float64, device="cuda")
-        zz = torch.empty_like(vv)
-        a64 = lambda: lib.mgr_apply(s64._h, ctypes.c_void_p(vv.data_ptr()), ctypes.c_void_p(zz.data_ptr()))
-        a32 = lambda: lib.mgr_apply(s32._h, ctypes.c_void_p(vv.data_ptr()), ctypes.c_void_p(zz.data_ptr()))
+        vin = torch.randn(sysd["n"], dtype=torch.float64, device="cuda")
+        zout = torch.empty_like(vin)
+        a64 = lambda: lib.mgr_apply(s64._h, ctypes.c_void_p(vin.data_ptr()), ctypes.c_void_p(zout.data_ptr()))
+        a32 = lambda: lib.mgr_apply(s32._h, ctypes.c_void_p(vin.data_ptr()), ctypes.c_void_p(zout.data_ptr()))
         a64(); a32()
-        ta64, _ = time_kernel(a64, stream, 10, flush)
-        ta32, _ = time_kernel(a32, stream, 10, flush)
-        # roofline of its FGMRES matvec: block-CSR (4 x 4) SpMV in FP64, an operator
-        # of about 1 GB, four times the Infinity Cache
-        mv = lambda: lib.mgr_matvec(s64._h, 0, ctypes.c_void_p(vv.data_ptr()), ctypes.c_void_p(zz.data_ptr()))
-        mv()
-        t_bsr, _ = time_kernel(mv, stream, 20, flush)
-        nbr2, nnzb2 = len(c2["rp"]) - 1, len(c2["ci"])
-        bb = bsr_spmv_bytes(4, nbr2, nnzb2)
-        comp_roof = {"kernel": "k_bsr_spmv<4, 8> (FGMRES matvec y = A x, 4 x 4 block CSR, FP64)", "bound": "hbm",
-                     "achieved": round(bb / t_bsr / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(bb / t_bsr / 1e9 / HBM_PEAK_GBS, 4),
-                     "traffic": kernel_traffic("k_bsr_spmv_compositional.md"),
-                     "bytes_per_launch": bb, "avg_launch_us": round(1e6 * t_bsr, 2)}
-        comp = {"workload": "compositional_wells_128x128x64", "n": c2["n"], "nnz": int(len(c2["ci"]) * 16),
-                "mgr": "L1 F = components (block-Jacobi), L2 F = wells (Jacobi), coarse pressure AMG",
-                "fp64": {"time_to_tol_s": round(t64, 6), "setup_s": round(statistics.mean(a for a, _, _, _ in r64), 6),
-                         "solve_s": round(statistics.mean(b for _, b, _, _ in r64), 6), "iterations": r64[-1][2],
-                         "rel_res_true": r64[-1][3], "apply_ms": round(1e3 * ta64, 4)},
-                "fp32": {"time_to_tol_s": round(t32, 6), "setup_s": round(statistics.mean(a for a, _, _, _ in r32), 6),
-                         "solve_s": round(statistics.mean(b for _, b, _, _ in r32), 6), "iterations": r32[-1][2],
-                         "rel_res_true": r32[-1][3], "apply_ms": round(1e3 * ta32, 4)},
-                "speedup_time_to_tol": round(t64 / t32, 4), "speedup_per_apply": round(ta64 / ta32, 4),
-                "roofline": comp_roof}
+        ta64, _ = time_kernel(a64, stream, apply_reps, flush)
+        ta32, _ = time_kernel(a32, stream, apply_reps, flush)
+        out_ = {"workload": sysd["name"], "n": sysd["n"], "nnz": int(len(sysd["ci"]) * sysd["b"] ** 2),
+                "mgr": mgr_desc}
+        for key, r, ta in (("fp64", r64, ta64), ("fp32", r32, ta32)):
+            out_[key] = {"time_to_tol_s": round(statistics.mean(a + b for a, b, _, _ in r), 6),
+                         "setup_s": round(statistics.mean(a for a, _, _, _ in r), 6),
+                         "solve_s": round(statistics.mean(b for _, b, _, _ in r), 6), "iterations": r[-1][2],
+                         "rel_res_true": r[-1][3], "apply_ms": round(1e3 * ta, 4)}
+        out_["speedup_time_to_tol"] = round(t64 / t32, 4)
+        out_["speedup_per_apply"] = round(ta64 / ta32, 4)
+        if roof:
+            # the FGMRES matvec on the block-CSR input, FP64
+            mv = lambda: lib.mgr_matvec(s64._h, 0, ctypes.c_void_p(vin.data_ptr()), ctypes.c_void_p(zout.data_ptr()))
+            mv()
+            t_mv, _ = time_kernel(mv, stream, 20, flush)
+            bb = bsr_spmv_bytes(sysd["b"], len(sysd["rp"]) - 1, len(sysd["ci"]))
+            out_["roofline"] = {"kernel": roof[0], "bound": "hbm", "achieved": round(bb / t_mv / 1e9, 1),
+                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                "frac": round(bb / t_mv / 1e9 / HBM_PEAK_GBS, 4), "traffic": kernel_traffic(roof[1]),
+                                "bytes_per_launch": bb, "avg_launch_us": round(1e6 * t_mv, 2)}
         s64.close()
         s32.close()
-        del c2, v2, b2, vv, zz
+        return out_
 
+    # ---- secondary: the compositional system with wells (128x128x64, 4 unknowns per
+    # cell, 16 wells; 2-level MGR), FP64 vs FP32 apply inside FP64 FGMRES; its block
+    # SpMV (about 1 GB, four times the Infinity Cache) is the HBM roofline case
+    comp = comp4 = frac = None
+    if args.comp_steps > 0:
+        log("generating compositional 128x128x64 + 16 wells ...")
+        comp = secondary(W.compositional_wells(seed=2), args.comp_steps,
+                         "L1 F = components (block-Jacobi), L2 F = wells (Jacobi), coarse pressure AMG", 10,
+                         ("k_bsr_spmv<4, 8> (FGMRES matvec y = A x, 4 x 4 block CSR, FP64)",
+                          "k_bsr_spmv_compositional.md"))
+        # the paper's own four-level order on the same grid: rho_2, rho_1, p (AMG
+        # F-relaxation), then the well system (zero diagonals) as the coarse grid
+        log("generating compositional 4-level 128x128x64 + 16 wells ...")
+        comp4 = secondary(W.compositional_4level(seed=4), args.comp_steps,
+                          "L1 F = rho_2 (Jacobi, exact), L2 F = rho_1 (Jacobi), L3 F = p (AMG V-cycle), "
+                          "coarse = wells (direct)", 10)
     # ---- secondary: the fracturing system (Q1 elasticity on 96^3 nodes + a 96 x 96
     # planar fracture; MGR_U with an unknown-based AMG V-cycle as F-relaxation)
-    frac = None
     if args.frac_steps > 0:
         log("generating fracturing 96^3 ...")
-        f3 = W.fracturing(96, seed=3)
-        v3 = torch.tensor(f3["vals"], device="cuda")
-        b3 = torch.tensor(f3["rhs"], device="cuda")
-        o3 = f3.get("solver_opts", {})
-        f64s, q64, _, _, _ = run_steps(P, f3, v3, b3, 64, args.frac_steps, 1, **o3)
-        f32s, q32, _, _, _ = run_steps(P, f3, v3, b3, 32, args.frac_steps, 1, **o3)
-        t64 = statistics.mean(a + b for a, b, _, _ in q64)
-        t32 = statistics.mean(a + b for a, b, _, _ in q32)
-        vv = torch.randn(f3["n"], dtype=torch.float64, device="cuda")
-        zz = torch.empty_like(vv)
-        a64 = lambda: lib.mgr_apply(f64s._h, ctypes.c_void_p(vv.data_ptr()), ctypes.c_void_p(zz.data_ptr()))
-        a32 = lambda: lib.mgr_apply(f32s._h, ctypes.c_void_p(vv.data_ptr()), ctypes.c_void_p(zz.data_ptr()))
-        a64(); a32()
-        ta64, _ = time_kernel(a64, stream, 5, flush)
-        ta32, _ = time_kernel(a32, stream, 5, flush)
-        frac = {"workload": "fracturing_96x96x96", "n": f3["n"], "nnz": int(len(f3["ci"]) * 9),
-                "mgr": "F = displacements (unknown-based AMG V(2,2) F-relaxation), C = fracture pressures -> AMG",
-                "fp64": {"time_to_tol_s": round(t64, 6), "setup_s": round(statistics.mean(a for a, _, _, _ in q64), 6),
-                         "solve_s": round(statistics.mean(b for _, b, _, _ in q64), 6), "iterations": q64[-1][2],
-                         "rel_res_true": q64[-1][3], "apply_ms": round(1e3 * ta64, 4)},
-                "fp32": {"time_to_tol_s": round(t32, 6), "setup_s": round(statistics.mean(a for a, _, _, _ in q32), 6),
-                         "solve_s": round(statistics.mean(b for _, b, _, _ in q32), 6), "iterations": q32[-1][2],
-                         "rel_res_true": q32[-1][3], "apply_ms": round(1e3 * ta32, 4)},
-                "speedup_time_to_tol": round(t64 / t32, 4), "speedup_per_apply": round(ta64 / ta32, 4)}
-        f64s.close()
-        f32s.close()
-        del f3, v3, b3, vv, zz
+        frac = secondary(W.fracturing(96, seed=3), args.frac_steps,
+                         "F = displacements (unknown-based AMG V(2,2) F-relaxation), C = fracture pressures -> AMG",
+                         5)
 
     # ---- FP64 oracle on the box's host cores (bounded sample: one full setup + solve of this workload)
     cpu = None
@@ -303,6 +289,7 @@ def main():
                      "traffic": kernel_traffic("k_spmv_fgmres_mimetic64.md"),
                      "bytes_per_launch": nbytes, "avg_launch_us": round(1e6 * t_spmv, 2)},
         "secondary_compositional": comp,
+        "secondary_compositional_4level": comp4,
         "secondary_fracturing": frac,
         "cpu_baseline": cpu,
     }

@@ -348,22 +348,11 @@ __global__ void k_frelax_len(int nF, const int* __restrict__ bnum, const int* __
 // then subtract f times it from every other row.  Every index is static so the
 // block stays in registers.  Returns false on a zero or non-finite pivot.
 template <int BS>
-__device__ inline bool frelax_block_inverse(int s0, const int* __restrict__ arp, const int* __restrict__ aci,
-                                            const double* __restrict__ av, double (&e)[BS][BS]) {
-    double a[BS][BS];
+__device__ inline bool block_inverse(double (&a)[BS][BS], double (&e)[BS][BS]) {
 #pragma unroll
     for (int r = 0; r < BS; ++r)
 #pragma unroll
-        for (int c = 0; c < BS; ++c) { a[r][c] = 0.0; e[r][c] = (r == c) ? 1.0 : 0.0; }
-#pragma unroll
-    for (int r = 0; r < BS; ++r)
-        for (int p = arp[s0 + r]; p < arp[s0 + r + 1]; ++p) {
-            int c = aci[p] - s0;
-            double v = av[p];
-#pragma unroll
-            for (int cc = 0; cc < BS; ++cc)
-                if (c == cc) a[r][cc] = v;
-        }
+        for (int c = 0; c < BS; ++c) e[r][c] = (r == c) ? 1.0 : 0.0;
 #pragma unroll
     for (int c = 0; c < BS; ++c) {
         int pv = c;
@@ -397,51 +386,84 @@ __device__ inline bool frelax_block_inverse(int s0, const int* __restrict__ arp,
     return true;
 }
 
+// One block with a group of four lanes: lane r reads the diagonal-block part of
+// row s0 + r (eight entries per load batch), the rows are exchanged, every
+// lane inverts the block and lane r writes row r of M.
 template <int BS>
-__device__ inline void frelax_block(int s0, const int* __restrict__ arp, const int* __restrict__ aci,
-                                    const double* __restrict__ av, const int* __restrict__ mrp, int* __restrict__ mci,
-                                    double* __restrict__ mv, int* __restrict__ flag) {
-    double e[BS][BS];
-    bool ok = frelax_block_inverse<BS>(s0, arp, aci, av, e);
-    if (!ok) set_flag(flag, 3);
+__device__ inline void frelax_block(int s0, int gl, int gbase, const int* __restrict__ arp,
+                                    const int* __restrict__ aci, const double* __restrict__ av,
+                                    const int* __restrict__ mrp, int* __restrict__ mci, double* __restrict__ mv,
+                                    int* __restrict__ flag) {
+    double row[BS];
 #pragma unroll
-    for (int r = 0; r < BS; ++r) {
-        int o = mrp[s0 + r];
+    for (int c = 0; c < BS; ++c) row[c] = 0.0;
+    if (gl < BS) {
+        const int p1 = arp[s0 + gl + 1];
+        for (int p = arp[s0 + gl]; p < p1; p += 8) {
+            int cs[8];
+            double vs[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                cs[u] = (p + u < p1) ? aci[p + u] - s0 : -1;
+                vs[u] = (p + u < p1) ? av[p + u] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int c = 0; c < BS; ++c)
+                    if (cs[u] == c) row[c] = vs[u];
+        }
+    }
+    double a[BS][BS], e[BS][BS];
+#pragma unroll
+    for (int r = 0; r < BS; ++r)
+#pragma unroll
+        for (int c = 0; c < BS; ++c) a[r][c] = __shfl(row[c], gbase + r, WAVE);
+    const bool ok = block_inverse<BS>(a, e);
+    if (!ok && gl == 0) set_flag(flag, 3);
+    if (gl < BS) {
+        const int o = mrp[s0 + gl];
 #pragma unroll
         for (int c = 0; c < BS; ++c) {
+            double x = 0.0;
+#pragma unroll
+            for (int r = 0; r < BS; ++r)
+                if (r == gl) x = e[r][c];
             mci[o + c] = s0 + c;
-            mv[o + c] = ok ? e[r][c] : 0.0;
+            mv[o + c] = ok ? x : 0.0;
         }
     }
 }
 
-// M = block-diagonal inverse of A_FF over the blocks [bstart[t], bstart[t+1]).
-// On a failure (block larger than 4, zero or non-finite pivot) the flag is
-// raised and the rows are still written, with valid column indices and zero
-// values, so that no later kernel reads an unwritten index.
-__global__ void k_frelax_fill(int nb, const int* __restrict__ bstart, const int* __restrict__ arp,
-                              const int* __restrict__ aci, const double* __restrict__ av,
-                              const int* __restrict__ mrp, int* __restrict__ mci, double* __restrict__ mv,
-                              int* __restrict__ flag) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+// M = block-diagonal inverse of A_FF over the blocks [bstart[t], bstart[t+1]),
+// four lanes per block.  On a failure (block larger than 4, zero or non-finite
+// pivot) the flag is raised and the rows are still written, with valid column
+// indices and zero values, so that no later kernel reads an unwritten index.
+__global__ __launch_bounds__(TPB) void k_frelax_fill(int nb, const int* __restrict__ bstart,
+                                                     const int* __restrict__ arp, const int* __restrict__ aci,
+                                                     const double* __restrict__ av, const int* __restrict__ mrp,
+                                                     int* __restrict__ mci, double* __restrict__ mv,
+                                                     int* __restrict__ flag) {
+    const int t = (int)(((long)blockIdx.x * TPB + threadIdx.x) / 4);
+    const int gl = threadIdx.x & 3, gbase = (threadIdx.x & (WAVE - 1)) - gl;
     if (t >= nb) return;
-    int s0 = bstart[t], bs = bstart[t + 1] - s0;
+    const int s0 = bstart[t], bs = bstart[t + 1] - s0;
     switch (bs) {
-        case 1: frelax_block<1>(s0, arp, aci, av, mrp, mci, mv, flag); break;
-        case 2: frelax_block<2>(s0, arp, aci, av, mrp, mci, mv, flag); break;
-        case 3: frelax_block<3>(s0, arp, aci, av, mrp, mci, mv, flag); break;
-        case 4: frelax_block<4>(s0, arp, aci, av, mrp, mci, mv, flag); break;
-        default: {
-            // larger blocks are not supported: flagged, structure written with zeros
-            set_flag(flag, 6);
-            for (int r = 0; r < bs; ++r) {
-                int o = mrp[s0 + r];
-                for (int c = 0; c < bs; ++c) {
-                    mci[o + c] = s0 + c;
-                    mv[o + c] = 0.0;
+        case 1: frelax_block<1>(s0, gl, gbase, arp, aci, av, mrp, mci, mv, flag); break;
+        case 2: frelax_block<2>(s0, gl, gbase, arp, aci, av, mrp, mci, mv, flag); break;
+        case 3: frelax_block<3>(s0, gl, gbase, arp, aci, av, mrp, mci, mv, flag); break;
+        case 4: frelax_block<4>(s0, gl, gbase, arp, aci, av, mrp, mci, mv, flag); break;
+        default:
+            if (gl == 0) {
+                set_flag(flag, 6);
+                for (int r = 0; r < bs; ++r) {
+                    int o = mrp[s0 + r];
+                    for (int c = 0; c < bs; ++c) {
+                        mci[o + c] = s0 + c;
+                        mv[o + c] = 0.0;
+                    }
                 }
             }
-        }
     }
 }
 
@@ -1953,7 +1975,8 @@ void frelax_row_len(int nF, const int* bnum, const int* bstart, int* len, hipStr
 
 void frelax_fill(int nb, const int* bstart, const DCsr& AFF, DCsr& M, int* flag, hipStream_t s) {
     if (nb <= 0) return;
-    k_frelax_fill<<<nblk(nb), TPB, 0, s>>>(nb, bstart, AFF.rp.p, AFF.ci.p, AFF.v.p, M.rp.p, M.ci.p, M.v.p, flag);
+    k_frelax_fill<<<grid_for(nb, 4), TPB, 0, s>>>(nb, bstart, AFF.rp.p, AFF.ci.p, AFF.v.p, M.rp.p, M.ci.p, M.v.p,
+                                                  flag);
     MGR_LAUNCH_CHECK();
 }
 

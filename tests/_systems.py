@@ -14,6 +14,10 @@ SMALL = {
     # 4x4 blocks + wells, two MGR levels (block-Jacobi, then Jacobi on wells)
     "comp_8x8x6": lambda: W.compositional_wells(8, 8, 6, seed=7),
     "comp_20x18x10": lambda: W.compositional_wells(20, 18, 10, seed=8, wells_per_axis=3),
+    # the paper's four-level compositional order: rho_2 (exact Jacobi), rho_1, p
+    # (AMG F-relaxation), wells with zero diagonals on the coarse grid
+    "comp4_10x9x8": lambda: W.compositional_4level(10, 9, 8, seed=5, wells_per_axis=2),
+    "comp4_20x18x12": lambda: W.compositional_4level(20, 18, 12, seed=6, wells_per_axis=3),
     # elasticity (3x3 blocks) + fracture pressures; F-relaxation = unknown-based AMG V-cycle
     "frac_12^3": lambda: W.fracturing(12, seed=5),
     "frac_18^3": lambda: W.fracturing(18, seed=6),

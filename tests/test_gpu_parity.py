@@ -114,7 +114,7 @@ def test_solve(built, name):
     assert rel(x, xo) <= 1e-8
 
 
-@pytest.mark.parametrize("name", ["tpfa_16^3", "mimetic_20^3", "comp_20x18x10"])
+@pytest.mark.parametrize("name", ["tpfa_16^3", "mimetic_20^3", "comp_20x18x10", "comp4_20x18x12"])
 def test_solve_fp32_apply(built, name):
     s, om, gs = built(name, precision=32)
     xo, io = om.solve(s["rhs"])

@@ -328,6 +328,56 @@ def test_schur_identity_injection_jacobi_p():
     np.testing.assert_allclose(ac, expect, rtol=1e-13, atol=1e-13 * np.abs(expect).max())
 
 
+def test_four_level_system_structure():
+    # the generator's structure that the reduction order relies on (Sec. 3.2):
+    # rho_2 rows couple only inside their cell, and every pressure-controlled
+    # well leaves a zero on the diagonal of the well block
+    s = W.compositional_4level(5, 4, 3, seed=2, wells_per_axis=2)
+    A = W.csr_of(s).tocoo()
+    cell = np.arange(s["n"]) // 3
+    rho2 = (s["field"][A.row] == 2) & (A.data != 0.0)   # stored zeros of the 3x3 blocks aside
+    assert np.all(cell[A.row[rho2]] == cell[A.col[rho2]])
+    d = W.csr_of(s).diagonal()
+    q_rows = np.where(s["field"] == 4)[0]
+    assert np.sum(d[q_rows] == 0.0) == s["nwells"] // 2
+
+
+def test_four_level_first_reduction_is_the_exact_schur_complement():
+    # level 1 eliminates rho_2 (+ padding), whose block is diagonal: Jacobi P is
+    # the ideal P of eq. (3) and A_c = A_CC - A_CF A_FF^{-1} A_FC exactly
+    s = W.compositional_4level(5, 4, 3, seed=3, wells_per_axis=2)
+    m = build(s)
+    A, F, C = _dense_blocks(s)
+    AFF = A[np.ix_(F, F)]
+    assert np.count_nonzero(AFF - np.diag(np.diag(AFF))) == 0
+    expect = A[np.ix_(C, C)] - A[np.ix_(C, F)] @ np.linalg.inv(AFF) @ A[np.ix_(F, C)]
+    ac = m.export(0, 0, 1).to_scipy().toarray()
+    np.testing.assert_allclose(ac, expect, rtol=1e-13, atol=1e-13 * np.abs(expect).max())
+
+
+def test_four_level_exact_with_exact_coarse_solve():
+    # only the first (exact) level, and a coarse grid small enough for the
+    # pivoted LU (which must cope with the zero well diagonals): MGR = A^{-1}
+    s = W.compositional_4level(4, 4, 2, seed=4, wells_per_axis=2)
+    m = build(s, levels=s["levels"][:1], max_coarse=128)
+    assert m.info()["amg_levels"] == [(s["n"] - 32 - 4, m.info()["amg_levels"][0][1])]
+    A = W.csr_of(s).toarray()
+    v = np.random.default_rng(7).standard_normal(s["n"])
+    ref = np.linalg.solve(A, v)
+    assert np.linalg.norm(m.apply(v) - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_four_level_fgmres_matches_direct_solve():
+    import scipy.sparse.linalg as spla
+    s = W.compositional_4level(10, 9, 8, seed=5, wells_per_axis=2)
+    m = build(s)
+    assert [l[0] for l in m.info()["mgr_levels"]] == [s["n"], s["n"] - 4 - 720, 728]
+    x, info = m.solve(s["rhs"])
+    xd = spla.spsolve(W.csr_of(s).tocsc(), s["rhs"])
+    assert info.status == 0 and info.iterations <= 15
+    assert np.linalg.norm(x - xd) <= 1e-7 * np.linalg.norm(xd)
+
+
 def test_rap_equals_literal_triple_product_jacobi_r():
     # eq. (5) restriction: A_c = R A P with the full R = [-A_CF D^{-1}, I], P = [-D^{-1} A_FC; I]
     s = W.two_field_tpfa(3, 2, 2, seed=4)

@@ -306,6 +306,117 @@ def compositional_wells(nx=128, ny=128, nz=64, seed=2, wells_per_axis=4, nperf=3
                    f"compositional_wells_{nx}x{ny}x{nz}", grid=(nx, ny, nz), nwells=nw, ncell=ncell)
 
 
+def compositional_4level(nx=128, ny=128, nz=64, seed=4, wells_per_axis=4, nperf=3, margin_p=1.1, margin_rho=2.0):
+    """Compositional system in the paper's four-level form (Sec. 3.2): per cell
+    the pressure p (field 0), the advected density rho_1 (field 1) and the
+    density rho_2 of the volume-constraint equation (field 2), as interleaved
+    3x3 blocks on the 7-point stencil; per well a bottom-hole pressure p_w
+    (field 3) and a rate q_w (field 4), stored as one block row with an identity
+    padding unknown (field 5).
+
+    Cell rows: off-diagonal block (c, d) = -T_cd W with W_pp = 1, W_{p,rho} and
+    W_{rho1,p} ~ U[0, 0.5], W_{rho1,rho} ~ U[0, 0.5] only when d is upwind of c,
+    and a zero rho_2 row (the constraint is cell-local); diagonal = margin times
+    the absolute off-diagonal row sum + U[0.1, 1] for p and rho_1, intra-cell
+    couplings U[-0.1, 0.1] times the diagonal.  The rho_2 row couples only to
+    its own cell: U[-0.5, 0.5] on p and rho_1, 1 + U[0, 1] on rho_2, so the
+    rho_2 block and its couplings are diagonal.
+
+    Wells at the centres of a wells_per_axis^2 lattice, perforated in layers
+    0..nperf-1 with WI = 10^N(0,1) k_c.  A perforated cell's p and rho_1 rows
+    gain WI m (p_c - p_w) (m = 1 for p, U[0.5, 1] for rho_1).  Well row p_w:
+    sum(WI) p_w - sum(WI p_c) - q_w; well row q_w: q_w = target for a rate-
+    controlled well, p_w = target for a pressure-controlled one (every other
+    well), which leaves a zero on the diagonal of the well block.
+
+    Reduction order (the paper's): rho_2 (+ padding) by Jacobi, which is exact
+    here; rho_1 by Jacobi; p by an AMG V-cycle as F-relaxation; the well system
+    is the coarse grid (solved directly: it has fewer unknowns than the AMG's
+    coarsest size)."""
+    g = _rngs(seed)
+    ncell = nx * ny * nz
+    k = 10.0 ** g["perm"].standard_normal(ncell)
+    acc = g["accum"].uniform(0.1, 1.0, (ncell, 2))
+    kz, ky, kx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    kx, ky, kz = kx.ravel(), ky.ravel(), kz.ravel()
+    cells = np.arange(ncell)
+    offs = np.array([-nx * ny, -nx, -1, 0, 1, nx, nx * ny])
+    exist = np.stack([kz > 0, ky > 0, kx > 0, np.ones(ncell, bool), kx < nx - 1, ky < ny - 1, kz < nz - 1], 1)
+    gface = g["upwind"].standard_normal((ncell, 3))
+    blocks = np.zeros((ncell, 8, 3, 3))
+    for sl in (0, 1, 2, 4, 5, 6):
+        m = exist[:, sl]
+        c = cells[m]
+        d = c + offs[sl]
+        T = 2.0 * k[c] * k[d] / (k[c] + k[d])
+        axis = {0: 2, 1: 1, 2: 0, 4: 0, 5: 1, 6: 2}[sl]
+        d_upwind = (gface[c, axis] < 0.0) if sl > 3 else (gface[d, axis] >= 0.0)
+        W = np.zeros((len(c), 3, 3))
+        W[:, 0, 0] = 1.0
+        W[:, 0, 1:] = g["noise"].uniform(0.0, 0.5, (len(c), 2))
+        W[:, 1, 0] = g["noise"].uniform(0.0, 0.5, len(c))
+        W[:, 1, 1:] = g["noise"].uniform(0.0, 0.5, (len(c), 2)) * d_upwind[:, None]
+        blocks[m, sl] = -T[:, None, None] * W
+    rowabs = np.abs(blocks).sum(axis=(1, 3))[:, :2]
+    diag = np.array([margin_p, margin_rho])[None, :] * rowabs + acc
+    intra = np.zeros((ncell, 3, 3))
+    intra[:, :2, :] = g["noise"].uniform(-0.1, 0.1, (ncell, 2, 3)) * diag[:, :, None]
+    intra[:, 0, 0] = diag[:, 0]
+    intra[:, 1, 1] = diag[:, 1]
+    intra[:, 2, :2] = g["noise"].uniform(-0.5, 0.5, (ncell, 2))
+    intra[:, 2, 2] = 1.0 + g["noise"].uniform(0.0, 1.0, ncell)
+    blocks[:, 3] = intra
+    # wells
+    pos = [(2 * m + 1) * nx // (2 * wells_per_axis) for m in range(wells_per_axis)]
+    posy = [(2 * m + 1) * ny // (2 * wells_per_axis) for m in range(wells_per_axis)]
+    wells = [(i, j) for j in posy for i in pos]
+    nw = len(wells)
+    nperf = min(nperf, nz)
+    perf_cells = np.array([[i + nx * (j + ny * kk) for kk in range(nperf)] for (i, j) in wells])
+    WI = (10.0 ** g["wells"].standard_normal((nw, nperf))) * k[perf_cells]
+    mob = np.stack([np.ones((nw, nperf)), g["wells"].uniform(0.5, 1.0, (nw, nperf))], -1)   # p, rho_1 rows
+    exist8 = np.concatenate([exist, np.zeros((ncell, 1), bool)], 1)
+    has_well = np.full(ncell, -1)
+    for w in range(nw):
+        for q in range(nperf):
+            c = perf_cells[w, q]
+            blocks[c, 3, :2, 0] += WI[w, q] * mob[w, q]
+            has_well[c] = w
+            exist8[c, 7] = True
+            blocks[c, 7, :2, 0] = -WI[w, q] * mob[w, q]       # column 0 of the well block = p_w
+    cnt = exist8.sum(1)
+    rp = np.concatenate([[0], np.cumsum(np.concatenate([cnt, np.full(nw, nperf + 1)]))]).astype(np.int64)
+    colmat = cells[:, None] + np.concatenate([offs, [0]])[None, :]
+    colmat[:, 7] = ncell + np.maximum(has_well, 0)
+    ci_cells = colmat[exist8]
+    vals_cells = blocks[exist8]
+    del blocks
+    ci_w, v_w = [], []
+    for w in range(nw):
+        for q in range(nperf):
+            b = np.zeros((3, 3))
+            b[0, 0] = -WI[w, q]
+            ci_w.append(perf_cells[w, q]); v_w.append(b)
+        b = np.zeros((3, 3))
+        b[0, 0] = WI[w].sum()
+        b[0, 1] = -1.0
+        if w % 2 == 0:
+            b[1, 1] = 1.0            # rate control: q_w = target
+        else:
+            b[1, 0] = 1.0            # pressure control: p_w = target (zero diagonal at q_w)
+        b[2, 2] = 1.0
+        ci_w.append(ncell + w); v_w.append(b)
+    ci = np.concatenate([ci_cells, np.array(ci_w, np.int64)]).astype(np.int32)
+    vals = np.concatenate([vals_cells.reshape(-1), np.array(v_w).reshape(-1)])
+    field = np.concatenate([np.tile(np.arange(3, dtype=np.int32), ncell),
+                            np.tile(np.array([3, 4, 5], np.int32), nw)])
+    rhs = g["rhs"].standard_normal(3 * (ncell + nw))
+    rhs[field == 5] = 0.0
+    levels = [level((1 << 2) | (1 << 5), "jacobi"), level(1 << 1, "jacobi"), level(1 << 0, "amg")]
+    return _system(3, rp.astype(np.int32), ci, vals, field, rhs, levels,
+                   f"compositional_4level_{nx}x{ny}x{nz}", grid=(nx, ny, nz), nwells=nw, ncell=ncell)
+
+
 def _q1_reference_stiffness(nu):
     """24x24 stiffness of the unit trilinear hex for E = 1 (2x2x2 Gauss points),
     dofs ordered (node a, component c) -> 3a + c, nodes in (x fastest) order."""
