@@ -129,6 +129,20 @@ int mgr_set_opts(mgr_handle h, const mgr_opts *o);
 int mgr_setup(mgr_handle h, const mgr_matrix *A, const int32_t *field_of_dof, int32_t nlevels,
               const mgr_level_opts *lvl);
 
+/* Setup reuse for a new matrix on the same pattern, as between the Newton
+ * solves of a simulation (AMG data reuse, Sec. 3.3 and Sec. 5).  values:
+ * device pointer, nnzb*b*b doubles in the block layout (row pointers and
+ * columns) of the last mgr_setup; copied.  The MGR levels are formed again
+ * from the new values.  Every AMG hierarchy keeps its C/F splits and
+ * interpolation and forms its Galerkin products, L1 diagonals and coarsest
+ * inverse anew; with flags = MGR_REUSE_KEEP_FRELAX_AMG the hierarchies used as
+ * F-relaxation are kept whole instead (the caller's A_FF of those levels is
+ * unchanged, like the mechanics block of the fracturing case).  Errors: ARG
+ * (no setup yet, null values, unknown flags), ZERO_PIVOT, UNSUPPORTED, OOM,
+ * HIP; after an error the handle needs a new mgr_setup. */
+#define MGR_REUSE_KEEP_FRELAX_AMG 1
+int mgr_update_values(mgr_handle h, const double *values, int32_t flags);
+
 /* z = M^{-1} r: one MGR V-cycle (Algorithm 1) from z = 0, no global
  * relaxation.  r, z: n doubles; may not alias.  Asynchronous. */
 int mgr_apply(mgr_handle h, const double *r, double *z);

@@ -49,6 +49,9 @@ def lib():
         i32, f64, u64 = ctypes.c_int, ctypes.c_double, ctypes.c_ulonglong
         L.orc_setup.restype = P
         L.orc_setup.argtypes = [i32, i32, P, P, P, P, i32, P, P, P, P, P, P, f64, i32, i32, i32, i32, i32, u64, P]
+        L.orc_update.restype = P
+        L.orc_update.argtypes = [P, i32, i32, P, P, P, P, i32, P, P, P, P, P, P, f64, i32, i32, i32, i32, i32, u64,
+                                 i32, P]
         L.orc_free.argtypes = [P]
         L.orc_apply.argtypes = [P, P, P, i32]
         L.orc_matvec.argtypes = [P, P, P, i32]
@@ -244,12 +247,29 @@ class MGR:
         omega = _f64([lv.omega for lv in levels] or [0])
         restr = _i32([RESTRICT[lv.restrict] for lv in levels] or [0])
         aub = _i32([int(lv.amg_unknown_based) for lv in levels] or [0])
+        self._lv = (nl, fmask, frelax, sweeps, omega, restr, aub)
+        self._amg = (float(theta), int(max_levels), int(max_coarse), int(nu_pre), int(nu_post),
+                     int(coarse_unknown_based), int(seed))
         st = ctypes.c_int(0)
         self.h = L.orc_setup(self.b, len(self.rp) - 1, _p(self.rp), _p(self.ci), _p(self.vals), _p(self.field),
-                             nl, _p(fmask), _p(frelax), _p(sweeps), _p(omega), _p(restr), _p(aub), float(theta),
-                             int(max_levels), int(max_coarse), int(nu_pre), int(nu_post), int(coarse_unknown_based),
-                             int(seed), ctypes.byref(st))
+                             nl, *[_p(a) for a in self._lv[1:]], *self._amg, ctypes.byref(st))
         self.status = st.value
+
+    def update(self, vals, keep_frelax_amg=False):
+        """Setup reuse for new values on the same pattern: a new hierarchy whose
+        AMG parts keep this one's C/F splits and interpolation (their Galerkin
+        products are formed again), or, with keep_frelax_amg, keep the
+        F-relaxation AMG hierarchies whole.  Returns the new MGR."""
+        new = MGR.__new__(MGR)
+        new.b, new.rp, new.ci, new.n, new.field = self.b, self.rp, self.ci, self.n, self.field
+        new.vals = _f64(vals)
+        new._lv, new._amg = self._lv, self._amg
+        st = ctypes.c_int(0)
+        new.h = lib().orc_update(self.h, self.b, len(self.rp) - 1, _p(self.rp), _p(self.ci), _p(new.vals),
+                                 _p(self.field), self._lv[0], *[_p(a) for a in self._lv[1:]], *self._amg,
+                                 int(bool(keep_frelax_amg)), ctypes.byref(st))
+        new.status = st.value
+        return new
 
     def __del__(self):
         if getattr(self, "h", None):

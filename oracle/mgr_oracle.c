@@ -549,6 +549,9 @@ static void amg_free(Amg *h) {
     free(h);
 }
 
+static int amg_finish(Amg *h, int k, int status);
+static int amg_l1_diag(Amg *h, int k);
+
 /* Setup of the AMG hierarchy: strength, PMIS, direct interpolation, Galerkin
  * product A_{k+1} = P^T (A_k P) (both SpGEMMs in Gustavson order), until the
  * level is small (<= max_coarse), the level cap is reached, or coarsening
@@ -587,18 +590,16 @@ static int amg_setup(const Csr *a0, const int *label0, const AmgOpts *o, Amg **o
             h->label[k + 1] = (int *)xmalloc((size_t)nc * sizeof(int));
             for (int i = 0, c = 0; i < n; ++i) if (cf[i] == 1) h->label[k + 1][c++] = h->label[k][i];
         }
-        h->dl1[k] = (double *)xmalloc((size_t)n * sizeof(double));
-        for (int i = 0; i < n; ++i) {
-            double s = 0.0, aii = 0.0;
-            for (int q = a->rp[i]; q < a->rp[i + 1]; ++q) {
-                if (a->ci[q] == i) aii = a->v[q];
-                else s += fabs(a->v[q]);
-            }
-            h->dl1[k][i] = aii + s;
-            if (!(h->dl1[k][i] > 0.0)) status = ORC_ERR_UNSUPPORTED;
-        }
+        int sl = amg_l1_diag(h, k);
+        if (sl != ORC_OK) status = sl;
         k++;
     }
+    *out = h;
+    return amg_finish(h, k, status);
+}
+
+/* Transposes, work vectors and the LU factors of the coarsest level k. */
+static int amg_finish(Amg *h, int k, int status) {
     h->nlev = k + 1;
     for (int l = 0; l < h->nlev; ++l) h->AT[l] = csr_transpose(&h->A[l]);
     int nc = h->A[k].nr;
@@ -622,8 +623,98 @@ static int amg_setup(const Csr *a0, const int *label0, const AmgOpts *o, Amg **o
             status = lu_factor(nc, h->lu, h->piv);
         }
     }
-    *out = h;
     return status;
+}
+
+/* L1 diagonal of level k (a_ii + sum_{j != i} |a_ij|); status if not positive. */
+static int amg_l1_diag(Amg *h, int k) {
+    const Csr *a = &h->A[k];
+    int n = a->nr, status = ORC_OK;
+    h->dl1[k] = (double *)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    for (int i = 0; i < n; ++i) {
+        double s = 0.0, aii = 0.0;
+        for (int q = a->rp[i]; q < a->rp[i + 1]; ++q) {
+            if (a->ci[q] == i) aii = a->v[q];
+            else s += fabs(a->v[q]);
+        }
+        h->dl1[k][i] = aii + s;
+        if (!(h->dl1[k][i] > 0.0)) status = ORC_ERR_UNSUPPORTED;
+    }
+    return status;
+}
+
+/* Setup reuse across value updates of one sparsity pattern: the C/F splits,
+ * labels and interpolation operators of `old` are kept; every Galerkin product
+ * A_{k+1} = P^T (A_k P), L1 diagonal and the coarsest factorisation are formed
+ * again from the new level-0 matrix a0. */
+static int amg_reuse(const Csr *a0, const Amg *old, Amg **out) {
+    Amg *h = (Amg *)xcalloc(1, sizeof(Amg));
+    h->nu_pre = old->nu_pre; h->nu_post = old->nu_post;
+    h->A[0] = csr_copy(a0);
+    int status = ORC_OK, k = 0;
+    if (old->label[0]) {
+        h->label[0] = (int *)xmalloc((size_t)a0->nr * sizeof(int));
+        memcpy(h->label[0], old->label[0], (size_t)a0->nr * sizeof(int));
+    }
+    if (a0->nr != old->A[0].nr) status = ORC_ERR_ARG;
+    for (; status == ORC_OK && k + 1 < old->nlev; ++k) {
+        int n = h->A[k].nr, nc = old->P[k].nc;
+        h->cf[k] = (int *)xmalloc((size_t)n * sizeof(int));
+        memcpy(h->cf[k], old->cf[k], (size_t)n * sizeof(int));
+        h->P[k] = csr_copy(&old->P[k]);
+        h->R[k] = csr_copy(&old->R[k]);
+        Csr ap = csr_spgemm(&h->A[k], &h->P[k]);
+        h->A[k + 1] = csr_spgemm(&h->R[k], &ap);
+        csr_free(&ap);
+        if (old->label[k + 1]) {
+            h->label[k + 1] = (int *)xmalloc((size_t)nc * sizeof(int));
+            memcpy(h->label[k + 1], old->label[k + 1], (size_t)nc * sizeof(int));
+        }
+        int st = amg_l1_diag(h, k);
+        if (st != ORC_OK) status = st;
+    }
+    *out = h;
+    return amg_finish(h, k, status);
+}
+
+/* An independent copy of a whole hierarchy (kept as is when its matrix does
+ * not change). */
+static Amg *amg_clone(const Amg *old) {
+    Amg *h = (Amg *)xcalloc(1, sizeof(Amg));
+    h->nu_pre = old->nu_pre; h->nu_post = old->nu_post;
+    h->nlev = old->nlev; h->nc = old->nc;
+    for (int k = 0; k < old->nlev; ++k) {
+        int n = old->A[k].nr;
+        h->A[k] = csr_copy(&old->A[k]);
+        h->AT[k] = csr_copy(&old->AT[k]);
+        if (old->label[k]) {
+            h->label[k] = (int *)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(int));
+            memcpy(h->label[k], old->label[k], (size_t)n * sizeof(int));
+        }
+        if (k + 1 < old->nlev) {
+            h->P[k] = csr_copy(&old->P[k]);
+            h->R[k] = csr_copy(&old->R[k]);
+            h->cf[k] = (int *)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(int));
+            memcpy(h->cf[k], old->cf[k], (size_t)n * sizeof(int));
+            h->dl1[k] = (double *)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+            memcpy(h->dl1[k], old->dl1[k], (size_t)n * sizeof(double));
+        }
+    }
+    h->wb = (double **)xcalloc((size_t)h->nlev, sizeof(double *));
+    h->wx = (double **)xcalloc((size_t)h->nlev, sizeof(double *));
+    h->wr = (double **)xcalloc((size_t)h->nlev, sizeof(double *));
+    for (int l = 0; l < h->nlev; ++l) {
+        h->wb[l] = (double *)xcalloc((size_t)h->A[l].nr + 1, sizeof(double));
+        h->wx[l] = (double *)xcalloc((size_t)h->A[l].nr + 1, sizeof(double));
+        h->wr[l] = (double *)xcalloc((size_t)h->A[l].nr + 1, sizeof(double));
+    }
+    if (old->lu) {
+        h->lu = (double *)xmalloc((size_t)old->nc * old->nc * sizeof(double));
+        memcpy(h->lu, old->lu, (size_t)old->nc * old->nc * sizeof(double));
+        h->piv = (int *)xmalloc((size_t)old->nc * sizeof(int));
+        memcpy(h->piv, old->piv, (size_t)old->nc * sizeof(int));
+    }
+    return h;
 }
 
 /* One L1-Jacobi sweep x <- x + D_l1^{-1} (b - A x) (Baker et al. 2011); the
@@ -832,7 +923,8 @@ typedef struct {
  *   A_c = R A P = A_CC + A_CF P_F + R_F A_FC + R_F (A_FF P_F),
  * summed in that order. */
 static int mgr_setup_level(MgrLevel *l, const Csr *a, const int *field, const LevelOpts *lo, int bsize,
-                           const int *global_block, const AmgOpts *ao, uint64_t amg_seed) {
+                           const int *global_block, const AmgOpts *ao, uint64_t amg_seed, const Amg *famg_old,
+                           int keep_famg) {
     int n = a->nr;
     l->n = n;
     l->A = csr_copy(a);
@@ -879,13 +971,20 @@ static int mgr_setup_level(MgrLevel *l, const Csr *a, const int *field, const Le
             status = ilu0_factor(&l->AFF, &l->ilu, &l->ilu_diag);
             if (status != ORC_OK) return status;
         } else if (l->frelax == FRELAX_AMG) {
-            AmgOpts fo = *ao;
-            fo.unknown_based = lo->amg_unknown_based;
-            fo.seed = amg_seed;
-            int *flab = (int *)xmalloc((size_t)nF * sizeof(int));
-            for (int k = 0; k < nF; ++k) flab[k] = field[l->fmap[k]];
-            status = amg_setup(&l->AFF, flab, &fo, &l->famg);
-            free(flab);
+            if (famg_old && keep_famg) {
+                /* A_FF unchanged (the mechanics block between Newton solves, Sec. 3.3) */
+                l->famg = amg_clone(famg_old);
+            } else if (famg_old) {
+                status = amg_reuse(&l->AFF, famg_old, &l->famg);
+            } else {
+                AmgOpts fo = *ao;
+                fo.unknown_based = lo->amg_unknown_based;
+                fo.seed = amg_seed;
+                int *flab = (int *)xmalloc((size_t)nF * sizeof(int));
+                for (int k = 0; k < nF; ++k) flab[k] = field[l->fmap[k]];
+                status = amg_setup(&l->AFF, flab, &fo, &l->famg);
+                free(flab);
+            }
             if (status != ORC_OK) return status;
         } else {
             return ORC_ERR_ARG;
@@ -1134,11 +1233,46 @@ static void h_prec(void *ctx, const double *x, double *y) {
 /* Build the oracle's MGR hierarchy.  Inputs: block-CSR (b = 1 is plain CSR),
  * the field label of every scalar unknown, per-level F-field bitmasks and
  * options, and the AMG options for the final coarse system. */
+static void *setup_impl(int b, int nbr, const int *rp, const int *ci, const double *val, const int *field,
+                        int nlevels, const unsigned *fmask, const int *frelax, const int *sweeps,
+                        const double *omega, const int *restrict_type, const int *amg_unknown_based_lvl,
+                        double theta, int max_levels, int max_coarse, int nu_pre, int nu_post,
+                        int coarse_unknown_based, unsigned long long seed, const void *reuse_from, int keep_famg,
+                        int *status);
+
 void *orc_setup(int b, int nbr, const int *rp, const int *ci, const double *val, const int *field, int nlevels,
                 const unsigned *fmask, const int *frelax, const int *sweeps, const double *omega,
                 const int *restrict_type, const int *amg_unknown_based_lvl, double theta, int max_levels,
                 int max_coarse, int nu_pre, int nu_post, int coarse_unknown_based, unsigned long long seed,
                 int *status) {
+    return setup_impl(b, nbr, rp, ci, val, field, nlevels, fmask, frelax, sweeps, omega, restrict_type,
+                      amg_unknown_based_lvl, theta, max_levels, max_coarse, nu_pre, nu_post, coarse_unknown_based,
+                      seed, NULL, 0, status);
+}
+
+/* Setup reuse for new values on the same pattern (the AMG data reuse between
+ * Newton solves of Sec. 3.3 and 5): the MGR levels are formed again; every AMG
+ * hierarchy (the coarse one and those used as F-relaxation) keeps the C/F
+ * splits and interpolation of `old` and forms its Galerkin products anew, or,
+ * with keep_famg, the F-relaxation hierarchies are kept whole (their A_FF is
+ * unchanged).  The other arguments must be those `old` was set up with. */
+void *orc_update(const void *old, int b, int nbr, const int *rp, const int *ci, const double *val, const int *field,
+                 int nlevels, const unsigned *fmask, const int *frelax, const int *sweeps, const double *omega,
+                 const int *restrict_type, const int *amg_unknown_based_lvl, double theta, int max_levels,
+                 int max_coarse, int nu_pre, int nu_post, int coarse_unknown_based, unsigned long long seed,
+                 int keep_famg, int *status) {
+    return setup_impl(b, nbr, rp, ci, val, field, nlevels, fmask, frelax, sweeps, omega, restrict_type,
+                      amg_unknown_based_lvl, theta, max_levels, max_coarse, nu_pre, nu_post, coarse_unknown_based,
+                      seed, old, keep_famg, status);
+}
+
+static void *setup_impl(int b, int nbr, const int *rp, const int *ci, const double *val, const int *field,
+                        int nlevels, const unsigned *fmask, const int *frelax, const int *sweeps,
+                        const double *omega, const int *restrict_type, const int *amg_unknown_based_lvl,
+                        double theta, int max_levels, int max_coarse, int nu_pre, int nu_post,
+                        int coarse_unknown_based, unsigned long long seed, const void *reuse_from, int keep_famg,
+                        int *status) {
+    const Handle *old = (const Handle *)reuse_from;
     Handle *h = (Handle *)xcalloc(1, sizeof(Handle));
     h->b = b; h->nbr = nbr;
     h->A0 = bsr_expand(b, nbr, nbr, rp, ci, val);
@@ -1161,8 +1295,9 @@ void *orc_setup(int b, int nbr, const int *rp, const int *ci, const double *val,
                         fmask[lev]};
         MgrLevel *l = &m->L[lev];
         m->nlev = lev + 1;
+        const Amg *fold = (old && lev < old->mgr->nlev) ? old->mgr->L[lev].famg : NULL;
         int st = mgr_setup_level(l, &cur, cfield, &lo, b, cblock, &ao,
-                                 (uint64_t)seed + 0x1000193ULL * (uint64_t)(lev + 1));
+                                 (uint64_t)seed + 0x1000193ULL * (uint64_t)(lev + 1), fold, keep_famg);
         if (st != ORC_OK) { *status = st; break; }
         Csr ac;
         mgr_coarse_product(l, &ac);
@@ -1180,7 +1315,8 @@ void *orc_setup(int b, int nbr, const int *rp, const int *ci, const double *val,
     m->Acoarse = cur;
     m->coarse_field = cfield;
     if (*status == ORC_OK) {
-        int st = amg_setup(&m->Acoarse, cfield, &ao, &m->camg);
+        int st = (old && old->mgr->camg) ? amg_reuse(&m->Acoarse, old->mgr->camg, &m->camg)
+                                         : amg_setup(&m->Acoarse, cfield, &ao, &m->camg);
         if (st != ORC_OK) *status = st;
     }
     m->wv = (double **)xcalloc((size_t)m->nlev + 1, sizeof(double *));

@@ -28,7 +28,7 @@ STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_ARG", -2: "ERR_HIP", -3: "ERR_ZE
 
 EXPORTED = ["mgr_default_opts", "mgr_create", "mgr_set_opts", "mgr_setup", "mgr_apply", "mgr_apply_transpose",
             "mgr_matvec", "mgr_solve", "mgr_solve_transpose", "mgr_grad_values", "mgr_hierarchy_info",
-            "mgr_export", "mgr_last_error", "mgr_destroy"]
+            "mgr_export", "mgr_last_error", "mgr_destroy", "mgr_update_values"]
 
 
 class MgrError(RuntimeError):
@@ -80,6 +80,7 @@ def lib():
         L.mgr_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(mgr_opts), P]
         L.mgr_set_opts.argtypes = [P, ctypes.POINTER(mgr_opts)]
         L.mgr_setup.argtypes = [P, ctypes.POINTER(mgr_matrix), P, i32, ctypes.POINTER(mgr_level_opts)]
+        L.mgr_update_values.argtypes = [P, P, i32]
         L.mgr_apply.argtypes = [P, P, P]
         L.mgr_apply_transpose.argtypes = [P, P, P]
         L.mgr_matvec.argtypes = [P, i32, P, P]
@@ -188,6 +189,15 @@ class Solver:
                                     int(bool(lv.get("amg_unknown_based", False))))
         self._check(lib().mgr_setup(self._h, ctypes.byref(A), ctypes.c_void_p(self.field.data_ptr()),
                                     len(self.levels), arr))
+
+    def update_values(self, vals, keep_frelax_amg=False):
+        """Setup reuse for new values on the same pattern (mgr_update_values):
+        AMG C/F splits and interpolation are kept, or, with keep_frelax_amg,
+        the F-relaxation AMG hierarchies whole."""
+        torch = _torch()
+        self.vals = _dev(vals, torch.float64)
+        self._check(lib().mgr_update_values(self._h, ctypes.c_void_p(self.vals.data_ptr()),
+                                            1 if keep_frelax_amg else 0))
 
     def set_opts(self, **kw):
         self._fill_opts(**kw)

@@ -398,6 +398,56 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
     H.have_trans = false;
 }
 
+// Setup reuse for new values of the level-0 matrix: C/F splits, labels,
+// interpolation P and R = P^T of every level are kept; the Galerkin products
+// A_{k+1} = P^T (A_k P), L1 diagonals, composed operators and the coarsest
+// inverse are formed again (same products and order as amg_setup).
+static void amg_refresh(Amg& H, DCsr A0, Slots& S) {
+    hipStream_t s = S.s;
+    if (H.lv.empty() || A0.nr != H.lv[0].n) throw Error(MGR_ERR_ARG, "AMG reuse: level-0 size changed");
+    H.lv[0].A = std::move(A0);
+    const int nl = (int)H.lv.size();
+    for (int k = 0; k + 1 < nl; ++k) {
+        AmgLevel& L = H.lv[k];
+        L.AT = DCsr();
+        L.G = DCsr(); L.W = DCsr(); L.Q = DCsr(); L.WQ = DCsr(); L.Qt = DCsr(); L.WGt = DCsr();
+        L.dinvf.reset();
+        DCsr AP, Ac;
+        Spgemm j1;
+        spgemm_begin(j1, L.A, L.P, AP, S);
+        S.sync("AMG Galerkin product");
+        spgemm_finish(j1, S);
+        Spgemm j2, j3;
+        spgemm_begin(j2, L.R, AP, Ac, S);
+        if (L.composed) spgemm_begin(j3, L.R, L.A, L.RA, S);
+        L.dinv.alloc((size_t)L.n, s);
+        l1_dinv(L.A, L.dinv.p, S.flag(), s);
+        S.sync("AMG Galerkin product");
+        spgemm_finish(j2, S);
+        if (L.composed) {
+            spgemm_finish(j3, S);
+            L.AP = std::move(AP);
+        }
+        H.lv[k + 1].A = std::move(Ac);
+    }
+    H.lv.back().AT = DCsr();
+    for (int k = 0; k + 1 < nl; ++k)
+        if (H.lv[k].composed) amg_compose_begin(H.lv[k], S);
+    int nc = H.nc;
+    DArr<double> dense((size_t)nc * nc + 1, s);
+    H.cinv.alloc((size_t)nc * nc + 1, s);
+    densify(H.lv.back().A, dense.p, s);
+    dense_inverse(nc, dense.p, H.cinv.p, S.flag(), s);
+    S.sync("AMG coarsest inverse");
+    for (int k = 0; k + 1 < nl; ++k)
+        if (H.lv[k].composed) amg_compose_finish(H.lv[k], S);
+    H.cinvT.reset();
+    H.cinvf.reset();
+    H.cinvTf.reset();
+    H.have_float = false;
+    H.have_trans = false;
+}
+
 static void amg_make_float(Amg& H, hipStream_t s) {
     if (H.have_float) return;
     for (size_t l = 0; l < H.lv.size(); ++l) {
@@ -650,6 +700,13 @@ struct Ctx {
     std::vector<MgrLevel> L;
     Amg camg;
     Slots slots;
+    // setup inputs kept for mgr_update_values: field labels and level options
+    DArr<int> field0;
+    std::vector<mgr_level_opts> lvl;
+    // hierarchies handed from the previous setup to the one being formed
+    std::vector<std::unique_ptr<Amg>> reuse_famg;
+    std::unique_ptr<Amg> reuse_camg;
+    bool reuse_keep_famg = false;
     // Krylov workspace
     int kr_m = 0;
     long kr_n = 0;
@@ -743,7 +800,12 @@ static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr& A, const int* field
         split_fill(LU, l.iluL, l.iluU, s);
         l.schU = level_schedule(l.iluU, false, S);
     }
-    if (o.frelax == MGR_FRELAX_AMG) {
+    if (o.frelax == MGR_FRELAX_AMG && lev < (int)c.reuse_famg.size() && c.reuse_famg[lev]) {
+        // setup reuse: the previous hierarchy of this level, kept whole (A_FF
+        // unchanged) or with new Galerkin products
+        l.famg = std::move(c.reuse_famg[lev]);
+        if (!c.reuse_keep_famg) amg_refresh(*l.famg, csr_copy(l.AFF, s), S);
+    } else if (o.frelax == MGR_FRELAX_AMG) {
         l.famg.reset(new Amg());
         mgr_amg_opts fo = c.o.amg;
         fo.unknown_based = o.amg_unknown_based;
@@ -1212,6 +1274,8 @@ static int fgmres(Ctx& c, bool tr, const double* b, double* x, mgr_solve_info* i
 }
 
 // ====================================================================== setup
+static void build_hierarchy(Ctx& c);
+
 static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nlevels, const mgr_level_opts* lvl) {
     hipStream_t s = c.s;
     if (!A || !field) throw Error(MGR_ERR_ARG, "null matrix or field array");
@@ -1252,8 +1316,20 @@ static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nle
         bsr_expand(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, c.Av.p, c.A0.rp.p, c.A0.ci.p, c.A0.v.p, s);
     }
     c.A0.max_row = max_row_len(c.A0, s);
+    c.field0.alloc((size_t)c.n, s);
+    MGR_HIP(hipMemcpyAsync(c.field0.p, field, sizeof(int) * c.n, hipMemcpyDeviceToDevice, s));
+    c.lvl.assign(lvl, lvl + nlevels);
+    build_hierarchy(c);
+}
+
+// The MGR levels and the coarse AMG on the current input (c.A0, c.field0, c.lvl);
+// AMG hierarchies found in c.reuse_* are reused instead of coarsened again.
+static void build_hierarchy(Ctx& c) {
+    hipStream_t s = c.s;
+    const int nlevels = (int)c.lvl.size();
+    const mgr_level_opts* lvl = c.lvl.data();
     DArr<int> fld((size_t)c.n, s), blk((size_t)c.n, s);
-    MGR_HIP(hipMemcpyAsync(fld.p, field, sizeof(int) * c.n, hipMemcpyDeviceToDevice, s));
+    MGR_HIP(hipMemcpyAsync(fld.p, c.field0.p, sizeof(int) * c.n, hipMemcpyDeviceToDevice, s));
     iota_div(c.n, c.b, blk.p, s);
     const DCsr* cur = &c.A0;
     DCsr next;
@@ -1274,14 +1350,59 @@ static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nle
             cur = &next;
         }
     }
-    amg_setup(c.camg, nlevels > 0 ? std::move(next) : csr_copy(c.A0, s), c.o.amg.unknown_based ? fld.p : nullptr,
-              c.o.amg, c.o.amg.seed, c.slots);
+    if (c.reuse_camg) {
+        c.camg = std::move(*c.reuse_camg);
+        c.reuse_camg.reset();
+        amg_refresh(c.camg, nlevels > 0 ? std::move(next) : csr_copy(c.A0, s), c.slots);
+    } else {
+        amg_setup(c.camg, nlevels > 0 ? std::move(next) : csr_copy(c.A0, s),
+                  c.o.amg.unknown_based ? fld.p : nullptr, c.o.amg, c.o.amg.seed, c.slots);
+    }
+    c.reuse_famg.clear();
     if (c.o.apply_precision == 32) {
         for (auto& l : c.L) mgr_level_make_float(c, l);
         amg_make_float(c.camg, s);
     }
     MGR_HIP(hipStreamSynchronize(s));
     c.ready = true;
+}
+
+// Setup reuse (Sec. 3.3 and Sec. 5: AMG data reuse across Newton solves): new
+// values on the pattern of the last setup.  The MGR levels are formed again;
+// the coarse AMG keeps its C/F splits and interpolation and forms its Galerkin
+// products anew; the F-relaxation AMG hierarchies do the same, or are kept
+// whole with MGR_REUSE_KEEP_FRELAX_AMG (their A_FF unchanged).
+static void update_values(Ctx& c, const double* values, int flags) {
+    hipStream_t s = c.s;
+    if (!c.ready) throw Error(MGR_ERR_ARG, "update before setup");
+    if (!values) throw Error(MGR_ERR_ARG, "null values");
+    if (flags & ~MGR_REUSE_KEEP_FRELAX_AMG) throw Error(MGR_ERR_ARG, "unknown reuse flags");
+    c.ready = false;
+    long bb = (long)c.b * c.b;
+    MGR_HIP(hipMemcpyAsync(c.Av.p, values, sizeof(double) * c.nnzb * bb, hipMemcpyDeviceToDevice, s));
+    if (c.b == 1) {
+        MGR_HIP(hipMemcpyAsync(c.A0.v.p, c.Av.p, sizeof(double) * c.nnzb, hipMemcpyDeviceToDevice, s));
+    } else {
+        bsr_expand(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, c.Av.p, c.A0.rp.p, c.A0.ci.p, c.A0.v.p, s);
+    }
+    c.A0.vf.reset();
+    c.A0t = DCsr();
+    c.ATrp.reset(); c.ATci.reset(); c.ATv.reset();
+    c.have_At = false;
+    c.reuse_famg.clear();
+    c.reuse_famg.resize(c.L.size());
+    for (size_t l = 0; l < c.L.size(); ++l) c.reuse_famg[l] = std::move(c.L[l].famg);
+    c.reuse_camg.reset(new Amg(std::move(c.camg)));
+    c.reuse_keep_famg = (flags & MGR_REUSE_KEEP_FRELAX_AMG) != 0;
+    c.L.clear();
+    c.camg = Amg();
+    try {
+        build_hierarchy(c);
+    } catch (...) {
+        c.reuse_famg.clear();
+        c.reuse_camg.reset();
+        throw;
+    }
 }
 
 // ====================================================================== export
@@ -1442,6 +1563,13 @@ int mgr_setup(mgr_handle h, const mgr_matrix* A, const int32_t* field_of_dof, in
               const mgr_level_opts* lvl) {
     return guarded(h, [&]() {
         mgr::setup(h->c, A, field_of_dof, nlevels, lvl);
+        return MGR_OK;
+    });
+}
+
+int mgr_update_values(mgr_handle h, const double* values, int32_t flags) {
+    return guarded(h, [&]() {
+        mgr::update_values(h->c, values, flags);
         return MGR_OK;
     });
 }

@@ -24,6 +24,22 @@ SMALL = {
 }
 
 
+def perturbed_values(s, scale=0.05, seed=0, rows_field=None):
+    """New values on the same pattern, as between two Newton solves: every
+    scalar row scaled by 1 + U[-scale, scale] (only the rows whose unknown has
+    field rows_field, if given).  Row scaling keeps the sign structure of every
+    Schur complement the reduction forms."""
+    rng = np.random.default_rng(seed)
+    b, nb = s["b"], len(s["ci"])
+    f = 1.0 + rng.uniform(-scale, scale, s["n"])
+    if rows_field is not None:
+        f[s["field"] != rows_field] = 1.0
+    brow = np.repeat(np.arange(len(s["rp"]) - 1), np.diff(s["rp"]))        # block row of each block
+    rows = brow[:, None] * b + np.arange(b)[None, :]                        # scalar row of each block row
+    v = s["vals"].reshape(nb, b, b) * f[rows][:, :, None]
+    return v.reshape(-1)
+
+
 def _opts(s, kw):
     o = dict(s.get("solver_opts", {}))
     o.update(kw)

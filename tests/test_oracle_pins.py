@@ -13,6 +13,7 @@ import scipy.sparse as sp
 import oracle as O
 import workloads as W
 from oracle import LevelOpts
+from _systems import perturbed_values as _perturbed
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -511,3 +512,68 @@ def test_two_grid_amg_on_1d_laplacian_converges():
     m = build(s, levels=lv, max_coarse=16)
     x, info = m.solve(np.random.default_rng(1).standard_normal(n + 3), rtol=1e-10)
     assert info.status == 0 and info.iterations < 40
+
+
+# --------------------------------------------------------------------------- setup reuse (Sec. 3.3, Sec. 5)
+def test_reuse_with_unchanged_values_is_the_same_hierarchy():
+    s = W.two_field_tpfa(7, 6, 5, seed=11)
+    m = build(s)
+    m2 = m.update(s["vals"])
+    assert m2.status == 0 and m2.info() == m.info()
+    for k in range(len(m.info()["amg_levels"])):
+        a, b = m.export(1, k, 1), m2.export(1, k, 1)
+        assert np.array_equal(a.ci, b.ci) and np.array_equal(a.v, b.v)
+    v = np.random.default_rng(2).standard_normal(s["n"])
+    assert np.array_equal(m.apply(v), m2.apply(v))
+
+
+def test_reuse_keeps_interpolation_and_forms_galerkin_products_anew():
+    s = W.two_field_tpfa(9, 8, 7, seed=12)
+    m = build(s)
+    vals2 = _perturbed(s, seed=3)
+    s2 = dict(s, vals=vals2)
+    r = m.update(vals2)
+    fresh = build(s2)
+    assert r.status == 0
+    # MGR levels do not depend on the AMG: equal to a fresh setup, bit for bit
+    for what in (1, 2, 5):
+        a, b = r.export(0, 0, what), fresh.export(0, 0, what)
+        assert np.array_equal(a.ci, b.ci) and np.array_equal(a.v, b.v)
+    nl = len(m.info()["amg_levels"])
+    for k in range(nl - 1):
+        assert np.array_equal(r.export(1, k, 0), m.export(1, k, 0))          # C/F split kept
+        P = m.export(1, k, 2).to_scipy()
+        assert np.array_equal(r.export(1, k, 2).to_scipy().toarray(), P.toarray())   # P kept
+        Ak = r.export(1, k, 1).to_scipy()
+        expect = (P.T @ (Ak @ P)).toarray()                                  # Galerkin product of the new values
+        got = r.export(1, k + 1, 1).to_scipy().toarray()
+        np.testing.assert_allclose(got, expect, rtol=1e-12, atol=1e-12 * np.abs(expect).max())
+    x, info = r.solve(s2["rhs"])
+    A2 = W.csr_of(s2)
+    assert info.status == 0 and np.linalg.norm(s2["rhs"] - A2 @ x) <= 1e-8 * np.linalg.norm(s2["rhs"])
+
+
+def test_reuse_keeping_the_frelaxation_amg_whole_equals_a_fresh_setup():
+    # fracturing: only the fracture (pressure) rows change, so A_uu -- the F-block
+    # relaxed by AMG -- is the same and its whole hierarchy can be kept (Sec. 3.3)
+    s = W.fracturing(9, seed=5)
+    opts = s["solver_opts"]
+    m = build(s, **opts)
+    vals2 = _perturbed(s, seed=4, rows_field=3)
+    s2 = dict(s, vals=vals2)
+    r = m.update(vals2, keep_frelax_amg=True)
+    fresh = build(s2, **opts)
+    assert r.status == 0 and r.info() == fresh.info()
+    k = 0
+    while True:
+        try:
+            a = fresh.export(2, k, 1, sub=0)
+        except KeyError:
+            break
+        b = r.export(2, k, 1, sub=0)
+        assert np.array_equal(a.ci, b.ci) and np.array_equal(a.v, b.v)
+        k += 1
+    assert k >= 2
+    v = np.random.default_rng(5).standard_normal(s["n"])
+    assert np.array_equal(r.apply(v), fresh.apply(v)) or \
+        np.linalg.norm(r.apply(v) - fresh.apply(v)) <= 1e-12 * np.linalg.norm(fresh.apply(v))
