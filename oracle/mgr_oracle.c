@@ -241,6 +241,9 @@ static Csr csr_extract(const Csr *a, const int *rows, int nrows, const int *colm
 
 /* Expand a block-CSR matrix (b x b row-major blocks) to scalar CSR, keeping
  * every stored block entry (explicit zeros included). */
+/* Scalar CSR of a block-CSR matrix.  An exact zero inside a stored block is not
+ * an entry of the operator (it contributes to no product or sum), so it is
+ * left out, except on the diagonal, which is always stored. */
 static Csr bsr_expand(int b, int nbr, int nbc, const int *rp, const int *ci, const double *val) {
     long nnzb = rp[nbr];
     Csr a = csr_alloc(nbr * b, nbc * b, nnzb * b * b);
@@ -250,8 +253,11 @@ static Csr bsr_expand(int b, int nbr, int nbc, const int *rp, const int *ci, con
             int row = I * b + r;
             for (int p = rp[I]; p < rp[I + 1]; ++p)
                 for (int c = 0; c < b; ++c) {
-                    a.ci[o] = ci[p] * b + c;
-                    a.v[o] = val[(long)p * b * b + r * b + c];
+                    int col = ci[p] * b + c;
+                    double v = val[(long)p * b * b + r * b + c];
+                    if (v == 0.0 && col != row) continue;
+                    a.ci[o] = col;
+                    a.v[o] = v;
                     o++;
                 }
             a.rp[row + 1] = (int)o;

@@ -205,28 +205,6 @@ __global__ void k_gather_int(int n, const int* __restrict__ map, const int* __re
 // ------------------------------------------------------------------ block layout
 // Scalar row i = I*b + r holds, for each block of block row I in order, the b
 // entries of block row r: the same order the block values are stored in.
-__global__ void k_bsr_expand(int b, int nbr, const int* __restrict__ brp, const int* __restrict__ bci,
-                             const double* __restrict__ bv, int* __restrict__ rp, int* __restrict__ ci,
-                             double* __restrict__ v) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int n = nbr * b;
-    if (i >= n) return;
-    int I = i / b, r = i - I * b;
-    int p0 = brp[I], p1 = brp[I + 1];
-    long o = (long)p0 * b * b + (long)r * (p1 - p0) * b;
-    rp[i] = (int)o;
-    if (i == n - 1) rp[n] = (int)((long)brp[nbr] * b * b);
-    for (int p = p0; p < p1; ++p) {
-        int J = bci[p];
-        const double* blk = bv + (long)p * b * b + r * b;
-        for (int c = 0; c < b; ++c) {
-            ci[o] = J * b + c;
-            v[o] = blk[c];
-            ++o;
-        }
-    }
-}
-
 __global__ void k_bsr_tcount(long nnzb, const int* __restrict__ ci, int* __restrict__ cnt) {
     long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p < nnzb) atomicAdd(&cnt[ci[p]], 1);
@@ -1295,26 +1273,73 @@ __global__ __launch_bounds__(TPB) void k_extract_fill_g(int n, const int* __rest
 }
 
 // scalar row i = I*b + r of a block row: G lanes take the row's blocks
+// Scalar CSR of the block-CSR input without the exact zeros inside blocks
+// (the diagonal is always kept): per scalar row, a count pass, then a fill pass
+// in which each lane takes one block and places its kept entries after those of
+// the lanes before it (a segmented prefix sum over the group).
 template <int G>
-__global__ __launch_bounds__(TPB) void k_bsr_expand_g(int b, int nbr, const int* __restrict__ brp,
-                                                      const int* __restrict__ bci, const double* __restrict__ bv,
-                                                      int* __restrict__ rp, int* __restrict__ ci, double* __restrict__ v) {
+__global__ __launch_bounds__(TPB) void k_bsr_count_g(int b, int nbr, const int* __restrict__ brp,
+                                                     const int* __restrict__ bci, const double* __restrict__ bv,
+                                                     int* __restrict__ cnt) {
     Grp<G> g;
-    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
-    int n = nbr * b;
-    if (i >= n) return;
-    int I = i / b, r = i - I * b;
-    int p0 = brp[I], p1 = brp[I + 1];
-    long o = (long)p0 * b * b + (long)r * (p1 - p0) * b;
-    if (g.gl == 0) {
-        rp[i] = (int)o;
-        if (i == n - 1) rp[n] = (int)((long)brp[nbr] * b * b);
+    const int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    const int n = nbr * b;
+    int k = 0;
+    if (i < n) {
+        const int I = i / b, r = i - I * b;
+        for (int p = brp[I] + g.gl; p < brp[I + 1]; p += G) {
+            const int J = bci[p];
+            const double* blk = bv + (long)p * b * b + r * b;
+            for (int c = 0; c < b; ++c) k += (blk[c] != 0.0 || J * b + c == i) ? 1 : 0;
+        }
     }
-    for (int p = p0 + g.gl; p < p1; p += G) {
-        int J = bci[p];
-        const double* blk = bv + (long)p * b * b + r * b;
-        long q = o + (long)(p - p0) * b;
-        for (int c = 0; c < b; ++c) { ci[q + c] = J * b + c; v[q + c] = blk[c]; }
+    k = g.sum(k);
+    if (i < n && g.gl == 0) cnt[i] = k;
+}
+
+template <int G>
+__global__ __launch_bounds__(TPB) void k_bsr_fill_g(int b, int nbr, const int* __restrict__ brp,
+                                                    const int* __restrict__ bci, const double* __restrict__ bv,
+                                                    const int* __restrict__ rp, int* __restrict__ ci,
+                                                    double* __restrict__ v) {
+    Grp<G> g;
+    const int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    const int n = nbr * b;
+    const bool valid = i < n;
+    int p0 = 0, p1 = 0, o = 0, I = 0, r = 0;
+    if (valid) {
+        I = i / b;
+        r = i - I * b;
+        p0 = brp[I];
+        p1 = brp[I + 1];
+        o = rp[i];
+    }
+    const int wl = wave_max_int(p1 - p0);
+    for (int base = 0; base < wl; base += G) {
+        const int p = p0 + base + g.gl;
+        const bool act = valid && p < p1;
+        int J = 0, keep = 0;
+        const double* blk = bv;
+        if (act) {
+            J = bci[p];
+            blk = bv + (long)p * b * b + r * b;
+            for (int c = 0; c < b; ++c) keep += (blk[c] != 0.0 || J * b + c == i) ? 1 : 0;
+        }
+        int incl = keep;
+        for (int off = 1; off < G; off <<= 1) {
+            int t = __shfl_up(incl, off, G);
+            if (g.gl >= off) incl += t;
+        }
+        if (act) {
+            int q = o + incl - keep;
+            for (int c = 0; c < b; ++c)
+                if (blk[c] != 0.0 || J * b + c == i) {
+                    ci[q] = J * b + c;
+                    v[q] = blk[c];
+                    ++q;
+                }
+        }
+        o += __shfl(incl, g.gbase + G - 1, WAVE);
     }
 }
 
@@ -1901,12 +1926,21 @@ void iota_div(int n, int b, int* out, hipStream_t s) {
     MGR_LAUNCH_CHECK();
 }
 
-void bsr_expand(int b, int nbr, long nnzb, const int* brp, const int* bci, const double* bv, int* rp, int* ci,
-                double* v, hipStream_t s) {
-    int n = nbr * b;
-    if (n <= 0) return;
+void bsr_count(int b, int nbr, long nnzb, const int* brp, const int* bci, const double* bv, int* cnt,
+               hipStream_t s) {
+    if (nbr <= 0) return;
+    long n = (long)nbr * b;
     int G = group_for((int)((nnzb + nbr - 1) / nbr));
-    MGR_DISPATCH_G4(G, (k_bsr_expand_g<GG><<<grid_for(n, GG), TPB, 0, s>>>(b, nbr, brp, bci, bv, rp, ci, v)));
+    MGR_DISPATCH_G4(G, (k_bsr_count_g<GG><<<grid_for(n, GG), TPB, 0, s>>>(b, nbr, brp, bci, bv, cnt)));
+    MGR_LAUNCH_CHECK();
+}
+
+void bsr_fill(int b, int nbr, long nnzb, const int* brp, const int* bci, const double* bv, DCsr& A, hipStream_t s) {
+    if (nbr <= 0) return;
+    long n = (long)nbr * b;
+    int G = group_for((int)((nnzb + nbr - 1) / nbr));
+    MGR_DISPATCH_G4(G, (k_bsr_fill_g<GG><<<grid_for(n, GG), TPB, 0, s>>>(b, nbr, brp, bci, bv, A.rp.p, A.ci.p,
+                                                                           A.v.p)));
     MGR_LAUNCH_CHECK();
 }
 

@@ -24,8 +24,12 @@ int read_int(const int* dptr, hipStream_t s);
 void flag_clear(int* flag, hipStream_t s);
 int flag_read(const int* flag, hipStream_t s);
 
-void bsr_expand(int b, int nbr, long nnzb, const int* brp, const int* bci, const double* bv, int* rp, int* ci,
-                double* v, hipStream_t s);
+// Scalar CSR of the block-CSR input without exact zeros inside blocks (the
+// diagonal is always kept): row lengths, then (rows allocated from their scan)
+// the entries.
+void bsr_count(int b, int nbr, long nnzb, const int* brp, const int* bci, const double* bv, int* cnt,
+               hipStream_t s);
+void bsr_fill(int b, int nbr, long nnzb, const int* brp, const int* bci, const double* bv, DCsr& A, hipStream_t s);
 void bsr_transpose_blocks(int b, int nbr, const int* rp, const int* ci, const double* v, int* trp, int* tci,
                           double* tv, hipStream_t s);
 

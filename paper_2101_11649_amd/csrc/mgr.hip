@@ -1276,6 +1276,18 @@ static int fgmres(Ctx& c, bool tr, const double* b, double* x, mgr_solve_info* i
 // ====================================================================== setup
 static void build_hierarchy(Ctx& c);
 
+// Scalar level-0 operator from the block-CSR input (exact zeros inside blocks
+// left out, the diagonal kept).
+static void expand_input(Ctx& c) {
+    hipStream_t s = c.s;
+    DArr<int> cnt((size_t)c.n + 1, s);
+    bsr_count(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, c.Av.p, cnt.p, s);
+    Pend pe = csr_begin(c.A0, c.n, c.n, cnt.p, c.slots);
+    c.slots.sync("input matrix");
+    csr_finish(pe, c.slots);
+    bsr_fill(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, c.Av.p, c.A0, s);
+}
+
 static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nlevels, const mgr_level_opts* lvl) {
     hipStream_t s = c.s;
     if (!A || !field) throw Error(MGR_ERR_ARG, "null matrix or field array");
@@ -1306,16 +1318,7 @@ static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nle
     MGR_HIP(hipMemcpyAsync(c.Aci.p, A->col_idx, sizeof(int) * c.nnzb, hipMemcpyDeviceToDevice, s));
     MGR_HIP(hipMemcpyAsync(c.Av.p, A->values, sizeof(double) * c.nnzb * bb, hipMemcpyDeviceToDevice, s));
     if (c.nnzb * bb > INT_MAX) throw Error(MGR_ERR_UNSUPPORTED, "more than 2^31 scalar entries");
-    // scalar operator of level 0
-    c.A0.alloc(c.n, c.n, c.nnzb * bb, s);
-    if (c.b == 1) {
-        MGR_HIP(hipMemcpyAsync(c.A0.rp.p, c.Arp.p, sizeof(int) * ((size_t)c.n + 1), hipMemcpyDeviceToDevice, s));
-        MGR_HIP(hipMemcpyAsync(c.A0.ci.p, c.Aci.p, sizeof(int) * c.nnzb, hipMemcpyDeviceToDevice, s));
-        MGR_HIP(hipMemcpyAsync(c.A0.v.p, c.Av.p, sizeof(double) * c.nnzb, hipMemcpyDeviceToDevice, s));
-    } else {
-        bsr_expand(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, c.Av.p, c.A0.rp.p, c.A0.ci.p, c.A0.v.p, s);
-    }
-    c.A0.max_row = max_row_len(c.A0, s);
+    expand_input(c);
     c.field0.alloc((size_t)c.n, s);
     MGR_HIP(hipMemcpyAsync(c.field0.p, field, sizeof(int) * c.n, hipMemcpyDeviceToDevice, s));
     c.lvl.assign(lvl, lvl + nlevels);
@@ -1380,12 +1383,7 @@ static void update_values(Ctx& c, const double* values, int flags) {
     c.ready = false;
     long bb = (long)c.b * c.b;
     MGR_HIP(hipMemcpyAsync(c.Av.p, values, sizeof(double) * c.nnzb * bb, hipMemcpyDeviceToDevice, s));
-    if (c.b == 1) {
-        MGR_HIP(hipMemcpyAsync(c.A0.v.p, c.Av.p, sizeof(double) * c.nnzb, hipMemcpyDeviceToDevice, s));
-    } else {
-        bsr_expand(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, c.Av.p, c.A0.rp.p, c.A0.ci.p, c.A0.v.p, s);
-    }
-    c.A0.vf.reset();
+    expand_input(c);
     c.A0t = DCsr();
     c.ATrp.reset(); c.ATci.reset(); c.ATv.reset();
     c.have_At = false;
