@@ -11,6 +11,10 @@ constexpr int KRYLOV_PARTS = 2048;
 // CSR-stream SpMV: nominal nonzeros per row block, and the LDS stage size.
 constexpr int SPMV_CHUNK = 1024;
 constexpr int SPMV_LDS = 2048;
+// a row counts as 1/SPMV_ROW_COST of a nonzero when rows are cut into blocks,
+// so a block never holds more than SPMV_CHUNK * SPMV_ROW_COST rows (matrices
+// with many empty rows, such as an interpolation onto a few wells)
+constexpr int SPMV_ROW_COST = 4;
 
 // Read-only view of a CSR operator in value type T with its SpMV group size
 // (lanes per row, chosen from the average row length).
@@ -26,7 +30,7 @@ struct SpOp {
 };
 
 // number of row blocks of an operator with nnz entries, and their boundaries
-int rowblock_count(long nnz);
+int rowblock_count(int nr, long nnz);
 void rowblocks(int nr, long nnz, const int* rp, int* blk, hipStream_t s);
 
 template <typename T>
@@ -36,7 +40,7 @@ inline SpOp<T> view(const DCsr& A);
 inline void ensure_rowblocks(const DCsr& A) {
     if (A.blk.p || A.nr <= 0) return;
     DCsr& M = const_cast<DCsr&>(A);
-    M.nblk = rowblock_count(M.nnz);
+    M.nblk = rowblock_count(M.nr, M.nnz);
     M.blk.alloc((size_t)M.nblk + 1, M.rp.s);
     rowblocks(M.nr, M.nnz, M.rp.p, M.blk.p, M.rp.s);
 }

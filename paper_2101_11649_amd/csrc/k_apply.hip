@@ -25,8 +25,9 @@ __device__ inline T group_sum(T v, int G) {
 }
 
 // ---------------------------------------------------------------- CSR-stream SpMV
-// Rows are partitioned into row blocks whose first entries fall in one chunk of
-// SPMV_CHUNK nonzeros (rowblocks(), computed once per operator at setup).  A
+// Rows are partitioned into row blocks of about SPMV_CHUNK nonzeros, a row
+// itself counting as 1/SPMV_ROW_COST of a nonzero so that mostly empty rows
+// still spread over many blocks (rowblocks(), made once per operator).  A
 // workgroup streams its block's nonzeros with fully coalesced loads of the
 // values and column indices, forms the products in LDS, then reduces the rows:
 // one thread per row when the block holds many short rows, a power-of-two lane
@@ -157,10 +158,10 @@ __global__ void k_rowblocks(int nr, int nb, const int* __restrict__ rp, int* __r
     if (b > nb) return;
     if (b == nb) { blk[b] = nr; return; }
     long target = (long)b * SPMV_CHUNK;
-    int lo = 0, hi = nr;  // first row r in [0, nr] with rp[r] >= target
+    int lo = 0, hi = nr;  // first row r in [0, nr] with cost(r) >= target
     while (lo < hi) {
         int mid = (lo + hi) >> 1;
-        if (rp[mid] < target) lo = mid + 1;
+        if ((long)rp[mid] + mid / SPMV_ROW_COST < target) lo = mid + 1;
         else hi = mid;
     }
     blk[b] = lo;
@@ -469,10 +470,13 @@ int pick_group(double avg) {
         default: { constexpr int GG = 64; __VA_ARGS__; } break; \
     }
 
-int rowblock_count(long nnz) { return nnz > 0 ? (int)((nnz + SPMV_CHUNK - 1) / SPMV_CHUNK) : 1; }
+int rowblock_count(int nr, long nnz) {
+    long cost = nnz + (long)nr / SPMV_ROW_COST;
+    return cost > 0 ? (int)((cost + SPMV_CHUNK - 1) / SPMV_CHUNK) : 1;
+}
 
 void rowblocks(int nr, long nnz, const int* rp, int* blk, hipStream_t s) {
-    int nb = rowblock_count(nnz);
+    int nb = rowblock_count(nr, nnz);
     k_rowblocks<<<nblk(nb + 1), TPB, 0, s>>>(nr, nb, rp, blk);
     MGR_LAUNCH_CHECK();
 }
