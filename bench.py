@@ -59,6 +59,40 @@ def bsr_spmv_bytes(b, nbr, nnzb, s=8):
     return nnzb * (b * b * s + 4) + 4 * (nbr + 1) + 2 * n * 8
 
 
+def row_scaled(sysd, scale=0.05, seed=0, rows_field=None):
+    """New values on the same pattern, as between two Newton solves: scalar rows
+    scaled by 1 + U[-scale, scale] (only rows of field rows_field, if given)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    b, nb = sysd["b"], len(sysd["ci"])
+    f = 1.0 + rng.uniform(-scale, scale, sysd["n"])
+    if rows_field is not None:
+        f[sysd["field"] != rows_field] = 1.0
+    brow = np.repeat(np.arange(len(sysd["rp"]) - 1), np.diff(sysd["rp"]))
+    rows = brow[:, None] * b + np.arange(b)[None, :]
+    return (sysd["vals"].reshape(nb, b, b) * f[rows][:, :, None]).reshape(-1)
+
+
+def time_reuse(solver, sysd, vals2, keep, reps=3):
+    """mgr_update_values with new values (setup reuse), then a solve."""
+    import torch
+    v2 = torch.tensor(vals2, device="cuda")
+    rhs = torch.tensor(sysd["rhs"], device="cuda")
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solver.update_values(v2, keep_frelax_amg=keep)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    _, [info] = solver.solve(rhs)
+    torch.cuda.synchronize()
+    return {"update_s": round(statistics.mean(ts), 6), "solve_s": round(time.perf_counter() - t0, 6),
+            "iterations": info.iterations, "rel_res_true": info.rel_res_true,
+            "kept": "F-relaxation AMG hierarchies whole" if keep else "AMG C/F splits and interpolation"}
+
+
 def kernel_traffic(name):
     """HBM bytes per launch of `name` from the committed rocprofv3 counter summary
     (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None if the summary
@@ -139,6 +173,7 @@ def main():
     solver, rec64, X64, info64, stream = run_steps(P, s, vals, rhs, 64, args.steps, args.warmup)
     solver32, rec32, X32, info32, _ = run_steps(P, s, vals, rhs, 32, args.steps, args.warmup)
 
+    reuse64 = time_reuse(solver, s, row_scaled(s, seed=11), False)
     tot64 = [a + b for a, b, _, _ in rec64]
     tot32 = [a + b for a, b, _, _ in rec32]
     value = statistics.mean(tot64)
@@ -171,7 +206,7 @@ def main():
     t_ap64, _ = time_kernel(ap64, stream, 20, flush)
     t_ap32, _ = time_kernel(ap32, stream, 20, flush)
 
-    def secondary(sysd, steps, mgr_desc, apply_reps, roof=None):
+    def secondary(sysd, steps, mgr_desc, apply_reps, roof=None, reuse=None):
         """FP64 and FP32 apply on one more workload: time to 1e-8, per-apply time
         (cache flushed), and optionally the roofline of its FGMRES matvec."""
         vv_ = torch.tensor(sysd["vals"], device="cuda")
@@ -207,6 +242,9 @@ def main():
                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                 "frac": round(bb / t_mv / 1e9 / HBM_PEAK_GBS, 4), "traffic": kernel_traffic(roof[1]),
                                 "bytes_per_launch": bb, "avg_launch_us": round(1e6 * t_mv, 2)}
+        if reuse is not None:
+            # setup reuse after a value change (rows of field reuse[0] scaled; reuse[1] = keep flag)
+            out_["setup_reuse"] = time_reuse(s64, sysd, row_scaled(sysd, seed=11, rows_field=reuse[0]), reuse[1])
         s64.close()
         s32.close()
         return out_
@@ -233,7 +271,7 @@ def main():
         log("generating fracturing 96^3 ...")
         frac = secondary(W.fracturing(96, seed=3), args.frac_steps,
                          "F = displacements (unknown-based AMG V(2,2) F-relaxation), C = fracture pressures -> AMG",
-                         5)
+                         5, reuse=(3, True))
 
     # ---- FP64 oracle on the machine's host cores (bounded sample: one full setup + solve of this workload)
     cpu = None
@@ -275,6 +313,7 @@ def main():
         "iterations": rec64[-1][2],
         "rel_res_true": rec64[-1][3],
         "x_rel_err_vs_oracle": x_err64,
+        "setup_reuse": reuse64,
         "fp32_apply": {
             "time_to_tol_s": round(statistics.mean(tot32), 6),
             "setup_s": round(statistics.mean(a for a, _, _, _ in rec32), 6),

@@ -1216,6 +1216,112 @@ __global__ __launch_bounds__(TPB) void k_add_g(int nr, const int* __restrict__ a
     }
 }
 
+// Numeric product with an LDS hash table per output row (a lane group of G
+// lanes per row, CAP >= 2 x the row's output length known from the symbolic
+// pass).  The entries of the row of A are taken one after another; for each,
+// the lanes insert the distinct columns of the matching row of B (linear
+// probing with an LDS compare-and-swap) and add a_ip * b_pj to the slot, so
+// every output value starts at 0.0 and adds its products in the order of A's
+// entries (Gustavson's order, as the merge).  The filled slots are then
+// gathered and written in column order by rank.
+constexpr int log2_pow2(int v) { return v <= 1 ? 0 : 1 + log2_pow2(v / 2); }
+
+template <int G, int CAP>
+__global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restrict__ arp,
+                                                     const int* __restrict__ aci, const double* __restrict__ av,
+                                                     const int* __restrict__ brp, const int* __restrict__ bci,
+                                                     const double* __restrict__ bv, const int* __restrict__ crp,
+                                                     int* __restrict__ cci, double* __restrict__ cv,
+                                                     int* __restrict__ flag) {
+    constexpr int NG = TPB / G;
+    constexpr int PER = CAP / G;
+    __shared__ int keys[NG][CAP];
+    __shared__ double vals[NG][CAP];
+    Grp<G> g;
+    const int grp = threadIdx.x / G;
+    const int row = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    const bool valid = row < nr;
+    int* K = keys[grp];
+    double* Vs = vals[grp];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        K[g.gl + G * u] = -1;
+        Vs[g.gl + G * u] = 0.0;
+    }
+    int a0 = 0, a1 = 0;
+    if (valid) {
+        a0 = arp[row];
+        a1 = arp[row + 1];
+    }
+    const int wl = wave_max_int(a1 - a0);
+    for (int base = 0; base < wl; base += G) {
+        // lane t holds entry base + t of the row of A
+        int kb0 = 0, kb1 = 0;
+        double ka = 0.0;
+        if (a0 + base + g.gl < a1) {
+            int k = aci[a0 + base + g.gl];
+            kb0 = brp[k];
+            kb1 = brp[k + 1];
+            ka = av[a0 + base + g.gl];
+        }
+        const int lim = min(G, wl - base);
+        for (int t = 0; t < lim; ++t) {
+            const int b0 = __shfl(kb0, g.gbase + t, WAVE);
+            const int b1 = __shfl(kb1, g.gbase + t, WAVE);
+            const double a = __shfl(ka, g.gbase + t, WAVE);
+            for (int q = b0 + g.gl; q < b1; q += G) {
+                const int j = bci[q];
+                const double prod = a * bv[q];
+                // multiplicative hash: the top log2(CAP) bits of j * 2654435761
+                int h = (int)(((unsigned)j * 2654435761u) >> (32 - log2_pow2(CAP)));
+                int probes = 0;
+                for (;;) {
+                    int old = atomicCAS(&K[h], -1, j);
+                    if (old == -1 || old == j) break;
+                    h = (h + 1) & (CAP - 1);
+                    if (++probes == CAP) { atomicMax(flag, 1); h = -1; break; }
+                }
+                if (h >= 0) Vs[h] = Vs[h] + prod;
+            }
+        }
+    }
+    // gather this lane's filled slots, place them after those of the lanes before it
+    int kk[PER];
+    double vv[PER];
+    int mine = 0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        kk[u] = K[g.gl + G * u];
+        vv[u] = Vs[g.gl + G * u];
+        mine += (kk[u] >= 0) ? 1 : 0;
+    }
+    int incl = mine;
+    for (int off = 1; off < G; off <<= 1) {
+        int t = __shfl_up(incl, off, G);
+        if (g.gl >= off) incl += t;
+    }
+    const int L = __shfl(incl, g.gbase + G - 1, WAVE);
+    int pos = incl - mine;
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+        if (kk[u] >= 0) {
+            K[pos] = kk[u];
+            Vs[pos] = vv[u];
+            ++pos;
+        }
+    // rank = number of smaller columns among the L gathered entries
+    if (valid) {
+        const int o = crp[row];
+        for (int e = g.gl; e < L; e += G) {
+            const int key = K[e];
+            int rank = 0;
+            for (int f = 0; f < L; ++f) rank += (K[f] < key) ? 1 : 0;
+            cci[o + rank] = key;
+            cv[o + rank] = Vs[e];
+        }
+    }
+}
+
 template <int G>
 __global__ __launch_bounds__(TPB) void k_extract_count_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                          const int* __restrict__ isF, const int* __restrict__ lmap,
@@ -2069,7 +2175,33 @@ void spgemm_count(const DCsr& A, const DCsr& B, int max_row, int* cnt, int* flag
     spgemm_launch<false>(A, B, max_row, nullptr, nullptr, nullptr, cnt, flag, s);
 }
 
-void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, hipStream_t s) {
+void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, int* flag, hipStream_t s) {
+    // hashed rows when the right factor is too wide for the dense LDS row and the
+    // output rows (known from the symbolic pass) fit a table of at most 512 slots
+    const bool dense = B.nc <= SPGEMM_DENSE && A.nr <= SPGEMM_DENSE_ROWS && (long)A.nr * B.nc <= SPGEMM_DENSE_WORK;
+    if (!dense && A.nr > 0 && C.max_row >= 0 && C.max_row <= 256 && B.max_row >= 0) {
+        int cap = 32;
+        while (cap < 2 * C.max_row) cap <<= 1;
+        int gb = 4;
+        while (gb < B.max_row && gb < 32) gb <<= 1;
+        int gl = (int)((long)cap * 12 * TPB / 65536);   // LDS: TPB / G tables of cap slots
+        int G = gb;
+        while (G < gl) G <<= 1;
+        if (G > 32) G = 32;
+#define MGR_HASH(GG, CC)                                                                                         \
+    k_spgemm_hash<GG, CC><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p, B.v.p, \
+                                                            C.rp.p, C.ci.p, C.v.p, flag)
+        switch (cap) {
+            case 32: if (G <= 4) MGR_HASH(4, 32); else if (G == 8) MGR_HASH(8, 32); else if (G == 16) MGR_HASH(16, 32); else MGR_HASH(32, 32); break;
+            case 64: if (G <= 4) MGR_HASH(4, 64); else if (G == 8) MGR_HASH(8, 64); else if (G == 16) MGR_HASH(16, 64); else MGR_HASH(32, 64); break;
+            case 128: if (G <= 8) MGR_HASH(8, 128); else if (G == 16) MGR_HASH(16, 128); else MGR_HASH(32, 128); break;
+            case 256: if (G <= 16) MGR_HASH(16, 256); else MGR_HASH(32, 256); break;
+            default: MGR_HASH(32, 512); break;
+        }
+#undef MGR_HASH
+        MGR_LAUNCH_CHECK();
+        return;
+    }
     spgemm_launch<true>(A, B, max_row, C.rp.p, C.ci.p, C.v.p, nullptr, nullptr, s);
 }
 

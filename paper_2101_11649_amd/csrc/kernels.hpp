@@ -59,7 +59,9 @@ int max_row_len(const DCsr& A, hipStream_t s);
 // columns) use a dense-row accumulator per output row instead of the merge.
 constexpr int SPGEMM_DENSE_COLS = 4096;
 void spgemm_count(const DCsr& A, const DCsr& B, int max_row, int* cnt, int* flag, hipStream_t s);
-void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, hipStream_t s);
+// C's row pointers and max_row come from the counts; a failure of the hashed
+// variant (a full table) sets *flag (an int in device memory).
+void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, int* flag, hipStream_t s);
 void add_count(const DCsr& A, const DCsr& B, int* cnt, hipStream_t s);
 void add_fill(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s);
 void negate(double* v, long n, hipStream_t s);

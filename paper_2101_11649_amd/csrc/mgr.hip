@@ -130,7 +130,7 @@ static void spgemm_begin(Spgemm& j, const DCsr& A, const DCsr& B, DCsr& C, Slots
 static void spgemm_finish(Spgemm& j, Slots& S) {
     if (S.val(j.lr) != 0) throw Error(MGR_ERR_ARG, "internal: spgemm row longer than its recorded length");
     csr_finish(j.pend, S);
-    spgemm_fill(*j.A, *j.B, j.A->max_row, *j.C, S.s);
+    spgemm_fill(*j.A, *j.B, j.A->max_row, *j.C, S.flag(), S.s);
     j.cnt.reset();
 }
 
