@@ -79,8 +79,8 @@ void presmooth(const SpOp<T>& A, const T* dinv, const T* b, T* x, T* r, hipStrea
 template <typename T>
 void presmooth_scaled(const SpOp<T>& A, const T* bd, const T* b, T* x, T* r, hipStream_t s);
 // y = A x and yd = dsc .* y (a restriction that also forms the next level's D^-1 b)
-template <typename T>
-void restrict_scaled(const SpOp<T>& A, const T* x, const T* dsc, T* y, T* yd, hipStream_t s);
+template <typename T, typename XT>
+void restrict_scaled(const SpOp<T>& A, const XT* x, const T* dsc, T* y, T* yd, hipStream_t s);
 // block-CSR y = alpha A x + beta w (FP64)
 void bsr_spmv(int bsize, int nbr, const int* rp, const int* ci, const double* v, long nnzb, const double* x,
               const double* w, double* y, double alpha, double beta, hipStream_t s);

@@ -67,11 +67,12 @@ struct PreOp {
     }
 };
 
-// RestrictOp  y = A x  and  yd = dsc .* y  (the next level's D^-1 b)
-template <typename T>
+// RestrictOp  y = A x  and  yd = dsc .* y  (the next level's D^-1 b); x may be
+// FP64 while the operator is FP32 (the first MGR restriction of the FP32 apply)
+template <typename T, typename XT>
 struct RestrictOp {
-    const T* x; const T* dsc; T* y; T* yd;
-    __device__ T xval(int c) const { return x[c]; }
+    const XT* x; const T* dsc; T* y; T* yd;
+    __device__ T xval(int c) const { return (T)x[c]; }
     __device__ void done(int r, T s) const {
         y[r] = s;
         yd[r] = dsc[r] * s;
@@ -519,11 +520,11 @@ void presmooth_scaled(const SpOp<T>& A, const T* bd, const T* b, T* x, T* r, hip
     MGR_LAUNCH_CHECK();
 }
 
-template <typename T>
-void restrict_scaled(const SpOp<T>& A, const T* x, const T* dsc, T* y, T* yd, hipStream_t s) {
+template <typename T, typename XT>
+void restrict_scaled(const SpOp<T>& A, const XT* x, const T* dsc, T* y, T* yd, hipStream_t s) {
     if (A.nr <= 0) return;
     if (!A.blk) throw Error(-1, "restrict: operator without row blocks");
-    RestrictOp<T> op{x, dsc, y, yd};
+    RestrictOp<T, XT> op{x, dsc, y, yd};
     k_spmv_stream<T, 0><<<A.nblk, TPB, 0, s>>>(A.blk, A.rp, A.ci, A.v, op);
     MGR_LAUNCH_CHECK();
 }
@@ -681,9 +682,12 @@ template void presmooth<float>(const SpOp<float>&, const float*, const float*, f
 template void presmooth_scaled<double>(const SpOp<double>&, const double*, const double*, double*, double*,
                                        hipStream_t);
 template void presmooth_scaled<float>(const SpOp<float>&, const float*, const float*, float*, float*, hipStream_t);
-template void restrict_scaled<double>(const SpOp<double>&, const double*, const double*, double*, double*,
-                                      hipStream_t);
-template void restrict_scaled<float>(const SpOp<float>&, const float*, const float*, float*, float*, hipStream_t);
+template void restrict_scaled<double, double>(const SpOp<double>&, const double*, const double*, double*, double*,
+                                              hipStream_t);
+template void restrict_scaled<float, float>(const SpOp<float>&, const float*, const float*, float*, float*,
+                                            hipStream_t);
+template void restrict_scaled<float, double>(const SpOp<float>&, const double*, const float*, float*, float*,
+                                             hipStream_t);
 template void dense_gemv<double, double>(int, const double*, const double*, double*, hipStream_t);
 template void dense_gemv<float, float>(int, const float*, const float*, float*, hipStream_t);
 template void dense_gemv<float, double>(int, const float*, const double*, float*, hipStream_t);

@@ -385,10 +385,10 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
         AmgLevel& L = H.lv[l];
         L.rd.alloc((size_t)L.n + 1, s);
         L.td.alloc((size_t)L.n + 1, s);
+        L.sd.alloc((size_t)L.n + 1, s);
         if (l > 0) {
             L.bd.alloc((size_t)L.n + 1, s);
             L.xd.alloc((size_t)L.n + 1, s);
-            L.sd.alloc((size_t)L.n + 1, s);
         }
     }
     S.sync("AMG coarsest inverse");
@@ -471,10 +471,10 @@ static void amg_make_float(Amg& H, hipStream_t s) {
         if (H.have_trans && L.AT.nr && !L.composed) make_float(L.AT, s);
         L.rf.alloc((size_t)L.n + 1, s);
         L.tf.alloc((size_t)L.n + 1, s);
+        L.sf.alloc((size_t)L.n + 1, s);
         if (l > 0) {
             L.bf.alloc((size_t)L.n + 1, s);
             L.xf.alloc((size_t)L.n + 1, s);
-            L.sf.alloc((size_t)L.n + 1, s);
         }
     }
     long nn = (long)H.nc * H.nc;
@@ -594,7 +594,7 @@ static void amg_vcycle(Amg& H, int k, const T* b, T* x, bool tr, hipStream_t s, 
     // a plain (not composed, not coarsest) next level gets D^-1 b_c from the restriction
     if (npre >= 1 && !Lc.composed && k + 2 < (int)H.lv.size()) {
         T* sc = Prec<T>::sb(Lc);
-        restrict_scaled<T>(view<T>(L.R), r, Prec<T>::dinv(Lc), bc, sc, s);
+        restrict_scaled<T, T>(view<T>(L.R), r, Prec<T>::dinv(Lc), bc, sc, s);
         amg_vcycle<T>(H, k + 1, bc, xc, tr, s, sc);
     } else {
         spmv<T, T, T, T, T>(view<T>(L.R), r, (const T*)nullptr, INT_MAX, (const T*)nullptr, bc, T(1), T(0), s);
@@ -981,7 +981,16 @@ static void frelax_apply(MgrLevel& l, const T* rF, T* tF, bool tr, hipStream_t s
 }
 
 template <typename T>
-static void mgr_apply_rec(Ctx& c, int lev, const void* vin, void* zout, bool tr);
+static void mgr_apply_rec(Ctx& c, int lev, const void* vin, void* zout, bool tr, const void* bd = nullptr);
+
+// D^-1 of the first AMG level when the last MGR restriction can form D^-1 b
+// for its pre-smoothing (a plain level with a sweep), else null.
+template <typename T>
+static const T* amg_first_dinv(Ctx& c, bool tr) {
+    Amg& H = c.camg;
+    if (H.lv.size() < 2 || H.lv[0].composed || (tr ? H.nu_post : H.nu_pre) < 1) return nullptr;
+    return Prec<T>::dinv(H.lv[0]);
+}
 
 // Algorithm 1 at level `lev` with working precision T; VT is the type of v and
 // z at this level (FP64 at level 0, T below).
@@ -994,8 +1003,16 @@ static void mgr_level_apply(Ctx& c, int lev, const VT* v, VT* z, bool tr) {
     if (l.fused) {
         SpOp<T> R = view<T>(tr ? l.RJt : l.RJ);
         SpOp<T> P = view<T>(tr ? l.PJt : l.PJ);
-        spmv<T, VT, VT, T, T>(R, v, (const VT*)nullptr, INT_MAX, (const T*)nullptr, rc, T(1), T(0), s);
-        mgr_apply_rec<T>(c, lev + 1, rc, ec, tr);
+        const T* d0 = (lev + 1 == (int)c.L.size()) ? amg_first_dinv<T>(c, tr) : nullptr;
+        if (d0) {
+            // the coarse AMG's first pre-smoothing gathers D^-1 r_c formed here
+            T* sc = Prec<T>::sb(c.camg.lv[0]);
+            restrict_scaled<T, VT>(R, v, d0, rc, sc, s);
+            mgr_apply_rec<T>(c, lev + 1, rc, ec, tr, sc);
+        } else {
+            spmv<T, VT, VT, T, T>(R, v, (const VT*)nullptr, INT_MAX, (const T*)nullptr, rc, T(1), T(0), s);
+            mgr_apply_rec<T>(c, lev + 1, rc, ec, tr);
+        }
         spmv<T, T, VT, VT, VT>(P, ec, v, l.nC, (const VT*)nullptr, z, T(1), T(0), s);
         return;
     }
@@ -1046,9 +1063,9 @@ static void mgr_level_apply(Ctx& c, int lev, const VT* v, VT* z, bool tr) {
 }
 
 template <typename T>
-static void mgr_apply_rec(Ctx& c, int lev, const void* vin, void* zout, bool tr) {
+static void mgr_apply_rec(Ctx& c, int lev, const void* vin, void* zout, bool tr, const void* bd) {
     if (lev == (int)c.L.size()) {
-        amg_vcycle<T>(c.camg, 0, (const T*)vin, (T*)zout, tr, c.s);
+        amg_vcycle<T>(c.camg, 0, (const T*)vin, (T*)zout, tr, c.s, (const T*)bd);
         return;
     }
     if (lev == 0)
