@@ -1226,17 +1226,17 @@ __global__ __launch_bounds__(TPB) void k_add_g(int nr, const int* __restrict__ a
 // gathered and written in column order by rank.
 constexpr int log2_pow2(int v) { return v <= 1 ? 0 : 1 + log2_pow2(v / 2); }
 
-template <int G, int CAP>
+template <int G, int CAP, bool FILL>
 __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restrict__ arp,
                                                      const int* __restrict__ aci, const double* __restrict__ av,
                                                      const int* __restrict__ brp, const int* __restrict__ bci,
                                                      const double* __restrict__ bv, const int* __restrict__ crp,
                                                      int* __restrict__ cci, double* __restrict__ cv,
-                                                     int* __restrict__ flag) {
+                                                     int* __restrict__ cnt, int* __restrict__ flag) {
     constexpr int NG = TPB / G;
     constexpr int PER = CAP / G;
     __shared__ int keys[NG][CAP];
-    __shared__ double vals[NG][CAP];
+    __shared__ double vals[NG][FILL ? CAP : 1];
     Grp<G> g;
     const int grp = threadIdx.x / G;
     const int row = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
@@ -1246,7 +1246,7 @@ __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restri
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         K[g.gl + G * u] = -1;
-        Vs[g.gl + G * u] = 0.0;
+        if (FILL) Vs[g.gl + G * u] = 0.0;
     }
     int a0 = 0, a1 = 0;
     if (valid) {
@@ -1262,7 +1262,7 @@ __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restri
             int k = aci[a0 + base + g.gl];
             kb0 = brp[k];
             kb1 = brp[k + 1];
-            ka = av[a0 + base + g.gl];
+            if (FILL) ka = av[a0 + base + g.gl];
         }
         const int lim = min(G, wl - base);
         for (int t = 0; t < lim; ++t) {
@@ -1271,7 +1271,7 @@ __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restri
             const double a = __shfl(ka, g.gbase + t, WAVE);
             for (int q = b0 + g.gl; q < b1; q += G) {
                 const int j = bci[q];
-                const double prod = a * bv[q];
+                const double prod = FILL ? a * bv[q] : 0.0;
                 // multiplicative hash: the top log2(CAP) bits of j * 2654435761
                 int h = (int)(((unsigned)j * 2654435761u) >> (32 - log2_pow2(CAP)));
                 int probes = 0;
@@ -1281,9 +1281,17 @@ __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restri
                     h = (h + 1) & (CAP - 1);
                     if (++probes == CAP) { atomicMax(flag, 1); h = -1; break; }
                 }
-                if (h >= 0) Vs[h] = Vs[h] + prod;
+                if (FILL && h >= 0) Vs[h] = Vs[h] + prod;
             }
         }
+    }
+    if (!FILL) {
+        int mine = 0;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) mine += (K[g.gl + G * u] >= 0) ? 1 : 0;
+        mine = g.sum(mine);
+        if (valid && g.gl == 0) cnt[row] = mine;
+        return;
     }
     // gather this lane's filled slots, place them after those of the lanes before it
     int kk[PER];
@@ -2171,35 +2179,55 @@ static void spgemm_launch(const DCsr& A, const DCsr& B, int max_row, const int* 
     MGR_LAUNCH_CHECK();
 }
 
+
+static bool spgemm_dense_ok(const DCsr& A, const DCsr& B) {
+    return B.nc <= SPGEMM_DENSE && A.nr <= SPGEMM_DENSE_ROWS && (long)A.nr * B.nc <= SPGEMM_DENSE_WORK;
+}
+
+// Hashed rows with tables of cap slots (cap >= 32, a power of two <= 512).
+template <bool FILL>
+static void spgemm_hash_launch(const DCsr& A, const DCsr& B, int cap, const int* crp, int* cci, double* cv,
+                               int* cnt, int* flag, hipStream_t s) {
+    int gb = 4;
+    while (gb < B.max_row && gb < 32) gb <<= 1;
+    int gl = (int)((long)cap * 12 * TPB / 65536);   // LDS: TPB / G tables of cap slots
+    int G = gb;
+    while (G < gl) G <<= 1;
+    if (G > 32) G = 32;
+#define MGR_HASH(GG, CC)                                                                                          \
+    k_spgemm_hash<GG, CC, FILL><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p,  \
+                                                                  B.v.p, crp, cci, cv, cnt, flag)
+    switch (cap) {
+        case 32: if (G <= 4) MGR_HASH(4, 32); else if (G == 8) MGR_HASH(8, 32); else if (G == 16) MGR_HASH(16, 32); else MGR_HASH(32, 32); break;
+        case 64: if (G <= 4) MGR_HASH(4, 64); else if (G == 8) MGR_HASH(8, 64); else if (G == 16) MGR_HASH(16, 64); else MGR_HASH(32, 64); break;
+        case 128: if (G <= 8) MGR_HASH(8, 128); else if (G == 16) MGR_HASH(16, 128); else MGR_HASH(32, 128); break;
+        case 256: if (G <= 16) MGR_HASH(16, 256); else MGR_HASH(32, 256); break;
+        default: MGR_HASH(32, 512); break;
+    }
+#undef MGR_HASH
+    MGR_LAUNCH_CHECK();
+}
+
 void spgemm_count(const DCsr& A, const DCsr& B, int max_row, int* cnt, int* flag, hipStream_t s) {
+    // hashed rows when the right factor is too wide for the dense LDS row and
+    // every output row is bounded by A.max_row * B.max_row <= 256 distinct columns
+    if (!spgemm_dense_ok(A, B) && A.nr > 0 && B.max_row >= 0 && max_row >= 0 &&
+        (long)max_row * B.max_row <= 256) {
+        int cap = 32;
+        while (cap < max_row * B.max_row) cap <<= 1;
+        spgemm_hash_launch<false>(A, B, cap, nullptr, nullptr, nullptr, cnt, flag, s);
+        return;
+    }
     spgemm_launch<false>(A, B, max_row, nullptr, nullptr, nullptr, cnt, flag, s);
 }
 
 void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, int* flag, hipStream_t s) {
     // hashed rows when the right factor is too wide for the dense LDS row and the
     // output rows (known from the symbolic pass) fit a table of at most 512 slots
-    const bool dense = B.nc <= SPGEMM_DENSE && A.nr <= SPGEMM_DENSE_ROWS && (long)A.nr * B.nc <= SPGEMM_DENSE_WORK;
-    if (!dense && A.nr > 0 && C.max_row >= 0 && C.max_row <= 256 && B.max_row >= 0) {
+    if (!spgemm_dense_ok(A, B) && A.nr > 0 && C.max_row >= 0 && C.max_row <= 256 && B.max_row >= 0) {
         int cap = 32;
         while (cap < 2 * C.max_row) cap <<= 1;
-        int gb = 4;
-        while (gb < B.max_row && gb < 32) gb <<= 1;
-        int gl = (int)((long)cap * 12 * TPB / 65536);   // LDS: TPB / G tables of cap slots
-        int G = gb;
-        while (G < gl) G <<= 1;
-        if (G > 32) G = 32;
-#define MGR_HASH(GG, CC)                                                                                         \
-    k_spgemm_hash<GG, CC><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p, B.v.p, \
-                                                            C.rp.p, C.ci.p, C.v.p, flag)
-        switch (cap) {
-            case 32: if (G <= 4) MGR_HASH(4, 32); else if (G == 8) MGR_HASH(8, 32); else if (G == 16) MGR_HASH(16, 32); else MGR_HASH(32, 32); break;
-            case 64: if (G <= 4) MGR_HASH(4, 64); else if (G == 8) MGR_HASH(8, 64); else if (G == 16) MGR_HASH(16, 64); else MGR_HASH(32, 64); break;
-            case 128: if (G <= 8) MGR_HASH(8, 128); else if (G == 16) MGR_HASH(16, 128); else MGR_HASH(32, 128); break;
-            case 256: if (G <= 16) MGR_HASH(16, 256); else MGR_HASH(32, 256); break;
-            default: MGR_HASH(32, 512); break;
-        }
-#undef MGR_HASH
-        MGR_LAUNCH_CHECK();
+        spgemm_hash_launch<true>(A, B, cap, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s);
         return;
     }
     spgemm_launch<true>(A, B, max_row, C.rp.p, C.ci.p, C.v.p, nullptr, nullptr, s);
