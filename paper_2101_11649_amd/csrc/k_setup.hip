@@ -1265,13 +1265,25 @@ __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restri
             if (FILL) ka = av[a0 + base + g.gl];
         }
         const int lim = min(G, wl - base);
+        // the first G entries of the next row of B are loaded while the current
+        // one is inserted (one step of software pipelining)
+        int nb0 = __shfl(kb0, g.gbase, WAVE), nb1 = __shfl(kb1, g.gbase, WAVE);
+        int nj = (nb0 + g.gl < nb1) ? bci[nb0 + g.gl] : -1;
+        double nv = (FILL && nb0 + g.gl < nb1) ? bv[nb0 + g.gl] : 0.0;
         for (int t = 0; t < lim; ++t) {
-            const int b0 = __shfl(kb0, g.gbase + t, WAVE);
-            const int b1 = __shfl(kb1, g.gbase + t, WAVE);
+            const int b0 = nb0, b1 = nb1;
+            const int j0 = nj;
+            const double v0 = nv;
             const double a = __shfl(ka, g.gbase + t, WAVE);
+            if (t + 1 < lim) {
+                nb0 = __shfl(kb0, g.gbase + t + 1, WAVE);
+                nb1 = __shfl(kb1, g.gbase + t + 1, WAVE);
+                nj = (nb0 + g.gl < nb1) ? bci[nb0 + g.gl] : -1;
+                nv = (FILL && nb0 + g.gl < nb1) ? bv[nb0 + g.gl] : 0.0;
+            }
             for (int q = b0 + g.gl; q < b1; q += G) {
-                const int j = bci[q];
-                const double prod = FILL ? a * bv[q] : 0.0;
+                const int j = (q == b0 + g.gl) ? j0 : bci[q];
+                const double prod = FILL ? a * ((q == b0 + g.gl) ? v0 : bv[q]) : 0.0;
                 // multiplicative hash: the top log2(CAP) bits of j * 2654435761
                 int h = (int)(((unsigned)j * 2654435761u) >> (32 - log2_pow2(CAP)));
                 int probes = 0;

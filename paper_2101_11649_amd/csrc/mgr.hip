@@ -308,8 +308,10 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
         DCsr P;
         Pend pp;
         long long* sc = nullptr;
-        int batch = 5;
-        for (int total = 0;; total += batch, batch = 2) {
+        // seven rounds usually decide every point: a first batch of eight rarely
+        // needs a second (each batch costs a sync and a speculative P count)
+        int batch = 8;
+        for (int total = 0;; total += batch, batch = 4) {
             if (total > 100000) throw Error(MGR_ERR_UNSUPPORTED, "PMIS did not terminate");
             long long* und = S.take(1);
             for (int r = 0; r < batch; ++r) {
