@@ -261,40 +261,7 @@ __global__ void k_cf_maps(int n, const int* __restrict__ isF, const int* __restr
     else { int c = i - fpos[i]; lmap[i] = c; cmap[c] = i; }
 }
 
-__global__ void k_extract_count(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                 const int* __restrict__ isF, const int* __restrict__ lmap, int* cFF, int* cFC,
-                                 int* cCF, int* cCC) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int f = 0, c = 0;
-    for (int p = rp[i]; p < rp[i + 1]; ++p) {
-        if (isF[ci[p]]) ++f;
-        else ++c;
-    }
-    int l = lmap[i];
-    if (isF[i]) { cFF[l] = f; cFC[l] = c; }
-    else { cCF[l] = f; cCC[l] = c; }
-}
 
-__global__ void k_extract_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                               const double* __restrict__ v, const int* __restrict__ isF,
-                               const int* __restrict__ lmap, const int* __restrict__ rpFF, int* ciFF, double* vFF,
-                               const int* __restrict__ rpFC, int* ciFC, double* vFC, const int* __restrict__ rpCF,
-                               int* ciCF, double* vCF, const int* __restrict__ rpCC, int* ciCC, double* vCC) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int l = lmap[i];
-    int oF, oC;
-    int *cF, *cC;
-    double *vF, *vC;
-    if (isF[i]) { oF = rpFF[l]; oC = rpFC[l]; cF = ciFF; vF = vFF; cC = ciFC; vC = vFC; }
-    else { oF = rpCF[l]; oC = rpCC[l]; cF = ciCF; vF = vCF; cC = ciCC; vC = vCC; }
-    for (int p = rp[i]; p < rp[i + 1]; ++p) {
-        int j = ci[p];
-        if (isF[j]) { cF[oF] = lmap[j]; vF[oF] = v[p]; ++oF; }
-        else { cC[oC] = lmap[j]; vC[oC] = v[p]; ++oC; }
-    }
-}
 
 // ------------------------------------------------------------------ F-relaxation operator
 __global__ void k_frelax_flags(int nF, const int* __restrict__ bid, int* __restrict__ flagk) {
@@ -446,18 +413,6 @@ __global__ __launch_bounds__(TPB) void k_frelax_fill(int nb, const int* __restri
 }
 
 // ------------------------------------------------------------------ sparse products
-__global__ void k_max_row(int n, const int* __restrict__ rp, int* __restrict__ out) {
-    __shared__ int sh[TPB];
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    sh[threadIdx.x] = (i < n) ? rp[i + 1] - rp[i] : 0;
-    __syncthreads();
-    for (int off = TPB / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) sh[threadIdx.x] = max(sh[threadIdx.x], sh[threadIdx.x + off]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicMax(out, sh[0]);
-}
-
 // C = A B, one wavefront per output row.  Each lane owns up to NH entries p of
 // row i of A (p = a0 + lane + 64 t) and walks row aci[p] of B: a k-way merge
 // whose current minimum column is found by a wave-wide min.  Every output
@@ -756,39 +711,7 @@ __global__ __launch_bounds__(TPB) void k_transpose_rank(int nr, const int* __res
     }
 }
 
-// ------------------------------------------------------------------ AMG setup
-// j in S_i iff j != i (same label under the unknown-based option) and
-// -a_ij >= theta * max_k(-a_ik); S_i empty when that max is not positive.
-__global__ void k_strength(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                           const double* __restrict__ v, double theta, const int* __restrict__ label,
-                           unsigned char* __restrict__ strong) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double mx = 0.0;
-    bool have = false;
-    int li = label ? label[i] : 0;
-    for (int p = rp[i]; p < rp[i + 1]; ++p) {
-        int j = ci[p];
-        if (j == i || (label && label[j] != li)) continue;
-        double t = -v[p];
-        if (!have || t > mx) { mx = t; have = true; }
-    }
-    double thr = theta * mx;
-    for (int p = rp[i]; p < rp[i + 1]; ++p) {
-        int j = ci[p];
-        unsigned char s = 0;
-        if (have && mx > 0.0 && j != i && !(label && label[j] != li) && -v[p] >= thr) s = 1;
-        strong[p] = s;
-    }
-}
 
-__global__ void k_lambda(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                         const unsigned char* __restrict__ strong, int* __restrict__ lam) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    for (int p = rp[i]; p < rp[i + 1]; ++p)
-        if (strong[p]) atomicAdd(&lam[ci[p]], 1);
-}
 
 __global__ void k_scount(int n, const int* __restrict__ rp, const unsigned char* __restrict__ strong,
                          int* __restrict__ cnt) {
@@ -799,14 +722,6 @@ __global__ void k_scount(int n, const int* __restrict__ rp, const unsigned char*
     cnt[i] = c;
 }
 
-__global__ void k_sfill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                        const unsigned char* __restrict__ strong, const int* __restrict__ srp, int* __restrict__ sci) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int o = srp[i];
-    for (int p = rp[i]; p < rp[i + 1]; ++p)
-        if (strong[p]) sci[o++] = ci[p];
-}
 
 // splitmix64 (Steele, Lea, Flood 2014): output k of the stream seeded with
 // `seed` is mix(seed + k * 0x9E3779B97F4A7C15).
@@ -867,67 +782,8 @@ __global__ void k_is_c(int n, const int* __restrict__ cf, int* __restrict__ isC)
     if (i < n) isC[i] = (cf[i] == 1) ? 1 : 0;
 }
 
-__global__ void k_interp_count(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                               const unsigned char* __restrict__ strong, const int* __restrict__ cf,
-                               int* __restrict__ cnt) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (cf[i] == 1) { cnt[i] = 1; return; }
-    int c = 0;
-    for (int p = rp[i]; p < rp[i + 1]; ++p)
-        if (strong[p] && cf[ci[p]] == 1) ++c;
-    cnt[i] = c;
-}
 
-// Direct interpolation with positive off-diagonals lumped into the diagonal
-// (Stueben 2001): w_ij = -(alpha_i a_ij) / atilde_ii, alpha_i = neg_i / cs_i.
-__global__ void k_interp_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                              const double* __restrict__ v, const unsigned char* __restrict__ strong,
-                              const int* __restrict__ cf, const int* __restrict__ cidx, const int* __restrict__ label,
-                              const int* __restrict__ prp, int* __restrict__ pci, double* __restrict__ pv,
-                              int* __restrict__ flag) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int o = prp[i];
-    if (cf[i] == 1) { pci[o] = cidx[i]; pv[o] = 1.0; return; }
-    if (prp[i + 1] == o) return;
-    int li = label ? label[i] : 0;
-    double aii = 0.0, neg = 0.0, pos = 0.0, cs = 0.0;
-    for (int p = rp[i]; p < rp[i + 1]; ++p) {
-        int k = ci[p];
-        double a = v[p];
-        if (k == i) { aii = a; continue; }
-        if (label && label[k] != li) continue;
-        if (a < 0.0) neg = neg + a;
-        else if (a > 0.0) pos = pos + a;
-        if (strong[p] && cf[k] == 1) cs = cs + a;
-    }
-    double atil = aii + pos;
-    if (!(atil > 0.0)) set_flag(flag, 6);
-    double alpha = neg / cs;
-    for (int p = rp[i]; p < rp[i + 1]; ++p) {
-        int k = ci[p];
-        if (strong[p] && cf[k] == 1) {
-            pci[o] = cidx[k];
-            pv[o] = -(alpha * v[p]) / atil;
-            ++o;
-        }
-    }
-}
 
-__global__ void k_l1_dinv(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                          const double* __restrict__ v, double* __restrict__ dinv, int* __restrict__ flag) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0, aii = 0.0;
-    for (int p = rp[i]; p < rp[i + 1]; ++p) {
-        if (ci[p] == i) aii = v[p];
-        else s = s + fabs(v[p]);
-    }
-    double d = aii + s;
-    if (!(d > 0.0)) { set_flag(flag, 6); d = 1.0; }
-    dinv[i] = 1.0 / d;
-}
 
 __global__ void k_densify(int n, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ v,
                           double* __restrict__ dense) {
@@ -1996,15 +1852,6 @@ void scan_async(const int* in, int* out, int n, long long* slot, hipStream_t s) 
 
 void scan_exclusive_async(const int* in, int* out, int n, hipStream_t s) { scan_async(in, out, n, nullptr, s); }
 
-long scan_exclusive(const int* in, int* out, int n, hipStream_t s) {
-    DArr<long long> slot(2, s);
-    scan_async(in, out, n, slot.p, s);
-    long long h[2] = {0, 0};
-    MGR_HIP(hipMemcpyAsync(h, slot.p, sizeof(h), hipMemcpyDeviceToHost, s));
-    MGR_HIP(hipStreamSynchronize(s));
-    if (h[0] > INT_MAX) throw Error(-6, "prefix sum exceeds the int32 index range");
-    return (long)h[0];
-}
 
 void fill_ll(long long* p, long long v, int n, hipStream_t s) {
     if (n <= 0) return;
@@ -2019,8 +1866,6 @@ int read_int(const int* dptr, hipStream_t s) {
     return h;
 }
 
-void flag_clear(int* flag, hipStream_t s) { fill_int(flag, 0, 1, s); }
-int flag_read(const int* flag, hipStream_t s) { return read_int(flag, s); }
 
 void fill_int(int* p, int v, long n, hipStream_t s) {
     if (n <= 0) return;
@@ -2140,14 +1985,6 @@ void frelax_fill(int nb, const int* bstart, const DCsr& AFF, DCsr& M, int* flag,
     MGR_LAUNCH_CHECK();
 }
 
-int max_row_len(const DCsr& A, hipStream_t s) {
-    if (A.nr <= 0) return 0;
-    DArr<int> m(1, s);
-    fill_int(m.p, 0, 1, s);
-    k_max_row<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, m.p);
-    MGR_LAUNCH_CHECK();
-    return read_int(m.p, s);
-}
 
 template <bool FILL>
 static void spgemm_launch(const DCsr& A, const DCsr& B, int max_row, const int* crp, int* cci, double* cv, int* cnt,
@@ -2303,11 +2140,6 @@ void amg_lambda(const DCsr& A, const unsigned char* strong, int* lam, hipStream_
     MGR_LAUNCH_CHECK();
 }
 
-void strength_compact_count(const DCsr& A, const unsigned char* strong, int* cnt, hipStream_t s) {
-    if (A.nr <= 0) return;
-    k_scount<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, strong, cnt);
-    MGR_LAUNCH_CHECK();
-}
 
 void strength_compact_fill(const DCsr& A, const unsigned char* strong, const int* srp, int* sci, hipStream_t s) {
     if (A.nr <= 0) return;

@@ -10,19 +10,13 @@
 namespace mgr {
 
 // ---------------------------------------------------------------- setup
-// out[0..n] = exclusive prefix sum of in[0..n), out[n] = total.  Returns the
-// total (synchronises the stream).  Throws UNSUPPORTED if the total exceeds int32.
-long scan_exclusive(const int* in, int* out, int n, hipStream_t s);
-// Same, without reading the total back.
+// out[0..n] = exclusive prefix sum of in[0..n), out[n] = total (clamped to
+// int32; scan_async reports the exact total), asynchronous.
 void scan_exclusive_async(const int* in, int* out, int n, hipStream_t s);
 // Asynchronous scan that also stores {total, max input} into slot[0..1] (device).
 void scan_async(const int* in, int* out, int n, long long* slot, hipStream_t s);
 void fill_ll(long long* p, long long v, int n, hipStream_t s);
 int read_int(const int* dptr, hipStream_t s);
-
-// Device-wide error flag helpers (a single int in device memory, 0 = ok).
-void flag_clear(int* flag, hipStream_t s);
-int flag_read(const int* flag, hipStream_t s);
 
 // Scalar CSR of the block-CSR input without exact zeros inside blocks (the
 // diagonal is always kept): row lengths, then (rows allocated from their scan)
@@ -52,7 +46,6 @@ void frelax_block_starts(int nF, const int* flagk, const int* excl, int* bstart,
 void frelax_row_len(int nF, const int* bnum, const int* bstart, int* len, hipStream_t s);
 void frelax_fill(int nb, const int* bstart, const DCsr& AFF, DCsr& M, int* flag, hipStream_t s);
 
-int max_row_len(const DCsr& A, hipStream_t s);
 // C = A B counts; rows of A longer than the variant chosen by max_row get a zero
 // count and set *flag (an int in device memory) to 1.
 // Right factors with at most SPGEMM_DENSE_COLS columns (and few enough rows x
@@ -74,7 +67,6 @@ void transpose_fill(const DCsr& A, DCsr& T, int* cnt, hipStream_t s);
 // strength flags per entry and the number of strong entries per row (scnt)
 void amg_strength(const DCsr& A, double theta, const int* label, unsigned char* strong, int* scnt, hipStream_t s);
 void amg_lambda(const DCsr& A, const unsigned char* strong, int* lam, hipStream_t s);
-void strength_compact_count(const DCsr& A, const unsigned char* strong, int* cnt, hipStream_t s);
 void strength_compact_fill(const DCsr& A, const unsigned char* strong, const int* srp, int* sci, hipStream_t s);
 void pattern_transpose_fill(int nr, const int* rp, const int* ci, const int* trp, int* cursor, int* tci,
                             hipStream_t s);
