@@ -179,7 +179,8 @@ int mgr_hierarchy_info(mgr_handle h, int64_t *out, int32_t cap);
  * flags (int32, 1 = C, 0 = F), 1 = coarse operator, 2 = P_F, 3 = R_F, 4 = A_FF,
  * 5 = F-relaxation operator M.  kind 1 = coarse AMG level `level`, kind 2 = the
  * F-relaxation AMG of MGR level `sub`: what 0 = C/F (+1 = C, -1 = F), 1 = A_k,
- * 2 = P_k.  sizes[0..2] = rows, cols, nnz (vector length in sizes[0]);
+ * 2 = P_k, 3 = the dense inverse of the coarsest level (level = last; n x n
+ * row-major doubles in b2).  sizes[0..2] = rows, cols, nnz (vector length in sizes[0]);
  * b0 = row_ptr (or the C/F vector), b1 = col_idx, b2 = values (double). */
 int mgr_export(mgr_handle h, int32_t kind, int32_t level, int32_t what, int32_t sub, int64_t *sizes,
                void *b0, void *b1, void *b2);

@@ -269,6 +269,18 @@ class Solver:
         self._check(L.mgr_export(self._h, kind, level, what, sub, P(sizes), P(rp), P(ci), P(v)))
         return nr, nc, rp, ci[:nnz], v[:nnz]
 
+    def coarsest_inverse(self):
+        """Dense inverse of the coarse AMG's coarsest level, an (n, n) numpy array."""
+        L = lib()
+        last = len(self.info()["amg_levels"]) - 1
+        sizes = np.zeros(3, np.int64)
+        P = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        self._check(L.mgr_export(self._h, 1, last, 3, -1, P(sizes), None, None, None))
+        n = int(sizes[0])
+        out = np.zeros(max(n * n, 1), np.float64)
+        self._check(L.mgr_export(self._h, 1, last, 3, -1, P(sizes), None, None, P(out)))
+        return out[: n * n].reshape(n, n)
+
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
             lib().mgr_destroy(self._h)

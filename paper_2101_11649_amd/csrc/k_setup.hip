@@ -785,12 +785,14 @@ __global__ void k_is_c(int n, const int* __restrict__ cf, int* __restrict__ isC)
 
 
 
+// one workgroup per row: the row is cleared, then its entries are stored
 __global__ void k_densify(int n, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ v,
                           double* __restrict__ dense) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    for (int j = 0; j < n; ++j) dense[(long)i * n + j] = 0.0;
-    for (int p = rp[i]; p < rp[i + 1]; ++p) dense[(long)i * n + ci[p]] = v[p];
+    const int i = blockIdx.x;
+    double* row = dense + (long)i * n;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) row[j] = 0.0;
+    __syncthreads();
+    for (int p = rp[i] + threadIdx.x; p < rp[i + 1]; p += blockDim.x) row[ci[p]] = v[p];
 }
 
 // Gauss-Jordan inverse with partial pivoting of the coarsest AMG matrix, one
@@ -1515,116 +1517,125 @@ __global__ __launch_bounds__(TPB) void k_transpose_scatter_g(int nr, const int* 
     }
 }
 
-// Coarsest-level inverse for n <= 128, kept in registers: 1024 threads, thread
-// t owns rows 4(t/32) .. 4(t/32)+3 and the eight columns t%32 + 32k of the
-// augmented matrix [A | I] (eight pivot-row values and four multipliers read
-// from LDS per step).  Gauss-Jordan with partial pivoting in place: the pivot
-// of column c is the largest |entry| among rows not yet used as pivots (ties
-// to the lower row); no rows are swapped, so at the end row p of the right
-// half is row c of the inverse when p was the pivot row of column c.
-__global__ __launch_bounds__(1024) void k_dense_inverse_small(int n, const double* __restrict__ a,
-                                                              double* __restrict__ inv, int* __restrict__ flag) {
-    __shared__ double prow[256];
-    __shared__ double fcol[128];
-    __shared__ double pv[128];
-    __shared__ int used[128];
-    __shared__ int pos[128];
-    __shared__ int piv_sh;
-    const int t = threadIdx.x;
-    const int rb = t >> 5, cb = t & 31;
-    double m[4][8];
+// Coarsest-level inverse for n <= 128, kept in registers: 256 threads, thread
+// (tr, tc) = (t / 16, t % 16) holds the entries (tr + 16 i, tc + 16 k), i, k < 8.
+// In-place Gauss-Jordan with partial pivoting and no row exchanges: the pivot
+// of column c is the largest |entry| among the rows not yet used as pivots
+// (ties to the lower row).  Step (p, c) scales row p by 1/a_pc and removes
+// column c from every other row.  Column c of the left half of [A | I] is the
+// unit vector e_p from then on, while column p of the right half starts to
+// differ from e_p, so the slot of column c stores that right-half column: the
+// pivot row gets 1/a_pc there and row r gets -a_rc/a_pc.  At the end slot
+// (r, c) holds entry (r, p(c)) of the right half, whose row p(c') is row c' of
+// the inverse: inv[c'][p(c)] = slot (p(c'), c).  Two barriers per step: one
+// publishes the per-wave pivot candidates, one the scaled pivot row; the
+// multipliers of a row travel by shuffles inside its 16-lane group.
+__global__ __launch_bounds__(256) void k_dense_inverse_small(int n, const double* __restrict__ a,
+                                                             double* __restrict__ inv, int* __restrict__ flag) {
+    __shared__ double cand_v[4];
+    __shared__ int cand_i[4];
+    __shared__ double prow[128];
+    __shared__ int pc[128], pos[128];
+    const int t = threadIdx.x, tr = t >> 4, tc = t & 15, w = t >> 6;
+    double m[8][8];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        int r = rb * 4 + i;
+    for (int i = 0; i < 8; ++i) {
+        const int r = tr + 16 * i;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            int c = cb + 32 * k;
-            double x = 0.0;
-            if (r < n) {
-                if (c < n) x = a[(long)r * n + c];
-                else if (c < 2 * n && c - n == r) x = 1.0;
-            }
-            m[i][k] = x;
+            const int c = tc + 16 * k;
+            m[i][k] = (r < n && c < n) ? a[(long)r * n + c] : 0.0;
         }
     }
-    if (t < 128) used[t] = 0;
-    __syncthreads();
-    for (int c = 0; c < n; ++c) {
-        const int kc = c >> 5;
-        if (cb == (c & 31)) {
+    unsigned used = 0;  // bit i: row tr + 16 i has been a pivot row
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                int r = rb * 4 + i;
-                double x = 0.0;
-#pragma unroll
-                for (int k = 0; k < 8; ++k)
-                    if (k == kc) x = m[i][k];
-                if (r < n) {
-                    fcol[r] = x;
-                    pv[r] = used[r] ? -1.0 : fabs(x);
-                }
-            }
-        }
-        __syncthreads();
-        if (t < WAVE) {
+    for (int KC = 0; KC < 8; ++KC) {
+        if (16 * KC >= n) break;
+        for (int cl = 0; cl < 16; ++cl) {
+            const int c = 16 * KC + cl;
+            if (c >= n) break;
+            // candidates: the best unused row of column c among this thread's
+            // rows, then among the four row groups of the wave
             double bv = -1.0;
             int bi = n;
-            for (int q = t; q < n; q += WAVE) {
-                double x = pv[q];
-                if (x > bv || (x == bv && q < bi)) { bv = x; bi = q; }
+            if (tc == cl) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int r = tr + 16 * i;
+                    const double ax = fabs(m[i][KC]);
+                    if (r < n && !((used >> i) & 1u) && ax > bv) { bv = ax; bi = r; }
+                }
             }
-            for (int off = WAVE / 2; off > 0; off >>= 1) {
-                double ov = __shfl_xor(bv, off, WAVE);
-                int oi = __shfl_xor(bi, off, WAVE);
+#pragma unroll
+            for (int off = 16; off <= 32; off <<= 1) {
+                const double ov = __shfl_xor(bv, off, WAVE);
+                const int oi = __shfl_xor(bi, off, WAVE);
                 if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
             }
-            if (t == 0) {
-                int p = (bv > 0.0 && isfinite(bv)) ? bi : -1;
-                piv_sh = p;
-                if (p < 0) set_flag(flag, 3);
-                else { used[p] = 1; pos[p] = c; }
-            }
-        }
-        __syncthreads();
-        const int p = piv_sh;
-        if (p < 0) return;
-        const double ip = 1.0 / fcol[p];
-        if (rb == (p >> 2)) {
-            const int ip4 = p & 3;
+            if ((t & (WAVE - 1)) == cl) { cand_v[w] = bv; cand_i[w] = bi; }
+            __syncthreads();
+            double pvv = cand_v[0];
+            int p = cand_i[0];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                if (i == ip4) {
+            for (int q = 1; q < 4; ++q) {
+                const double ov = cand_v[q];
+                const int oi = cand_i[q];
+                if (ov > pvv || (ov == pvv && oi < p)) { pvv = ov; p = oi; }
+            }
+            if (!(pvv > 0.0) || !isfinite(pvv)) {
+                if (t == 0) set_flag(flag, 3);
+                return;
+            }
+            if (t == 0) { pc[c] = p; pos[p] = c; }
+            const int pi = p >> 4;
+            if (tr == (p & 15)) {
+                used |= 1u << pi;
+                double x[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    if (i == pi) {
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) x[k] = m[i][k];
+                    }
+                const double ip = 1.0 / __shfl(x[KC], cl, 16);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) x[k] = (k == KC && tc == cl) ? ip : x[k] * ip;
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    if (i == pi) {
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) m[i][k] = x[k];
+                    }
+#pragma unroll
+                for (int k = 0; k < 8; ++k) prow[tc + 16 * k] = x[k];
+            }
+            __syncthreads();
+            double pr[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) pr[k] = prow[tc + 16 * k];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const double f = __shfl(m[i][KC], cl, 16);
+                if (tr + 16 * i != p) {
 #pragma unroll
                     for (int k = 0; k < 8; ++k) {
-                        m[i][k] = m[i][k] * ip;
-                        prow[cb + 32 * k] = m[i][k];
+                        const double base = (k == KC && tc == cl) ? 0.0 : m[i][k];
+                        m[i][k] = base - f * pr[k];
                     }
                 }
-        }
-        __syncthreads();
-        double pr[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) pr[k] = prow[cb + 32 * k];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            int r = rb * 4 + i;
-            if (r < n && r != p) {
-                double f = fcol[r];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) m[i][k] = m[i][k] - f * pr[k];
             }
         }
-        __syncthreads();
     }
+    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        int r = rb * 4 + i;
+    for (int i = 0; i < 8; ++i) {
+        const int r = tr + 16 * i;
         if (r >= n) continue;
-        int row = pos[r];
+        const long row = (long)pos[r] * n;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            int c = cb + 32 * k;
-            if (c >= n && c < 2 * n) inv[(long)row * n + (c - n)] = m[i][k];
+            const int c = tc + 16 * k;
+            if (c < n) inv[row + pc[c]] = m[i][k];
         }
     }
 }
@@ -2209,14 +2220,14 @@ void l1_dinv(const DCsr& A, double* dinv, int* flag, hipStream_t s) {
 
 void densify(const DCsr& A, double* dense, hipStream_t s) {
     if (A.nr <= 0) return;
-    k_densify<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, dense);
+    k_densify<<<A.nr, 128, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, dense);
     MGR_LAUNCH_CHECK();
 }
 
 void dense_inverse(int n, double* a, double* inv, int* flag, hipStream_t s) {
     if (n <= 0) return;
     if (n <= 128) {
-        k_dense_inverse_small<<<1, 1024, 0, s>>>(n, a, inv, flag);
+        k_dense_inverse_small<<<1, 256, 0, s>>>(n, a, inv, flag);
         MGR_LAUNCH_CHECK();
         return;
     }

@@ -1475,6 +1475,14 @@ static int do_export(Ctx& c, int kind, int level, int what, int sub, int64_t* si
     }
     if (what == 1) { export_csr(L.A, sizes, b0, b1, b2, s); return MGR_OK; }
     if (what == 2 && level + 1 < (int)H->lv.size()) { export_csr(L.P, sizes, b0, b1, b2, s); return MGR_OK; }
+    if (what == 3 && level + 1 == (int)H->lv.size()) {
+        // the coarsest level's dense inverse, n x n row-major in b2
+        sizes[0] = H->nc; sizes[1] = H->nc; sizes[2] = (int64_t)H->nc * H->nc;
+        if (b2 && H->nc > 0)
+            MGR_HIP(hipMemcpyAsync(b2, H->cinv.p, sizeof(double) * H->nc * H->nc, hipMemcpyDeviceToHost, s));
+        MGR_HIP(hipStreamSynchronize(s));
+        return MGR_OK;
+    }
     throw Error(MGR_ERR_ARG, "unknown export item");
 }
 
