@@ -112,9 +112,11 @@ void mdot(long n, const double* V, long ldv, int nvec, const double* w, double* 
 // nvec <= 16 (returns false otherwise, and does nothing).
 bool maxpy_mdot(long n, const double* V, long ldv, int nvec, const double* h, double* w, double* part,
                 double* out, hipStream_t s);
-// w -= hscale * sum_i h[i] V_i; if norm2_out, *norm2_out = ||w_new||^2.
+// w -= hscale * sum_i h[i] V_i; if norm2_out, *norm2_out = ||w_new||^2, after
+// which csrc[0..ncopy) (device, may hold norm2_out) is stored to the
+// host-mapped cdst.
 void maxpy(long n, const double* V, long ldv, int nvec, const double* h, double hscale, double* w, double* part,
-           double* norm2_out, hipStream_t s);
+           double* norm2_out, hipStream_t s, const double* csrc = nullptr, double* cdst = nullptr, int ncopy = 0);
 // rows[0..cnt) of one level of a triangular solve with matrix A: x_i = (b_i - sum_{j!=i} a_ij x_j) / a_ii
 // (unit: diagonal 1 and not stored).  b may alias x.
 template <typename T>

@@ -291,6 +291,31 @@ __device__ inline void block_reduce_write(double (&acc)[NB], double* __restrict_
     }
 }
 
+// Workgroup sums of NB per-thread accumulators: out[t * stride] = sum over the
+// workgroup of acc[t], for t < nv.  Eight accumulators at a time go through
+// LDS; then 32 lanes per accumulator add eight values each and finish with a
+// shuffle tree (a fixed order, so every call rounds alike).
+template <int NB>
+__device__ inline void block_sums(const double (&acc)[NB], int nv, double* __restrict__ out, long stride) {
+    constexpr int G = 8, L = TPB / G;
+    __shared__ double sh[G][TPB];
+    const int tid = threadIdx.x, v = tid / L, k = tid % L;
+#pragma unroll
+    for (int g0 = 0; g0 < NB; g0 += G) {
+        if (g0 >= nv) break;
+        if (g0 > 0) __syncthreads();
+#pragma unroll
+        for (int t = 0; t < G; ++t)
+            if (g0 + t < NB) sh[t][tid] = acc[g0 + t];
+        __syncthreads();
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < G; ++m) s += sh[v][k + L * m];
+        for (int off = L / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, L);
+        if (k == 0 && g0 + v < nv) out[(long)(g0 + v) * stride] = s;
+    }
+}
+
 // part[(i0+t) * gridDim.x + block] = partial of <V_{i0+t}, w>
 template <int NB>
 __global__ __launch_bounds__(TPB) void k_mdot(long n, const double* __restrict__ V, long ldv, int nvec,
@@ -306,20 +331,7 @@ __global__ __launch_bounds__(TPB) void k_mdot(long n, const double* __restrict__
         for (int t = 0; t < NB; ++t)
             if (i0 + t < nvec) acc[t] += V[(long)(i0 + t) * ldv + r] * wr;
     }
-    __shared__ double sh[NB][TPB / WAVE];
-    int wid = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-#pragma unroll
-    for (int t = 0; t < NB; ++t) {
-        double v = group_sum<double>(acc[t], WAVE);
-        if (lane == 0) sh[t][wid] = v;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < NB && i0 + (int)threadIdx.x < nvec) {
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < TPB / WAVE; ++q) s += sh[threadIdx.x][q];
-        part[(long)(i0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
-    }
+    block_sums<NB>(acc, min(NB, nvec - i0), part + (long)i0 * gridDim.x + blockIdx.x, gridDim.x);
 }
 
 // First Gram-Schmidt correction fused with the products of the second pass
@@ -332,7 +344,6 @@ __global__ __launch_bounds__(TPB) void k_maxpy_mdot(long n, const double* __rest
                                                     const double* __restrict__ h, double* __restrict__ w,
                                                     double* __restrict__ part) {
     __shared__ double hs[NV];
-    __shared__ double sh[NV][TPB / WAVE];
     if ((int)threadIdx.x < nvec) hs[threadIdx.x] = h[threadIdx.x];
     __syncthreads();
     double acc[NV];
@@ -353,37 +364,34 @@ __global__ __launch_bounds__(TPB) void k_maxpy_mdot(long n, const double* __rest
         for (int t = 0; t < NV; ++t)
             if (t < nvec) acc[t] += vv[t] * wn;
     }
-    int wid = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-#pragma unroll
-    for (int t = 0; t < NV; ++t) {
-        if (t < nvec) {
-            double v = group_sum<double>(acc[t], WAVE);
-            if (lane == 0) sh[t][wid] = v;
-        }
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < nvec) {
-        double sacc = 0.0;
-#pragma unroll
-        for (int q = 0; q < TPB / WAVE; ++q) sacc += sh[threadIdx.x][q];
-        part[(long)threadIdx.x * gridDim.x + blockIdx.x] = sacc;
-    }
+    block_sums<NV>(acc, nvec, part + blockIdx.x, gridDim.x);
 }
 
 // out[i] = sum over the nparts partials of vector i, in a fixed tree order.
+// With ncopy > 0 (a single workgroup), csrc[0..ncopy) -- which may include
+// out[0] -- is then also stored to cdst, a host-mapped buffer, and released to
+// the host.
 __global__ __launch_bounds__(TPB) void k_reduce_parts(int nparts, const double* __restrict__ part,
-                                                      double* __restrict__ out) {
-    __shared__ double sh[TPB];
+                                                      double* __restrict__ out, const double* csrc,
+                                                      double* __restrict__ cdst, int ncopy) {
+    __shared__ double sh[TPB / WAVE];
     const double* p = part + (long)blockIdx.x * nparts;
     double s = 0.0;
     for (int q = threadIdx.x; q < nparts; q += TPB) s += p[q];
-    sh[threadIdx.x] = s;
+    s = group_sum<double>(s, WAVE);
+    if ((threadIdx.x & (WAVE - 1)) == 0) sh[threadIdx.x / WAVE] = s;
     __syncthreads();
-    for (int off = TPB / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < TPB / WAVE; ++q) t += sh[q];
+        out[blockIdx.x] = t;
     }
-    if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+    if (ncopy > 0) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < ncopy; q += TPB) cdst[q] = csrc[q];
+        __threadfence_system();
+    }
 }
 
 // w -= sum_i h[i] V_i  (h on the device); optionally partial sums of w_new^2.
@@ -622,7 +630,7 @@ void mdot(long n, const double* V, long ldv, int nvec, const double* w, double* 
     constexpr int NB = 8;
     dim3 grid(np, ceil_div(nvec, NB));
     k_mdot<NB><<<grid, TPB, 0, s>>>(n, V, ldv, nvec, w, part);
-    k_reduce_parts<<<nvec, TPB, 0, s>>>(np, part, out);
+    k_reduce_parts<<<nvec, TPB, 0, s>>>(np, part, out, nullptr, nullptr, 0);
     MGR_LAUNCH_CHECK();
 }
 
@@ -632,18 +640,19 @@ bool maxpy_mdot(long n, const double* V, long ldv, int nvec, const double* h, do
     int np = krylov_parts(n);
     if (nvec <= 8) k_maxpy_mdot<8><<<np, TPB, 0, s>>>(n, V, ldv, nvec, h, w, part);
     else k_maxpy_mdot<16><<<np, TPB, 0, s>>>(n, V, ldv, nvec, h, w, part);
-    k_reduce_parts<<<nvec, TPB, 0, s>>>(np, part, out);
+    k_reduce_parts<<<nvec, TPB, 0, s>>>(np, part, out, nullptr, nullptr, 0);
     MGR_LAUNCH_CHECK();
     return true;
 }
 
 void maxpy(long n, const double* V, long ldv, int nvec, const double* h, double hscale, double* w, double* part,
-           double* norm2_out, hipStream_t s) {
+           double* norm2_out, hipStream_t s, const double* csrc, double* cdst, int ncopy) {
     if (nvec > 64) throw Error(-1, "maxpy: at most 64 vectors");
+    if (ncopy > 0 && !norm2_out) throw Error(-1, "maxpy: a host copy needs the norm reduction");
     int np = krylov_parts(n);
     if (nvec <= 0 && !norm2_out) return;
     k_maxpy<<<np, TPB, 0, s>>>(n, V, ldv, nvec, h, hscale, w, norm2_out ? part : nullptr);
-    if (norm2_out) k_reduce_parts<<<1, TPB, 0, s>>>(np, part, norm2_out);
+    if (norm2_out) k_reduce_parts<<<1, TPB, 0, s>>>(np, part, norm2_out, csrc, cdst, ncopy);
     MGR_LAUNCH_CHECK();
 }
 

@@ -718,6 +718,7 @@ struct Ctx {
     // and the event that marks each copy
     static constexpr int HROW = 130;
     double* hpin = nullptr;
+    double* hpin_dev = nullptr;  // the same rows as seen by kernels
     std::vector<hipEvent_t> hev;
     ~Ctx() {
         for (hipEvent_t e : hev) (void)hipEventDestroy(e);
@@ -1145,8 +1146,10 @@ static void ensure_krylov(Ctx& c) {
     c.yd.alloc(64, s);
     if (c.hpin) (void)hipHostFree(c.hpin);
     c.hpin = nullptr;
+    c.hpin_dev = nullptr;
     MGR_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.hpin), sizeof(double) * Ctx::HROW * (m + 1),
                           hipHostMallocDefault));
+    MGR_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c.hpin_dev), c.hpin, 0));
     while ((int)c.hev.size() < m) {
         hipEvent_t e;
         MGR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -1254,11 +1257,12 @@ static int fgmres(Ctx& c, bool tr, const double* b, double* x, mgr_solve_info* i
                 maxpy(n, V, n, j + 1, hb, 1.0, w, c.part.p, nullptr, s);
                 mdot(n, V, n, j + 1, w, c.part.p, hb + 64, s);
             }
-            maxpy(n, V, n, j + 1, hb + 64, 1.0, w, c.part.p, hb + 128, s);
-            scale_by_norm(n, hb + 128, w, s);
-            MGR_HIP(hipMemcpyAsync(c.hpin + (size_t)Ctx::HROW * j, hb, sizeof(double) * 129, hipMemcpyDeviceToHost,
-                                   s));
+            // the norm's reduction also stores the column's 129 coefficients to
+            // its pinned host row
+            maxpy(n, V, n, j + 1, hb + 64, 1.0, w, c.part.p, hb + 128, s, hb, c.hpin_dev + (size_t)Ctx::HROW * j,
+                  129);
             MGR_HIP(hipEventRecord(c.hev[j], s));
+            scale_by_norm(n, hb + 128, w, s);
             // wait for this column if convergence looks near (predicted from the
             // last processed column), else for the previous one
             double pred = std::fabs(g[k]) * std::pow(rate, (double)(j + 1 - k));
