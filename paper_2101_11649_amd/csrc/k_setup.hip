@@ -30,9 +30,11 @@ __device__ inline int wave_min_int(int v) {
 __device__ inline void set_flag(int* flag, int code) { atomicMax(flag, code); }
 
 // ------------------------------------------------------------------ scan
-// Exclusive prefix sum in three passes (block sums, scan of block sums, block
-// scans + offsets).  The scan also reports the total and the largest input
-// value (the longest row when the inputs are row counts) into a device slot.
+// Exclusive prefix sum in two passes: block sums (and block maxima), then block
+// scans, each block first adding up the sums of the blocks before it (there
+// are at most a few thousand).  The scan also reports the total and the
+// largest input value (the longest row when the inputs are row counts) into a
+// device slot.
 __global__ void k_scan_reduce(const int* __restrict__ in, int n, long long* __restrict__ bsum,
                               long long* __restrict__ bmax) {
     __shared__ long long sh[SCAN_T];
@@ -57,41 +59,36 @@ __global__ void k_scan_reduce(const int* __restrict__ in, int n, long long* __re
     if (threadIdx.x == 0) { bsum[blockIdx.x] = sh[0]; bmax[blockIdx.x] = sm[0]; }
 }
 
-__global__ void k_scan_blocks(long long* __restrict__ bsum, const long long* __restrict__ bmax, int nb,
-                              int* __restrict__ out_last, long long* __restrict__ slot) {
-    __shared__ long long sh[1024];
-    __shared__ long long sm[1024];
-    int chunk = (nb + 1023) / 1024;
-    int b0 = threadIdx.x * chunk, b1 = min(nb, b0 + chunk);
-    long long s = 0, m = 0;
-    for (int b = b0; b < b1; ++b) { s += bsum[b]; m = max(m, bmax[b]); }
-    sh[threadIdx.x] = s;
-    sm[threadIdx.x] = m;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        long long t = ((int)threadIdx.x >= off) ? sh[threadIdx.x - off] : 0;
-        long long u = ((int)threadIdx.x >= off) ? sm[threadIdx.x - off] : 0;
-        __syncthreads();
-        sh[threadIdx.x] += t;
-        sm[threadIdx.x] = max(sm[threadIdx.x], u);
-        __syncthreads();
-    }
-    long long run = threadIdx.x ? sh[threadIdx.x - 1] : 0;
-    for (int b = b0; b < b1; ++b) {
-        long long v = bsum[b];
-        bsum[b] = run;
-        run += v;
-    }
-    if (threadIdx.x == 1023) {
-        *out_last = (sh[1023] > INT_MAX) ? INT_MAX : (int)sh[1023];
-        if (slot) { slot[0] = sh[1023]; slot[1] = sm[1023]; }
-    }
-}
-
-__global__ void k_scan_apply(const int* __restrict__ in, int n, const long long* __restrict__ boff,
-                             int* __restrict__ out) {
+__global__ void k_scan_apply(const int* __restrict__ in, int n, const long long* __restrict__ bsum,
+                             const long long* __restrict__ bmax, int nb, int* __restrict__ out,
+                             long long* __restrict__ slot) {
     __shared__ int sh[SCAN_T];
-    int base = blockIdx.x * SCAN_B + threadIdx.x * SCAN_I;
+    __shared__ long long wa[SCAN_T / WAVE], wm[SCAN_T / WAVE];
+    __shared__ long long boff;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
+    const bool last = (int)blockIdx.x == nb - 1;
+    // this block's offset (and, in the last block, the total and the maximum)
+    long long a = 0, m = 0;
+    for (int b = tid; b < (int)blockIdx.x; b += SCAN_T) a += bsum[b];
+    if (last)
+        for (int b = tid; b < nb; b += SCAN_T) m = max(m, bmax[b]);
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, WAVE);
+        m = max(m, __shfl_xor(m, off, WAVE));
+    }
+    if (lane == 0) { wa[wid] = a; wm[wid] = m; }
+    __syncthreads();
+    if (tid == 0) {
+        long long ta = 0, tm = 0;
+        for (int q = 0; q < SCAN_T / WAVE; ++q) { ta += wa[q]; tm = max(tm, wm[q]); }
+        boff = ta;
+        if (last) {
+            long long total = ta + bsum[nb - 1];
+            out[n] = (total > INT_MAX) ? INT_MAX : (int)total;
+            if (slot) { slot[0] = total; slot[1] = tm; }
+        }
+    }
+    int base = blockIdx.x * SCAN_B + tid * SCAN_I;
     int v[SCAN_I];
     int s = 0;
     for (int t = 0; t < SCAN_I; ++t) {
@@ -99,15 +96,15 @@ __global__ void k_scan_apply(const int* __restrict__ in, int n, const long long*
         v[t] = (i < n) ? in[i] : 0;
         s += v[t];
     }
-    sh[threadIdx.x] = s;
+    sh[tid] = s;
     __syncthreads();
     for (int off = 1; off < SCAN_T; off <<= 1) {
-        int t = ((int)threadIdx.x >= off) ? sh[threadIdx.x - off] : 0;
+        int t = (tid >= off) ? sh[tid - off] : 0;
         __syncthreads();
-        sh[threadIdx.x] += t;
+        sh[tid] += t;
         __syncthreads();
     }
-    long long off = boff[blockIdx.x] + (threadIdx.x ? sh[threadIdx.x - 1] : 0);
+    long long off = boff + (tid ? sh[tid - 1] : 0);
     for (int t = 0; t < SCAN_I; ++t) {
         int i = base + t;
         if (i < n) out[i] = (int)off;
@@ -742,41 +739,6 @@ __global__ void k_pmis_init(int n, const int* __restrict__ lam, uint64_t seed, i
     cf[i] = (lam[i] == 0) ? -1 : 0;
 }
 
-// An undecided point becomes C when its (w, index) beats every undecided
-// neighbour in S_i and S^T_i (decided on the state at the start of the round).
-__global__ void k_pmis_select(int n, const int* __restrict__ srp, const int* __restrict__ sci,
-                              const int* __restrict__ trp, const int* __restrict__ tci, const double* __restrict__ w,
-                              const int* __restrict__ cf, unsigned char* __restrict__ newc) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (cf[i] != 0) { newc[i] = 0; return; }
-    double wi = w[i];
-    bool best = true;
-    for (int q = srp[i]; q < srp[i + 1] && best; ++q) {
-        int j = sci[q];
-        if (cf[j] == 0 && (w[j] > wi || (w[j] == wi && j > i))) best = false;
-    }
-    for (int q = trp[i]; q < trp[i + 1] && best; ++q) {
-        int j = tci[q];
-        if (cf[j] == 0 && (w[j] > wi || (w[j] == wi && j > i))) best = false;
-    }
-    newc[i] = best ? 1 : 0;
-}
-
-// New C-points are set; an undecided point that strongly depends on a new
-// C-point becomes F.  Counts what is still undecided.
-__global__ void k_pmis_update(int n, const int* __restrict__ srp, const int* __restrict__ sci,
-                              const unsigned char* __restrict__ newc, int* __restrict__ cf,
-                              int* __restrict__ undecided) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (newc[i]) { cf[i] = 1; return; }
-    if (cf[i] != 0) return;
-    for (int q = srp[i]; q < srp[i + 1]; ++q)
-        if (newc[sci[q]]) { cf[i] = -1; return; }
-    if (undecided) atomicAdd(undecided, 1);
-}
-
 __global__ void k_is_c(int n, const int* __restrict__ cf, int* __restrict__ isC) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) isC[i] = (cf[i] == 1) ? 1 : 0;
@@ -995,6 +957,60 @@ struct Grp {
 __device__ inline int wave_max_int(int v) {
     for (int off = WAVE / 2; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, WAVE));
     return v;
+}
+
+constexpr int PMIS_GROUP_MIN = 12;  // strong rows up to this mean length: a thread per point
+
+// PMIS round, G lanes per point.  Selection: an undecided point becomes C
+// when its (w, index) beats every undecided neighbour in S_i and S^T_i, judged
+// on the state at the start of the round.
+template <int G>
+__global__ __launch_bounds__(TPB) void k_pmis_select_g(int n, const int* __restrict__ srp, const int* __restrict__ sci,
+                                                       const int* __restrict__ trp, const int* __restrict__ tci,
+                                                       const double* __restrict__ w, const int* __restrict__ cf,
+                                                       unsigned char* __restrict__ newc) {
+    Grp<G> g;
+    const int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    const bool valid = i < n;
+    const bool cand = valid && cf[i] == 0;
+    bool beaten = false;
+    if (cand) {
+        const double wi = w[i];
+        for (int q = srp[i] + g.gl; q < srp[i + 1] && !beaten; q += G) {
+            const int j = sci[q];
+            if (cf[j] == 0 && (w[j] > wi || (w[j] == wi && j > i))) beaten = true;
+        }
+        for (int q = trp[i] + g.gl; q < trp[i + 1] && !beaten; q += G) {
+            const int j = tci[q];
+            if (cf[j] == 0 && (w[j] > wi || (w[j] == wi && j > i))) beaten = true;
+        }
+    }
+    beaten = g.bits(beaten) != 0;
+    if (valid && g.gl == 0) newc[i] = (cand && !beaten) ? 1 : 0;
+}
+
+// Update: new C-points are set; an undecided point that strongly depends on a
+// new C-point becomes F.  Counts what is still undecided (one atomic per wave).
+template <int G>
+__global__ __launch_bounds__(TPB) void k_pmis_update_g(int n, const int* __restrict__ srp, const int* __restrict__ sci,
+                                                       const unsigned char* __restrict__ newc, int* __restrict__ cf,
+                                                       int* __restrict__ undecided) {
+    Grp<G> g;
+    const int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    const bool valid = i < n;
+    const bool isnew = valid && newc[i];
+    const bool und = valid && !isnew && cf[i] == 0;
+    bool hit = false;
+    if (und)
+        for (int q = srp[i] + g.gl; q < srp[i + 1] && !hit; q += G)
+            if (newc[sci[q]]) hit = true;
+    hit = g.bits(hit) != 0;
+    if (valid && g.gl == 0) {
+        if (isnew) cf[i] = 1;
+        else if (und && hit) cf[i] = -1;
+    }
+    const unsigned long long left = __ballot(valid && g.gl == 0 && und && !hit);
+    if (undecided && g.lane == 0 && left) atomicAdd(undecided, (int)__popcll(left));
 }
 
 // C = A + B with a lane group of G lanes per row.  An entry of A with column c
@@ -1410,69 +1426,97 @@ __global__ __launch_bounds__(TPB) void k_interp_count_g(int n, const int* __rest
     if (valid && g.gl == 0) cnt[i] = (cf[i] == 1) ? 1 : c;
 }
 
-// Direct interpolation: the row sums are formed strictly left to right (each
-// chunk's values are broadcast lane by lane), exactly as the thread-per-row
-// version and the oracle do.
-template <int G>
-__global__ __launch_bounds__(TPB) void k_interp_fill_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                       const double* __restrict__ v,
-                                                       const unsigned char* __restrict__ strong,
-                                                       const int* __restrict__ cf, const int* __restrict__ cidx,
-                                                       const int* __restrict__ label, const int* __restrict__ prp,
-                                                       int* __restrict__ pci, double* __restrict__ pv,
-                                                       int* __restrict__ flag) {
-    Grp<G> g;
-    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
-    bool valid = i < n;
-    bool frow = valid && cf[i] != 1 && prp[i + 1] > prp[i];
-    if (valid && cf[i] == 1 && g.gl == 0) { pci[prp[i]] = cidx[i]; pv[prp[i]] = 1.0; }
-    int p0 = valid ? rp[i] : 0, len = frow ? rp[i + 1] - p0 : 0;
-    int maxlen = wave_max_int(len);
-    int li = (frow && label) ? label[i] : 0;
+// Direct interpolation of one F row from its entries: kind bit 0 = diagonal,
+// bit 1 = same-label off-diagonal, bit 2 = strong C neighbour (with bit 1).
+// The sums run strictly left to right, as in the oracle; a term that does not
+// belong to a sum is added as +0.0, which leaves it unchanged (none of the sums
+// can be -0.0), and keeps the sums in registers.
+struct InterpRow {
     double aii = 0.0, neg = 0.0, pos = 0.0, cs = 0.0;
-    for (int base = 0; base < maxlen; base += G) {
-        int q = base + g.gl;
-        bool act = q < len;
-        int k = act ? ci[p0 + q] : -1;
-        double a = act ? v[p0 + q] : 0.0;
-        int kind = 0;  // 1 diag, 2 same-label off-diagonal, 0 other / inactive
-        bool sc = false;
-        if (act) {
-            if (k == i) kind = 1;
-            else if (!(label && label[k] != li)) {
-                kind = 2;
-                sc = strong[p0 + q] && cf[k] == 1;
-            }
-        }
-        const int lim = min(G, maxlen - base);
-        for (int t = 0; t < lim; ++t) {
-            double at = __shfl(a, g.gbase + t, WAVE);
-            int kt = __shfl(kind, g.gbase + t, WAVE);
-            int st = __shfl((int)sc, g.gbase + t, WAVE);
-            if (kt == 1) aii = at;
-            else if (kt == 2) {
-                if (at < 0.0) neg = neg + at;
-                else if (at > 0.0) pos = pos + at;
-                if (st) cs = cs + at;
-            }
-        }
+    __device__ void add(int kind, double a) {
+        if (kind & 1) aii = a;
+        const bool off = (kind & 2) != 0;
+        neg = neg + ((off && a < 0.0) ? a : 0.0);
+        pos = pos + ((off && a > 0.0) ? a : 0.0);
+        cs = cs + ((kind & 4) ? a : 0.0);
     }
-    double atil = aii + pos;
-    if (frow && g.gl == 0 && !(atil > 0.0)) set_flag(flag, 6);
-    double alpha = neg / cs;
-    int o = frow ? prp[i] : 0;
-    for (int base = 0; base < maxlen; base += G) {
-        int q = base + g.gl;
-        bool act = q < len;
-        int k = act ? ci[p0 + q] : 0;
-        bool w = act && strong[p0 + q] && cf[k] == 1;
-        unsigned long long bw = g.bits(w);
-        if (w) {
-            int oo = o + g.below(bw);
-            pci[oo] = cidx[k];
-            pv[oo] = -(alpha * v[p0 + q]) / atil;
+};
+
+// One workgroup per row block of A (the CSR-stream partition).  The block's
+// values and columns are staged in LDS with coalesced loads, each entry marked
+// when it is a strong C neighbour (strength already excludes the diagonal and
+// other labels), whose slot then holds its P column instead; then one thread
+// per row forms the sums and writes the row of P.  A block beyond the LDS
+// stage is done thread per row from global memory.
+constexpr int IF_LDS = 2048, IF_ROWS = 1024;
+__global__ __launch_bounds__(TPB) void k_interp_fill_blk(const int* __restrict__ blk, const int* __restrict__ rp,
+                                                         const int* __restrict__ ci, const double* __restrict__ v,
+                                                         const unsigned char* __restrict__ strong,
+                                                         const int* __restrict__ cf, const int* __restrict__ cidx,
+                                                         const int* __restrict__ label, const int* __restrict__ prp,
+                                                         int* __restrict__ pci, double* __restrict__ pv,
+                                                         int* __restrict__ flag) {
+    __shared__ double sv[IF_LDS];
+    __shared__ int sc[IF_LDS];
+    __shared__ unsigned char sk[IF_LDS];
+    __shared__ int srp[IF_ROWS + 1];
+    const int tid = threadIdx.x;
+    const int r0 = blk[blockIdx.x], r1 = blk[blockIdx.x + 1];
+    if (r0 >= r1) return;
+    const int p0 = rp[r0], nnz = rp[r1] - p0, nrows = r1 - r0;
+    const bool staged = nnz <= IF_LDS && nrows <= IF_ROWS;
+    if (staged) {
+        for (int t = tid; t <= nrows; t += TPB) srp[t] = rp[r0 + t] - p0;
+        for (int q = tid; q < nnz; q += TPB) {
+            const int k = ci[p0 + q];
+            const bool sc4 = strong[p0 + q] && cf[k] == 1;
+            sk[q] = sc4 ? 1 : 0;
+            sc[q] = sc4 ? cidx[k] : k;
+            sv[q] = v[p0 + q];
         }
-        o += __popcll(bw);
+        __syncthreads();
+    }
+    for (int t = tid; t < nrows; t += TPB) {
+        const int i = r0 + t;
+        const int o0 = prp[i], o1 = prp[i + 1];
+        if (cf[i] == 1) {
+            pci[o0] = cidx[i];
+            pv[o0] = 1.0;
+            continue;
+        }
+        if (o1 <= o0) continue;
+        const int li = label ? label[i] : 0;
+        const int qb = staged ? srp[t] : rp[i] - p0, qe = staged ? srp[t + 1] : rp[i + 1] - p0;
+        InterpRow s;
+        for (int q = qb; q < qe; ++q) {
+            bool s4;
+            int k;
+            double a;
+            if (staged) { s4 = sk[q] != 0; k = sc[q]; a = sv[q]; }
+            else { k = ci[p0 + q]; s4 = strong[p0 + q] && cf[k] == 1; a = v[p0 + q]; }
+            const int kind = s4 ? 6 : (k == i ? 1 : ((label && label[k] != li) ? 0 : 2));
+            s.add(kind, a);
+        }
+        const double atil = s.aii + s.pos, alpha = s.neg / s.cs;
+        if (!(atil > 0.0)) set_flag(flag, 6);
+        int o = o0;
+        for (int q = qb; q < qe; ++q) {
+            bool s4;
+            int pc;
+            double a;
+            if (staged) { s4 = sk[q] != 0; pc = sc[q]; a = sv[q]; }
+            else {
+                const int k = ci[p0 + q];
+                s4 = strong[p0 + q] && cf[k] == 1;
+                pc = s4 ? cidx[k] : 0;
+                a = v[p0 + q];
+            }
+            if (s4) {
+                pci[o] = pc;
+                pv[o] = -(alpha * a) / atil;
+                ++o;
+            }
+        }
     }
 }
 
@@ -1856,8 +1900,7 @@ void scan_async(const int* in, int* out, int n, long long* slot, hipStream_t s) 
     int nb = ceil_div(n > 0 ? n : 1, SCAN_B);
     DArr<long long> tmp((size_t)2 * nb + 2, s);
     k_scan_reduce<<<nb, SCAN_T, 0, s>>>(in, n, tmp.p, tmp.p + nb);
-    k_scan_blocks<<<1, 1024, 0, s>>>(tmp.p, tmp.p + nb, nb, out + n, slot);
-    k_scan_apply<<<nb, SCAN_T, 0, s>>>(in, n, tmp.p, out);
+    k_scan_apply<<<nb, SCAN_T, 0, s>>>(in, n, tmp.p, tmp.p + nb, nb, out, slot);
     MGR_LAUNCH_CHECK();
 }
 
@@ -2173,17 +2216,28 @@ void pmis_init(int n, const int* lam, uint64_t seed, int level, double* w, int* 
     MGR_LAUNCH_CHECK();
 }
 
+// thread per point for short strong rows, lane groups for long ones
 void pmis_select(int n, const int* srp, const int* sci, const int* trp, const int* tci, const double* w,
-                 const int* cf, unsigned char* newc, hipStream_t s) {
+                 const int* cf, unsigned char* newc, int avg_row, hipStream_t s) {
     if (n <= 0) return;
-    k_pmis_select<<<nblk(n), TPB, 0, s>>>(n, srp, sci, trp, tci, w, cf, newc);
+    if (avg_row <= PMIS_GROUP_MIN) {
+        k_pmis_select_g<1><<<grid_for(n, 1), TPB, 0, s>>>(n, srp, sci, trp, tci, w, cf, newc);
+    } else {
+        int G = group_for(avg_row);
+        MGR_DISPATCH_G4(G, (k_pmis_select_g<GG><<<grid_for(n, GG), TPB, 0, s>>>(n, srp, sci, trp, tci, w, cf, newc)));
+    }
     MGR_LAUNCH_CHECK();
 }
 
 void pmis_update(int n, const int* srp, const int* sci, const unsigned char* newc, int* cf, int* undecided,
-                 hipStream_t s) {
+                 int avg_row, hipStream_t s) {
     if (n <= 0) return;
-    k_pmis_update<<<nblk(n), TPB, 0, s>>>(n, srp, sci, newc, cf, undecided);
+    if (avg_row <= PMIS_GROUP_MIN) {
+        k_pmis_update_g<1><<<grid_for(n, 1), TPB, 0, s>>>(n, srp, sci, newc, cf, undecided);
+    } else {
+        int G = group_for(avg_row);
+        MGR_DISPATCH_G4(G, (k_pmis_update_g<GG><<<grid_for(n, GG), TPB, 0, s>>>(n, srp, sci, newc, cf, undecided)));
+    }
     MGR_LAUNCH_CHECK();
 }
 
@@ -2203,11 +2257,9 @@ void interp_count(const DCsr& A, const unsigned char* strong, const int* cf, int
 void interp_fill(const DCsr& A, const unsigned char* strong, const int* cf, const int* cidx, const int* label,
                  DCsr& P, int* flag, hipStream_t s) {
     if (A.nr <= 0) return;
-    // the row sums run lane by lane through each chunk of G entries, so the
-    // group is sized to the average row, not the longest
-    int G = group_for((int)((A.nnz + A.nr - 1) / A.nr));
-    MGR_DISPATCH_G4(G, (k_interp_fill_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(
-                           A.nr, A.rp.p, A.ci.p, A.v.p, strong, cf, cidx, label, P.rp.p, P.ci.p, P.v.p, flag)));
+    if (!A.blk.p) throw Error(-1, "interp_fill: operator without row blocks");
+    k_interp_fill_blk<<<A.nblk, TPB, 0, s>>>(A.blk.p, A.rp.p, A.ci.p, A.v.p, strong, cf, cidx, label, P.rp.p, P.ci.p,
+                                             P.v.p, flag);
     MGR_LAUNCH_CHECK();
 }
 

@@ -71,12 +71,14 @@ void strength_compact_fill(const DCsr& A, const unsigned char* strong, const int
 void pattern_transpose_fill(int nr, const int* rp, const int* ci, const int* trp, int* cursor, int* tci,
                             hipStream_t s);
 void pmis_init(int n, const int* lam, uint64_t seed, int level, double* w, int* cf, hipStream_t s);
+// PMIS rounds with lane groups sized to avg_row (the mean row length of A)
 void pmis_select(int n, const int* srp, const int* sci, const int* trp, const int* tci, const double* w,
-                 const int* cf, unsigned char* newc, hipStream_t s);
+                 const int* cf, unsigned char* newc, int avg_row, hipStream_t s);
 void pmis_update(int n, const int* srp, const int* sci, const unsigned char* newc, int* cf, int* undecided,
-                 hipStream_t s);
+                 int avg_row, hipStream_t s);
 void cf_is_c(int n, const int* cf, int* isC, hipStream_t s);
 void interp_count(const DCsr& A, const unsigned char* strong, const int* cf, int* cnt, hipStream_t s);
+// needs A's CSR-stream row blocks (one workgroup each)
 void interp_fill(const DCsr& A, const unsigned char* strong, const int* cf, const int* cidx, const int* label,
                  DCsr& P, int* flag, hipStream_t s);
 void l1_dinv(const DCsr& A, double* dinv, int* flag, hipStream_t s);

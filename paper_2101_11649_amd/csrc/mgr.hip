@@ -311,14 +311,16 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
         // seven rounds usually decide every point: a first batch of eight rarely
         // needs a second (each batch costs a sync and a speculative P count)
         int batch = 8;
+        // strong rows hold about half of a row of A
+        const int avg_row = (int)((A.nnz + 2L * n - 1) / (2L * n));
         for (int total = 0;; total += batch, batch = 4) {
             if (total > 100000) throw Error(MGR_ERR_UNSUPPORTED, "PMIS did not terminate");
             long long* und = S.take(1);
             for (int r = 0; r < batch; ++r) {
-                pmis_select(n, srp.p, sci.p, trp.p, tci.p, w.p, cf.p, newc.p, s);
+                pmis_select(n, srp.p, sci.p, trp.p, tci.p, w.p, cf.p, newc.p, avg_row, s);
                 // the undecided points are counted after the last round of the batch
                 pmis_update(n, srp.p, sci.p, newc.p, cf.p, r + 1 == batch ? reinterpret_cast<int*>(und) : nullptr,
-                            s);
+                            avg_row, s);
             }
             // speculative: C numbering and interpolation row counts for this state
             cf_is_c(n, cf.p, isC.p, s);
@@ -333,6 +335,7 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
         if (nc == 0 || (double)nc > 0.9 * (double)n) break;
         P.nc = (int)nc;
         csr_finish(pp, S);
+        ensure_rowblocks(A);
         interp_fill(A, strong.p, cf.p, cidx.p, L.label.p, P, S.flag(), s);
         // R = P^T and A P, then P^T (A P)
         DCsr R, AP, Ac;
