@@ -959,7 +959,10 @@ __device__ inline int wave_max_int(int v) {
     return v;
 }
 
-constexpr int PMIS_GROUP_MIN = 12;  // strong rows up to this mean length: a thread per point
+// a thread per point (which stops at the first deciding neighbour) for short
+// strong rows or many points; lane groups for small levels with long rows
+constexpr int PMIS_GROUP_MIN = 12;
+constexpr int PMIS_GROUP_MAX_N = 65536;
 
 // PMIS round, G lanes per point.  Selection: an undecided point becomes C
 // when its (w, index) beats every undecided neighbour in S_i and S^T_i, judged
@@ -1445,8 +1448,9 @@ struct InterpRow {
 // One workgroup per row block of A (the CSR-stream partition).  The block's
 // values and columns are staged in LDS with coalesced loads, each entry marked
 // when it is a strong C neighbour (strength already excludes the diagonal and
-// other labels), whose slot then holds its P column instead; then one thread
-// per row forms the sums and writes the row of P.  A block beyond the LDS
+// other labels), whose slot then holds its P column instead, or when it has
+// another label than its row; then one thread per row forms the sums and
+// writes the row of P.  A block beyond the LDS
 // stage is done thread per row from global memory.
 constexpr int IF_LDS = 2048, IF_ROWS = 1024;
 __global__ __launch_bounds__(TPB) void k_interp_fill_blk(const int* __restrict__ blk, const int* __restrict__ rp,
@@ -1467,10 +1471,23 @@ __global__ __launch_bounds__(TPB) void k_interp_fill_blk(const int* __restrict__
     const bool staged = nnz <= IF_LDS && nrows <= IF_ROWS;
     if (staged) {
         for (int t = tid; t <= nrows; t += TPB) srp[t] = rp[r0 + t] - p0;
+        if (label) __syncthreads();
         for (int q = tid; q < nnz; q += TPB) {
             const int k = ci[p0 + q];
             const bool sc4 = strong[p0 + q] && cf[k] == 1;
-            sk[q] = sc4 ? 1 : 0;
+            int mark = sc4 ? 1 : 0;
+            if (label && !sc4) {
+                // another label than the row's: the row is the last one that
+                // starts at or before q
+                int lo = 0, hi = nrows - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (srp[mid] <= q) lo = mid;
+                    else hi = mid - 1;
+                }
+                if (label[k] != label[r0 + lo]) mark = 2;
+            }
+            sk[q] = (unsigned char)mark;
             sc[q] = sc4 ? cidx[k] : k;
             sv[q] = v[p0 + q];
         }
@@ -1492,9 +1509,15 @@ __global__ __launch_bounds__(TPB) void k_interp_fill_blk(const int* __restrict__
             bool s4;
             int k;
             double a;
-            if (staged) { s4 = sk[q] != 0; k = sc[q]; a = sv[q]; }
-            else { k = ci[p0 + q]; s4 = strong[p0 + q] && cf[k] == 1; a = v[p0 + q]; }
-            const int kind = s4 ? 6 : (k == i ? 1 : ((label && label[k] != li) ? 0 : 2));
+            bool other;
+            if (staged) { const int mk = sk[q]; s4 = mk == 1; other = mk == 2; k = sc[q]; a = sv[q]; }
+            else {
+                k = ci[p0 + q];
+                s4 = strong[p0 + q] && cf[k] == 1;
+                other = label && label[k] != li;
+                a = v[p0 + q];
+            }
+            const int kind = s4 ? 6 : (k == i ? 1 : (other ? 0 : 2));
             s.add(kind, a);
         }
         const double atil = s.aii + s.pos, alpha = s.neg / s.cs;
@@ -1504,7 +1527,7 @@ __global__ __launch_bounds__(TPB) void k_interp_fill_blk(const int* __restrict__
             bool s4;
             int pc;
             double a;
-            if (staged) { s4 = sk[q] != 0; pc = sc[q]; a = sv[q]; }
+            if (staged) { s4 = sk[q] == 1; pc = sc[q]; a = sv[q]; }
             else {
                 const int k = ci[p0 + q];
                 s4 = strong[p0 + q] && cf[k] == 1;
@@ -2216,11 +2239,10 @@ void pmis_init(int n, const int* lam, uint64_t seed, int level, double* w, int* 
     MGR_LAUNCH_CHECK();
 }
 
-// thread per point for short strong rows, lane groups for long ones
 void pmis_select(int n, const int* srp, const int* sci, const int* trp, const int* tci, const double* w,
                  const int* cf, unsigned char* newc, int avg_row, hipStream_t s) {
     if (n <= 0) return;
-    if (avg_row <= PMIS_GROUP_MIN) {
+    if (avg_row <= PMIS_GROUP_MIN || n > PMIS_GROUP_MAX_N) {
         k_pmis_select_g<1><<<grid_for(n, 1), TPB, 0, s>>>(n, srp, sci, trp, tci, w, cf, newc);
     } else {
         int G = group_for(avg_row);
@@ -2232,7 +2254,7 @@ void pmis_select(int n, const int* srp, const int* sci, const int* trp, const in
 void pmis_update(int n, const int* srp, const int* sci, const unsigned char* newc, int* cf, int* undecided,
                  int avg_row, hipStream_t s) {
     if (n <= 0) return;
-    if (avg_row <= PMIS_GROUP_MIN) {
+    if (avg_row <= PMIS_GROUP_MIN || n > PMIS_GROUP_MAX_N) {
         k_pmis_update_g<1><<<grid_for(n, 1), TPB, 0, s>>>(n, srp, sci, newc, cf, undecided);
     } else {
         int G = group_for(avg_row);
