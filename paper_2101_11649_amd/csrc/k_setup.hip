@@ -1453,6 +1453,8 @@ struct InterpRow {
 // writes the row of P.  A block beyond the LDS
 // stage is done thread per row from global memory.
 constexpr int IF_LDS = 2048, IF_ROWS = 1024;
+// rows longer than this on average use the lane-group kernel below instead
+constexpr int INTERP_LDS_MAX_AVG = 45;
 __global__ __launch_bounds__(TPB) void k_interp_fill_blk(const int* __restrict__ blk, const int* __restrict__ rp,
                                                          const int* __restrict__ ci, const double* __restrict__ v,
                                                          const unsigned char* __restrict__ strong,
@@ -1540,6 +1542,72 @@ __global__ __launch_bounds__(TPB) void k_interp_fill_blk(const int* __restrict__
                 ++o;
             }
         }
+    }
+}
+
+// Direct interpolation for long rows, G lanes per row: the row sums are formed
+// strictly left to right (each chunk's values are broadcast lane by lane), as
+// the oracle does.
+template <int G>
+__global__ __launch_bounds__(TPB) void k_interp_fill_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                       const double* __restrict__ v,
+                                                       const unsigned char* __restrict__ strong,
+                                                       const int* __restrict__ cf, const int* __restrict__ cidx,
+                                                       const int* __restrict__ label, const int* __restrict__ prp,
+                                                       int* __restrict__ pci, double* __restrict__ pv,
+                                                       int* __restrict__ flag) {
+    Grp<G> g;
+    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    bool valid = i < n;
+    bool frow = valid && cf[i] != 1 && prp[i + 1] > prp[i];
+    if (valid && cf[i] == 1 && g.gl == 0) { pci[prp[i]] = cidx[i]; pv[prp[i]] = 1.0; }
+    int p0 = valid ? rp[i] : 0, len = frow ? rp[i + 1] - p0 : 0;
+    int maxlen = wave_max_int(len);
+    int li = (frow && label) ? label[i] : 0;
+    double aii = 0.0, neg = 0.0, pos = 0.0, cs = 0.0;
+    for (int base = 0; base < maxlen; base += G) {
+        int q = base + g.gl;
+        bool act = q < len;
+        int k = act ? ci[p0 + q] : -1;
+        double a = act ? v[p0 + q] : 0.0;
+        int kind = 0;  // 1 diag, 2 same-label off-diagonal, 0 other / inactive
+        bool sc = false;
+        if (act) {
+            if (k == i) kind = 1;
+            else if (!(label && label[k] != li)) {
+                kind = 2;
+                sc = strong[p0 + q] && cf[k] == 1;
+            }
+        }
+        const int lim = min(G, maxlen - base);
+        for (int t = 0; t < lim; ++t) {
+            double at = __shfl(a, g.gbase + t, WAVE);
+            int kt = __shfl(kind, g.gbase + t, WAVE);
+            int st = __shfl((int)sc, g.gbase + t, WAVE);
+            if (kt == 1) aii = at;
+            else if (kt == 2) {
+                if (at < 0.0) neg = neg + at;
+                else if (at > 0.0) pos = pos + at;
+                if (st) cs = cs + at;
+            }
+        }
+    }
+    double atil = aii + pos;
+    if (frow && g.gl == 0 && !(atil > 0.0)) set_flag(flag, 6);
+    double alpha = neg / cs;
+    int o = frow ? prp[i] : 0;
+    for (int base = 0; base < maxlen; base += G) {
+        int q = base + g.gl;
+        bool act = q < len;
+        int k = act ? ci[p0 + q] : 0;
+        bool w = act && strong[p0 + q] && cf[k] == 1;
+        unsigned long long bw = g.bits(w);
+        if (w) {
+            int oo = o + g.below(bw);
+            pci[oo] = cidx[k];
+            pv[oo] = -(alpha * v[p0 + q]) / atil;
+        }
+        o += __popcll(bw);
     }
 }
 
@@ -2279,9 +2347,18 @@ void interp_count(const DCsr& A, const unsigned char* strong, const int* cf, int
 void interp_fill(const DCsr& A, const unsigned char* strong, const int* cf, const int* cidx, const int* label,
                  DCsr& P, int* flag, hipStream_t s) {
     if (A.nr <= 0) return;
-    if (!A.blk.p) throw Error(-1, "interp_fill: operator without row blocks");
-    k_interp_fill_blk<<<A.nblk, TPB, 0, s>>>(A.blk.p, A.rp.p, A.ci.p, A.v.p, strong, cf, cidx, label, P.rp.p, P.ci.p,
-                                             P.v.p, flag);
+    const int avg = (int)((A.nnz + A.nr - 1) / A.nr);
+    if (avg > INTERP_LDS_MAX_AVG) {
+        // the row sums run lane by lane through each chunk of G entries, so
+        // the group is sized to the average row, not the longest
+        int G = group_for(avg);
+        MGR_DISPATCH_G4(G, (k_interp_fill_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(
+                               A.nr, A.rp.p, A.ci.p, A.v.p, strong, cf, cidx, label, P.rp.p, P.ci.p, P.v.p, flag)));
+    } else {
+        if (!A.blk.p) throw Error(-1, "interp_fill: operator without row blocks");
+        k_interp_fill_blk<<<A.nblk, TPB, 0, s>>>(A.blk.p, A.rp.p, A.ci.p, A.v.p, strong, cf, cidx, label, P.rp.p,
+                                                 P.ci.p, P.v.p, flag);
+    }
     MGR_LAUNCH_CHECK();
 }
 
