@@ -112,6 +112,17 @@ void mdot(long n, const double* V, long ldv, int nvec, const double* w, double* 
 // nvec <= 16 (returns false otherwise, and does nothing).
 bool maxpy_mdot(long n, const double* V, long ldv, int nvec, const double* h, double* w, double* part,
                 double* out, hipStream_t s);
+// Arnoldi step with delayed reorthogonalisation (two passes over the basis).
+// arnoldi_dots: out[0..nvec) = V_i . V_{nvec-1}, out[nvec..2 nvec) = V_i . w
+// (part needs 2 nvec KRYLOV_PARTS doubles).  arnoldi_update: from those dots,
+// V_{nvec-1} gets its second Gram-Schmidt pass and normalisation, w is
+// orthogonalised once against the final V_0..V_{nvec-1}; coef[0..nvec) = w's
+// coefficients, coef[64] = the normalisation; *norm2_out = ||w||^2, after
+// which csrc[0..ncopy) is stored to the host-mapped cdst.
+void arnoldi_dots(long n, const double* V, long ldv, int nvec, const double* w, double* part, double* out,
+                  hipStream_t s);
+void arnoldi_update(long n, double* V, long ldv, int nvec, const double* sh, double* w, double* part,
+                    double* norm2_out, double* coef, const double* csrc, double* cdst, int ncopy, hipStream_t s);
 // w -= hscale * sum_i h[i] V_i; if norm2_out, *norm2_out = ||w_new||^2, after
 // which csrc[0..ncopy) (device, may hold norm2_out) is stored to the
 // host-mapped cdst.

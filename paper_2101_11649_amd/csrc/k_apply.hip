@@ -416,6 +416,88 @@ __global__ __launch_bounds__(TPB) void k_maxpy(long n, const double* __restrict_
     }
 }
 
+// Arnoldi step with delayed reorthogonalisation, first pass: the dots of
+// V_0 .. V_{nvec-1} with u = V_{nvec-1} (the newest basis vector, so far
+// orthogonalised once) and with w = A z, as partials part[i * np + block] (u)
+// and part[(nvec + i) * np + block] (w).
+template <int NB>
+__global__ __launch_bounds__(TPB) void k_mdot2(long n, const double* __restrict__ V, long ldv, int nvec,
+                                               const double* __restrict__ w, double* __restrict__ part) {
+    const int i0 = blockIdx.y * NB;
+    const double* u = V + (long)(nvec - 1) * ldv;
+    double au[NB], aw[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) au[t] = aw[t] = 0.0;
+    long stride = (long)gridDim.x * TPB;
+    for (long r = (long)blockIdx.x * TPB + threadIdx.x; r < n; r += stride) {
+        const double ur = u[r], wr = w[r];
+#pragma unroll
+        for (int t = 0; t < NB; ++t)
+            if (i0 + t < nvec) {
+                const double x = V[(long)(i0 + t) * ldv + r];
+                au[t] += x * ur;
+                aw[t] += x * wr;
+            }
+    }
+    const int nv = min(NB, nvec - i0);
+    block_sums<NB>(au, nv, part + (long)i0 * gridDim.x + blockIdx.x, gridDim.x);
+    __syncthreads();
+    block_sums<NB>(aw, nv, part + (long)(nvec + i0) * gridDim.x + blockIdx.x, gridDim.x);
+}
+
+// Second pass.  From the first pass's s_i = V_i . u and h_i = V_i . w (i <= j =
+// nvec - 1): u's coefficients a_i = s_i (i < j) and alpha = sqrt(s_j - sum a_i^2)
+// give the final basis vector v_j = (u - sum_{i<j} a_i V_i) / alpha, and w's
+// coefficients in the final basis are c_i = h_i (i < j), c_j = (h_j - sum_{i<j}
+// a_i h_i) / alpha.  Then V_j = v_j, w -= sum_{i<j} c_i V_i + c_j v_j, with
+// partial sums of ||w||^2; block 0 stores c_0..c_j at coef[0..j] and alpha at
+// coef[64].  alpha = 0 (u in the span of V_0..V_{j-1}) leaves v_j = 0.
+__global__ __launch_bounds__(TPB) void k_arnoldi_update(long n, double* __restrict__ V, long ldv, int nvec,
+                                                        const double* __restrict__ sh, double* __restrict__ w,
+                                                        double* __restrict__ normpart, double* __restrict__ coef) {
+    __shared__ double as[64], cs[64];
+    __shared__ double scal[2];
+    const int j = nvec - 1;
+    const double* sd = sh;
+    const double* hd = sh + nvec;
+    if ((int)threadIdx.x < j) { as[threadIdx.x] = sd[threadIdx.x]; cs[threadIdx.x] = hd[threadIdx.x]; }
+    if (threadIdx.x == 0) {
+        double ss = 0.0, sx = 0.0;
+        for (int i = 0; i < j; ++i) {
+            ss += sd[i] * sd[i];
+            sx += sd[i] * hd[i];
+        }
+        const double a2 = sd[j] - ss;
+        const double alpha = a2 > 0.0 ? sqrt(a2) : 0.0;
+        const double ainv = alpha > 0.0 ? 1.0 / alpha : 0.0;
+        const double cj = (hd[j] - sx) * ainv;
+        scal[0] = ainv;
+        scal[1] = cj;
+        if (blockIdx.x == 0) { coef[64] = alpha; coef[j] = cj; }
+    }
+    if (blockIdx.x == 0 && (int)threadIdx.x < j) coef[threadIdx.x] = hd[threadIdx.x];
+    __syncthreads();
+    const double ainv = scal[0], cj = scal[1];
+    double* u = V + (long)j * ldv;
+    double acc = 0.0;
+    long stride = (long)gridDim.x * TPB;
+    for (long r = (long)blockIdx.x * TPB + threadIdx.x; r < n; r += stride) {
+        double t = u[r], q = w[r];
+        for (int i = 0; i < j; ++i) {
+            const double x = V[(long)i * ldv + r];
+            t -= as[i] * x;
+            q -= cs[i] * x;
+        }
+        const double v = t * ainv;
+        q -= cj * v;
+        u[r] = v;
+        w[r] = q;
+        acc += q * q;
+    }
+    double a[1] = {acc};
+    block_reduce_write<1>(a, normpart + blockIdx.x, 0);
+}
+
 // One level of a triangular solve: for the rows of this level,
 // x_i = (b_i - sum_{j != i} t_ij x_j) / t_ii (unit: no division, no diagonal stored).
 template <typename T>
@@ -653,6 +735,26 @@ void maxpy(long n, const double* V, long ldv, int nvec, const double* h, double 
     if (nvec <= 0 && !norm2_out) return;
     k_maxpy<<<np, TPB, 0, s>>>(n, V, ldv, nvec, h, hscale, w, norm2_out ? part : nullptr);
     if (norm2_out) k_reduce_parts<<<1, TPB, 0, s>>>(np, part, norm2_out, csrc, cdst, ncopy);
+    MGR_LAUNCH_CHECK();
+}
+
+void arnoldi_dots(long n, const double* V, long ldv, int nvec, const double* w, double* part, double* out,
+                  hipStream_t s) {
+    if (nvec <= 0 || nvec > 64) throw Error(-1, "arnoldi_dots: 1 to 64 vectors");
+    int np = krylov_parts(n);
+    constexpr int NB = 8;
+    dim3 grid(np, ceil_div(nvec, NB));
+    k_mdot2<NB><<<grid, TPB, 0, s>>>(n, V, ldv, nvec, w, part);
+    k_reduce_parts<<<2 * nvec, TPB, 0, s>>>(np, part, out, nullptr, nullptr, 0);
+    MGR_LAUNCH_CHECK();
+}
+
+void arnoldi_update(long n, double* V, long ldv, int nvec, const double* sh, double* w, double* part,
+                    double* norm2_out, double* coef, const double* csrc, double* cdst, int ncopy, hipStream_t s) {
+    if (nvec <= 0 || nvec > 64) throw Error(-1, "arnoldi_update: 1 to 64 vectors");
+    int np = krylov_parts(n);
+    k_arnoldi_update<<<np, TPB, 0, s>>>(n, V, ldv, nvec, sh, w, part, coef);
+    k_reduce_parts<<<1, TPB, 0, s>>>(np, part, norm2_out, csrc, cdst, ncopy);
     MGR_LAUNCH_CHECK();
 }
 

@@ -586,8 +586,10 @@ __global__ __launch_bounds__(WAVE) void k_spgemm_dw(int nr, const int* __restric
                                                     const int* __restrict__ bci, const double* __restrict__ bv,
                                                     int ncols, const int* __restrict__ crp, int* __restrict__ cci,
                                                     double* __restrict__ cv, int* __restrict__ cnt) {
-    __shared__ double acc[FILL ? SPGEMM_DENSE : 1];
-    __shared__ unsigned char hit[SPGEMM_DENSE];
+    // dynamic LDS sized to the columns: ncols doubles (fill only), then ncols flags
+    extern __shared__ double dyn_lds[];
+    double* acc = dyn_lds;
+    unsigned char* hit = reinterpret_cast<unsigned char*>(dyn_lds + (FILL ? ncols : 0));
     const int row = blockIdx.x;
     const int lane = threadIdx.x;
     if (row >= nr) return;
@@ -2137,7 +2139,8 @@ static void spgemm_launch(const DCsr& A, const DCsr& B, int max_row, const int* 
     // max_row selects the variant: <= 64 entries per row of A -> one head per lane
     if (A.nr <= 0) return;
     if (B.nc <= SPGEMM_DENSE && A.nr <= SPGEMM_DENSE_ROWS && (long)A.nr * B.nc <= SPGEMM_DENSE_WORK) {
-        k_spgemm_dw<FILL><<<A.nr, WAVE, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p, B.v.p, B.nc, crp, cci,
+        const size_t lds = (size_t)B.nc * (FILL ? sizeof(double) + 1 : 1);
+        k_spgemm_dw<FILL><<<A.nr, WAVE, lds, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p, B.v.p, B.nc, crp, cci,
                                                 cv, cnt);
         MGR_LAUNCH_CHECK();
         return;

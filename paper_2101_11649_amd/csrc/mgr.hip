@@ -719,7 +719,7 @@ struct Ctx {
     DArr<double> apply_tmp;
     // pinned copies of the Arnoldi coefficients, one row of HROW per iteration,
     // and the event that marks each copy
-    static constexpr int HROW = 130;
+    static constexpr int HROW = 200;
     double* hpin = nullptr;
     double* hpin_dev = nullptr;  // the same rows as seen by kernels
     std::vector<hipEvent_t> hev;
@@ -1144,8 +1144,8 @@ static void ensure_krylov(Ctx& c) {
     hipStream_t s = c.s;
     c.V.alloc((size_t)(m + 1) * c.n, s);
     c.Z.alloc((size_t)m * c.n, s);
-    c.hbuf.alloc(256, s);
-    c.part.alloc((size_t)(m + 2) * KRYLOV_PARTS, s);
+    c.hbuf.alloc(512, s);
+    c.part.alloc((size_t)2 * (m + 2) * KRYLOV_PARTS, s);
     c.yd.alloc(64, s);
     if (c.hpin) (void)hipHostFree(c.hpin);
     c.hpin = nullptr;
@@ -1162,16 +1162,29 @@ static void ensure_krylov(Ctx& c) {
     c.kr_n = c.n;
 }
 
-// Flexible GMRES(m) with right preconditioning (Saad 1993): x0 = 0, CGS2
-// Arnoldi, Givens rotations on the host, stop when |g_{j+1}| <= rtol ||b||,
-// then the true residual ||b - A x|| is checked and the cycle restarted if needed.
+// Flexible GMRES(m) with right preconditioning (Saad 1993): x0 = 0, Givens
+// rotations on the host, stop when |g_{k}| <= rtol ||b||, then the true
+// residual ||b - A x|| is checked and the cycle restarted if needed.
 //
-// The basis vector is normalised on the device, so iteration j+1 can be queued
-// before the host has seen the coefficients of iteration j: the host processes
-// column j-1 while the GPU runs iteration j.  When the residual estimate
-// predicts convergence within the next column, the host waits for the current
-// column instead, so that no iteration is queued past convergence in the usual
-// case (one queued past it is only wasted work: it never enters the solution).
+// Arnoldi: classical Gram-Schmidt applied twice, with the second pass of each
+// basis vector delayed into the next step (two passes over the basis per
+// step instead of three).  Step j starts from u_j, the newest basis vector
+// after one pass and a normalisation, stored as V_j: z_j = M^-1 u_j, w = A z_j;
+// the first pass forms V_i . u_j and V_i . w (i <= j); the second turns u_j into
+// the final v_j = (u_j - sum_{i<j} a_i v_i) / alpha_j and orthogonalises w once
+// against v_0 .. v_j with coefficients c_i, leaving w' = nu_j u_{j+1}.  Since
+// u_{j+1} = sum_{i<=j} a'_i v_i + alpha_{j+1} v_{j+1}, column j of the
+// Hessenberg matrix is c_i + nu_j a'_i (i <= j) and nu_j alpha_{j+1}: it is
+// complete once the next step's first pass (or a separate one at the end of a
+// cycle or near convergence) has given a' and alpha_{j+1}.  z_j comes from u_j
+// rather than v_j, which the flexible method allows (A Z = V H holds with the
+// final basis).
+//
+// The coefficients of step j reach a pinned host row from the kernel that
+// ends the step, so step j+1 is queued before the host has seen step j; the
+// host processes step j-1 meanwhile.  When the residual estimate predicts
+// convergence with the newest column, the host completes that column with a
+// separate first pass on the newest vector instead of queuing another step.
 static int fgmres(Ctx& c, bool tr, const double* b, double* x, mgr_solve_info* info) {
     hipStream_t s = c.s;
     ensure_krylov(c);
@@ -1179,14 +1192,21 @@ static int fgmres(Ctx& c, bool tr, const double* b, double* x, mgr_solve_info* i
     const int m = c.o.restart;
     double* V = c.V.p;
     double* Z = c.Z.p;
-    double* hb = c.hbuf.p;  // [0,64): h1, [64,128): h2, [128]: ||w||^2, [129]: scratch
+    // device scalars: [0, 2 nv) first-pass dots, [HC, HC + nv) coefficients c,
+    // [HA] alpha, [HN] ||w'||^2, [HF, HF + nv + 1) dots of a separate pass,
+    // [HS] a norm
+    double* hb = c.hbuf.p;
+    constexpr int HC = 128, HA = 192, HN = 193, HF = 256, HS = 511, NPUB = 194;
     double* hscr = c.hpin + (size_t)Ctx::HROW * m;   // host row for the scalar reads
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), cpend(m + 1);
     set<double>(n, x, 0.0, s);
-    mdot(n, b, n, 1, b, c.part.p, hb + 129, s);
-    MGR_HIP(hipMemcpyAsync(hscr + 129, hb + 129, sizeof(double), hipMemcpyDeviceToHost, s));
-    MGR_HIP(hipStreamSynchronize(s));
-    double bnorm = std::sqrt(hscr[129]);
+    auto read_scalar = [&](const double* dptr) {
+        MGR_HIP(hipMemcpyAsync(hscr, dptr, sizeof(double), hipMemcpyDeviceToHost, s));
+        MGR_HIP(hipStreamSynchronize(s));
+        return hscr[0];
+    };
+    mdot(n, b, n, 1, b, c.part.p, hb + HS, s);
+    double bnorm = std::sqrt(read_scalar(hb + HS));
     mgr_solve_info inf{};
     if (bnorm == 0.0) {
         inf.status = MGR_OK;
@@ -1203,10 +1223,8 @@ static int fgmres(Ctx& c, bool tr, const double* b, double* x, mgr_solve_info* i
         if (first) copy<double, double>(n, b, V, s);
         else matvec(c, tr, x, b, V, -1.0, 1.0);
         first = false;
-        mdot(n, V, n, 1, V, c.part.p, hb + 129, s);
-        MGR_HIP(hipMemcpyAsync(hscr + 129, hb + 129, sizeof(double), hipMemcpyDeviceToHost, s));
-        MGR_HIP(hipStreamSynchronize(s));
-        double beta = std::sqrt(hscr[129]);
+        mdot(n, V, n, 1, V, c.part.p, hb + HS, s);
+        double beta = std::sqrt(read_scalar(hb + HS));
         if (beta <= tol) {
             converged = true;
             est = truer = beta / bnorm;
@@ -1216,63 +1234,108 @@ static int fgmres(Ctx& c, bool tr, const double* b, double* x, mgr_solve_info* i
         scale(n, 1.0 / beta, V, s);
         std::fill(g.begin(), g.end(), 0.0);
         std::fill(H.begin(), H.end(), 0.0);
-        g[0] = beta;
+        g[0] = beta;  // times alpha_0 (about 1) once step 0 is read
         const int jmax = std::min(m, c.o.maxiter - iters);
-        int k = 0;          // columns processed on the host
+        int k = 0;          // Hessenberg columns completed
+        int rows = 0;       // steps whose coefficients the host has read
         bool stop = false;  // converged, broke down, or out of iterations
-        double rate = 1.0;  // last ratio |g_{j+1}| / |g_j|
-        // Givens update of column j from its pinned coefficients
-        auto process = [&](int j) {
-            MGR_HIP(hipEventSynchronize(c.hev[j]));
-            const double* hh = c.hpin + (size_t)Ctx::HROW * j;
-            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[64 + i];
-            double hn = std::sqrt(hh[128]);
-            H[(size_t)(j + 1) * m + j] = hn;
-            for (int i = 0; i < j; ++i) {
-                double a0 = H[(size_t)i * m + j], a1 = H[(size_t)(i + 1) * m + j];
-                H[(size_t)i * m + j] = cs[i] * a0 + sn[i] * a1;
-                H[(size_t)(i + 1) * m + j] = -sn[i] * a0 + cs[i] * a1;
+        double rate = 1.0;  // last ratio |g_{k+1}| / |g_k|
+        double nupend = 0.0;
+        // Givens update of column col = k from its entries (H column already filled)
+        auto rotate = [&](int col) {
+            for (int i = 0; i < col; ++i) {
+                double a0 = H[(size_t)i * m + col], a1 = H[(size_t)(i + 1) * m + col];
+                H[(size_t)i * m + col] = cs[i] * a0 + sn[i] * a1;
+                H[(size_t)(i + 1) * m + col] = -sn[i] * a0 + cs[i] * a1;
             }
-            double a0 = H[(size_t)j * m + j], a1 = H[(size_t)(j + 1) * m + j];
+            const double hn = H[(size_t)(col + 1) * m + col];
+            double a0 = H[(size_t)col * m + col], a1 = hn;
             double den = std::sqrt(a0 * a0 + a1 * a1);
-            if (den == 0.0) { cs[j] = 1.0; sn[j] = 0.0; }
-            else { cs[j] = a0 / den; sn[j] = a1 / den; }
-            H[(size_t)j * m + j] = cs[j] * a0 + sn[j] * a1;
-            H[(size_t)(j + 1) * m + j] = 0.0;
-            double gprev = std::fabs(g[j]);
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
+            if (den == 0.0) { cs[col] = 1.0; sn[col] = 0.0; }
+            else { cs[col] = a0 / den; sn[col] = a1 / den; }
+            H[(size_t)col * m + col] = cs[col] * a0 + sn[col] * a1;
+            H[(size_t)(col + 1) * m + col] = 0.0;
+            double gprev = std::fabs(g[col]);
+            g[col + 1] = -sn[col] * g[col];
+            g[col] = cs[col] * g[col];
             ++iters;
-            k = j + 1;
-            est = std::fabs(g[j + 1]) / bnorm;
-            if (gprev > 0.0) rate = std::min(1.0, std::max(0.05, std::fabs(g[j + 1]) / gprev));
-            if (hn == 0.0 || std::fabs(g[j + 1]) <= tol || iters >= c.o.maxiter) stop = true;
+            k = col + 1;
+            est = std::fabs(g[col + 1]) / bnorm;
+            if (gprev > 0.0) rate = std::min(1.0, std::max(0.05, std::fabs(g[col + 1]) / gprev));
+            if (hn == 0.0 || std::fabs(g[col + 1]) <= tol || iters >= c.o.maxiter) stop = true;
+        };
+        // column col from its pending coefficients and the next vector's
+        // first-pass dots a[0..col] and normalisation alpha
+        auto complete = [&](int col, const double* a, double alpha) {
+            for (int i = 0; i <= col; ++i) H[(size_t)i * m + col] = cpend[i] + nupend * a[i];
+            H[(size_t)(col + 1) * m + col] = nupend * alpha;
+            rotate(col);
+        };
+        auto alpha_of = [](const double* sdots, int j) {
+            double ss = 0.0;
+            for (int i = 0; i < j; ++i) ss += sdots[i] * sdots[i];
+            double a2 = sdots[j] - ss;
+            return a2 > 0.0 ? std::sqrt(a2) : 0.0;
+        };
+        // read step r's row: complete column r-1 (unless done already), keep column r pending
+        auto process_row = [&](int r) {
+            MGR_HIP(hipEventSynchronize(c.hev[r]));
+            const double* hh = c.hpin + (size_t)Ctx::HROW * r;
+            const double alpha = hh[HA];
+            if (r == 0) g[0] = beta * alpha;
+            else if (k == r - 1) complete(r - 1, hh, alpha);
+            if (!(alpha > 0.0) && !stop) stop = true;  // breakdown of the basis
+            for (int i = 0; i <= r; ++i) cpend[i] = hh[HC + i];
+            nupend = std::sqrt(hh[HN]);
+        };
+        // a separate first pass on u_{col+1} = V_{col+1} completes column col
+        auto finish_column = [&](int col) {
+            mdot(n, V, n, col + 2, V + (long)(col + 1) * n, c.part.p, hb + HF, s);
+            MGR_HIP(hipMemcpyAsync(hscr, hb + HF, sizeof(double) * (col + 2), hipMemcpyDeviceToHost, s));
+            MGR_HIP(hipStreamSynchronize(s));
+            complete(col, hscr, alpha_of(hscr, col + 1));
         };
         for (int j = 0; j < jmax && !stop; ++j) {
-            double* vj = V + (long)j * n;
+            if (j >= 1 && k < j) {
+                // would column j-1 converge?  (predicted from the last rate)
+                double pred = std::fabs(g[k]) * std::pow(rate, (double)(j - k));
+                if (pred <= 4.0 * tol) {
+                    while (rows < j && !stop) process_row(rows++);
+                    if (stop) break;
+                    // tentative: column j-1 as if u_j were final
+                    std::vector<double> col(j + 1);
+                    for (int i = 0; i < j; ++i) col[i] = cpend[i];
+                    col[j] = nupend;
+                    for (int i = 0; i < j - 1; ++i) {
+                        double a0 = col[i], a1 = col[i + 1];
+                        col[i] = cs[i] * a0 + sn[i] * a1;
+                        col[i + 1] = -sn[i] * a0 + cs[i] * a1;
+                    }
+                    double den = std::sqrt(col[j - 1] * col[j - 1] + col[j] * col[j]);
+                    double tg = den > 0.0 ? std::fabs(g[j - 1] * col[j] / den) : 0.0;
+                    if (tg <= 2.0 * tol) {
+                        finish_column(j - 1);
+                        if (stop) break;
+                    }
+                }
+            }
+            double* uj = V + (long)j * n;
             double* zj = Z + (long)j * n;
             double* w = V + (long)(j + 1) * n;
-            mgr_apply_top(c, vj, zj, tr);
+            mgr_apply_top(c, uj, zj, tr);
             matvec(c, tr, zj, nullptr, w, 1.0, 0.0);
-            // classical Gram-Schmidt, twice; then w /= ||w|| on the device
-            mdot(n, V, n, j + 1, w, c.part.p, hb, s);
-            if (!maxpy_mdot(n, V, n, j + 1, hb, w, c.part.p, hb + 64, s)) {
-                maxpy(n, V, n, j + 1, hb, 1.0, w, c.part.p, nullptr, s);
-                mdot(n, V, n, j + 1, w, c.part.p, hb + 64, s);
-            }
-            // the norm's reduction also stores the column's 129 coefficients to
-            // its pinned host row
-            maxpy(n, V, n, j + 1, hb + 64, 1.0, w, c.part.p, hb + 128, s, hb, c.hpin_dev + (size_t)Ctx::HROW * j,
-                  129);
+            arnoldi_dots(n, V, n, j + 1, w, c.part.p, hb, s);
+            // the norm's reduction also stores the step's coefficients to its pinned row
+            arnoldi_update(n, V, n, j + 1, hb, w, c.part.p, hb + HN, hb + HC, hb, c.hpin_dev + (size_t)Ctx::HROW * j,
+                           NPUB, s);
             MGR_HIP(hipEventRecord(c.hev[j], s));
-            scale_by_norm(n, hb + 128, w, s);
-            // wait for this column if convergence looks near (predicted from the
-            // last processed column), else for the previous one
-            double pred = std::fabs(g[k]) * std::pow(rate, (double)(j + 1 - k));
-            int upto = (j + 1 == jmax || pred <= 4.0 * tol) ? j : j - 1;
-            while (k <= upto && !stop) process(k);
+            scale_by_norm(n, hb + HN, w, s);
+            while (rows < j && !stop) process_row(rows++);
         }
-        while (!stop && k < jmax) process(k);
+        if (!stop) {
+            while (rows < jmax && !stop) process_row(rows++);
+            if (!stop && k < jmax) finish_column(jmax - 1);
+        }
         for (int i = k - 1; i >= 0; --i) {
             double t = g[i];
             for (int q = i + 1; q < k; ++q) t -= H[(size_t)i * m + q] * y[q];
@@ -1283,10 +1346,8 @@ static int fgmres(Ctx& c, bool tr, const double* b, double* x, mgr_solve_info* i
         // true residual
         double* r = V;
         matvec(c, tr, x, b, r, -1.0, 1.0);
-        mdot(n, r, n, 1, r, c.part.p, hb + 129, s);
-        MGR_HIP(hipMemcpyAsync(hscr + 129, hb + 129, sizeof(double), hipMemcpyDeviceToHost, s));
-        MGR_HIP(hipStreamSynchronize(s));
-        truer = std::sqrt(hscr[129]) / bnorm;
+        mdot(n, r, n, 1, r, c.part.p, hb + HS, s);
+        truer = std::sqrt(read_scalar(hb + HS)) / bnorm;
         if (truer <= c.o.rtol) { converged = true; break; }
         if (iters >= c.o.maxiter) break;
         first = false;

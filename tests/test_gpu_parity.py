@@ -248,3 +248,26 @@ def test_ilu0_on_compositional_components():
     gs.set_opts(precision=32)
     X32, [i32] = gs.solve(s["rhs"])
     assert i32.status == 0 and rel(X32.cpu().numpy(), xo) <= 1e-7
+
+
+@pytest.mark.parametrize("name,restart", [("tpfa_7x6x5", 7), ("mimetic_9x7x6", 5), ("comp_8x8x6", 3),
+                                          ("frac_12^3", 10)])
+def test_solve_with_restarts(name, restart):
+    """Short restart cycles: every cycle ends on a completed Hessenberg column
+    and the next one restarts from the true residual; iteration counts and
+    solutions as the oracle's FGMRES(restart)."""
+    s = SMALL[name]()
+    om = oracle_mgr(s)
+    gs = gpu_solver(s, restart=restart, rtol=1e-10)
+    xo, io = om.solve(s["rhs"], restart=restart, rtol=1e-10)
+    X, [ig] = gs.solve(s["rhs"])
+    x = X.cpu().numpy()
+    A = W.csr_of(s)
+    tr = np.linalg.norm(s["rhs"] - A @ x) / np.linalg.norm(s["rhs"])
+    say(f"{name} restart {restart}: iters gpu {ig.iterations} ({ig.restarts} restarts) oracle {io.iterations} "
+        f"({io.restarts}); true res {tr:.2e}; x err {rel(x, xo):.2e}")
+    assert ig.status == 0 and io.status == 0 and ig.restarts >= 1
+    assert abs(ig.iterations - io.iterations) <= 1
+    assert tr <= 1e-10
+    assert rel(x, xo) <= 1e-8
+    gs.close()
