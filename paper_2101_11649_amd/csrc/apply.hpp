@@ -118,14 +118,15 @@ bool maxpy_mdot(long n, const double* V, long ldv, int nvec, const double* h, do
 // V_{nvec-1} gets its second Gram-Schmidt pass and normalisation, w is
 // orthogonalised once against the final V_0..V_{nvec-1}; coef[0..nvec) = w's
 // coefficients, coef[64] = the normalisation; *norm2_out = ||w||^2, after
-// which csrc[0..ncopy) is stored to the host-mapped cdst.
+// which csrc[0..ncopy) is stored to the host-mapped cdst and then 1.0 to
+// cdst[ncopy] (the ready flag).
 void arnoldi_dots(long n, const double* V, long ldv, int nvec, const double* w, double* part, double* out,
                   hipStream_t s);
 void arnoldi_update(long n, double* V, long ldv, int nvec, const double* sh, double* w, double* part,
                     double* norm2_out, double* coef, const double* csrc, double* cdst, int ncopy, hipStream_t s);
 // w -= hscale * sum_i h[i] V_i; if norm2_out, *norm2_out = ||w_new||^2, after
 // which csrc[0..ncopy) (device, may hold norm2_out) is stored to the
-// host-mapped cdst.
+// host-mapped cdst and then 1.0 to cdst[ncopy] (the ready flag).
 void maxpy(long n, const double* V, long ldv, int nvec, const double* h, double hscale, double* w, double* part,
            double* norm2_out, hipStream_t s, const double* csrc = nullptr, double* cdst = nullptr, int ncopy = 0);
 // rows[0..cnt) of one level of a triangular solve with matrix A: x_i = (b_i - sum_{j!=i} a_ij x_j) / a_ii

@@ -369,8 +369,8 @@ __global__ __launch_bounds__(TPB) void k_maxpy_mdot(long n, const double* __rest
 
 // out[i] = sum over the nparts partials of vector i, in a fixed tree order.
 // With ncopy > 0 (a single workgroup), csrc[0..ncopy) -- which may include
-// out[0] -- is then also stored to cdst, a host-mapped buffer, and released to
-// the host.
+// out[0] -- is then also stored to cdst, a host-mapped buffer, released to the
+// host, and cdst[ncopy] = 1 is stored after it as the host's ready flag.
 __global__ __launch_bounds__(TPB) void k_reduce_parts(int nparts, const double* __restrict__ part,
                                                       double* __restrict__ out, const double* csrc,
                                                       double* __restrict__ cdst, int ncopy) {
@@ -391,6 +391,11 @@ __global__ __launch_bounds__(TPB) void k_reduce_parts(int nparts, const double* 
         __syncthreads();
         for (int q = threadIdx.x; q < ncopy; q += TPB) cdst[q] = csrc[q];
         __threadfence_system();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            *(volatile double*)(cdst + ncopy) = 1.0;
+            __threadfence_system();
+        }
     }
 }
 

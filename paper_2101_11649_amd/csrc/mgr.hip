@@ -8,6 +8,7 @@
 // Algorithm 1 from z = 0 without global relaxation; FGMRES uses it as a right
 // preconditioner (Sec. 4.1).  Every numeric step runs in the kernels of
 // k_setup.hip / k_apply.hip; this file only sequences launches and sizes.
+#include <atomic>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -717,14 +718,12 @@ struct Ctx {
     long kr_n = 0;
     DArr<double> V, Z, hbuf, part, yd;
     DArr<double> apply_tmp;
-    // pinned copies of the Arnoldi coefficients, one row of HROW per iteration,
-    // and the event that marks each copy
+    // pinned copies of the Arnoldi coefficients, one row of HROW per
+    // iteration, each ending in a ready flag that the kernel sets last
     static constexpr int HROW = 200;
     double* hpin = nullptr;
     double* hpin_dev = nullptr;  // the same rows as seen by kernels
-    std::vector<hipEvent_t> hev;
     ~Ctx() {
-        for (hipEvent_t e : hev) (void)hipEventDestroy(e);
         if (hpin) (void)hipHostFree(hpin);
     }
 };
@@ -1153,13 +1152,26 @@ static void ensure_krylov(Ctx& c) {
     MGR_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.hpin), sizeof(double) * Ctx::HROW * (m + 1),
                           hipHostMallocDefault));
     MGR_HIP(hipHostGetDevicePointer(reinterpret_cast<void**>(&c.hpin_dev), c.hpin, 0));
-    while ((int)c.hev.size() < m) {
-        hipEvent_t e;
-        MGR_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        c.hev.push_back(e);
-    }
     c.kr_m = m;
     c.kr_n = c.n;
+}
+
+// Wait until a kernel has set the host-mapped ready flag *f to 1 (and then
+// read what it stored before it).  The stream is polled now and then, so
+// that a flag that can no longer be set ends in an error, not a hang.
+static void wait_flag(const double* f, hipStream_t s) {
+    const volatile double* vf = f;
+    for (long spins = 1; *vf != 1.0; ++spins) {
+        if (spins % 4096 == 0) {
+            hipError_t e = hipStreamQuery(s);
+            if (e == hipSuccess) {
+                if (*vf == 1.0) break;
+                throw Error(MGR_ERR_HIP, "FGMRES: the stream finished without publishing the Arnoldi step");
+            }
+            if (e != hipErrorNotReady) MGR_HIP(e);
+        }
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
 }
 
 // Flexible GMRES(m) with right preconditioning (Saad 1993): x0 = 0, Givens
@@ -1279,8 +1291,8 @@ static int fgmres(Ctx& c, bool tr, const double* b, double* x, mgr_solve_info* i
         };
         // read step r's row: complete column r-1 (unless done already), keep column r pending
         auto process_row = [&](int r) {
-            MGR_HIP(hipEventSynchronize(c.hev[r]));
             const double* hh = c.hpin + (size_t)Ctx::HROW * r;
+            wait_flag(hh + NPUB, s);
             const double alpha = hh[HA];
             if (r == 0) g[0] = beta * alpha;
             else if (k == r - 1) complete(r - 1, hh, alpha);
@@ -1322,13 +1334,15 @@ static int fgmres(Ctx& c, bool tr, const double* b, double* x, mgr_solve_info* i
             double* uj = V + (long)j * n;
             double* zj = Z + (long)j * n;
             double* w = V + (long)(j + 1) * n;
+            // clear the row's ready flag (no kernel of this solve writes row j
+            // before the step queued below)
+            *(volatile double*)(c.hpin + (size_t)Ctx::HROW * j + NPUB) = 0.0;
             mgr_apply_top(c, uj, zj, tr);
             matvec(c, tr, zj, nullptr, w, 1.0, 0.0);
             arnoldi_dots(n, V, n, j + 1, w, c.part.p, hb, s);
             // the norm's reduction also stores the step's coefficients to its pinned row
             arnoldi_update(n, V, n, j + 1, hb, w, c.part.p, hb + HN, hb + HC, hb, c.hpin_dev + (size_t)Ctx::HROW * j,
                            NPUB, s);
-            MGR_HIP(hipEventRecord(c.hev[j], s));
             scale_by_norm(n, hb + HN, w, s);
             while (rows < j && !stop) process_row(rows++);
         }
