@@ -1170,7 +1170,7 @@ __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restri
                     int old = atomicCAS(&K[h], -1, j);
                     if (old == -1 || old == j) break;
                     h = (h + 1) & (CAP - 1);
-                    if (++probes == CAP) { atomicMax(flag, 1); h = -1; break; }
+                    if (++probes == CAP) { atomicMax(flag, FILL ? 1 : 2); h = -1; break; }
                 }
                 if (FILL && h >= 0) Vs[h] = Vs[h] + prod;
             }
@@ -2205,15 +2205,19 @@ static void spgemm_hash_launch(const DCsr& A, const DCsr& B, int cap, const int*
     MGR_LAUNCH_CHECK();
 }
 
-void spgemm_count(const DCsr& A, const DCsr& B, int max_row, int* cnt, int* flag, hipStream_t s) {
+void spgemm_count(const DCsr& A, const DCsr& B, int max_row, int* cnt, int* flag, hipStream_t s, bool loose) {
     // hashed rows when the right factor is too wide for the dense LDS row and
-    // every output row is bounded by A.max_row * B.max_row <= 256 distinct columns
-    if (!spgemm_dense_ok(A, B) && A.nr > 0 && B.max_row >= 0 && max_row >= 0 &&
-        (long)max_row * B.max_row <= 256) {
-        int cap = 32;
-        while (cap < max_row * B.max_row) cap <<= 1;
-        spgemm_hash_launch<false>(A, B, cap, nullptr, nullptr, nullptr, cnt, flag, s);
-        return;
+    // every output row is bounded by A.max_row * B.max_row <= 256 distinct
+    // columns; with `loose`, also up to a bound of SPGEMM_HASH_LOOSE with
+    // tables of 512 slots, a full table then setting *flag to 2
+    if (!spgemm_dense_ok(A, B) && A.nr > 0 && B.max_row >= 0 && max_row >= 0) {
+        const long bound = (long)max_row * B.max_row;
+        if (bound <= 256 || (loose && bound <= SPGEMM_HASH_LOOSE)) {
+            int cap = 32;
+            while (cap < bound && cap < 512) cap <<= 1;
+            spgemm_hash_launch<false>(A, B, cap, nullptr, nullptr, nullptr, cnt, flag, s);
+            return;
+        }
     }
     spgemm_launch<false>(A, B, max_row, nullptr, nullptr, nullptr, cnt, flag, s);
 }

@@ -50,8 +50,12 @@ void frelax_fill(int nb, const int* bstart, const DCsr& AFF, DCsr& M, int* flag,
 // count and set *flag (an int in device memory) to 1.
 // Right factors with at most SPGEMM_DENSE_COLS columns (and few enough rows x
 // columns) use a dense-row accumulator per output row instead of the merge.
+// With `loose`, products whose rows may exceed 256 columns (up to a bound of
+// SPGEMM_HASH_LOOSE) are counted in hash tables of 512 slots; a full table
+// sets *flag to 2, and the count must then be made again without `loose`.
 constexpr int SPGEMM_DENSE_COLS = 4096;
-void spgemm_count(const DCsr& A, const DCsr& B, int max_row, int* cnt, int* flag, hipStream_t s);
+constexpr long SPGEMM_HASH_LOOSE = 2048;
+void spgemm_count(const DCsr& A, const DCsr& B, int max_row, int* cnt, int* flag, hipStream_t s, bool loose = false);
 // C's row pointers and max_row come from the counts; a failure of the hashed
 // variant (a full table) sets *flag (an int in device memory).
 void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, int* flag, hipStream_t s);

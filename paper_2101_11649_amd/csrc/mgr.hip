@@ -124,13 +124,42 @@ static void spgemm_begin(Spgemm& j, const DCsr& A, const DCsr& B, DCsr& C, Slots
     j.C = &C;
     j.cnt.alloc((size_t)A.nr + 1, S.s);
     j.lr = S.take(1);
-    spgemm_count(A, B, A.max_row, j.cnt.p, reinterpret_cast<int*>(j.lr), S.s);
+    spgemm_count(A, B, A.max_row, j.cnt.p, reinterpret_cast<int*>(j.lr), S.s, true);
     j.pend = csr_begin(C, A.nr, B.nc, j.cnt.p, S);
 }
 
+// A row overflowed its hash table in the symbolic pass: count again with the
+// merging kernels and size C from a read of its own (not through the slots,
+// whose other pending values the caller has yet to use).
+static void spgemm_recount(Spgemm& j, hipStream_t s) {
+    DCsr& C = *j.C;
+    DArr<long long> t(3, s);
+    fill_ll(t.p, 0, 3, s);
+    spgemm_count(*j.A, *j.B, j.A->max_row, j.cnt.p, reinterpret_cast<int*>(t.p), s, false);
+    C = DCsr();
+    C.nr = j.A->nr;
+    C.nc = j.B->nc;
+    C.rp.alloc((size_t)C.nr + 1, s);
+    scan_async(j.cnt.p, C.rp.p, C.nr, t.p + 1, s);
+    long long h[3] = {0, 0, 0};
+    MGR_HIP(hipMemcpyAsync(h, t.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    MGR_HIP(hipStreamSynchronize(s));
+    if (h[0] != 0) throw Error(MGR_ERR_ARG, "internal: spgemm row longer than its recorded length");
+    if (h[1] > INT_MAX) throw Error(MGR_ERR_UNSUPPORTED, "operator exceeds the int32 index range");
+    C.nnz = (long)h[1];
+    C.max_row = (int)h[2];
+    C.ci.alloc((size_t)(C.nnz > 0 ? C.nnz : 1), s);
+    C.v.alloc((size_t)(C.nnz > 0 ? C.nnz : 1), s);
+}
+
 static void spgemm_finish(Spgemm& j, Slots& S) {
-    if (S.val(j.lr) != 0) throw Error(MGR_ERR_ARG, "internal: spgemm row longer than its recorded length");
-    csr_finish(j.pend, S);
+    const long long v = S.val(j.lr);
+    if (v == 2) {
+        spgemm_recount(j, S.s);
+    } else {
+        if (v != 0) throw Error(MGR_ERR_ARG, "internal: spgemm row longer than its recorded length");
+        csr_finish(j.pend, S);
+    }
     spgemm_fill(*j.A, *j.B, j.A->max_row, *j.C, S.flag(), S.s);
     j.cnt.reset();
 }
