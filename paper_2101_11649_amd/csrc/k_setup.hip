@@ -1669,6 +1669,9 @@ __global__ __launch_bounds__(TPB) void k_transpose_scatter_g(int nr, const int* 
 // multipliers of a row travel by shuffles inside its 16-lane group.
 __global__ __launch_bounds__(256) void k_dense_inverse_small(int n, const double* __restrict__ a,
                                                              double* __restrict__ inv, int* __restrict__ flag) {
+    // the inverse is compared with the oracle's to a tolerance, not bit for
+    // bit, so the update may use fused multiply-adds
+#pragma clang fp contract(fast)
     __shared__ double cand_v[4];
     __shared__ int cand_i[4];
     __shared__ double prow[128];
@@ -1712,13 +1715,16 @@ __global__ __launch_bounds__(256) void k_dense_inverse_small(int n, const double
             if ((t & (WAVE - 1)) == cl) { cand_v[w] = bv; cand_i[w] = bi; }
             __syncthreads();
             double pvv = cand_v[0];
-            int p = cand_i[0];
+            int pl = cand_i[0];
 #pragma unroll
             for (int q = 1; q < 4; ++q) {
                 const double ov = cand_v[q];
                 const int oi = cand_i[q];
-                if (ov > pvv || (ov == pvv && oi < p)) { pvv = ov; p = oi; }
+                if (ov > pvv || (ov == pvv && oi < pl)) { pvv = ov; pl = oi; }
             }
+            // every thread read the same candidates: the pivot row is uniform,
+            // which turns the row selections below into scalar branches
+            const int p = __builtin_amdgcn_readfirstlane(pl);
             if (!(pvv > 0.0) || !isfinite(pvv)) {
                 if (t == 0) set_flag(flag, 3);
                 return;
