@@ -1105,13 +1105,15 @@ __global__ __launch_bounds__(TPB) void k_add_g(int nr, const int* __restrict__ a
 // gathered and written in column order by rank.
 constexpr int log2_pow2(int v) { return v <= 1 ? 0 : 1 + log2_pow2(v / 2); }
 
-template <int G, int CAP, bool FILL>
+template <int G, int CAP, bool FILL, bool ADD>
 __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restrict__ arp,
                                                      const int* __restrict__ aci, const double* __restrict__ av,
                                                      const int* __restrict__ brp, const int* __restrict__ bci,
-                                                     const double* __restrict__ bv, const int* __restrict__ crp,
-                                                     int* __restrict__ cci, double* __restrict__ cv,
-                                                     int* __restrict__ cnt, int* __restrict__ flag) {
+                                                     const double* __restrict__ bv, const int* __restrict__ drp,
+                                                     const int* __restrict__ dci, const double* __restrict__ dv,
+                                                     const int* __restrict__ crp, int* __restrict__ cci,
+                                                     double* __restrict__ cv, int* __restrict__ cnt,
+                                                     int* __restrict__ flag) {
     constexpr int NG = TPB / G;
     constexpr int PER = CAP / G;
     __shared__ int keys[NG][CAP];
@@ -1174,6 +1176,24 @@ __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restri
                 }
                 if (FILL && h >= 0) Vs[h] = Vs[h] + prod;
             }
+        }
+    }
+    if (ADD && valid) {
+        // C = D + A B: the entries of D's row join the table after every
+        // product, so a shared entry is d + (its Gustavson sum), as in a
+        // separate sparse add of the finished product; a D-only entry is d
+        for (int q = drp[row] + g.gl; q < drp[row + 1]; q += G) {
+            const int j = dci[q];
+            int h = (int)(((unsigned)j * 2654435761u) >> (32 - log2_pow2(CAP)));
+            int probes = 0;
+            int old;
+            for (;;) {
+                old = atomicCAS(&K[h], -1, j);
+                if (old == -1 || old == j) break;
+                h = (h + 1) & (CAP - 1);
+                if (++probes == CAP) { atomicMax(flag, FILL ? 1 : 2); h = -1; break; }
+            }
+            if (FILL && h >= 0) Vs[h] = (old == -1) ? dv[q] : dv[q] + Vs[h];
         }
     }
     if (!FILL) {
@@ -2187,10 +2207,14 @@ static bool spgemm_dense_ok(const DCsr& A, const DCsr& B) {
     return B.nc <= SPGEMM_DENSE && A.nr <= SPGEMM_DENSE_ROWS && (long)A.nr * B.nc <= SPGEMM_DENSE_WORK;
 }
 
-// Hashed rows with tables of cap slots (cap >= 32, a power of two <= 512).
-template <bool FILL>
-static void spgemm_hash_launch(const DCsr& A, const DCsr& B, int cap, const int* crp, int* cci, double* cv,
-                               int* cnt, int* flag, hipStream_t s) {
+// Hashed rows with tables of cap slots (cap >= 32, a power of two <= 512);
+// with D, C = D + A B.
+template <bool FILL, bool ADD>
+static void spgemm_hash_launch(const DCsr& A, const DCsr& B, const DCsr* D, int cap, const int* crp, int* cci,
+                               double* cv, int* cnt, int* flag, hipStream_t s) {
+    const int* drp = ADD ? D->rp.p : nullptr;
+    const int* dci = ADD ? D->ci.p : nullptr;
+    const double* dvv = ADD ? D->v.p : nullptr;
     int gb = 4;
     while (gb < B.max_row && gb < 32) gb <<= 1;
     int gl = (int)((long)cap * 12 * TPB / 65536);   // LDS: TPB / G tables of cap slots
@@ -2198,8 +2222,9 @@ static void spgemm_hash_launch(const DCsr& A, const DCsr& B, int cap, const int*
     while (G < gl) G <<= 1;
     if (G > 32) G = 32;
 #define MGR_HASH(GG, CC)                                                                                          \
-    k_spgemm_hash<GG, CC, FILL><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p,  \
-                                                                  B.v.p, crp, cci, cv, cnt, flag)
+    k_spgemm_hash<GG, CC, FILL, ADD><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p,     \
+                                                                       B.ci.p, B.v.p, drp, dci, dvv, crp, cci, cv, \
+                                                                       cnt, flag)
     switch (cap) {
         case 32: if (G <= 4) MGR_HASH(4, 32); else if (G == 8) MGR_HASH(8, 32); else if (G == 16) MGR_HASH(16, 32); else MGR_HASH(32, 32); break;
         case 64: if (G <= 4) MGR_HASH(4, 64); else if (G == 8) MGR_HASH(8, 64); else if (G == 16) MGR_HASH(16, 64); else MGR_HASH(32, 64); break;
@@ -2221,7 +2246,7 @@ void spgemm_count(const DCsr& A, const DCsr& B, int max_row, int* cnt, int* flag
         if (bound <= 256 || (loose && bound <= SPGEMM_HASH_LOOSE)) {
             int cap = 32;
             while (cap < bound && cap < 512) cap <<= 1;
-            spgemm_hash_launch<false>(A, B, cap, nullptr, nullptr, nullptr, cnt, flag, s);
+            spgemm_hash_launch<false, false>(A, B, nullptr, cap, nullptr, nullptr, nullptr, cnt, flag, s);
             return;
         }
     }
@@ -2234,10 +2259,31 @@ void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, int* flag, 
     if (!spgemm_dense_ok(A, B) && A.nr > 0 && C.max_row >= 0 && C.max_row <= 256 && B.max_row >= 0) {
         int cap = 32;
         while (cap < 2 * C.max_row) cap <<= 1;
-        spgemm_hash_launch<true>(A, B, cap, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s);
+        spgemm_hash_launch<true, false>(A, B, nullptr, cap, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s);
         return;
     }
     spgemm_launch<true>(A, B, max_row, C.rp.p, C.ci.p, C.v.p, nullptr, nullptr, s);
+}
+
+bool spgemm_add_fusable(const DCsr& A, const DCsr& B, const DCsr& D) {
+    return D.nr == A.nr && D.nc == B.nc && A.max_row >= 0 && B.max_row >= 0 && D.max_row >= 0 &&
+           (long)A.max_row * B.max_row + D.max_row <= 256;
+}
+
+void spgemm_add_count(const DCsr& A, const DCsr& B, const DCsr& D, int* cnt, int* flag, hipStream_t s) {
+    if (!spgemm_add_fusable(A, B, D)) throw Error(-1, "spgemm_add: rows may exceed 256 entries");
+    if (A.nr <= 0) return;
+    const long bound = (long)A.max_row * B.max_row + D.max_row;
+    int cap = 32;
+    while (cap < bound) cap <<= 1;
+    spgemm_hash_launch<false, true>(A, B, &D, cap, nullptr, nullptr, nullptr, cnt, flag, s);
+}
+
+void spgemm_add_fill(const DCsr& A, const DCsr& B, const DCsr& D, DCsr& C, int* flag, hipStream_t s) {
+    if (A.nr <= 0) return;
+    int cap = 32;
+    while (cap < 2 * C.max_row) cap <<= 1;
+    spgemm_hash_launch<true, true>(A, B, &D, cap, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s);
 }
 
 static int add_group(const DCsr& A, const DCsr& B) {

@@ -110,6 +110,7 @@ static DCsr csr_from_counts(int nr, int nc, const int* counts, Slots& S, const c
 struct Spgemm {
     const DCsr* A = nullptr;
     const DCsr* B = nullptr;
+    const DCsr* D = nullptr;  // C = D + A B when set
     DCsr* C = nullptr;
     DArr<int> cnt;
     long long* lr = nullptr;
@@ -152,15 +153,29 @@ static void spgemm_recount(Spgemm& j, hipStream_t s) {
     C.v.alloc((size_t)(C.nnz > 0 ? C.nnz : 1), s);
 }
 
+// C = D + A B in one hashed product (requires spgemm_add_fusable(A, B, D)).
+static void spgemm_add_begin(Spgemm& j, const DCsr& A, const DCsr& B, const DCsr& D, DCsr& C, Slots& S) {
+    if (A.nc != B.nr) throw Error(MGR_ERR_ARG, "spgemm: inner dimensions differ");
+    j.A = &A;
+    j.B = &B;
+    j.D = &D;
+    j.C = &C;
+    j.cnt.alloc((size_t)A.nr + 1, S.s);
+    j.lr = S.take(1);
+    spgemm_add_count(A, B, D, j.cnt.p, reinterpret_cast<int*>(j.lr), S.s);
+    j.pend = csr_begin(C, A.nr, B.nc, j.cnt.p, S);
+}
+
 static void spgemm_finish(Spgemm& j, Slots& S) {
     const long long v = S.val(j.lr);
-    if (v == 2) {
+    if (v == 2 && !j.D) {
         spgemm_recount(j, S.s);
     } else {
         if (v != 0) throw Error(MGR_ERR_ARG, "internal: spgemm row longer than its recorded length");
         csr_finish(j.pend, S);
     }
-    spgemm_fill(*j.A, *j.B, j.A->max_row, *j.C, S.flag(), S.s);
+    if (j.D) spgemm_add_fill(*j.A, *j.B, *j.D, *j.C, S.flag(), S.s);
+    else spgemm_fill(*j.A, *j.B, j.A->max_row, *j.C, S.flag(), S.s);
     j.cnt.reset();
 }
 
@@ -863,9 +878,12 @@ static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr& A, const int* field
         l.RF = csr_copy(l.W, s);
         negate(l.RF.v.p, l.RF.nnz, s);
     }
-    DCsr T1;
+    // A_c = A_CC + A_CF P_F, as one hashed product when its rows are short
+    const bool fuse_add = spgemm_add_fusable(l.ACF, l.PF, l.ACC);
+    DCsr T1, Ac;
     Spgemm j1;
-    spgemm_begin(j1, l.ACF, l.PF, T1, S);
+    if (fuse_add) spgemm_add_begin(j1, l.ACF, l.PF, l.ACC, Ac, S);
+    else spgemm_begin(j1, l.ACF, l.PF, T1, S);
     // fused one-sweep apply: r_c = [-omega A_CF M | I] v ; z = [P_F | omega M] [e_c ; v]
     l.fused = fused_ok(o);
     DArr<int> lenR, lenP;
@@ -886,8 +904,10 @@ static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr& A, const int* field
         rj_fill(l.nC, l.W, -o.omega, l.fmap.p, l.cmap.p, l.RJ, s);
         pj_fill(n, l.nC, l.isF.p, l.lmap.p, l.PF, 1.0, l.M, o.omega, l.fmap.p, l.PJ, s);
     }
-    DCsr Ac = csr_add(l.ACC, T1, S);
-    T1 = DCsr();
+    if (!fuse_add) {
+        Ac = csr_add(l.ACC, T1, S);
+        T1 = DCsr();
+    }
     if (o.restrict_type == MGR_RESTRICT_JACOBI) {
         DCsr T2 = spgemm(l.RF, l.AFC, S);
         DCsr S2 = csr_add(Ac, T2, S);
