@@ -108,10 +108,6 @@ int krylov_parts(long n);
 // out[i] = <V_i, w> for i < nvec (V column-major with leading dimension ldv);
 // part needs nvec * KRYLOV_PARTS doubles.
 void mdot(long n, const double* V, long ldv, int nvec, const double* w, double* part, double* out, hipStream_t s);
-// w -= sum_i h[i] V_i, then out[i] = <V_i, w_new>, in one pass over V; only for
-// nvec <= 16 (returns false otherwise, and does nothing).
-bool maxpy_mdot(long n, const double* V, long ldv, int nvec, const double* h, double* w, double* part,
-                double* out, hipStream_t s);
 // Arnoldi step with delayed reorthogonalisation (two passes over the basis).
 // arnoldi_dots: out[0..nvec) = V_i . V_{nvec-1}, out[nvec..2 nvec) = V_i . w
 // (part needs 2 nvec KRYLOV_PARTS doubles).  arnoldi_update: from those dots,
@@ -124,11 +120,9 @@ void arnoldi_dots(long n, const double* V, long ldv, int nvec, const double* w, 
                   hipStream_t s);
 void arnoldi_update(long n, double* V, long ldv, int nvec, const double* sh, double* w, double* part,
                     double* norm2_out, double* coef, const double* csrc, double* cdst, int ncopy, hipStream_t s);
-// w -= hscale * sum_i h[i] V_i; if norm2_out, *norm2_out = ||w_new||^2, after
-// which csrc[0..ncopy) (device, may hold norm2_out) is stored to the
-// host-mapped cdst and then 1.0 to cdst[ncopy] (the ready flag).
+// w -= hscale * sum_i h[i] V_i; if norm2_out, *norm2_out = ||w_new||^2.
 void maxpy(long n, const double* V, long ldv, int nvec, const double* h, double hscale, double* w, double* part,
-           double* norm2_out, hipStream_t s, const double* csrc = nullptr, double* cdst = nullptr, int ncopy = 0);
+           double* norm2_out, hipStream_t s);
 // rows[0..cnt) of one level of a triangular solve with matrix A: x_i = (b_i - sum_{j!=i} a_ij x_j) / a_ii
 // (unit: diagonal 1 and not stored).  b may alias x.
 template <typename T>

@@ -334,39 +334,6 @@ __global__ __launch_bounds__(TPB) void k_mdot(long n, const double* __restrict__
     block_sums<NB>(acc, min(NB, nvec - i0), part + (long)i0 * gridDim.x + blockIdx.x, gridDim.x);
 }
 
-// First Gram-Schmidt correction fused with the products of the second pass
-// (nvec <= NV <= 16, where the row of V stays in registers): w -= sum_i h[i] V_i,
-// then part[i * gridDim.x + block] = partial of <V_i, w_new>.  The per-row sum
-// and the per-thread accumulations run in the same order as the separate
-// maxpy and mdot kernels.
-template <int NV>
-__global__ __launch_bounds__(TPB) void k_maxpy_mdot(long n, const double* __restrict__ V, long ldv, int nvec,
-                                                    const double* __restrict__ h, double* __restrict__ w,
-                                                    double* __restrict__ part) {
-    __shared__ double hs[NV];
-    if ((int)threadIdx.x < nvec) hs[threadIdx.x] = h[threadIdx.x];
-    __syncthreads();
-    double acc[NV];
-#pragma unroll
-    for (int t = 0; t < NV; ++t) acc[t] = 0.0;
-    long stride = (long)gridDim.x * TPB;
-    for (long r = (long)blockIdx.x * TPB + threadIdx.x; r < n; r += stride) {
-        double vv[NV];
-        double sum = 0.0;
-#pragma unroll
-        for (int t = 0; t < NV; ++t) {
-            vv[t] = (t < nvec) ? V[(long)t * ldv + r] : 0.0;
-            if (t < nvec) sum += hs[t] * vv[t];
-        }
-        double wn = w[r] - sum;
-        w[r] = wn;
-#pragma unroll
-        for (int t = 0; t < NV; ++t)
-            if (t < nvec) acc[t] += vv[t] * wn;
-    }
-    block_sums<NV>(acc, nvec, part + blockIdx.x, gridDim.x);
-}
-
 // out[i] = sum over the nparts partials of vector i, in a fixed tree order.
 // With ncopy > 0 (a single workgroup), csrc[0..ncopy) -- which may include
 // out[0] -- is then also stored to cdst, a host-mapped buffer, released to the
@@ -721,25 +688,13 @@ void mdot(long n, const double* V, long ldv, int nvec, const double* w, double* 
     MGR_LAUNCH_CHECK();
 }
 
-bool maxpy_mdot(long n, const double* V, long ldv, int nvec, const double* h, double* w, double* part,
-                double* out, hipStream_t s) {
-    if (nvec <= 0 || nvec > 16) return false;
-    int np = krylov_parts(n);
-    if (nvec <= 8) k_maxpy_mdot<8><<<np, TPB, 0, s>>>(n, V, ldv, nvec, h, w, part);
-    else k_maxpy_mdot<16><<<np, TPB, 0, s>>>(n, V, ldv, nvec, h, w, part);
-    k_reduce_parts<<<nvec, TPB, 0, s>>>(np, part, out, nullptr, nullptr, 0);
-    MGR_LAUNCH_CHECK();
-    return true;
-}
-
 void maxpy(long n, const double* V, long ldv, int nvec, const double* h, double hscale, double* w, double* part,
-           double* norm2_out, hipStream_t s, const double* csrc, double* cdst, int ncopy) {
+           double* norm2_out, hipStream_t s) {
     if (nvec > 64) throw Error(-1, "maxpy: at most 64 vectors");
-    if (ncopy > 0 && !norm2_out) throw Error(-1, "maxpy: a host copy needs the norm reduction");
     int np = krylov_parts(n);
     if (nvec <= 0 && !norm2_out) return;
     k_maxpy<<<np, TPB, 0, s>>>(n, V, ldv, nvec, h, hscale, w, norm2_out ? part : nullptr);
-    if (norm2_out) k_reduce_parts<<<1, TPB, 0, s>>>(np, part, norm2_out, csrc, cdst, ncopy);
+    if (norm2_out) k_reduce_parts<<<1, TPB, 0, s>>>(np, part, norm2_out, nullptr, nullptr, 0);
     MGR_LAUNCH_CHECK();
 }
 
