@@ -1368,11 +1368,14 @@ __global__ __launch_bounds__(TPB) void k_bsr_fill_g(int b, int nbr, const int* _
     }
 }
 
+// Strength of connection per entry, the number of strong entries of each row
+// (scnt) and, by atomic increments, the number of rows that strongly depend
+// on each column (lam, which must start at zero).
 template <int G>
 __global__ __launch_bounds__(TPB) void k_strength_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                     const double* __restrict__ v, double theta,
                                                     const int* __restrict__ label, unsigned char* __restrict__ strong,
-                                                    int* __restrict__ scnt) {
+                                                    int* __restrict__ scnt, int* __restrict__ lam) {
     Grp<G> g;
     int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
     bool valid = i < n;
@@ -1401,20 +1404,11 @@ __global__ __launch_bounds__(TPB) void k_strength_g(int n, const int* __restrict
             if (have && mx > 0.0 && j != i && !(label && label[j] != li) && -v[p] >= thr) sflag = 1;
             strong[p] = sflag;
             c += sflag;
+            if (sflag) atomicAdd(&lam[j], 1);
         }
     }
     c = g.sum(c);
     if (valid && g.gl == 0) scnt[i] = c;
-}
-
-template <int G>
-__global__ __launch_bounds__(TPB) void k_lambda_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                  const unsigned char* __restrict__ strong, int* __restrict__ lam) {
-    Grp<G> g;
-    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
-    if (i >= n) return;
-    for (int p = rp[i] + g.gl; p < rp[i + 1]; p += G)
-        if (strong[p]) atomicAdd(&lam[ci[p]], 1);
 }
 
 template <int G>
@@ -2329,18 +2323,12 @@ void transpose_fill(const DCsr& A, DCsr& T, int* cnt, hipStream_t s) {
     MGR_LAUNCH_CHECK();
 }
 
-void amg_strength(const DCsr& A, double theta, const int* label, unsigned char* strong, int* scnt, hipStream_t s) {
+void amg_strength(const DCsr& A, double theta, const int* label, unsigned char* strong, int* scnt, int* lam,
+                  hipStream_t s) {
     if (A.nr <= 0) return;
     int G = group_for(A.max_row);
     MGR_DISPATCH_G4(G, (k_strength_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, theta, label,
-                                                                              strong, scnt)));
-    MGR_LAUNCH_CHECK();
-}
-
-void amg_lambda(const DCsr& A, const unsigned char* strong, int* lam, hipStream_t s) {
-    if (A.nr <= 0) return;
-    int G = group_for(A.max_row);
-    MGR_DISPATCH_G4(G, (k_lambda_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, strong, lam)));
+                                                                              strong, scnt, lam)));
     MGR_LAUNCH_CHECK();
 }
 

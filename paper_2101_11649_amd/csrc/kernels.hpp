@@ -74,9 +74,10 @@ void transpose_count(const DCsr& A, int* cnt, hipStream_t s);
 void transpose_fill(const DCsr& A, DCsr& T, int* cnt, hipStream_t s);
 
 // AMG setup
-// strength flags per entry and the number of strong entries per row (scnt)
-void amg_strength(const DCsr& A, double theta, const int* label, unsigned char* strong, int* scnt, hipStream_t s);
-void amg_lambda(const DCsr& A, const unsigned char* strong, int* lam, hipStream_t s);
+// strength flags per entry, the number of strong entries per row (scnt) and
+// per column (lam, incremented: it must start at zero)
+void amg_strength(const DCsr& A, double theta, const int* label, unsigned char* strong, int* scnt, int* lam,
+                  hipStream_t s);
 void strength_compact_fill(const DCsr& A, const unsigned char* strong, const int* srp, int* sci, hipStream_t s);
 void pattern_transpose_fill(int nr, const int* rp, const int* ci, const int* trp, int* cursor, int* tci,
                             hipStream_t s);

@@ -334,10 +334,9 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
         size_t nz = (size_t)(A.nnz > 0 ? A.nnz : 1);
         DArr<unsigned char> strong(nz, s);
         DArr<int> scnt((size_t)n + 1, s), srp((size_t)n + 1, s), trp((size_t)n + 1, s), cursor((size_t)n + 1, s);
-        amg_strength(A, o.theta, L.label.p, strong.p, scnt.p, s);
         DArr<int> lam((size_t)n + 1, s);
         fill_int(lam.p, 0, n + 1, s);
-        amg_lambda(A, strong.p, lam.p, s);
+        amg_strength(A, o.theta, L.label.p, strong.p, scnt.p, lam.p, s);
         // strength graph S (row i lists S_i) and its transpose; both fit in nnz(A)
         DArr<int> sci(nz, s), tci(nz, s);
         scan_exclusive_async(scnt.p, srp.p, n, s);
