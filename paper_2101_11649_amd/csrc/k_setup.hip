@@ -1370,25 +1370,38 @@ __global__ __launch_bounds__(TPB) void k_bsr_fill_g(int b, int nbr, const int* _
 
 // Strength of connection per entry, the number of strong entries of each row
 // (scnt) and, by atomic increments, the number of rows that strongly depend
-// on each column (lam, which must start at zero).
+// on each column (lam, which must start at zero); with dinv, also the L1
+// Jacobi diagonal 1 / (a_ii + sum_{j != i} |a_ij|) as l1_dinv forms it.
 template <int G>
 __global__ __launch_bounds__(TPB) void k_strength_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                     const double* __restrict__ v, double theta,
                                                     const int* __restrict__ label, unsigned char* __restrict__ strong,
-                                                    int* __restrict__ scnt, int* __restrict__ lam) {
+                                                    int* __restrict__ scnt, int* __restrict__ lam,
+                                                    double* __restrict__ dinv, int* __restrict__ flag) {
     Grp<G> g;
     int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
     bool valid = i < n;
     int li = (valid && label) ? label[i] : 0;
-    double mx = 0.0;
+    double mx = 0.0, sabs = 0.0, aii = 0.0;
     int have = 0;
     if (valid)
         for (int p = rp[i] + g.gl; p < rp[i + 1]; p += G) {
             int j = ci[p];
+            if (j == i) aii = v[p];
+            else sabs += fabs(v[p]);
             if (j == i || (label && label[j] != li)) continue;
             double t = -v[p];
             if (!have || t > mx) { mx = t; have = 1; }
         }
+    if (dinv) {
+        sabs = g.sumd(sabs);
+        aii = g.sumd(aii);
+        if (valid && g.gl == 0) {
+            double d = aii + sabs;
+            if (!(d > 0.0)) { set_flag(flag, 6); d = 1.0; }
+            dinv[i] = 1.0 / d;
+        }
+    }
     for (int off = G / 2; off > 0; off >>= 1) {
         double om = __shfl_xor(mx, off, WAVE);
         int oh = __shfl_xor(have, off, WAVE);
@@ -2324,11 +2337,11 @@ void transpose_fill(const DCsr& A, DCsr& T, int* cnt, hipStream_t s) {
 }
 
 void amg_strength(const DCsr& A, double theta, const int* label, unsigned char* strong, int* scnt, int* lam,
-                  hipStream_t s) {
+                  double* dinv, int* flag, hipStream_t s) {
     if (A.nr <= 0) return;
     int G = group_for(A.max_row);
     MGR_DISPATCH_G4(G, (k_strength_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, theta, label,
-                                                                              strong, scnt, lam)));
+                                                                              strong, scnt, lam, dinv, flag)));
     MGR_LAUNCH_CHECK();
 }
 

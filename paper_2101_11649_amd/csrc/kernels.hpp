@@ -75,9 +75,11 @@ void transpose_fill(const DCsr& A, DCsr& T, int* cnt, hipStream_t s);
 
 // AMG setup
 // strength flags per entry, the number of strong entries per row (scnt) and
-// per column (lam, incremented: it must start at zero)
+// per column (lam, incremented: it must start at zero); with dinv, also the
+// L1 Jacobi diagonal exactly as l1_dinv forms it (*flag set where it is not
+// positive)
 void amg_strength(const DCsr& A, double theta, const int* label, unsigned char* strong, int* scnt, int* lam,
-                  hipStream_t s);
+                  double* dinv, int* flag, hipStream_t s);
 void strength_compact_fill(const DCsr& A, const unsigned char* strong, const int* srp, int* sci, hipStream_t s);
 void pattern_transpose_fill(int nr, const int* rp, const int* ci, const int* trp, int* cursor, int* tci,
                             hipStream_t s);

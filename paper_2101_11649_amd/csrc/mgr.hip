@@ -336,7 +336,8 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
         DArr<int> scnt((size_t)n + 1, s), srp((size_t)n + 1, s), trp((size_t)n + 1, s), cursor((size_t)n + 1, s);
         DArr<int> lam((size_t)n + 1, s);
         fill_int(lam.p, 0, n + 1, s);
-        amg_strength(A, o.theta, L.label.p, strong.p, scnt.p, lam.p, s);
+        L.dinv.alloc((size_t)n, s);
+        amg_strength(A, o.theta, L.label.p, strong.p, scnt.p, lam.p, L.dinv.p, S.flag(), s);
         // strength graph S (row i lists S_i) and its transpose; both fit in nnz(A)
         DArr<int> sci(nz, s), tci(nz, s);
         scan_exclusive_async(scnt.p, srp.p, n, s);
@@ -394,8 +395,6 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
         // small V(1,1) levels are applied in composed form (two SpMVs instead of four)
         L.composed = H.nu_pre == 1 && H.nu_post == 1 && A.nnz <= AMG_COMPOSE_NNZ && n <= SPGEMM_DENSE_COLS;
         if (L.composed) spgemm_begin(j3, R, A, L.RA, S);
-        L.dinv.alloc((size_t)n, s);
-        l1_dinv(A, L.dinv.p, S.flag(), s);
         S.sync("AMG Galerkin product");
         spgemm_finish(j2, S);
         if (L.composed) {
