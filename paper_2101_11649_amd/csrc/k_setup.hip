@@ -174,6 +174,11 @@ __global__ void k_fill_ll(long long* p, long long v, int n) {
 }
 
 // ------------------------------------------------------------------ misc
+__global__ void k_fill_u8(unsigned char* p, unsigned char v, long n) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 __global__ void k_fill_int(int* p, int v, long n) {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -671,18 +676,6 @@ __global__ void k_transpose_count(long nnz, const int* __restrict__ ci, int* __r
     if (p < nnz) atomicAdd(&cnt[ci[p]], 1);
 }
 
-__global__ void k_transpose_scatter(int nr, const int* __restrict__ rp, const int* __restrict__ ci,
-                                    const double* __restrict__ v, int* __restrict__ cursor, int* __restrict__ tci,
-                                    double* __restrict__ tv) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nr) return;
-    for (int p = rp[i]; p < rp[i + 1]; ++p) {
-        int q = atomicAdd(&cursor[ci[p]], 1);
-        tci[q] = i;
-        if (tv) tv[q] = v[p];
-    }
-}
-
 // Row i of the transpose, scattered in arbitrary order into tci / tv, is
 // written to ci / v in ascending column order: one wavefront per row, the
 // position of each entry is the number of smaller keys in the row (keys of a
@@ -966,53 +959,57 @@ __device__ inline int wave_max_int(int v) {
 constexpr int PMIS_GROUP_MIN = 12;
 constexpr int PMIS_GROUP_MAX_N = 65536;
 
-// PMIS round, G lanes per point.  Selection: an undecided point becomes C
-// when its (w, index) beats every undecided neighbour in S_i and S^T_i, judged
-// on the state at the start of the round.
+// PMIS round, G lanes per point, without the transpose of S.  Selection: an
+// undecided point j is beaten when an undecided point of S_j or of S^T_j (a
+// point i with j in S_i) has the larger (w, index), judged on the state cf at
+// the start of the round.  Each undecided point walks its own row S_j once:
+// a neighbour that beats it marks j (pull), a neighbour it beats is marked
+// (push: j is in that neighbour's S^T row).  The marks are plain stores of 1.
 template <int G>
 __global__ __launch_bounds__(TPB) void k_pmis_select_g(int n, const int* __restrict__ srp, const int* __restrict__ sci,
-                                                       const int* __restrict__ trp, const int* __restrict__ tci,
                                                        const double* __restrict__ w, const int* __restrict__ cf,
-                                                       unsigned char* __restrict__ newc) {
+                                                       unsigned char* __restrict__ beaten) {
     Grp<G> g;
-    const int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
-    const bool valid = i < n;
-    const bool cand = valid && cf[i] == 0;
-    bool beaten = false;
-    if (cand) {
+    const int j = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    if (j >= n || cf[j] != 0) return;
+    const double wj = w[j];
+    bool lost = false;
+    for (int q = srp[j] + g.gl; q < srp[j + 1]; q += G) {
+        const int i = sci[q];
+        if (cf[i] != 0) continue;
         const double wi = w[i];
-        for (int q = srp[i] + g.gl; q < srp[i + 1] && !beaten; q += G) {
-            const int j = sci[q];
-            if (cf[j] == 0 && (w[j] > wi || (w[j] == wi && j > i))) beaten = true;
-        }
-        for (int q = trp[i] + g.gl; q < trp[i + 1] && !beaten; q += G) {
-            const int j = tci[q];
-            if (cf[j] == 0 && (w[j] > wi || (w[j] == wi && j > i))) beaten = true;
-        }
+        if (wi > wj || (wi == wj && i > j)) lost = true;
+        else beaten[i] = 1;
     }
-    beaten = g.bits(beaten) != 0;
-    if (valid && g.gl == 0) newc[i] = (cand && !beaten) ? 1 : 0;
+    if (lost) beaten[j] = 1;
 }
 
-// Update: new C-points are set; an undecided point that strongly depends on a
-// new C-point becomes F.  Counts what is still undecided (one atomic per wave).
+// Update: undecided points that were not beaten become C; an undecided point
+// that strongly depends on a new C-point becomes F.  Reads the round's state
+// (cf, beaten), writes the next one (cf_next, and beaten_next cleared), and
+// counts what is still undecided (one atomic per wave).
 template <int G>
 __global__ __launch_bounds__(TPB) void k_pmis_update_g(int n, const int* __restrict__ srp, const int* __restrict__ sci,
-                                                       const unsigned char* __restrict__ newc, int* __restrict__ cf,
+                                                       const int* __restrict__ cf,
+                                                       const unsigned char* __restrict__ beaten,
+                                                       int* __restrict__ cf_next, unsigned char* __restrict__ beaten_next,
                                                        int* __restrict__ undecided) {
     Grp<G> g;
     const int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
     const bool valid = i < n;
-    const bool isnew = valid && newc[i];
-    const bool und = valid && !isnew && cf[i] == 0;
+    const int ci_ = valid ? cf[i] : 1;
+    const bool isnew = valid && ci_ == 0 && !beaten[i];
+    const bool und = valid && ci_ == 0 && !isnew;
     bool hit = false;
     if (und)
-        for (int q = srp[i] + g.gl; q < srp[i + 1] && !hit; q += G)
-            if (newc[sci[q]]) hit = true;
+        for (int q = srp[i] + g.gl; q < srp[i + 1] && !hit; q += G) {
+            const int j = sci[q];
+            if (cf[j] == 0 && !beaten[j]) hit = true;
+        }
     hit = g.bits(hit) != 0;
     if (valid && g.gl == 0) {
-        if (isnew) cf[i] = 1;
-        else if (und && hit) cf[i] = -1;
+        cf_next[i] = isnew ? 1 : (und ? (hit ? -1 : 0) : ci_);
+        beaten_next[i] = 0;
     }
     const unsigned long long left = __ballot(valid && g.gl == 0 && und && !hit);
     if (undecided && g.lane == 0 && left) atomicAdd(undecided, (int)__popcll(left));
@@ -2047,6 +2044,12 @@ int read_int(const int* dptr, hipStream_t s) {
 }
 
 
+void fill_bytes(unsigned char* p, unsigned char v, long n, hipStream_t s) {
+    if (n <= 0) return;
+    k_fill_u8<<<nblk(n), TPB, 0, s>>>(p, v, n);
+    MGR_LAUNCH_CHECK();
+}
+
 void fill_int(int* p, int v, long n, hipStream_t s) {
     if (n <= 0) return;
     k_fill_int<<<nblk(n), TPB, 0, s>>>(p, v, n);
@@ -2353,13 +2356,6 @@ void strength_compact_fill(const DCsr& A, const unsigned char* strong, const int
     MGR_LAUNCH_CHECK();
 }
 
-void pattern_transpose_fill(int nr, const int* rp, const int* ci, const int* trp, int* cursor, int* tci,
-                            hipStream_t s) {
-    (void)trp;
-    if (nr <= 0) return;
-    k_transpose_scatter<<<nblk(nr), TPB, 0, s>>>(nr, rp, ci, nullptr, cursor, tci, nullptr);
-    MGR_LAUNCH_CHECK();
-}
 
 void pmis_init(int n, const int* lam, uint64_t seed, int level, double* w, int* cf, hipStream_t s) {
     if (n <= 0) return;
@@ -2367,26 +2363,27 @@ void pmis_init(int n, const int* lam, uint64_t seed, int level, double* w, int* 
     MGR_LAUNCH_CHECK();
 }
 
-void pmis_select(int n, const int* srp, const int* sci, const int* trp, const int* tci, const double* w,
-                 const int* cf, unsigned char* newc, int avg_row, hipStream_t s) {
+void pmis_select(int n, const int* srp, const int* sci, const double* w, const int* cf, unsigned char* beaten,
+                 int avg_row, hipStream_t s) {
     if (n <= 0) return;
     if (avg_row <= PMIS_GROUP_MIN || n > PMIS_GROUP_MAX_N) {
-        k_pmis_select_g<1><<<grid_for(n, 1), TPB, 0, s>>>(n, srp, sci, trp, tci, w, cf, newc);
+        k_pmis_select_g<1><<<grid_for(n, 1), TPB, 0, s>>>(n, srp, sci, w, cf, beaten);
     } else {
         int G = group_for(avg_row);
-        MGR_DISPATCH_G4(G, (k_pmis_select_g<GG><<<grid_for(n, GG), TPB, 0, s>>>(n, srp, sci, trp, tci, w, cf, newc)));
+        MGR_DISPATCH_G4(G, (k_pmis_select_g<GG><<<grid_for(n, GG), TPB, 0, s>>>(n, srp, sci, w, cf, beaten)));
     }
     MGR_LAUNCH_CHECK();
 }
 
-void pmis_update(int n, const int* srp, const int* sci, const unsigned char* newc, int* cf, int* undecided,
-                 int avg_row, hipStream_t s) {
+void pmis_update(int n, const int* srp, const int* sci, const int* cf, const unsigned char* beaten, int* cf_next,
+                 unsigned char* beaten_next, int* undecided, int avg_row, hipStream_t s) {
     if (n <= 0) return;
     if (avg_row <= PMIS_GROUP_MIN || n > PMIS_GROUP_MAX_N) {
-        k_pmis_update_g<1><<<grid_for(n, 1), TPB, 0, s>>>(n, srp, sci, newc, cf, undecided);
+        k_pmis_update_g<1><<<grid_for(n, 1), TPB, 0, s>>>(n, srp, sci, cf, beaten, cf_next, beaten_next, undecided);
     } else {
         int G = group_for(avg_row);
-        MGR_DISPATCH_G4(G, (k_pmis_update_g<GG><<<grid_for(n, GG), TPB, 0, s>>>(n, srp, sci, newc, cf, undecided)));
+        MGR_DISPATCH_G4(G, (k_pmis_update_g<GG><<<grid_for(n, GG), TPB, 0, s>>>(n, srp, sci, cf, beaten, cf_next,
+                                                                                 beaten_next, undecided)));
     }
     MGR_LAUNCH_CHECK();
 }

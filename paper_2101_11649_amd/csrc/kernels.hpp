@@ -81,14 +81,14 @@ void transpose_fill(const DCsr& A, DCsr& T, int* cnt, hipStream_t s);
 void amg_strength(const DCsr& A, double theta, const int* label, unsigned char* strong, int* scnt, int* lam,
                   double* dinv, int* flag, hipStream_t s);
 void strength_compact_fill(const DCsr& A, const unsigned char* strong, const int* srp, int* sci, hipStream_t s);
-void pattern_transpose_fill(int nr, const int* rp, const int* ci, const int* trp, int* cursor, int* tci,
-                            hipStream_t s);
 void pmis_init(int n, const int* lam, uint64_t seed, int level, double* w, int* cf, hipStream_t s);
-// PMIS rounds with lane groups sized to avg_row (the mean row length of A)
-void pmis_select(int n, const int* srp, const int* sci, const int* trp, const int* tci, const double* w,
-                 const int* cf, unsigned char* newc, int avg_row, hipStream_t s);
-void pmis_update(int n, const int* srp, const int* sci, const unsigned char* newc, int* cf, int* undecided,
+// PMIS rounds (lane groups sized to avg_row, the mean strong-row length):
+// select marks the beaten undecided points (beaten must start at zero);
+// update moves the state cf -> cf_next and clears beaten_next.
+void pmis_select(int n, const int* srp, const int* sci, const double* w, const int* cf, unsigned char* beaten,
                  int avg_row, hipStream_t s);
+void pmis_update(int n, const int* srp, const int* sci, const int* cf, const unsigned char* beaten, int* cf_next,
+                 unsigned char* beaten_next, int* undecided, int avg_row, hipStream_t s);
 void cf_is_c(int n, const int* cf, int* isC, hipStream_t s);
 void interp_count(const DCsr& A, const unsigned char* strong, const int* cf, int* cnt, hipStream_t s);
 // needs A's CSR-stream row blocks (one workgroup each)
@@ -126,5 +126,6 @@ void pj_fill(int n, int nC, const int* isF, const int* lmap, const DCsr& Y, doub
 
 void to_float(const double* src, float* dst, long n, hipStream_t s);
 void fill_int(int* p, int v, long n, hipStream_t s);
+void fill_bytes(unsigned char* p, unsigned char v, long n, hipStream_t s);
 
 }  // namespace mgr

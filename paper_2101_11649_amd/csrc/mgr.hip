@@ -333,23 +333,23 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
         if (n <= o.max_coarse || k + 1 >= o.max_levels) break;
         size_t nz = (size_t)(A.nnz > 0 ? A.nnz : 1);
         DArr<unsigned char> strong(nz, s);
-        DArr<int> scnt((size_t)n + 1, s), srp((size_t)n + 1, s), trp((size_t)n + 1, s), cursor((size_t)n + 1, s);
+        DArr<int> scnt((size_t)n + 1, s), srp((size_t)n + 1, s);
         DArr<int> lam((size_t)n + 1, s);
         fill_int(lam.p, 0, n + 1, s);
         L.dinv.alloc((size_t)n, s);
         amg_strength(A, o.theta, L.label.p, strong.p, scnt.p, lam.p, L.dinv.p, S.flag(), s);
-        // strength graph S (row i lists S_i) and its transpose; both fit in nnz(A)
-        DArr<int> sci(nz, s), tci(nz, s);
+        // strength graph S (row i lists S_i)
+        DArr<int> sci(nz, s);
         scan_exclusive_async(scnt.p, srp.p, n, s);
         strength_compact_fill(A, strong.p, srp.p, sci.p, s);
-        scan_exclusive_async(lam.p, trp.p, n, s);
-        MGR_HIP(hipMemcpyAsync(cursor.p, trp.p, sizeof(int) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
-        pattern_transpose_fill(n, srp.p, sci.p, trp.p, cursor.p, tci.p, s);
-        // PMIS rounds, run in batches between checks of the undecided count
+        // PMIS rounds, run in batches between checks of the undecided count;
+        // the state (cf, beaten) alternates between two buffers
         DArr<double> w((size_t)n, s);
-        DArr<int> cf((size_t)n, s), isC((size_t)n + 1, s), cidx((size_t)n + 1, s), pcnt((size_t)n + 1, s);
-        DArr<unsigned char> newc((size_t)n, s);
+        DArr<int> cf((size_t)n, s), cf2((size_t)n, s), isC((size_t)n + 1, s), cidx((size_t)n + 1, s),
+            pcnt((size_t)n + 1, s);
+        DArr<unsigned char> bt((size_t)n, s), bt2((size_t)n, s);
         pmis_init(n, lam.p, seed, k, w.p, cf.p, s);
+        fill_bytes(bt.p, 0, n, s);
         DCsr P;
         Pend pp;
         long long* sc = nullptr;
@@ -362,10 +362,12 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
             if (total > 100000) throw Error(MGR_ERR_UNSUPPORTED, "PMIS did not terminate");
             long long* und = S.take(1);
             for (int r = 0; r < batch; ++r) {
-                pmis_select(n, srp.p, sci.p, trp.p, tci.p, w.p, cf.p, newc.p, avg_row, s);
+                pmis_select(n, srp.p, sci.p, w.p, cf.p, bt.p, avg_row, s);
                 // the undecided points are counted after the last round of the batch
-                pmis_update(n, srp.p, sci.p, newc.p, cf.p, r + 1 == batch ? reinterpret_cast<int*>(und) : nullptr,
-                            avg_row, s);
+                pmis_update(n, srp.p, sci.p, cf.p, bt.p, cf2.p, bt2.p,
+                            r + 1 == batch ? reinterpret_cast<int*>(und) : nullptr, avg_row, s);
+                std::swap(cf, cf2);
+                std::swap(bt, bt2);
             }
             // speculative: C numbering and interpolation row counts for this state
             cf_is_c(n, cf.p, isC.p, s);
