@@ -8,6 +8,8 @@
 // order written (a separate multiply and add, no fused multiply-add).
 #include <climits>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace mgr {
@@ -246,6 +248,22 @@ __global__ void k_bsr_tvalues(long nnzb, int b, const int* __restrict__ src, con
 }
 
 // ------------------------------------------------------------------ C/F split and block extraction
+// Histogram of the field labels (32 bins, hist zeroed beforehand); a label
+// outside [0, 32) sets *flag to 5.
+__global__ __launch_bounds__(TPB) void k_field_hist(int n, const int* __restrict__ field, int* __restrict__ hist,
+                                                    int* __restrict__ flag) {
+    __shared__ int h[32];
+    if (threadIdx.x < 32) h[threadIdx.x] = 0;
+    __syncthreads();
+    for (int i = blockIdx.x * TPB + threadIdx.x; i < n; i += gridDim.x * TPB) {
+        const int f = field[i];
+        if (f < 0 || f >= 32) set_flag(flag, 5);
+        else atomicAdd(&h[f], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < 32 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
 __global__ void k_cf_flags(int n, const int* __restrict__ field, uint32_t mask, int* __restrict__ isF,
                            int* __restrict__ flag) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2043,6 +2061,12 @@ int read_int(const int* dptr, hipStream_t s) {
     return h;
 }
 
+
+void field_hist(int n, const int* field, int* hist, int* flag, hipStream_t s) {
+    k_fill_int<<<1, 32, 0, s>>>(hist, 0, 32);
+    if (n > 0) k_field_hist<<<std::min(nblk(n), 1024), TPB, 0, s>>>(n, field, hist, flag);
+    MGR_LAUNCH_CHECK();
+}
 
 void fill_bytes(unsigned char* p, unsigned char v, long n, hipStream_t s) {
     if (n <= 0) return;

@@ -27,6 +27,9 @@ void bsr_fill(int b, int nbr, long nnzb, const int* brp, const int* bci, const d
 void bsr_transpose_blocks(int b, int nbr, const int* rp, const int* ci, const double* v, int* trp, int* tci,
                           double* tv, hipStream_t s);
 
+// hist[f] = number of labels equal to f (32 bins); *flag = 5 for a label
+// outside [0, 32).
+void field_hist(int n, const int* field, int* hist, int* flag, hipStream_t s);
 // isF[i] = bit field[i] of mask; flag set to 1 if a label is outside [0,32).
 void cf_flags(int n, const int* field, uint32_t mask, int* isF, int* flag, hipStream_t s);
 // fpos = exclusive scan of isF; lmap[i] = local index in F or C; fmap / cmap.

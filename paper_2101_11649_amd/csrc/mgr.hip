@@ -750,8 +750,10 @@ struct Ctx {
     std::vector<MgrLevel> L;
     Amg camg;
     Slots slots;
-    // setup inputs kept for mgr_update_values: field labels and level options
-    DArr<int> field0;
+    // setup inputs kept for mgr_update_values: field labels and level options,
+    // and the labels' histogram (pinned; it sizes every level's F and C sets)
+    DArr<int> field0, fhist;
+    int* fhist_h = nullptr;
     std::vector<mgr_level_opts> lvl;
     // hierarchies handed from the previous setup to the one being formed
     std::vector<std::unique_ptr<Amg>> reuse_famg;
@@ -769,6 +771,7 @@ struct Ctx {
     double* hpin_dev = nullptr;  // the same rows as seen by kernels
     ~Ctx() {
         if (hpin) (void)hipHostFree(hpin);
+        if (fhist_h) (void)hipHostFree(fhist_h);
     }
 };
 
@@ -780,8 +783,11 @@ static bool fused_ok(const mgr_level_opts& o) {
 // One MGR level (Sec. 2): C/F split by field, blocks A_FF, A_FC, A_CF, A_CC,
 // F-relaxation operator M, P_F = -M A_FC, R_F = -A_CF M (Jacobi restriction),
 // coarse operator A_c = A_CC + A_CF P_F (+ R_F A_FC + R_F (A_FF P_F)).
+// nF (the number of F-points, known from the label histogram) sizes the
+// level's arrays without a sync; the scan's own count is checked at the first
+// sync.
 static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr& A, const int* field, const int* block,
-                            const mgr_level_opts& o, int lev) {
+                            const mgr_level_opts& o, int lev, int nF) {
     hipStream_t s = c.s;
     Slots& S = c.slots;
     int n = A.nr;
@@ -790,20 +796,20 @@ static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr& A, const int* field
     l.isF.alloc((size_t)n + 1, s);
     l.lmap.alloc((size_t)n + 1, s);
     DArr<int> fpos((size_t)n + 1, s);
+    l.nF = nF;
+    l.nC = n - nF;
+    if (l.nF == 0 || l.nC == 0)
+        throw Error(MGR_ERR_BAD_LABELS, "MGR level " + std::to_string(lev) + ": empty F or C set");
     cf_flags(n, field, o.f_field_mask, l.isF.p, S.flag(), s);
     long long* sF = S.take(2);
     scan_async(l.isF.p, fpos.p, n, sF, s);
-    S.sync("C/F split");
-    l.nF = (int)S.val(sF);
-    l.nC = n - l.nF;
-    if (l.nF == 0 || l.nC == 0)
-        throw Error(MGR_ERR_BAD_LABELS, "MGR level " + std::to_string(lev) + ": empty F or C set");
-    l.fmap.alloc((size_t)l.nF, s);
-    l.cmap.alloc((size_t)l.nC, s);
+    // the maps and counts below are sized for n until the scan's count of F-points is read
+    l.fmap.alloc((size_t)n, s);
+    l.cmap.alloc((size_t)n, s);
     cf_maps(n, l.isF.p, fpos.p, l.lmap.p, l.fmap.p, l.cmap.p, s);
     // block extraction and the F-relaxation block structure (Jacobi: 1x1 blocks;
     // block-Jacobi: the F-points of one block row)
-    DArr<int> cFF((size_t)l.nF + 1, s), cFC((size_t)l.nF + 1, s), cCF((size_t)l.nC + 1, s), cCC((size_t)l.nC + 1, s);
+    DArr<int> cFF((size_t)n + 1, s), cFC((size_t)n + 1, s), cCF((size_t)n + 1, s), cCC((size_t)n + 1, s);
     extract_count(A, l.isF.p, l.lmap.p, cFF.p, cFC.p, cCF.p, cCC.p, s);
     Pend pFF = csr_begin(l.AFF, l.nF, l.nF, cFF.p, S);
     Pend pFC = csr_begin(l.AFC, l.nF, l.nC, cFC.p, S);
@@ -824,12 +830,13 @@ static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr& A, const int* field
     frelax_row_len(l.nF, bnum.p, bstart.p, len.p, s);
     Pend pM = csr_begin(l.M, l.nF, l.nF, len.p, S);
     S.sync("block extraction");
+    if (S.val(sF) != l.nF) throw Error(MGR_ERR_ARG, "internal: F-point count differs from the label histogram");
     csr_finish(pFF, S); csr_finish(pFC, S); csr_finish(pCF, S); csr_finish(pCC, S); csr_finish(pM, S);
     long nb = (long)S.val(sB);
     extract_fill(A, l.isF.p, l.lmap.p, l.AFF, l.AFC, l.ACF, l.ACC, s);
+    // M's pivots are checked at the next sync (an invalid one sets the flag);
+    // until then M is only an operand of products, never used for control
     frelax_fill((int)nb, bstart.p, l.AFF, l.M, S.flag(), s);
-    // nothing may consume M before its pivots are known to be valid
-    S.sync("F-relaxation operator");
     if (o.frelax == MGR_FRELAX_ILU0) {
         // ILU(0) on the pattern of A_FF in the natural order, one level of rows at a time
         DCsr LU = csr_copy(l.AFF, s);
@@ -1468,9 +1475,14 @@ static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nle
     MGR_HIP(hipMemcpyAsync(c.Aci.p, A->col_idx, sizeof(int) * c.nnzb, hipMemcpyDeviceToDevice, s));
     MGR_HIP(hipMemcpyAsync(c.Av.p, A->values, sizeof(double) * c.nnzb * bb, hipMemcpyDeviceToDevice, s));
     if (c.nnzb * bb > INT_MAX) throw Error(MGR_ERR_UNSUPPORTED, "more than 2^31 scalar entries");
-    expand_input(c);
     c.field0.alloc((size_t)c.n, s);
     MGR_HIP(hipMemcpyAsync(c.field0.p, field, sizeof(int) * c.n, hipMemcpyDeviceToDevice, s));
+    // the label histogram reaches the host with the input matrix's sync
+    if (!c.fhist_h) MGR_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.fhist_h), sizeof(int) * 32, hipHostMallocDefault));
+    c.fhist.alloc(32, s);
+    field_hist(c.n, c.field0.p, c.fhist.p, c.slots.flag(), s);
+    MGR_HIP(hipMemcpyAsync(c.fhist_h, c.fhist.p, sizeof(int) * 32, hipMemcpyDeviceToHost, s));
+    expand_input(c);
     c.lvl.assign(lvl, lvl + nlevels);
     build_hierarchy(c);
 }
@@ -1487,8 +1499,18 @@ static void build_hierarchy(Ctx& c) {
     const DCsr* cur = &c.A0;
     DCsr next;
     c.L.resize(nlevels);
+    uint32_t used = 0;  // fields that were F on an earlier level
     for (int l = 0; l < nlevels; ++l) {
-        DCsr Ac = mgr_setup_level(c, c.L[l], *cur, fld.p, blk.p, lvl[l], l);
+        // F-points of this level: the remaining points whose field is in the mask
+        long nF = 0, nrem = 0;
+        for (int f = 0; f < 32; ++f) {
+            if ((used >> f) & 1u) continue;
+            nrem += c.fhist_h[f];
+            if ((lvl[l].f_field_mask >> f) & 1u) nF += c.fhist_h[f];
+        }
+        used |= lvl[l].f_field_mask;
+        if (nrem != cur->nr) throw Error(MGR_ERR_ARG, "internal: label histogram and level size differ");
+        DCsr Ac = mgr_setup_level(c, c.L[l], *cur, fld.p, blk.p, lvl[l], l, (int)nF);
         MgrLevel& L = c.L[l];
         DArr<int> f2((size_t)L.nC, s), b2((size_t)L.nC, s);
         gather_int(L.nC, L.cmap.p, fld.p, f2.p, s);
