@@ -255,10 +255,23 @@ __global__ __launch_bounds__(TPB) void k_field_hist(int n, const int* __restrict
     __shared__ int h[32];
     if (threadIdx.x < 32) h[threadIdx.x] = 0;
     __syncthreads();
-    for (int i = blockIdx.x * TPB + threadIdx.x; i < n; i += gridDim.x * TPB) {
-        const int f = field[i];
-        if (f < 0 || f >= 32) set_flag(flag, 5);
-        else atomicAdd(&h[f], 1);
+    // per wavefront, one atomic per distinct label (there are few)
+    for (int base = blockIdx.x * TPB; base < n; base += gridDim.x * TPB) {
+        const int i = base + threadIdx.x;
+        int f = (i < n) ? field[i] : -1;
+        if (i < n && (f < 0 || f >= 32)) {
+            set_flag(flag, 5);
+            f = -1;
+        }
+        bool left = f >= 0;
+        while (__any(left)) {
+            const unsigned long long act = __ballot(left);
+            const int lead = __ffsll(act) - 1;
+            const int fl = __shfl(f, lead, WAVE);
+            const unsigned long long same = __ballot(left && f == fl);
+            if ((int)(threadIdx.x & (WAVE - 1)) == lead) atomicAdd(&h[fl], (int)__popcll(same));
+            if (left && f == fl) left = false;
+        }
     }
     __syncthreads();
     if (threadIdx.x < 32 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
