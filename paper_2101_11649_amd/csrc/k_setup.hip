@@ -773,14 +773,47 @@ __global__ void k_is_c(int n, const int* __restrict__ cf, int* __restrict__ isC)
 
 
 
-// one workgroup per row: the row is cleared, then its entries are stored
-__global__ void k_densify(int n, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ v,
+// one workgroup per row: the row (nc entries) is cleared, then its entries are stored
+__global__ void k_densify(int nc, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ v,
                           double* __restrict__ dense) {
     const int i = blockIdx.x;
-    double* row = dense + (long)i * n;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) row[j] = 0.0;
+    double* row = dense + (long)i * nc;
+    for (int j = threadIdx.x; j < nc; j += blockDim.x) row[j] = 0.0;
     __syncthreads();
     for (int p = rp[i] + threadIdx.x; p < rp[i + 1]; p += blockDim.x) row[ci[p]] = v[p];
+}
+
+// C (m x n) = A (m x k) B (k x n), dense row-major, one thread per entry
+// (small factors only: the coarse tail of an AMG cycle).
+__global__ void k_dense_gemm(int m, int k, int n, const double* __restrict__ a, const double* __restrict__ b,
+                             double* __restrict__ c) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)m * n) return;
+    const int i = (int)(idx / n), j = (int)(idx % n);
+    double acc = 0.0;
+    for (int q = 0; q < k; ++q) acc += a[(long)i * k + q] * b[(long)q * n + j];
+    c[idx] = acc;
+}
+
+// T (nr x n, dense) += Q X with Q sparse (nr rows) and X dense (rows of n):
+// one workgroup per row of T.
+__global__ void k_sparse_dense_add(int n, const int* __restrict__ qrp, const int* __restrict__ qci,
+                                   const double* __restrict__ qv, const double* __restrict__ x,
+                                   double* __restrict__ t) {
+    const int i = blockIdx.x;
+    const int p0 = qrp[i], p1 = qrp[i + 1];
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        double acc = t[(long)i * n + j];
+        for (int p = p0; p < p1; ++p) acc += qv[p] * x[(long)qci[p] * n + j];
+        t[(long)i * n + j] = acc;
+    }
+}
+
+__global__ void k_dense_transpose(int n, const double* __restrict__ a, double* __restrict__ t) {
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)n * n) return;
+    const int i = (int)(idx / n), j = (int)(idx % n);
+    t[(long)j * n + i] = a[idx];
 }
 
 // Gauss-Jordan inverse with partial pivoting of the coarsest AMG matrix, one
@@ -2465,7 +2498,25 @@ void l1_dinv(const DCsr& A, double* dinv, int* flag, hipStream_t s) {
 
 void densify(const DCsr& A, double* dense, hipStream_t s) {
     if (A.nr <= 0) return;
-    k_densify<<<A.nr, 128, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, dense);
+    k_densify<<<A.nr, 128, 0, s>>>(A.nc, A.rp.p, A.ci.p, A.v.p, dense);
+    MGR_LAUNCH_CHECK();
+}
+
+void dense_gemm(int m, int k, int n, const double* a, const double* b, double* c, hipStream_t s) {
+    if ((long)m * n <= 0) return;
+    k_dense_gemm<<<nblk((long)m * n), TPB, 0, s>>>(m, k, n, a, b, c);
+    MGR_LAUNCH_CHECK();
+}
+
+void sparse_dense_add(const DCsr& Q, const double* x, int n, double* t, hipStream_t s) {
+    if (Q.nr <= 0 || n <= 0) return;
+    k_sparse_dense_add<<<Q.nr, TPB, 0, s>>>(n, Q.rp.p, Q.ci.p, Q.v.p, x, t);
+    MGR_LAUNCH_CHECK();
+}
+
+void dense_transpose(int n, const double* a, double* t, hipStream_t s) {
+    if (n <= 0) return;
+    k_dense_transpose<<<nblk((long)n * n), TPB, 0, s>>>(n, a, t);
     MGR_LAUNCH_CHECK();
 }
 

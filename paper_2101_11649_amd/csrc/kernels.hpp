@@ -106,7 +106,13 @@ void compose_w(const DCsr& A, const double* dinv, double* w, int* bad, hipStream
 void compose_sub(const DCsr& X, const DCsr& Y, const double* rs, const double* cs, double* out, int* bad,
                  hipStream_t s);
 void concat_rows(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s);
+// dense row-major copy of A (nr x nc)
 void densify(const DCsr& A, double* dense, hipStream_t s);
+// small dense helpers for the coarse tail of the AMG cycle: C = A B (m x k
+// times k x n), T += Q X (Q sparse, X with rows of n), T = A^T (n x n)
+void dense_gemm(int m, int k, int n, const double* a, const double* b, double* c, hipStream_t s);
+void sparse_dense_add(const DCsr& Q, const double* x, int n, double* t, hipStream_t s);
+void dense_transpose(int n, const double* a, double* t, hipStream_t s);
 void dense_inverse(int n, double* a, double* inv, int* flag, hipStream_t s);
 
 // ILU(0): level analysis (fwd: dependencies on columns < i; else > i), bucketing

@@ -270,6 +270,11 @@ struct Amg {
     std::vector<AmgLevel> lv;
     DArr<double> cinv, cinvT;
     DArr<float> cinvf, cinvTf;
+    // the level above the coarsest when composed: its whole cycle as one dense
+    // n x n operator T = W + Q C^-1 G (tail = its index, -1 if none)
+    int tail = -1;
+    DArr<double> td, tdT;
+    DArr<float> tdf, tdTf;
     int nc = 0, nu_pre = 1, nu_post = 1;
     bool have_float = false, have_trans = false;
 };
@@ -305,6 +310,27 @@ static void amg_compose_finish(AmgLevel& L, Slots& S) {
         L.WQ = DCsr();
     }
     L.bad = nullptr;
+}
+
+// The cycle of the last level above the coarsest, when applied in composed
+// form (b_c = G b, x_c = C^-1 b_c, x = W b + Q x_c), is the linear map
+// T = W + Q C^-1 G; for small levels it is formed densely once and applied as
+// one GEMV, so three dependent launches become one.
+constexpr int AMG_TAIL_MAX = 1024;
+static void amg_make_tail(Amg& H, hipStream_t s) {
+    H.tail = -1;
+    H.td.reset(); H.tdT.reset(); H.tdf.reset(); H.tdTf.reset();
+    const int L = (int)H.lv.size() - 2;
+    if (L < 0 || !H.lv[L].composed || H.lv[L].n > AMG_TAIL_MAX) return;
+    AmgLevel& Lv = H.lv[L];
+    const int n = Lv.n, nc = H.nc;
+    DArr<double> gd((size_t)nc * n + 1, s), x((size_t)nc * n + 1, s);
+    densify(Lv.G, gd.p, s);
+    dense_gemm(nc, nc, n, H.cinv.p, gd.p, x.p, s);
+    H.td.alloc((size_t)n * n + 1, s);
+    densify(Lv.W, H.td.p, s);
+    sparse_dense_add(Lv.Q, x.p, n, H.td.p, s);
+    H.tail = L;
 }
 
 // Classical AMG setup (the coarse solver of Sec. 4.1, with PMIS coarsening,
@@ -444,6 +470,7 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
     S.sync("AMG coarsest inverse");
     for (size_t l = 0; l + 1 < H.lv.size(); ++l)
         if (H.lv[l].composed) amg_compose_finish(H.lv[l], S);
+    amg_make_tail(H, s);
     H.have_float = false;
     H.have_trans = false;
 }
@@ -491,6 +518,7 @@ static void amg_refresh(Amg& H, DCsr A0, Slots& S) {
     S.sync("AMG coarsest inverse");
     for (int k = 0; k + 1 < nl; ++k)
         if (H.lv[k].composed) amg_compose_finish(H.lv[k], S);
+    amg_make_tail(H, s);
     H.cinvT.reset();
     H.cinvf.reset();
     H.cinvTf.reset();
@@ -534,6 +562,15 @@ static void amg_make_float(Amg& H, hipStream_t s) {
         H.cinvTf.alloc((size_t)nn + 1, s);
         to_float(H.cinvT.p, H.cinvTf.p, nn, s);
     }
+    if (H.tail >= 0) {
+        const long tn = (long)H.lv[H.tail].n * H.lv[H.tail].n;
+        H.tdf.alloc((size_t)tn + 1, s);
+        to_float(H.td.p, H.tdf.p, tn, s);
+        if (H.have_trans) {
+            H.tdTf.alloc((size_t)tn + 1, s);
+            to_float(H.tdT.p, H.tdTf.p, tn, s);
+        }
+    }
     H.have_float = true;
 }
 
@@ -573,6 +610,15 @@ static void amg_make_trans(Amg& H, Slots& S) {
         H.cinvTf.alloc((size_t)nc * nc + 1, s);
         to_float(H.cinvT.p, H.cinvTf.p, (long)nc * nc, s);
     }
+    if (H.tail >= 0) {
+        const int tn = H.lv[H.tail].n;
+        H.tdT.alloc((size_t)tn * tn + 1, s);
+        dense_transpose(tn, H.td.p, H.tdT.p, s);
+        if (H.have_float) {
+            H.tdTf.alloc((size_t)tn * tn + 1, s);
+            to_float(H.tdT.p, H.tdTf.p, (long)tn * tn, s);
+        }
+    }
     MGR_HIP(hipStreamSynchronize(s));
     H.have_trans = true;
 }
@@ -586,6 +632,7 @@ template <> struct Prec<double> {
     static double* sb(AmgLevel& L) { return L.sd.p; }
     static const double* dinv(AmgLevel& L) { return L.dinv.p; }
     static const double* cinv(Amg& H, bool tr) { return tr ? H.cinvT.p : H.cinv.p; }
+    static const double* tail(Amg& H, bool tr) { return tr ? H.tdT.p : H.td.p; }
 };
 template <> struct Prec<float> {
     static float* r(AmgLevel& L) { return L.rf.p; }
@@ -595,6 +642,7 @@ template <> struct Prec<float> {
     static float* sb(AmgLevel& L) { return L.sf.p; }
     static const float* dinv(AmgLevel& L) { return L.dinvf.p; }
     static const float* cinv(Amg& H, bool tr) { return tr ? H.cinvTf.p : H.cinvf.p; }
+    static const float* tail(Amg& H, bool tr) { return tr ? H.tdTf.p : H.tdf.p; }
 };
 
 // V(nu_pre, nu_post) cycle from x = 0 with L1-Jacobi smoothing; the transposed
@@ -607,6 +655,10 @@ static void amg_vcycle(Amg& H, int k, const T* b, T* x, bool tr, hipStream_t s, 
     int n = L.n;
     if (k + 1 == (int)H.lv.size()) {
         dense_gemv<T, T>(n, Prec<T>::cinv(H, tr), b, x, s);
+        return;
+    }
+    if (k == H.tail) {
+        dense_gemv<T, T>(n, Prec<T>::tail(H, tr), b, x, s);
         return;
     }
     if (L.composed) {
