@@ -148,8 +148,8 @@ def main():
                     help="timed steps of the secondary fracturing workload (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is not part of "
-              f"this build", file=sys.stderr)
+        print(f"bench.py measures one GPU (got --gpus {args.gpus}): the solver runs on a single device and "
+              f"has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -570,14 +570,14 @@ def csr_of(system):
     return sp.bsr_matrix((blocks, system["ci"], system["rp"]), shape=(nbr * b, nbr * b)).tocsr()
 
 
-CONFIGS = {
-    0: lambda: two_field_tpfa(16, 16, 16, seed=0),
-    1: lambda: hybrid_mimetic(64, 64, 64, seed=1),
-    2: lambda: compositional_wells(128, 128, 64, seed=2),
-    3: lambda: fracturing(96, seed=3),
+WORKLOADS = {
+    "two_field_tpfa_16^3": lambda: two_field_tpfa(16, 16, 16, seed=0),
+    "hybrid_mimetic_64^3": lambda: hybrid_mimetic(64, 64, 64, seed=1),
+    "compositional_wells_128x128x64": lambda: compositional_wells(128, 128, 64, seed=2),
+    "fracturing_96^3": lambda: fracturing(96, seed=3),
 }
 
 
-def config(k):
-    """The benchmark workloads by index (see the module docstring)."""
-    return CONFIGS[k]()
+def workload(name):
+    """A full-size synthetic workload by name (the keys of WORKLOADS)."""
+    return WORKLOADS[name]()
