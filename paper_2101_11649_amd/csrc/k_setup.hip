@@ -2067,6 +2067,11 @@ static int group_for(int max_row) {
     return G;
 }
 
+// Lane groups for streaming row kernels that are bound by memory latency:
+// about four chunks per row, so a wavefront covers several rows and keeps
+// more loads in flight than one lane per entry of the longest row would.
+static int group_rows(int max_row) { return max_row < 0 ? 64 : group_for((max_row + 3) / 4); }
+
 #define MGR_DISPATCH_G4(G, ...)                                  \
     switch (G) {                                                 \
         case 4: { constexpr int GG = 4; __VA_ARGS__; } break;    \
@@ -2197,7 +2202,7 @@ void cf_maps(int n, const int* isF, const int* fpos, int* lmap, int* fmap, int* 
 void extract_count(const DCsr& A, const int* isF, const int* lmap, int* cFF, int* cFC, int* cCF, int* cCC,
                    hipStream_t s) {
     if (A.nr <= 0) return;
-    int G = group_for(A.max_row);
+    int G = group_rows(A.max_row);
     MGR_DISPATCH_G4(G, (k_extract_count_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, isF, lmap, cFF,
                                                                                    cFC, cCF, cCC)));
     MGR_LAUNCH_CHECK();
@@ -2206,7 +2211,7 @@ void extract_count(const DCsr& A, const int* isF, const int* lmap, int* cFF, int
 void extract_fill(const DCsr& A, const int* isF, const int* lmap, DCsr& FF, DCsr& FC, DCsr& CF, DCsr& CC,
                   hipStream_t s) {
     if (A.nr <= 0) return;
-    int G = group_for(A.max_row);
+    int G = group_rows(A.max_row);
     MGR_DISPATCH_G4(G, (k_extract_fill_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(
                            A.nr, A.rp.p, A.ci.p, A.v.p, isF, lmap, FF.rp.p, FF.ci.p, FF.v.p, FC.rp.p, FC.ci.p, FC.v.p,
                            CF.rp.p, CF.ci.p, CF.v.p, CC.rp.p, CC.ci.p, CC.v.p)));
@@ -2412,7 +2417,7 @@ void transpose_fill(const DCsr& A, DCsr& T, int* cnt, hipStream_t s) {
 void amg_strength(const DCsr& A, double theta, const int* label, unsigned char* strong, int* scnt, int* lam,
                   double* dinv, int* flag, hipStream_t s) {
     if (A.nr <= 0) return;
-    int G = group_for(A.max_row);
+    int G = group_rows(A.max_row);
     MGR_DISPATCH_G4(G, (k_strength_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, theta, label,
                                                                               strong, scnt, lam, dinv, flag)));
     MGR_LAUNCH_CHECK();
@@ -2421,7 +2426,7 @@ void amg_strength(const DCsr& A, double theta, const int* label, unsigned char* 
 
 void strength_compact_fill(const DCsr& A, const unsigned char* strong, const int* srp, int* sci, hipStream_t s) {
     if (A.nr <= 0) return;
-    int G = group_for(A.max_row);
+    int G = group_rows(A.max_row);
     MGR_DISPATCH_G4(G, (k_sfill_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, strong, srp, sci)));
     MGR_LAUNCH_CHECK();
 }
@@ -2466,7 +2471,7 @@ void cf_is_c(int n, const int* cf, int* isC, hipStream_t s) {
 
 void interp_count(const DCsr& A, const unsigned char* strong, const int* cf, int* cnt, hipStream_t s) {
     if (A.nr <= 0) return;
-    int G = group_for(A.max_row);
+    int G = group_rows(A.max_row);
     MGR_DISPATCH_G4(G, (k_interp_count_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, strong, cf, cnt)));
     MGR_LAUNCH_CHECK();
 }
@@ -2491,7 +2496,7 @@ void interp_fill(const DCsr& A, const unsigned char* strong, const int* cf, cons
 
 void l1_dinv(const DCsr& A, double* dinv, int* flag, hipStream_t s) {
     if (A.nr <= 0) return;
-    int G = group_for(A.max_row);
+    int G = group_rows(A.max_row);
     MGR_DISPATCH_G4(G, (k_l1_dinv_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, dinv, flag)));
     MGR_LAUNCH_CHECK();
 }
