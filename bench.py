@@ -144,6 +144,8 @@ def main():
     ap.add_argument("--grid", type=int, default=64, help="grid size per axis of the mimetic system")
     ap.add_argument("--comp-steps", type=int, default=2,
                     help="timed steps of the secondary compositional workload (0 = skip)")
+    ap.add_argument("--tpfa-steps", type=int, default=2,
+                    help="timed steps of the MGR_P vs MGR_Pi comparison on the TPFA mimetic system (0 = skip)")
     ap.add_argument("--frac-steps", type=int, default=1,
                     help="timed steps of the secondary fracturing workload (0 = skip)")
     args = ap.parse_args()
@@ -265,6 +267,28 @@ def main():
         comp4 = secondary(W.compositional_4level(seed=4), args.comp_steps,
                           "L1 F = rho_2 (Jacobi, exact), L2 F = rho_1 (Jacobi), L3 F = p (AMG V-cycle), "
                           "coarse = wells (direct)", 10)
+    # ---- secondary: the two reductions of the hybrid system (Sec. 3.1) on its TPFA
+    # variant, where both eliminate a diagonal block: MGR_P (F = cells, faces to
+    # AMG) against MGR_Pi (F = faces, the 7-point cell Schur complement to AMG)
+    tpfa = None
+    if args.tpfa_steps > 0:
+        tpfa = {"workload": f"hybrid_mimetic_tpfa_{g}x{g}x{g}", "apply": "fp64"}
+        for red, key in (("p", "mgr_p"), ("pi", "mgr_pi")):
+            log(f"generating hybrid mimetic TPFA {g}^3, reduction {key} ...")
+            st = W.hybrid_mimetic(g, g, g, seed=1, consistent=False, reduction=red)
+            vt = torch.tensor(st["vals"], device="cuda")
+            bt = torch.tensor(st["rhs"], device="cuda")
+            sv, rt, _, _, _ = run_steps(P, st, vt, bt, 64, args.tpfa_steps, 1)
+            hi = sv.info()
+            tpfa[key] = {"time_to_tol_s": round(statistics.mean(a + b for a, b, _, _ in rt), 6),
+                         "setup_s": round(statistics.mean(a for a, _, _, _ in rt), 6),
+                         "solve_s": round(statistics.mean(b for _, b, _, _ in rt), 6),
+                         "iterations": rt[-1][2], "rel_res_true": rt[-1][3],
+                         "coarse_n": hi["amg_levels"][0][0], "coarse_nnz": hi["amg_levels"][0][1],
+                         "amg_levels": len(hi["amg_levels"])}
+            sv.close()
+        tpfa["speedup_pi_over_p"] = round(tpfa["mgr_p"]["time_to_tol_s"] / tpfa["mgr_pi"]["time_to_tol_s"], 4)
+
     # ---- secondary: the fracturing system (Q1 elasticity on 96^3 nodes + a 96 x 96
     # planar fracture; MGR_U with an unknown-based AMG V-cycle as F-relaxation)
     if args.frac_steps > 0:
@@ -335,6 +359,7 @@ def main():
         "secondary_compositional": comp,
         "secondary_compositional_4level": comp4,
         "secondary_fracturing": frac,
+        "secondary_mimetic_tpfa_reductions": tpfa,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

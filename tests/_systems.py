@@ -11,6 +11,9 @@ SMALL = {
     "mimetic_9x7x6": lambda: W.hybrid_mimetic(9, 7, 6, seed=3),
     "mimetic_tpfa_sym_6^3": lambda: W.hybrid_mimetic(6, 6, 6, seed=4, consistent=False, upwind=False),
     "mimetic_20^3": lambda: W.hybrid_mimetic(20, 20, 20, seed=5),
+    # MGR_Pi on the TPFA variant: F = faces (diagonal block), C = cells -> AMG
+    "mimetic_tpfa_pi_9x7x6": lambda: W.hybrid_mimetic(9, 7, 6, seed=9, consistent=False, reduction="pi"),
+    "mimetic_tpfa_pi_26x21x17": lambda: W.hybrid_mimetic(26, 21, 17, seed=10, consistent=False, reduction="pi"),
     # 4x4 blocks + wells, two MGR levels (block-Jacobi, then Jacobi on wells)
     "comp_8x8x6": lambda: W.compositional_wells(8, 8, 6, seed=7),
     "comp_20x18x10": lambda: W.compositional_wells(20, 18, 10, seed=8, wells_per_axis=3),

@@ -52,6 +52,8 @@ def _check_hierarchy(gs, om, levels=()):
 FULL = {
     "mimetic_64^3": lambda: W.hybrid_mimetic(64, 64, 64, seed=1),
     "compositional_128x128x64": lambda: W.compositional_wells(seed=2),
+    # MGR_Pi (F = faces, C = the 262,144 cells) on the TPFA variant of the 64^3 grid
+    "mimetic_tpfa_64^3_mgr_pi": lambda: W.hybrid_mimetic(64, 64, 64, seed=1, consistent=False, reduction="pi"),
     # the paper's four-level order at 64x64x32 cells (393,264 unknowns; the
     # oracle's setup and solve take about 11 s there)
     "compositional_4level_64x64x32": lambda: W.compositional_4level(64, 64, 32, seed=4),

@@ -329,6 +329,47 @@ def test_schur_identity_injection_jacobi_p():
     np.testing.assert_allclose(ac, expect, rtol=1e-13, atol=1e-13 * np.abs(expect).max())
 
 
+def test_mgr_pi_on_tpfa_mimetic_is_the_exact_cell_schur_complement():
+    # MGR_Pi of Sec. 3.1 (F = faces, C = cells): in the TPFA variant A_pipi is
+    # diagonal, so Jacobi P is the ideal P of eq. (3), the coarse system is
+    # S = A_pp - A_ppi A_pipi^-1 A_pip, and S couples a cell only with the cells
+    # that share one of its faces (7 points)
+    nx, ny, nz = 4, 3, 3
+    s = W.hybrid_mimetic(nx, ny, nz, seed=6, consistent=False, reduction="pi")
+    m = build(s)
+    A, F, C = _dense_blocks(s)
+    assert len(C) == nx * ny * nz and np.all(s["field"][C] == 0)
+    AFF = A[np.ix_(F, F)]
+    assert np.count_nonzero(AFF - np.diag(np.diag(AFF))) == 0
+    expect = A[np.ix_(C, C)] - A[np.ix_(C, F)] @ np.linalg.inv(AFF) @ A[np.ix_(F, C)]
+    ac = m.export(0, 0, 1).to_scipy()
+    np.testing.assert_allclose(ac.toarray(), expect, rtol=1e-13, atol=1e-13 * np.abs(expect).max())
+    # brute-force 7-point pattern of the cell grid (cells numbered x fastest)
+    pattern = set()
+    for c in range(nx * ny * nz):
+        x, y, z = c % nx, (c // nx) % ny, c // (nx * ny)
+        for dx, dy, dz in [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]:
+            if 0 <= x + dx < nx and 0 <= y + dy < ny and 0 <= z + dz < nz:
+                pattern.add((c, (x + dx) + nx * ((y + dy) + ny * (z + dz))))
+    coo = ac.tocoo()
+    assert set(zip(coo.row.tolist(), coo.col.tolist())) == pattern
+
+
+@pytest.mark.parametrize("reduction", ["p", "pi"])
+def test_mgr_p_and_mgr_pi_exact_on_tpfa_mimetic(reduction):
+    # both reductions of Sec. 3.1 eliminate a diagonal block in the TPFA
+    # variant; with the coarse grid solved by LU (108 faces or 27 cells, both
+    # <= max_coarse) MGR is A^{-1} and FGMRES takes one iteration
+    s = W.hybrid_mimetic(3, 3, 3, seed=7, consistent=False, reduction=reduction)
+    m = build(s)
+    A = W.csr_of(s).toarray()
+    v = np.random.default_rng(8).standard_normal(s["n"])
+    ref = np.linalg.solve(A, v)
+    assert np.linalg.norm(m.apply(v) - ref) <= 1e-12 * np.linalg.norm(ref)
+    x, info = m.solve(s["rhs"], rtol=1e-12)
+    assert info.iterations == 1 and info.status == 0
+
+
 def test_four_level_system_structure():
     # the generator's structure that the reduction order relies on (Sec. 3.2):
     # rho_2 rows couple only inside their cell, and every pressure-controlled

@@ -148,7 +148,7 @@ def _g_matrix():
     return G
 
 
-def hybrid_mimetic(nx=64, ny=64, nz=64, seed=1, consistent=True, upwind=True, nrhs=1):
+def hybrid_mimetic(nx=64, ny=64, nz=64, seed=1, consistent=True, upwind=True, nrhs=1, reduction="p"):
     """Statically condensed hybrid mimetic system on an nx x ny x nz hex grid.
 
     Unknowns: cell pressures (field 0, numbered first) then face multipliers
@@ -159,7 +159,16 @@ def hybrid_mimetic(nx=64, ny=64, nz=64, seed=1, consistent=True, upwind=True, nr
         pi-row: -(T_K 1)_f,                  T_K
     with a_K ~ U[0.1,1] and upwind density factors u_f ~ U[0.9,1.1] (u_f = 1
     when upwind=False gives a symmetric system).  ln k_{x,y,z} ~ N(0, 2^2) i.i.d.
-    So A_pp is diagonal, A_ppi has 6 entries per row and A_pipi is 11-point."""
+    So A_pp is diagonal, A_ppi has 6 entries per row and A_pipi is 11-point
+    (diagonal in the TPFA variant, its off-diagonal entries stored as zeros).
+
+    reduction="p" is MGR_P of Sec. 3.1 (F = cells, whose block A_pp is
+    diagonal, so Jacobi interpolation is the ideal one; the faces go to AMG).
+    reduction="pi" is MGR_Pi (F = faces, C = cells): ideal only where A_pipi is
+    diagonal, that is in the TPFA variant, where the coarse system is the
+    7-point cell Schur complement A_pp - A_ppi A_pipi^-1 A_pip."""
+    if reduction not in ("p", "pi"):
+        raise ValueError("reduction must be 'p' or 'pi'")
     g = _rngs(seed)
     ncell = nx * ny * nz
     nfx, nfy, nfz = (nx + 1) * ny * nz, nx * (ny + 1) * nz, nx * ny * (nz + 1)
@@ -194,13 +203,14 @@ def hybrid_mimetic(nx=64, ny=64, nz=64, seed=1, consistent=True, upwind=True, nr
     A.sort_indices()
     field = np.concatenate([np.zeros(ncell, np.int32), np.ones(nface, np.int32)])
     rhs = g["rhs"].standard_normal((nrhs, n)) if nrhs > 1 else g["rhs"].standard_normal(n)
-    levels = [level(1 << 0, "jacobi")]
+    levels = [level(1 << 0 if reduction == "p" else 1 << 1, "jacobi")]
     extra = dict(grid=(nx, ny, nz), ncell=ncell, nface=nface)
     if nrhs > 1:
         extra["fd_rng"] = g["fd"]
         extra["loss_weights"] = g["loss"].standard_normal((nrhs, n))
     return _system(1, A.indptr, A.indices, A.data, field, rhs, levels,
-                   f"hybrid_mimetic_{'consistent' if consistent else 'tpfa'}_{nx}x{ny}x{nz}", **extra)
+                   f"hybrid_mimetic_{'consistent' if consistent else 'tpfa'}_{nx}x{ny}x{nz}"
+                   + ("_mgr_pi" if reduction == "pi" else ""), **extra)
 
 
 def compositional_wells(nx=128, ny=128, nz=64, seed=2, wells_per_axis=4, nperf=3, margin_p=1.1, margin_rho=2.0):
