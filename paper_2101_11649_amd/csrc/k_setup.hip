@@ -1206,36 +1206,43 @@ __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restri
             kb1 = brp[k + 1];
             if (FILL) ka = av[a0 + base + g.gl];
         }
-        const int lim = min(G, wl - base);
-        // the first G entries of the next row of B are loaded while the current
-        // one is inserted (one step of software pipelining)
-        int nb0 = __shfl(kb0, g.gbase, WAVE), nb1 = __shfl(kb1, g.gbase, WAVE);
-        int nj = (nb0 + g.gl < nb1) ? bci[nb0 + g.gl] : -1;
-        double nv = (FILL && nb0 + g.gl < nb1) ? bv[nb0 + g.gl] : 0.0;
-        for (int t = 0; t < lim; ++t) {
-            const int b0 = nb0, b1 = nb1;
-            const int j0 = nj;
-            const double v0 = nv;
-            const double a = __shfl(ka, g.gbase + t, WAVE);
-            if (t + 1 < lim) {
-                nb0 = __shfl(kb0, g.gbase + t + 1, WAVE);
-                nb1 = __shfl(kb1, g.gbase + t + 1, WAVE);
-                nj = (nb0 + g.gl < nb1) ? bci[nb0 + g.gl] : -1;
-                nv = (FILL && nb0 + g.gl < nb1) ? bv[nb0 + g.gl] : 0.0;
+        const int lim = min(G, wl - base);   // the same for the whole wavefront
+        // The first G entries of the rows of B that the next D entries of A
+        // select are loaded together (independent loads, one memory latency),
+        // then inserted one row after another, in the order of A's entries.
+        // Tables of 64 slots or more already limit the occupancy through LDS,
+        // so eight rows of B in registers cost nothing there; small tables
+        // take four.
+        constexpr int D = CAP >= 64 ? (G < 8 ? G : 8) : (G < 4 ? G : 4);
+        for (int t0 = 0; t0 < lim; t0 += D) {
+            int hj[D];
+            double hv[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const int b0 = __shfl(kb0, g.gbase + t0 + d, WAVE), b1 = __shfl(kb1, g.gbase + t0 + d, WAVE);
+                const bool in = t0 + d < lim && b0 + g.gl < b1;
+                hj[d] = in ? bci[b0 + g.gl] : -1;
+                hv[d] = (FILL && in) ? bv[b0 + g.gl] : 0.0;
             }
-            for (int q = b0 + g.gl; q < b1; q += G) {
-                const int j = (q == b0 + g.gl) ? j0 : bci[q];
-                const double prod = FILL ? a * ((q == b0 + g.gl) ? v0 : bv[q]) : 0.0;
-                // multiplicative hash: the top log2(CAP) bits of j * 2654435761
-                int h = (int)(((unsigned)j * 2654435761u) >> (32 - log2_pow2(CAP)));
-                int probes = 0;
-                for (;;) {
-                    int old = atomicCAS(&K[h], -1, j);
-                    if (old == -1 || old == j) break;
-                    h = (h + 1) & (CAP - 1);
-                    if (++probes == CAP) { atomicMax(flag, FILL ? 1 : 2); h = -1; break; }
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                if (t0 + d >= lim) break;
+                const int b0 = __shfl(kb0, g.gbase + t0 + d, WAVE), b1 = __shfl(kb1, g.gbase + t0 + d, WAVE);
+                const double a = __shfl(ka, g.gbase + t0 + d, WAVE);
+                for (int q = b0 + g.gl; q < b1; q += G) {
+                    const int j = (q == b0 + g.gl) ? hj[d] : bci[q];
+                    const double prod = FILL ? a * ((q == b0 + g.gl) ? hv[d] : bv[q]) : 0.0;
+                    // multiplicative hash: the top log2(CAP) bits of j * 2654435761
+                    int h = (int)(((unsigned)j * 2654435761u) >> (32 - log2_pow2(CAP)));
+                    int probes = 0;
+                    for (;;) {
+                        int old = atomicCAS(&K[h], -1, j);
+                        if (old == -1 || old == j) break;
+                        h = (h + 1) & (CAP - 1);
+                        if (++probes == CAP) { atomicMax(flag, FILL ? 1 : 2); h = -1; break; }
+                    }
+                    if (FILL && h >= 0) Vs[h] = Vs[h] + prod;
                 }
-                if (FILL && h >= 0) Vs[h] = Vs[h] + prod;
             }
         }
     }
