@@ -56,6 +56,14 @@ extern "C" {
 
 #define MGR_ORTHO_CGS2 0           /* classical Gram-Schmidt applied twice         */
 
+/* AMG interpolation: direct (Stueben 2001; the reading of the BoomerAMG
+ * settings of Sec. 4.1 both codes share) or extended+i (De Sterck, Falgout,
+ * Nolting, Yang 2008: distance two, the long-range interpolation that
+ * Sec. 4.1 pairs with HMIS coarsening).  Extended+i needs every interpolatory
+ * set to stay within 256 points, else the setup fails with MGR_ERR_UNSUPPORTED. */
+#define MGR_INTERP_DIRECT 0
+#define MGR_INTERP_EXT_I 1
+
 typedef struct mgr_ctx *mgr_handle;
 
 /* Block-CSR matrix with b x b row-major dense blocks.  b = 1 is plain CSR.
@@ -86,6 +94,7 @@ typedef struct {
     int32_t max_coarse;      /* stop coarsening at or below this size          */
     int32_t nu_pre, nu_post; /* L1-Jacobi sweeps                               */
     int32_t unknown_based;   /* coarse AMG: strength/interpolation per field   */
+    int32_t interp;          /* MGR_INTERP_DIRECT or MGR_INTERP_EXT_I          */
     uint64_t seed;           /* PMIS random weights (splitmix64)                */
 } mgr_amg_opts;
 
@@ -107,7 +116,8 @@ typedef struct {
 } mgr_solve_info;
 
 /* Defaults: apply_precision 64, restart 50, maxiter 1000, rtol 1e-8, CGS2,
- * theta 0.25, max_levels 25, max_coarse 128, V(1,1), seed 12345.  (host) */
+ * theta 0.25, max_levels 25, max_coarse 128, V(1,1), direct interpolation,
+ * seed 12345.  (host) */
 void mgr_default_opts(mgr_opts *o);
 
 /* Create a handle bound to a HIP stream (NULL = the null stream) on the

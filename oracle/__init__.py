@@ -48,10 +48,11 @@ def lib():
         P = ctypes.c_void_p
         i32, f64, u64 = ctypes.c_int, ctypes.c_double, ctypes.c_ulonglong
         L.orc_setup.restype = P
-        L.orc_setup.argtypes = [i32, i32, P, P, P, P, i32, P, P, P, P, P, P, f64, i32, i32, i32, i32, i32, u64, P]
+        L.orc_setup.argtypes = [i32, i32, P, P, P, P, i32, P, P, P, P, P, P, f64, i32, i32, i32, i32, i32, i32, u64,
+                                P]
         L.orc_update.restype = P
-        L.orc_update.argtypes = [P, i32, i32, P, P, P, P, i32, P, P, P, P, P, P, f64, i32, i32, i32, i32, i32, u64,
-                                 i32, P]
+        L.orc_update.argtypes = [P, i32, i32, P, P, P, P, i32, P, P, P, P, P, P, f64, i32, i32, i32, i32, i32, i32,
+                                 u64, i32, P]
         L.orc_free.argtypes = [P]
         L.orc_apply.argtypes = [P, P, P, i32]
         L.orc_matvec.argtypes = [P, P, P, i32]
@@ -74,6 +75,8 @@ def lib():
         L.orc_pmis_uniform.argtypes = [u64, i32, i32]
         L.orc_direct_interp.restype = P
         L.orc_direct_interp.argtypes = [i32, P, P, P, P, P, P, P]
+        L.orc_ext_interp.restype = P
+        L.orc_ext_interp.argtypes = [i32, P, P, P, P, P, P, P]
         L.orc_lu_solve.argtypes = [i32, P, P, P, i32]
         L.orc_small_inverse.argtypes = [i32, P, P]
         _lib = L
@@ -178,6 +181,21 @@ def direct_interp(a, strong, cf, label=None):
     return _unbox(box), st.value
 
 
+def ext_interp(a, strong, cf, label=None):
+    """Extended+i interpolation (distance two) of the AMG setup: (P, status)."""
+    n, _, rp, ci, v = _csr_args(a)
+    st = ctypes.c_int(0)
+    s = np.ascontiguousarray(strong, dtype=np.uint8)
+    if s.size == 0:
+        s = np.zeros(1, np.uint8)
+    lab = None if label is None else _i32(label)
+    box = lib().orc_ext_interp(n, _p(rp), _p(ci), _p(v), _p(s), _p(_i32(cf)), _p(lab), ctypes.byref(st))
+    return _unbox(box), st.value
+
+
+INTERP = {"direct": 0, "ext+i": 1}
+
+
 def lu_solve(dense, b, trans: bool = False):
     m = _f64(dense)
     n = m.shape[0]
@@ -230,11 +248,12 @@ class MGR:
     Parameters mirror the C-ABI of the GPU library: block size ``b`` (1 = CSR),
     block row pointers / columns / values (b*b row-major per block), the field
     label of every scalar unknown, a list of LevelOpts (one per MGR level), and
-    AMG options for the final coarse system.
+    AMG options for the final coarse system (``interp``: "direct" or "ext+i"
+    interpolation, also used by the F-relaxation AMG hierarchies).
     """
 
     def __init__(self, b, rp, ci, vals, field, levels, theta=0.25, max_levels=25, max_coarse=128,
-                 nu_pre=1, nu_post=1, coarse_unknown_based=False, seed=12345):
+                 nu_pre=1, nu_post=1, coarse_unknown_based=False, seed=12345, interp="direct"):
         L = lib()
         self.b = int(b)
         self.rp, self.ci, self.vals = _i32(rp), _i32(ci), _f64(vals)
@@ -249,7 +268,7 @@ class MGR:
         aub = _i32([int(lv.amg_unknown_based) for lv in levels] or [0])
         self._lv = (nl, fmask, frelax, sweeps, omega, restr, aub)
         self._amg = (float(theta), int(max_levels), int(max_coarse), int(nu_pre), int(nu_post),
-                     int(coarse_unknown_based), int(seed))
+                     int(coarse_unknown_based), INTERP[interp], int(seed))
         st = ctypes.c_int(0)
         self.h = L.orc_setup(self.b, len(self.rp) - 1, _p(self.rp), _p(self.ci), _p(self.vals), _p(self.field),
                              nl, *[_p(a) for a in self._lv[1:]], *self._amg, ctypes.byref(st))

@@ -43,6 +43,8 @@
 #define ORC_ERR_ZERO_PIVOT (-3)
 #define ORC_ERR_BAD_LABELS (-5)
 #define ORC_ERR_UNSUPPORTED (-6)
+#define AMG_INTERP_DIRECT 0
+#define AMG_INTERP_EXT_I 1
 
 #define FRELAX_JACOBI 0
 #define FRELAX_BLOCK_JACOBI 1
@@ -522,9 +524,118 @@ static int amg_direct_interp(const Csr *a, const unsigned char *strong, const in
     return status;
 }
 
+/* Extended+i interpolation (De Sterck, Falgout, Nolting, Yang, Numer. Linear
+ * Algebra Appl. 15 (2008), the distance-two interpolation paired with PMIS-type
+ * coarsening).  For an F-point i with strong C- and F-neighbours C_i^s, F_i^s
+ * (S_i, as in the strength definition) and other same-label neighbours
+ * (weak), the interpolatory set is
+ *   Chat_i = C_i^s  union  (union over k in F_i^s of C_k^s),
+ * abar_kl = a_kl where a_kl < 0 (opposite in sign to the positive a_kk), else 0,
+ * d_k = sum over l in Chat_i + {i} of abar_kl (row k left to right), and
+ *   atilde_ii = a_ii + sum_{weak n not in Chat_i} a_in
+ *               + sum_{k in F_i^s} a_ik abar_ki / d_k,
+ *   w_ij = -(a_ij + sum_{k in F_i^s} a_ik abar_kj / d_k) / atilde_ii   (j in Chat_i),
+ * with a_ij = 0 when j is not a neighbour of i.  A strong F-neighbour with
+ * d_k = 0 is lumped into the diagonal (atilde_ii += a_ik).  Order: the weak
+ * terms follow a_ii in row order, then the k terms in row order; each w_ij
+ * numerator starts from a_ij and adds its k terms in row order; each term is
+ * (a_ik * abar_kl) / d_k.  Columns of P ascend.  C-rows are unit rows; F-rows
+ * with an empty Chat_i are zero.  With labels only same-label couplings are
+ * used. */
+static int amg_ext_interp(const Csr *a, const unsigned char *strong, const int *cf, const int *label, Csr *pout) {
+    int n = a->nr;
+    int *cidx = (int *)xmalloc((size_t)n * sizeof(int));
+    int nc = 0;
+    for (int i = 0; i < n; ++i) cidx[i] = (cf[i] == 1) ? nc++ : -1;
+    int *mark = (int *)xmalloc((size_t)n * sizeof(int));       /* mark[j] == i + 1: j in Chat_i */
+    int *slot = (int *)xmalloc((size_t)n * sizeof(int));       /* position of j in the sorted Chat_i */
+    for (int i = 0; i < n; ++i) mark[i] = 0;
+    int *rp = (int *)xcalloc((size_t)n + 1, sizeof(int));
+    int *list = (int *)xmalloc((size_t)n * sizeof(int));
+    /* symbolic pass: |Chat_i| */
+    for (int i = 0; i < n; ++i) {
+        int cnt = 0;
+        if (cf[i] == 1) cnt = 1;
+        else
+            for (int p = a->rp[i]; p < a->rp[i + 1]; ++p) {
+                if (!strong[p]) continue;
+                int k = a->ci[p];
+                if (cf[k] == 1) { if (mark[k] != i + 1) { mark[k] = i + 1; cnt++; } continue; }
+                for (int q = a->rp[k]; q < a->rp[k + 1]; ++q) {
+                    int l = a->ci[q];
+                    if (strong[q] && cf[l] == 1 && mark[l] != i + 1) { mark[l] = i + 1; cnt++; }
+                }
+            }
+        rp[i + 1] = rp[i] + cnt;
+    }
+    Csr pm;
+    pm.nr = n; pm.nc = nc; pm.rp = rp;
+    pm.ci = (int *)xmalloc((size_t)(rp[n] > 0 ? rp[n] : 1) * sizeof(int));
+    pm.v = (double *)xmalloc((size_t)(rp[n] > 0 ? rp[n] : 1) * sizeof(double));
+    double *num = (double *)xmalloc((size_t)n * sizeof(double));
+    for (int i = 0; i < n; ++i) mark[i] = 0;
+    int status = ORC_OK;
+    for (int i = 0; i < n; ++i) {
+        int o = rp[i];
+        if (cf[i] == 1) { pm.ci[o] = cidx[i]; pm.v[o] = 1.0; continue; }
+        int m = rp[i + 1] - rp[i];
+        if (m == 0) continue;
+        /* Chat_i in ascending order */
+        int c = 0;
+        for (int p = a->rp[i]; p < a->rp[i + 1]; ++p) {
+            if (!strong[p]) continue;
+            int k = a->ci[p];
+            if (cf[k] == 1) { if (mark[k] != i + 1) { mark[k] = i + 1; list[c++] = k; } continue; }
+            for (int q = a->rp[k]; q < a->rp[k + 1]; ++q) {
+                int l = a->ci[q];
+                if (strong[q] && cf[l] == 1 && mark[l] != i + 1) { mark[l] = i + 1; list[c++] = l; }
+            }
+        }
+        qsort(list, (size_t)c, sizeof(int), cmp_int);
+        for (int t = 0; t < c; ++t) { slot[list[t]] = t; num[t] = 0.0; }
+        /* a_ii, a_ij (j in Chat_i) and the weak terms */
+        double aii = 0.0, atil;
+        for (int p = a->rp[i]; p < a->rp[i + 1]; ++p)
+            if (a->ci[p] == i) aii = a->v[p];
+        atil = aii;
+        for (int p = a->rp[i]; p < a->rp[i + 1]; ++p) {
+            int j = a->ci[p];
+            if (j == i || (label && label[j] != label[i])) continue;
+            if (mark[j] == i + 1) num[slot[j]] = a->v[p];
+            else if (!strong[p]) atil += a->v[p];
+        }
+        /* the strong F-neighbours, in row order */
+        for (int p = a->rp[i]; p < a->rp[i + 1]; ++p) {
+            int k = a->ci[p];
+            if (!strong[p] || cf[k] == 1) continue;
+            double aik = a->v[p], d = 0.0;
+            for (int q = a->rp[k]; q < a->rp[k + 1]; ++q) {
+                int l = a->ci[q];
+                if (a->v[q] < 0.0 && l != k && (l == i || mark[l] == i + 1)) d += a->v[q];
+            }
+            if (d == 0.0) { atil += aik; continue; }
+            for (int q = a->rp[k]; q < a->rp[k + 1]; ++q) {
+                int l = a->ci[q];
+                if (!(a->v[q] < 0.0) || l == k) continue;
+                if (l == i) atil += (aik * a->v[q]) / d;
+                else if (mark[l] == i + 1) num[slot[l]] += (aik * a->v[q]) / d;
+            }
+        }
+        if (!(atil > 0.0)) status = ORC_ERR_UNSUPPORTED;
+        for (int t = 0; t < c; ++t) {
+            pm.ci[o + t] = cidx[list[t]];
+            pm.v[o + t] = -num[t] / atil;
+        }
+    }
+    free(cidx); free(mark); free(slot); free(list); free(num);
+    *pout = pm;
+    return status;
+}
+
 typedef struct {
     double theta;
     int max_levels, max_coarse, nu_pre, nu_post, unknown_based;
+    int interp;             /* AMG_INTERP_DIRECT or AMG_INTERP_EXT_I */
     uint64_t seed;
 } AmgOpts;
 
@@ -583,7 +694,8 @@ static int amg_setup(const Csr *a0, const int *label0, const AmgOpts *o, Amg **o
         for (int i = 0; i < n; ++i) nc += (cf[i] == 1);
         if (nc == 0 || (double)nc > 0.9 * (double)n) { free(strong); free(cf); break; }
         Csr p;
-        int st = amg_direct_interp(a, strong, cf, h->label[k], &p);
+        int st = o->interp == AMG_INTERP_EXT_I ? amg_ext_interp(a, strong, cf, h->label[k], &p)
+                                               : amg_direct_interp(a, strong, cf, h->label[k], &p);
         free(strong);
         if (st != ORC_OK) { free(cf); csr_free(&p); status = st; break; }
         h->cf[k] = cf;
@@ -1243,17 +1355,17 @@ static void *setup_impl(int b, int nbr, const int *rp, const int *ci, const doub
                         int nlevels, const unsigned *fmask, const int *frelax, const int *sweeps,
                         const double *omega, const int *restrict_type, const int *amg_unknown_based_lvl,
                         double theta, int max_levels, int max_coarse, int nu_pre, int nu_post,
-                        int coarse_unknown_based, unsigned long long seed, const void *reuse_from, int keep_famg,
+                        int coarse_unknown_based, int interp, unsigned long long seed, const void *reuse_from, int keep_famg,
                         int *status);
 
 void *orc_setup(int b, int nbr, const int *rp, const int *ci, const double *val, const int *field, int nlevels,
                 const unsigned *fmask, const int *frelax, const int *sweeps, const double *omega,
                 const int *restrict_type, const int *amg_unknown_based_lvl, double theta, int max_levels,
-                int max_coarse, int nu_pre, int nu_post, int coarse_unknown_based, unsigned long long seed,
+                int max_coarse, int nu_pre, int nu_post, int coarse_unknown_based, int interp, unsigned long long seed,
                 int *status) {
     return setup_impl(b, nbr, rp, ci, val, field, nlevels, fmask, frelax, sweeps, omega, restrict_type,
                       amg_unknown_based_lvl, theta, max_levels, max_coarse, nu_pre, nu_post, coarse_unknown_based,
-                      seed, NULL, 0, status);
+                      interp, seed, NULL, 0, status);
 }
 
 /* Setup reuse for new values on the same pattern (the AMG data reuse between
@@ -1265,18 +1377,18 @@ void *orc_setup(int b, int nbr, const int *rp, const int *ci, const double *val,
 void *orc_update(const void *old, int b, int nbr, const int *rp, const int *ci, const double *val, const int *field,
                  int nlevels, const unsigned *fmask, const int *frelax, const int *sweeps, const double *omega,
                  const int *restrict_type, const int *amg_unknown_based_lvl, double theta, int max_levels,
-                 int max_coarse, int nu_pre, int nu_post, int coarse_unknown_based, unsigned long long seed,
-                 int keep_famg, int *status) {
+                 int max_coarse, int nu_pre, int nu_post, int coarse_unknown_based, int interp,
+                 unsigned long long seed, int keep_famg, int *status) {
     return setup_impl(b, nbr, rp, ci, val, field, nlevels, fmask, frelax, sweeps, omega, restrict_type,
                       amg_unknown_based_lvl, theta, max_levels, max_coarse, nu_pre, nu_post, coarse_unknown_based,
-                      seed, old, keep_famg, status);
+                      interp, seed, old, keep_famg, status);
 }
 
 static void *setup_impl(int b, int nbr, const int *rp, const int *ci, const double *val, const int *field,
                         int nlevels, const unsigned *fmask, const int *frelax, const int *sweeps,
                         const double *omega, const int *restrict_type, const int *amg_unknown_based_lvl,
                         double theta, int max_levels, int max_coarse, int nu_pre, int nu_post,
-                        int coarse_unknown_based, unsigned long long seed, const void *reuse_from, int keep_famg,
+                        int coarse_unknown_based, int interp, unsigned long long seed, const void *reuse_from, int keep_famg,
                         int *status) {
     const Handle *old = (const Handle *)reuse_from;
     Handle *h = (Handle *)xcalloc(1, sizeof(Handle));
@@ -1289,7 +1401,7 @@ static void *setup_impl(int b, int nbr, const int *rp, const int *ci, const doub
     m->b = b; m->nbr = nbr;
     *status = ORC_OK;
     if (nlevels < 0 || nlevels > MAX_MGR_LEVELS) { *status = ORC_ERR_ARG; return h; }
-    AmgOpts ao = {theta, max_levels, max_coarse, nu_pre, nu_post, coarse_unknown_based, (uint64_t)seed};
+    AmgOpts ao = {theta, max_levels, max_coarse, nu_pre, nu_post, coarse_unknown_based, interp, (uint64_t)seed};
     int *gblock = (int *)xmalloc((size_t)n * sizeof(int));
     for (int i = 0; i < n; ++i) gblock[i] = i / b;
     Csr cur = csr_copy(&h->A0);
@@ -1536,6 +1648,13 @@ void *orc_direct_interp(int n, const int *rp, const int *ci, const double *v, co
     Csr a = wrap(n, n, rp, ci, v);
     CsrBox *box = (CsrBox *)xcalloc(1, sizeof(CsrBox));
     *status = amg_direct_interp(&a, strong, cf, label, &box->c);
+    return box;
+}
+void *orc_ext_interp(int n, const int *rp, const int *ci, const double *v, const unsigned char *strong,
+                     const int *cf, const int *label, int *status) {
+    Csr a = wrap(n, n, rp, ci, v);
+    CsrBox *box = (CsrBox *)xcalloc(1, sizeof(CsrBox));
+    *status = amg_ext_interp(&a, strong, cf, label, &box->c);
     return box;
 }
 int orc_lu_solve(int n, const double *dense, const double *b, double *x, int trans) {

@@ -37,6 +37,9 @@ class MgrError(RuntimeError):
         self.code = code
 
 
+INTERP = {"direct": 0, "ext+i": 1}
+
+
 class mgr_matrix(ctypes.Structure):
     _fields_ = [("block_size", ctypes.c_int32), ("n_block_rows", ctypes.c_int32), ("row_ptr", ctypes.c_void_p),
                 ("col_idx", ctypes.c_void_p), ("values", ctypes.c_void_p)]
@@ -51,7 +54,7 @@ class mgr_level_opts(ctypes.Structure):
 class mgr_amg_opts(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("max_levels", ctypes.c_int32), ("max_coarse", ctypes.c_int32),
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32), ("unknown_based", ctypes.c_int32),
-                ("seed", ctypes.c_uint64)]
+                ("interp", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
 class mgr_opts(ctypes.Structure):
@@ -131,11 +134,13 @@ class Solver:
     ``b``: block size (1 = CSR); ``rp``, ``ci``, ``vals``: block-CSR arrays (any
     array-like or device tensor; copied by the library); ``field``: field label
     of every scalar unknown; ``levels``: list of dicts (fmask, frelax, sweeps,
-    omega, restrict, amg_unknown_based) -- one per MGR level.
+    omega, restrict, amg_unknown_based) -- one per MGR level; ``interp``: AMG
+    interpolation, "direct" or "ext+i" (extended+i, distance two).
     """
 
     def __init__(self, b, rp, ci, vals, field, levels, precision=64, restart=50, maxiter=1000, rtol=1e-8,
-                 theta=0.25, max_levels=25, max_coarse=128, nu_pre=1, nu_post=1, unknown_based=False, seed=12345):
+                 theta=0.25, max_levels=25, max_coarse=128, nu_pre=1, nu_post=1, unknown_based=False, seed=12345,
+                 interp="direct"):
         torch = _torch()
         L = lib()
         self._h = ctypes.c_void_p()
@@ -143,7 +148,7 @@ class Solver:
         L.mgr_default_opts(ctypes.byref(self.opts))
         self._fill_opts(precision=precision, restart=restart, maxiter=maxiter, rtol=rtol, theta=theta,
                         max_levels=max_levels, max_coarse=max_coarse, nu_pre=nu_pre, nu_post=nu_post,
-                        unknown_based=unknown_based, seed=seed)
+                        unknown_based=unknown_based, seed=seed, interp=interp)
         self.stream = torch.cuda.current_stream()
         self._check(L.mgr_create(ctypes.byref(self._h), ctypes.byref(self.opts), ctypes.c_void_p(self.stream.cuda_stream)))
         self.b = int(b)
@@ -157,7 +162,7 @@ class Solver:
         self.setup(vals)
 
     def _fill_opts(self, precision=None, restart=None, maxiter=None, rtol=None, theta=None, max_levels=None,
-                   max_coarse=None, nu_pre=None, nu_post=None, unknown_based=None, seed=None):
+                   max_coarse=None, nu_pre=None, nu_post=None, unknown_based=None, seed=None, interp=None):
         o = self.opts
         if precision is not None: o.apply_precision = int(precision)
         if restart is not None: o.restart = int(restart)
@@ -170,6 +175,7 @@ class Solver:
         if nu_post is not None: o.amg.nu_post = int(nu_post)
         if unknown_based is not None: o.amg.unknown_based = int(bool(unknown_based))
         if seed is not None: o.amg.seed = int(seed)
+        if interp is not None: o.amg.interp = INTERP[interp]
 
     def _check(self, code):
         if code < 0:

@@ -1708,6 +1708,257 @@ __global__ __launch_bounds__(TPB) void k_interp_fill_g(int n, const int* __restr
     }
 }
 
+// ------------------------------------------------------------ extended+i interpolation
+// Distance-two interpolation (De Sterck, Falgout, Nolting and Yang, Numer.
+// Linear Algebra Appl. 15 (2008)).  A lane group of G lanes per row keeps the
+// row's interpolatory set -- its strong C-neighbours and the strong
+// C-neighbours of its strong F-neighbours -- as the keys of an LDS hash table
+// (linear probing, as in the hashed SpGEMM).  The counts use tables of 512
+// slots; a set that fills its table sets *flag.
+constexpr int INTERP_EXT_COUNT_CAP = 512;
+
+template <int CAP>
+__device__ inline void ext_insert(int* K, int j, int* flag) {
+    int h = (int)(((unsigned)j * 2654435761u) >> (32 - log2_pow2(CAP)));
+    for (int probes = 0; probes < CAP; ++probes) {
+        const int old = atomicCAS(&K[h], -1, j);
+        if (old == -1 || old == j) return;
+        h = (h + 1) & (CAP - 1);
+    }
+    set_flag(flag, 6);
+}
+
+template <int CAP>
+__device__ inline int ext_find(const int* K, int j) {
+    int h = (int)(((unsigned)j * 2654435761u) >> (32 - log2_pow2(CAP)));
+    for (int probes = 0; probes < CAP; ++probes) {
+        const int key = K[h];
+        if (key == j) return h;
+        if (key == -1) return -1;
+        h = (h + 1) & (CAP - 1);
+    }
+    return -1;
+}
+
+// Inserts the interpolatory set of the group's row (entries p0 .. p0+len of A;
+// len = 0 for C-rows); maxlen is the longest len of the wavefront.
+template <int G, int CAP>
+__device__ inline void ext_gather_set(const Grp<G>& g, int p0, int len, int maxlen, const int* __restrict__ rp,
+                                      const int* __restrict__ ci, const unsigned char* __restrict__ strong,
+                                      const int* __restrict__ cf, int* K, int* flag) {
+    for (int base = 0; base < maxlen; base += G) {
+        const int q = base + g.gl;
+        const bool act = q < len;
+        const int k = act ? ci[p0 + q] : 0;
+        const bool st = act && strong[p0 + q];
+        const bool isc = st && cf[k] == 1;
+        if (isc) ext_insert<CAP>(K, k, flag);
+        int kb0 = 0, kb1 = 0;
+        if (st && !isc) {
+            kb0 = rp[k];
+            kb1 = rp[k + 1];
+        }
+        // the strong C-neighbours of each strong F-neighbour, one row after another
+        const int lim = min(G, maxlen - base);
+        for (int t = 0; t < lim; ++t) {
+            const int b0 = __shfl(kb0, g.gbase + t, WAVE), b1 = __shfl(kb1, g.gbase + t, WAVE);
+            for (int r = b0 + g.gl; r < b1; r += G) {
+                const int l = ci[r];
+                if (strong[r] && cf[l] == 1) ext_insert<CAP>(K, l, flag);
+            }
+        }
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(TPB) void k_interp_ext_count(int n, const int* __restrict__ rp,
+                                                          const int* __restrict__ ci,
+                                                          const unsigned char* __restrict__ strong,
+                                                          const int* __restrict__ cf, int* __restrict__ cnt,
+                                                          int* __restrict__ flag) {
+    constexpr int CAP = INTERP_EXT_COUNT_CAP, NG = TPB / G, PER = CAP / G;
+    __shared__ int keys[NG][CAP];
+    Grp<G> g;
+    const int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    const bool valid = i < n;
+    const bool frow = valid && cf[i] != 1;
+    int* K = keys[threadIdx.x / G];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) K[g.gl + G * u] = -1;
+    const int p0 = valid ? rp[i] : 0, len = frow ? rp[i + 1] - p0 : 0;
+    const int maxlen = wave_max_int(len);
+    ext_gather_set<G, CAP>(g, p0, len, maxlen, rp, ci, strong, cf, K, flag);
+    int mine = 0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) mine += (K[g.gl + G * u] >= 0) ? 1 : 0;
+    mine = g.sum(mine);
+    if (valid && g.gl == 0) cnt[i] = frow ? mine : 1;
+}
+
+// The weights, summed exactly as the oracle does: a_ii, then the weak couplings
+// outside the set in row order (every lane of the group adds the same terms,
+// broadcast one at a time); each set member's numerator starts from a_ij; for
+// every strong F-neighbour k in row order, d_k (row k's negative couplings to
+// the set and to i, in row order) is formed the same way, then the lanes add
+// (a_ik a_kl) / d_k to the numerators of the distinct columns l of row k (or
+// to the diagonal for l = i; d_k = 0 lumps a_ik into the diagonal).  The row is
+// written in column order (rank among its keys), w_ij = -num_j / atilde_ii.
+template <int G, int CAP>
+__global__ __launch_bounds__(TPB) void k_interp_ext_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                         const double* __restrict__ v,
+                                                         const unsigned char* __restrict__ strong,
+                                                         const int* __restrict__ cf, const int* __restrict__ cidx,
+                                                         const int* __restrict__ label, const int* __restrict__ prp,
+                                                         int* __restrict__ pci, double* __restrict__ pv,
+                                                         int* __restrict__ flag) {
+    constexpr int NG = TPB / G, PER = CAP / G;
+    __shared__ int keys[NG][CAP];
+    __shared__ double vals[NG][CAP];
+    Grp<G> g;
+    const int grp = threadIdx.x / G;
+    const int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    const bool valid = i < n;
+    if (valid && cf[i] == 1 && g.gl == 0) {
+        pci[prp[i]] = cidx[i];
+        pv[prp[i]] = 1.0;
+    }
+    const bool frow = valid && cf[i] != 1 && prp[i + 1] > prp[i];
+    int* K = keys[grp];
+    double* Vs = vals[grp];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        K[g.gl + G * u] = -1;
+        Vs[g.gl + G * u] = 0.0;
+    }
+    const int p0 = valid ? rp[i] : 0, len = frow ? rp[i + 1] - p0 : 0;
+    const int maxlen = wave_max_int(len);
+    ext_gather_set<G, CAP>(g, p0, len, maxlen, rp, ci, strong, cf, K, flag);
+    const int li = (frow && label) ? label[i] : 0;
+    double aii = 0.0;
+    for (int base = 0; base < maxlen; base += G) {
+        const int q = base + g.gl;
+        const bool isd = q < len && ci[p0 + q] == i;
+        const double a = isd ? v[p0 + q] : 0.0;
+        const unsigned long long m = g.bits(isd);
+        const double at = __shfl(a, g.gbase + (m ? __ffsll((unsigned long long)m) - 1 : 0), WAVE);
+        if (m) aii = at;
+    }
+    double atil = aii;
+    for (int base = 0; base < maxlen; base += G) {
+        const int q = base + g.gl;
+        const bool act = q < len;
+        const int j = act ? ci[p0 + q] : i;
+        const double a = act ? v[p0 + q] : 0.0;
+        bool weak = false;
+        if (act && j != i && !(label && label[j] != li)) {
+            const int h = ext_find<CAP>(K, j);
+            if (h >= 0) Vs[h] = a;
+            else weak = !strong[p0 + q];
+        }
+        const int lim = min(G, maxlen - base);
+        for (int t = 0; t < lim; ++t) {
+            const double x = __shfl(a, g.gbase + t, WAVE);
+            const int wk = __shfl((int)weak, g.gbase + t, WAVE);
+            if (wk) atil = atil + x;
+        }
+    }
+    for (int base = 0; base < maxlen; base += G) {
+        const int q = base + g.gl;
+        const bool act = q < len;
+        const int k = act ? ci[p0 + q] : 0;
+        const bool isf = act && strong[p0 + q] && cf[k] != 1;
+        const double aik = isf ? v[p0 + q] : 0.0;
+        int kb0 = 0, kb1 = 0;
+        if (isf) {
+            kb0 = rp[k];
+            kb1 = rp[k + 1];
+        }
+        const int lim = min(G, maxlen - base);
+        for (int t = 0; t < lim; ++t) {
+            const int src = g.gbase + t;
+            const int ft = __shfl((int)isf, src, WAVE);
+            const int kt = __shfl(k, src, WAVE);
+            const double at = __shfl(aik, src, WAVE);
+            const int b0 = __shfl(kb0, src, WAVE), b1 = __shfl(kb1, src, WAVE);
+            const int kmax = wave_max_int(b1 - b0);
+            double d = 0.0;
+            for (int kb = 0; kb < kmax; kb += G) {
+                const int r = b0 + kb + g.gl;
+                bool mem = false;
+                double a2 = 0.0;
+                if (r < b1) {
+                    const int l = ci[r];
+                    a2 = v[r];
+                    if (a2 < 0.0 && l != kt) mem = (l == i) || ext_find<CAP>(K, l) >= 0;
+                }
+                const int lim2 = min(G, kmax - kb);
+                for (int u = 0; u < lim2; ++u) {
+                    const double x = __shfl(a2, g.gbase + u, WAVE);
+                    const int mu = __shfl((int)mem, g.gbase + u, WAVE);
+                    if (mu) d = d + x;
+                }
+            }
+            double dterm = 0.0;
+            bool dhas = false;
+            if (ft && d != 0.0) {
+                for (int r = b0 + g.gl; r < b1; r += G) {
+                    const int l = ci[r];
+                    const double a2 = v[r];
+                    if (!(a2 < 0.0) || l == kt) continue;
+                    if (l == i) {
+                        dterm = (at * a2) / d;
+                        dhas = true;
+                    } else {
+                        const int h = ext_find<CAP>(K, l);
+                        if (h >= 0) Vs[h] = Vs[h] + (at * a2) / d;
+                    }
+                }
+            }
+            const unsigned long long dm = g.bits(dhas);
+            const double dv = __shfl(dterm, g.gbase + (dm ? __ffsll((unsigned long long)dm) - 1 : 0), WAVE);
+            if (ft) {
+                if (d == 0.0) atil = atil + at;
+                else if (dm) atil = atil + dv;
+            }
+        }
+    }
+    if (frow && g.gl == 0 && !(atil > 0.0)) set_flag(flag, 6);
+    // gather the filled slots, place them after those of the lanes before
+    int kk[PER];
+    double vv[PER];
+    int mine = 0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        kk[u] = K[g.gl + G * u];
+        vv[u] = Vs[g.gl + G * u];
+        mine += (kk[u] >= 0) ? 1 : 0;
+    }
+    int incl = mine;
+    for (int off = 1; off < G; off <<= 1) {
+        int t = __shfl_up(incl, off, G);
+        if (g.gl >= off) incl += t;
+    }
+    const int L = __shfl(incl, g.gbase + G - 1, WAVE);
+    int pos = incl - mine;
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+        if (kk[u] >= 0) {
+            K[pos] = kk[u];
+            Vs[pos] = vv[u];
+            ++pos;
+        }
+    if (frow) {
+        const int o = prp[i];
+        for (int e = g.gl; e < L; e += G) {
+            const int key = K[e];
+            int rank = 0;
+            for (int f = 0; f < L; ++f) rank += (K[f] < key) ? 1 : 0;
+            pci[o + rank] = cidx[key];
+            pv[o + rank] = -Vs[e] / atil;
+        }
+    }
+}
+
 template <int G>
 __global__ __launch_bounds__(TPB) void k_l1_dinv_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                    const double* __restrict__ v, double* __restrict__ dinv,
@@ -2498,6 +2749,37 @@ void interp_fill(const DCsr& A, const unsigned char* strong, const int* cf, cons
         k_interp_fill_blk<<<A.nblk, TPB, 0, s>>>(A.blk.p, A.rp.p, A.ci.p, A.v.p, strong, cf, cidx, label, P.rp.p,
                                                  P.ci.p, P.v.p, flag);
     }
+    MGR_LAUNCH_CHECK();
+}
+
+void interp_ext_count(const DCsr& A, const unsigned char* strong, const int* cf, int* cnt, int* flag, hipStream_t s) {
+    if (A.nr <= 0) return;
+    if (A.max_row <= 16)
+        k_interp_ext_count<16><<<grid_for(A.nr, 16), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, strong, cf, cnt, flag);
+    else
+        k_interp_ext_count<32><<<grid_for(A.nr, 32), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, strong, cf, cnt, flag);
+    MGR_LAUNCH_CHECK();
+}
+
+void interp_ext_fill(const DCsr& A, const unsigned char* strong, const int* cf, const int* cidx, const int* label,
+                     DCsr& P, int* flag, hipStream_t s) {
+    if (A.nr <= 0) return;
+    if (P.max_row > INTERP_EXT_COUNT_CAP / 2)
+        throw Error(-6, "extended+i interpolation: an interpolatory set exceeds 256 points");
+    int cap = 64;
+    while (cap < 2 * P.max_row) cap <<= 1;
+    // 48 KB of LDS per workgroup at most: 16 rows of 256 slots or 8 of 512
+    const bool g32 = A.max_row > 16 || cap == 512;
+#define MGR_EXT_FILL(GG, CC)                                                                                     \
+    k_interp_ext_fill<GG, CC><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, strong, cf, cidx, \
+                                                                label, P.rp.p, P.ci.p, P.v.p, flag)
+    switch (cap) {
+        case 64: if (g32) MGR_EXT_FILL(32, 64); else MGR_EXT_FILL(16, 64); break;
+        case 128: if (g32) MGR_EXT_FILL(32, 128); else MGR_EXT_FILL(16, 128); break;
+        case 256: if (g32) MGR_EXT_FILL(32, 256); else MGR_EXT_FILL(16, 256); break;
+        default: MGR_EXT_FILL(32, 512); break;
+    }
+#undef MGR_EXT_FILL
     MGR_LAUNCH_CHECK();
 }
 

@@ -97,6 +97,12 @@ void interp_count(const DCsr& A, const unsigned char* strong, const int* cf, int
 // needs A's CSR-stream row blocks (one workgroup each)
 void interp_fill(const DCsr& A, const unsigned char* strong, const int* cf, const int* cidx, const int* label,
                  DCsr& P, int* flag, hipStream_t s);
+// Extended+i interpolation: the row counts of P (the size of each F-point's
+// interpolatory set; *flag set where one exceeds the table), then the weights
+// (P's row pointers and max_row from the counts; max_row <= 256)
+void interp_ext_count(const DCsr& A, const unsigned char* strong, const int* cf, int* cnt, int* flag, hipStream_t s);
+void interp_ext_fill(const DCsr& A, const unsigned char* strong, const int* cf, const int* cidx, const int* label,
+                     DCsr& P, int* flag, hipStream_t s);
 void l1_dinv(const DCsr& A, double* dinv, int* flag, hipStream_t s);
 // Composed operators of one L1-Jacobi V(1,1) level (b_c = G b, x = W b + Q x_c):
 // w = 2 D^-1 - D^-1 A D^-1 on A's pattern; out = X - S Y on Y's pattern with

@@ -399,7 +399,8 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
             cf_is_c(n, cf.p, isC.p, s);
             sc = S.take(2);
             scan_async(isC.p, cidx.p, n, sc, s);
-            interp_count(A, strong.p, cf.p, pcnt.p, s);
+            if (o.interp == MGR_INTERP_EXT_I) interp_ext_count(A, strong.p, cf.p, pcnt.p, S.flag(), s);
+            else interp_count(A, strong.p, cf.p, pcnt.p, s);
             pp = csr_begin(P, n, 0, pcnt.p, S);
             S.sync("PMIS");
             if ((S.val(und) & 0xffffffffLL) == 0) break;
@@ -409,7 +410,8 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
         P.nc = (int)nc;
         csr_finish(pp, S);
         ensure_rowblocks(A);
-        interp_fill(A, strong.p, cf.p, cidx.p, L.label.p, P, S.flag(), s);
+        if (o.interp == MGR_INTERP_EXT_I) interp_ext_fill(A, strong.p, cf.p, cidx.p, L.label.p, P, S.flag(), s);
+        else interp_fill(A, strong.p, cf.p, cidx.p, L.label.p, P, S.flag(), s);
         // R = P^T and A P, then P^T (A P)
         DCsr R, AP, Ac;
         Transp tr = csr_transpose_begin(P, R, S);
@@ -1737,6 +1739,7 @@ void mgr_default_opts(mgr_opts* o) {
     o->amg.nu_pre = 1;
     o->amg.nu_post = 1;
     o->amg.unknown_based = 0;
+    o->amg.interp = MGR_INTERP_DIRECT;
     o->amg.seed = 12345;
 }
 
@@ -1744,6 +1747,7 @@ static int check_opts(const mgr_opts* o) {
     if (o->apply_precision != 32 && o->apply_precision != 64) return MGR_ERR_ARG;
     if (o->restart < 1 || o->restart > 63 || o->maxiter < 1 || !(o->rtol >= 0.0)) return MGR_ERR_ARG;
     if (o->amg.max_levels < 1 || o->amg.max_coarse < 1 || o->amg.nu_pre < 0 || o->amg.nu_post < 0) return MGR_ERR_ARG;
+    if (o->amg.interp != MGR_INTERP_DIRECT && o->amg.interp != MGR_INTERP_EXT_I) return MGR_ERR_ARG;
     return MGR_OK;
 }
 

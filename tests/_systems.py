@@ -52,7 +52,7 @@ def _opts(s, kw):
 def oracle_mgr(s, levels=None, **kw):
     lv = [O.LevelOpts(**l) for l in (levels if levels is not None else s["levels"])]
     kw = {k: v for k, v in _opts(s, kw).items() if k in ("theta", "max_levels", "max_coarse", "nu_pre", "nu_post",
-                                                         "coarse_unknown_based", "seed")}
+                                                         "coarse_unknown_based", "seed", "interp")}
     m = O.MGR(s["b"], s["rp"], s["ci"], s["vals"], s["field"], lv, **kw)
     assert m.status == 0, m.status
     return m

@@ -240,6 +240,96 @@ def test_direct_interp_preserves_constants_on_zero_row_sum():
         assert p.rp[i + 1] - p.rp[i] == 1 and p.v[p.rp[i]] == 1.0
 
 
+# --------------------------------------------------------------------------- extended+i interpolation
+def test_ext_interp_is_linear_interpolation_across_two_f_points():
+    # 1-D Laplacian with the split C F F C F F C: every F-point has one strong
+    # C-neighbour and one strong F-neighbour, whose other C-neighbour joins the
+    # interpolatory set; extended+i then reproduces linear interpolation
+    # (weights 2/3 and 1/3), which direct interpolation cannot (one C-point)
+    n = 7
+    a = lap1d(n)
+    a.sort_indices()
+    cf = np.array([1, -1, -1, 1, -1, -1, 1], np.int32)
+    strong = O.strength(a, 0.25)
+    p, st = O.ext_interp(a, strong, cf)
+    assert st == 0
+    expect = np.zeros((n, 3))
+    expect[[0, 3, 6], [0, 1, 2]] = 1.0
+    expect[1, :2] = [2 / 3, 1 / 3]
+    expect[2, :2] = [1 / 3, 2 / 3]
+    expect[4, 1:] = [2 / 3, 1 / 3]
+    expect[5, 1:] = [1 / 3, 2 / 3]
+    np.testing.assert_allclose(p.to_scipy().toarray(), expect, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_ext_interp_preserves_constants_on_zero_row_sum(seed):
+    # graph Laplacian (random positive weights on a 2-D grid with diagonals):
+    # with zero row sums the weights of every F-row add up to one
+    rng = np.random.default_rng(seed)
+    nx = 12
+    idx = np.arange(nx * nx).reshape(nx, nx)
+    pairs = [(idx[:, :-1], idx[:, 1:]), (idx[:-1, :], idx[1:, :]), (idx[:-1, :-1], idx[1:, 1:])]
+    r = np.concatenate([u.ravel() for u, _ in pairs]); c = np.concatenate([v.ravel() for _, v in pairs])
+    w = rng.uniform(0.1, 2.0, len(r))
+    W_ = sp.coo_matrix((np.r_[w, w], (np.r_[r, c], np.r_[c, r])), shape=(nx * nx,) * 2).tocsr()
+    a = (sp.diags(np.asarray(W_.sum(axis=1)).ravel()) - W_).tocsr()
+    a.sort_indices()
+    strong = O.strength(a, 0.25)
+    cf, _ = O.pmis(a, strong, 3)
+    p, st = O.ext_interp(a, strong, cf)
+    assert st == 0
+    ps = p.to_scipy()
+    has = np.diff(p.rp) > 0
+    np.testing.assert_allclose((ps @ np.ones(ps.shape[1]))[has], 1.0, rtol=1e-13)
+    # the interpolatory set reaches distance two: some F-row interpolates from
+    # a C-point that is not its neighbour
+    nb = a.copy(); nb.data[:] = 1.0
+    cols = np.where(cf == 1)[0]
+    reach = (ps.toarray() != 0) & (nb.toarray()[:, cols] == 0)
+    assert reach[cf != 1].any()
+
+
+def test_ext_interp_equals_direct_where_all_neighbours_are_strong_c():
+    # F-rows whose every off-diagonal coupling is negative and strong to a
+    # C-point have F_i^s empty and nothing to lump: both formulas give
+    # -a_ij / a_ii, to the last bit
+    rng = np.random.default_rng(4)
+    n = 41
+    off = -rng.uniform(0.5, 1.5, n - 1)
+    a = sp.diags([off, 2.5 + rng.uniform(0, 1, n), off * rng.uniform(0.8, 1.2, n - 1)], [-1, 0, 1]).tocsr()
+    a.sort_indices()
+    cf = np.where(np.arange(n) % 2 == 0, 1, -1).astype(np.int32)
+    strong = O.strength(a, 0.25)
+    pe, st = O.ext_interp(a, strong, cf)
+    pd, st2 = O.direct_interp(a, strong, cf)
+    assert st == 0 and st2 == 0
+    assert np.array_equal(pe.rp, pd.rp) and np.array_equal(pe.ci, pd.ci) and np.array_equal(pe.v, pd.v)
+
+
+def test_ext_interp_two_grid_and_fgmres_on_laplacians():
+    # AMG with extended+i on the 2-D Laplacian behind a trivial MGR level:
+    # FGMRES reaches 1e-10 quickly and agrees with a dense solve
+    L = lap2d(24)
+    A = sp.block_diag([sp.identity(3) * 2.0, L]).tocsr()
+    A.sort_indices()
+    n = A.shape[0]
+    field = np.array([1] * 3 + [0] * (n - 3), np.int32)
+    s = dict(b=1, rp=A.indptr.astype(np.int32), ci=A.indices.astype(np.int32), vals=A.data.copy(),
+             field=field, n=n)
+    lv = [dict(fmask=1 << 1, frelax="jacobi", sweeps=1, omega=1.0, restrict="injection",
+               amg_unknown_based=False)]
+    b = np.random.default_rng(2).standard_normal(n)
+    its = {}
+    for interp in ("direct", "ext+i"):
+        m = build(s, levels=lv, max_coarse=16, interp=interp)
+        x, info = m.solve(b, rtol=1e-10)
+        assert info.status == 0
+        np.testing.assert_allclose(x, np.linalg.solve(A.toarray(), b), rtol=1e-8, atol=1e-9)
+        its[interp] = info.iterations
+    assert its["ext+i"] <= its["direct"]
+
+
 # --------------------------------------------------------------------------- whole MGR: exactness pins
 def small_mimetic(n=3, consistent=True, upwind=True, seed=5):
     return W.hybrid_mimetic(n, n, n, seed=seed, consistent=consistent, upwind=upwind)
