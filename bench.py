@@ -369,7 +369,7 @@ def main():
             "apply_ms_fp32": round(1e3 * t_ap32, 4),
             "speedup_per_apply": round(t_ap64 / t_ap32, 4),
         },
-        "roofline": {"kernel": "k_spmv_stream<double, 1, SpmvOp> (FGMRES matvec y = A x, CSR, FP64, "
+        "roofline": {"kernel": "k_spmv_ell<double, 1, SpmvOp> (FGMRES matvec y = A x, sliced ELL copy of the CSR, FP64, "
                                f"{nnz_op} entries)",
                      "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -27,6 +27,10 @@ struct SpOp {
     const T* v = nullptr;
     const int* blk = nullptr;  // row-block boundaries (nblk + 1)
     int nblk = 0;
+    const int* eci = nullptr;  // sliced ELL copy, if any (see DCsr)
+    const int* esw = nullptr;
+    const T* ev = nullptr;
+    int ew = 0;
 };
 
 // number of row blocks of an operator with nnz entries, and their boundaries
@@ -35,8 +39,69 @@ void rowblocks(int nr, long nnz, const int* rp, int* blk, hipStream_t s);
 
 template <typename T>
 inline SpOp<T> view(const DCsr& A);
-// The row-block partition of an operator is made on its first use by an SpMV
-// (on the operator's stream), so setup temporaries never pay for one.
+// Sliced ELL copies for operators of at least ELL_MIN_ROWS rows whose longest
+// row (at most ELL_MAX_W) is within 1/0.7 of the mean: one thread per row then
+// reads its slots with coalesced loads and no row pointers or LDS stage, and
+// each workgroup's slice is only as wide as its own longest row.  Whether the
+// copy pays is decided once per operator, on its first use, from the slice
+// widths (read back with a synchronisation): its slots may exceed the stored
+// entries by 15% at most (rows of very different lengths mixed within slices
+// would make the copy longer than the CSR stream it replaces).
+constexpr int ELL_MAX_W = 16;
+constexpr int ELL_MIN_ROWS = 32768;
+constexpr int ELL_SLICE = 256;   // rows per slice = threads per workgroup of the kernel
+inline bool ell_ok(const DCsr& A) {
+    return A.nc >= 1 && A.nr >= ELL_MIN_ROWS && A.max_row >= 1 && A.max_row <= ELL_MAX_W &&
+           7L * A.max_row * A.nr <= 10L * A.nnz;
+}
+// slice widths (esw, one per ELL_SLICE rows), then the slices (with eci = nullptr
+// only the values: the columns are there already)
+void ell_widths(int nr, const int* rp, int* esw, hipStream_t s);
+long ell_total_width(const int* esw, int nsl, hipStream_t s);   // sum of esw (synchronises)
+void to_ell(int nr, int nc, int w, const int* esw, const int* rp, const int* ci, const double* v, int* eci,
+            double* ev, hipStream_t s);
+void to_ell(int nr, int nc, int w, const int* esw, const int* rp, const int* ci, const float* v, int* eci,
+            float* ev, hipStream_t s);
+
+// The row-block partition of an operator (and its ELL copy, where one pays) is
+// made on its first use by an SpMV (on the operator's stream), so setup
+// temporaries never pay for one.
+inline void ensure_ell(const DCsr& A, bool fp32) {
+    if (A.ell_state < 0) return;
+    DCsr& M = const_cast<DCsr&>(A);
+    const size_t nsl = (size_t)(M.nr + ELL_SLICE - 1) / ELL_SLICE;
+    const size_t slots = (size_t)M.max_row * ELL_SLICE * nsl;
+    if (M.ell_state == 0) {
+        if (!ell_ok(M)) {
+            M.ell_state = -1;
+            return;
+        }
+        M.esw.alloc(nsl, M.rp.s);
+        ell_widths(M.nr, M.rp.p, M.esw.p, M.rp.s);
+        const long used = ell_total_width(M.esw.p, (int)nsl, M.rp.s) * ELL_SLICE;
+        if (20 * used > 23L * M.nnz) {
+            M.esw.reset();
+            M.ell_state = -1;
+            return;
+        }
+        M.ell_state = 1;
+    }
+    if (!fp32 && !M.ev.p) {
+        M.ev.alloc(slots, M.rp.s);
+        const bool need_ci = !M.eci.p;
+        if (need_ci) M.eci.alloc(slots, M.rp.s);
+        to_ell(M.nr, M.nc, M.max_row, M.esw.p, M.rp.p, M.ci.p, M.v.p, need_ci ? M.eci.p : nullptr, M.ev.p,
+               M.rp.s);
+    }
+    if (fp32 && !M.evf.p && M.vf.p) {
+        M.evf.alloc(slots, M.rp.s);
+        const bool need_ci = !M.eci.p;
+        if (need_ci) M.eci.alloc(slots, M.rp.s);
+        to_ell(M.nr, M.nc, M.max_row, M.esw.p, M.rp.p, M.ci.p, M.vf.p, need_ci ? M.eci.p : nullptr, M.evf.p,
+               M.rp.s);
+    }
+    M.ew = M.max_row;
+}
 inline void ensure_rowblocks(const DCsr& A) {
     if (A.blk.p || A.nr <= 0) return;
     DCsr& M = const_cast<DCsr&>(A);
@@ -51,6 +116,8 @@ inline SpOp<double> view<double>(const DCsr& A) {
     SpOp<double> o;
     o.nr = A.nr; o.nc = A.nc; o.nnz = A.nnz; o.rp = A.rp.p; o.ci = A.ci.p; o.v = A.v.p;
     o.blk = A.blk.p; o.nblk = A.nblk;
+    ensure_ell(A, false);
+    if (A.ev.p) { o.eci = A.eci.p; o.esw = A.esw.p; o.ev = A.ev.p; o.ew = A.ew; }
     return o;
 }
 template <>
@@ -59,6 +126,8 @@ inline SpOp<float> view<float>(const DCsr& A) {
     SpOp<float> o;
     o.nr = A.nr; o.nc = A.nc; o.nnz = A.nnz; o.rp = A.rp.p; o.ci = A.ci.p; o.v = A.vf.p;
     o.blk = A.blk.p; o.nblk = A.nblk;
+    ensure_ell(A, true);
+    if (A.evf.p) { o.eci = A.eci.p; o.esw = A.esw.p; o.ev = A.evf.p; o.ew = A.ew; }
     return o;
 }
 

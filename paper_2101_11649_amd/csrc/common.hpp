@@ -138,6 +138,15 @@ struct DCsr {
     DArr<float> vf;
     DArr<int> blk;   // row-block boundaries of the CSR-stream SpMV
     int nblk = 0;
+    // sliced ELL copy for SpMVs on operators with short, fairly uniform rows:
+    // slices of one workgroup's rows, each slot-major with the slice's own
+    // width (esw, in slots) and a fixed stride of ew slots per row; ew = the
+    // longest row (0 = no copy)
+    DArr<int> eci, esw;
+    DArr<double> ev;
+    DArr<float> evf;
+    int ew = 0;
+    int ell_state = 0;   // 0 = not decided, 1 = the copy pays, -1 = it does not
     int max_row = -1;  // longest row (-1 = not known yet)
     bool empty() const { return nr == 0 && nnz == 0; }
     void alloc(int rows, int cols, long nz, hipStream_t s) {
@@ -150,6 +159,12 @@ struct DCsr {
         vf.reset();
         blk.reset();
         nblk = 0;
+        eci.reset();
+        esw.reset();
+        ev.reset();
+        evf.reset();
+        ew = 0;
+        ell_state = 0;
         max_row = -1;
     }
 };

@@ -533,6 +533,122 @@ int pick_group(double avg) {
         default: { constexpr int GG = 64; __VA_ARGS__; } break; \
     }
 
+static_assert(ELL_SLICE == TPB, "an ELL slice is one workgroup's rows");
+
+// One thread per row over the operator's sliced ELL copy: the workgroup's
+// slice holds its rows slot-major (slot k of row r at base + k TPB + r % TPB,
+// base = slice * w * TPB) up to the slice's width; every slot's column and
+// value come in with coalesced loads, all of them before the first gather, and
+// the products are summed in row order (padding slots hold zero values and the
+// row's own column, or column 0 beyond the last column).
+template <typename MT, int TAG, class Op>
+__global__ __launch_bounds__(TPB) void k_spmv_ell(int nr, int w, const int* __restrict__ esw,
+                                                  const int* __restrict__ eci, const MT* __restrict__ ev, Op op) {
+    const int r = blockIdx.x * TPB + threadIdx.x;
+    const int sw = min(esw[blockIdx.x], w);
+    if (r >= nr) return;
+    const long base = (long)blockIdx.x * w * TPB + threadIdx.x;
+    int c[ELL_MAX_W];
+    MT a[ELL_MAX_W];
+#pragma unroll
+    for (int k = 0; k < ELL_MAX_W; ++k)
+        if (k < sw) {
+            c[k] = eci[base + (long)k * TPB];
+            a[k] = ev[base + (long)k * TPB];
+        }
+    MT s = MT(0);
+#pragma unroll
+    for (int k = 0; k < ELL_MAX_W; ++k)
+        if (k < sw) s += a[k] * op.xval(c[k]);
+    op.done(r, s);
+}
+
+// esw[slice] = the longest row of the slice's TPB rows
+__global__ __launch_bounds__(TPB) void k_ell_widths(int nr, const int* __restrict__ rp, int* __restrict__ esw) {
+    __shared__ int red[TPB / WAVE];
+    const int r = blockIdx.x * TPB + threadIdx.x;
+    int len = r < nr ? rp[r + 1] - rp[r] : 0;
+    for (int off = WAVE / 2; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, WAVE));
+    if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = len;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int m = 0;
+        for (int q = 0; q < TPB / WAVE; ++q) m = max(m, red[q]);
+        esw[blockIdx.x] = m;
+    }
+}
+
+template <typename MT>
+__global__ __launch_bounds__(TPB) void k_to_ell(int nr, int nc, int w, const int* __restrict__ esw,
+                                                const int* __restrict__ rp, const int* __restrict__ ci,
+                                                const MT* __restrict__ v, int* __restrict__ eci,
+                                                MT* __restrict__ ev) {
+    const int r = blockIdx.x * TPB + threadIdx.x;
+    if (r >= nr) return;
+    const int sw = min(esw[blockIdx.x], w);
+    const long base = (long)blockIdx.x * w * TPB + threadIdx.x;
+    const int p0 = rp[r], len = rp[r + 1] - p0;
+    for (int k = 0; k < sw; ++k) {
+        const bool in = k < len;
+        if (eci) eci[base + (long)k * TPB] = in ? ci[p0 + k] : (r < nc ? r : 0);
+        ev[base + (long)k * TPB] = in ? v[p0 + k] : MT(0);
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_sum_widths(const int* __restrict__ esw, int nsl, long long* __restrict__ out) {
+    __shared__ long long red[TPB / WAVE];
+    long long t = 0;
+    for (int q = threadIdx.x; q < nsl; q += TPB) t += esw[q];
+    for (int off = WAVE / 2; off > 0; off >>= 1) t += __shfl_xor(t, off, WAVE);
+    if ((threadIdx.x & (WAVE - 1)) == 0) red[threadIdx.x / WAVE] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long m = 0;
+        for (int q = 0; q < TPB / WAVE; ++q) m += red[q];
+        *out = m;
+    }
+}
+
+long ell_total_width(const int* esw, int nsl, hipStream_t s) {
+    if (nsl <= 0) return 0;
+    DArr<long long> d(1, s);
+    k_sum_widths<<<1, TPB, 0, s>>>(esw, nsl, d.p);
+    MGR_LAUNCH_CHECK();
+    long long h = 0;
+    MGR_HIP(hipMemcpyAsync(&h, d.p, sizeof(long long), hipMemcpyDeviceToHost, s));
+    MGR_HIP(hipStreamSynchronize(s));
+    return (long)h;
+}
+
+void ell_widths(int nr, const int* rp, int* esw, hipStream_t s) {
+    if (nr <= 0) return;
+    k_ell_widths<<<nblk(nr), TPB, 0, s>>>(nr, rp, esw);
+    MGR_LAUNCH_CHECK();
+}
+
+void to_ell(int nr, int nc, int w, const int* esw, const int* rp, const int* ci, const double* v, int* eci,
+            double* ev, hipStream_t s) {
+    if (nr <= 0) return;
+    k_to_ell<double><<<nblk(nr), TPB, 0, s>>>(nr, nc, w, esw, rp, ci, v, eci, ev);
+    MGR_LAUNCH_CHECK();
+}
+
+void to_ell(int nr, int nc, int w, const int* esw, const int* rp, const int* ci, const float* v, int* eci,
+            float* ev, hipStream_t s) {
+    if (nr <= 0) return;
+    k_to_ell<float><<<nblk(nr), TPB, 0, s>>>(nr, nc, w, esw, rp, ci, v, eci, ev);
+    MGR_LAUNCH_CHECK();
+}
+
+// the sliced ELL kernel where the operator has that copy, else the CSR stream
+template <typename MT, int TAG, class Op>
+static void launch_rows(const SpOp<MT>& A, const Op& op, hipStream_t s) {
+    if (A.ew > 0 && A.eci && A.ev && A.esw)
+        k_spmv_ell<MT, TAG, Op><<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.ew, A.esw, A.eci, A.ev, op);
+    else
+        k_spmv_stream<MT, TAG><<<A.nblk, TPB, 0, s>>>(A.blk, A.rp, A.ci, A.v, op);
+}
+
 int rowblock_count(int nr, long nnz) {
     long cost = nnz + (long)nr / SPMV_ROW_COST;
     return cost > 0 ? (int)((cost + SPMV_CHUNK - 1) / SPMV_CHUNK) : 1;
@@ -551,9 +667,9 @@ void spmv(const SpOp<MT>& A, const XT* x, const X2T* x2, int split, const WT* w,
     if (!A.blk) throw Error(-1, "spmv: operator without row blocks");
     SpmvOp<MT, XT, X2T, YT, WT> op{x, x2, split, w, y, alpha, beta};
     if (tag == 1)
-        k_spmv_stream<MT, 1><<<A.nblk, TPB, 0, s>>>(A.blk, A.rp, A.ci, A.v, op);
+        launch_rows<MT, 1>(A, op, s);
     else
-        k_spmv_stream<MT, 0><<<A.nblk, TPB, 0, s>>>(A.blk, A.rp, A.ci, A.v, op);
+        launch_rows<MT, 0>(A, op, s);
     MGR_LAUNCH_CHECK();
 }
 
@@ -561,7 +677,7 @@ template <typename T>
 void jacobi_sweep(const SpOp<T>& A, const T* dinv, const T* b, const T* x, T* y, hipStream_t s) {
     if (A.nr <= 0) return;
     JacobiOp<T> op{dinv, b, x, y};
-    k_spmv_stream<T, 0><<<A.nblk, TPB, 0, s>>>(A.blk, A.rp, A.ci, A.v, op);
+    launch_rows<T, 0>(A, op, s);
     MGR_LAUNCH_CHECK();
 }
 
@@ -569,7 +685,7 @@ template <typename T>
 void presmooth(const SpOp<T>& A, const T* dinv, const T* b, T* x, T* r, hipStream_t s) {
     if (A.nr <= 0) return;
     PreOp<T> op{dinv, b, x, r};
-    k_spmv_stream<T, 0><<<A.nblk, TPB, 0, s>>>(A.blk, A.rp, A.ci, A.v, op);
+    launch_rows<T, 0>(A, op, s);
     MGR_LAUNCH_CHECK();
 }
 
@@ -578,7 +694,7 @@ void presmooth_scaled(const SpOp<T>& A, const T* bd, const T* b, T* x, T* r, hip
     if (A.nr <= 0) return;
     if (!A.blk) throw Error(-1, "presmooth: operator without row blocks");
     PreOpD<T> op{bd, b, x, r};
-    k_spmv_stream<T, 0><<<A.nblk, TPB, 0, s>>>(A.blk, A.rp, A.ci, A.v, op);
+    launch_rows<T, 0>(A, op, s);
     MGR_LAUNCH_CHECK();
 }
 
@@ -587,7 +703,7 @@ void restrict_scaled(const SpOp<T>& A, const XT* x, const T* dsc, T* y, T* yd, h
     if (A.nr <= 0) return;
     if (!A.blk) throw Error(-1, "restrict: operator without row blocks");
     RestrictOp<T, XT> op{x, dsc, y, yd};
-    k_spmv_stream<T, 0><<<A.nblk, TPB, 0, s>>>(A.blk, A.rp, A.ci, A.v, op);
+    launch_rows<T, 0>(A, op, s);
     MGR_LAUNCH_CHECK();
 }
 
