@@ -1484,6 +1484,58 @@ static int fgmres(Ctx& c, bool tr, const double* b, double* x, mgr_solve_info* i
     return inf.status;
 }
 
+// Whether a sliced ELL copy pays (see ensure_ell) is decided here for the
+// operators of the apply and of the FGMRES matvec, with one sync for all of
+// them instead of one per operator on its first use inside a solve; the copies
+// themselves are made on first use (no sync).
+static void prepare_ell(Ctx& c) {
+    std::vector<const DCsr*> ops;
+    auto add = [&](const DCsr& A) {
+        if (A.ell_state == 0 && ell_ok(A)) ops.push_back(&A);
+    };
+    auto add_amg = [&](const Amg& H) {
+        for (const auto& L : H.lv) {
+            add(L.A);
+            add(L.P);
+            add(L.R);
+        }
+    };
+    if (c.b == 1) add(c.A0);
+    for (const auto& l : c.L) {
+        add(l.RJ);
+        add(l.PJ);
+        if (l.famg) add_amg(*l.famg);
+    }
+    add_amg(c.camg);
+    Slots& S = c.slots;
+    constexpr size_t BATCH = 24;   // two slots each
+    for (size_t i0 = 0; i0 < ops.size(); i0 += BATCH) {
+        const size_t i1 = std::min(ops.size(), i0 + BATCH);
+        std::vector<long long*> slot(i1 - i0);
+        std::vector<DArr<int>> tmp(i1 - i0);
+        for (size_t i = i0; i < i1; ++i) {
+            DCsr& M = const_cast<DCsr&>(*ops[i]);
+            const int nsl = (M.nr + ELL_SLICE - 1) / ELL_SLICE;
+            M.esw.alloc((size_t)nsl, c.s);
+            ell_widths(M.nr, M.rp.p, M.esw.p, c.s);
+            tmp[i - i0].alloc((size_t)nsl + 1, c.s);
+            slot[i - i0] = S.take(2);
+            scan_async(M.esw.p, tmp[i - i0].p, nsl, slot[i - i0], c.s);
+        }
+        S.sync("sliced ELL widths");
+        for (size_t i = i0; i < i1; ++i) {
+            DCsr& M = const_cast<DCsr&>(*ops[i]);
+            const long used = (long)S.val(slot[i - i0]) * ELL_SLICE;
+            if (20 * used > 23L * M.nnz) {
+                M.esw.reset();
+                M.ell_state = -1;
+            } else {
+                M.ell_state = 1;
+            }
+        }
+    }
+}
+
 // ====================================================================== setup
 static void build_hierarchy(Ctx& c);
 
@@ -1592,6 +1644,7 @@ static void build_hierarchy(Ctx& c) {
         for (auto& l : c.L) mgr_level_make_float(c, l);
         amg_make_float(c.camg, s);
     }
+    prepare_ell(c);
     MGR_HIP(hipStreamSynchronize(s));
     c.ready = true;
 }
