@@ -43,13 +43,33 @@ def test_default_opts_without_gpu():
     assert o.amg.theta == 0.25 and o.amg.max_coarse == 128 and o.amg.seed == 12345
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    # compile a probe against include/mgr.h and compare every field's offset
+    # and every struct's size with the ctypes binding
+    import shutil
+    import subprocess
     import paper_2101_11649_amd as P
-    assert ctypes.sizeof(P.mgr_matrix) == 32
-    assert ctypes.sizeof(P.mgr_level_opts) == 32
-    assert ctypes.sizeof(P.mgr_amg_opts) == 40
-    assert ctypes.sizeof(P.mgr_opts) == 72
-    assert ctypes.sizeof(P.mgr_solve_info) == 32
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    structs = [P.mgr_matrix, P.mgr_level_opts, P.mgr_amg_opts, P.mgr_opts, P.mgr_solve_info]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mgr.h"', 'int main(void) {']
+    for st in structs:
+        name = st.__name__
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for f, _ in st._fields_:
+            lines.append(f'  printf("{name} {f} %zu\\n", offsetof({name}, {f}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {" ".join(l.split()[:-1]): int(l.split()[-1]) for l in out if l.strip()}
+    for st in structs:
+        name = st.__name__
+        assert got[f"{name} size"] == ctypes.sizeof(st), name
+        for f, _ in st._fields_:
+            assert got[f"{name} {f}"] == getattr(st, f).offset, (name, f)
 
 
 def test_no_cpu_fallback():

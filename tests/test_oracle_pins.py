@@ -307,6 +307,44 @@ def test_ext_interp_equals_direct_where_all_neighbours_are_strong_c():
     assert np.array_equal(pe.rp, pd.rp) and np.array_equal(pe.ci, pd.ci) and np.array_equal(pe.v, pd.v)
 
 
+def test_ext_interp_with_labels_ignores_other_labels():
+    # two 1-D Laplacians interleaved (label 0 on even rows, 1 on odd rows) with
+    # weak cross-label couplings: with labels, the strength, the interpolatory
+    # sets and every sum of extended+i ignore the other label, so each label's
+    # weights are those of its own Laplacian on its own
+    rng = np.random.default_rng(6)
+    m = 20
+    parts = [lap1d(m).tolil(), lap1d(m).tolil()]
+    for q in parts:
+        for i in range(m):
+            q[i, i] = 2.0 + rng.uniform(0.0, 0.2)
+    n = 2 * m
+    a = sp.lil_matrix((n, n))
+    for lab in (0, 1):
+        q = parts[lab].tocoo()
+        a[2 * q.row + lab, 2 * q.col + lab] = q.data
+    for i in range(m):                       # cross-label couplings, either sign
+        a[2 * i, 2 * i + 1] = rng.uniform(-0.3, 0.3)
+        a[2 * i + 1, 2 * i] = rng.uniform(-0.3, 0.3)
+    a = a.tocsr(); a.sort_indices()
+    label = np.arange(n) % 2
+    cf1 = np.array([1 if i % 3 == 0 or i == m - 1 else -1 for i in range(m)], np.int32)
+    cf = np.repeat(cf1, 2)                   # the same split on both labels
+    p, st = O.ext_interp(a, O.strength(a, 0.25, label), cf, label)
+    assert st == 0
+    pd = p.to_scipy().toarray()
+    for lab in (0, 1):
+        q = parts[lab].tocsr(); q.sort_indices()
+        ps, st2 = O.ext_interp(q, O.strength(q, 0.25), cf1)
+        assert st2 == 0
+        rows = np.arange(lab, n, 2)
+        ccols = np.cumsum(cf == 1) - 1       # coarse index of each C-point
+        cols = ccols[rows[cf1 == 1]]
+        np.testing.assert_array_equal(pd[np.ix_(rows, cols)], ps.to_scipy().toarray())
+        other = np.setdiff1d(np.arange(pd.shape[1]), cols)
+        assert not pd[np.ix_(rows, other)].any()
+
+
 def test_ext_interp_two_grid_and_fgmres_on_laplacians():
     # AMG with extended+i on the 2-D Laplacian behind a trivial MGR level:
     # FGMRES reaches 1e-10 quickly and agrees with a dense solve
