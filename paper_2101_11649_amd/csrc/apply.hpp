@@ -54,6 +54,9 @@ inline bool ell_ok(const DCsr& A) {
     return A.nc >= 1 && A.nr >= ELL_MIN_ROWS && A.max_row >= 1 && A.max_row <= ELL_MAX_W &&
            7L * A.max_row * A.nr <= 10L * A.nnz;
 }
+// the copy pays when its slots (sum of the slice widths times ELL_SLICE)
+// exceed the stored entries by at most 15%
+inline bool ell_pays(long slots, long nnz) { return 20 * slots <= 23 * nnz; }
 // slice widths (esw, one per ELL_SLICE rows), then the slices (with eci = nullptr
 // only the values: the columns are there already)
 void ell_widths(int nr, const int* rp, int* esw, hipStream_t s);
@@ -79,7 +82,7 @@ inline void ensure_ell(const DCsr& A, bool fp32) {
         M.esw.alloc(nsl, M.rp.s);
         ell_widths(M.nr, M.rp.p, M.esw.p, M.rp.s);
         const long used = ell_total_width(M.esw.p, (int)nsl, M.rp.s) * ELL_SLICE;
-        if (20 * used > 23L * M.nnz) {
+        if (!ell_pays(used, M.nnz)) {
             M.esw.reset();
             M.ell_state = -1;
             return;

@@ -1526,7 +1526,7 @@ static void prepare_ell(Ctx& c) {
         for (size_t i = i0; i < i1; ++i) {
             DCsr& M = const_cast<DCsr&>(*ops[i]);
             const long used = (long)S.val(slot[i - i0]) * ELL_SLICE;
-            if (20 * used > 23L * M.nnz) {
+            if (!ell_pays(used, M.nnz)) {
                 M.esw.reset();
                 M.ell_state = -1;
             } else {
