@@ -133,9 +133,14 @@ int mgr_set_opts(mgr_handle h, const mgr_opts *o);
  * (Jacobi interpolation, eq. (4), ideal when A_FF is (block-)diagonal, eq. (3)),
  * R~ by lvl[l].restrict_type, coarse operator R~ A P~; then AMG on the last
  * coarse system.  field_of_dof: n labels in [0, 32).  lvl: (host) nlevels.
+ * The handle owns all the device memory of the hierarchy; operators with
+ * short, nearly uniform rows (at least 32768 rows of at most 16 entries) also
+ * get a sliced ELL copy for their SpMVs, made on first use, when it exceeds
+ * their entries by at most 15%.
  * Errors: ARG, BAD_LABELS (empty F or C set, label out of range), ZERO_PIVOT,
  * UNSUPPORTED (block of more than 4 F-points, a_ii <= 0 in AMG, coarsest AMG
- * level above 2048 unknowns), OOM, HIP. */
+ * level above 2048 unknowns, an extended+i interpolatory set above 256
+ * points), OOM, HIP. */
 int mgr_setup(mgr_handle h, const mgr_matrix *A, const int32_t *field_of_dof, int32_t nlevels,
               const mgr_level_opts *lvl);
 
