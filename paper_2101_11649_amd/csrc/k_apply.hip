@@ -578,20 +578,45 @@ __global__ __launch_bounds__(TPB) void k_ell_widths(int nr, const int* __restric
     }
 }
 
+// One workgroup per slice: the slice's entries (one contiguous range of the
+// CSR arrays) come into LDS with coalesced loads, then each thread writes its
+// row's slots (coalesced across the slice's rows).  A slice with more entries
+// than the stage (only if a row exceeds the recorded longest row) reads them
+// from memory instead.
 template <typename MT>
 __global__ __launch_bounds__(TPB) void k_to_ell(int nr, int nc, int w, const int* __restrict__ esw,
                                                 const int* __restrict__ rp, const int* __restrict__ ci,
                                                 const MT* __restrict__ v, int* __restrict__ eci,
                                                 MT* __restrict__ ev) {
-    const int r = blockIdx.x * TPB + threadIdx.x;
-    if (r >= nr) return;
+    __shared__ int srp[TPB + 1];
+    __shared__ int sci[ELL_MAX_W * TPB];
+    __shared__ MT sv[ELL_MAX_W * TPB];
+    const int r0 = blockIdx.x * TPB;
+    const int rows = min(TPB, nr - r0);
     const int sw = min(esw[blockIdx.x], w);
+    for (int t = threadIdx.x; t <= rows; t += TPB) srp[t] = rp[r0 + t];
+    __syncthreads();
+    const int p0 = srp[0], cnt = srp[rows] - p0;
+    const bool staged = cnt <= ELL_MAX_W * TPB;
+    if (staged)
+        for (int q = threadIdx.x; q < cnt; q += TPB) {
+            sci[q] = ci[p0 + q];
+            sv[q] = v[p0 + q];
+        }
+    __syncthreads();
+    if ((int)threadIdx.x >= rows) return;
+    const int r = r0 + threadIdx.x;
+    const int b = srp[threadIdx.x] - p0, len = srp[threadIdx.x + 1] - srp[threadIdx.x];
     const long base = (long)blockIdx.x * w * TPB + threadIdx.x;
-    const int p0 = rp[r], len = rp[r + 1] - p0;
     for (int k = 0; k < sw; ++k) {
-        const bool in = k < len;
-        if (eci) eci[base + (long)k * TPB] = in ? ci[p0 + k] : (r < nc ? r : 0);
-        ev[base + (long)k * TPB] = in ? v[p0 + k] : MT(0);
+        int c = r < nc ? r : 0;
+        MT val = MT(0);
+        if (k < len) {
+            c = staged ? sci[b + k] : ci[p0 + b + k];
+            val = staged ? sv[b + k] : v[p0 + b + k];
+        }
+        if (eci) eci[base + (long)k * TPB] = c;
+        ev[base + (long)k * TPB] = val;
     }
 }
 
