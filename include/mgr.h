@@ -145,7 +145,7 @@ int mgr_setup(mgr_handle h, const mgr_matrix *A, const int32_t *field_of_dof, in
               const mgr_level_opts *lvl);
 
 /* Setup reuse for a new matrix on the same pattern, as between the Newton
- * solves of a simulation (AMG data reuse, Sec. 3.3 and Sec. 5).  values:
+ * solves of a simulation (AMG data reuse, Sec. 3.3 and Sec. 4.4).  values:
  * device pointer, nnzb*b*b doubles in the block layout (row pointers and
  * columns) of the last mgr_setup; copied.  The MGR levels are formed again
  * from the new values.  Every AMG hierarchy keeps its C/F splits and

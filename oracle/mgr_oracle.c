@@ -241,11 +241,10 @@ static Csr csr_extract(const Csr *a, const int *rows, int nrows, const int *colm
     return c;
 }
 
-/* Expand a block-CSR matrix (b x b row-major blocks) to scalar CSR, keeping
- * every stored block entry (explicit zeros included). */
-/* Scalar CSR of a block-CSR matrix.  An exact zero inside a stored block is not
- * an entry of the operator (it contributes to no product or sum), so it is
- * left out, except on the diagonal, which is always stored. */
+/* Scalar CSR of a block-CSR matrix (b x b row-major blocks).  An exact zero
+ * inside a stored block is not an entry of the operator (it contributes to no
+ * product or sum), so it is left out, except on the diagonal, which is always
+ * stored. */
 static Csr bsr_expand(int b, int nbr, int nbc, const int *rp, const int *ci, const double *val) {
     long nnzb = rp[nbr];
     Csr a = csr_alloc(nbr * b, nbc * b, nnzb * b * b);

@@ -304,4 +304,4 @@ def solver_for(system, **kw):
     return Solver(system["b"], system["rp"], system["ci"], system["vals"], system["field"], system["levels"], **kw)
 
 
-from .autograd import MGRSolve  # noqa: E402  (needs the names above)
+from .autograd import MGRSolve, NotConvergedError  # noqa: E402  (needs the names above)

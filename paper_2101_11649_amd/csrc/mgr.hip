@@ -1649,7 +1649,7 @@ static void build_hierarchy(Ctx& c) {
     c.ready = true;
 }
 
-// Setup reuse (Sec. 3.3 and Sec. 5: AMG data reuse across Newton solves): new
+// Setup reuse (Sec. 3.3 and Sec. 4.4: AMG data reuse across Newton solves): new
 // values on the pattern of the last setup.  The MGR levels are formed again;
 // the coarse AMG keeps its C/F splits and interpolation and forms its Galerkin
 // products anew; the F-relaxation AMG hierarchies do the same, or are kept

@@ -68,3 +68,26 @@ def test_adjoint_batch_48():
         say(f"[fd] entry {p}: adjoint {g[p]:+.10e} fd {fd:+.10e} rel {err:.2e} (solve residuals {rp_:.1e}, {rm_:.1e})")
     say(f"[fd] worst relative difference {worst:.2e}")
     assert worst <= 1e-6
+
+
+def test_autograd_unconverged_raises():
+    """A forward solve cut off at maxiter raises instead of returning an
+    unconverged X (whose gradient would be wrong)."""
+    import torch
+    import paper_2101_11649_amd as P
+    s = W.two_field_tpfa(8, 8, 8, seed=0)
+    say(f"[adjoint] unconverged forward, two-field TPFA 8^3 n={s['n']}")
+    vals = torch.tensor(s["vals"], device="cuda", requires_grad=True)
+    B = torch.tensor(s["rhs"], device="cuda", requires_grad=True)
+    struct = dict(b=s["b"], rp=s["rp"], ci=s["ci"], field=s["field"], levels=s["levels"], opts=dict(maxiter=2))
+    with pytest.raises(P.NotConvergedError):
+        P.MGRSolve.apply(vals, B, struct)
+    # a retained graph differentiates twice with the same result
+    struct["opts"] = dict(rtol=1e-12)
+    X = P.MGRSolve.apply(vals, B, struct)
+    L = (X * X).sum()
+    L.backward(retain_graph=True)
+    g1 = vals.grad.clone()
+    vals.grad = None
+    L.backward()
+    assert torch.equal(vals.grad, g1)

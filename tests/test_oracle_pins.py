@@ -683,7 +683,7 @@ def test_two_grid_amg_on_1d_laplacian_converges():
     assert info.status == 0 and info.iterations < 40
 
 
-# --------------------------------------------------------------------------- setup reuse (Sec. 3.3, Sec. 5)
+# --------------------------------------------------------------------------- setup reuse (Sec. 3.3, Sec. 4.4)
 def test_reuse_with_unchanged_values_is_the_same_hierarchy():
     s = W.two_field_tpfa(7, 6, 5, seed=11)
     m = build(s)
