@@ -79,6 +79,8 @@ def lib():
         L.orc_ext_interp.argtypes = [i32, P, P, P, P, P, P, P]
         L.orc_lu_solve.argtypes = [i32, P, P, P, i32]
         L.orc_small_inverse.argtypes = [i32, P, P]
+        L.orc_ilu0.argtypes = [i32, P, P, P, P, P]
+        L.orc_ilu0_solve.argtypes = [i32, P, P, P, P, P, P, i32]
         _lib = L
     return _lib
 
@@ -210,6 +212,25 @@ def small_inverse(blk):
     inv = np.zeros((bs, bs))
     st = lib().orc_small_inverse(bs, _p(b), _p(inv))
     return inv, st
+
+
+def ilu0(a):
+    """ILU(0) of a square CSR matrix on its own pattern: (lu values on a's
+    pattern with L strictly below the diagonal (unit diagonal implied) and U on
+    and above it, positions of the diagonal entries, status)."""
+    n, _, rp, ci, v = _csr_args(a)
+    lu = np.zeros(max(len(ci), 1))
+    diag = np.zeros(n, np.int32)
+    st = lib().orc_ilu0(n, _p(rp), _p(ci), _p(v), _p(lu), _p(diag))
+    return lu[: len(ci)], diag, st
+
+
+def ilu0_solve(a, lu, diag, r, trans: bool = False):
+    """z = (LU)^{-1} r, or (LU)^{-T} r, with the factors of ilu0(a)."""
+    n, _, rp, ci, _ = _csr_args(a)
+    z = np.zeros(n)
+    lib().orc_ilu0_solve(n, _p(rp), _p(ci), _p(_f64(lu)), _p(_i32(diag)), _p(_f64(r)), _p(z), int(trans))
+    return z
 
 
 def grad_values(b: int, rp, ci, lam, x):

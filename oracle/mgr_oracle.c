@@ -1666,3 +1666,20 @@ int orc_lu_solve(int n, const double *dense, const double *b, double *x, int tra
     return st;
 }
 int orc_small_inverse(int bs, const double *blk, double *inv) { return small_inverse(bs, blk, inv); }
+/* ILU(0) factor of a square CSR matrix on its own pattern (lu: nnz values,
+ * diag: n positions of the diagonal entries) and the solves with it. */
+int orc_ilu0(int n, const int *rp, const int *ci, const double *v, double *lu, int *diag) {
+    Csr a = wrap(n, n, rp, ci, v);
+    double *f = NULL;
+    int *d = NULL;
+    int st = ilu0_factor(&a, &f, &d);
+    memcpy(lu, f, (size_t)csr_nnz(&a) * sizeof(double));
+    memcpy(diag, d, (size_t)n * sizeof(int));
+    free(f); free(d);
+    return st;
+}
+void orc_ilu0_solve(int n, const int *rp, const int *ci, const double *lu, const int *diag, const double *r,
+                    double *z, int trans) {
+    Csr a = wrap(n, n, rp, ci, NULL);
+    ilu0_solve(&a, lu, diag, r, z, trans);
+}
