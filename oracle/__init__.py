@@ -27,9 +27,11 @@ RESTRICT = {"injection": 0, "jacobi": 1}
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no contraction, no fast-math, no -march)."""
+    """Compile the oracle with gcc (no contraction, no fast-math, no -march;
+    OpenMP for the solve phase's row loops, whose results do not depend on
+    the thread count)."""
     if force or not os.path.exists(_LIB):
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fPIC", "-shared",
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-fopenmp", "-fPIC", "-shared",
                "-o", _LIB + ".tmp", _SRC, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
@@ -79,6 +81,7 @@ def lib():
         L.orc_ext_interp.argtypes = [i32, P, P, P, P, P, P, P]
         L.orc_lu_solve.argtypes = [i32, P, P, P, i32]
         L.orc_small_inverse.argtypes = [i32, P, P]
+        L.orc_set_threads.argtypes = [i32]
         L.orc_ilu0.argtypes = [i32, P, P, P, P, P]
         L.orc_ilu0_solve.argtypes = [i32, P, P, P, P, P, P, i32]
         _lib = L
@@ -212,6 +215,12 @@ def small_inverse(blk):
     inv = np.zeros((bs, bs))
     st = lib().orc_small_inverse(bs, _p(b), _p(inv))
     return inv, st
+
+
+def set_threads(n: int) -> int:
+    """Threads for the oracle's solve phase (matvec, cycles, FGMRES vector
+    work); 0 keeps the current setting.  Returns the number in use."""
+    return lib().orc_set_threads(int(n))
 
 
 def ilu0(a):

@@ -36,6 +36,9 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_OK 0
 #define ORC_NOT_CONVERGED 1
@@ -52,6 +55,12 @@
 #define FRELAX_AMG 3
 #define RESTRICT_INJECTION 0
 #define RESTRICT_JACOBI 1
+
+/* Threads: the solve phase (matvec, residuals, the MGR and AMG cycles, the
+ * FGMRES vector work) runs its row loops with OpenMP; every row or entry is
+ * still computed by one thread in the same order, and dot products use fixed
+ * chunks, so results do not depend on the thread count.  Setup is serial. */
+#define PAR_OK(n) ((n) > 4096)
 
 #define MAX_AMG_LEVELS 40
 #define MAX_MGR_LEVELS 8
@@ -101,6 +110,7 @@ static Csr csr_copy(const Csr *a) {
 
 /* y = A x, each row summed left to right. */
 static void csr_matvec(const Csr *a, const double *x, double *y) {
+    #pragma omp parallel for schedule(static) if (PAR_OK(a->nr))
     for (int i = 0; i < a->nr; ++i) {
         double s = 0.0;
         for (int p = a->rp[i]; p < a->rp[i + 1]; ++p) s += a->v[p] * x[a->ci[p]];
@@ -110,6 +120,7 @@ static void csr_matvec(const Csr *a, const double *x, double *y) {
 
 /* r = b - A x */
 static void csr_residual(const Csr *a, const double *b, const double *x, double *r) {
+    #pragma omp parallel for schedule(static) if (PAR_OK(a->nr))
     for (int i = 0; i < a->nr; ++i) {
         double s = 0.0;
         for (int p = a->rp[i]; p < a->rp[i + 1]; ++p) s += a->v[p] * x[a->ci[p]];
@@ -266,9 +277,28 @@ static Csr bsr_expand(int b, int nbr, int nbc, const int *rp, const int *ci, con
     return a;
 }
 
+/* Dot product in fixed chunks of DOT_CHUNK entries: each chunk is summed left
+ * to right, then the chunk sums left to right, so the result is the same
+ * whatever the number of threads (one chunk: the plain left-to-right sum). */
+#define DOT_CHUNK 8192
 static double dot(int n, const double *x, const double *y) {
+    int nch = (n + DOT_CHUNK - 1) / DOT_CHUNK;
+    if (nch <= 1) {
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) s += x[i] * y[i];
+        return s;
+    }
+    double *part = (double *)xmalloc((size_t)nch * sizeof(double));
+    #pragma omp parallel for schedule(static)
+    for (int c = 0; c < nch; ++c) {
+        int i1 = (c + 1) * DOT_CHUNK < n ? (c + 1) * DOT_CHUNK : n;
+        double s = 0.0;
+        for (int i = c * DOT_CHUNK; i < i1; ++i) s += x[i] * y[i];
+        part[c] = s;
+    }
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += x[i] * y[i];
+    for (int c = 0; c < nch; ++c) s += part[c];
+    free(part);
     return s;
 }
 static double nrm2(int n, const double *x) { return sqrt(dot(n, x, x)); }
@@ -838,6 +868,7 @@ static Amg *amg_clone(const Amg *old) {
  * transposed cycle uses A^T but the same row-based D_l1. */
 static void l1_sweep(const Csr *a, const double *d, const double *b, double *x, double *r) {
     csr_residual(a, b, x, r);
+    #pragma omp parallel for schedule(static) if (PAR_OK(a->nr))
     for (int i = 0; i < a->nr; ++i) x[i] += r[i] / d[i];
 }
 
@@ -849,6 +880,7 @@ static void amg_vcycle(Amg *h, int k, const double *b, double *x, int trans) {
     if (k == h->nlev - 1) { lu_solve(n, h->lu, h->piv, b, x, trans); return; }
     int npre = trans ? h->nu_post : h->nu_pre, npost = trans ? h->nu_pre : h->nu_post;
     double *r = h->wr[k];
+    #pragma omp parallel for schedule(static) if (PAR_OK(n))
     for (int i = 0; i < n; ++i) x[i] = 0.0;
     for (int s = 0; s < npre; ++s) l1_sweep(a, h->dl1[k], b, x, r);
     csr_residual(a, b, x, r);
@@ -856,6 +888,7 @@ static void amg_vcycle(Amg *h, int k, const double *b, double *x, int trans) {
     csr_matvec(&h->R[k], r, bc);
     amg_vcycle(h, k + 1, bc, xc, trans);
     const Csr *p = &h->P[k];
+    #pragma omp parallel for schedule(static) if (PAR_OK(n))
     for (int i = 0; i < n; ++i) {
         double s = 0.0;
         for (int q = p->rp[i]; q < p->rp[i + 1]; ++q) s += p->v[q] * xc[p->ci[q]];
@@ -1160,18 +1193,24 @@ static void mgr_vcycle(Mgr *m, int lev, const double *v, double *z) {
     int n = l->n, nF = l->nF, nC = l->nC;
     double *r = m->wr[lev], *t = m->wt[lev];
     double *rF = t, *zF = t + nF;  /* scratch split: rF[nF], zF[nF] */
+    #pragma omp parallel for schedule(static) if (PAR_OK(n))
     for (int i = 0; i < n; ++i) z[i] = 0.0;
     for (int s = 0; s < l->sweeps; ++s) {
         csr_residual(&l->A, v, z, r);
+        #pragma omp parallel for schedule(static) if (PAR_OK(nF))
         for (int k = 0; k < nF; ++k) rF[k] = r[l->fmap[k]];
         frelax_solve(l, rF, zF, 0);
+        #pragma omp parallel for schedule(static) if (PAR_OK(nF))
         for (int k = 0; k < nF; ++k) z[l->fmap[k]] += l->omega * zF[k];
     }
     csr_residual(&l->A, v, z, r);
     double *rc = m->wv[lev + 1], *ec = m->wz[lev + 1];
+    #pragma omp parallel for schedule(static) if (PAR_OK(nC))
     for (int i = 0; i < nC; ++i) rc[i] = r[l->cmap[i]];
     if (l->restrict_type == RESTRICT_JACOBI) {
+        #pragma omp parallel for schedule(static) if (PAR_OK(nF))
         for (int k = 0; k < nF; ++k) rF[k] = r[l->fmap[k]];
+        #pragma omp parallel for schedule(static) if (PAR_OK(nC))
         for (int i = 0; i < nC; ++i) {
             double s = 0.0;
             for (int p = l->RF.rp[i]; p < l->RF.rp[i + 1]; ++p) s += l->RF.v[p] * rF[l->RF.ci[p]];
@@ -1179,11 +1218,13 @@ static void mgr_vcycle(Mgr *m, int lev, const double *v, double *z) {
         }
     }
     mgr_vcycle(m, lev + 1, rc, ec);
+    #pragma omp parallel for schedule(static) if (PAR_OK(nF))
     for (int k = 0; k < nF; ++k) {
         double s = 0.0;
         for (int p = l->PF.rp[k]; p < l->PF.rp[k + 1]; ++p) s += l->PF.v[p] * ec[l->PF.ci[p]];
         z[l->fmap[k]] += s;
     }
+    #pragma omp parallel for schedule(static) if (PAR_OK(nC))
     for (int i = 0; i < nC; ++i) z[l->cmap[i]] += ec[i];
 }
 
@@ -1198,6 +1239,7 @@ static void mgr_vcycle_t(Mgr *m, int lev, const double *v, double *z) {
     double *t = m->wt[lev];
     double *tF = t, *zF = t + nF;
     double *uc = m->wv[lev + 1], *ec = m->wz[lev + 1];
+    #pragma omp parallel for schedule(static) if (PAR_OK(nC))
     for (int i = 0; i < nC; ++i) {
         double s = 0.0;
         for (int p = l->PFT.rp[i]; p < l->PFT.rp[i + 1]; ++p) s += l->PFT.v[p] * v[l->fmap[l->PFT.ci[p]]];
@@ -1205,12 +1247,14 @@ static void mgr_vcycle_t(Mgr *m, int lev, const double *v, double *z) {
     }
     mgr_vcycle_t(m, lev + 1, uc, ec);
     double *yF = m->wr[lev];  /* y_F = R_F^T e (zero for injection) */
+    #pragma omp parallel for schedule(static) if (PAR_OK(nF))
     for (int k = 0; k < nF; ++k) {
         double s = 0.0;
         if (l->restrict_type == RESTRICT_JACOBI)
             for (int p = l->RFT.rp[k]; p < l->RFT.rp[k + 1]; ++p) s += l->RFT.v[p] * ec[l->RFT.ci[p]];
         yF[k] = s;
     }
+    #pragma omp parallel for schedule(static) if (PAR_OK(nF))
     for (int k = 0; k < nF; ++k) {
         double s = 0.0;
         for (int p = l->AFFT.rp[k]; p < l->AFFT.rp[k + 1]; ++p) s += l->AFFT.v[p] * yF[l->AFFT.ci[p]];
@@ -1218,7 +1262,9 @@ static void mgr_vcycle_t(Mgr *m, int lev, const double *v, double *z) {
         tF[k] = v[l->fmap[k]] - s;
     }
     frelax_solve(l, tF, zF, 1);
+    #pragma omp parallel for schedule(static) if (PAR_OK(nF))
     for (int k = 0; k < nF; ++k) z[l->fmap[k]] = yF[k] + l->omega * zF[k];
+    #pragma omp parallel for schedule(static) if (PAR_OK(nC))
     for (int i = 0; i < nC; ++i) z[l->cmap[i]] = ec[i];
 }
 
@@ -1235,6 +1281,7 @@ typedef struct {
 static void fgmres(int n, op_fn matvec, op_fn prec, void *ctx, const double *b, double *x, int m, int maxiter,
                    double rtol, int mgs, SolveInfo *info) {
     memset(info, 0, sizeof(*info));
+    #pragma omp parallel for schedule(static) if (PAR_OK(n))
     for (int i = 0; i < n; ++i) x[i] = 0.0;
     double bnorm = nrm2(n, b);
     if (bnorm == 0.0) { info->status = ORC_OK; return; }
@@ -1252,10 +1299,12 @@ static void fgmres(int n, op_fn matvec, op_fn prec, void *ctx, const double *b, 
     for (int cycle = 0;; ++cycle) {
         /* r = b - A x */
         matvec(ctx, x, w);
+        #pragma omp parallel for schedule(static) if (PAR_OK(n))
         for (int i = 0; i < n; ++i) V[i] = b[i] - w[i];
         double beta = nrm2(n, V);
         if (beta <= rtol * bnorm) { converged = 1; est = beta / bnorm; truer = est; break; }
         if (cycle > 0) info->restarts++;
+        #pragma omp parallel for schedule(static) if (PAR_OK(n))
         for (int i = 0; i < n; ++i) V[i] /= beta;
         memset(g, 0, (size_t)(m + 1) * sizeof(double));
         memset(H, 0, (size_t)(m + 1) * m * sizeof(double));
@@ -1270,11 +1319,13 @@ static void fgmres(int n, op_fn matvec, op_fn prec, void *ctx, const double *b, 
                 for (int i = 0; i <= j; ++i) {
                     double h = dot(n, V + (size_t)i * n, w);
                     H[i * m + j] += h;
+                    #pragma omp parallel for schedule(static) if (PAR_OK(n))
                     for (int q = 0; q < n; ++q) w[q] -= h * V[(size_t)i * n + q];
                 }
             } else {
                 for (int pass = 0; pass < 2; ++pass) {           /* classical Gram-Schmidt, twice */
                     for (int i = 0; i <= j; ++i) hp[i] = dot(n, V + (size_t)i * n, w);
+                    #pragma omp parallel for schedule(static) if (PAR_OK(n))
                     for (int q = 0; q < n; ++q) {
                         double s = 0.0;
                         for (int i = 0; i <= j; ++i) s += hp[i] * V[(size_t)i * n + q];
@@ -1303,6 +1354,7 @@ static void fgmres(int n, op_fn matvec, op_fn prec, void *ctx, const double *b, 
             est = fabs(g[j + 1]) / bnorm;
             if (hn == 0.0) break;                                /* lucky breakdown */
             double *vn = V + (size_t)(j + 1) * n;
+            #pragma omp parallel for schedule(static) if (PAR_OK(n))
             for (int q = 0; q < n; ++q) vn[q] = w[q] / hn;
             if (fabs(g[j + 1]) <= rtol * bnorm || iters >= maxiter) break;
         }
@@ -1311,9 +1363,11 @@ static void fgmres(int n, op_fn matvec, op_fn prec, void *ctx, const double *b, 
             for (int q = i + 1; q < k; ++q) s -= H[i * m + q] * y[q];
             y[i] = s / H[i * m + i];
         }
-        for (int i = 0; i < k; ++i)
-            for (int q = 0; q < n; ++q) x[q] += y[i] * Z[(size_t)i * n + q];
+        #pragma omp parallel for schedule(static) if (PAR_OK(n))
+        for (int q = 0; q < n; ++q)
+            for (int i = 0; i < k; ++i) x[q] += y[i] * Z[(size_t)i * n + q];
         matvec(ctx, x, w);
+        #pragma omp parallel for schedule(static) if (PAR_OK(n))
         for (int q = 0; q < n; ++q) w[q] = b[q] - w[q];
         truer = nrm2(n, w) / bnorm;
         if (truer <= rtol) { converged = 1; break; }
@@ -1682,4 +1736,15 @@ void orc_ilu0_solve(int n, const int *rp, const int *ci, const double *lu, const
                     double *z, int trans) {
     Csr a = wrap(n, n, rp, ci, NULL);
     ilu0_solve(&a, lu, diag, r, z, trans);
+}
+
+/* Threads used by the solve phase (OpenMP); 0 or less leaves the default. */
+int orc_set_threads(int nthreads) {
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    return omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
 }

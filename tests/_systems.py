@@ -71,5 +71,28 @@ def rel(a, b):
     return np.linalg.norm(a - b) / (d if d > 0 else 1.0)
 
 
+def elem_err(a, b, field=None):
+    """Entry-wise difference of a from the reference b: the largest |a_i - b_i|
+    over the entries of each field label, relative to the largest |b_i| of that
+    label, and the worst label.  Unlike a 2-norm over the whole vector it sees a
+    wrong value in a small set of unknowns (the well pressures, the fracture
+    pressures) however many other unknowns there are.  2-D arrays are taken
+    row by row (one right-hand side per row) with the same labels."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    if field is not None and a.ndim == 2:
+        field = np.tile(np.asarray(field), a.shape[0])
+    a, b = a.reshape(-1), b.reshape(-1)
+    groups = [np.ones(len(b), bool)] if field is None else [field == f for f in np.unique(field)]
+    worst = 0.0
+    for g in groups:
+        d = np.abs(a[g] - b[g]).max() if g.any() else 0.0
+        if d == 0.0:
+            continue
+        sc = np.abs(b[g]).max()
+        worst = max(worst, d / sc if sc > 0 else np.inf)
+    return worst
+
+
 def say(*args):
     print(*args, flush=True)

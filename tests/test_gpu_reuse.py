@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from _systems import SMALL, gpu_solver, oracle_mgr, perturbed_values, rel, say
+from _systems import elem_err, SMALL, gpu_solver, oracle_mgr, perturbed_values, rel, say
 
 pytestmark = pytest.mark.gpu
 
@@ -58,12 +58,12 @@ def test_update_values_matches_oracle_reuse(name):
     assert om2.status == 0
     _same_hierarchy(gs, om2, s["levels"])
     v = np.random.default_rng(3).standard_normal(s["n"])
-    assert rel(gs.apply(v).cpu().numpy(), om2.apply(v)) <= 1e-10
-    assert rel(gs.apply(v, transpose=True).cpu().numpy(), om2.apply(v, trans=True)) <= 1e-10
+    assert elem_err(gs.apply(v).cpu().numpy(), om2.apply(v), s["field"]) <= 1e-10
+    assert elem_err(gs.apply(v, transpose=True).cpu().numpy(), om2.apply(v, trans=True), s["field"]) <= 1e-10
     X, [ig] = gs.solve(s2["rhs"])
     xo, io = om2.solve(s2["rhs"])
     say(f"[reuse] {name}: iterations gpu {ig.iterations} oracle {io.iterations}, x err {rel(X.cpu().numpy(), xo):.2e}")
-    assert ig.status == 0 and abs(ig.iterations - io.iterations) <= 1 and rel(X.cpu().numpy(), xo) <= 1e-8
+    assert ig.status == 0 and abs(ig.iterations - io.iterations) <= 1 and elem_err(X.cpu().numpy(), xo, s["field"]) <= 1e-8
     # the FP32 apply is formed from the new values too
     gs.set_opts(precision=32)
     X32, [i32] = gs.solve(s2["rhs"])
@@ -87,11 +87,11 @@ def test_update_keeping_frelaxation_amg_whole():
     om2 = om.update(vals2, keep_frelax_amg=True)
     _same_hierarchy(gs, om2, s["levels"])
     v = np.random.default_rng(4).standard_normal(s["n"])
-    assert rel(gs.apply(v).cpu().numpy(), om2.apply(v)) <= 1e-10
+    assert elem_err(gs.apply(v).cpu().numpy(), om2.apply(v), s["field"]) <= 1e-10
     s2 = dict(s, vals=vals2)
     X, [ig] = gs.solve(s2["rhs"])
     xo, io = om2.solve(s2["rhs"])
-    assert ig.status == 0 and abs(ig.iterations - io.iterations) <= 1 and rel(X.cpu().numpy(), xo) <= 1e-8
+    assert ig.status == 0 and abs(ig.iterations - io.iterations) <= 1 and elem_err(X.cpu().numpy(), xo, s["field"]) <= 1e-8
 
 
 def test_update_errors():
