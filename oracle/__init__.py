@@ -51,10 +51,10 @@ def lib():
         i32, f64, u64 = ctypes.c_int, ctypes.c_double, ctypes.c_ulonglong
         L.orc_setup.restype = P
         L.orc_setup.argtypes = [i32, i32, P, P, P, P, i32, P, P, P, P, P, P, f64, i32, i32, i32, i32, i32, i32, u64,
-                                P]
+                                P, P]
         L.orc_update.restype = P
         L.orc_update.argtypes = [P, i32, i32, P, P, P, P, i32, P, P, P, P, P, P, f64, i32, i32, i32, i32, i32, i32,
-                                 u64, i32, P]
+                                 u64, P, i32, P]
         L.orc_free.argtypes = [P]
         L.orc_apply.argtypes = [P, P, P, i32]
         L.orc_matvec.argtypes = [P, P, P, i32]
@@ -279,11 +279,14 @@ class MGR:
     block row pointers / columns / values (b*b row-major per block), the field
     label of every scalar unknown, a list of LevelOpts (one per MGR level), and
     AMG options for the final coarse system (``interp``: "direct" or "ext+i"
-    interpolation, also used by the F-relaxation AMG hierarchies).
+    interpolation, also used by the F-relaxation AMG hierarchies).  ``block``:
+    optional group id of every scalar unknown for block-Jacobi F-relaxation
+    (a block is a run of consecutive F-points with one id); default: the
+    block row of the input layout.
     """
 
     def __init__(self, b, rp, ci, vals, field, levels, theta=0.25, max_levels=25, max_coarse=128,
-                 nu_pre=1, nu_post=1, coarse_unknown_based=False, seed=12345, interp="direct"):
+                 nu_pre=1, nu_post=1, coarse_unknown_based=False, seed=12345, interp="direct", block=None):
         L = lib()
         self.b = int(b)
         self.rp, self.ci, self.vals = _i32(rp), _i32(ci), _f64(vals)
@@ -299,9 +302,11 @@ class MGR:
         self._lv = (nl, fmask, frelax, sweeps, omega, restr, aub)
         self._amg = (float(theta), int(max_levels), int(max_coarse), int(nu_pre), int(nu_post),
                      int(coarse_unknown_based), INTERP[interp], int(seed))
+        self.block = None if block is None else _i32(block)
         st = ctypes.c_int(0)
         self.h = L.orc_setup(self.b, len(self.rp) - 1, _p(self.rp), _p(self.ci), _p(self.vals), _p(self.field),
-                             nl, *[_p(a) for a in self._lv[1:]], *self._amg, ctypes.byref(st))
+                             nl, *[_p(a) for a in self._lv[1:]], *self._amg,
+                             None if self.block is None else _p(self.block), ctypes.byref(st))
         self.status = st.value
 
     def update(self, vals, keep_frelax_amg=False):
@@ -310,13 +315,14 @@ class MGR:
         products are formed again), or, with keep_frelax_amg, keep the
         F-relaxation AMG hierarchies whole.  Returns the new MGR."""
         new = MGR.__new__(MGR)
-        new.b, new.rp, new.ci, new.n, new.field = self.b, self.rp, self.ci, self.n, self.field
+        new.b, new.rp, new.ci, new.n, new.field, new.block = self.b, self.rp, self.ci, self.n, self.field, self.block
         new.vals = _f64(vals)
         new._lv, new._amg = self._lv, self._amg
         st = ctypes.c_int(0)
         new.h = lib().orc_update(self.h, self.b, len(self.rp) - 1, _p(self.rp), _p(self.ci), _p(new.vals),
                                  _p(self.field), self._lv[0], *[_p(a) for a in self._lv[1:]], *self._amg,
-                                 int(bool(keep_frelax_amg)), ctypes.byref(st))
+                                 None if self.block is None else _p(self.block), int(bool(keep_frelax_amg)),
+                                 ctypes.byref(st))
         new.status = st.value
         return new
 

@@ -1408,21 +1408,21 @@ static void *setup_impl(int b, int nbr, const int *rp, const int *ci, const doub
                         int nlevels, const unsigned *fmask, const int *frelax, const int *sweeps,
                         const double *omega, const int *restrict_type, const int *amg_unknown_based_lvl,
                         double theta, int max_levels, int max_coarse, int nu_pre, int nu_post,
-                        int coarse_unknown_based, int interp, unsigned long long seed, const void *reuse_from, int keep_famg,
-                        int *status);
+                        int coarse_unknown_based, int interp, unsigned long long seed, const int *block_of_dof,
+                        const void *reuse_from, int keep_famg, int *status);
 
 void *orc_setup(int b, int nbr, const int *rp, const int *ci, const double *val, const int *field, int nlevels,
                 const unsigned *fmask, const int *frelax, const int *sweeps, const double *omega,
                 const int *restrict_type, const int *amg_unknown_based_lvl, double theta, int max_levels,
                 int max_coarse, int nu_pre, int nu_post, int coarse_unknown_based, int interp, unsigned long long seed,
-                int *status) {
+                const int *block_of_dof, int *status) {
     return setup_impl(b, nbr, rp, ci, val, field, nlevels, fmask, frelax, sweeps, omega, restrict_type,
                       amg_unknown_based_lvl, theta, max_levels, max_coarse, nu_pre, nu_post, coarse_unknown_based,
-                      interp, seed, NULL, 0, status);
+                      interp, seed, block_of_dof, NULL, 0, status);
 }
 
 /* Setup reuse for new values on the same pattern (the AMG data reuse between
- * Newton solves of Sec. 3.3 and 5): the MGR levels are formed again; every AMG
+ * Newton solves of Sec. 3.3 and Sec. 4.4): the MGR levels are formed again; every AMG
  * hierarchy (the coarse one and those used as F-relaxation) keeps the C/F
  * splits and interpolation of `old` and forms its Galerkin products anew, or,
  * with keep_famg, the F-relaxation hierarchies are kept whole (their A_FF is
@@ -1431,18 +1431,18 @@ void *orc_update(const void *old, int b, int nbr, const int *rp, const int *ci, 
                  int nlevels, const unsigned *fmask, const int *frelax, const int *sweeps, const double *omega,
                  const int *restrict_type, const int *amg_unknown_based_lvl, double theta, int max_levels,
                  int max_coarse, int nu_pre, int nu_post, int coarse_unknown_based, int interp,
-                 unsigned long long seed, int keep_famg, int *status) {
+                 unsigned long long seed, const int *block_of_dof, int keep_famg, int *status) {
     return setup_impl(b, nbr, rp, ci, val, field, nlevels, fmask, frelax, sweeps, omega, restrict_type,
                       amg_unknown_based_lvl, theta, max_levels, max_coarse, nu_pre, nu_post, coarse_unknown_based,
-                      interp, seed, old, keep_famg, status);
+                      interp, seed, block_of_dof, old, keep_famg, status);
 }
 
 static void *setup_impl(int b, int nbr, const int *rp, const int *ci, const double *val, const int *field,
                         int nlevels, const unsigned *fmask, const int *frelax, const int *sweeps,
                         const double *omega, const int *restrict_type, const int *amg_unknown_based_lvl,
                         double theta, int max_levels, int max_coarse, int nu_pre, int nu_post,
-                        int coarse_unknown_based, int interp, unsigned long long seed, const void *reuse_from, int keep_famg,
-                        int *status) {
+                        int coarse_unknown_based, int interp, unsigned long long seed, const int *block_of_dof,
+                        const void *reuse_from, int keep_famg, int *status) {
     const Handle *old = (const Handle *)reuse_from;
     Handle *h = (Handle *)xcalloc(1, sizeof(Handle));
     h->b = b; h->nbr = nbr;
@@ -1455,8 +1455,9 @@ static void *setup_impl(int b, int nbr, const int *rp, const int *ci, const doub
     *status = ORC_OK;
     if (nlevels < 0 || nlevels > MAX_MGR_LEVELS) { *status = ORC_ERR_ARG; return h; }
     AmgOpts ao = {theta, max_levels, max_coarse, nu_pre, nu_post, coarse_unknown_based, interp, (uint64_t)seed};
+    /* block-Jacobi groups: the caller's group id of every unknown, else its block row */
     int *gblock = (int *)xmalloc((size_t)n * sizeof(int));
-    for (int i = 0; i < n; ++i) gblock[i] = i / b;
+    for (int i = 0; i < n; ++i) gblock[i] = block_of_dof ? block_of_dof[i] : i / b;
     Csr cur = csr_copy(&h->A0);
     int *cfield = (int *)xmalloc((size_t)n * sizeof(int));
     memcpy(cfield, field, (size_t)n * sizeof(int));

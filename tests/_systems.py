@@ -24,6 +24,10 @@ SMALL = {
     # elasticity (3x3 blocks) + fracture pressures; F-relaxation = unknown-based AMG V-cycle
     "frac_12^3": lambda: W.fracturing(12, seed=5),
     "frac_18^3": lambda: W.fracturing(18, seed=6),
+    # MGR_P (Sec. 3.3): F = fracture pressures (AMG F-relaxation), coarse
+    # A_uu - A_up D_pp^-1 A_pu to unknown-based AMG
+    "frac_p_12^3": lambda: W.fracturing(12, seed=5, reduction="p"),
+    "frac_p_18^3": lambda: W.fracturing(18, seed=6, reduction="p"),
 }
 
 
@@ -51,7 +55,10 @@ def _opts(s, kw):
 
 def oracle_mgr(s, levels=None, **kw):
     lv = [O.LevelOpts(**l) for l in (levels if levels is not None else s["levels"])]
-    kw = {k: v for k, v in _opts(s, kw).items() if k in ("theta", "max_levels", "max_coarse", "nu_pre", "nu_post",
+    kw = _opts(s, kw)
+    if "unknown_based" in kw:     # the binding's name for the coarse AMG's unknown-based option
+        kw["coarse_unknown_based"] = kw.pop("unknown_based")
+    kw = {k: v for k, v in kw.items() if k in ("theta", "max_levels", "max_coarse", "nu_pre", "nu_post",
                                                          "coarse_unknown_based", "seed", "interp")}
     m = O.MGR(s["b"], s["rp"], s["ci"], s["vals"], s["field"], lv, **kw)
     assert m.status == 0, m.status

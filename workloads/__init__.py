@@ -458,7 +458,7 @@ def _q1_reference_stiffness(nu):
     return K, corners.astype(int)
 
 
-def fracturing(nn=96, seed=3, nu=0.25, cs=0.1, storage=1e-2):
+def fracturing(nn=96, seed=3, nu=0.25, cs=0.1, storage=1e-2, reduction="u"):
     """Hydraulic-fracturing-style system (Sec. 3.3, App. C): Q1 hexahedral
     elasticity on an nn^3 node grid (3 displacement unknowns per node, fields
     0-2), Young's modulus per element with ln E ~ N(0,1), Poisson ratio 0.25,
@@ -471,8 +471,14 @@ def fracturing(nn=96, seed=3, nu=0.25, cs=0.1, storage=1e-2):
     Coupling at the node tied to each interior cell: -1 from pressure into the
     node's u_y equation (traction) and +cs from u_y into the cell's mass balance
     (aperture storage), so the pressure Schur complement gains a positive term.
-    Reduction (MGR_U): F = displacements, F-relaxation one unknown-based AMG
-    V-cycle on A_uu, Jacobi interpolation, injection; AMG on the coarse system."""
+    reduction="u" is MGR_U of Sec. 3.3: F = displacements, F-relaxation one
+    unknown-based AMG V-cycle on A_uu, Jacobi interpolation, injection; AMG on
+    the coarse pressure system.  reduction="p" is MGR_P, the other order of
+    Sec. 3.3: F = fracture pressures, F-relaxation one AMG V-cycle on A_pp,
+    Jacobi interpolation, injection; the coarse system A_uu - A_up D_pp^-1 A_pu
+    goes to unknown-based AMG over the three displacement components."""
+    if reduction not in ("u", "p"):
+        raise ValueError("reduction must be 'u' or 'p'")
     if (nn * nn) % 3:
         raise ValueError("nn^2 must be a multiple of 3 (pressures are grouped three per block row)")
     g = _rngs(seed)
@@ -564,10 +570,16 @@ def fracturing(nn=96, seed=3, nu=0.25, cs=0.1, storage=1e-2):
     field = np.concatenate([np.tile(np.arange(3, dtype=np.int32), nnode), np.full(ncell, 3, np.int32)])
     rhs = g["rhs"].standard_normal(3 * nnode + ncell)
     rhs[:3 * nnode][np.repeat(bnd, 3)] = 0.0
-    levels = [level((1 << 0) | (1 << 1) | (1 << 2), "amg", amg_unknown_based=True)]
     # two L1-Jacobi sweeps per side stand in for the paper's hybrid L1 Gauss-Seidel
-    return _system(3, rp.astype(np.int32), ci, vals, field, rhs, levels, f"fracturing_{nn}^3",
-                   nnode=nnode, ncell=ncell, solver_opts=dict(nu_pre=2, nu_post=2))
+    if reduction == "u":
+        levels = [level((1 << 0) | (1 << 1) | (1 << 2), "amg", amg_unknown_based=True)]
+        opts = dict(nu_pre=2, nu_post=2)
+    else:
+        levels = [level(1 << 3, "amg")]
+        opts = dict(nu_pre=2, nu_post=2, unknown_based=True)
+    return _system(3, rp.astype(np.int32), ci, vals, field, rhs, levels,
+                   f"fracturing_{nn}^3" + ("_mgr_p" if reduction == "p" else ""),
+                   nnode=nnode, ncell=ncell, solver_opts=opts)
 
 
 def csr_of(system):
