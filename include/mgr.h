@@ -162,6 +162,24 @@ int mgr_update_values(mgr_handle h, const double *values, int32_t flags);
  * relaxation.  r, z: n doubles; may not alias.  Asynchronous. */
 int mgr_apply(mgr_handle h, const double *r, double *z);
 
+/* z = M^{-1} r exactly as mgr_apply computes it (the same kernels on the same
+ * operators, so the same result), for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation.  It calls no allocating routine: its work vectors live in
+ * one static device array per GPU of MGR_NOALLOC_SCRATCH_BYTES (64 MiB), held
+ * from the library's first handle on that GPU until the process ends.  Every
+ * call on a GPU shares that array, so calls that overlap on one GPU (other
+ * streams, other handles, other threads) race; the array keeps the last call's
+ * contents, and every value the apply reads from it is written by the same
+ * call first.  Requires one mgr_apply or mgr_solve on the current hierarchy
+ * beforehand (it makes the operator copies the apply reads; after mgr_setup,
+ * mgr_update_values or a change of apply precision, again).  r, z: n doubles;
+ * may not alias.  Asynchronous.  Errors: ARG (no setup, no earlier apply, null
+ * vector), UNSUPPORTED (the hierarchy's work vectors, each rounded up to 256
+ * bytes, exceed the scratch size). */
+#define MGR_NOALLOC_SCRATCH_BYTES (64u << 20)
+int mgr_apply_noalloc(mgr_handle h, const double *r, double *z);
+
 /* z = M^{-T} r, the exact transpose of mgr_apply (requires sweeps == 1 on
  * every level).  Asynchronous. */
 int mgr_apply_transpose(mgr_handle h, const double *r, double *z);

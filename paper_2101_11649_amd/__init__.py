@@ -28,7 +28,7 @@ STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_ARG", -2: "ERR_HIP", -3: "ERR_ZE
 
 EXPORTED = ["mgr_default_opts", "mgr_create", "mgr_set_opts", "mgr_setup", "mgr_apply", "mgr_apply_transpose",
             "mgr_matvec", "mgr_solve", "mgr_solve_transpose", "mgr_grad_values", "mgr_hierarchy_info",
-            "mgr_export", "mgr_last_error", "mgr_destroy", "mgr_update_values"]
+            "mgr_export", "mgr_last_error", "mgr_destroy", "mgr_update_values", "mgr_apply_noalloc"]
 
 
 class MgrError(RuntimeError):
@@ -86,6 +86,7 @@ def lib():
         L.mgr_update_values.argtypes = [P, P, i32]
         L.mgr_apply.argtypes = [P, P, P]
         L.mgr_apply_transpose.argtypes = [P, P, P]
+        L.mgr_apply_noalloc.argtypes = [P, P, P]
         L.mgr_matvec.argtypes = [P, i32, P, P]
         L.mgr_solve.argtypes = [P, i32, P, P, ctypes.POINTER(mgr_solve_info)]
         L.mgr_solve_transpose.argtypes = [P, i32, P, P, ctypes.POINTER(mgr_solve_info)]
@@ -216,6 +217,15 @@ class Solver:
         f = lib().mgr_apply_transpose if transpose else lib().mgr_apply
         self._check(f(self._h, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(z.data_ptr())))
         return z
+
+    def apply_noalloc(self, r, out):
+        """z = M^{-1} r through mgr_apply_noalloc: work vectors in the library's
+        static scratch array, nothing allocated (needs one apply or solve on
+        this setup first).  out: a float64 device tensor of n entries."""
+        torch = _torch()
+        r = _dev(r, torch.float64)
+        self._check(lib().mgr_apply_noalloc(self._h, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def matvec(self, x, transpose=False):
         torch = _torch()

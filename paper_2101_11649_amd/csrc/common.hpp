@@ -31,6 +31,14 @@ struct Error : public std::runtime_error {
 
 #define MGR_LAUNCH_CHECK() MGR_HIP(hipGetLastError())
 
+// Set for the duration of a call that must not allocate device memory (the
+// no-allocation apply): an allocation then fails with an error instead of
+// reaching the runtime.
+inline thread_local bool tl_noalloc = false;
+inline void check_may_allocate() {
+    if (tl_noalloc) throw Error(-1, "internal: a device allocation was requested by a call that allocates nothing");
+}
+
 // Stream-ordered block cache of one solver context.  A setup makes hundreds of
 // short-lived device arrays; handing their blocks back to a free list (by size
 // class) and out again to later allocations on the same stream costs a map
@@ -50,6 +58,7 @@ struct BlockCache {
         return (bytes + step - 1) / step * step;
     }
     void* get(size_t bytes, size_t& cls) {
+        check_may_allocate();
         cls = size_class(bytes);
         auto it = free_.find(cls);
         if (it != free_.end()) {
@@ -108,6 +117,7 @@ struct DArr {
         s = st;
         n = count;
         if (!count) return;
+        check_may_allocate();
         if (tl_cache && tl_cache->s == st) {
             cache = tl_cache;
             p = static_cast<T*>(cache->get(count * sizeof(T), cls));

@@ -12,8 +12,11 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "apply.hpp"
@@ -818,6 +821,13 @@ struct Ctx {
     long kr_n = 0;
     DArr<double> V, Z, hbuf, part, yd;
     DArr<double> apply_tmp;
+    // no-allocation apply: whether a forward / transposed apply has run on the
+    // current hierarchy (every operator copy it reads then exists), this
+    // device's scratch array, and room for the work-vector addresses it swaps
+    bool warm[2] = {false, false};
+    unsigned char* scratch = nullptr;
+    std::vector<std::pair<DArr<double>*, double*>> saved_d;
+    std::vector<std::pair<DArr<float>*, float*>> saved_f;
     // pinned copies of the Arnoldi coefficients, one row of HROW per
     // iteration, each ending in a ready flag that the kernel sets last
     static constexpr int HROW = 200;
@@ -1213,10 +1223,105 @@ static void mgr_apply_top(Ctx& c, const double* v, double* z, bool tr) {
         } else {
             amg_vcycle<double>(c.camg, 0, v, z, tr, c.s);
         }
+        c.warm[tr ? 1 : 0] = true;
         return;
     }
     if (f32) mgr_apply_rec<float>(c, 0, v, z, tr);
     else mgr_apply_rec<double>(c, 0, v, z, tr);
+    c.warm[tr ? 1 : 0] = true;
+}
+
+// ====================================================================== no-allocation apply
+// Work vectors of mgr_apply_noalloc live in one static device array per GPU,
+// held until the process ends.  In host code the array's name only stands in
+// for the symbol: its device address (one per device) comes from
+// hipGetSymbolAddress, looked up once per device when a handle is created on
+// it, and only that address is ever passed to kernels.
+static __device__ __align__(256) unsigned char scratch[MGR_NOALLOC_SCRATCH_BYTES];
+
+static unsigned char* scratch_for_device(int dev) {
+    static std::mutex mu;
+    static std::map<int, unsigned char*> addr;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = addr.find(dev);
+    if (it != addr.end()) return it->second;
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        throw Error(MGR_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    addr[dev] = static_cast<unsigned char*>(p);
+    return static_cast<unsigned char*>(p);
+}
+
+// Every work vector of the apply (level vectors of the MGR levels, of the
+// F-relaxation and coarse AMG hierarchies, and the FP32 staging of a pure AMG
+// preconditioner): the only device memory an apply writes besides z.
+template <typename F>
+static void for_each_work(Amg& H, F&& f) {
+    for (auto& L : H.lv) {
+        f(L.rd); f(L.td); f(L.bd); f(L.xd); f(L.sd);
+        f(L.rf); f(L.tf); f(L.bf); f(L.xf); f(L.sf);
+    }
+}
+template <typename F>
+static void for_each_work(Ctx& c, F&& f) {
+    for (auto& l : c.L) {
+        f(l.rcd); f(l.ecd); f(l.vFd); f(l.vCd); f(l.zFd); f(l.rFd); f(l.tFd);
+        f(l.rcf); f(l.ecf); f(l.vFf); f(l.vCf); f(l.zFf); f(l.rFf); f(l.tFf);
+        if (l.famg) for_each_work(*l.famg, f);
+    }
+    for_each_work(c.camg, f);
+    f(c.apply_tmp);
+}
+
+// z = M^{-1} v with every work vector placed in the device's scratch array:
+// the hierarchy's own work vectors are pointed into it for the enqueue and
+// pointed back afterwards (kernels take their addresses at launch).  Needs a
+// hierarchy on which a forward apply has already run, so that every operator
+// copy the apply reads exists; allocates nothing.
+static void mgr_apply_noalloc_impl(Ctx& c, const double* v, double* z) {
+    if (!c.ready) throw Error(MGR_ERR_ARG, "apply before setup");
+    if (!c.warm[0])
+        throw Error(MGR_ERR_ARG, "mgr_apply_noalloc needs one mgr_apply (or mgr_solve) on this hierarchy first");
+    if (!c.scratch) throw Error(MGR_ERR_ARG, "internal: no scratch address for this device");
+    // the work vectors of the apply precision in use (the FP32 apply of a pure
+    // AMG preconditioner also stages v and z in apply_tmp)
+    const bool f32 = (c.o.apply_precision == 32);
+    auto used = [&](auto& a) {
+        using T = std::remove_pointer_t<decltype(a.p)>;
+        if (!a.p) return false;
+        if ((const void*)&a == (const void*)&c.apply_tmp) return f32;
+        return std::is_same_v<T, float> == f32;
+    };
+    size_t need = 0;
+    auto round = [](size_t b) { return (b + 255) & ~size_t(255); };
+    for_each_work(c, [&](auto& a) { if (used(a)) need += round(a.bytes()); });
+    if (need > MGR_NOALLOC_SCRATCH_BYTES)
+        throw Error(MGR_ERR_UNSUPPORTED, "mgr_apply_noalloc: the hierarchy's work vectors need " +
+                                             std::to_string(need) + " bytes, above the scratch size of " +
+                                             std::to_string((size_t)MGR_NOALLOC_SCRATCH_BYTES) + " bytes");
+    struct Restore {
+        Ctx& c;
+        ~Restore() {
+            for (auto& q : c.saved_d) q.first->p = q.second;
+            for (auto& q : c.saved_f) q.first->p = q.second;
+            c.saved_d.clear();
+            c.saved_f.clear();
+            tl_noalloc = false;
+        }
+    } restore{c};
+    size_t off = 0;
+    for_each_work(c, [&](auto& a) {
+        if (!used(a)) return;
+        using T = std::remove_pointer_t<decltype(a.p)>;
+        T* q = reinterpret_cast<T*>(c.scratch + off);
+        if constexpr (std::is_same_v<T, double>) c.saved_d.emplace_back(&a, a.p);
+        else c.saved_f.emplace_back(&a, a.p);
+        a.p = q;
+        off += round(a.bytes());
+    });
+    tl_noalloc = true;
+    mgr_apply_top(c, v, z, false);
 }
 
 static void ensure_At(Ctx& c) {
@@ -1597,6 +1702,7 @@ static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nle
 // AMG hierarchies found in c.reuse_* are reused instead of coarsened again.
 static void build_hierarchy(Ctx& c) {
     hipStream_t s = c.s;
+    c.warm[0] = c.warm[1] = false;
     const int nlevels = (int)c.lvl.size();
     const mgr_level_opts* lvl = c.lvl.data();
     DArr<int> fld((size_t)c.n, s), blk((size_t)c.n, s);
@@ -1828,6 +1934,11 @@ int mgr_create(mgr_handle* h, const mgr_opts* o, void* hip_stream) {
         uint64_t thr = UINT64_MAX;
         MGR_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
         c->c.slots.init(c->c.s);
+        // this device's scratch array of the no-allocation apply, and room for
+        // the addresses it swaps (so that call allocates no host memory either)
+        c->c.scratch = mgr::scratch_for_device(dev);
+        c->c.saved_d.reserve(4096);
+        c->c.saved_f.reserve(4096);
         hipError_t e = hipStreamSynchronize(c->c.s);
         if (e != hipSuccess) throw Error(MGR_ERR_HIP, hipGetErrorString(e));
     } catch (...) {
@@ -1841,6 +1952,8 @@ int mgr_create(mgr_handle* h, const mgr_opts* o, void* hip_stream) {
 int mgr_set_opts(mgr_handle h, const mgr_opts* o) {
     return guarded(h, [&]() {
         if (!o || check_opts(o) != MGR_OK) throw Error(MGR_ERR_ARG, "invalid options");
+        // another apply precision reads other operator copies, made by the next apply
+        if (o->apply_precision != h->c.o.apply_precision) h->c.warm[0] = h->c.warm[1] = false;
         h->c.o = *o;
         return MGR_OK;
     });
@@ -1865,6 +1978,14 @@ int mgr_apply(mgr_handle h, const double* r, double* z) {
     return guarded(h, [&]() {
         if (!r || !z) throw Error(MGR_ERR_ARG, "null vector");
         mgr::mgr_apply_top(h->c, r, z, false);
+        return MGR_OK;
+    });
+}
+
+int mgr_apply_noalloc(mgr_handle h, const double* r, double* z) {
+    return guarded(h, [&]() {
+        if (!r || !z) throw Error(MGR_ERR_ARG, "null vector");
+        mgr::mgr_apply_noalloc_impl(h->c, r, z);
         return MGR_OK;
     });
 }
