@@ -1,12 +1,16 @@
 """Benchmark: FGMRES + MGR time-to-1e-8 on one MI355X.
 
-Workload: the hybrid mimetic single-phase system on a 64^3 hex grid (cell
-pressures + face multipliers, 1,060,864 unknowns, 12,070,912 nonzeros,
-lognormal diagonal permeability with sigma = 2), one MGR level eliminating the
-cells exactly (F = cells, Jacobi), AMG V-cycle on the face system, FGMRES(50)
-to a relative residual of 1e-8.  One step = MGR/AMG setup + solve, with the
-matrix already resident in HBM.  The FP64 apply is the headline; the same steps
-with the FP32 MGR apply are reported beside it (FP32-vs-FP64 speedup).
+Workload (headline): the compositional-style system with wells on a
+128 x 128 x 64 grid, 4 unknowns per cell (pressure + 3 component densities) in
+4 x 4 blocks plus 16 wells (4,194,368 unknowns, 116,391,936 stored block
+values), lognormal permeability; MGR in two levels (components by
+block-Jacobi, then wells by Jacobi), AMG V-cycle on the pressure system,
+FGMRES(50) to a relative residual of 1e-8.  One step = MGR/AMG setup + solve,
+with the matrix already resident in HBM.  The FP64 apply is the headline; the
+same steps with the FP32 MGR apply are reported beside it (FP32-vs-FP64
+speedup).  The other workloads (hybrid mimetic 64^3, the paper's four-level
+compositional order, fracturing with MGR_U and MGR_P, MGR_P vs MGR_Pi on the
+TPFA mimetic system) are reported as secondaries.
 
 Prints one JSON line (stdout).  Progress goes to stderr.
 """
@@ -14,6 +18,7 @@ import argparse
 import json
 import os
 import statistics
+import subprocess
 import sys
 import time
 
@@ -93,13 +98,26 @@ def time_reuse(solver, sysd, vals2, keep, reps=3):
             "kept": "F-relaxation AMG hierarchies whole" if keep else "AMG C/F splits and interpolation"}
 
 
-def kernel_traffic(name):
-    """HBM bytes per launch of `name` from the committed rocprofv3 counter summary
-    (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None if the summary
-    is missing or the kernel source changed since the counters were taken."""
+def kernel_source_sha256(kernel):
+    """sha256 of the text of one kernel in k_apply.hip: from the line that
+    declares `__global__ ... kernel(` to the first closing brace in column 0."""
     import hashlib
+    src = open(os.path.join(ROOT, "paper_2101_11649_amd", "csrc", "k_apply.hip")).read().splitlines(keepends=True)
+    for i, line in enumerate(src):
+        if "__global__" in line and f" {kernel}(" in line:
+            j = i
+            while src[j].rstrip("\n") != "}":
+                j += 1
+            return hashlib.sha256("".join(src[i:j + 1]).encode()).hexdigest()
+    return None
+
+
+def kernel_traffic(name):
+    """HBM bytes per launch of a kernel from its committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or None if
+    the summary is missing or the kernel's source text changed since the
+    counters were taken."""
     path = os.path.join(ROOT, "profiles", name)
-    src = os.path.join(ROOT, "paper_2101_11649_amd", "csrc", "k_apply.hip")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -107,8 +125,10 @@ def kernel_traffic(name):
         if ":" in line and line.startswith("- "):
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.strip().strip("`")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if fields.get("k_apply.hip sha256") != sha or "traffic bytes per launch" not in fields:
+    kern = fields.get("kernel")
+    if not kern or "traffic bytes per launch" not in fields:
+        return None
+    if fields.get("kernel source sha256") != kernel_source_sha256(kern):
         return None
     return int(float(fields["traffic bytes per launch"]))
 
@@ -135,26 +155,115 @@ def run_steps(P, s, vals, rhs, precision, steps, warmup, **opts):
     return solver, rec, X, info, stream
 
 
+def apply_launches(solver, precision, nu_pre=1, nu_post=1):
+    """The launches of one forward MGR apply (Algorithm 1 with the fused
+    one-sweep levels, then the AMG V-cycle on the coarse system), in order, each
+    with its algorithmic bytes: operator values + column indices + row pointers
+    once, every vector it reads or writes once.  s = bytes of a value in the
+    apply precision; the apply's input and output stay FP64.  Returns None for
+    hierarchies with a level in general form (several launches per step that
+    this model does not list)."""
+    s = 4 if precision == 32 else 8
+    info = solver.info()
+    mgr, amg = info["mgr_levels"], info["amg_levels"]
+    out = []
+
+    def sp(nr, nnz):
+        return nnz * (s + 4) + 4 * (nr + 1)
+
+    def amg_cycle(k, scaled):
+        n = amg[k][0]
+        last = len(amg) - 1
+        if k == last:
+            out.append((f"AMG{k} coarsest GEMV", n * n * s + 2 * n * s))
+            return
+        if solver.export_sizes(1, k, 6) is not None:
+            out.append((f"AMG{k} dense cycle GEMV", n * n * s + 2 * n * s))
+            return
+        nc = amg[k + 1][0]
+        g = solver.export_sizes(1, k, 4)
+        if g is not None:
+            wq = solver.export_sizes(1, k, 5)
+            out.append((f"AMG{k} G (composed restriction)", sp(nc, g[2]) + n * s + nc * s))
+            amg_cycle(k + 1, False)
+            out.append((f"AMG{k} [W|Q] (composed smoothing + prolongation)", sp(n, wq[2]) + 2 * n * s + nc * s))
+            return
+        a = sp(n, amg[k][1])
+        p = solver.export_sizes(1, k, 2)[2]
+        if nu_pre >= 1:
+            out.append((f"AMG{k} pre-smoothing + residual", a + 4 * n * s))
+            for _ in range(1, nu_pre):
+                out.append((f"AMG{k} Jacobi sweep", a + 4 * n * s))
+                out.append((f"AMG{k} copy", 2 * n * s))
+            if nu_pre > 1:
+                out.append((f"AMG{k} residual", a + 3 * n * s))
+        else:
+            out.append((f"AMG{k} set", n * s))
+            out.append((f"AMG{k} copy", 2 * n * s))
+        nxt_plain = (k + 2 <= last) and solver.export_sizes(1, k + 1, 4) is None \
+            and solver.export_sizes(1, k + 1, 6) is None
+        if nu_pre >= 1 and nxt_plain:
+            out.append((f"AMG{k} restriction (+ D^-1 b_c)", sp(nc, p) + n * s + 3 * nc * s))
+            amg_cycle(k + 1, True)
+        else:
+            out.append((f"AMG{k} restriction", sp(nc, p) + n * s + nc * s))
+            amg_cycle(k + 1, False)
+        out.append((f"AMG{k} prolongation", sp(n, p) + nc * s + 2 * n * s))
+        for _ in range(nu_post):
+            out.append((f"AMG{k} post-smoothing", a + 4 * n * s))
+
+    for l, (n, nF, nC, _) in enumerate(mgr):
+        rj = solver.export_sizes(0, l, 6)
+        if rj is None:
+            return None
+    sv = 8                                  # level-0 vectors are the caller's FP64 ones
+    first_plain = len(amg) >= 2 and solver.export_sizes(1, 0, 4) is None and solver.export_sizes(1, 0, 6) is None \
+        and nu_pre >= 1
+    for l, (n, nF, nC, _) in enumerate(mgr):
+        vs = sv if l == 0 else s
+        rj = solver.export_sizes(0, l, 6)[2]
+        scaled = (l + 1 == len(mgr)) and first_plain
+        out.append((f"MGR{l} restriction R_J", sp(nC, rj) + n * vs + (3 if scaled else 1) * nC * s))
+    # interpolations run after the coarse solve, innermost level first
+    amg_cycle(0, first_plain)
+    for l in reversed(range(len(mgr))):
+        n, nF, nC, _ = mgr[l]
+        vs = sv if l == 0 else s
+        pj = solver.export_sizes(0, l, 7)[2]
+        out.append((f"MGR{l} interpolation P_J", sp(n, pj) + nC * s + 2 * n * vs))
+    # restrictions are listed outermost first, so the order of launches is
+    # R_J(0) .. R_J(L-1), the V-cycle, P_J(L-1) .. P_J(0)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--grid", type=int, default=64, help="grid size per axis of the mimetic system")
-    ap.add_argument("--comp-steps", type=int, default=2,
-                    help="timed steps of the secondary compositional workload (0 = skip)")
+    ap.add_argument("--mimetic-steps", type=int, default=2,
+                    help="timed steps of the hybrid mimetic 64^3 secondary (0 = skip)")
+    ap.add_argument("--comp4-steps", type=int, default=2,
+                    help="timed steps of the paper's four-level compositional order (0 = skip)")
     ap.add_argument("--tpfa-steps", type=int, default=2,
                     help="timed steps of the MGR_P vs MGR_Pi comparison on the TPFA mimetic system (0 = skip)")
-    ap.add_argument("--interp-steps", type=int, default=2,
+    ap.add_argument("--interp-steps", type=int, default=1,
                     help="timed steps of the mimetic system with extended+i AMG interpolation (0 = skip)")
     ap.add_argument("--frac-steps", type=int, default=1,
-                    help="timed steps of the secondary fracturing workload (0 = skip)")
+                    help="timed steps of the fracturing workload, MGR_U and MGR_P (0 = skip)")
+    ap.add_argument("--no-headline", action="store_true",
+                    help="skip the headline workload (profiling runs of the secondaries alone)")
+    ap.add_argument("--launch-table", action="store_true",
+                    help="add each workload's list of apply launches with their algorithmic bytes (to pair "
+                         "with a kernel trace)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU (got --gpus {args.gpus}): the solver runs on a single device and "
               f"has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+
+    import ctypes
 
     import numpy as np
     import torch
@@ -164,227 +273,258 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    g = args.grid
-    log(f"generating hybrid mimetic {g}^3 ...")
-    s = W.hybrid_mimetic(g, g, g, seed=1)
-    n, nnz = s["n"], len(s["ci"])
-    log(f"n = {n}, nnz = {nnz}")
-    vals = torch.tensor(s["vals"], device="cuda")
-    rhs = torch.tensor(s["rhs"], device="cuda")
-    torch.cuda.synchronize()
-
-    # ---- FP64 apply (headline) and FP32 apply, K timed steps each
-    solver, rec64, X64, info64, stream = run_steps(P, s, vals, rhs, 64, args.steps, args.warmup)
-    solver32, rec32, X32, info32, _ = run_steps(P, s, vals, rhs, 32, args.steps, args.warmup)
-
-    reuse64 = time_reuse(solver, s, row_scaled(s, seed=11), False)
-    tot64 = [a + b for a, b, _, _ in rec64]
-    tot32 = [a + b for a, b, _, _ in rec32]
-    value = statistics.mean(tot64)
-
-    # ---- roofline of the dominant kernel: the FGMRES CSR SpMV on A (FP64)
+    lib = P.lib()
+    stream = torch.cuda.current_stream()
     flush = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
     # calibration launch for the byte counters: a plain 512 MB device copy
     calib = torch.empty_like(flush)
     calib.copy_(flush)
-    xv = torch.randn(n, dtype=torch.float64, device="cuda")
-    yv = torch.empty_like(xv)
-    lib = P.lib()
-    import ctypes
-    fn = lambda: lib.mgr_matvec(solver._h, 0, ctypes.c_void_p(xv.data_ptr()), ctypes.c_void_p(yv.data_ptr()))
-    fn()
-    t_spmv, _ = time_kernel(fn, stream, 50, flush)
-    # the library's scalar operator leaves out the exact zeros of the input
-    # (diagonal kept): its entries are what the matvec reads
-    rows = np.repeat(np.arange(n), np.diff(s["rp"]))
-    nnz_op = int(np.count_nonzero((s["vals"] != 0.0) | (s["ci"] == rows)))
-    nbytes = spmv_bytes(n, nnz_op)
-    achieved = nbytes / t_spmv / 1e9
+    del calib
 
-    # per-apply FP64 vs FP32 (cache flushed between launches; an apply is several kernels)
-    v = torch.randn(n, dtype=torch.float64, device="cuda")
-    z = torch.empty_like(v)
-    ap64 = lambda: lib.mgr_apply(solver._h, ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(z.data_ptr()))
-    ap32 = lambda: lib.mgr_apply(solver32._h, ctypes.c_void_p(v.data_ptr()), ctypes.c_void_p(z.data_ptr()))
-    ap64(); ap32()
-    t_ap64, _ = time_kernel(ap64, stream, 20, flush)
-    t_ap32, _ = time_kernel(ap32, stream, 20, flush)
+    def stats(rec):
+        return {"time_to_tol_s": round(statistics.mean(a + b for a, b, _, _ in rec), 6),
+                "setup_s": round(statistics.mean(a for a, _, _, _ in rec), 6),
+                "solve_s": round(statistics.mean(b for _, b, _, _ in rec), 6),
+                "iterations": rec[-1][2], "rel_res_true": rec[-1][3]}
 
-    def secondary(sysd, steps, mgr_desc, apply_reps, roof=None, reuse=None):
+    def apply_timing(s64, s32, n, reps):
+        """Per-apply FP64 and FP32 time (Infinity Cache flushed between applies) and
+        the apply chain's algorithmic bytes and GB/s."""
+        vin = torch.randn(n, dtype=torch.float64, device="cuda")
+        zout = torch.empty_like(vin)
+        a64 = lambda: lib.mgr_apply(s64._h, ctypes.c_void_p(vin.data_ptr()), ctypes.c_void_p(zout.data_ptr()))
+        a32 = lambda: lib.mgr_apply(s32._h, ctypes.c_void_p(vin.data_ptr()), ctypes.c_void_p(zout.data_ptr()))
+        a64(); a32()
+        t64, _ = time_kernel(a64, stream, reps, flush)
+        t32, _ = time_kernel(a32, stream, reps, flush)
+        o = s64.opts.amg
+        res = {"apply_ms_fp64": round(1e3 * t64, 4), "apply_ms_fp32": round(1e3 * t32, 4),
+               "speedup_per_apply": round(t64 / t32, 4)}
+        for key, sv, t, prec in (("fp64", s64, t64, 64), ("fp32", s32, t32, 32)):
+            la = apply_launches(sv, prec, o.nu_pre, o.nu_post)
+            if la is None:
+                continue
+            b = sum(x for _, x in la)
+            res[f"apply_roofline_{key}"] = {"bound": "hbm", "bytes_per_apply": int(b), "launches": len(la),
+                                            "achieved": round(b / t / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                            "frac": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}
+            if args.launch_table:
+                res[f"apply_launches_{key}"] = [[lbl, int(x)] for lbl, x in la]
+        return res
+
+    # ---- headline: compositional 128x128x64 + 16 wells, FP64 apply (and FP32 beside it)
+    s = solver = solver32 = X64 = X32 = None
+    value = value32 = t_mv = mv_bytes = None
+    rec64 = rec32 = reuse64 = app = None
+    n = nnzb = b = 0
+    if not args.no_headline:
+        log("generating compositional 128x128x64 + 16 wells ...")
+        s = W.compositional_wells(seed=2)
+        n, nnzb, b = s["n"], len(s["ci"]), s["b"]
+        log(f"n = {n}, block nnz = {nnzb}")
+        vals = torch.tensor(s["vals"], device="cuda")
+        rhs = torch.tensor(s["rhs"], device="cuda")
+        torch.cuda.synchronize()
+        solver, rec64, X64, info64, _ = run_steps(P, s, vals, rhs, 64, args.steps, args.warmup)
+        solver32, rec32, X32, info32, _ = run_steps(P, s, vals, rhs, 32, args.steps, args.warmup)
+        value = statistics.mean(a + b_ for a, b_, _, _ in rec64)
+        value32 = statistics.mean(a + b_ for a, b_, _, _ in rec32)
+        reuse64 = time_reuse(solver, s, row_scaled(s, seed=11), False)
+
+        # roofline of the dominant kernel: the FGMRES block SpMV on A (FP64)
+        xv = torch.randn(n, dtype=torch.float64, device="cuda")
+        yv = torch.empty_like(xv)
+        mv = lambda: lib.mgr_matvec(solver._h, 0, ctypes.c_void_p(xv.data_ptr()), ctypes.c_void_p(yv.data_ptr()))
+        mv()
+        t_mv, _ = time_kernel(mv, stream, 20, flush)
+        mv_bytes = bsr_spmv_bytes(b, len(s["rp"]) - 1, nnzb)
+        app = apply_timing(solver, solver32, n, 10)
+
+    def secondary(sysd, steps, mgr_desc, apply_reps, reuse=None, matvec_roof=None):
         """FP64 and FP32 apply on one more workload: time to 1e-8, per-apply time
-        (cache flushed), and optionally the roofline of its FGMRES matvec."""
+        (cache flushed) and the apply chain's GB/s."""
         vv_ = torch.tensor(sysd["vals"], device="cuda")
         bb_ = torch.tensor(sysd["rhs"], device="cuda")
         o = sysd.get("solver_opts", {})
         s64, r64, _, _, _ = run_steps(P, sysd, vv_, bb_, 64, steps, 1, **o)
         s32, r32, _, _, _ = run_steps(P, sysd, vv_, bb_, 32, steps, 1, **o)
-        t64 = statistics.mean(a + b for a, b, _, _ in r64)
-        t32 = statistics.mean(a + b for a, b, _, _ in r32)
-        vin = torch.randn(sysd["n"], dtype=torch.float64, device="cuda")
-        zout = torch.empty_like(vin)
-        a64 = lambda: lib.mgr_apply(s64._h, ctypes.c_void_p(vin.data_ptr()), ctypes.c_void_p(zout.data_ptr()))
-        a32 = lambda: lib.mgr_apply(s32._h, ctypes.c_void_p(vin.data_ptr()), ctypes.c_void_p(zout.data_ptr()))
-        a64(); a32()
-        ta64, _ = time_kernel(a64, stream, apply_reps, flush)
-        ta32, _ = time_kernel(a32, stream, apply_reps, flush)
         out_ = {"workload": sysd["name"], "n": sysd["n"], "nnz": int(len(sysd["ci"]) * sysd["b"] ** 2),
-                "mgr": mgr_desc}
-        for key, r, ta in (("fp64", r64, ta64), ("fp32", r32, ta32)):
-            out_[key] = {"time_to_tol_s": round(statistics.mean(a + b for a, b, _, _ in r), 6),
-                         "setup_s": round(statistics.mean(a for a, _, _, _ in r), 6),
-                         "solve_s": round(statistics.mean(b for _, b, _, _ in r), 6), "iterations": r[-1][2],
-                         "rel_res_true": r[-1][3], "apply_ms": round(1e3 * ta, 4)}
-        out_["speedup_time_to_tol"] = round(t64 / t32, 4)
-        out_["speedup_per_apply"] = round(ta64 / ta32, 4)
-        if roof:
-            # the FGMRES matvec on the block-CSR input, FP64
-            mv = lambda: lib.mgr_matvec(s64._h, 0, ctypes.c_void_p(vin.data_ptr()), ctypes.c_void_p(zout.data_ptr()))
-            mv()
-            t_mv, _ = time_kernel(mv, stream, 20, flush)
-            bb = bsr_spmv_bytes(sysd["b"], len(sysd["rp"]) - 1, len(sysd["ci"]))
-            out_["roofline"] = {"kernel": roof[0], "bound": "hbm", "achieved": round(bb / t_mv / 1e9, 1),
-                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                "frac": round(bb / t_mv / 1e9 / HBM_PEAK_GBS, 4), "traffic": kernel_traffic(roof[1]),
-                                "bytes_per_launch": bb, "avg_launch_us": round(1e6 * t_mv, 2)}
+                "mgr": mgr_desc, "fp64": stats(r64), "fp32": stats(r32)}
+        out_["speedup_time_to_tol"] = round(out_["fp64"]["time_to_tol_s"] / out_["fp32"]["time_to_tol_s"], 4)
+        out_.update(apply_timing(s64, s32, sysd["n"], apply_reps))
+        if matvec_roof:
+            xs = torch.randn(sysd["n"], dtype=torch.float64, device="cuda")
+            ys = torch.empty_like(xs)
+            f = lambda: lib.mgr_matvec(s64._h, 0, ctypes.c_void_p(xs.data_ptr()), ctypes.c_void_p(ys.data_ptr()))
+            f()
+            t, _ = time_kernel(f, stream, 50, flush)
+            nb = matvec_roof[0](sysd)
+            out_["matvec_roofline"] = {"kernel": matvec_roof[1], "bound": "hbm", "achieved": round(nb / t / 1e9, 1),
+                                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                       "frac": round(nb / t / 1e9 / HBM_PEAK_GBS, 4),
+                                       "traffic": kernel_traffic(matvec_roof[2]),
+                                       "bytes_per_launch": nb, "avg_launch_us": round(1e6 * t, 2)}
         if reuse is not None:
-            # setup reuse after a value change (rows of field reuse[0] scaled; reuse[1] = keep flag)
             out_["setup_reuse"] = time_reuse(s64, sysd, row_scaled(sysd, seed=11, rows_field=reuse[0]), reuse[1])
         s64.close()
         s32.close()
         return out_
 
-    # ---- secondary: the compositional system with wells (128x128x64, 4 unknowns per
-    # cell, 16 wells; 2-level MGR), FP64 vs FP32 apply inside FP64 FGMRES; its block
-    # SpMV (about 1 GB, four times the Infinity Cache) is the HBM roofline case
-    comp = comp4 = frac = None
-    if args.comp_steps > 0:
-        log("generating compositional 128x128x64 + 16 wells ...")
-        comp = secondary(W.compositional_wells(seed=2), args.comp_steps,
-                         "L1 F = components (block-Jacobi), L2 F = wells (Jacobi), coarse pressure AMG", 10,
-                         ("k_bsr_spmv<4, 8> (FGMRES matvec y = A x, 4 x 4 block CSR, FP64)",
-                          "k_bsr_spmv_compositional.md"))
-        # the paper's own four-level order on the same grid: rho_2, rho_1, p (AMG
-        # F-relaxation), then the well system (zero diagonals) as the coarse grid
+    def mimetic_matvec_bytes(sysd):
+        # the library's scalar operator leaves out the exact zeros of the input (diagonal kept)
+        rows = np.repeat(np.arange(sysd["n"]), np.diff(sysd["rp"]))
+        return spmv_bytes(sysd["n"], int(np.count_nonzero((sysd["vals"] != 0.0) | (sysd["ci"] == rows))))
+
+    mim = comp4 = tpfa = ext = frac = fracp = None
+    if args.mimetic_steps > 0:
+        log("generating hybrid mimetic 64^3 ...")
+        sm = W.hybrid_mimetic(64, 64, 64, seed=1)
+        mim = secondary(sm, args.mimetic_steps, "1 level, F = cells (Jacobi), C = faces -> AMG V(1,1)", 20,
+                        reuse=(None, False),
+                        matvec_roof=(mimetic_matvec_bytes,
+                                     "k_spmv_ell<double, 1, SpmvOp> (FGMRES matvec, sliced ELL copy of the CSR, FP64)",
+                                     "k_spmv_fgmres_mimetic64.md"))
+        if args.interp_steps > 0:
+            # the same system with extended+i (distance-two) AMG interpolation
+            log("mimetic 64^3 with extended+i interpolation ...")
+            vm = torch.tensor(sm["vals"], device="cuda")
+            bm = torch.tensor(sm["rhs"], device="cuda")
+            se, re_, _, _, _ = run_steps(P, sm, vm, bm, 64, args.interp_steps, 1, interp="ext+i")
+            hi = se.info()
+            ext = {"workload": sm["name"], "apply": "fp64", "direct": {k: mim["fp64"][k] for k in
+                                                                      ("time_to_tol_s", "iterations")},
+                   "ext+i": stats(re_), "ext+i_amg_nnz": int(sum(a[1] for a in hi["amg_levels"]))}
+            se.close()
+        del sm
+    if args.comp4_steps > 0:
+        # the paper's own four-level order: rho_2, rho_1, p (AMG F-relaxation), then
+        # the well system (zero diagonals) as the coarse grid
         log("generating compositional 4-level 128x128x64 + 16 wells ...")
-        comp4 = secondary(W.compositional_4level(seed=4), args.comp_steps,
+        comp4 = secondary(W.compositional_4level(seed=4), args.comp4_steps,
                           "L1 F = rho_2 (Jacobi, exact), L2 F = rho_1 (Jacobi), L3 F = p (AMG V-cycle), "
                           "coarse = wells (direct)", 10)
-    # ---- secondary: the two reductions of the hybrid system (Sec. 3.1) on its TPFA
-    # variant, where both eliminate a diagonal block: MGR_P (F = cells, faces to
-    # AMG) against MGR_Pi (F = faces, the 7-point cell Schur complement to AMG)
-    tpfa = None
     if args.tpfa_steps > 0:
-        tpfa = {"workload": f"hybrid_mimetic_tpfa_{g}x{g}x{g}", "apply": "fp64"}
+        # the two reductions of the hybrid system (Sec. 3.1) on its TPFA variant, where
+        # both eliminate a diagonal block: MGR_P (F = cells, faces to AMG) against
+        # MGR_Pi (F = faces, the 7-point cell Schur complement to AMG)
+        tpfa = {"workload": "hybrid_mimetic_tpfa_64x64x64", "apply": "fp64"}
         for red, key in (("p", "mgr_p"), ("pi", "mgr_pi")):
-            log(f"generating hybrid mimetic TPFA {g}^3, reduction {key} ...")
-            st = W.hybrid_mimetic(g, g, g, seed=1, consistent=False, reduction=red)
+            log(f"generating hybrid mimetic TPFA 64^3, reduction {key} ...")
+            st = W.hybrid_mimetic(64, 64, 64, seed=1, consistent=False, reduction=red)
             vt = torch.tensor(st["vals"], device="cuda")
             bt = torch.tensor(st["rhs"], device="cuda")
             sv, rt, _, _, _ = run_steps(P, st, vt, bt, 64, args.tpfa_steps, 1)
             hi = sv.info()
-            tpfa[key] = {"time_to_tol_s": round(statistics.mean(a + b for a, b, _, _ in rt), 6),
-                         "setup_s": round(statistics.mean(a for a, _, _, _ in rt), 6),
-                         "solve_s": round(statistics.mean(b for _, b, _, _ in rt), 6),
-                         "iterations": rt[-1][2], "rel_res_true": rt[-1][3],
-                         "coarse_n": hi["amg_levels"][0][0], "coarse_nnz": hi["amg_levels"][0][1],
-                         "amg_levels": len(hi["amg_levels"])}
+            tpfa[key] = dict(stats(rt), coarse_n=hi["amg_levels"][0][0], coarse_nnz=hi["amg_levels"][0][1],
+                             amg_levels=len(hi["amg_levels"]))
             sv.close()
         tpfa["speedup_pi_over_p"] = round(tpfa["mgr_p"]["time_to_tol_s"] / tpfa["mgr_pi"]["time_to_tol_s"], 4)
-
-    # ---- secondary: the same mimetic workload with extended+i (distance-two) AMG
-    # interpolation instead of direct interpolation
-    ext = None
-    if args.interp_steps > 0:
-        log(f"mimetic {g}^3 with extended+i interpolation ...")
-        se, re_, _, _, _ = run_steps(P, s, vals, rhs, 64, args.interp_steps, 1, interp="ext+i")
-        hi, hd = se.info(), solver.info()
-        ext = {"workload": f"hybrid_mimetic_consistent_{g}x{g}x{g}", "apply": "fp64",
-               "direct": {"time_to_tol_s": round(value, 6), "iterations": rec64[-1][2],
-                          "amg_nnz": int(sum(a[1] for a in hd["amg_levels"]))},
-               "ext+i": {"time_to_tol_s": round(statistics.mean(a + b for a, b, _, _ in re_), 6),
-                         "setup_s": round(statistics.mean(a for a, _, _, _ in re_), 6),
-                         "solve_s": round(statistics.mean(b for _, b, _, _ in re_), 6),
-                         "iterations": re_[-1][2], "rel_res_true": re_[-1][3],
-                         "amg_nnz": int(sum(a[1] for a in hi["amg_levels"]))}}
-        se.close()
-
-    # ---- secondary: the fracturing system (Q1 elasticity on 96^3 nodes + a 96 x 96
-    # planar fracture; MGR_U with an unknown-based AMG V-cycle as F-relaxation)
     if args.frac_steps > 0:
+        # the fracturing system (Q1 elasticity on 96^3 nodes + a 96 x 96 planar
+        # fracture) with both reductions of Sec. 3.3
         log("generating fracturing 96^3 ...")
-        frac = secondary(W.fracturing(96, seed=3), args.frac_steps,
-                         "F = displacements (unknown-based AMG V(2,2) F-relaxation), C = fracture pressures -> AMG",
-                         5, reuse=(3, True))
+        sf = W.fracturing(96, seed=3)
+        frac = secondary(sf, args.frac_steps,
+                         "MGR_U: F = displacements (unknown-based AMG V(2,2) F-relaxation), C = fracture pressures "
+                         "-> AMG", 5, reuse=(3, True))
+        sp_ = dict(sf, name=sf["name"] + "_mgr_p", levels=[W.level(1 << 3, "amg")],
+                   solver_opts=dict(nu_pre=2, nu_post=2, unknown_based=True))
+        fracp = secondary(sp_, args.frac_steps,
+                          "MGR_P: F = fracture pressures (AMG V(2,2) F-relaxation), C = displacements -> "
+                          "unknown-based AMG", 5)
+        del sf, sp_
 
-    # ---- FP64 oracle on the box's host cores (bounded sample: one full setup + solve of this workload)
+    # ---- FP64 oracle on the box's host cores, on the headline workload
     cpu = None
     x_err64 = x_err32 = None
-    if not args.no_cpu_baseline:
+    host = {"nproc": len(os.sched_getaffinity(0)), "cpu_model": None}
+    try:
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True).stdout.splitlines():
+            if line.startswith("Model name:"):
+                host["cpu_model"] = line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    if not args.no_cpu_baseline and s is not None:
         import oracle as O
-        log("oracle (CPU, single thread): one setup + solve of the same workload ...")
+        ncores = host["nproc"]
+        O.set_threads(1)
+        log("oracle (CPU): setup (serial), solve on 1 thread, solve on all host cores ...")
         t0 = time.perf_counter()
         om = O.MGR(s["b"], s["rp"], s["ci"], s["vals"], s["field"], [O.LevelOpts(**l) for l in s["levels"]])
         t1 = time.perf_counter()
         xo, io = om.solve(s["rhs"])
         t2 = time.perf_counter()
-        log(f"  oracle setup {t1 - t0:.2f} s, solve {t2 - t1:.2f} s, iters {io.iterations}")
-        cpu = {"value": round(t2 - t0, 4), "unit": "s", "cores": 1, "kind": "oracle",
-               "sample": f"one full setup + FGMRES solve to 1e-8 of the {g}^3 mimetic system "
-                         f"(setup {t1 - t0:.2f} s, solve {t2 - t1:.2f} s, {io.iterations} iterations)"}
+        used = O.set_threads(ncores)
+        t3 = time.perf_counter()
+        xo2, io2 = om.solve(s["rhs"])
+        t4 = time.perf_counter()
+        O.set_threads(1)
+        assert np.array_equal(xo, xo2), "oracle result depends on the thread count"
+        log(f"  oracle setup {t1 - t0:.2f} s, solve {t2 - t1:.2f} s (1 thread), {t4 - t3:.2f} s ({used} threads), "
+            f"iters {io.iterations}")
+        cpu = {"value": round((t1 - t0) + (t4 - t3), 4), "unit": "s", "cores": used, "kind": "oracle",
+               "sample": f"one full setup (serial code) + FGMRES solve to 1e-8 of the headline compositional "
+                         f"system: setup {t1 - t0:.2f} s, solve {t4 - t3:.2f} s on {used} threads, "
+                         f"{io.iterations} iterations",
+               "single_thread": {"value": round(t2 - t0, 4), "setup_s": round(t1 - t0, 4),
+                                 "solve_s": round(t2 - t1, 4)},
+               "host": host}
         nx = np.linalg.norm(xo)
         x_err64 = float(np.linalg.norm(X64.cpu().numpy() - xo) / nx)
         x_err32 = float(np.linalg.norm(X32.cpu().numpy() - xo) / nx)
 
+    head = {}
+    if s is not None:
+        head = {
+            "value": round(value, 6),
+            "ms_per_step": round(1e3 * value, 3),
+            "config": {"workload": s["name"], "n": n, "nnz": int(nnzb * b * b), "block_size": b,
+                       "mgr": "L1 F = components (block-Jacobi), L2 F = wells (Jacobi), coarse pressure AMG V(1,1)",
+                       "rtol": 1e-8, "restart": 50},
+            "setup_s": round(statistics.mean(a for a, _, _, _ in rec64), 6),
+            "solve_s": round(statistics.mean(b_ for _, b_, _, _ in rec64), 6),
+            "iterations": rec64[-1][2],
+            "rel_res_true": rec64[-1][3],
+            "x_rel_err_vs_oracle": x_err64,
+            "setup_reuse": reuse64,
+            "fp32_apply": dict(stats(rec32), x_rel_err_vs_oracle=x_err32,
+                               speedup_time_to_tol=round(value / value32, 4)),
+            "apply": app,
+            "roofline": {"kernel": f"k_bsr_spmv<{b}, 8> (FGMRES matvec y = A x, {b} x {b} block CSR, FP64)",
+                         "bound": "hbm", "achieved": round(mv_bytes / t_mv / 1e9, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(mv_bytes / t_mv / 1e9 / HBM_PEAK_GBS, 4),
+                         "traffic": kernel_traffic("k_bsr_spmv_compositional.md"),
+                         "bytes_per_launch": mv_bytes, "avg_launch_us": round(1e6 * t_mv, 2)},
+        }
     out = {
         "metric": "FGMRES+MGR time-to-1e-8 (s), HBM GB/s; FP32-vs-FP64 apply speedup",
-        "value": round(value, 6),
+        "value": head.pop("value", None),
         "unit": "s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * value, 3),
+        "ms_per_step": head.pop("ms_per_step", None),
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"hybrid_mimetic_consistent_{g}x{g}x{g}", "n": n, "nnz": nnz, "nnz_operator": nnz_op,
-                   "mgr": "1 level, F = cells (Jacobi), C = faces -> AMG V(1,1)", "rtol": 1e-8,
-                   "restart": 50},
-        "setup_s": round(statistics.mean(a for a, _, _, _ in rec64), 6),
-        "solve_s": round(statistics.mean(b for _, b, _, _ in rec64), 6),
-        "iterations": rec64[-1][2],
-        "rel_res_true": rec64[-1][3],
-        "x_rel_err_vs_oracle": x_err64,
-        "setup_reuse": reuse64,
-        "fp32_apply": {
-            "time_to_tol_s": round(statistics.mean(tot32), 6),
-            "setup_s": round(statistics.mean(a for a, _, _, _ in rec32), 6),
-            "solve_s": round(statistics.mean(b for _, b, _, _ in rec32), 6),
-            "iterations": rec32[-1][2],
-            "rel_res_true": rec32[-1][3],
-            "x_rel_err_vs_oracle": x_err32,
-            "speedup_time_to_tol": round(value / statistics.mean(tot32), 4),
-            "apply_ms_fp64": round(1e3 * t_ap64, 4),
-            "apply_ms_fp32": round(1e3 * t_ap32, 4),
-            "speedup_per_apply": round(t_ap64 / t_ap32, 4),
-        },
-        "roofline": {"kernel": "k_spmv_ell<double, 1, SpmvOp> (FGMRES matvec y = A x, sliced ELL copy of the CSR, FP64, "
-                               f"{nnz_op} entries)",
-                     "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": kernel_traffic("k_spmv_fgmres_mimetic64.md"),
-                     "bytes_per_launch": nbytes, "avg_launch_us": round(1e6 * t_spmv, 2)},
-        "secondary_compositional": comp,
-        "secondary_compositional_4level": comp4,
-        "secondary_fracturing": frac,
-        "secondary_mimetic_tpfa_reductions": tpfa,
-        "secondary_mimetic_ext_interp": ext,
-        "cpu_baseline": cpu,
+        "config": head.pop("config", None),
     }
+    out.update(head)
+    out.update({
+        "secondary_mimetic": mim,
+        "secondary_mimetic_ext_interp": ext,
+        "secondary_compositional_4level": comp4,
+        "secondary_mimetic_tpfa_reductions": tpfa,
+        "secondary_fracturing_mgr_u": frac,
+        "secondary_fracturing_mgr_p": fracp,
+        "cpu_baseline": cpu,
+    })
     print(json.dumps(out), flush=True)
-    solver.close()
-    solver32.close()
+    if solver is not None:
+        solver.close()
+        solver32.close()
 
 
 if __name__ == "__main__":

@@ -210,10 +210,17 @@ int mgr_hierarchy_info(mgr_handle h, int64_t *out, int32_t cap);
 /* Copy a piece of the hierarchy to host buffers (all host pointers; pass NULL
  * buffers to query sizes only).  kind 0 = MGR level `level`: what 0 = C/F
  * flags (int32, 1 = C, 0 = F), 1 = coarse operator, 2 = P_F, 3 = R_F, 4 = A_FF,
- * 5 = F-relaxation operator M.  kind 1 = coarse AMG level `level`, kind 2 = the
- * F-relaxation AMG of MGR level `sub`: what 0 = C/F (+1 = C, -1 = F), 1 = A_k,
- * 2 = P_k, 3 = the dense inverse of the coarsest level (level = last; n x n
- * row-major doubles in b2).  sizes[0..2] = rows, cols, nnz (vector length in sizes[0]);
+ * 5 = F-relaxation operator M, 6 = R_J = [-omega A_CF M | I] and 7 = P_J =
+ * [P_F | omega M ; I | 0] (the two operators of the one-sweep apply with
+ * injection, global numbering, columns of P_J: coarse then fine; ARG for a
+ * level applied in general form).  kind 1 = coarse AMG level `level`, kind 2 =
+ * the F-relaxation AMG of MGR level `sub`: what 0 = C/F (+1 = C, -1 = F), 1 =
+ * A_k, 2 = P_k, 3 = the dense inverse of the coarsest level (level = last; n x
+ * n row-major doubles in b2), 4 = G = R - (R A) D^-1 and 5 = [W | Q] (W = 2D^-1
+ * - D^-1 A D^-1, Q = P - D^-1 A P) of a level applied in composed form (ARG
+ * otherwise), 6 = the dense cycle operator W + Q C^-1 G of the composed level
+ * above the coarsest, when its cycle is applied as one GEMV (n x n row-major
+ * doubles in b2; ARG for any other level).  sizes[0..2] = rows, cols, nnz (vector length in sizes[0]);
  * b0 = row_ptr (or the C/F vector), b1 = col_idx, b2 = values (double). */
 int mgr_export(mgr_handle h, int32_t kind, int32_t level, int32_t what, int32_t sub, int64_t *sizes,
                void *b0, void *b1, void *b2);

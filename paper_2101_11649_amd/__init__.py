@@ -285,6 +285,17 @@ class Solver:
         self._check(L.mgr_export(self._h, kind, level, what, sub, P(sizes), P(rp), P(ci), P(v)))
         return nr, nc, rp, ci[:nnz], v[:nnz]
 
+    def export_sizes(self, kind, level, what, sub=-1):
+        """(rows, cols, nnz) of an exported item (mgr_export with no buffers), or
+        None when the hierarchy has no such item (MGR_ERR_ARG)."""
+        sizes = np.zeros(3, np.int64)
+        rc = lib().mgr_export(self._h, kind, level, what, sub, sizes.ctypes.data_as(ctypes.c_void_p), None, None,
+                              None)
+        if rc == -1:
+            return None
+        self._check(rc)
+        return tuple(int(x) for x in sizes)
+
     def coarsest_inverse(self):
         """Dense inverse of the coarse AMG's coarsest level, an (n, n) numpy array."""
         L = lib()

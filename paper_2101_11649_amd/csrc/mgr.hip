@@ -1823,6 +1823,9 @@ static int do_export(Ctx& c, int kind, int level, int what, int sub, int64_t* si
         if (what == 3) A = &l.RF;
         if (what == 4) A = &l.AFF;
         if (what == 5) A = &l.M;
+        if ((what == 6 || what == 7) && !l.fused) throw Error(MGR_ERR_ARG, "level has no fused apply operators");
+        if (what == 6) A = &l.RJ;
+        if (what == 7) A = &l.PJ;
         if (!A) throw Error(MGR_ERR_ARG, "unknown export item");
         export_csr(*A, sizes, b0, b1, b2, s);
         return MGR_OK;
@@ -1841,6 +1844,21 @@ static int do_export(Ctx& c, int kind, int level, int what, int sub, int64_t* si
     }
     if (what == 1) { export_csr(L.A, sizes, b0, b1, b2, s); return MGR_OK; }
     if (what == 2 && level + 1 < (int)H->lv.size()) { export_csr(L.P, sizes, b0, b1, b2, s); return MGR_OK; }
+    if ((what == 4 || what == 5) && level + 1 < (int)H->lv.size()) {
+        // composed form of the level: G, or [W | Q]; the level above the
+        // coarsest whose cycle is one dense operator reports G and [W | Q] too
+        if (!L.composed) throw Error(MGR_ERR_ARG, "level is not applied in composed form");
+        export_csr(what == 4 ? L.G : L.WQ, sizes, b0, b1, b2, s);
+        return MGR_OK;
+    }
+    if (what == 6) {
+        // the dense cycle operator T = W + Q C^-1 G of the level above the coarsest
+        if (level != H->tail) throw Error(MGR_ERR_ARG, "level has no dense cycle operator");
+        sizes[0] = L.n; sizes[1] = L.n; sizes[2] = (int64_t)L.n * L.n;
+        if (b2) MGR_HIP(hipMemcpyAsync(b2, H->td.p, sizeof(double) * L.n * L.n, hipMemcpyDeviceToHost, s));
+        MGR_HIP(hipStreamSynchronize(s));
+        return MGR_OK;
+    }
     if (what == 3 && level + 1 == (int)H->lv.size()) {
         // the coarsest level's dense inverse, n x n row-major in b2
         sizes[0] = H->nc; sizes[1] = H->nc; sizes[2] = (int64_t)H->nc * H->nc;
