@@ -120,9 +120,24 @@ typedef struct {
  * seed 12345.  (host) */
 void mgr_default_opts(mgr_opts *o);
 
+/* Device memory provider of a handle (for instance a framework's caching
+ * allocator).  alloc returns `bytes` of device memory that work ordered on
+ * `stream` may use (NULL on failure); free gives such a pointer back (the
+ * library has synchronised `stream` before it frees).  ctx is passed through. */
+typedef void *(*mgr_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*mgr_free_fn)(void *p, void *stream, void *ctx);
+
 /* Create a handle bound to a HIP stream (NULL = the null stream) on the
- * current device.  o (host) may be NULL for the defaults. */
-int mgr_create(mgr_handle *h, const mgr_opts *o, void *hip_stream);
+ * current device.  o (host) may be NULL for the defaults.  alloc / free_ /
+ * alloc_ctx: the provider of every device array of the handle, or both NULL
+ * for the library's own stream-ordered allocations (hipMallocAsync).  Either
+ * way the handle keeps freed arrays in a cache of its own (by size class) and
+ * hands them out again to later requests on its stream; everything goes back
+ * to the provider in mgr_destroy.  Pinned host buffers (a few KB) are the
+ * library's own.  Errors: ARG (h NULL, invalid options, only one of alloc and
+ * free_ given), OOM, HIP. */
+int mgr_create(mgr_handle *h, const mgr_opts *o, void *hip_stream, mgr_alloc_fn alloc, mgr_free_fn free_,
+               void *alloc_ctx);
 
 /* Replace the solver options (restart, maxiter, rtol, ortho, apply precision)
  * of an existing handle; AMG options take effect at the next mgr_setup. (host o) */
@@ -133,6 +148,12 @@ int mgr_set_opts(mgr_handle h, const mgr_opts *o);
  * (Jacobi interpolation, eq. (4), ideal when A_FF is (block-)diagonal, eq. (3)),
  * R~ by lvl[l].restrict_type, coarse operator R~ A P~; then AMG on the last
  * coarse system.  field_of_dof: n labels in [0, 32).  lvl: (host) nlevels.
+ * block_of_dof: n group ids for MGR_FRELAX_BLOCK_JACOBI, or NULL for the block
+ * row of the input layout (i / b); on every level a block is a maximal run of
+ * consecutive F-points (in the order of the unknowns) with one id, so a group
+ * should hold consecutive unknowns (the F-points of a b = 1 input's cell, for
+ * instance); a block of more than 4 F-points is UNSUPPORTED.  Copied; kept for
+ * mgr_update_values.
  * The handle owns all the device memory of the hierarchy; operators with
  * short, nearly uniform rows (at least 32768 rows of at most 16 entries) also
  * get a sliced ELL copy for their SpMVs, made on first use, when it exceeds
@@ -142,7 +163,7 @@ int mgr_set_opts(mgr_handle h, const mgr_opts *o);
  * level above 2048 unknowns, an extended+i interpolatory set above 256
  * points), OOM, HIP. */
 int mgr_setup(mgr_handle h, const mgr_matrix *A, const int32_t *field_of_dof, int32_t nlevels,
-              const mgr_level_opts *lvl);
+              const mgr_level_opts *lvl, const int32_t *block_of_dof);
 
 /* Setup reuse for a new matrix on the same pattern, as between the Newton
  * solves of a simulation (AMG data reuse, Sec. 3.3 and Sec. 4.4).  values:

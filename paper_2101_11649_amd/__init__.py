@@ -67,6 +67,33 @@ class mgr_solve_info(ctypes.Structure):
                 ("rel_res_est", ctypes.c_double), ("rel_res_true", ctypes.c_double)]
 
 
+# Device memory provider passed to mgr_create: torch's caching allocator, so
+# the solver's arrays come from (and go back to) the same pool as the caller's
+# tensors.  The callbacks run while the library holds the call; they take the
+# GIL themselves (ctypes) and must not raise across the ABI.
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+def _torch_alloc(nbytes, stream, ctx):
+    try:
+        import torch
+        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception:
+        return None
+
+
+def _torch_free(ptr, stream, ctx):
+    try:
+        import torch
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass
+
+
+TORCH_ALLOC = _ALLOC_FN(_torch_alloc)
+TORCH_FREE = _FREE_FN(_torch_free)
+
 _lib = None
 
 
@@ -80,9 +107,9 @@ def lib():
         P, i32 = ctypes.c_void_p, ctypes.c_int32
         L.mgr_default_opts.argtypes = [ctypes.POINTER(mgr_opts)]
         L.mgr_default_opts.restype = None
-        L.mgr_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(mgr_opts), P]
+        L.mgr_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(mgr_opts), P, _ALLOC_FN, _FREE_FN, P]
         L.mgr_set_opts.argtypes = [P, ctypes.POINTER(mgr_opts)]
-        L.mgr_setup.argtypes = [P, ctypes.POINTER(mgr_matrix), P, i32, ctypes.POINTER(mgr_level_opts)]
+        L.mgr_setup.argtypes = [P, ctypes.POINTER(mgr_matrix), P, i32, ctypes.POINTER(mgr_level_opts), P]
         L.mgr_update_values.argtypes = [P, P, i32]
         L.mgr_apply.argtypes = [P, P, P]
         L.mgr_apply_transpose.argtypes = [P, P, P]
@@ -141,7 +168,7 @@ class Solver:
 
     def __init__(self, b, rp, ci, vals, field, levels, precision=64, restart=50, maxiter=1000, rtol=1e-8,
                  theta=0.25, max_levels=25, max_coarse=128, nu_pre=1, nu_post=1, unknown_based=False, seed=12345,
-                 interp="direct"):
+                 interp="direct", block=None, allocator="torch"):
         torch = _torch()
         L = lib()
         self._h = ctypes.c_void_p()
@@ -151,7 +178,14 @@ class Solver:
                         max_levels=max_levels, max_coarse=max_coarse, nu_pre=nu_pre, nu_post=nu_post,
                         unknown_based=unknown_based, seed=seed, interp=interp)
         self.stream = torch.cuda.current_stream()
-        self._check(L.mgr_create(ctypes.byref(self._h), ctypes.byref(self.opts), ctypes.c_void_p(self.stream.cuda_stream)))
+        if allocator == "torch":
+            fa, ff = TORCH_ALLOC, TORCH_FREE
+        elif allocator is None:
+            fa, ff = _ALLOC_FN(), _FREE_FN()        # NULL: the library's own stream-ordered allocations
+        else:
+            raise ValueError("allocator must be 'torch' or None")
+        self._check(L.mgr_create(ctypes.byref(self._h), ctypes.byref(self.opts),
+                                 ctypes.c_void_p(self.stream.cuda_stream), fa, ff, None))
         self.b = int(b)
         self.rp = _dev(rp, torch.int32)
         self.ci = _dev(ci, torch.int32)
@@ -160,6 +194,7 @@ class Solver:
         self.nnzb = int(self.rp[-1].item())
         self.levels = list(levels)
         self.field = _dev(field, torch.int32)
+        self.block = None if block is None else _dev(block, torch.int32)
         self.setup(vals)
 
     def _fill_opts(self, precision=None, restart=None, maxiter=None, rtol=None, theta=None, max_levels=None,
@@ -195,7 +230,8 @@ class Solver:
                                     float(lv.get("omega", 1.0)), RESTRICT[lv.get("restrict", "injection")],
                                     int(bool(lv.get("amg_unknown_based", False))))
         self._check(lib().mgr_setup(self._h, ctypes.byref(A), ctypes.c_void_p(self.field.data_ptr()),
-                                    len(self.levels), arr))
+                                    len(self.levels), arr,
+                                    None if self.block is None else ctypes.c_void_p(self.block.data_ptr())))
 
     def update_values(self, vals, keep_frelax_amg=False):
         """Setup reuse for new values on the same pattern (mgr_update_values):

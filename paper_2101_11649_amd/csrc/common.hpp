@@ -12,6 +12,8 @@
 #include <utility>
 #include <vector>
 
+#include "mgr.h"
+
 namespace mgr {
 
 // Errors carry one of the MGR_ERR_* codes of mgr.h.
@@ -47,6 +49,10 @@ inline void check_may_allocate() {
 // with the context until it is destroyed.
 struct BlockCache {
     hipStream_t s = nullptr;
+    // the caller's device memory provider, if one was given to mgr_create
+    mgr_alloc_fn af = nullptr;
+    mgr_free_fn ff = nullptr;
+    void* actx = nullptr;
     std::multimap<size_t, void*> free_;
     std::vector<void*> owned_;
     // 256-byte granules up to 4 KiB, then four classes per power of two
@@ -67,14 +73,23 @@ struct BlockCache {
             return q;
         }
         void* q = nullptr;
-        MGR_HIP(hipMallocAsync(&q, cls, s));
+        if (af) {
+            q = af(cls, (void*)s, actx);
+            if (!q) throw Error(MGR_ERR_OOM, "the caller's allocator returned no memory for " + std::to_string(cls) +
+                                                 " bytes");
+        } else {
+            MGR_HIP(hipMallocAsync(&q, cls, s));
+        }
         owned_.push_back(q);
         return q;
     }
     void put(void* q, size_t cls) { free_.emplace(cls, q); }
-    // every block goes back to the runtime (the caller has synchronised s)
+    // every block goes back to where it came from (the caller has synchronised s)
     void release() {
-        for (void* q : owned_) (void)hipFreeAsync(q, s);
+        for (void* q : owned_) {
+            if (ff) ff(q, (void*)s, actx);
+            else (void)hipFreeAsync(q, s);
+        }
         owned_.clear();
         free_.clear();
     }

@@ -313,12 +313,21 @@ __global__ void k_frelax_starts(int nF, const int* __restrict__ flagk, const int
     if (k == nF - 1) bstart[excl[nF]] = nF;
 }
 
+// Row lengths of M: the size of the row's block, at most 4.  A larger block
+// (caller-supplied groups) is flagged unsupported and its rows get a single
+// (zero) entry, so that M stays small and valid until the flag is read.
 __global__ void k_frelax_len(int nF, const int* __restrict__ bnum, const int* __restrict__ bstart,
-                             int* __restrict__ len) {
+                             int* __restrict__ len, int* __restrict__ flag) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nF) return;
     int b = bnum[k];
-    len[k] = bstart[b + 1] - bstart[b];
+    const int bs = bstart[b + 1] - bstart[b];
+    if (bs > 4) {
+        len[k] = 1;
+        if (k == bstart[b]) set_flag(flag, 6);
+    } else {
+        len[k] = bs;
+    }
 }
 
 // Inverse of one BS x BS diagonal block by Gauss-Jordan with partial pivoting
@@ -432,14 +441,15 @@ __global__ __launch_bounds__(TPB) void k_frelax_fill(int nb, const int* __restri
         case 3: frelax_block<3>(s0, gl, gbase, arp, aci, av, mrp, mci, mv, flag); break;
         case 4: frelax_block<4>(s0, gl, gbase, arp, aci, av, mrp, mci, mv, flag); break;
         default:
+            // a block larger than 4 (flagged by k_frelax_len): one zero entry
+            // per row on its diagonal, a valid column for the products that
+            // may read M before the flag is seen
             if (gl == 0) {
                 set_flag(flag, 6);
                 for (int r = 0; r < bs; ++r) {
                     int o = mrp[s0 + r];
-                    for (int c = 0; c < bs; ++c) {
-                        mci[o + c] = s0 + c;
-                        mv[o + c] = 0.0;
-                    }
+                    mci[o] = s0 + r;
+                    mv[o] = 0.0;
                 }
             }
     }
@@ -2488,9 +2498,9 @@ void frelax_block_starts(int nF, const int* flagk, const int* excl, int* bstart,
     MGR_LAUNCH_CHECK();
 }
 
-void frelax_row_len(int nF, const int* bnum, const int* bstart, int* len, hipStream_t s) {
+void frelax_row_len(int nF, const int* bnum, const int* bstart, int* len, int* flag, hipStream_t s) {
     if (nF <= 0) return;
-    k_frelax_len<<<nblk(nF), TPB, 0, s>>>(nF, bnum, bstart, len);
+    k_frelax_len<<<nblk(nF), TPB, 0, s>>>(nF, bnum, bstart, len, flag);
     MGR_LAUNCH_CHECK();
 }
 

@@ -46,7 +46,7 @@ void extract_fill(const DCsr& A, const int* isF, const int* lmap, DCsr& FF, DCsr
 // (Jacobi: every point its own block).  bstart gets nb+1 entries.
 void frelax_block_flags(int nF, const int* bid, int* flagk, hipStream_t s);
 void frelax_block_starts(int nF, const int* flagk, const int* excl, int* bstart, int* bnum, hipStream_t s);
-void frelax_row_len(int nF, const int* bnum, const int* bstart, int* len, hipStream_t s);
+void frelax_row_len(int nF, const int* bnum, const int* bstart, int* len, int* flag, hipStream_t s);
 void frelax_fill(int nb, const int* bstart, const DCsr& AFF, DCsr& M, int* flag, hipStream_t s);
 
 // C = A B counts; rows of A longer than the variant chosen by max_row get a zero

@@ -810,6 +810,7 @@ struct Ctx {
     // setup inputs kept for mgr_update_values: field labels and level options,
     // and the labels' histogram (pinned; it sizes every level's F and C sets)
     DArr<int> field0, fhist;
+    DArr<int> block0;   // block-Jacobi group of every unknown (empty: its block row)
     int* fhist_h = nullptr;
     std::vector<mgr_level_opts> lvl;
     // hierarchies handed from the previous setup to the one being formed
@@ -891,7 +892,7 @@ static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr& A, const int* field
     long long* sB = S.take(2);
     scan_async(flagk.p, excl.p, l.nF, sB, s);
     frelax_block_starts(l.nF, flagk.p, excl.p, bstart.p, bnum.p, s);
-    frelax_row_len(l.nF, bnum.p, bstart.p, len.p, s);
+    frelax_row_len(l.nF, bnum.p, bstart.p, len.p, S.flag(), s);
     Pend pM = csr_begin(l.M, l.nF, l.nF, len.p, S);
     S.sync("block extraction");
     if (S.val(sF) != l.nF) throw Error(MGR_ERR_ARG, "internal: F-point count differs from the label histogram");
@@ -1656,7 +1657,8 @@ static void expand_input(Ctx& c) {
     bsr_fill(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, c.Av.p, c.A0, s);
 }
 
-static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nlevels, const mgr_level_opts* lvl) {
+static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nlevels, const mgr_level_opts* lvl,
+                  const int32_t* block) {
     hipStream_t s = c.s;
     if (!A || !field) throw Error(MGR_ERR_ARG, "null matrix or field array");
     if (A->block_size < 1 || A->block_size > 4) throw Error(MGR_ERR_ARG, "block_size must be 1..4");
@@ -1688,6 +1690,12 @@ static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nle
     if (c.nnzb * bb > INT_MAX) throw Error(MGR_ERR_UNSUPPORTED, "more than 2^31 scalar entries");
     c.field0.alloc((size_t)c.n, s);
     MGR_HIP(hipMemcpyAsync(c.field0.p, field, sizeof(int) * c.n, hipMemcpyDeviceToDevice, s));
+    if (block) {
+        c.block0.alloc((size_t)c.n, s);
+        MGR_HIP(hipMemcpyAsync(c.block0.p, block, sizeof(int) * c.n, hipMemcpyDeviceToDevice, s));
+    } else {
+        c.block0.reset();
+    }
     // the label histogram reaches the host with the input matrix's sync
     if (!c.fhist_h) MGR_HIP(hipHostMalloc(reinterpret_cast<void**>(&c.fhist_h), sizeof(int) * 32, hipHostMallocDefault));
     c.fhist.alloc(32, s);
@@ -1707,7 +1715,8 @@ static void build_hierarchy(Ctx& c) {
     const mgr_level_opts* lvl = c.lvl.data();
     DArr<int> fld((size_t)c.n, s), blk((size_t)c.n, s);
     MGR_HIP(hipMemcpyAsync(fld.p, c.field0.p, sizeof(int) * c.n, hipMemcpyDeviceToDevice, s));
-    iota_div(c.n, c.b, blk.p, s);
+    if (c.block0.p) MGR_HIP(hipMemcpyAsync(blk.p, c.block0.p, sizeof(int) * c.n, hipMemcpyDeviceToDevice, s));
+    else iota_div(c.n, c.b, blk.p, s);
     const DCsr* cur = &c.A0;
     DCsr next;
     c.L.resize(nlevels);
@@ -1928,9 +1937,11 @@ static int check_opts(const mgr_opts* o) {
     return MGR_OK;
 }
 
-int mgr_create(mgr_handle* h, const mgr_opts* o, void* hip_stream) {
+int mgr_create(mgr_handle* h, const mgr_opts* o, void* hip_stream, mgr_alloc_fn alloc, mgr_free_fn free_,
+               void* alloc_ctx) {
     if (!h) return MGR_ERR_ARG;
     *h = nullptr;
+    if ((alloc == nullptr) != (free_ == nullptr)) return MGR_ERR_ARG;
     mgr_opts d;
     mgr_default_opts(&d);
     if (o) {
@@ -1941,7 +1952,13 @@ int mgr_create(mgr_handle* h, const mgr_opts* o, void* hip_stream) {
     if (!c) return MGR_ERR_OOM;
     c->c.s = (hipStream_t)hip_stream;
     c->c.cache.s = c->c.s;
+    c->c.cache.af = alloc;
+    c->c.cache.ff = free_;
+    c->c.cache.actx = alloc_ctx;
     c->c.o = d;
+    // the handle's own arrays made here come from its block cache too
+    mgr::BlockCache* prev_cache = mgr::tl_cache;
+    mgr::tl_cache = &c->c.cache;
     try {
         // keep freed blocks in the stream-ordered pool across synchronisations:
         // a setup re-allocates the same sizes every time it runs
@@ -1959,10 +1976,16 @@ int mgr_create(mgr_handle* h, const mgr_opts* o, void* hip_stream) {
         c->c.saved_f.reserve(4096);
         hipError_t e = hipStreamSynchronize(c->c.s);
         if (e != hipSuccess) throw Error(MGR_ERR_HIP, hipGetErrorString(e));
+    } catch (const Error& e) {
+        mgr::tl_cache = prev_cache;
+        delete c;
+        return e.code;
     } catch (...) {
+        mgr::tl_cache = prev_cache;
         delete c;
         return MGR_ERR_HIP;
     }
+    mgr::tl_cache = prev_cache;
     *h = c;
     return MGR_OK;
 }
@@ -1978,9 +2001,9 @@ int mgr_set_opts(mgr_handle h, const mgr_opts* o) {
 }
 
 int mgr_setup(mgr_handle h, const mgr_matrix* A, const int32_t* field_of_dof, int32_t nlevels,
-              const mgr_level_opts* lvl) {
+              const mgr_level_opts* lvl, const int32_t* block_of_dof) {
     return guarded(h, [&]() {
-        mgr::setup(h->c, A, field_of_dof, nlevels, lvl);
+        mgr::setup(h->c, A, field_of_dof, nlevels, lvl, block_of_dof);
         return MGR_OK;
     });
 }

@@ -99,7 +99,7 @@ def test_update_errors():
     import paper_2101_11649_amd as P
     L = P.lib()
     h = ctypes.c_void_p()
-    assert L.mgr_create(ctypes.byref(h), None, None) == 0
+    assert L.mgr_create(ctypes.byref(h), None, None, P._ALLOC_FN(), P._FREE_FN(), None) == 0
     buf = torch.zeros(4, dtype=torch.float64, device="cuda")
     say("[reuse] update before setup")
     assert L.mgr_update_values(h, ctypes.c_void_p(buf.data_ptr()), 0) == -1
