@@ -23,6 +23,7 @@ _SRC = os.path.join(_HERE, "mgr_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 FRELAX = {"jacobi": 0, "block_jacobi": 1, "ilu0": 2, "amg": 3}
+SMOOTHER = {"l1-jacobi": 0, "hybrid-gs": 1}
 RESTRICT = {"injection": 0, "jacobi": 1}
 
 
@@ -50,11 +51,11 @@ def lib():
         P = ctypes.c_void_p
         i32, f64, u64 = ctypes.c_int, ctypes.c_double, ctypes.c_ulonglong
         L.orc_setup.restype = P
-        L.orc_setup.argtypes = [i32, i32, P, P, P, P, i32, P, P, P, P, P, P, f64, i32, i32, i32, i32, i32, i32, u64,
-                                P, P]
+        L.orc_setup.argtypes = [i32, i32, P, P, P, P, i32, P, P, P, P, P, P, f64, i32, i32, i32, i32, i32, i32, i32,
+                                i32, u64, P, P]
         L.orc_update.restype = P
         L.orc_update.argtypes = [P, i32, i32, P, P, P, P, i32, P, P, P, P, P, P, f64, i32, i32, i32, i32, i32, i32,
-                                 u64, P, i32, P]
+                                 i32, i32, u64, P, i32, P]
         L.orc_free.argtypes = [P]
         L.orc_apply.argtypes = [P, P, P, i32]
         L.orc_matvec.argtypes = [P, P, P, i32]
@@ -282,11 +283,14 @@ class MGR:
     interpolation, also used by the F-relaxation AMG hierarchies).  ``block``:
     optional group id of every scalar unknown for block-Jacobi F-relaxation
     (a block is a run of consecutive F-points with one id); default: the
-    block row of the input layout.
+    block row of the input layout.  ``smoother``: the AMG smoother, "l1-jacobi"
+    or "hybrid-gs" (hybrid L1 Gauss-Seidel, forward on the way down and
+    backward on the way up, over chunks of ``chunk`` consecutive rows).
     """
 
     def __init__(self, b, rp, ci, vals, field, levels, theta=0.25, max_levels=25, max_coarse=128,
-                 nu_pre=1, nu_post=1, coarse_unknown_based=False, seed=12345, interp="direct", block=None):
+                 nu_pre=1, nu_post=1, coarse_unknown_based=False, seed=12345, interp="direct", block=None,
+                 smoother="l1-jacobi", chunk=32):
         L = lib()
         self.b = int(b)
         self.rp, self.ci, self.vals = _i32(rp), _i32(ci), _f64(vals)
@@ -301,7 +305,7 @@ class MGR:
         aub = _i32([int(lv.amg_unknown_based) for lv in levels] or [0])
         self._lv = (nl, fmask, frelax, sweeps, omega, restr, aub)
         self._amg = (float(theta), int(max_levels), int(max_coarse), int(nu_pre), int(nu_post),
-                     int(coarse_unknown_based), INTERP[interp], int(seed))
+                     int(coarse_unknown_based), INTERP[interp], SMOOTHER[smoother], int(chunk), int(seed))
         self.block = None if block is None else _i32(block)
         st = ctypes.c_int(0)
         self.h = L.orc_setup(self.b, len(self.rp) - 1, _p(self.rp), _p(self.ci), _p(self.vals), _p(self.field),

@@ -48,6 +48,8 @@
 #define ORC_ERR_UNSUPPORTED (-6)
 #define AMG_INTERP_DIRECT 0
 #define AMG_INTERP_EXT_I 1
+#define AMG_SMOOTH_L1_JACOBI 0
+#define AMG_SMOOTH_HYBRID_GS 1
 
 #define FRELAX_JACOBI 0
 #define FRELAX_BLOCK_JACOBI 1
@@ -665,6 +667,8 @@ typedef struct {
     double theta;
     int max_levels, max_coarse, nu_pre, nu_post, unknown_based;
     int interp;             /* AMG_INTERP_DIRECT or AMG_INTERP_EXT_I */
+    int smoother;           /* AMG_SMOOTH_L1_JACOBI or AMG_SMOOTH_HYBRID_GS */
+    int chunk;              /* rows per chunk of the hybrid Gauss-Seidel smoother */
     uint64_t seed;
 } AmgOpts;
 
@@ -675,6 +679,8 @@ typedef struct {
     int *cf[MAX_AMG_LEVELS];
     int *label[MAX_AMG_LEVELS];
     double *dl1[MAX_AMG_LEVELS];      /* L1 diagonal a_ii + sum_{j!=i} |a_ij|   */
+    double *dgs[MAX_AMG_LEVELS];      /* hybrid GS diagonal a_ii + sum_{j outside i's chunk} |a_ij| */
+    int smoother, chunk;
     int nu_pre, nu_post;
     int nc;                           /* coarsest size                         */
     double *lu;
@@ -686,7 +692,9 @@ static void amg_free(Amg *h) {
     if (!h) return;
     for (int k = 0; k < h->nlev; ++k) {
         csr_free(&h->A[k]); csr_free(&h->AT[k]);
-        if (k < h->nlev - 1) { csr_free(&h->P[k]); csr_free(&h->R[k]); free(h->cf[k]); free(h->dl1[k]); }
+        if (k < h->nlev - 1) {
+            csr_free(&h->P[k]); csr_free(&h->R[k]); free(h->cf[k]); free(h->dl1[k]); free(h->dgs[k]);
+        }
         free(h->label[k]);
         free(h->wb[k]); free(h->wx[k]); free(h->wr[k]);
     }
@@ -705,6 +713,7 @@ static int amg_l1_diag(Amg *h, int k);
 static int amg_setup(const Csr *a0, const int *label0, const AmgOpts *o, Amg **out) {
     Amg *h = (Amg *)xcalloc(1, sizeof(Amg));
     h->nu_pre = o->nu_pre; h->nu_post = o->nu_post;
+    h->smoother = o->smoother; h->chunk = o->chunk;
     h->A[0] = csr_copy(a0);
     if (o->unknown_based && label0) {
         h->label[0] = (int *)xmalloc((size_t)a0->nr * sizeof(int));
@@ -787,6 +796,21 @@ static int amg_l1_diag(Amg *h, int k) {
         h->dl1[k][i] = aii + s;
         if (!(h->dl1[k][i] > 0.0)) status = ORC_ERR_UNSUPPORTED;
     }
+    if (h->smoother == AMG_SMOOTH_HYBRID_GS) {
+        /* the hybrid smoother's l1 term covers only the entries outside the row's chunk */
+        h->dgs[k] = (double *)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+        for (int i = 0; i < n; ++i) {
+            int c0 = i / h->chunk * h->chunk, c1 = c0 + h->chunk;
+            double s = 0.0, aii = 0.0;
+            for (int q = a->rp[i]; q < a->rp[i + 1]; ++q) {
+                int j = a->ci[q];
+                if (j == i) aii = a->v[q];
+                else if (j < c0 || j >= c1) s += fabs(a->v[q]);
+            }
+            h->dgs[k][i] = aii + s;
+            if (!(h->dgs[k][i] > 0.0)) status = ORC_ERR_UNSUPPORTED;
+        }
+    }
     return status;
 }
 
@@ -797,6 +821,7 @@ static int amg_l1_diag(Amg *h, int k) {
 static int amg_reuse(const Csr *a0, const Amg *old, Amg **out) {
     Amg *h = (Amg *)xcalloc(1, sizeof(Amg));
     h->nu_pre = old->nu_pre; h->nu_post = old->nu_post;
+    h->smoother = old->smoother; h->chunk = old->chunk;
     h->A[0] = csr_copy(a0);
     int status = ORC_OK, k = 0;
     if (old->label[0]) {
@@ -829,6 +854,7 @@ static int amg_reuse(const Csr *a0, const Amg *old, Amg **out) {
 static Amg *amg_clone(const Amg *old) {
     Amg *h = (Amg *)xcalloc(1, sizeof(Amg));
     h->nu_pre = old->nu_pre; h->nu_post = old->nu_post;
+    h->smoother = old->smoother; h->chunk = old->chunk;
     h->nlev = old->nlev; h->nc = old->nc;
     for (int k = 0; k < old->nlev; ++k) {
         int n = old->A[k].nr;
@@ -845,6 +871,10 @@ static Amg *amg_clone(const Amg *old) {
             memcpy(h->cf[k], old->cf[k], (size_t)n * sizeof(int));
             h->dl1[k] = (double *)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(double));
             memcpy(h->dl1[k], old->dl1[k], (size_t)n * sizeof(double));
+            if (old->dgs[k]) {
+                h->dgs[k] = (double *)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+                memcpy(h->dgs[k], old->dgs[k], (size_t)n * sizeof(double));
+            }
         }
     }
     h->wb = (double **)xcalloc((size_t)h->nlev, sizeof(double *));
@@ -872,6 +902,46 @@ static void l1_sweep(const Csr *a, const double *d, const double *b, double *x, 
     for (int i = 0; i < a->nr; ++i) x[i] += r[i] / d[i];
 }
 
+/* One sweep of hybrid L1 Gauss-Seidel (Baker, Falgout, Kolev, Yang, SIAM J.
+ * Sci. Comput. 33 (2011)), the smoother of the paper's AMG settings (Sec. 4.1),
+ * with chunks of `chunk` consecutive rows in place of the processors' row
+ * blocks: inside a chunk the rows are relaxed one after another, in increasing
+ * order (forward) or decreasing order (backward), each with the values this
+ * sweep already gave the chunk's earlier rows and the previous values of every
+ * other unknown; the diagonal d_i is a_ii plus the l1 norm of row i's entries
+ * outside its chunk.  With chunk = 1 this is the L1-Jacobi sweep; with one
+ * chunk, sequential Gauss-Seidel.  xold: scratch of n entries. */
+static void hgs_sweep(const Csr *a, const double *d, int chunk, const double *b, double *x, double *xold,
+                      int backward) {
+    int n = a->nr;
+    memcpy(xold, x, (size_t)n * sizeof(double));
+    int nch = (n + chunk - 1) / chunk;
+    #pragma omp parallel for schedule(static) if (PAR_OK(n))
+    for (int c = 0; c < nch; ++c) {
+        int c0 = c * chunk, c1 = c0 + chunk < n ? c0 + chunk : n;
+        for (int t = 0; t < c1 - c0; ++t) {
+            int i = backward ? c1 - 1 - t : c0 + t;
+            double s = 0.0;
+            for (int p = a->rp[i]; p < a->rp[i + 1]; ++p) {
+                int j = a->ci[p];
+                int fresh = backward ? (j > i && j < c1) : (j >= c0 && j < i);
+                s += a->v[p] * (fresh ? x[j] : xold[j]);
+            }
+            x[i] = xold[i] + (b[i] - s) / d[i];
+        }
+    }
+}
+
+/* Pre-smoothing (post = 0: L1-Jacobi, or forward hybrid Gauss-Seidel) and
+ * post-smoothing (post = 1: L1-Jacobi, or backward hybrid Gauss-Seidel) on
+ * level k; the transposed cycle passes A^T with the same row-based diagonals
+ * and the same directions (the transpose of a backward sweep on A is a forward
+ * sweep on A^T). */
+static void amg_smooth(const Amg *h, int k, const Csr *a, const double *b, double *x, double *r, int post) {
+    if (h->smoother == AMG_SMOOTH_HYBRID_GS) hgs_sweep(a, h->dgs[k], h->chunk, b, x, r, post);
+    else l1_sweep(a, h->dl1[k], b, x, r);
+}
+
 /* V(nu_pre, nu_post) cycle from a zero initial guess.  trans = 1 applies the
  * exact transpose: A^T on every level, sweep counts swapped, coarse LU^T. */
 static void amg_vcycle(Amg *h, int k, const double *b, double *x, int trans) {
@@ -882,7 +952,7 @@ static void amg_vcycle(Amg *h, int k, const double *b, double *x, int trans) {
     double *r = h->wr[k];
     #pragma omp parallel for schedule(static) if (PAR_OK(n))
     for (int i = 0; i < n; ++i) x[i] = 0.0;
-    for (int s = 0; s < npre; ++s) l1_sweep(a, h->dl1[k], b, x, r);
+    for (int s = 0; s < npre; ++s) amg_smooth(h, k, a, b, x, r, 0);
     csr_residual(a, b, x, r);
     double *bc = h->wb[k + 1], *xc = h->wx[k + 1];
     csr_matvec(&h->R[k], r, bc);
@@ -894,7 +964,7 @@ static void amg_vcycle(Amg *h, int k, const double *b, double *x, int trans) {
         for (int q = p->rp[i]; q < p->rp[i + 1]; ++q) s += p->v[q] * xc[p->ci[q]];
         x[i] += s;
     }
-    for (int s = 0; s < npost; ++s) l1_sweep(a, h->dl1[k], b, x, r);
+    for (int s = 0; s < npost; ++s) amg_smooth(h, k, a, b, x, r, 1);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -1408,17 +1478,17 @@ static void *setup_impl(int b, int nbr, const int *rp, const int *ci, const doub
                         int nlevels, const unsigned *fmask, const int *frelax, const int *sweeps,
                         const double *omega, const int *restrict_type, const int *amg_unknown_based_lvl,
                         double theta, int max_levels, int max_coarse, int nu_pre, int nu_post,
-                        int coarse_unknown_based, int interp, unsigned long long seed, const int *block_of_dof,
+                        int coarse_unknown_based, int interp, int smoother, int chunk, unsigned long long seed, const int *block_of_dof,
                         const void *reuse_from, int keep_famg, int *status);
 
 void *orc_setup(int b, int nbr, const int *rp, const int *ci, const double *val, const int *field, int nlevels,
                 const unsigned *fmask, const int *frelax, const int *sweeps, const double *omega,
                 const int *restrict_type, const int *amg_unknown_based_lvl, double theta, int max_levels,
-                int max_coarse, int nu_pre, int nu_post, int coarse_unknown_based, int interp, unsigned long long seed,
+                int max_coarse, int nu_pre, int nu_post, int coarse_unknown_based, int interp, int smoother, int chunk, unsigned long long seed,
                 const int *block_of_dof, int *status) {
     return setup_impl(b, nbr, rp, ci, val, field, nlevels, fmask, frelax, sweeps, omega, restrict_type,
                       amg_unknown_based_lvl, theta, max_levels, max_coarse, nu_pre, nu_post, coarse_unknown_based,
-                      interp, seed, block_of_dof, NULL, 0, status);
+                      interp, smoother, chunk, seed, block_of_dof, NULL, 0, status);
 }
 
 /* Setup reuse for new values on the same pattern (the AMG data reuse between
@@ -1430,18 +1500,18 @@ void *orc_setup(int b, int nbr, const int *rp, const int *ci, const double *val,
 void *orc_update(const void *old, int b, int nbr, const int *rp, const int *ci, const double *val, const int *field,
                  int nlevels, const unsigned *fmask, const int *frelax, const int *sweeps, const double *omega,
                  const int *restrict_type, const int *amg_unknown_based_lvl, double theta, int max_levels,
-                 int max_coarse, int nu_pre, int nu_post, int coarse_unknown_based, int interp,
-                 unsigned long long seed, const int *block_of_dof, int keep_famg, int *status) {
+                 int max_coarse, int nu_pre, int nu_post, int coarse_unknown_based, int interp, int smoother,
+                 int chunk, unsigned long long seed, const int *block_of_dof, int keep_famg, int *status) {
     return setup_impl(b, nbr, rp, ci, val, field, nlevels, fmask, frelax, sweeps, omega, restrict_type,
                       amg_unknown_based_lvl, theta, max_levels, max_coarse, nu_pre, nu_post, coarse_unknown_based,
-                      interp, seed, block_of_dof, old, keep_famg, status);
+                      interp, smoother, chunk, seed, block_of_dof, old, keep_famg, status);
 }
 
 static void *setup_impl(int b, int nbr, const int *rp, const int *ci, const double *val, const int *field,
                         int nlevels, const unsigned *fmask, const int *frelax, const int *sweeps,
                         const double *omega, const int *restrict_type, const int *amg_unknown_based_lvl,
                         double theta, int max_levels, int max_coarse, int nu_pre, int nu_post,
-                        int coarse_unknown_based, int interp, unsigned long long seed, const int *block_of_dof,
+                        int coarse_unknown_based, int interp, int smoother, int chunk, unsigned long long seed, const int *block_of_dof,
                         const void *reuse_from, int keep_famg, int *status) {
     const Handle *old = (const Handle *)reuse_from;
     Handle *h = (Handle *)xcalloc(1, sizeof(Handle));
@@ -1454,7 +1524,10 @@ static void *setup_impl(int b, int nbr, const int *rp, const int *ci, const doub
     m->b = b; m->nbr = nbr;
     *status = ORC_OK;
     if (nlevels < 0 || nlevels > MAX_MGR_LEVELS) { *status = ORC_ERR_ARG; return h; }
-    AmgOpts ao = {theta, max_levels, max_coarse, nu_pre, nu_post, coarse_unknown_based, interp, (uint64_t)seed};
+    if (smoother != AMG_SMOOTH_L1_JACOBI && smoother != AMG_SMOOTH_HYBRID_GS) { *status = ORC_ERR_ARG; return h; }
+    if (chunk < 1) { *status = ORC_ERR_ARG; return h; }
+    AmgOpts ao = {theta, max_levels, max_coarse, nu_pre, nu_post, coarse_unknown_based, interp, smoother, chunk,
+                  (uint64_t)seed};
     /* block-Jacobi groups: the caller's group id of every unknown, else its block row */
     int *gblock = (int *)xmalloc((size_t)n * sizeof(int));
     for (int i = 0; i < n; ++i) gblock[i] = block_of_dof ? block_of_dof[i] : i / b;

@@ -59,7 +59,8 @@ def oracle_mgr(s, levels=None, **kw):
     if "unknown_based" in kw:     # the binding's name for the coarse AMG's unknown-based option
         kw["coarse_unknown_based"] = kw.pop("unknown_based")
     kw = {k: v for k, v in kw.items() if k in ("theta", "max_levels", "max_coarse", "nu_pre", "nu_post",
-                                                         "coarse_unknown_based", "seed", "interp", "block")}
+                                                         "coarse_unknown_based", "seed", "interp", "block", "smoother",
+                                                         "chunk")}
     m = O.MGR(s["b"], s["rp"], s["ci"], s["vals"], s["field"], lv, **kw)
     assert m.status == 0, m.status
     return m
