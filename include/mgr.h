@@ -64,6 +64,17 @@ extern "C" {
 #define MGR_INTERP_DIRECT 0
 #define MGR_INTERP_EXT_I 1
 
+/* AMG smoother: L1-Jacobi (Baker, Falgout, Kolev, Yang 2011), or the paper's
+ * hybrid L1 Gauss-Seidel (Sec. 4.1: one forward sweep on the way down, one
+ * backward sweep on the way up) with chunks of gs_chunk consecutive rows in
+ * place of the processors' row blocks: inside a chunk the rows are relaxed one
+ * after another with this sweep's values of the chunk's earlier rows, the
+ * previous values elsewhere, and a_ii plus the l1 norm of the row's entries
+ * outside the chunk as the diagonal (gs_chunk = 1 is L1-Jacobi).  Levels are
+ * then never applied in composed form. */
+#define MGR_SMOOTH_L1_JACOBI 0
+#define MGR_SMOOTH_HYBRID_GS 1
+
 typedef struct mgr_ctx *mgr_handle;
 
 /* Block-CSR matrix with b x b row-major dense blocks.  b = 1 is plain CSR.
@@ -95,6 +106,8 @@ typedef struct {
     int32_t nu_pre, nu_post; /* L1-Jacobi sweeps                               */
     int32_t unknown_based;   /* coarse AMG: strength/interpolation per field   */
     int32_t interp;          /* MGR_INTERP_DIRECT or MGR_INTERP_EXT_I          */
+    int32_t smoother;        /* MGR_SMOOTH_L1_JACOBI or MGR_SMOOTH_HYBRID_GS   */
+    int32_t gs_chunk;        /* rows per chunk of the hybrid smoother (1..128) */
     uint64_t seed;           /* PMIS random weights (splitmix64)                */
 } mgr_amg_opts;
 
@@ -117,7 +130,7 @@ typedef struct {
 
 /* Defaults: apply_precision 64, restart 50, maxiter 1000, rtol 1e-8, CGS2,
  * theta 0.25, max_levels 25, max_coarse 128, V(1,1), direct interpolation,
- * seed 12345.  (host) */
+ * L1-Jacobi smoothing (gs_chunk 32 for the hybrid smoother), seed 12345.  (host) */
 void mgr_default_opts(mgr_opts *o);
 
 /* Device memory provider of a handle (for instance a framework's caching

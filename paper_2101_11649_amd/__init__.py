@@ -38,6 +38,7 @@ class MgrError(RuntimeError):
 
 
 INTERP = {"direct": 0, "ext+i": 1}
+SMOOTHER = {"l1-jacobi": 0, "hybrid-gs": 1}
 
 
 class mgr_matrix(ctypes.Structure):
@@ -54,7 +55,8 @@ class mgr_level_opts(ctypes.Structure):
 class mgr_amg_opts(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("max_levels", ctypes.c_int32), ("max_coarse", ctypes.c_int32),
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32), ("unknown_based", ctypes.c_int32),
-                ("interp", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("interp", ctypes.c_int32), ("smoother", ctypes.c_int32), ("gs_chunk", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
 
 
 class mgr_opts(ctypes.Structure):
@@ -163,12 +165,16 @@ class Solver:
     array-like or device tensor; copied by the library); ``field``: field label
     of every scalar unknown; ``levels``: list of dicts (fmask, frelax, sweeps,
     omega, restrict, amg_unknown_based) -- one per MGR level; ``interp``: AMG
-    interpolation, "direct" or "ext+i" (extended+i, distance two).
+    interpolation, "direct" or "ext+i" (extended+i, distance two);
+    ``smoother``: "l1-jacobi" or "hybrid-gs" (hybrid L1 Gauss-Seidel over chunks
+    of ``chunk`` rows); ``block``: block-Jacobi group of every unknown;
+    ``allocator``: "torch" (device memory from torch's caching allocator) or
+    None (the library's own stream-ordered allocations).
     """
 
     def __init__(self, b, rp, ci, vals, field, levels, precision=64, restart=50, maxiter=1000, rtol=1e-8,
                  theta=0.25, max_levels=25, max_coarse=128, nu_pre=1, nu_post=1, unknown_based=False, seed=12345,
-                 interp="direct", block=None, allocator="torch"):
+                 interp="direct", block=None, allocator="torch", smoother="l1-jacobi", chunk=32):
         torch = _torch()
         L = lib()
         self._h = ctypes.c_void_p()
@@ -176,7 +182,7 @@ class Solver:
         L.mgr_default_opts(ctypes.byref(self.opts))
         self._fill_opts(precision=precision, restart=restart, maxiter=maxiter, rtol=rtol, theta=theta,
                         max_levels=max_levels, max_coarse=max_coarse, nu_pre=nu_pre, nu_post=nu_post,
-                        unknown_based=unknown_based, seed=seed, interp=interp)
+                        unknown_based=unknown_based, seed=seed, interp=interp, smoother=smoother, chunk=chunk)
         self.stream = torch.cuda.current_stream()
         if allocator == "torch":
             fa, ff = TORCH_ALLOC, TORCH_FREE
@@ -198,7 +204,8 @@ class Solver:
         self.setup(vals)
 
     def _fill_opts(self, precision=None, restart=None, maxiter=None, rtol=None, theta=None, max_levels=None,
-                   max_coarse=None, nu_pre=None, nu_post=None, unknown_based=None, seed=None, interp=None):
+                   max_coarse=None, nu_pre=None, nu_post=None, unknown_based=None, seed=None, interp=None,
+                   smoother=None, chunk=None):
         o = self.opts
         if precision is not None: o.apply_precision = int(precision)
         if restart is not None: o.restart = int(restart)
@@ -212,6 +219,8 @@ class Solver:
         if unknown_based is not None: o.amg.unknown_based = int(bool(unknown_based))
         if seed is not None: o.amg.seed = int(seed)
         if interp is not None: o.amg.interp = INTERP[interp]
+        if smoother is not None: o.amg.smoother = SMOOTHER[smoother]
+        if chunk is not None: o.amg.gs_chunk = int(chunk)
 
     def _check(self, code):
         if code < 0:

@@ -487,6 +487,56 @@ __global__ void k_trsv_level(int cnt, const int* __restrict__ rows, const int* _
     x[i] = unit ? s : s / d;
 }
 
+// Second pass of one hybrid L1 Gauss-Seidel sweep (the first is r = b - A x on
+// the whole operator).  Thread c owns the chunk of rows [c*chunk, min(n,
+// (c+1)*chunk)) and relaxes them one after another (forward: increasing,
+// backward: decreasing), x_i += delta_i with
+//   delta_i = (r_i - sum_{j in the chunk, already relaxed} a_ij delta_j) / d_i,
+// which with r_i = b_i - sum_j a_ij x_j is the sweep
+//   x_i <- x_i + (b_i - sum_j a_ij y_j) / d_i,  y_j new for the chunk's rows
+// already relaxed and old for every other unknown.  The relaxed entries of a
+// row lie next to its diagonal (columns ascending), so they are read from the
+// diagonal outwards until the chunk boundary.  The corrections of the chunk
+// live in LDS, slot k of thread t at k * blockDim + t (consecutive threads,
+// consecutive banks).  from_zero: x starts at 0 (r = b) and is overwritten.
+template <typename T>
+__global__ __launch_bounds__(64) void k_hgs_chunk(int n, int chunk, const int* __restrict__ rp,
+                                                  const int* __restrict__ ci, const T* __restrict__ v,
+                                                  const int* __restrict__ dpos, const T* __restrict__ d,
+                                                  const T* __restrict__ r, T* __restrict__ x, int backward,
+                                                  int from_zero) {
+    extern __shared__ unsigned char hgs_lds[];
+    T* dl = reinterpret_cast<T*>(hgs_lds);
+    const int tg = blockDim.x, me = threadIdx.x;
+    const long c0l = ((long)blockIdx.x * tg + me) * chunk;
+    if (c0l >= n) return;
+    const int c0 = (int)c0l, c1 = min(n, c0 + chunk), len = c1 - c0;
+    for (int t = 0; t < len; ++t) {
+        const int i = backward ? c1 - 1 - t : c0 + t;
+        T acc = r[i];
+        const int pd = dpos[i];   // >= 0: setup refuses a row without a diagonal entry
+        if (pd < 0) {
+        } else if (!backward) {
+            const int pb = rp[i];
+            for (int p = pd - 1; p >= pb; --p) {
+                const int j = ci[p];
+                if (j < c0) break;
+                acc -= v[p] * dl[(j - c0) * tg + me];
+            }
+        } else {
+            const int pe = rp[i + 1];
+            for (int p = pd + 1; p < pe; ++p) {
+                const int j = ci[p];
+                if (j >= c1) break;
+                acc -= v[p] * dl[(j - c0) * tg + me];
+            }
+        }
+        const T del = acc / d[i];
+        dl[(i - c0) * tg + me] = del;
+        x[i] = from_zero ? del : x[i] + del;
+    }
+}
+
 // Adjoint gradient on the block pattern: dv[p,r,c] = -sum_k lam_k[I b + r] x_k[J b + c].
 __global__ void k_grad(long nnzb, int b, int nbr, const int* __restrict__ rp, const int* __restrict__ ci, long n,
                        int nrhs, const double* __restrict__ lam, const double* __restrict__ x,
@@ -858,6 +908,22 @@ void arnoldi_update(long n, double* V, long ldv, int nvec, const double* sh, dou
     k_reduce_parts<<<1, TPB, 0, s>>>(np, part, norm2_out, csrc, cdst, ncopy);
     MGR_LAUNCH_CHECK();
 }
+
+template <typename T>
+void hgs_chunk(const SpOp<T>& A, const int* dpos, const T* d, const T* r, T* x, int chunk, bool backward,
+               bool from_zero, hipStream_t s) {
+    if (A.nr <= 0) return;
+    const int tg = chunk <= HGS_CHUNK_MAX / 2 ? 64 : 32;
+    const long nch = ((long)A.nr + chunk - 1) / chunk;
+    const size_t lds = (size_t)tg * chunk * sizeof(T);
+    k_hgs_chunk<T><<<(unsigned)((nch + tg - 1) / tg), tg, lds, s>>>(A.nr, chunk, A.rp, A.ci, A.v, dpos, d, r, x,
+                                                                      backward ? 1 : 0, from_zero ? 1 : 0);
+    MGR_LAUNCH_CHECK();
+}
+template void hgs_chunk<double>(const SpOp<double>&, const int*, const double*, const double*, double*, int, bool,
+                                bool, hipStream_t);
+template void hgs_chunk<float>(const SpOp<float>&, const int*, const float*, const float*, float*, int, bool, bool,
+                               hipStream_t);
 
 template <typename T>
 void trsv_level(int cnt, const int* rows, const SpOp<T>& A, const T* b, T* x, bool unit, hipStream_t s) {

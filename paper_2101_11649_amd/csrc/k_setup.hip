@@ -1991,6 +1991,34 @@ __global__ __launch_bounds__(TPB) void k_l1_dinv_g(int n, const int* __restrict_
     }
 }
 
+// Diagonal of the hybrid L1 Gauss-Seidel smoother: d_i = a_ii plus the l1 norm
+// of row i's entries outside its chunk [i - i % chunk, + chunk) (*flag set
+// where it is not positive).
+template <int G>
+__global__ __launch_bounds__(TPB) void k_hgs_diag_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                    const double* __restrict__ v, int chunk, double* __restrict__ d,
+                                                    int* __restrict__ flag) {
+    Grp<G> g;
+    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    bool valid = i < n;
+    double s = 0.0, aii = 0.0;
+    if (valid) {
+        const int c0 = i - i % chunk, c1 = c0 + chunk;
+        for (int p = rp[i] + g.gl; p < rp[i + 1]; p += G) {
+            const int j = ci[p];
+            if (j == i) aii = v[p];
+            else if (j < c0 || j >= c1) s += fabs(v[p]);
+        }
+    }
+    s = g.sumd(s);
+    aii = g.sumd(aii);
+    if (valid && g.gl == 0) {
+        double di = aii + s;
+        if (!(di > 0.0)) { set_flag(flag, 6); di = 1.0; }
+        d[i] = di;
+    }
+}
+
 // Scatter of A's entries into the rows of its transpose: row j of the
 // transpose has cnt[j] slots from trp[j]; each entry takes one by decrementing
 // cnt[j] (which ends at zero), so the order inside a row is arbitrary.
@@ -2797,6 +2825,14 @@ void l1_dinv(const DCsr& A, double* dinv, int* flag, hipStream_t s) {
     if (A.nr <= 0) return;
     int G = group_rows(A.max_row);
     MGR_DISPATCH_G4(G, (k_l1_dinv_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, dinv, flag)));
+    MGR_LAUNCH_CHECK();
+}
+
+void hgs_diag(const DCsr& A, int chunk, double* d, int* flag, hipStream_t s) {
+    if (A.nr <= 0) return;
+    int G = group_rows(A.max_row);
+    MGR_DISPATCH_G4(G, (k_hgs_diag_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, chunk, d,
+                                                                              flag)));
     MGR_LAUNCH_CHECK();
 }
 

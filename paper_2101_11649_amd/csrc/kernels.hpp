@@ -104,6 +104,9 @@ void interp_ext_count(const DCsr& A, const unsigned char* strong, const int* cf,
 void interp_ext_fill(const DCsr& A, const unsigned char* strong, const int* cf, const int* cidx, const int* label,
                      DCsr& P, int* flag, hipStream_t s);
 void l1_dinv(const DCsr& A, double* dinv, int* flag, hipStream_t s);
+// diagonal of the hybrid L1 Gauss-Seidel smoother: a_ii + sum of |a_ij| over the
+// entries of row i outside its chunk of `chunk` consecutive rows
+void hgs_diag(const DCsr& A, int chunk, double* d, int* flag, hipStream_t s);
 // Composed operators of one L1-Jacobi V(1,1) level (b_c = G b, x = W b + Q x_c):
 // w = 2 D^-1 - D^-1 A D^-1 on A's pattern; out = X - S Y on Y's pattern with
 // S = diag(rs) on the left or diag(cs) on the right; C = [A | B].  *bad is set

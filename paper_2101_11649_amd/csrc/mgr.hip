@@ -267,6 +267,11 @@ struct AmgLevel {
     DArr<float> dinvf;
     DArr<double> rd, td, bd, xd, sd;   // sd = D^-1 b, formed by the restriction from the level above
     DArr<float> rf, tf, bf, xf, sf;
+    // hybrid L1 Gauss-Seidel: chunked L1 diagonal, and the diagonal's position
+    // in each row of A and of A^T
+    DArr<double> dgs;
+    DArr<float> dgsf;
+    DArr<int> dpos, dposT;
 };
 
 struct Amg {
@@ -279,6 +284,7 @@ struct Amg {
     DArr<double> td, tdT;
     DArr<float> tdf, tdTf;
     int nc = 0, nu_pre = 1, nu_post = 1;
+    int smoother = MGR_SMOOTH_L1_JACOBI, chunk = 1;
     bool have_float = false, have_trans = false;
 };
 
@@ -336,6 +342,23 @@ static void amg_make_tail(Amg& H, hipStream_t s) {
     H.tail = L;
 }
 
+// Hybrid L1 Gauss-Seidel data of every level but the coarsest: the chunked L1
+// diagonal (from the current values) and the diagonal positions (validity read
+// back at the next sync).
+static void amg_hgs_setup(Amg& H, Slots& S) {
+    hipStream_t s = S.s;
+    for (size_t l = 0; l + 1 < H.lv.size(); ++l) {
+        AmgLevel& L = H.lv[l];
+        L.dgs.alloc((size_t)L.n + 1, s);
+        hgs_diag(L.A, H.chunk, L.dgs.p, S.flag(), s);
+        if (!L.dpos.p) {
+            L.dpos.alloc((size_t)L.n + 1, s);
+            diag_pos(L.A, L.dpos.p, S.flag(), s);
+        }
+        L.dgsf.reset();
+    }
+}
+
 // Classical AMG setup (the coarse solver of Sec. 4.1, with PMIS coarsening,
 // direct interpolation and L1-Jacobi smoothing; see the oracle for the
 // definitions): stops at n <= max_coarse, at max_levels, or when coarsening
@@ -346,6 +369,8 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
     H.lv.clear();
     H.nu_pre = o.nu_pre;
     H.nu_post = o.nu_post;
+    H.smoother = o.smoother;
+    H.chunk = o.gs_chunk;
     H.lv.emplace_back();
     int n0 = A0.nr;
     H.lv[0].A = std::move(A0);
@@ -425,8 +450,9 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
         spgemm_finish(j1, S);
         Spgemm j2, j3;
         spgemm_begin(j2, R, AP, Ac, S);
-        // small V(1,1) levels are applied in composed form (two SpMVs instead of four)
-        L.composed = H.nu_pre == 1 && H.nu_post == 1 && A.nnz <= AMG_COMPOSE_NNZ && n <= SPGEMM_DENSE_COLS;
+        // small V(1,1) L1-Jacobi levels are applied in composed form (two SpMVs instead of four)
+        L.composed = H.smoother == MGR_SMOOTH_L1_JACOBI && H.nu_pre == 1 && H.nu_post == 1 &&
+                     A.nnz <= AMG_COMPOSE_NNZ && n <= SPGEMM_DENSE_COLS;
         if (L.composed) spgemm_begin(j3, R, A, L.RA, S);
         S.sync("AMG Galerkin product");
         spgemm_finish(j2, S);
@@ -453,6 +479,7 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
     H.lv.back().composed = false;
     for (size_t l = 0; l + 1 < H.lv.size(); ++l)
         if (H.lv[l].composed) amg_compose_begin(H.lv[l], S);
+    if (H.smoother == MGR_SMOOTH_HYBRID_GS) amg_hgs_setup(H, S);
     AmgLevel& Lc = H.lv.back();
     H.nc = Lc.n;
     if (H.nc > 2048) throw Error(MGR_ERR_UNSUPPORTED, "AMG: coarsest level has more than 2048 unknowns");
@@ -492,6 +519,7 @@ static void amg_refresh(Amg& H, DCsr A0, Slots& S) {
     for (int k = 0; k + 1 < nl; ++k) {
         AmgLevel& L = H.lv[k];
         L.AT = DCsr();
+        L.dposT.reset();
         L.G = DCsr(); L.W = DCsr(); L.Q = DCsr(); L.WQ = DCsr(); L.Qt = DCsr(); L.WGt = DCsr();
         L.dinvf.reset();
         DCsr AP, Ac;
@@ -515,6 +543,7 @@ static void amg_refresh(Amg& H, DCsr A0, Slots& S) {
     H.lv.back().AT = DCsr();
     for (int k = 0; k + 1 < nl; ++k)
         if (H.lv[k].composed) amg_compose_begin(H.lv[k], S);
+    if (H.smoother == MGR_SMOOTH_HYBRID_GS) amg_hgs_setup(H, S);
     int nc = H.nc;
     DArr<double> dense((size_t)nc * nc + 1, s);
     H.cinv.alloc((size_t)nc * nc + 1, s);
@@ -550,6 +579,10 @@ static void amg_make_float(Amg& H, hipStream_t s) {
             make_float(L.R, s);
             L.dinvf.alloc((size_t)L.n, s);
             to_float(L.dinv.p, L.dinvf.p, L.n, s);
+            if (L.dgs.p) {
+                L.dgsf.alloc((size_t)L.n + 1, s);
+                to_float(L.dgs.p, L.dgsf.p, L.n, s);
+            }
         }
         if (H.have_trans && L.AT.nr && !L.composed) make_float(L.AT, s);
         L.rf.alloc((size_t)L.n + 1, s);
@@ -602,6 +635,11 @@ static void amg_make_trans(Amg& H, Slots& S) {
         }
         L.AT = csr_transpose(L.A, S);
         if (H.have_float) make_float(L.AT, s);
+        if (H.smoother == MGR_SMOOTH_HYBRID_GS) {
+            // A^T keeps every diagonal entry of A
+            L.dposT.alloc((size_t)L.n + 1, s);
+            diag_pos(L.AT, L.dposT.p, S.flag(), s);
+        }
     }
     int nc = H.nc;
     std::vector<double> h((size_t)nc * nc), t((size_t)nc * nc);
@@ -636,6 +674,7 @@ template <> struct Prec<double> {
     static double* x(AmgLevel& L) { return L.xd.p; }
     static double* sb(AmgLevel& L) { return L.sd.p; }
     static const double* dinv(AmgLevel& L) { return L.dinv.p; }
+    static const double* dgs(AmgLevel& L) { return L.dgs.p; }
     static const double* cinv(Amg& H, bool tr) { return tr ? H.cinvT.p : H.cinv.p; }
     static const double* tail(Amg& H, bool tr) { return tr ? H.tdT.p : H.td.p; }
 };
@@ -646,6 +685,7 @@ template <> struct Prec<float> {
     static float* x(AmgLevel& L) { return L.xf.p; }
     static float* sb(AmgLevel& L) { return L.sf.p; }
     static const float* dinv(AmgLevel& L) { return L.dinvf.p; }
+    static const float* dgs(AmgLevel& L) { return L.dgsf.p; }
     static const float* cinv(Amg& H, bool tr) { return tr ? H.cinvTf.p : H.cinvf.p; }
     static const float* tail(Amg& H, bool tr) { return tr ? H.tdTf.p : H.tdf.p; }
 };
@@ -681,6 +721,35 @@ static void amg_vcycle(Amg& H, int k, const T* b, T* x, bool tr, hipStream_t s, 
     T* r = Prec<T>::r(L);
     T* t = Prec<T>::t(L);
     int npre = tr ? H.nu_post : H.nu_pre, npost = tr ? H.nu_pre : H.nu_post;
+    if (H.smoother == MGR_SMOOTH_HYBRID_GS) {
+        // forward sweeps down, backward sweeps up; the transposed cycle runs the
+        // same directions on A^T (the transpose of a backward sweep on A is a
+        // forward sweep on A^T) with A's row-based diagonal
+        const T* d = Prec<T>::dgs(L);
+        const int* dp = tr ? L.dposT.p : L.dpos.p;
+        if (npre >= 1) {
+            hgs_chunk<T>(A, dp, d, b, x, H.chunk, false, true, s);
+            for (int q = 1; q < npre; ++q) {
+                spmv<T, T, T, T, T>(A, x, (const T*)nullptr, INT_MAX, b, t, T(-1), T(1), s);
+                hgs_chunk<T>(A, dp, d, t, x, H.chunk, false, false, s);
+            }
+            spmv<T, T, T, T, T>(A, x, (const T*)nullptr, INT_MAX, b, r, T(-1), T(1), s);
+        } else {
+            set<T>(n, x, T(0), s);
+            copy<T, T>(n, b, r, s);
+        }
+        AmgLevel& Lc = H.lv[k + 1];
+        T* bc = Prec<T>::b(Lc);
+        T* xc = Prec<T>::x(Lc);
+        spmv<T, T, T, T, T>(view<T>(L.R), r, (const T*)nullptr, INT_MAX, (const T*)nullptr, bc, T(1), T(0), s);
+        amg_vcycle<T>(H, k + 1, bc, xc, tr, s);
+        spmv<T, T, T, T, T>(view<T>(L.P), xc, (const T*)nullptr, INT_MAX, x, x, T(1), T(1), s);
+        for (int q = 0; q < npost; ++q) {
+            spmv<T, T, T, T, T>(A, x, (const T*)nullptr, INT_MAX, b, t, T(-1), T(1), s);
+            hgs_chunk<T>(A, dp, d, t, x, H.chunk, true, false, s);
+        }
+        return;
+    }
     if (npre >= 1) {
         if (bd) presmooth_scaled<T>(A, bd, b, x, r, s);
         else presmooth<T>(A, dinv, b, x, r, s);
@@ -1115,6 +1184,7 @@ template <typename T>
 static const T* amg_first_dinv(Ctx& c, bool tr) {
     Amg& H = c.camg;
     if (H.lv.size() < 2 || H.lv[0].composed || (tr ? H.nu_post : H.nu_pre) < 1) return nullptr;
+    if (H.smoother != MGR_SMOOTH_L1_JACOBI) return nullptr;   // the first sweep is not D^-1 b
     return Prec<T>::dinv(H.lv[0]);
 }
 
@@ -1926,6 +1996,8 @@ void mgr_default_opts(mgr_opts* o) {
     o->amg.nu_post = 1;
     o->amg.unknown_based = 0;
     o->amg.interp = MGR_INTERP_DIRECT;
+    o->amg.smoother = MGR_SMOOTH_L1_JACOBI;
+    o->amg.gs_chunk = 32;
     o->amg.seed = 12345;
 }
 
@@ -1934,6 +2006,9 @@ static int check_opts(const mgr_opts* o) {
     if (o->restart < 1 || o->restart > 63 || o->maxiter < 1 || !(o->rtol >= 0.0)) return MGR_ERR_ARG;
     if (o->amg.max_levels < 1 || o->amg.max_coarse < 1 || o->amg.nu_pre < 0 || o->amg.nu_post < 0) return MGR_ERR_ARG;
     if (o->amg.interp != MGR_INTERP_DIRECT && o->amg.interp != MGR_INTERP_EXT_I) return MGR_ERR_ARG;
+    if (o->amg.smoother != MGR_SMOOTH_L1_JACOBI && o->amg.smoother != MGR_SMOOTH_HYBRID_GS) return MGR_ERR_ARG;
+    if (o->amg.smoother == MGR_SMOOTH_HYBRID_GS && (o->amg.gs_chunk < 1 || o->amg.gs_chunk > mgr::HGS_CHUNK_MAX))
+        return MGR_ERR_ARG;
     return MGR_OK;
 }
 
