@@ -51,11 +51,11 @@ def lib():
         P = ctypes.c_void_p
         i32, f64, u64 = ctypes.c_int, ctypes.c_double, ctypes.c_ulonglong
         L.orc_setup.restype = P
-        L.orc_setup.argtypes = [i32, i32, P, P, P, P, i32, P, P, P, P, P, P, f64, i32, i32, i32, i32, i32, i32, i32,
-                                i32, u64, P, P]
+        L.orc_setup.argtypes = [i32, i32, P, P, P, P, i32, P, P, P, P, P, P, P, f64, i32, i32, i32, i32, i32, i32,
+                                i32, i32, i32, u64, P, P]
         L.orc_update.restype = P
-        L.orc_update.argtypes = [P, i32, i32, P, P, P, P, i32, P, P, P, P, P, P, f64, i32, i32, i32, i32, i32, i32,
-                                 i32, i32, u64, P, i32, P]
+        L.orc_update.argtypes = [P, i32, i32, P, P, P, P, i32, P, P, P, P, P, P, P, f64, i32, i32, i32, i32, i32,
+                                 i32, i32, i32, i32, u64, P, i32, P]
         L.orc_free.argtypes = [P]
         L.orc_apply.argtypes = [P, P, P, i32]
         L.orc_matvec.argtypes = [P, P, P, i32]
@@ -78,6 +78,9 @@ def lib():
         L.orc_pmis_uniform.argtypes = [u64, i32, i32]
         L.orc_direct_interp.restype = P
         L.orc_direct_interp.argtypes = [i32, P, P, P, P, P, P, P]
+        L.orc_aggressive_split.argtypes = [i32, P, P, P, u64, i32, P]
+        L.orc_multipass_interp.restype = P
+        L.orc_multipass_interp.argtypes = [i32, P, P, P, P, P, P, P]
         L.orc_ext_interp.restype = P
         L.orc_ext_interp.argtypes = [i32, P, P, P, P, P, P, P]
         L.orc_lu_solve.argtypes = [i32, P, P, P, i32]
@@ -187,6 +190,29 @@ def direct_interp(a, strong, cf, label=None):
     return _unbox(box), st.value
 
 
+def aggressive_split(a, strong, seed: int, level: int = 0):
+    """C/F split of an aggressively coarsened level (+1 = C, -1 = F)."""
+    n, _, rp, ci, _ = _csr_args(a)
+    cf = np.zeros(n, np.int32)
+    s = np.ascontiguousarray(strong, dtype=np.uint8)
+    if s.size == 0:
+        s = np.zeros(1, np.uint8)
+    lib().orc_aggressive_split(n, _p(rp), _p(ci), _p(s), int(seed), int(level), _p(cf))
+    return cf
+
+
+def multipass_interp(a, strong, cf, label=None):
+    """Multi-pass interpolation of an aggressively coarsened level: (P, status)."""
+    n, _, rp, ci, v = _csr_args(a)
+    st = ctypes.c_int(0)
+    s = np.ascontiguousarray(strong, dtype=np.uint8)
+    if s.size == 0:
+        s = np.zeros(1, np.uint8)
+    lab = None if label is None else _i32(label)
+    box = lib().orc_multipass_interp(n, _p(rp), _p(ci), _p(v), _p(s), _p(_i32(cf)), _p(lab), ctypes.byref(st))
+    return _unbox(box), st.value
+
+
 def ext_interp(a, strong, cf, label=None):
     """Extended+i interpolation (distance two) of the AMG setup: (P, status)."""
     n, _, rp, ci, v = _csr_args(a)
@@ -271,6 +297,7 @@ class LevelOpts:
     omega: float = 1.0
     restrict: str = "injection"
     amg_unknown_based: bool = False
+    amg_agg_levels: int = 0
 
 
 class MGR:
@@ -286,11 +313,14 @@ class MGR:
     block row of the input layout.  ``smoother``: the AMG smoother, "l1-jacobi"
     or "hybrid-gs" (hybrid L1 Gauss-Seidel, forward on the way down and
     backward on the way up, over chunks of ``chunk`` consecutive rows).
+    ``agg_levels``: the coarse AMG's first levels with aggressive coarsening
+    and multi-pass interpolation (LevelOpts.amg_agg_levels for the AMG used as
+    F-relaxation).
     """
 
     def __init__(self, b, rp, ci, vals, field, levels, theta=0.25, max_levels=25, max_coarse=128,
                  nu_pre=1, nu_post=1, coarse_unknown_based=False, seed=12345, interp="direct", block=None,
-                 smoother="l1-jacobi", chunk=32):
+                 smoother="l1-jacobi", chunk=32, agg_levels=0):
         L = lib()
         self.b = int(b)
         self.rp, self.ci, self.vals = _i32(rp), _i32(ci), _f64(vals)
@@ -303,9 +333,11 @@ class MGR:
         omega = _f64([lv.omega for lv in levels] or [0])
         restr = _i32([RESTRICT[lv.restrict] for lv in levels] or [0])
         aub = _i32([int(lv.amg_unknown_based) for lv in levels] or [0])
-        self._lv = (nl, fmask, frelax, sweeps, omega, restr, aub)
+        aag = _i32([int(lv.amg_agg_levels) for lv in levels] or [0])
+        self._lv = (nl, fmask, frelax, sweeps, omega, restr, aub, aag)
         self._amg = (float(theta), int(max_levels), int(max_coarse), int(nu_pre), int(nu_post),
-                     int(coarse_unknown_based), INTERP[interp], SMOOTHER[smoother], int(chunk), int(seed))
+                     int(coarse_unknown_based), int(agg_levels), INTERP[interp], SMOOTHER[smoother], int(chunk),
+                     int(seed))
         self.block = None if block is None else _i32(block)
         st = ctypes.c_int(0)
         self.h = L.orc_setup(self.b, len(self.rp) - 1, _p(self.rp), _p(self.ci), _p(self.vals), _p(self.field),

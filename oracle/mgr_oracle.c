@@ -505,12 +505,17 @@ static int amg_pmis(const Csr *a, const unsigned char *strong, uint64_t seed, in
  *   atilde_ii = a_ii + sum_{k != i, a_ik > 0} a_ik,
  * every sum taken left to right over the row.  C-rows are unit rows; F-rows with
  * an empty C_i are zero.  With labels only same-label couplings are used. */
-static int amg_direct_interp(const Csr *a, const unsigned char *strong, const int *cf, const int *label,
-                             Csr *pout) {
+static int amg_direct_interp_cols(const Csr *a, const unsigned char *strong, const int *cf, const int *label,
+                                  int identity_cols, Csr *pout) {
     int n = a->nr;
     int *cidx = (int *)xmalloc((size_t)n * sizeof(int));
     int nc = 0;
     for (int i = 0; i < n; ++i) cidx[i] = (cf[i] == 1) ? nc++ : -1;
+    if (identity_cols) {
+        /* columns are the points themselves (an n x n operator) */
+        for (int i = 0; i < n; ++i) if (cf[i] == 1) cidx[i] = i;
+        nc = n;
+    }
     int *rp = (int *)xcalloc((size_t)n + 1, sizeof(int));
     for (int i = 0; i < n; ++i) {
         int cnt = 0;
@@ -553,6 +558,109 @@ static int amg_direct_interp(const Csr *a, const unsigned char *strong, const in
     free(cidx);
     *pout = pm;
     return status;
+}
+
+static int amg_direct_interp(const Csr *a, const unsigned char *strong, const int *cf, const int *label,
+                             Csr *pout) {
+    return amg_direct_interp_cols(a, strong, cf, label, 0, pout);
+}
+
+/* Multi-pass interpolation (Stueben, J. Comput. Appl. Math. 128 (2001)), the
+ * interpolation of an aggressively coarsened level, where many F-points have no
+ * strong C-neighbour.  Pass 1 is direct interpolation.  In each further pass,
+ * every F-point still without interpolation whose strong neighbours include
+ * points interpolated before this pass (C-points, or F-points of earlier
+ * passes) takes the direct-interpolation weights w_ij over those neighbours
+ * (their couplings play the part of C_i) and substitutes their interpolation:
+ * P_i = sum_j w_ij P_j, formed as the product W P of the pass's weight operator
+ * (unit rows for the points interpolated before) with the current P, in
+ * Gustavson order.  F-points reached by no pass keep zero rows. */
+static int amg_multipass_interp(const Csr *a, const unsigned char *strong, const int *cf, const int *label,
+                                Csr *pout) {
+    int n = a->nr;
+    Csr P;
+    int status = amg_direct_interp_cols(a, strong, cf, label, 0, &P);
+    int *cfm = (int *)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(int));
+    while (status == ORC_OK) {
+        for (int i = 0; i < n; ++i) cfm[i] = (cf[i] == 1 || P.rp[i + 1] > P.rp[i]) ? 1 : -1;
+        int reach = 0;
+        for (int i = 0; i < n && !reach; ++i) {
+            if (cfm[i] == 1) continue;
+            for (int p = a->rp[i]; p < a->rp[i + 1]; ++p)
+                if (strong[p] && cfm[a->ci[p]] == 1) { reach = 1; break; }
+        }
+        if (!reach) break;
+        Csr W;
+        status = amg_direct_interp_cols(a, strong, cfm, label, 1, &W);
+        Csr Pn = csr_spgemm(&W, &P);
+        csr_free(&W);
+        csr_free(&P);
+        P = Pn;
+    }
+    free(cfm);
+    *pout = P;
+    return status;
+}
+
+/* Aggressive coarsening of one level (Stueben 2001: coarse points at distance
+ * two).  PMIS on the strength graph S gives a first set C1.  On C1, point j is
+ * a second-order strong neighbour of i (i != j) when one or two strong
+ * connections lead from i to j (j in S_i, or j in S_k for some k in S_i, any
+ * intermediate point).  PMIS again on that graph of C1 points, with the random
+ * weights of stream (seed, level + 64) indexed by the position in C1, keeps
+ * the final C-points; the other points of C1 become F.  cf: +1 = C, -1 = F. */
+static void amg_aggressive_split(const Csr *a, const unsigned char *strong, uint64_t seed, int level, int *cf) {
+    int n = a->nr;
+    amg_pmis(a, strong, seed, level, cf);
+    int *c1 = (int *)xmalloc((size_t)(n > 0 ? n : 1) * sizeof(int));
+    int n1 = 0;
+    for (int i = 0; i < n; ++i) c1[i] = (cf[i] == 1) ? n1++ : -1;
+    int *mark = (int *)xmalloc((size_t)(n1 > 0 ? n1 : 1) * sizeof(int));
+    int *list = (int *)xmalloc((size_t)(n1 > 0 ? n1 : 1) * sizeof(int));
+    Csr g;
+    g.nr = g.nc = n1;
+    g.rp = (int *)xcalloc((size_t)n1 + 1, sizeof(int));
+    g.v = NULL;
+    long cap = 16, used = 0;
+    g.ci = (int *)xmalloc((size_t)cap * sizeof(int));
+    for (int j = 0; j < n1; ++j) mark[j] = -1;
+    for (int i = 0; i < n; ++i) {
+        int ii = c1[i];
+        if (ii < 0) continue;
+        int cnt = 0;
+        for (int p = a->rp[i]; p < a->rp[i + 1]; ++p) {
+            if (!strong[p]) continue;
+            int k = a->ci[p];
+            int kk = c1[k];
+            if (kk >= 0 && kk != ii && mark[kk] != ii) { mark[kk] = ii; list[cnt++] = kk; }
+            for (int q = a->rp[k]; q < a->rp[k + 1]; ++q) {
+                if (!strong[q]) continue;
+                int jj = c1[a->ci[q]];
+                if (jj >= 0 && jj != ii && mark[jj] != ii) { mark[jj] = ii; list[cnt++] = jj; }
+            }
+        }
+        /* ascending columns (insertion sort: rows are short) */
+        for (int t = 1; t < cnt; ++t) {
+            int v = list[t], u = t - 1;
+            while (u >= 0 && list[u] > v) { list[u + 1] = list[u]; u--; }
+            list[u + 1] = v;
+        }
+        if (used + cnt > cap) {
+            while (used + cnt > cap) cap *= 2;
+            g.ci = (int *)realloc(g.ci, (size_t)cap * sizeof(int));
+            if (!g.ci) { fprintf(stderr, "oracle: out of memory\n"); abort(); }
+        }
+        memcpy(g.ci + used, list, (size_t)cnt * sizeof(int));
+        used += cnt;
+        g.rp[ii + 1] = (int)used;
+    }
+    unsigned char *all = (unsigned char *)xmalloc((size_t)(used > 0 ? used : 1));
+    memset(all, 1, (size_t)(used > 0 ? used : 1));
+    int *cf2 = (int *)xmalloc((size_t)(n1 > 0 ? n1 : 1) * sizeof(int));
+    amg_pmis(&g, all, seed, level + 64, cf2);
+    for (int i = 0; i < n; ++i)
+        if (c1[i] >= 0 && cf2[c1[i]] != 1) cf[i] = -1;
+    free(cf2); free(all); free(g.rp); free(g.ci); free(list); free(mark); free(c1);
 }
 
 /* Extended+i interpolation (De Sterck, Falgout, Nolting, Yang, Numer. Linear
@@ -669,6 +777,7 @@ typedef struct {
     int interp;             /* AMG_INTERP_DIRECT or AMG_INTERP_EXT_I */
     int smoother;           /* AMG_SMOOTH_L1_JACOBI or AMG_SMOOTH_HYBRID_GS */
     int chunk;              /* rows per chunk of the hybrid Gauss-Seidel smoother */
+    int agg_levels;         /* the first agg_levels levels coarsen aggressively */
     uint64_t seed;
 } AmgOpts;
 
@@ -727,13 +836,16 @@ static int amg_setup(const Csr *a0, const int *label0, const AmgOpts *o, Amg **o
         unsigned char *strong = (unsigned char *)xmalloc((size_t)(csr_nnz(a) > 0 ? csr_nnz(a) : 1));
         amg_strength(a, o->theta, h->label[k], strong);
         int *cf = (int *)xmalloc((size_t)n * sizeof(int));
-        amg_pmis(a, strong, o->seed, k, cf);
+        const int aggressive = k < o->agg_levels;
+        if (aggressive) amg_aggressive_split(a, strong, o->seed, k, cf);
+        else amg_pmis(a, strong, o->seed, k, cf);
         int nc = 0;
         for (int i = 0; i < n; ++i) nc += (cf[i] == 1);
         if (nc == 0 || (double)nc > 0.9 * (double)n) { free(strong); free(cf); break; }
         Csr p;
-        int st = o->interp == AMG_INTERP_EXT_I ? amg_ext_interp(a, strong, cf, h->label[k], &p)
-                                               : amg_direct_interp(a, strong, cf, h->label[k], &p);
+        int st = aggressive ? amg_multipass_interp(a, strong, cf, h->label[k], &p)
+                 : o->interp == AMG_INTERP_EXT_I ? amg_ext_interp(a, strong, cf, h->label[k], &p)
+                                                 : amg_direct_interp(a, strong, cf, h->label[k], &p);
         free(strong);
         if (st != ORC_OK) { free(cf); csr_free(&p); status = st; break; }
         h->cf[k] = cf;
@@ -1131,7 +1243,7 @@ static int build_frelax_operator(MgrLevel *l, int bsize, const int *global_block
 }
 
 typedef struct {
-    int frelax, sweeps, restrict_type, amg_unknown_based;
+    int frelax, sweeps, restrict_type, amg_unknown_based, amg_agg_levels;
     double omega;
     unsigned fmask;
 } LevelOpts;
@@ -1199,6 +1311,7 @@ static int mgr_setup_level(MgrLevel *l, const Csr *a, const int *field, const Le
             } else {
                 AmgOpts fo = *ao;
                 fo.unknown_based = lo->amg_unknown_based;
+                fo.agg_levels = lo->amg_agg_levels;
                 fo.seed = amg_seed;
                 int *flab = (int *)xmalloc((size_t)nF * sizeof(int));
                 for (int k = 0; k < nF; ++k) flab[k] = field[l->fmap[k]];
@@ -1476,18 +1589,19 @@ static void h_prec(void *ctx, const double *x, double *y) {
  * options, and the AMG options for the final coarse system. */
 static void *setup_impl(int b, int nbr, const int *rp, const int *ci, const double *val, const int *field,
                         int nlevels, const unsigned *fmask, const int *frelax, const int *sweeps,
-                        const double *omega, const int *restrict_type, const int *amg_unknown_based_lvl,
+                        const double *omega, const int *restrict_type, const int *amg_unknown_based_lvl, const int *amg_agg_lvl,
                         double theta, int max_levels, int max_coarse, int nu_pre, int nu_post,
-                        int coarse_unknown_based, int interp, int smoother, int chunk, unsigned long long seed, const int *block_of_dof,
+                        int coarse_unknown_based, int coarse_agg_levels, int interp, int smoother, int chunk, unsigned long long seed, const int *block_of_dof,
                         const void *reuse_from, int keep_famg, int *status);
 
 void *orc_setup(int b, int nbr, const int *rp, const int *ci, const double *val, const int *field, int nlevels,
                 const unsigned *fmask, const int *frelax, const int *sweeps, const double *omega,
-                const int *restrict_type, const int *amg_unknown_based_lvl, double theta, int max_levels,
-                int max_coarse, int nu_pre, int nu_post, int coarse_unknown_based, int interp, int smoother, int chunk, unsigned long long seed,
+                const int *restrict_type, const int *amg_unknown_based_lvl, const int *amg_agg_lvl, double theta, int max_levels,
+                int max_coarse, int nu_pre, int nu_post, int coarse_unknown_based, int coarse_agg_levels, int interp, int smoother, int chunk, unsigned long long seed,
                 const int *block_of_dof, int *status) {
     return setup_impl(b, nbr, rp, ci, val, field, nlevels, fmask, frelax, sweeps, omega, restrict_type,
-                      amg_unknown_based_lvl, theta, max_levels, max_coarse, nu_pre, nu_post, coarse_unknown_based,
+                      amg_unknown_based_lvl, amg_agg_lvl, theta, max_levels, max_coarse, nu_pre, nu_post,
+                      coarse_unknown_based, coarse_agg_levels,
                       interp, smoother, chunk, seed, block_of_dof, NULL, 0, status);
 }
 
@@ -1499,19 +1613,20 @@ void *orc_setup(int b, int nbr, const int *rp, const int *ci, const double *val,
  * unchanged).  The other arguments must be those `old` was set up with. */
 void *orc_update(const void *old, int b, int nbr, const int *rp, const int *ci, const double *val, const int *field,
                  int nlevels, const unsigned *fmask, const int *frelax, const int *sweeps, const double *omega,
-                 const int *restrict_type, const int *amg_unknown_based_lvl, double theta, int max_levels,
-                 int max_coarse, int nu_pre, int nu_post, int coarse_unknown_based, int interp, int smoother,
+                 const int *restrict_type, const int *amg_unknown_based_lvl, const int *amg_agg_lvl, double theta, int max_levels,
+                 int max_coarse, int nu_pre, int nu_post, int coarse_unknown_based, int coarse_agg_levels, int interp, int smoother,
                  int chunk, unsigned long long seed, const int *block_of_dof, int keep_famg, int *status) {
     return setup_impl(b, nbr, rp, ci, val, field, nlevels, fmask, frelax, sweeps, omega, restrict_type,
-                      amg_unknown_based_lvl, theta, max_levels, max_coarse, nu_pre, nu_post, coarse_unknown_based,
+                      amg_unknown_based_lvl, amg_agg_lvl, theta, max_levels, max_coarse, nu_pre, nu_post,
+                      coarse_unknown_based, coarse_agg_levels,
                       interp, smoother, chunk, seed, block_of_dof, old, keep_famg, status);
 }
 
 static void *setup_impl(int b, int nbr, const int *rp, const int *ci, const double *val, const int *field,
                         int nlevels, const unsigned *fmask, const int *frelax, const int *sweeps,
-                        const double *omega, const int *restrict_type, const int *amg_unknown_based_lvl,
+                        const double *omega, const int *restrict_type, const int *amg_unknown_based_lvl, const int *amg_agg_lvl,
                         double theta, int max_levels, int max_coarse, int nu_pre, int nu_post,
-                        int coarse_unknown_based, int interp, int smoother, int chunk, unsigned long long seed, const int *block_of_dof,
+                        int coarse_unknown_based, int coarse_agg_levels, int interp, int smoother, int chunk, unsigned long long seed, const int *block_of_dof,
                         const void *reuse_from, int keep_famg, int *status) {
     const Handle *old = (const Handle *)reuse_from;
     Handle *h = (Handle *)xcalloc(1, sizeof(Handle));
@@ -1526,8 +1641,9 @@ static void *setup_impl(int b, int nbr, const int *rp, const int *ci, const doub
     if (nlevels < 0 || nlevels > MAX_MGR_LEVELS) { *status = ORC_ERR_ARG; return h; }
     if (smoother != AMG_SMOOTH_L1_JACOBI && smoother != AMG_SMOOTH_HYBRID_GS) { *status = ORC_ERR_ARG; return h; }
     if (chunk < 1) { *status = ORC_ERR_ARG; return h; }
+    if (coarse_agg_levels < 0) { *status = ORC_ERR_ARG; return h; }
     AmgOpts ao = {theta, max_levels, max_coarse, nu_pre, nu_post, coarse_unknown_based, interp, smoother, chunk,
-                  (uint64_t)seed};
+                  coarse_agg_levels, (uint64_t)seed};
     /* block-Jacobi groups: the caller's group id of every unknown, else its block row */
     int *gblock = (int *)xmalloc((size_t)n * sizeof(int));
     for (int i = 0; i < n; ++i) gblock[i] = block_of_dof ? block_of_dof[i] : i / b;
@@ -1536,7 +1652,8 @@ static void *setup_impl(int b, int nbr, const int *rp, const int *ci, const doub
     memcpy(cfield, field, (size_t)n * sizeof(int));
     int *cblock = gblock;
     for (int lev = 0; lev < nlevels; ++lev) {
-        LevelOpts lo = {frelax[lev], sweeps[lev], restrict_type[lev], amg_unknown_based_lvl[lev], omega[lev],
+        LevelOpts lo = {frelax[lev], sweeps[lev], restrict_type[lev], amg_unknown_based_lvl[lev], amg_agg_lvl[lev],
+                        omega[lev],
                         fmask[lev]};
         MgrLevel *l = &m->L[lev];
         m->nlev = lev + 1;
@@ -1775,6 +1892,18 @@ void *orc_direct_interp(int n, const int *rp, const int *ci, const double *v, co
     Csr a = wrap(n, n, rp, ci, v);
     CsrBox *box = (CsrBox *)xcalloc(1, sizeof(CsrBox));
     *status = amg_direct_interp(&a, strong, cf, label, &box->c);
+    return box;
+}
+void orc_aggressive_split(int n, const int *rp, const int *ci, const unsigned char *strong, unsigned long long seed,
+                          int level, int *cf) {
+    Csr a = wrap(n, n, rp, ci, NULL);
+    amg_aggressive_split(&a, strong, (uint64_t)seed, level, cf);
+}
+void *orc_multipass_interp(int n, const int *rp, const int *ci, const double *v, const unsigned char *strong,
+                           const int *cf, const int *label, int *status) {
+    Csr a = wrap(n, n, rp, ci, v);
+    CsrBox *box = (CsrBox *)xcalloc(1, sizeof(CsrBox));
+    *status = amg_multipass_interp(&a, strong, cf, label, &box->c);
     return box;
 }
 void *orc_ext_interp(int n, const int *rp, const int *ci, const double *v, const unsigned char *strong,

@@ -60,7 +60,7 @@ def oracle_mgr(s, levels=None, **kw):
         kw["coarse_unknown_based"] = kw.pop("unknown_based")
     kw = {k: v for k, v in kw.items() if k in ("theta", "max_levels", "max_coarse", "nu_pre", "nu_post",
                                                          "coarse_unknown_based", "seed", "interp", "block", "smoother",
-                                                         "chunk")}
+                                                         "chunk", "agg_levels")}
     m = O.MGR(s["b"], s["rp"], s["ci"], s["vals"], s["field"], lv, **kw)
     assert m.status == 0, m.status
     return m
