@@ -96,6 +96,7 @@ typedef struct {
     double omega;            /* F-relaxation weight                            */
     int32_t restrict_type;   /* MGR_RESTRICT_*                                 */
     int32_t amg_unknown_based; /* MGR_FRELAX_AMG: AMG restricted per field label */
+    int32_t amg_agg_levels;  /* MGR_FRELAX_AMG: levels with aggressive coarsening (see mgr_amg_opts) */
 } mgr_level_opts;
 
 /* Classical AMG used for the final coarse system and for MGR_FRELAX_AMG. */
@@ -108,6 +109,12 @@ typedef struct {
     int32_t interp;          /* MGR_INTERP_DIRECT or MGR_INTERP_EXT_I          */
     int32_t smoother;        /* MGR_SMOOTH_L1_JACOBI or MGR_SMOOTH_HYBRID_GS   */
     int32_t gs_chunk;        /* rows per chunk of the hybrid smoother (1..128) */
+    int32_t agg_levels;      /* coarse AMG: the first agg_levels levels coarsen
+                                aggressively (Sec. 4.1, the mechanics block: a
+                                second PMIS on the graph of first-pass C-points
+                                one or two strong connections apart) and
+                                interpolate by multiple passes of direct
+                                interpolation (Stueben 2001)                   */
     uint64_t seed;           /* PMIS random weights (splitmix64)                */
 } mgr_amg_opts;
 
@@ -130,7 +137,8 @@ typedef struct {
 
 /* Defaults: apply_precision 64, restart 50, maxiter 1000, rtol 1e-8, CGS2,
  * theta 0.25, max_levels 25, max_coarse 128, V(1,1), direct interpolation,
- * L1-Jacobi smoothing (gs_chunk 32 for the hybrid smoother), seed 12345.  (host) */
+ * L1-Jacobi smoothing (gs_chunk 32 for the hybrid smoother), no aggressive
+ * coarsening, seed 12345.  (host) */
 void mgr_default_opts(mgr_opts *o);
 
 /* Device memory provider of a handle (for instance a framework's caching

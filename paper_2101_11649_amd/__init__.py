@@ -49,14 +49,14 @@ class mgr_matrix(ctypes.Structure):
 class mgr_level_opts(ctypes.Structure):
     _fields_ = [("f_field_mask", ctypes.c_uint32), ("frelax", ctypes.c_int32), ("sweeps", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("restrict_type", ctypes.c_int32),
-                ("amg_unknown_based", ctypes.c_int32)]
+                ("amg_unknown_based", ctypes.c_int32), ("amg_agg_levels", ctypes.c_int32)]
 
 
 class mgr_amg_opts(ctypes.Structure):
     _fields_ = [("theta", ctypes.c_double), ("max_levels", ctypes.c_int32), ("max_coarse", ctypes.c_int32),
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32), ("unknown_based", ctypes.c_int32),
                 ("interp", ctypes.c_int32), ("smoother", ctypes.c_int32), ("gs_chunk", ctypes.c_int32),
-                ("seed", ctypes.c_uint64)]
+                ("agg_levels", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
 class mgr_opts(ctypes.Structure):
@@ -153,9 +153,10 @@ class SolveInfo:
     rel_res_true: float
 
 
-def level_opts(fmask, frelax="jacobi", sweeps=1, omega=1.0, restrict="injection", amg_unknown_based=False):
+def level_opts(fmask, frelax="jacobi", sweeps=1, omega=1.0, restrict="injection", amg_unknown_based=False,
+               amg_agg_levels=0):
     return dict(fmask=int(fmask), frelax=frelax, sweeps=int(sweeps), omega=float(omega), restrict=restrict,
-                amg_unknown_based=bool(amg_unknown_based))
+                amg_unknown_based=bool(amg_unknown_based), amg_agg_levels=int(amg_agg_levels))
 
 
 class Solver:
@@ -169,12 +170,14 @@ class Solver:
     ``smoother``: "l1-jacobi" or "hybrid-gs" (hybrid L1 Gauss-Seidel over chunks
     of ``chunk`` rows); ``block``: block-Jacobi group of every unknown;
     ``allocator``: "torch" (device memory from torch's caching allocator) or
-    None (the library's own stream-ordered allocations).
+    None (the library's own stream-ordered allocations); ``agg_levels``: the
+    coarse AMG's levels with aggressive coarsening (a level's
+    "amg_agg_levels" for its F-relaxation AMG).
     """
 
     def __init__(self, b, rp, ci, vals, field, levels, precision=64, restart=50, maxiter=1000, rtol=1e-8,
                  theta=0.25, max_levels=25, max_coarse=128, nu_pre=1, nu_post=1, unknown_based=False, seed=12345,
-                 interp="direct", block=None, allocator="torch", smoother="l1-jacobi", chunk=32):
+                 interp="direct", block=None, allocator="torch", smoother="l1-jacobi", chunk=32, agg_levels=0):
         torch = _torch()
         L = lib()
         self._h = ctypes.c_void_p()
@@ -182,7 +185,8 @@ class Solver:
         L.mgr_default_opts(ctypes.byref(self.opts))
         self._fill_opts(precision=precision, restart=restart, maxiter=maxiter, rtol=rtol, theta=theta,
                         max_levels=max_levels, max_coarse=max_coarse, nu_pre=nu_pre, nu_post=nu_post,
-                        unknown_based=unknown_based, seed=seed, interp=interp, smoother=smoother, chunk=chunk)
+                        unknown_based=unknown_based, seed=seed, interp=interp, smoother=smoother, chunk=chunk,
+                        agg_levels=agg_levels)
         self.stream = torch.cuda.current_stream()
         if allocator == "torch":
             fa, ff = TORCH_ALLOC, TORCH_FREE
@@ -205,7 +209,7 @@ class Solver:
 
     def _fill_opts(self, precision=None, restart=None, maxiter=None, rtol=None, theta=None, max_levels=None,
                    max_coarse=None, nu_pre=None, nu_post=None, unknown_based=None, seed=None, interp=None,
-                   smoother=None, chunk=None):
+                   smoother=None, chunk=None, agg_levels=None):
         o = self.opts
         if precision is not None: o.apply_precision = int(precision)
         if restart is not None: o.restart = int(restart)
@@ -221,6 +225,7 @@ class Solver:
         if interp is not None: o.amg.interp = INTERP[interp]
         if smoother is not None: o.amg.smoother = SMOOTHER[smoother]
         if chunk is not None: o.amg.gs_chunk = int(chunk)
+        if agg_levels is not None: o.amg.agg_levels = int(agg_levels)
 
     def _check(self, code):
         if code < 0:
@@ -237,7 +242,8 @@ class Solver:
         for i, lv in enumerate(self.levels):
             arr[i] = mgr_level_opts(int(lv["fmask"]), FRELAX[lv.get("frelax", "jacobi")], int(lv.get("sweeps", 1)),
                                     float(lv.get("omega", 1.0)), RESTRICT[lv.get("restrict", "injection")],
-                                    int(bool(lv.get("amg_unknown_based", False))))
+                                    int(bool(lv.get("amg_unknown_based", False))),
+                                    int(lv.get("amg_agg_levels", 0)))
         self._check(lib().mgr_setup(self._h, ctypes.byref(A), ctypes.c_void_p(self.field.data_ptr()),
                                     len(self.levels), arr,
                                     None if self.block is None else ctypes.c_void_p(self.block.data_ptr())))

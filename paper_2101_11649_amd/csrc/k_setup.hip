@@ -1991,6 +1991,109 @@ __global__ __launch_bounds__(TPB) void k_l1_dinv_g(int n, const int* __restrict_
     }
 }
 
+// ------------------------------------------------------------------ aggressive coarsening
+// Second-order strength on the first C-points (C1; isC1 flags, e1 their exclusive
+// prefix = C1 index): the graph is the pattern of L * Rt without its diagonal,
+// with L = the strong rows of the C1 points (global columns) and Rt = S
+// restricted to C1 columns plus a unit entry (k, C1 index of k) for every C1
+// point k, so that row i of L * Rt holds every C1 point one or two strong
+// connections away from i.  All values are 1 (the products count paths).
+__global__ void k_agg_rt_count(int n, const int* __restrict__ srp, const int* __restrict__ sci,
+                               const int* __restrict__ isC1, int* __restrict__ cnt) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int c = isC1[k];
+    for (int q = srp[k]; q < srp[k + 1]; ++q) c += isC1[sci[q]];
+    cnt[k] = c;
+}
+
+__global__ void k_agg_rt_fill(int n, const int* __restrict__ srp, const int* __restrict__ sci,
+                              const int* __restrict__ isC1, const int* __restrict__ e1, const int* __restrict__ rp,
+                              int* __restrict__ ci, double* __restrict__ v) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    int o = rp[k];
+    bool own = isC1[k] != 0;
+    for (int q = srp[k]; q < srp[k + 1]; ++q) {
+        int j = sci[q];
+        if (own && j > k) {          // the unit entry in column order (e1 grows with the point index)
+            ci[o] = e1[k]; v[o] = 1.0; ++o;
+            own = false;
+        }
+        if (isC1[j]) { ci[o] = e1[j]; v[o] = 1.0; ++o; }
+    }
+    if (own) { ci[o] = e1[k]; v[o] = 1.0; }
+}
+
+// rows of L: the strong row of the C1 point pts[r]
+__global__ void k_agg_l_count(int n1, const int* __restrict__ pts, const int* __restrict__ srp,
+                              int* __restrict__ cnt) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n1) return;
+    int i = pts[r];
+    cnt[r] = srp[i + 1] - srp[i];
+}
+
+__global__ void k_agg_l_fill(int n1, const int* __restrict__ pts, const int* __restrict__ srp,
+                             const int* __restrict__ sci, const int* __restrict__ rp, int* __restrict__ ci,
+                             double* __restrict__ v) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n1) return;
+    int i = pts[r], o = rp[r];
+    for (int q = srp[i]; q < srp[i + 1]; ++q, ++o) { ci[o] = sci[q]; v[o] = 1.0; }
+}
+
+// the pattern of a square CSR without its diagonal entries
+__global__ void k_nodiag_count(int n, const int* __restrict__ rp, const int* __restrict__ ci, int* __restrict__ cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int c = 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) c += (ci[p] != i);
+    cnt[i] = c;
+}
+
+__global__ void k_nodiag_fill(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                              const int* __restrict__ orp, int* __restrict__ oci) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int o = orp[i];
+    for (int p = rp[i]; p < rp[i + 1]; ++p)
+        if (ci[p] != i) oci[o++] = ci[p];
+}
+
+// lam[j] = number of entries in column j (the PMIS measure of a strength graph)
+__global__ void k_col_count(long nnz, const int* __restrict__ ci, int* __restrict__ lam) {
+    long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nnz) atomicAdd(lam + ci[p], 1);
+}
+
+// final split: C where the point is a C1 point chosen again by the second PMIS
+__global__ void k_agg_final(int n, const int* __restrict__ isC1, const int* __restrict__ e1,
+                            const int* __restrict__ cf2, int* __restrict__ cf) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    cf[i] = (isC1[i] && cf2[e1[i]] == 1) ? 1 : -1;
+}
+
+// multi-pass interpolation: points interpolated so far (C-points and the rows
+// of P that are not empty) count as C in the next pass
+__global__ void k_mp_assigned(int n, const int* __restrict__ cf, const int* __restrict__ prp,
+                              int* __restrict__ cfm) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    cfm[i] = (cf[i] == 1 || prp[i + 1] > prp[i]) ? 1 : -1;
+}
+
+// number of points the next pass reaches (not yet interpolated, with a strong
+// neighbour that is), one atomic per wavefront
+__global__ void k_mp_reach(int n, const int* __restrict__ cfm, const int* __restrict__ wcnt,
+                           unsigned long long* __restrict__ reach) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool r = i < n && cfm[i] != 1 && wcnt[i] > 0;
+    unsigned long long m = __ballot(r);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && m) atomicAdd(reach, (unsigned long long)__popcll(m));
+}
+
 // Diagonal of the hybrid L1 Gauss-Seidel smoother: d_i = a_ii plus the l1 norm
 // of row i's entries outside its chunk [i - i % chunk, + chunk) (*flag set
 // where it is not positive).
@@ -2825,6 +2928,57 @@ void l1_dinv(const DCsr& A, double* dinv, int* flag, hipStream_t s) {
     if (A.nr <= 0) return;
     int G = group_rows(A.max_row);
     MGR_DISPATCH_G4(G, (k_l1_dinv_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, dinv, flag)));
+    MGR_LAUNCH_CHECK();
+}
+
+void agg_rt_count(int n, const int* srp, const int* sci, const int* isC1, int* cnt, hipStream_t s) {
+    if (n <= 0) return;
+    k_agg_rt_count<<<nblk(n), TPB, 0, s>>>(n, srp, sci, isC1, cnt);
+    MGR_LAUNCH_CHECK();
+}
+void agg_rt_fill(int n, const int* srp, const int* sci, const int* isC1, const int* e1, DCsr& Rt, hipStream_t s) {
+    if (n <= 0) return;
+    k_agg_rt_fill<<<nblk(n), TPB, 0, s>>>(n, srp, sci, isC1, e1, Rt.rp.p, Rt.ci.p, Rt.v.p);
+    MGR_LAUNCH_CHECK();
+}
+void agg_l_count(int n1, const int* pts, const int* srp, int* cnt, hipStream_t s) {
+    if (n1 <= 0) return;
+    k_agg_l_count<<<nblk(n1), TPB, 0, s>>>(n1, pts, srp, cnt);
+    MGR_LAUNCH_CHECK();
+}
+void agg_l_fill(int n1, const int* pts, const int* srp, const int* sci, DCsr& L, hipStream_t s) {
+    if (n1 <= 0) return;
+    k_agg_l_fill<<<nblk(n1), TPB, 0, s>>>(n1, pts, srp, sci, L.rp.p, L.ci.p, L.v.p);
+    MGR_LAUNCH_CHECK();
+}
+void nodiag_count(const DCsr& A, int* cnt, hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_nodiag_count<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, cnt);
+    MGR_LAUNCH_CHECK();
+}
+void nodiag_fill(const DCsr& A, DCsr& B, hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_nodiag_fill<<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, B.rp.p, B.ci.p);
+    MGR_LAUNCH_CHECK();
+}
+void col_count(long nnz, const int* ci, int* lam, hipStream_t s) {
+    if (nnz <= 0) return;
+    k_col_count<<<nblk(nnz), TPB, 0, s>>>(nnz, ci, lam);
+    MGR_LAUNCH_CHECK();
+}
+void agg_final(int n, const int* isC1, const int* e1, const int* cf2, int* cf, hipStream_t s) {
+    if (n <= 0) return;
+    k_agg_final<<<nblk(n), TPB, 0, s>>>(n, isC1, e1, cf2, cf);
+    MGR_LAUNCH_CHECK();
+}
+void mp_assigned(int n, const int* cf, const int* prp, int* cfm, hipStream_t s) {
+    if (n <= 0) return;
+    k_mp_assigned<<<nblk(n), TPB, 0, s>>>(n, cf, prp, cfm);
+    MGR_LAUNCH_CHECK();
+}
+void mp_reach(int n, const int* cfm, const int* wcnt, long long* reach, hipStream_t s) {
+    if (n <= 0) return;
+    k_mp_reach<<<nblk(n), TPB, 0, s>>>(n, cfm, wcnt, reinterpret_cast<unsigned long long*>(reach));
     MGR_LAUNCH_CHECK();
 }
 

@@ -104,6 +104,20 @@ void interp_ext_count(const DCsr& A, const unsigned char* strong, const int* cf,
 void interp_ext_fill(const DCsr& A, const unsigned char* strong, const int* cf, const int* cidx, const int* label,
                      DCsr& P, int* flag, hipStream_t s);
 void l1_dinv(const DCsr& A, double* dinv, int* flag, hipStream_t s);
+// aggressive coarsening: the factors of the second-order strength graph on the
+// first C-points (C1 flags isC1, C1 index e1, C1 points pts), its diagonal
+// dropped, column counts, the final split; multi-pass interpolation's
+// interpolated-so-far flags and the count of points the next pass reaches
+void agg_rt_count(int n, const int* srp, const int* sci, const int* isC1, int* cnt, hipStream_t s);
+void agg_rt_fill(int n, const int* srp, const int* sci, const int* isC1, const int* e1, DCsr& Rt, hipStream_t s);
+void agg_l_count(int n1, const int* pts, const int* srp, int* cnt, hipStream_t s);
+void agg_l_fill(int n1, const int* pts, const int* srp, const int* sci, DCsr& L, hipStream_t s);
+void nodiag_count(const DCsr& A, int* cnt, hipStream_t s);
+void nodiag_fill(const DCsr& A, DCsr& B, hipStream_t s);
+void col_count(long nnz, const int* ci, int* lam, hipStream_t s);
+void agg_final(int n, const int* isC1, const int* e1, const int* cf2, int* cf, hipStream_t s);
+void mp_assigned(int n, const int* cf, const int* prp, int* cfm, hipStream_t s);
+void mp_reach(int n, const int* cfm, const int* wcnt, long long* reach, hipStream_t s);
 // diagonal of the hybrid L1 Gauss-Seidel smoother: a_ii + sum of |a_ij| over the
 // entries of row i outside its chunk of `chunk` consecutive rows
 void hgs_diag(const DCsr& A, int chunk, double* d, int* flag, hipStream_t s);

@@ -359,6 +359,125 @@ static void amg_hgs_setup(Amg& H, Slots& S) {
     }
 }
 
+// PMIS to completion on a strength graph (srp, sci) with measures lam and the
+// random stream of `level`; cf gets +1 = C / -1 = F.  Host checks every four
+// rounds (after a first batch of eight).
+static void pmis_run(int n, const int* srp, const int* sci, const int* lam, uint64_t seed, int level, DArr<int>& cf,
+                     int avg_row, Slots& S) {
+    hipStream_t s = S.s;
+    DArr<double> w((size_t)n + 1, s);
+    DArr<int> cf2((size_t)n + 1, s);
+    DArr<unsigned char> bt((size_t)n + 1, s), bt2((size_t)n + 1, s);
+    cf.alloc((size_t)n + 1, s);
+    pmis_init(n, lam, seed, level, w.p, cf.p, s);
+    fill_bytes(bt.p, 0, n, s);
+    for (int total = 0, batch = 8;; total += batch, batch = 4) {
+        if (total > 100000) throw Error(MGR_ERR_UNSUPPORTED, "PMIS did not terminate");
+        long long* und = S.take(1);
+        for (int r = 0; r < batch; ++r) {
+            pmis_select(n, srp, sci, w.p, cf.p, bt.p, avg_row, s);
+            pmis_update(n, srp, sci, cf.p, bt.p, cf2.p, bt2.p, r + 1 == batch ? reinterpret_cast<int*>(und) : nullptr,
+                        avg_row, s);
+            std::swap(cf, cf2);
+            std::swap(bt, bt2);
+        }
+        S.sync("PMIS");
+        if ((S.val(und) & 0xffffffffLL) == 0) break;
+    }
+}
+
+// Aggressive coarsening of one level (Stueben 2001; the first level of the
+// mechanics AMG, Sec. 4.1): PMIS on S gives C1; PMIS again on the graph of C1
+// points one or two strong connections apart (random stream level + 64,
+// indexed by the position in C1) keeps the final C-points; interpolation by
+// multiple passes of direct interpolation, each pass substituting the
+// interpolation of the points reached before (P_i = sum_j w_ij P_j, as the
+// product W P).  Fills cf (+1 / -1), isC, cidx (C numbering) and P; returns
+// the number of C-points (P is left empty when that is 0).
+static long amg_aggressive_level(const DCsr& A, const unsigned char* strong, const int* srp, const int* sci,
+                                 const int* lam, uint64_t seed, int k, const int* label, DArr<int>& cf,
+                                 DArr<int>& isC, DArr<int>& cidx, DCsr& P, Slots& S) {
+    hipStream_t s = S.s;
+    const int n = A.nr;
+    const int avg_row = (int)((A.nnz + 2L * n - 1) / (2L * n));
+    DArr<int> cf1;
+    pmis_run(n, srp, sci, lam, seed, k, cf1, avg_row, S);
+    // C1 numbering
+    DArr<int> isC1((size_t)n + 1, s), e1((size_t)n + 1, s);
+    cf_is_c(n, cf1.p, isC1.p, s);
+    long long* s1 = S.take(2);
+    scan_async(isC1.p, e1.p, n, s1, s);
+    DArr<int> rtc((size_t)n + 1, s);
+    agg_rt_count(n, srp, sci, isC1.p, rtc.p, s);
+    DCsr Rt;
+    Pend prt = csr_begin(Rt, n, 0, rtc.p, S);
+    S.sync("aggressive coarsening: first C-points");
+    const int n1 = (int)S.val(s1);
+    csr_finish(prt, S);
+    Rt.nc = n1;
+    DArr<int> cf2;
+    if (n1 > 0) {
+        agg_rt_fill(n, srp, sci, isC1.p, e1.p, Rt, s);
+        // the C1 points in order, and the rows of L
+        DArr<int> pts((size_t)n1 + 1, s), lmap((size_t)n + 1, s), rest((size_t)n + 1, s), lc((size_t)n1 + 1, s);
+        cf_maps(n, isC1.p, e1.p, lmap.p, pts.p, rest.p, s);
+        agg_l_count(n1, pts.p, srp, lc.p, s);
+        DCsr Lr = csr_from_counts(n1, n, lc.p, S, "aggressive coarsening: strong rows of C1");
+        agg_l_fill(n1, pts.p, srp, sci, Lr, s);
+        DCsr G2 = spgemm(Lr, Rt, S);
+        Lr = DCsr();
+        Rt = DCsr();
+        DArr<int> gc((size_t)n1 + 1, s);
+        nodiag_count(G2, gc.p, s);
+        DCsr S2 = csr_from_counts(n1, n1, gc.p, S, "aggressive coarsening: second-order strength");
+        nodiag_fill(G2, S2, s);
+        G2 = DCsr();
+        DArr<int> lam2((size_t)n1 + 1, s);
+        fill_int(lam2.p, 0, n1 + 1, s);
+        col_count(S2.nnz, S2.ci.p, lam2.p, s);
+        const int avg2 = (int)((S2.nnz + n1 - 1) / (n1 > 0 ? n1 : 1));
+        pmis_run(n1, S2.rp.p, S2.ci.p, lam2.p, seed, k + 64, cf2, avg2, S);
+    }
+    cf.alloc((size_t)n + 1, s);
+    if (n1 > 0) agg_final(n, isC1.p, e1.p, cf2.p, cf.p, s);
+    else fill_int(cf.p, -1, n, s);
+    // final C numbering, then multi-pass interpolation
+    cf_is_c(n, cf.p, isC.p, s);
+    long long* sc = S.take(2);
+    scan_async(isC.p, cidx.p, n, sc, s);
+    DArr<int> pcnt((size_t)n + 1, s);
+    interp_count(A, strong, cf.p, pcnt.p, s);
+    Pend pp = csr_begin(P, n, 0, pcnt.p, S);
+    S.sync("aggressive coarsening: final C-points");
+    const long nc = (long)S.val(sc);
+    if (nc == 0 || (double)nc > 0.9 * (double)n) {
+        P = DCsr();
+        return nc;
+    }
+    P.nc = (int)nc;
+    csr_finish(pp, S);
+    ensure_rowblocks(A);
+    interp_fill(A, strong, cf.p, cidx.p, label, P, S.flag(), s);
+    DArr<int> cfm((size_t)n + 1, s), wcnt((size_t)n + 1, s), ident((size_t)n + 1, s);
+    iota_div(n, 1, ident.p, s);
+    for (int pass = 2;; ++pass) {
+        if (pass > n + 1) throw Error(MGR_ERR_UNSUPPORTED, "multi-pass interpolation did not terminate");
+        mp_assigned(n, cf.p, P.rp.p, cfm.p, s);
+        interp_count(A, strong, cfm.p, wcnt.p, s);
+        long long* reach = S.take(1);
+        mp_reach(n, cfm.p, wcnt.p, reach, s);
+        DCsr Wp;
+        Pend pw = csr_begin(Wp, n, n, wcnt.p, S);
+        S.sync("multi-pass interpolation");
+        if (S.val(reach) == 0) break;
+        csr_finish(pw, S);
+        interp_fill(A, strong, cfm.p, ident.p, label, Wp, S.flag(), s);
+        P = spgemm(Wp, P, S);
+        P.nc = (int)nc;
+    }
+    return nc;
+}
+
 // Classical AMG setup (the coarse solver of Sec. 4.1, with PMIS coarsening,
 // direct interpolation and L1-Jacobi smoothing; see the oracle for the
 // definitions): stops at n <= max_coarse, at max_levels, or when coarsening
@@ -396,15 +515,20 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
         DArr<int> sci(nz, s);
         scan_exclusive_async(scnt.p, srp.p, n, s);
         strength_compact_fill(A, strong.p, srp.p, sci.p, s);
+        DArr<int> cf((size_t)n, s), isC((size_t)n + 1, s), cidx((size_t)n + 1, s);
+        DCsr P;
+        long nc = 0;
+        if (k < o.agg_levels) {
+            nc = amg_aggressive_level(A, strong.p, srp.p, sci.p, lam.p, seed, k, L.label.p, cf, isC, cidx, P, S);
+            if (nc == 0 || (double)nc > 0.9 * (double)n) break;
+        } else {
         // PMIS rounds, run in batches between checks of the undecided count;
         // the state (cf, beaten) alternates between two buffers
         DArr<double> w((size_t)n, s);
-        DArr<int> cf((size_t)n, s), cf2((size_t)n, s), isC((size_t)n + 1, s), cidx((size_t)n + 1, s),
-            pcnt((size_t)n + 1, s);
+        DArr<int> cf2((size_t)n, s), pcnt((size_t)n + 1, s);
         DArr<unsigned char> bt((size_t)n, s), bt2((size_t)n, s);
         pmis_init(n, lam.p, seed, k, w.p, cf.p, s);
         fill_bytes(bt.p, 0, n, s);
-        DCsr P;
         Pend pp;
         long long* sc = nullptr;
         // seven rounds usually decide every point: a first batch of eight rarely
@@ -433,13 +557,14 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
             S.sync("PMIS");
             if ((S.val(und) & 0xffffffffLL) == 0) break;
         }
-        long nc = (long)S.val(sc);
+        nc = (long)S.val(sc);
         if (nc == 0 || (double)nc > 0.9 * (double)n) break;
         P.nc = (int)nc;
         csr_finish(pp, S);
         ensure_rowblocks(A);
         if (o.interp == MGR_INTERP_EXT_I) interp_ext_fill(A, strong.p, cf.p, cidx.p, L.label.p, P, S.flag(), s);
         else interp_fill(A, strong.p, cf.p, cidx.p, L.label.p, P, S.flag(), s);
+        }
         // R = P^T and A P, then P^T (A P)
         DCsr R, AP, Ac;
         Transp tr = csr_transpose_begin(P, R, S);
@@ -999,6 +1124,7 @@ static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr& A, const int* field
         l.famg.reset(new Amg());
         mgr_amg_opts fo = c.o.amg;
         fo.unknown_based = o.amg_unknown_based;
+        fo.agg_levels = o.amg_agg_levels;
         DArr<int> flab;
         if (o.amg_unknown_based) {
             flab.alloc((size_t)l.nF, s);
@@ -1740,6 +1866,7 @@ static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nle
         if (lvl[l].frelax < 0 || lvl[l].frelax > 3) throw Error(MGR_ERR_ARG, "unknown F-relaxation");
         if (lvl[l].restrict_type < 0 || lvl[l].restrict_type > 1) throw Error(MGR_ERR_ARG, "unknown restriction");
         if (lvl[l].f_field_mask == 0) throw Error(MGR_ERR_BAD_LABELS, "empty F-field mask");
+        if (lvl[l].amg_agg_levels < 0) throw Error(MGR_ERR_ARG, "amg_agg_levels must be >= 0");
     }
     c.ready = false;
     c.L.clear();
@@ -1998,6 +2125,7 @@ void mgr_default_opts(mgr_opts* o) {
     o->amg.interp = MGR_INTERP_DIRECT;
     o->amg.smoother = MGR_SMOOTH_L1_JACOBI;
     o->amg.gs_chunk = 32;
+    o->amg.agg_levels = 0;
     o->amg.seed = 12345;
 }
 
@@ -2007,6 +2135,7 @@ static int check_opts(const mgr_opts* o) {
     if (o->amg.max_levels < 1 || o->amg.max_coarse < 1 || o->amg.nu_pre < 0 || o->amg.nu_post < 0) return MGR_ERR_ARG;
     if (o->amg.interp != MGR_INTERP_DIRECT && o->amg.interp != MGR_INTERP_EXT_I) return MGR_ERR_ARG;
     if (o->amg.smoother != MGR_SMOOTH_L1_JACOBI && o->amg.smoother != MGR_SMOOTH_HYBRID_GS) return MGR_ERR_ARG;
+    if (o->amg.agg_levels < 0) return MGR_ERR_ARG;
     if (o->amg.smoother == MGR_SMOOTH_HYBRID_GS && (o->amg.gs_chunk < 1 || o->amg.gs_chunk > mgr::HGS_CHUNK_MAX))
         return MGR_ERR_ARG;
     return MGR_OK;
