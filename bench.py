@@ -375,7 +375,7 @@ def main():
         rows = np.repeat(np.arange(sysd["n"]), np.diff(sysd["rp"]))
         return spmv_bytes(sysd["n"], int(np.count_nonzero((sysd["vals"] != 0.0) | (sysd["ci"] == rows))))
 
-    mim = comp4 = tpfa = ext = frac = fracp = None
+    mim = comp4 = tpfa = ext = frac = fracp = frac_paper = frac_grid = None
     if args.mimetic_steps > 0:
         log("generating hybrid mimetic 64^3 ...")
         sm = W.hybrid_mimetic(64, 64, 64, seed=1)
@@ -427,12 +427,43 @@ def main():
         frac = secondary(sf, args.frac_steps,
                          "MGR_U: F = displacements (unknown-based AMG V(2,2) F-relaxation), C = fracture pressures "
                          "-> AMG", 5, reuse=(3, True))
+        # the AMG settings of Sec. 4.1 for the mechanics block: one level of aggressive
+        # coarsening (multi-pass interpolation) and hybrid L1 Gauss-Seidel, V(1,1)
+        # and V(2,2) (chunks of 32 rows)
+        sfa = dict(sf, levels=[W.level(7, "amg", amg_unknown_based=True, amg_agg_levels=1)])
+        frac_paper = {}
+        for nu in (1, 2):
+            sfa["solver_opts"] = dict(nu_pre=nu, nu_post=nu, smoother="hybrid-gs", chunk=32)
+            frac_paper[f"v{nu}{nu}"] = secondary(
+                dict(sfa, name=sf["name"] + f"_agg1_hgs_v{nu}{nu}"), args.frac_steps,
+                f"MGR_U, F-relaxation AMG with one aggressive level and hybrid L1 Gauss-Seidel V({nu},{nu})", 5,
+                reuse=(3, True))
         sp_ = dict(sf, name=sf["name"] + "_mgr_p", levels=[W.level(1 << 3, "amg")],
                    solver_opts=dict(nu_pre=2, nu_post=2, unknown_based=True))
         fracp = secondary(sp_, args.frac_steps,
                           "MGR_P: F = fracture pressures (AMG V(2,2) F-relaxation), C = displacements -> "
                           "unknown-based AMG", 5)
-        del sf, sp_
+        del sf, sp_, sfa
+        # iteration counts to 1e-8 against the grid, for each setting
+        frac_grid = {}
+        for nn, sd in ((12, 5), (18, 6), (30, 7), (48, 8)):
+            sg = W.fracturing(nn, seed=sd)
+            row = {}
+            for key, lv, o in (
+                    ("mgr_u_l1jacobi_v22", sg["levels"], dict(nu_pre=2, nu_post=2)),
+                    ("mgr_u_agg1_hgs_v11", [W.level(7, "amg", amg_unknown_based=True, amg_agg_levels=1)],
+                     dict(nu_pre=1, nu_post=1, smoother="hybrid-gs", chunk=32)),
+                    ("mgr_u_agg1_hgs_v22", [W.level(7, "amg", amg_unknown_based=True, amg_agg_levels=1)],
+                     dict(nu_pre=2, nu_post=2, smoother="hybrid-gs", chunk=32))):
+                g_ = P.Solver(sg["b"], sg["rp"], sg["ci"], sg["vals"], sg["field"], lv, **o)
+                _, [ig] = g_.solve(torch.tensor(sg["rhs"], device="cuda"))
+                row[key] = ig.iterations
+                g_.close()
+            frac_grid[f"{nn}^3"] = row
+            log(f"  fracturing {nn}^3 iterations: {row}")
+        frac_grid["96^3"] = {"mgr_u_l1jacobi_v22": frac["fp64"]["iterations"],
+                             "mgr_u_agg1_hgs_v11": frac_paper["v11"]["fp64"]["iterations"],
+                             "mgr_u_agg1_hgs_v22": frac_paper["v22"]["fp64"]["iterations"]}
 
     # ---- FP64 oracle on the machine's host cores, on the headline workload
     cpu = None
@@ -519,6 +550,8 @@ def main():
         "secondary_mimetic_tpfa_reductions": tpfa,
         "secondary_fracturing_mgr_u": frac,
         "secondary_fracturing_mgr_p": fracp,
+        "secondary_fracturing_mgr_u_paper_amg": frac_paper,
+        "fracturing_iterations_by_grid": frac_grid,
         "cpu_baseline": cpu,
     })
     print(json.dumps(out), flush=True)
