@@ -591,24 +591,25 @@ static_assert(ELL_SLICE == TPB, "an ELL slice is one workgroup's rows");
 // value come in with coalesced loads, all of them before the first gather, and
 // the products are summed in row order (padding slots hold zero values and the
 // row's own column, or column 0 beyond the last column).
-template <typename MT, int TAG, class Op>
+// WMAX (16 or 32) bounds the slots a thread holds in registers.
+template <typename MT, int TAG, int WMAX, class Op>
 __global__ __launch_bounds__(TPB) void k_spmv_ell(int nr, int w, const int* __restrict__ esw,
                                                   const int* __restrict__ eci, const MT* __restrict__ ev, Op op) {
     const int r = blockIdx.x * TPB + threadIdx.x;
     const int sw = min(esw[blockIdx.x], w);
     if (r >= nr) return;
     const long base = (long)blockIdx.x * w * TPB + threadIdx.x;
-    int c[ELL_MAX_W];
-    MT a[ELL_MAX_W];
+    int c[WMAX];
+    MT a[WMAX];
 #pragma unroll
-    for (int k = 0; k < ELL_MAX_W; ++k)
+    for (int k = 0; k < WMAX; ++k)
         if (k < sw) {
             c[k] = eci[base + (long)k * TPB];
             a[k] = ev[base + (long)k * TPB];
         }
     MT s = MT(0);
 #pragma unroll
-    for (int k = 0; k < ELL_MAX_W; ++k)
+    for (int k = 0; k < WMAX; ++k)
         if (k < sw) s += a[k] * op.xval(c[k]);
     op.done(r, s);
 }
@@ -629,44 +630,49 @@ __global__ __launch_bounds__(TPB) void k_ell_widths(int nr, const int* __restric
 }
 
 // One workgroup per slice: the slice's entries (one contiguous range of the
-// CSR arrays) come into LDS with coalesced loads, then each thread writes its
-// row's slots (coalesced across the slice's rows).  A slice with more entries
-// than the stage (only if a row exceeds the recorded longest row) reads them
-// from memory instead.
+// CSR arrays) come into LDS with coalesced loads, a window of ELL_STAGE_W * TPB
+// entries at a time, and each thread writes the slots of its row that the
+// window holds (coalesced across the slice's rows); the padding slots last.
+constexpr int ELL_STAGE_W = 16;
 template <typename MT>
 __global__ __launch_bounds__(TPB) void k_to_ell(int nr, int nc, int w, const int* __restrict__ esw,
                                                 const int* __restrict__ rp, const int* __restrict__ ci,
                                                 const MT* __restrict__ v, int* __restrict__ eci,
                                                 MT* __restrict__ ev) {
+    constexpr int STAGE = ELL_STAGE_W * TPB;
     __shared__ int srp[TPB + 1];
-    __shared__ int sci[ELL_MAX_W * TPB];
-    __shared__ MT sv[ELL_MAX_W * TPB];
+    __shared__ int sci[STAGE];
+    __shared__ MT sv[STAGE];
     const int r0 = blockIdx.x * TPB;
     const int rows = min(TPB, nr - r0);
     const int sw = min(esw[blockIdx.x], w);
     for (int t = threadIdx.x; t <= rows; t += TPB) srp[t] = rp[r0 + t];
     __syncthreads();
     const int p0 = srp[0], cnt = srp[rows] - p0;
-    const bool staged = cnt <= ELL_MAX_W * TPB;
-    if (staged)
-        for (int q = threadIdx.x; q < cnt; q += TPB) {
-            sci[q] = ci[p0 + q];
-            sv[q] = v[p0 + q];
-        }
-    __syncthreads();
-    if ((int)threadIdx.x >= rows) return;
+    const bool active = (int)threadIdx.x < rows;
     const int r = r0 + threadIdx.x;
-    const int b = srp[threadIdx.x] - p0, len = srp[threadIdx.x + 1] - srp[threadIdx.x];
+    const int b = active ? srp[threadIdx.x] - p0 : 0;
+    const int len = active ? min(srp[threadIdx.x + 1] - srp[threadIdx.x], sw) : 0;
     const long base = (long)blockIdx.x * w * TPB + threadIdx.x;
-    for (int k = 0; k < sw; ++k) {
-        int c = r < nc ? r : 0;
-        MT val = MT(0);
-        if (k < len) {
-            c = staged ? sci[b + k] : ci[p0 + b + k];
-            val = staged ? sv[b + k] : v[p0 + b + k];
+    for (int w0 = 0; w0 < cnt; w0 += STAGE) {
+        const int wn = min(STAGE, cnt - w0);
+        __syncthreads();
+        for (int q = threadIdx.x; q < wn; q += TPB) {
+            if (eci) sci[q] = ci[p0 + w0 + q];
+            sv[q] = v[p0 + w0 + q];
         }
-        if (eci) eci[base + (long)k * TPB] = c;
-        ev[base + (long)k * TPB] = val;
+        __syncthreads();
+        const int k0 = max(0, w0 - b), k1 = min(len, w0 + wn - b);
+        for (int k = k0; k < k1; ++k) {
+            if (eci) eci[base + (long)k * TPB] = sci[b + k - w0];
+            ev[base + (long)k * TPB] = sv[b + k - w0];
+        }
+    }
+    if (!active) return;
+    const int pad = r < nc ? r : 0;
+    for (int k = len; k < sw; ++k) {
+        if (eci) eci[base + (long)k * TPB] = pad;
+        ev[base + (long)k * TPB] = MT(0);
     }
 }
 
@@ -718,8 +724,10 @@ void to_ell(int nr, int nc, int w, const int* esw, const int* rp, const int* ci,
 // the sliced ELL kernel where the operator has that copy, else the CSR stream
 template <typename MT, int TAG, class Op>
 static void launch_rows(const SpOp<MT>& A, const Op& op, hipStream_t s) {
-    if (A.ew > 0 && A.eci && A.ev && A.esw)
-        k_spmv_ell<MT, TAG, Op><<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.ew, A.esw, A.eci, A.ev, op);
+    if (A.ew > 0 && A.eci && A.ev && A.esw && A.ew <= 16)
+        k_spmv_ell<MT, TAG, 16, Op><<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.ew, A.esw, A.eci, A.ev, op);
+    else if (A.ew > 0 && A.eci && A.ev && A.esw)
+        k_spmv_ell<MT, TAG, ELL_MAX_W, Op><<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.ew, A.esw, A.eci, A.ev, op);
     else
         k_spmv_stream<MT, TAG><<<A.nblk, TPB, 0, s>>>(A.blk, A.rp, A.ci, A.v, op);
 }

@@ -1319,31 +1319,43 @@ __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restri
     }
 }
 
+// Block extraction (Sec. 2, the partition of eq. (2)): each row i goes to
+// A_FF / A_FC (F rows) or A_CF / A_CC (C rows) with local numbering lmap.
+// With fblk (the F-relaxation block of each F-point), an F row keeps in A_FF
+// only the columns of its own block: the part of A_FF that M is formed from
+// (the one-sweep apply never reads the rest).  A null output array skips that
+// output (the count stays to be written).
 template <int G>
 __global__ __launch_bounds__(TPB) void k_extract_count_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                          const int* __restrict__ isF, const int* __restrict__ lmap,
-                                                         int* cFF, int* cFC, int* cCF, int* cCC) {
+                                                         const int* __restrict__ fblk, int* cFF, int* cFC, int* cCF,
+                                                         int* cCC) {
     Grp<G> g;
     int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
     int f = 0, c = 0;
-    if (i < n)
+    if (i < n) {
+        const bool rowF = isF[i] != 0;
+        const int fi = (rowF && fblk) ? fblk[lmap[i]] : -1;
         for (int p = rp[i] + g.gl; p < rp[i + 1]; p += G) {
-            if (isF[ci[p]]) ++f;
+            const int j = ci[p];
+            if (isF[j]) f += (fi < 0 || fblk[lmap[j]] == fi) ? 1 : 0;
             else ++c;
         }
+    }
     f = g.sum(f);
     c = g.sum(c);
     if (i < n && g.gl == 0) {
         int l = lmap[i];
-        if (isF[i]) { cFF[l] = f; cFC[l] = c; }
-        else { cCF[l] = f; cCC[l] = c; }
+        if (isF[i]) { if (cFF) cFF[l] = f; if (cFC) cFC[l] = c; }
+        else { if (cCF) cCF[l] = f; if (cCC) cCC[l] = c; }
     }
 }
 
 template <int G>
 __global__ __launch_bounds__(TPB) void k_extract_fill_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                         const double* __restrict__ v, const int* __restrict__ isF,
-                                                        const int* __restrict__ lmap, const int* __restrict__ rpFF,
+                                                        const int* __restrict__ lmap, const int* __restrict__ fblk,
+                                                        const int* __restrict__ rpFF,
                                                         int* ciFF, double* vFF, const int* __restrict__ rpFC,
                                                         int* ciFC, double* vFC, const int* __restrict__ rpCF,
                                                         int* ciCF, double* vCF, const int* __restrict__ rpCC,
@@ -1353,23 +1365,116 @@ __global__ __launch_bounds__(TPB) void k_extract_fill_g(int n, const int* __rest
     bool valid = i < n;
     int p0 = valid ? rp[i] : 0, len = valid ? rp[i + 1] - p0 : 0;
     int maxlen = wave_max_int(len);
-    int oF = 0, oC = 0;
+    int oF = 0, oC = 0, fi = -1;
     int *cF = nullptr, *cC = nullptr;
     double *vF = nullptr, *vC = nullptr;
     if (valid) {
         int l = lmap[i];
-        if (isF[i]) { oF = rpFF[l]; oC = rpFC[l]; cF = ciFF; vF = vFF; cC = ciFC; vC = vFC; }
-        else { oF = rpCF[l]; oC = rpCC[l]; cF = ciCF; vF = vCF; cC = ciCC; vC = vCC; }
+        if (isF[i]) {
+            if (ciFF) { oF = rpFF[l]; cF = ciFF; vF = vFF; }
+            if (ciFC) { oC = rpFC[l]; cC = ciFC; vC = vFC; }
+            if (fblk) fi = fblk[l];
+        } else {
+            if (ciCF) { oF = rpCF[l]; cF = ciCF; vF = vCF; }
+            if (ciCC) { oC = rpCC[l]; cC = ciCC; vC = vCC; }
+        }
     }
     for (int base = 0; base < maxlen; base += G) {
         int q = base + g.gl;
         bool act = q < len;
         int j = act ? ci[p0 + q] : 0;
-        bool f = act && isF[j];
+        bool f = act && isF[j] && (fi < 0 || fblk[lmap[j]] == fi);
         bool c = act && !isF[j];
         unsigned long long bf = g.bits(f), bc = g.bits(c);
-        if (f) { int o = oF + g.below(bf); cF[o] = lmap[j]; vF[o] = v[p0 + q]; }
-        if (c) { int o = oC + g.below(bc); cC[o] = lmap[j]; vC[o] = v[p0 + q]; }
+        if (f && cF) { int o = oF + g.below(bf); cF[o] = lmap[j]; vF[o] = v[p0 + q]; }
+        if (c && cC) { int o = oC + g.below(bc); cC[o] = lmap[j]; vC[o] = v[p0 + q]; }
+        oF += __popcll(bf);
+        oC += __popcll(bc);
+    }
+}
+
+// The same extraction straight from the block-CSR input (b = B): entry q of
+// scalar row i = I B + r is entry r*B + (q mod B) of block q / B of block row
+// I, in column order; an exact zero off the diagonal is not an entry (the
+// scalar operator of the input leaves it out).
+template <int G, int B>
+__global__ __launch_bounds__(TPB) void k_bsr_extract_count_g(int nbr, const int* __restrict__ brp,
+                                                             const int* __restrict__ bci, const double* __restrict__ bv,
+                                                             const int* __restrict__ isF, const int* __restrict__ lmap,
+                                                             const int* __restrict__ fblk, int* cFF, int* cFC,
+                                                             int* cCF, int* cCC) {
+    Grp<G> g;
+    const int n = nbr * B;
+    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    int f = 0, c = 0;
+    if (i < n) {
+        const int I = i / B, r = i - I * B, p0 = brp[I], len = (brp[I + 1] - p0) * B;
+        const bool rowF = isF[i] != 0;
+        const int fi = (rowF && fblk) ? fblk[lmap[i]] : -1;
+        for (int q = g.gl; q < len; q += G) {
+            const int k = q / B, cc = q - k * B;
+            const int j = bci[p0 + k] * B + cc;
+            const double a = bv[((long)(p0 + k) * B + r) * B + cc];
+            if (a == 0.0 && j != i) continue;
+            if (isF[j]) f += (fi < 0 || fblk[lmap[j]] == fi) ? 1 : 0;
+            else ++c;
+        }
+    }
+    f = g.sum(f);
+    c = g.sum(c);
+    if (i < n && g.gl == 0) {
+        int l = lmap[i];
+        if (isF[i]) { if (cFF) cFF[l] = f; if (cFC) cFC[l] = c; }
+        else { if (cCF) cCF[l] = f; if (cCC) cCC[l] = c; }
+    }
+}
+
+template <int G, int B>
+__global__ __launch_bounds__(TPB) void k_bsr_extract_fill_g(int nbr, const int* __restrict__ brp,
+                                                            const int* __restrict__ bci, const double* __restrict__ bv,
+                                                            const int* __restrict__ isF, const int* __restrict__ lmap,
+                                                            const int* __restrict__ fblk,
+                                                            const int* __restrict__ rpFF, int* ciFF, double* vFF,
+                                                            const int* __restrict__ rpFC, int* ciFC, double* vFC,
+                                                            const int* __restrict__ rpCF, int* ciCF, double* vCF,
+                                                            const int* __restrict__ rpCC, int* ciCC, double* vCC) {
+    Grp<G> g;
+    const int n = nbr * B;
+    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    const bool valid = i < n;
+    const int I = valid ? i / B : 0, r = valid ? i - I * B : 0;
+    const int p0 = valid ? brp[I] : 0, len = valid ? (brp[I + 1] - p0) * B : 0;
+    const int maxlen = wave_max_int(len);
+    int oF = 0, oC = 0, fi = -1;
+    int *cF = nullptr, *cC = nullptr;
+    double *vF = nullptr, *vC = nullptr;
+    if (valid) {
+        int l = lmap[i];
+        if (isF[i]) {
+            if (ciFF) { oF = rpFF[l]; cF = ciFF; vF = vFF; }
+            if (ciFC) { oC = rpFC[l]; cC = ciFC; vC = vFC; }
+            if (fblk) fi = fblk[l];
+        } else {
+            if (ciCF) { oF = rpCF[l]; cF = ciCF; vF = vCF; }
+            if (ciCC) { oC = rpCC[l]; cC = ciCC; vC = vCC; }
+        }
+    }
+    for (int base = 0; base < maxlen; base += G) {
+        const int q = base + g.gl;
+        const bool act = q < len;
+        int j = 0;
+        double a = 0.0;
+        if (act) {
+            const int k = q / B, cc = q - k * B;
+            j = bci[p0 + k] * B + cc;
+            a = bv[((long)(p0 + k) * B + r) * B + cc];
+        }
+        const bool keep = act && (a != 0.0 || j == i);
+        const bool f = keep && isF[j] && (fi < 0 || fblk[lmap[j]] == fi);
+        const bool c = keep && !isF[j];
+        unsigned long long bf = g.bits(f), bc = g.bits(c);
+        if (f && cF) { int o = oF + g.below(bf); cF[o] = lmap[j]; vF[o] = a; }
+        if (c && cC) { int o = oC + g.below(bc); cC[o] = lmap[j]; vC[o] = a; }
         oF += __popcll(bf);
         oC += __popcll(bc);
     }
@@ -2598,22 +2703,55 @@ void cf_maps(int n, const int* isF, const int* fpos, int* lmap, int* fmap, int* 
     MGR_LAUNCH_CHECK();
 }
 
-void extract_count(const DCsr& A, const int* isF, const int* lmap, int* cFF, int* cFC, int* cCF, int* cCC,
-                   hipStream_t s) {
+void extract_count(const DCsr& A, const int* isF, const int* lmap, const int* fblk, int* cFF, int* cFC, int* cCF,
+                   int* cCC, hipStream_t s) {
     if (A.nr <= 0) return;
     int G = group_rows(A.max_row);
-    MGR_DISPATCH_G4(G, (k_extract_count_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, isF, lmap, cFF,
-                                                                                   cFC, cCF, cCC)));
+    MGR_DISPATCH_G4(G, (k_extract_count_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, isF, lmap, fblk,
+                                                                                   cFF, cFC, cCF, cCC)));
     MGR_LAUNCH_CHECK();
 }
 
-void extract_fill(const DCsr& A, const int* isF, const int* lmap, DCsr& FF, DCsr& FC, DCsr& CF, DCsr& CC,
-                  hipStream_t s) {
+// the arrays of an output CSR, or nulls when it is not produced (nr == 0 and no rows)
+static inline const int* orp(const DCsr* M) { return M ? M->rp.p : nullptr; }
+static inline int* oci(DCsr* M) { return M ? M->ci.p : nullptr; }
+static inline double* ov(DCsr* M) { return M ? M->v.p : nullptr; }
+
+void extract_fill(const DCsr& A, const int* isF, const int* lmap, const int* fblk, DCsr* FF, DCsr* FC, DCsr* CF,
+                  DCsr* CC, hipStream_t s) {
     if (A.nr <= 0) return;
     int G = group_rows(A.max_row);
     MGR_DISPATCH_G4(G, (k_extract_fill_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(
-                           A.nr, A.rp.p, A.ci.p, A.v.p, isF, lmap, FF.rp.p, FF.ci.p, FF.v.p, FC.rp.p, FC.ci.p, FC.v.p,
-                           CF.rp.p, CF.ci.p, CF.v.p, CC.rp.p, CC.ci.p, CC.v.p)));
+                           A.nr, A.rp.p, A.ci.p, A.v.p, isF, lmap, fblk, orp(FF), oci(FF), ov(FF), orp(FC), oci(FC),
+                           ov(FC), orp(CF), oci(CF), ov(CF), orp(CC), oci(CC), ov(CC))));
+    MGR_LAUNCH_CHECK();
+}
+
+#define MGR_DISPATCH_B(B, ...)                                    \
+    switch (B) {                                                  \
+        case 2: { constexpr int BB = 2; __VA_ARGS__; } break;     \
+        case 3: { constexpr int BB = 3; __VA_ARGS__; } break;     \
+        default: { constexpr int BB = 4; __VA_ARGS__; } break;    \
+    }
+
+void bsr_extract_count(int b, int nbr, long nnzb, const int* brp, const int* bci, const double* bv, const int* isF,
+                       const int* lmap, const int* fblk, int* cFF, int* cFC, int* cCF, int* cCC, hipStream_t s) {
+    if (nbr <= 0) return;
+    const int n = nbr * b;
+    const int G = group_rows((int)((nnzb + nbr - 1) / nbr) * b);
+    MGR_DISPATCH_B(b, MGR_DISPATCH_G4(G, (k_bsr_extract_count_g<GG, BB><<<grid_for(n, GG), TPB, 0, s>>>(
+                                             nbr, brp, bci, bv, isF, lmap, fblk, cFF, cFC, cCF, cCC))));
+    MGR_LAUNCH_CHECK();
+}
+
+void bsr_extract_fill(int b, int nbr, long nnzb, const int* brp, const int* bci, const double* bv, const int* isF,
+                      const int* lmap, const int* fblk, DCsr* FF, DCsr* FC, DCsr* CF, DCsr* CC, hipStream_t s) {
+    if (nbr <= 0) return;
+    const int n = nbr * b;
+    const int G = group_rows((int)((nnzb + nbr - 1) / nbr) * b);
+    MGR_DISPATCH_B(b, MGR_DISPATCH_G4(G, (k_bsr_extract_fill_g<GG, BB><<<grid_for(n, GG), TPB, 0, s>>>(
+                                             nbr, brp, bci, bv, isF, lmap, fblk, orp(FF), oci(FF), ov(FF), orp(FC),
+                                             oci(FC), ov(FC), orp(CF), oci(CF), ov(CF), orp(CC), oci(CC), ov(CC)))));
     MGR_LAUNCH_CHECK();
 }
 

@@ -36,11 +36,19 @@ void cf_flags(int n, const int* field, uint32_t mask, int* isF, int* flag, hipSt
 void cf_maps(int n, const int* isF, const int* fpos, int* lmap, int* fmap, int* cmap, hipStream_t s);
 void iota_div(int n, int b, int* out, hipStream_t s);
 void gather_int(int n, const int* map, const int* src, int* dst, hipStream_t s);
-// row counts of the four blocks A_FF, A_FC (F rows), A_CF, A_CC (C rows)
-void extract_count(const DCsr& A, const int* isF, const int* lmap, int* cFF, int* cFC, int* cCF, int* cCC,
-                   hipStream_t s);
-void extract_fill(const DCsr& A, const int* isF, const int* lmap, DCsr& FF, DCsr& FC, DCsr& CF, DCsr& CC,
-                  hipStream_t s);
+// row counts of the four blocks A_FF, A_FC (F rows), A_CF, A_CC (C rows), then
+// their entries; fblk (F-relaxation block of each F-point, or null) keeps in
+// A_FF only each F row's own block; null counts / outputs are skipped.  The
+// bsr_ variants read the block-CSR input directly (exact zeros inside blocks
+// off the diagonal are not entries).
+void extract_count(const DCsr& A, const int* isF, const int* lmap, const int* fblk, int* cFF, int* cFC, int* cCF,
+                   int* cCC, hipStream_t s);
+void extract_fill(const DCsr& A, const int* isF, const int* lmap, const int* fblk, DCsr* FF, DCsr* FC, DCsr* CF,
+                  DCsr* CC, hipStream_t s);
+void bsr_extract_count(int b, int nbr, long nnzb, const int* brp, const int* bci, const double* bv, const int* isF,
+                       const int* lmap, const int* fblk, int* cFF, int* cFC, int* cCF, int* cCC, hipStream_t s);
+void bsr_extract_fill(int b, int nbr, long nnzb, const int* brp, const int* bci, const double* bv, const int* isF,
+                      const int* lmap, const int* fblk, DCsr* FF, DCsr* FC, DCsr* CF, DCsr* CC, hipStream_t s);
 
 // F-relaxation operator: blocks = runs of consecutive F-points with equal block id
 // (Jacobi: every point its own block).  bstart gets nb+1 entries.

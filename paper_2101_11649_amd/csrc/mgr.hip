@@ -974,6 +974,7 @@ struct MgrLevel {
                                              // last level's is owned by the coarse AMG)
     DCsr AFFt, ACFt, PFt, RFt, Mt;           // general transposed apply
     bool have_float = false, have_trans = false;
+    bool aff_partial = false;                // AFF holds only the F-relaxation blocks
     std::unique_ptr<Amg> famg;
     // ILU(0) F-relaxation: L (unit, strict lower), U (diagonal + upper), their
     // transposes, and the level schedules of the four triangular solves
@@ -1045,11 +1046,38 @@ static bool fused_ok(const mgr_level_opts& o) {
 // nF (the number of F-points, known from the label histogram) sizes the
 // level's arrays without a sync; the scan's own count is checked at the first
 // sync.
-static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr& A, const int* field, const int* block,
+// The level's input is the scalar operator A, or, for the first level of a
+// block input (A null), the block-CSR input itself.
+static void level_extract_count(Ctx& c, const DCsr* A, const int* isF, const int* lmap, const int* fblk, int* cFF,
+                                int* cFC, int* cCF, int* cCC) {
+    if (A) extract_count(*A, isF, lmap, fblk, cFF, cFC, cCF, cCC, c.s);
+    else bsr_extract_count(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, c.Av.p, isF, lmap, fblk, cFF, cFC, cCF, cCC, c.s);
+}
+static void level_extract_fill(Ctx& c, const DCsr* A, const int* isF, const int* lmap, const int* fblk, DCsr* FF,
+                               DCsr* FC, DCsr* CF, DCsr* CC) {
+    if (A) extract_fill(*A, isF, lmap, fblk, FF, FC, CF, CC, c.s);
+    else bsr_extract_fill(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, c.Av.p, isF, lmap, fblk, FF, FC, CF, CC, c.s);
+}
+
+// The whole of A_FF for a level that kept only its F-relaxation blocks (for
+// export): extracted again from the level's input.
+static void ensure_full_aff(Ctx& c, int lev) {
+    MgrLevel& l = c.L[lev];
+    if (!l.aff_partial) return;
+    const DCsr* A = lev > 0 ? &c.L[lev - 1].Aout : (c.A0.nr ? &c.A0 : nullptr);
+    DArr<int> cFF((size_t)l.n + 1, c.s);
+    level_extract_count(c, A, l.isF.p, l.lmap.p, nullptr, cFF.p, nullptr, nullptr, nullptr);
+    DCsr FF = csr_from_counts(l.nF, l.nF, cFF.p, c.slots, "A_FF");
+    level_extract_fill(c, A, l.isF.p, l.lmap.p, nullptr, &FF, nullptr, nullptr, nullptr);
+    l.AFF = std::move(FF);
+    l.aff_partial = false;
+}
+
+static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr* A, const int* field, const int* block,
                             const mgr_level_opts& o, int lev, int nF) {
     hipStream_t s = c.s;
     Slots& S = c.slots;
-    int n = A.nr;
+    int n = A ? A->nr : c.n;
     l.n = n;
     l.o = o;
     l.isF.alloc((size_t)n + 1, s);
@@ -1066,15 +1094,9 @@ static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr& A, const int* field
     l.fmap.alloc((size_t)n, s);
     l.cmap.alloc((size_t)n, s);
     cf_maps(n, l.isF.p, fpos.p, l.lmap.p, l.fmap.p, l.cmap.p, s);
-    // block extraction and the F-relaxation block structure (Jacobi: 1x1 blocks;
-    // block-Jacobi: the F-points of one block row)
-    DArr<int> cFF((size_t)n + 1, s), cFC((size_t)n + 1, s), cCF((size_t)n + 1, s), cCC((size_t)n + 1, s);
-    extract_count(A, l.isF.p, l.lmap.p, cFF.p, cFC.p, cCF.p, cCC.p, s);
-    Pend pFF = csr_begin(l.AFF, l.nF, l.nF, cFF.p, S);
-    Pend pFC = csr_begin(l.AFC, l.nF, l.nC, cFC.p, S);
-    Pend pCF = csr_begin(l.ACF, l.nC, l.nF, cCF.p, S);
-    Pend pCC = csr_begin(l.ACC, l.nC, l.nC, cCC.p, S);
-    DArr<int> bid, flagk((size_t)l.nF + 1, s), excl((size_t)l.nF + 1, s), bnum((size_t)l.nF, s),
+    // the F-relaxation block structure (Jacobi: 1x1 blocks; block-Jacobi: the
+    // F-points of one group), then the block extraction
+    DArr<int> bid, flagk((size_t)l.nF + 1, s), excl((size_t)l.nF + 1, s), bnum((size_t)l.nF + 1, s),
         len((size_t)l.nF + 1, s), bstart((size_t)l.nF + 1, s);
     const int* bidp = nullptr;
     if (o.frelax == MGR_FRELAX_BLOCK_JACOBI) {
@@ -1088,11 +1110,21 @@ static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr& A, const int* field
     frelax_block_starts(l.nF, flagk.p, excl.p, bstart.p, bnum.p, s);
     frelax_row_len(l.nF, bnum.p, bstart.p, len.p, S.flag(), s);
     Pend pM = csr_begin(l.M, l.nF, l.nF, len.p, S);
+    // the one-sweep apply never reads A_FF: only the part M is formed from (each
+    // F row's own block) is extracted; the rest follows on demand (export)
+    l.aff_partial = fused_ok(o);
+    const int* fblk = l.aff_partial ? bnum.p : nullptr;
+    DArr<int> cFF((size_t)n + 1, s), cFC((size_t)n + 1, s), cCF((size_t)n + 1, s), cCC((size_t)n + 1, s);
+    level_extract_count(c, A, l.isF.p, l.lmap.p, fblk, cFF.p, cFC.p, cCF.p, cCC.p);
+    Pend pFF = csr_begin(l.AFF, l.nF, l.nF, cFF.p, S);
+    Pend pFC = csr_begin(l.AFC, l.nF, l.nC, cFC.p, S);
+    Pend pCF = csr_begin(l.ACF, l.nC, l.nF, cCF.p, S);
+    Pend pCC = csr_begin(l.ACC, l.nC, l.nC, cCC.p, S);
     S.sync("block extraction");
     if (S.val(sF) != l.nF) throw Error(MGR_ERR_ARG, "internal: F-point count differs from the label histogram");
     csr_finish(pFF, S); csr_finish(pFC, S); csr_finish(pCF, S); csr_finish(pCC, S); csr_finish(pM, S);
     long nb = (long)S.val(sB);
-    extract_fill(A, l.isF.p, l.lmap.p, l.AFF, l.AFC, l.ACF, l.ACC, s);
+    level_extract_fill(c, A, l.isF.p, l.lmap.p, fblk, &l.AFF, &l.AFC, &l.ACF, &l.ACC);
     // M's pivots are checked at the next sync (an invalid one sets the flag);
     // until then M is only an operand of products, never used for control
     frelax_fill((int)nb, bstart.p, l.AFF, l.M, S.flag(), s);
@@ -1853,6 +1885,19 @@ static void expand_input(Ctx& c) {
     bsr_fill(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, c.Av.p, c.A0, s);
 }
 
+// The scalar level-0 operator is needed for a plain CSR input (its matvec and
+// first level) and for an AMG without MGR levels; the first MGR level of a
+// block input is extracted from the blocks directly, and then only the label
+// histogram (which sizes the levels) has to reach the host.
+static void prepare_input(Ctx& c, int nlevels) {
+    if (c.b == 1 || nlevels == 0) {
+        expand_input(c);
+        return;
+    }
+    c.A0 = DCsr();
+    c.slots.sync("input labels");
+}
+
 static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nlevels, const mgr_level_opts* lvl,
                   const int32_t* block) {
     hipStream_t s = c.s;
@@ -1898,7 +1943,7 @@ static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nle
     c.fhist.alloc(32, s);
     field_hist(c.n, c.field0.p, c.fhist.p, c.slots.flag(), s);
     MGR_HIP(hipMemcpyAsync(c.fhist_h, c.fhist.p, sizeof(int) * 32, hipMemcpyDeviceToHost, s));
-    expand_input(c);
+    prepare_input(c, nlevels);
     c.lvl.assign(lvl, lvl + nlevels);
     build_hierarchy(c);
 }
@@ -1914,7 +1959,8 @@ static void build_hierarchy(Ctx& c) {
     MGR_HIP(hipMemcpyAsync(fld.p, c.field0.p, sizeof(int) * c.n, hipMemcpyDeviceToDevice, s));
     if (c.block0.p) MGR_HIP(hipMemcpyAsync(blk.p, c.block0.p, sizeof(int) * c.n, hipMemcpyDeviceToDevice, s));
     else iota_div(c.n, c.b, blk.p, s);
-    const DCsr* cur = &c.A0;
+    // a block input's first level is extracted from the blocks themselves
+    const DCsr* cur = c.A0.nr ? &c.A0 : nullptr;
     DCsr next;
     c.L.resize(nlevels);
     uint32_t used = 0;  // fields that were F on an earlier level
@@ -1927,8 +1973,8 @@ static void build_hierarchy(Ctx& c) {
             if ((lvl[l].f_field_mask >> f) & 1u) nF += c.fhist_h[f];
         }
         used |= lvl[l].f_field_mask;
-        if (nrem != cur->nr) throw Error(MGR_ERR_ARG, "internal: label histogram and level size differ");
-        DCsr Ac = mgr_setup_level(c, c.L[l], *cur, fld.p, blk.p, lvl[l], l, (int)nF);
+        if (nrem != (cur ? cur->nr : c.n)) throw Error(MGR_ERR_ARG, "internal: label histogram and level size differ");
+        DCsr Ac = mgr_setup_level(c, c.L[l], cur, fld.p, blk.p, lvl[l], l, (int)nF);
         MgrLevel& L = c.L[l];
         DArr<int> f2((size_t)L.nC, s), b2((size_t)L.nC, s);
         gather_int(L.nC, L.cmap.p, fld.p, f2.p, s);
@@ -1974,7 +2020,7 @@ static void update_values(Ctx& c, const double* values, int flags) {
     c.ready = false;
     long bb = (long)c.b * c.b;
     MGR_HIP(hipMemcpyAsync(c.Av.p, values, sizeof(double) * c.nnzb * bb, hipMemcpyDeviceToDevice, s));
-    expand_input(c);
+    prepare_input(c, (int)c.lvl.size());
     c.A0t = DCsr();
     c.ATrp.reset(); c.ATci.reset(); c.ATv.reset();
     c.have_At = false;
@@ -2027,7 +2073,10 @@ static int do_export(Ctx& c, int kind, int level, int what, int sub, int64_t* si
         if (what == 1) A = (level + 1 < (int)c.L.size()) ? &l.Aout : &c.camg.lv[0].A;
         if (what == 2) A = &l.PF;
         if (what == 3) A = &l.RF;
-        if (what == 4) A = &l.AFF;
+        if (what == 4) {
+            ensure_full_aff(c, level);
+            A = &l.AFF;
+        }
         if (what == 5) A = &l.M;
         if ((what == 6 || what == 7) && !l.fused) throw Error(MGR_ERR_ARG, "level has no fused apply operators");
         if (what == 6) A = &l.RJ;
