@@ -176,7 +176,7 @@ int mgr_set_opts(mgr_handle h, const mgr_opts *o);
  * instance); a block of more than 4 F-points is UNSUPPORTED.  Copied; kept for
  * mgr_update_values.
  * The handle owns all the device memory of the hierarchy; operators with
- * short, nearly uniform rows (at least 32768 rows of at most 32 entries) also
+ * short, nearly uniform rows (at least 32768 rows of at most 16 entries) also
  * get a sliced ELL copy for their SpMVs, made on first use, when it exceeds
  * their entries by at most 15%.
  * Errors: ARG, BAD_LABELS (empty F or C set, label out of range), ZERO_PIVOT,

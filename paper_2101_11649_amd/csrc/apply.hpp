@@ -47,7 +47,7 @@ inline SpOp<T> view(const DCsr& A);
 // widths (read back with a synchronisation): its slots may exceed the stored
 // entries by 15% at most (rows of very different lengths mixed within slices
 // would make the copy longer than the CSR stream it replaces).
-constexpr int ELL_MAX_W = 32;
+constexpr int ELL_MAX_W = 16;
 constexpr int ELL_MIN_ROWS = 32768;
 constexpr int ELL_SLICE = 256;   // rows per slice = threads per workgroup of the kernel
 inline bool ell_ok(const DCsr& A) {

@@ -591,7 +591,7 @@ static_assert(ELL_SLICE == TPB, "an ELL slice is one workgroup's rows");
 // value come in with coalesced loads, all of them before the first gather, and
 // the products are summed in row order (padding slots hold zero values and the
 // row's own column, or column 0 beyond the last column).
-// WMAX (16 or 32) bounds the slots a thread holds in registers.
+// WMAX bounds the slots a thread holds in registers.
 template <typename MT, int TAG, int WMAX, class Op>
 __global__ __launch_bounds__(TPB) void k_spmv_ell(int nr, int w, const int* __restrict__ esw,
                                                   const int* __restrict__ eci, const MT* __restrict__ ev, Op op) {
@@ -724,9 +724,7 @@ void to_ell(int nr, int nc, int w, const int* esw, const int* rp, const int* ci,
 // the sliced ELL kernel where the operator has that copy, else the CSR stream
 template <typename MT, int TAG, class Op>
 static void launch_rows(const SpOp<MT>& A, const Op& op, hipStream_t s) {
-    if (A.ew > 0 && A.eci && A.ev && A.esw && A.ew <= 16)
-        k_spmv_ell<MT, TAG, 16, Op><<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.ew, A.esw, A.eci, A.ev, op);
-    else if (A.ew > 0 && A.eci && A.ev && A.esw)
+    if (A.ew > 0 && A.eci && A.ev && A.esw)
         k_spmv_ell<MT, TAG, ELL_MAX_W, Op><<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.ew, A.esw, A.eci, A.ev, op);
     else
         k_spmv_stream<MT, TAG><<<A.nblk, TPB, 0, s>>>(A.blk, A.rp, A.ci, A.v, op);

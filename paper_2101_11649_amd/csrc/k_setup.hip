@@ -1393,10 +1393,61 @@ __global__ __launch_bounds__(TPB) void k_extract_fill_g(int n, const int* __rest
     }
 }
 
-// The same extraction straight from the block-CSR input (b = B): entry q of
-// scalar row i = I B + r is entry r*B + (q mod B) of block q / B of block row
-// I, in column order; an exact zero off the diagonal is not an entry (the
-// scalar operator of the input leaves it out).
+// The same extraction straight from the block-CSR input (b = B): G lanes per
+// block row, one block per lane at a time (its B x B values in one contiguous
+// load, the F flags of its B columns together), so that the block values are
+// read once for the B scalar rows.  Entry (r, c) of block (I, J) is entry
+// (I B + r, J B + c) of the scalar operator unless it is an exact zero off the
+// diagonal (the scalar operator of the input leaves those out).  Lanes hold
+// consecutive blocks, so the per-lane counts scanned in lane order place the
+// entries in column order.
+template <int B>
+struct BsrBlock {
+    double a[B][B];
+    int J;
+    bool cf[B];     // column J B + c is an F-point
+    int cl[B];      // its local index
+    __device__ void load(int p, const int* __restrict__ bci, const double* __restrict__ bv,
+                         const int* __restrict__ isF, const int* __restrict__ lmap) {
+        J = bci[p];
+        const double* src = bv + (long)p * B * B;
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+            for (int c = 0; c < B; ++c) a[r][c] = src[r * B + c];
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+            cf[c] = isF[J * B + c] != 0;
+            cl[c] = lmap[J * B + c];
+        }
+    }
+};
+
+// row r of this lane's block: kept F (in A_FF's block when ffb >= 0) and C entries
+template <int B>
+__device__ inline void bsr_row_counts(const BsrBlock<B>& k, int I, int r, int ffb, const int* __restrict__ fblk,
+                                      int& nf, int& nc) {
+    nf = 0;
+    nc = 0;
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+        const bool keep = k.a[r][c] != 0.0 || (k.J == I && c == r);
+        if (!keep) continue;
+        if (k.cf[c]) nf += (ffb < 0 || fblk[k.cl[c]] == ffb) ? 1 : 0;
+        else ++nc;
+    }
+}
+
+template <int G>
+__device__ inline int group_scan_incl(int v, int gl) {
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) {
+        const int t = __shfl_up(v, off, G);
+        if (gl >= off) v += t;
+    }
+    return v;
+}
+
 template <int G, int B>
 __global__ __launch_bounds__(TPB) void k_bsr_extract_count_g(int nbr, const int* __restrict__ brp,
                                                              const int* __restrict__ bci, const double* __restrict__ bv,
@@ -1404,28 +1455,39 @@ __global__ __launch_bounds__(TPB) void k_bsr_extract_count_g(int nbr, const int*
                                                              const int* __restrict__ fblk, int* cFF, int* cFC,
                                                              int* cCF, int* cCC) {
     Grp<G> g;
-    const int n = nbr * B;
-    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
-    int f = 0, c = 0;
-    if (i < n) {
-        const int I = i / B, r = i - I * B, p0 = brp[I], len = (brp[I + 1] - p0) * B;
-        const bool rowF = isF[i] != 0;
-        const int fi = (rowF && fblk) ? fblk[lmap[i]] : -1;
-        for (int q = g.gl; q < len; q += G) {
-            const int k = q / B, cc = q - k * B;
-            const int j = bci[p0 + k] * B + cc;
-            const double a = bv[((long)(p0 + k) * B + r) * B + cc];
-            if (a == 0.0 && j != i) continue;
-            if (isF[j]) f += (fi < 0 || fblk[lmap[j]] == fi) ? 1 : 0;
-            else ++c;
+    const int I = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    const bool valid = I < nbr;
+    int ffb[B], nf[B], nc[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+        nf[r] = nc[r] = 0;
+        ffb[r] = (valid && fblk && isF[I * B + r]) ? fblk[lmap[I * B + r]] : -1;
+    }
+    if (valid) {
+        BsrBlock<B> k;
+        for (int p = brp[I] + g.gl; p < brp[I + 1]; p += G) {
+            k.load(p, bci, bv, isF, lmap);
+#pragma unroll
+            for (int r = 0; r < B; ++r) {
+                int f, c;
+                bsr_row_counts<B>(k, I, r, ffb[r], fblk, f, c);
+                nf[r] += f;
+                nc[r] += c;
+            }
         }
     }
-    f = g.sum(f);
-    c = g.sum(c);
-    if (i < n && g.gl == 0) {
-        int l = lmap[i];
-        if (isF[i]) { if (cFF) cFF[l] = f; if (cFC) cFC[l] = c; }
-        else { if (cCF) cCF[l] = f; if (cCC) cCC[l] = c; }
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+        nf[r] = g.sum(nf[r]);
+        nc[r] = g.sum(nc[r]);
+    }
+    if (valid && g.gl == 0) {
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            const int i = I * B + r, l = lmap[i];
+            if (isF[i]) { if (cFF) cFF[l] = nf[r]; if (cFC) cFC[l] = nc[r]; }
+            else { if (cCF) cCF[l] = nf[r]; if (cCC) cCC[l] = nc[r]; }
+        }
     }
 }
 
@@ -1439,44 +1501,60 @@ __global__ __launch_bounds__(TPB) void k_bsr_extract_fill_g(int nbr, const int* 
                                                             const int* __restrict__ rpCF, int* ciCF, double* vCF,
                                                             const int* __restrict__ rpCC, int* ciCC, double* vCC) {
     Grp<G> g;
-    const int n = nbr * B;
-    int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
-    const bool valid = i < n;
-    const int I = valid ? i / B : 0, r = valid ? i - I * B : 0;
-    const int p0 = valid ? brp[I] : 0, len = valid ? (brp[I + 1] - p0) * B : 0;
-    const int maxlen = wave_max_int(len);
-    int oF = 0, oC = 0, fi = -1;
-    int *cF = nullptr, *cC = nullptr;
-    double *vF = nullptr, *vC = nullptr;
-    if (valid) {
-        int l = lmap[i];
+    const int I = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    const bool valid = I < nbr;
+    const int p0 = valid ? brp[I] : 0, nb = valid ? brp[I + 1] - p0 : 0;
+    int maxnb = nb;
+    for (int off = WAVE / 2; off > 0; off >>= 1) maxnb = max(maxnb, __shfl_xor(maxnb, off, WAVE));
+    int ffb[B], oF[B], oC[B];
+    int* cF[B];
+    int* cC[B];
+    double* vF[B];
+    double* vC[B];
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+        ffb[r] = -1; oF[r] = oC[r] = 0;
+        cF[r] = cC[r] = nullptr; vF[r] = vC[r] = nullptr;
+        if (!valid) continue;
+        const int i = I * B + r, l = lmap[i];
         if (isF[i]) {
-            if (ciFF) { oF = rpFF[l]; cF = ciFF; vF = vFF; }
-            if (ciFC) { oC = rpFC[l]; cC = ciFC; vC = vFC; }
-            if (fblk) fi = fblk[l];
+            if (ciFF) { oF[r] = rpFF[l]; cF[r] = ciFF; vF[r] = vFF; }
+            if (ciFC) { oC[r] = rpFC[l]; cC[r] = ciFC; vC[r] = vFC; }
+            if (fblk) ffb[r] = fblk[l];
         } else {
-            if (ciCF) { oF = rpCF[l]; cF = ciCF; vF = vCF; }
-            if (ciCC) { oC = rpCC[l]; cC = ciCC; vC = vCC; }
+            if (ciCF) { oF[r] = rpCF[l]; cF[r] = ciCF; vF[r] = vCF; }
+            if (ciCC) { oC[r] = rpCC[l]; cC[r] = ciCC; vC[r] = vCC; }
         }
     }
-    for (int base = 0; base < maxlen; base += G) {
+    for (int base = 0; base < maxnb; base += G) {
         const int q = base + g.gl;
-        const bool act = q < len;
-        int j = 0;
-        double a = 0.0;
-        if (act) {
-            const int k = q / B, cc = q - k * B;
-            j = bci[p0 + k] * B + cc;
-            a = bv[((long)(p0 + k) * B + r) * B + cc];
+        const bool act = q < nb;
+        BsrBlock<B> k;
+        if (act) k.load(p0 + q, bci, bv, isF, lmap);
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            int f = 0, c = 0;
+            if (act) bsr_row_counts<B>(k, I, r, ffb[r], fblk, f, c);
+            const int fi = group_scan_incl<G>(f, g.gl), ci = group_scan_incl<G>(c, g.gl);
+            int wf = oF[r] + fi - f, wc = oC[r] + ci - c;
+            if (act) {
+#pragma unroll
+                for (int cc = 0; cc < B; ++cc) {
+                    const double a = k.a[r][cc];
+                    if (!(a != 0.0 || (k.J == I && cc == r))) continue;
+                    if (k.cf[cc]) {
+                        if (ffb[r] >= 0 && fblk[k.cl[cc]] != ffb[r]) continue;
+                        if (cF[r]) { cF[r][wf] = k.cl[cc]; vF[r][wf] = a; }
+                        ++wf;
+                    } else {
+                        if (cC[r]) { cC[r][wc] = k.cl[cc]; vC[r][wc] = a; }
+                        ++wc;
+                    }
+                }
+            }
+            oF[r] += __shfl(fi, g.gbase + G - 1, WAVE);
+            oC[r] += __shfl(ci, g.gbase + G - 1, WAVE);
         }
-        const bool keep = act && (a != 0.0 || j == i);
-        const bool f = keep && isF[j] && (fi < 0 || fblk[lmap[j]] == fi);
-        const bool c = keep && !isF[j];
-        unsigned long long bf = g.bits(f), bc = g.bits(c);
-        if (f && cF) { int o = oF + g.below(bf); cF[o] = lmap[j]; vF[o] = a; }
-        if (c && cC) { int o = oC + g.below(bc); cC[o] = lmap[j]; vC[o] = a; }
-        oF += __popcll(bf);
-        oC += __popcll(bc);
     }
 }
 
@@ -2734,12 +2812,17 @@ void extract_fill(const DCsr& A, const int* isF, const int* lmap, const int* fbl
         default: { constexpr int BB = 4; __VA_ARGS__; } break;    \
     }
 
+// lanes per block row: about one block per lane
+static int bsr_group(int nbr, long nnzb) {
+    const int avg = (int)((nnzb + nbr - 1) / nbr);
+    return avg <= 4 ? 4 : avg <= 8 ? 8 : avg <= 16 ? 16 : avg <= 32 ? 32 : 64;
+}
+
 void bsr_extract_count(int b, int nbr, long nnzb, const int* brp, const int* bci, const double* bv, const int* isF,
                        const int* lmap, const int* fblk, int* cFF, int* cFC, int* cCF, int* cCC, hipStream_t s) {
     if (nbr <= 0) return;
-    const int n = nbr * b;
-    const int G = group_rows((int)((nnzb + nbr - 1) / nbr) * b);
-    MGR_DISPATCH_B(b, MGR_DISPATCH_G4(G, (k_bsr_extract_count_g<GG, BB><<<grid_for(n, GG), TPB, 0, s>>>(
+    const int G = bsr_group(nbr, nnzb);
+    MGR_DISPATCH_B(b, MGR_DISPATCH_G4(G, (k_bsr_extract_count_g<GG, BB><<<grid_for(nbr, GG), TPB, 0, s>>>(
                                              nbr, brp, bci, bv, isF, lmap, fblk, cFF, cFC, cCF, cCC))));
     MGR_LAUNCH_CHECK();
 }
@@ -2747,9 +2830,8 @@ void bsr_extract_count(int b, int nbr, long nnzb, const int* brp, const int* bci
 void bsr_extract_fill(int b, int nbr, long nnzb, const int* brp, const int* bci, const double* bv, const int* isF,
                       const int* lmap, const int* fblk, DCsr* FF, DCsr* FC, DCsr* CF, DCsr* CC, hipStream_t s) {
     if (nbr <= 0) return;
-    const int n = nbr * b;
-    const int G = group_rows((int)((nnzb + nbr - 1) / nbr) * b);
-    MGR_DISPATCH_B(b, MGR_DISPATCH_G4(G, (k_bsr_extract_fill_g<GG, BB><<<grid_for(n, GG), TPB, 0, s>>>(
+    const int G = bsr_group(nbr, nnzb);
+    MGR_DISPATCH_B(b, MGR_DISPATCH_G4(G, (k_bsr_extract_fill_g<GG, BB><<<grid_for(nbr, GG), TPB, 0, s>>>(
                                              nbr, brp, bci, bv, isF, lmap, fblk, orp(FF), oci(FF), ov(FF), orp(FC),
                                              oci(FC), ov(FC), orp(CF), oci(CF), ov(CF), orp(CC), oci(CC), ov(CC)))));
     MGR_LAUNCH_CHECK();

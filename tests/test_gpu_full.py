@@ -97,8 +97,8 @@ def test_full_size_parity(cfg):
 def test_full_size_fracturing():
     """96^3 nodes (2,654,208 displacements + 9,216 fracture pressures).  The
     oracle's setup is compared level by level (MGR split, the unknown-based AMG
-    used as F-relaxation, the coarse AMG) and one apply; the oracle solve is too
-    slow here, so the GPU solution is checked by its true residual."""
+    used as F-relaxation, the coarse AMG), one apply, and the solution (the
+    oracle's solve phase runs on all host cores)."""
     t0 = time.time()
     s = W.fracturing(96, seed=3)
     say(f"[full] fracturing 96^3: n={s['n']}, stored values {len(s['vals'])}, generated in {time.time() - t0:.1f} s")
@@ -115,3 +115,37 @@ def test_full_size_fracturing():
     _check_hierarchy(gs, om, s["levels"])
     v = np.random.default_rng(12).standard_normal(s["n"])
     assert elem_err(gs.apply(v).cpu().numpy(), om.apply(v), s["field"]) <= 1e-10
+    t0 = time.time()
+    xo, io = om.solve(s["rhs"])
+    say(f"[full] fracturing: oracle solve {time.time() - t0:.1f} s, iterations {io.iterations}; "
+        f"x diff {rel(x, xo):.2e}, entry-wise {elem_err(x, xo, s['field']):.2e}")
+    assert abs(ig.iterations - io.iterations) <= 1
+    assert elem_err(x, xo, s["field"]) <= 1e-8
+
+
+def test_full_size_ilu0_on_compositional_components():
+    """ILU(0) as F-relaxation of the three component densities (Sec. 3.2's
+    choice for transport blocks) at the full compositional size: A_FF of
+    3,145,744 rows factored on its own pattern, level-scheduled triangular
+    solves; hierarchy, apply and solution against the oracle."""
+    s = W.compositional_wells(seed=2)
+    lv = [dict(s["levels"][0], frelax="ilu0"), s["levels"][1]]
+    say(f"[full] compositional 128x128x64 with ILU(0) on the components: n={s['n']}")
+    gs = gpu_solver(s, levels=lv)
+    X, [ig] = gs.solve(s["rhs"])
+    x = X.cpu().numpy()
+    A = W.csr_of(s)
+    tr = np.linalg.norm(s["rhs"] - A @ x) / np.linalg.norm(s["rhs"])
+    say(f"[full] ilu0: gpu iterations {ig.iterations}, true residual {tr:.2e}")
+    assert ig.status == 0 and tr <= 1e-8
+    t0 = time.time()
+    om = oracle_mgr(s, levels=lv)
+    say(f"[full] ilu0: oracle setup {time.time() - t0:.1f} s")
+    _check_hierarchy(gs, om, lv)
+    v = np.random.default_rng(13).standard_normal(s["n"])
+    assert elem_err(gs.apply(v).cpu().numpy(), om.apply(v), s["field"]) <= 1e-10
+    t0 = time.time()
+    xo, io = om.solve(s["rhs"])
+    say(f"[full] ilu0: oracle solve {time.time() - t0:.1f} s, iterations {io.iterations}")
+    assert abs(ig.iterations - io.iterations) <= 1
+    assert elem_err(x, xo, s["field"]) <= 1e-8
