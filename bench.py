@@ -155,84 +155,145 @@ def run_steps(P, s, vals, rhs, precision, steps, warmup, **opts):
     return solver, rec, X, info, stream
 
 
-def apply_launches(solver, precision, nu_pre=1, nu_post=1):
-    """The launches of one forward MGR apply (Algorithm 1 with the fused
-    one-sweep levels, then the AMG V-cycle on the coarse system), in order, each
-    with its algorithmic bytes: operator values + column indices + row pointers
-    once, every vector it reads or writes once.  s = bytes of a value in the
-    apply precision; the apply's input and output stay FP64.  Returns None for
-    hierarchies with a level in general form (several launches per step that
-    this model does not list)."""
+def apply_launches(solver, precision, nu_pre=1, nu_post=1, levels=None, smoother="l1-jacobi"):
+    """The launches of one forward MGR apply (Algorithm 1, then the AMG V-cycle
+    on the coarse system), in order, each with its algorithmic bytes: operator
+    values + column indices + row pointers once, every vector it reads or
+    writes once.  s = bytes of a value in the apply precision; the apply's
+    input and output stay FP64.  One-sweep levels with injection are the fused
+    pair R_J / P_J; other levels (one sweep, injection) gather, relax (M, or
+    the F-relaxation AMG's V-cycle), restrict with A_CF, interpolate with P_F
+    and scatter.  With the hybrid Gauss-Seidel smoother the per-chunk pass is
+    counted by its vectors only (a lower bound).  None for level options this
+    model does not list (several sweeps, Jacobi restriction, ILU(0))."""
     s = 4 if precision == 32 else 8
     info = solver.info()
     mgr, amg = info["mgr_levels"], info["amg_levels"]
+    levels = levels or [{}] * len(mgr)
+    gs = smoother == "hybrid-gs"
     out = []
 
     def sp(nr, nnz):
         return nnz * (s + 4) + 4 * (nr + 1)
 
-    def amg_cycle(k, scaled):
-        n = amg[k][0]
-        last = len(amg) - 1
-        if k == last:
-            out.append((f"AMG{k} coarsest GEMV", n * n * s + 2 * n * s))
-            return
-        if solver.export_sizes(1, k, 6) is not None:
-            out.append((f"AMG{k} dense cycle GEMV", n * n * s + 2 * n * s))
-            return
-        nc = amg[k + 1][0]
-        g = solver.export_sizes(1, k, 4)
-        if g is not None:
-            wq = solver.export_sizes(1, k, 5)
-            out.append((f"AMG{k} G (composed restriction)", sp(nc, g[2]) + n * s + nc * s))
-            amg_cycle(k + 1, False)
-            out.append((f"AMG{k} [W|Q] (composed smoothing + prolongation)", sp(n, wq[2]) + 2 * n * s + nc * s))
-            return
-        a = sp(n, amg[k][1])
-        p = solver.export_sizes(1, k, 2)[2]
-        if nu_pre >= 1:
-            out.append((f"AMG{k} pre-smoothing + residual", a + 4 * n * s))
-            for _ in range(1, nu_pre):
-                out.append((f"AMG{k} Jacobi sweep", a + 4 * n * s))
-                out.append((f"AMG{k} copy", 2 * n * s))
-            if nu_pre > 1:
-                out.append((f"AMG{k} residual", a + 3 * n * s))
-        else:
-            out.append((f"AMG{k} set", n * s))
-            out.append((f"AMG{k} copy", 2 * n * s))
-        nxt_plain = (k + 2 <= last) and solver.export_sizes(1, k + 1, 4) is None \
-            and solver.export_sizes(1, k + 1, 6) is None
-        if nu_pre >= 1 and nxt_plain:
-            out.append((f"AMG{k} restriction (+ D^-1 b_c)", sp(nc, p) + n * s + 3 * nc * s))
-            amg_cycle(k + 1, True)
-        else:
-            out.append((f"AMG{k} restriction", sp(nc, p) + n * s + nc * s))
-            amg_cycle(k + 1, False)
-        out.append((f"AMG{k} prolongation", sp(n, p) + nc * s + 2 * n * s))
-        for _ in range(nu_post):
-            out.append((f"AMG{k} post-smoothing", a + 4 * n * s))
+    def amg_sizes(kind, sub):
+        if kind == 1:
+            return amg
+        sz, k = [], 0
+        while True:
+            a = solver.export_sizes(2, k, 1, sub)
+            if a is None:
+                return sz
+            sz.append((a[0], a[2]))
+            k += 1
 
-    for l, (n, nF, nC, _) in enumerate(mgr):
-        rj = solver.export_sizes(0, l, 6)
-        if rj is None:
-            return None
-    sv = 8                                  # level-0 vectors are the caller's FP64 ones
-    first_plain = len(amg) >= 2 and solver.export_sizes(1, 0, 4) is None and solver.export_sizes(1, 0, 6) is None \
-        and nu_pre >= 1
-    for l, (n, nF, nC, _) in enumerate(mgr):
-        vs = sv if l == 0 else s
-        rj = solver.export_sizes(0, l, 6)[2]
-        scaled = (l + 1 == len(mgr)) and first_plain
-        out.append((f"MGR{l} restriction R_J", sp(nC, rj) + n * vs + (3 if scaled else 1) * nC * s))
-    # interpolations run after the coarse solve, innermost level first
-    amg_cycle(0, first_plain)
-    for l in reversed(range(len(mgr))):
+    def amg_cycle(kind, sub, lv, k, tag):
+        n = lv[k][0]
+        last = len(lv) - 1
+        if k == last:
+            out.append((f"{tag}{k} coarsest GEMV", n * n * s + 2 * n * s))
+            return
+        if solver.export_sizes(kind, k, 6, sub) is not None:
+            out.append((f"{tag}{k} dense cycle GEMV", n * n * s + 2 * n * s))
+            return
+        nc = lv[k + 1][0]
+        g = solver.export_sizes(kind, k, 4, sub)
+        if g is not None:
+            wq = solver.export_sizes(kind, k, 5, sub)
+            out.append((f"{tag}{k} G (composed restriction)", sp(nc, g[2]) + n * s + nc * s))
+            amg_cycle(kind, sub, lv, k + 1, tag)
+            out.append((f"{tag}{k} [W|Q] (composed smoothing + prolongation)", sp(n, wq[2]) + 2 * n * s + nc * s))
+            return
+        a = sp(n, lv[k][1])
+        p = solver.export_sizes(kind, k, 2, sub)[2]
+        chunk = 8 * n + 4 * n * s              # row pointers, diagonal positions, d, r, x read and written
+        if gs:
+            if nu_pre >= 1:
+                out.append((f"{tag}{k} Gauss-Seidel chunks (from zero)", chunk))
+                for _ in range(1, nu_pre):
+                    out.append((f"{tag}{k} residual", a + 3 * n * s))
+                    out.append((f"{tag}{k} Gauss-Seidel chunks", chunk))
+                out.append((f"{tag}{k} residual", a + 3 * n * s))
+            else:
+                out.append((f"{tag}{k} set", n * s))
+                out.append((f"{tag}{k} copy", 2 * n * s))
+            out.append((f"{tag}{k} restriction", sp(nc, p) + n * s + nc * s))
+            amg_cycle(kind, sub, lv, k + 1, tag)
+            out.append((f"{tag}{k} prolongation", sp(n, p) + nc * s + 2 * n * s))
+            for _ in range(nu_post):
+                out.append((f"{tag}{k} residual", a + 3 * n * s))
+                out.append((f"{tag}{k} Gauss-Seidel chunks", chunk))
+            return
+        if nu_pre >= 1:
+            out.append((f"{tag}{k} pre-smoothing + residual", a + 4 * n * s))
+            for _ in range(1, nu_pre):
+                out.append((f"{tag}{k} Jacobi sweep", a + 4 * n * s))
+                out.append((f"{tag}{k} copy", 2 * n * s))
+            if nu_pre > 1:
+                out.append((f"{tag}{k} residual", a + 3 * n * s))
+        else:
+            out.append((f"{tag}{k} set", n * s))
+            out.append((f"{tag}{k} copy", 2 * n * s))
+        nxt_plain = (k + 2 <= last) and solver.export_sizes(kind, k + 1, 4, sub) is None \
+            and solver.export_sizes(kind, k + 1, 6, sub) is None
+        if nu_pre >= 1 and nxt_plain:
+            out.append((f"{tag}{k} restriction (+ D^-1 b_c)", sp(nc, p) + n * s + 3 * nc * s))
+        else:
+            out.append((f"{tag}{k} restriction", sp(nc, p) + n * s + nc * s))
+        amg_cycle(kind, sub, lv, k + 1, tag)
+        out.append((f"{tag}{k} prolongation", sp(n, p) + nc * s + 2 * n * s))
+        for _ in range(nu_post):
+            out.append((f"{tag}{k} post-smoothing", a + 4 * n * s))
+
+    def mgr_level(l):
         n, nF, nC, _ = mgr[l]
-        vs = sv if l == 0 else s
-        pj = solver.export_sizes(0, l, 7)[2]
-        out.append((f"MGR{l} interpolation P_J", sp(n, pj) + nC * s + 2 * n * vs))
-    # restrictions are listed outermost first, so the order of launches is
-    # R_J(0) .. R_J(L-1), the V-cycle, P_J(L-1) .. P_J(0)
+        vs = 8 if l == 0 else s                 # level-0 vectors are the caller's FP64 ones
+        lo = levels[l] if l < len(levels) else {}
+        if lo.get("sweeps", 1) != 1 or lo.get("restrict", "injection") != "injection":
+            return False
+        rj = solver.export_sizes(0, l, 6)
+        if rj is not None:
+            first_plain = len(amg) >= 2 and solver.export_sizes(1, 0, 4) is None \
+                and solver.export_sizes(1, 0, 6) is None and nu_pre >= 1 and not gs
+            scaled = (l + 1 == len(mgr)) and first_plain
+            out.append((f"MGR{l} restriction R_J", sp(nC, rj[2]) + n * vs + (3 if scaled else 1) * nC * s))
+            if l + 1 < len(mgr):
+                if not mgr_level(l + 1):
+                    return False
+            else:
+                amg_cycle(1, -1, amg, 0, "AMG")
+            pj = solver.export_sizes(0, l, 7)[2]
+            out.append((f"MGR{l} interpolation P_J", sp(n, pj) + nC * s + 2 * n * vs))
+            return True
+        fr = lo.get("frelax", "jacobi")
+        if fr == "ilu0":
+            return False
+        out.append((f"MGR{l} gather v_F", 4 * nF + nF * vs + nF * s))
+        out.append((f"MGR{l} gather v_C", 4 * nC + nC * vs + nC * s))
+        if fr == "amg":
+            famg = amg_sizes(2, l)
+            amg_cycle(2, l, famg, 0, f"MGR{l}.FAMG")
+        else:
+            m = solver.export_sizes(0, l, 5)
+            out.append((f"MGR{l} F-relaxation M", sp(nF, m[2]) + 2 * nF * s))
+        out.append((f"MGR{l} scale z_F = omega t_F", 2 * nF * s))
+        acf = solver.export_sizes(0, l, 9)
+        out.append((f"MGR{l} restriction A_CF", sp(nC, acf[2]) + nF * s + 2 * nC * s))
+        if l + 1 < len(mgr):
+            if not mgr_level(l + 1):
+                return False
+        else:
+            amg_cycle(1, -1, amg, 0, "AMG")
+        pf = solver.export_sizes(0, l, 2)
+        out.append((f"MGR{l} interpolation P_F", sp(nF, pf[2]) + nC * s + 2 * nF * s))
+        out.append((f"MGR{l} scatter z_F", 4 * nF + nF * s + nF * vs))
+        out.append((f"MGR{l} scatter z_C", 4 * nC + nC * s + nC * vs))
+        return True
+
+    if not mgr:
+        return None
+    if not mgr_level(0):
+        return None
     return out
 
 
@@ -252,6 +313,10 @@ def main():
                     help="timed steps of the mimetic system with extended+i AMG interpolation (0 = skip)")
     ap.add_argument("--frac-steps", type=int, default=1,
                     help="timed steps of the fracturing workload, MGR_U and MGR_P (0 = skip)")
+    ap.add_argument("--ilu-steps", type=int, default=1,
+                    help="timed steps of the headline system with ILU(0) F-relaxation of the components (0 = skip)")
+    ap.add_argument("--frac-variant", default="all", choices=["all", "u", "u_paper_v11", "u_paper_v22", "p"],
+                    help="run one fracturing variant only (profiling runs); 'all' adds the grid sweep")
     ap.add_argument("--no-headline", action="store_true",
                     help="skip the headline workload (profiling runs of the secondaries alone)")
     ap.add_argument("--launch-table", action="store_true",
@@ -300,8 +365,9 @@ def main():
         o = s64.opts.amg
         res = {"apply_ms_fp64": round(1e3 * t64, 4), "apply_ms_fp32": round(1e3 * t32, 4),
                "speedup_per_apply": round(t64 / t32, 4)}
+        sm = "hybrid-gs" if o.smoother == 1 else "l1-jacobi"
         for key, sv, t, prec in (("fp64", s64, t64, 64), ("fp32", s32, t32, 32)):
-            la = apply_launches(sv, prec, o.nu_pre, o.nu_post)
+            la = apply_launches(sv, prec, o.nu_pre, o.nu_post, levels=sv.levels, smoother=sm)
             if la is None:
                 continue
             b = sum(x for _, x in la)
@@ -375,7 +441,13 @@ def main():
         rows = np.repeat(np.arange(sysd["n"]), np.diff(sysd["rp"]))
         return spmv_bytes(sysd["n"], int(np.count_nonzero((sysd["vals"] != 0.0) | (sysd["ci"] == rows))))
 
-    mim = comp4 = tpfa = ext = frac = fracp = frac_paper = frac_grid = None
+    mim = comp4 = tpfa = ext = frac = fracp = frac_paper = frac_grid = ilu = None
+    if args.ilu_steps > 0 and s is not None:
+        # ILU(0) as F-relaxation of the three component densities (Sec. 3.2), level-scheduled
+        log("compositional 128x128x64 with ILU(0) on the components ...")
+        si = dict(s, name=s["name"] + "_ilu0", levels=[dict(s["levels"][0], frelax="ilu0"), s["levels"][1]])
+        ilu = secondary(si, args.ilu_steps, "L1 F = components (ILU(0)), L2 F = wells (Jacobi), coarse pressure AMG", 5)
+        del si
     if args.mimetic_steps > 0:
         log("generating hybrid mimetic 64^3 ...")
         sm = W.hybrid_mimetic(64, 64, 64, seed=1)
@@ -424,29 +496,35 @@ def main():
         # fracture) with both reductions of Sec. 3.3
         log("generating fracturing 96^3 ...")
         sf = W.fracturing(96, seed=3)
-        frac = secondary(sf, args.frac_steps,
-                         "MGR_U: F = displacements (unknown-based AMG V(2,2) F-relaxation), C = fracture pressures "
-                         "-> AMG", 5, reuse=(3, True))
+        fv = args.frac_variant
+        if fv in ("all", "u"):
+            frac = secondary(sf, args.frac_steps,
+                             "MGR_U: F = displacements (unknown-based AMG V(2,2) F-relaxation), C = fracture "
+                             "pressures -> AMG", 5, reuse=(3, True))
         # the AMG settings of Sec. 4.1 for the mechanics block: one level of aggressive
         # coarsening (multi-pass interpolation) and hybrid L1 Gauss-Seidel, V(1,1)
         # and V(2,2) (chunks of 32 rows)
         sfa = dict(sf, levels=[W.level(7, "amg", amg_unknown_based=True, amg_agg_levels=1)])
         frac_paper = {}
         for nu in (1, 2):
+            if fv not in ("all", f"u_paper_v{nu}{nu}"):
+                continue
             sfa["solver_opts"] = dict(nu_pre=nu, nu_post=nu, smoother="hybrid-gs", chunk=32)
             frac_paper[f"v{nu}{nu}"] = secondary(
                 dict(sfa, name=sf["name"] + f"_agg1_hgs_v{nu}{nu}"), args.frac_steps,
                 f"MGR_U, F-relaxation AMG with one aggressive level and hybrid L1 Gauss-Seidel V({nu},{nu})", 5,
                 reuse=(3, True))
-        sp_ = dict(sf, name=sf["name"] + "_mgr_p", levels=[W.level(1 << 3, "amg")],
-                   solver_opts=dict(nu_pre=2, nu_post=2, unknown_based=True))
-        fracp = secondary(sp_, args.frac_steps,
-                          "MGR_P: F = fracture pressures (AMG V(2,2) F-relaxation), C = displacements -> "
-                          "unknown-based AMG", 5)
-        del sf, sp_, sfa
+        if fv in ("all", "p"):
+            sp_ = dict(sf, name=sf["name"] + "_mgr_p", levels=[W.level(1 << 3, "amg")],
+                       solver_opts=dict(nu_pre=2, nu_post=2, unknown_based=True))
+            fracp = secondary(sp_, args.frac_steps,
+                              "MGR_P: F = fracture pressures (AMG V(2,2) F-relaxation), C = displacements -> "
+                              "unknown-based AMG", 5)
+            del sp_
+        del sf, sfa
         # iteration counts to 1e-8 against the grid, for each setting
-        frac_grid = {}
-        for nn, sd in ((12, 5), (18, 6), (30, 7), (48, 8)):
+        frac_grid = {} if fv == "all" else None
+        for nn, sd in ((12, 5), (18, 6), (30, 7), (48, 8)) if fv == "all" else ():
             sg = W.fracturing(nn, seed=sd)
             row = {}
             for key, lv, o in (
@@ -461,9 +539,10 @@ def main():
                 g_.close()
             frac_grid[f"{nn}^3"] = row
             log(f"  fracturing {nn}^3 iterations: {row}")
-        frac_grid["96^3"] = {"mgr_u_l1jacobi_v22": frac["fp64"]["iterations"],
-                             "mgr_u_agg1_hgs_v11": frac_paper["v11"]["fp64"]["iterations"],
-                             "mgr_u_agg1_hgs_v22": frac_paper["v22"]["fp64"]["iterations"]}
+        if frac_grid is not None:
+            frac_grid["96^3"] = {"mgr_u_l1jacobi_v22": frac["fp64"]["iterations"],
+                                 "mgr_u_agg1_hgs_v11": frac_paper["v11"]["fp64"]["iterations"],
+                                 "mgr_u_agg1_hgs_v22": frac_paper["v22"]["fp64"]["iterations"]}
 
     # ---- FP64 oracle on the machine's host cores, on the headline workload
     cpu = None
@@ -547,6 +626,7 @@ def main():
         "secondary_mimetic": mim,
         "secondary_mimetic_ext_interp": ext,
         "secondary_compositional_4level": comp4,
+        "secondary_compositional_ilu0": ilu,
         "secondary_mimetic_tpfa_reductions": tpfa,
         "secondary_fracturing_mgr_u": frac,
         "secondary_fracturing_mgr_p": fracp,

@@ -255,7 +255,8 @@ int mgr_hierarchy_info(mgr_handle h, int64_t *out, int32_t cap);
  * 5 = F-relaxation operator M, 6 = R_J = [-omega A_CF M | I] and 7 = P_J =
  * [P_F | omega M ; I | 0] (the two operators of the one-sweep apply with
  * injection, global numbering, columns of P_J: coarse then fine; ARG for a
- * level applied in general form).  kind 1 = coarse AMG level `level`, kind 2 =
+ * level applied in general form), 8 = A_FC, 9 = A_CF, 10 = A_CC.  kind 1 =
+ * coarse AMG level `level`, kind 2 =
  * the F-relaxation AMG of MGR level `sub`: what 0 = C/F (+1 = C, -1 = F), 1 =
  * A_k, 2 = P_k, 3 = the dense inverse of the coarsest level (level = last; n x
  * n row-major doubles in b2), 4 = G = R - (R A) D^-1 and 5 = [W | Q] (W = 2D^-1

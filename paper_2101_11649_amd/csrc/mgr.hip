@@ -2081,6 +2081,9 @@ static int do_export(Ctx& c, int kind, int level, int what, int sub, int64_t* si
         if ((what == 6 || what == 7) && !l.fused) throw Error(MGR_ERR_ARG, "level has no fused apply operators");
         if (what == 6) A = &l.RJ;
         if (what == 7) A = &l.PJ;
+        if (what == 8) A = &l.AFC;
+        if (what == 9) A = &l.ACF;
+        if (what == 10) A = &l.ACC;
         if (!A) throw Error(MGR_ERR_ARG, "unknown export item");
         export_csr(*A, sizes, b0, b1, b2, s);
         return MGR_OK;
