@@ -163,8 +163,9 @@ def apply_launches(solver, precision, nu_pre=1, nu_post=1, levels=None, smoother
     input and output stay FP64.  One-sweep levels with injection are the fused
     pair R_J / P_J; other levels (one sweep, injection) gather, relax (M, or
     the F-relaxation AMG's V-cycle), restrict with A_CF, interpolate with P_F
-    and scatter.  With the hybrid Gauss-Seidel smoother the per-chunk pass is
-    counted by its vectors only (a lower bound).  None for level options this
+    and scatter.  With the hybrid Gauss-Seidel smoother the per-chunk pass
+    counts its slot table as stored (padding included), the diagonal in the
+    table's layout and its vectors.  None for level options this
     model does not list (several sweeps, Jacobi restriction, ILU(0))."""
     s = 4 if precision == 32 else 8
     info = solver.info()
@@ -206,13 +207,17 @@ def apply_launches(solver, precision, nu_pre=1, nu_post=1, levels=None, smoother
             return
         a = sp(n, lv[k][1])
         p = solver.export_sizes(kind, k, 2, sub)[2]
-        chunk = 8 * n + 4 * n * s              # row pointers, diagonal positions, d, r, x read and written
         if gs:
+            def chunk(what, from_zero):
+                # slot table (local column byte + value per slot), d in the
+                # table layout, r read, x read (not from zero) and written
+                per, _, slots = solver.export_sizes(kind, k, what, sub)
+                return slots * (1 + s) + per * s + (2 if from_zero else 3) * n * s
             if nu_pre >= 1:
-                out.append((f"{tag}{k} Gauss-Seidel chunks (from zero)", chunk))
+                out.append((f"{tag}{k} Gauss-Seidel chunks (from zero)", chunk(7, True)))
                 for _ in range(1, nu_pre):
                     out.append((f"{tag}{k} residual", a + 3 * n * s))
-                    out.append((f"{tag}{k} Gauss-Seidel chunks", chunk))
+                    out.append((f"{tag}{k} Gauss-Seidel chunks", chunk(7, False)))
                 out.append((f"{tag}{k} residual", a + 3 * n * s))
             else:
                 out.append((f"{tag}{k} set", n * s))
@@ -222,7 +227,7 @@ def apply_launches(solver, precision, nu_pre=1, nu_post=1, levels=None, smoother
             out.append((f"{tag}{k} prolongation", sp(n, p) + nc * s + 2 * n * s))
             for _ in range(nu_post):
                 out.append((f"{tag}{k} residual", a + 3 * n * s))
-                out.append((f"{tag}{k} Gauss-Seidel chunks", chunk))
+                out.append((f"{tag}{k} Gauss-Seidel chunks", chunk(8, False)))
             return
         if nu_pre >= 1:
             out.append((f"{tag}{k} pre-smoothing + residual", a + 4 * n * s))

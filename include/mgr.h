@@ -263,7 +263,13 @@ int mgr_hierarchy_info(mgr_handle h, int64_t *out, int32_t cap);
  * - D^-1 A D^-1, Q = P - D^-1 A P) of a level applied in composed form (ARG
  * otherwise), 6 = the dense cycle operator W + Q C^-1 G of the composed level
  * above the coarsest, when its cycle is applied as one GEMV (n x n row-major
- * doubles in b2; ARG for any other level).  sizes[0..2] = rows, cols, nnz (vector length in sizes[0]);
+ * doubles in b2; ARG for any other level), 7 and 8 = the slot tables of the
+ * hybrid Gauss-Seidel sweeps on A_k (7: forward, each row's entries left of
+ * its diagonal inside its chunk; 8: backward, right of it): sizes = (chunk
+ * positions x table chunks, slots per row, their product); slot k of position
+ * t of chunk c at (t W + k) nchunks + c, b1 = its column relative to the chunk
+ * start (int32), b2 = its value (0 in padding slots); ARG without the hybrid
+ * smoother.  sizes[0..2] = rows, cols, nnz (vector length in sizes[0]);
  * b0 = row_ptr (or the C/F vector), b1 = col_idx, b2 = values (double). */
 int mgr_export(mgr_handle h, int32_t kind, int32_t level, int32_t what, int32_t sub, int64_t *sizes,
                void *b0, void *b1, void *b2);

@@ -195,14 +195,16 @@ void arnoldi_update(long n, double* V, long ldv, int nvec, const double* sh, dou
 // w -= hscale * sum_i h[i] V_i; if norm2_out, *norm2_out = ||w_new||^2.
 void maxpy(long n, const double* V, long ldv, int nvec, const double* h, double hscale, double* w, double* part,
            double* norm2_out, hipStream_t s);
-// Hybrid L1 Gauss-Seidel: chunks of `chunk` consecutive rows (1..HGS_CHUNK_MAX),
-// each relaxed in order by one thread; r = b - A x of the old x (or b when the
-// sweep starts from zero, which then overwrites x); d = the chunked L1
-// diagonal; dpos = the position of each row's diagonal entry in A.
+// Hybrid L1 Gauss-Seidel, second pass of a sweep: chunks of `chunk`
+// consecutive rows (1..HGS_CHUNK_MAX), each relaxed in order by one thread;
+// r = b - A x of the old x (or b when the sweep starts from zero, which then
+// overwrites x).  The in-chunk entries of the sweep's direction come from the
+// slot tables of hgs_tri_fill (width w, nchp chunks, a multiple of 64), dT =
+// the reciprocal chunked L1 diagonal in the same chunk-position layout.
 constexpr int HGS_CHUNK_MAX = 128;
 template <typename T>
-void hgs_chunk(const SpOp<T>& A, const int* dpos, const T* d, const T* r, T* x, int chunk, bool backward,
-               bool from_zero, hipStream_t s);
+void hgs_tri(int n, int chunk, int w, int nchp, const unsigned char* lc, const T* lv, const T* dT, const T* r, T* x,
+             bool backward, bool from_zero, hipStream_t s);
 // rows[0..cnt) of one level of a triangular solve with matrix A: x_i = (b_i - sum_{j!=i} a_ij x_j) / a_ii
 // (unit: diagonal 1 and not stored).  b may alias x.
 template <typename T>

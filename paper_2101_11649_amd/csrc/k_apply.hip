@@ -488,53 +488,133 @@ __global__ void k_trsv_level(int cnt, const int* __restrict__ rows, const int* _
 }
 
 // Second pass of one hybrid L1 Gauss-Seidel sweep (the first is r = b - A x on
-// the whole operator).  Thread c owns the chunk of rows [c*chunk, min(n,
-// (c+1)*chunk)) and relaxes them one after another (forward: increasing,
-// backward: decreasing), x_i += delta_i with
+// the whole operator).  Thread c of the workgroup owns chunk c of its 64
+// chunks of `chunk` consecutive rows and relaxes them one after another
+// (forward: increasing, backward: decreasing), x_i += delta_i with
 //   delta_i = (r_i - sum_{j in the chunk, already relaxed} a_ij delta_j) / d_i,
 // which with r_i = b_i - sum_j a_ij x_j is the sweep
 //   x_i <- x_i + (b_i - sum_j a_ij y_j) / d_i,  y_j new for the chunk's rows
-// already relaxed and old for every other unknown.  The relaxed entries of a
-// row lie next to its diagonal (columns ascending), so they are read from the
-// diagonal outwards until the chunk boundary.  The corrections of the chunk
-// live in LDS, slot k of thread t at k * blockDim + t (consecutive threads,
-// consecutive banks).  from_zero: x starts at 0 (r = b) and is overwritten.
-template <typename T>
-__global__ __launch_bounds__(64) void k_hgs_chunk(int n, int chunk, const int* __restrict__ rp,
-                                                  const int* __restrict__ ci, const T* __restrict__ v,
-                                                  const int* __restrict__ dpos, const T* __restrict__ d,
-                                                  const T* __restrict__ r, T* __restrict__ x, int backward,
-                                                  int from_zero) {
-    extern __shared__ unsigned char hgs_lds[];
-    T* dl = reinterpret_cast<T*>(hgs_lds);
-    const int tg = blockDim.x, me = threadIdx.x;
-    const long c0l = ((long)blockIdx.x * tg + me) * chunk;
-    if (c0l >= n) return;
-    const int c0 = (int)c0l, c1 = min(n, c0 + chunk), len = c1 - c0;
-    for (int t = 0; t < len; ++t) {
-        const int i = backward ? c1 - 1 - t : c0 + t;
-        T acc = r[i];
-        const int pd = dpos[i];   // >= 0: setup refuses a row without a diagonal entry
-        if (pd < 0) {
-        } else if (!backward) {
-            const int pb = rp[i];
-            for (int p = pd - 1; p >= pb; --p) {
-                const int j = ci[p];
-                if (j < c0) break;
-                acc -= v[p] * dl[(j - c0) * tg + me];
-            }
-        } else {
-            const int pe = rp[i + 1];
-            for (int p = pd + 1; p < pe; ++p) {
-                const int j = ci[p];
-                if (j >= c1) break;
-                acc -= v[p] * dl[(j - c0) * tg + me];
+// already relaxed and old for every other unknown.  The in-chunk entries come
+// from slot tables made at setup (slot k of position t of chunk c at
+// (t W + k) nchp + c: the 64 threads read adjacent addresses, and a step's
+// loads are issued one step ahead, so the sequential part waits on LDS, not
+// on memory); padding slots hold 0.  r is staged in LDS with coalesced loads,
+// row t of thread c at t * 65 + c (conflict-free for the threads of a step),
+// each r_i there is overwritten by delta_i, and x is updated with coalesced
+// stores at the end.  WMAX > 0: tables of at most WMAX slots per row held in
+// registers; WMAX = 0: any width, loads inside the step.  from_zero: x starts
+// at 0 (r = b) and is overwritten.
+constexpr int HGS_LDS_STRIDE = 65;
+// Batched staging: every thread issues HGS_BATCH loads before its first LDS
+// store, so a workgroup waits for memory once per batch rather than once per
+// element.
+constexpr int HGS_BATCH = 16;
+
+// r[q] (q < span, the workgroup's rows) to LDS at (q % chunk) stride + q / chunk
+template <typename T, int NT>
+__device__ inline void hgs_stage_r(T* buf, int stride, int chunk, const T* __restrict__ r, int span) {
+    for (int q0 = threadIdx.x; q0 < span; q0 += NT * HGS_BATCH) {
+        T v[HGS_BATCH];
+#pragma unroll
+        for (int u = 0; u < HGS_BATCH; ++u) {
+            const int q = q0 + u * NT;
+            v[u] = q < span ? r[q] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < HGS_BATCH; ++u) {
+            const int q = q0 + u * NT;
+            if (q < span) buf[(q % chunk) * stride + q / chunk] = v[u];
+        }
+    }
+}
+
+// x[q] = delta (from_zero) or x[q] + delta for the workgroup's rows
+template <typename T, int NT>
+__device__ inline void hgs_write_x(const T* buf, int stride, int chunk, T* __restrict__ x, int span, int from_zero) {
+    for (int q0 = threadIdx.x; q0 < span; q0 += NT * HGS_BATCH) {
+        T v[HGS_BATCH];
+#pragma unroll
+        for (int u = 0; u < HGS_BATCH; ++u) {
+            const int q = q0 + u * NT;
+            v[u] = (q < span && !from_zero) ? x[q] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < HGS_BATCH; ++u) {
+            const int q = q0 + u * NT;
+            if (q < span) {
+                const T del = buf[(q % chunk) * stride + q / chunk];
+                x[q] = from_zero ? del : v[u] + del;
             }
         }
-        const T del = acc / d[i];
-        dl[(i - c0) * tg + me] = del;
-        x[i] = from_zero ? del : x[i] + del;
     }
+}
+// below this many 64-chunk workgroups a level takes the LDS-staged kernel,
+// whose LDS is kept within the default 64 KB limit
+constexpr int HGS_SMALL_GRID = 256;
+constexpr size_t HGS_LDS_MAX = 65536;
+
+template <typename T, int WMAX>
+__global__ __launch_bounds__(64) void k_hgs_tri(int n, int chunk, int w, int nchp,
+                                                const unsigned char* __restrict__ lc, const T* __restrict__ lv,
+                                                const T* __restrict__ dT, const T* __restrict__ r,
+                                                T* __restrict__ x, int backward, int from_zero) {
+    extern __shared__ unsigned char hgs_lds[];
+    T* buf = reinterpret_cast<T*>(hgs_lds);
+    const int me = threadIdx.x;
+    const int c = blockIdx.x * 64 + me;
+    const long base = (long)blockIdx.x * 64 * chunk;
+    const int span = (int)min((long)64 * chunk, (long)n - base);
+    hgs_stage_r<T, 64>(buf, HGS_LDS_STRIDE, chunk, r + base, span);
+    __syncthreads();
+    const long c0 = (long)c * chunk;
+    const int len = c0 < n ? (int)min((long)chunk, (long)n - c0) : 0;
+    if (WMAX > 0) {
+        constexpr int WR = WMAX > 0 ? WMAX : 1;
+        int cc[WR] = {}, nc[WR] = {};
+        T cv[WR] = {}, nv[WR] = {};
+        T cd = T(1), nd = T(1);
+        // slots past w read column 0 with value 0, so every step issues all
+        // WMAX gathers before its first product (no per-slot branch)
+        auto load = [&](int t, int* kc, T* kv, T& kd) {
+#pragma unroll
+            for (int k = 0; k < WR; ++k) {
+                const size_t o = ((size_t)t * w + k) * nchp + c;
+                kc[k] = k < w ? lc[o] : 0;
+                kv[k] = k < w ? lv[o] : T(0);
+            }
+            kd = dT[(size_t)t * nchp + c];
+        };
+        if (len > 0) load(backward ? len - 1 : 0, cc, cv, cd);
+        for (int s = 0; s < len; ++s) {
+            const int t = backward ? len - 1 - s : s;
+            if (s + 1 < len) load(backward ? t - 1 : t + 1, nc, nv, nd);
+            T g[WR];
+#pragma unroll
+            for (int k = 0; k < WR; ++k) g[k] = buf[cc[k] * HGS_LDS_STRIDE + me];
+            T acc = buf[t * HGS_LDS_STRIDE + me];
+#pragma unroll
+            for (int k = 0; k < WR; ++k) acc -= cv[k] * g[k];
+            buf[t * HGS_LDS_STRIDE + me] = acc * cd;
+#pragma unroll
+            for (int k = 0; k < WR; ++k) {
+                cc[k] = nc[k];
+                cv[k] = nv[k];
+            }
+            cd = nd;
+        }
+    } else {
+        for (int s = 0; s < len; ++s) {
+            const int t = backward ? len - 1 - s : s;
+            T acc = buf[t * HGS_LDS_STRIDE + me];
+            for (int k = 0; k < w; ++k) {
+                const size_t o = ((size_t)t * w + k) * nchp + c;
+                acc -= lv[o] * buf[lc[o] * HGS_LDS_STRIDE + me];
+            }
+            buf[t * HGS_LDS_STRIDE + me] = acc * dT[(size_t)t * nchp + c];
+        }
+    }
+    __syncthreads();
+    hgs_write_x<T, 64>(buf, HGS_LDS_STRIDE, chunk, x + base, span, from_zero);
 }
 
 // Adjoint gradient on the block pattern: dv[p,r,c] = -sum_k lam_k[I b + r] x_k[J b + c].
@@ -915,21 +995,261 @@ void arnoldi_update(long n, double* V, long ldv, int nvec, const double* sh, dou
     MGR_LAUNCH_CHECK();
 }
 
+// The same pass for levels too small to hide memory latency behind other
+// waves (fewer workgroups than compute units).  Each workgroup first stages
+// the slot tables and diagonals of its chunks in LDS with batched coalesced
+// loads, so the sequential steps wait only on LDS; then a single wave, one
+// lane per chunk, runs the steps, and there the instruction count per step is
+// what bounds the time (each wave instruction costs the same however few lanes
+// are active).  The fast variant (chunks of at most HGS_FAST_CHUNK rows, at
+// most WMAX slots per row) therefore fixes the table width and the number of
+// chunks TG at compile time, so that slot reads take immediate offsets, reads
+// a step's slots one step ahead into alternating register sets, issues every
+// gather of a step before its first product and multiplies by the stored 1/d.
+// LDS: r / delta of position t of chunk c at t (TG + 1) + c, slot k of
+// position t at (t WMAX + k) TG + c (slots past the table's width hold column
+// 0 and value 0), 1/d at t TG + c.  The general variant takes any chunk and
+// width with loops over runtime bounds.
+constexpr int HGS_LDS_NT = 256;
+constexpr int HGS_FAST_CHUNK = 32;
+
+template <typename T, int WMAX>
+constexpr size_t hgs_fast_lds(int tg) {
+    return (size_t)HGS_FAST_CHUNK * (tg + 1) * sizeof(T) + (size_t)HGS_FAST_CHUNK * WMAX * tg * (sizeof(T) + 1) +
+           (size_t)HGS_FAST_CHUNK * tg * sizeof(T);
+}
+
+// chunks per workgroup of the fast variant: the most that fit HGS_LDS_MAX
+template <typename T, int WMAX>
+constexpr int hgs_fast_tg() {
+    int tg = 64;
+    while (tg > 1 && hgs_fast_lds<T, WMAX>(tg) > HGS_LDS_MAX) tg /= 2;
+    return tg;
+}
+
+template <typename T, int WMAX>
+__global__ __launch_bounds__(HGS_LDS_NT) void k_hgs_tri_fast(int n, int chunk, int w, int nchp,
+                                                             const unsigned char* __restrict__ lc,
+                                                             const T* __restrict__ lv, const T* __restrict__ dT,
+                                                             const T* __restrict__ r, T* __restrict__ x,
+                                                             int backward, int from_zero) {
+    constexpr int NT = HGS_LDS_NT, TG = hgs_fast_tg<T, WMAX>(), ST = TG + 1, C = HGS_FAST_CHUNK;
+    static_assert(hgs_fast_lds<T, WMAX>(TG) <= HGS_LDS_MAX, "fast Gauss-Seidel tables exceed the LDS budget");
+    __shared__ T buf[C * ST];
+    __shared__ T tv[C * WMAX * TG];
+    __shared__ T td[C * TG];
+    __shared__ unsigned char tc[C * WMAX * TG];
+    const int me = threadIdx.x;
+    const int cb = blockIdx.x * TG;
+    const long base = (long)cb * chunk;
+    const int span = (int)min((long)TG * chunk, (long)n - base);
+    hgs_stage_r<T, NT>(buf, ST, chunk, r + base, span);
+    const int ts = chunk * WMAX * TG;
+    for (int q0 = me; q0 < ts; q0 += NT * HGS_BATCH) {
+        T v[HGS_BATCH];
+        unsigned char cc[HGS_BATCH];
+#pragma unroll
+        for (int u = 0; u < HGS_BATCH; ++u) {
+            const int q = q0 + u * NT;
+            const int t = q / (WMAX * TG), k = (q / TG) % WMAX, c = q % TG;
+            const bool in = q < ts && k < w;
+            const size_t o = ((size_t)t * w + k) * nchp + cb + c;
+            v[u] = in ? lv[o] : T(0);
+            cc[u] = in ? lc[o] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < HGS_BATCH; ++u) {
+            const int q = q0 + u * NT;
+            if (q < ts) {
+                tv[q] = v[u];
+                tc[q] = cc[u];
+            }
+        }
+    }
+    for (int q0 = me; q0 < chunk * TG; q0 += NT * HGS_BATCH) {
+        T v[HGS_BATCH];
+#pragma unroll
+        for (int u = 0; u < HGS_BATCH; ++u) {
+            const int q = q0 + u * NT;
+            v[u] = q < chunk * TG ? dT[(size_t)(q / TG) * nchp + cb + q % TG] : T(1);
+        }
+#pragma unroll
+        for (int u = 0; u < HGS_BATCH; ++u) {
+            const int q = q0 + u * NT;
+            if (q < chunk * TG) td[q] = v[u];
+        }
+    }
+    __syncthreads();
+    if (me < TG) {
+        const long c0 = (long)(cb + me) * chunk;
+        const int len = c0 < n ? (int)min((long)chunk, (long)n - c0) : 0;
+        int ca[WMAX], cbk[WMAX];
+        T va[WMAX], vb[WMAX];
+        T da = T(1), db = T(1);
+        auto load = [&](int t, int* kc, T* kv, T& kd) {
+            const int q0 = t * WMAX * TG + me;
+#pragma unroll
+            for (int k = 0; k < WMAX; ++k) {
+                kc[k] = tc[q0 + k * TG];
+                kv[k] = tv[q0 + k * TG];
+            }
+            kd = td[t * TG + me];
+        };
+        auto step = [&](int t, const int* kc, const T* kv, T kd) {
+            T g[WMAX];
+#pragma unroll
+            for (int k = 0; k < WMAX; ++k) g[k] = buf[kc[k] * ST + me];
+            T acc = buf[t * ST + me];
+#pragma unroll
+            for (int k = 0; k < WMAX; ++k) acc -= kv[k] * g[k];
+            buf[t * ST + me] = acc * kd;
+        };
+        const int dir = backward ? -1 : 1, t0 = backward ? len - 1 : 0;
+        if (len > 0) load(t0, ca, va, da);
+        for (int s = 0; s < len; s += 2) {
+            const int t = t0 + dir * s;
+            if (s + 1 < len) load(t + dir, cbk, vb, db);
+            step(t, ca, va, da);
+            if (s + 1 >= len) break;
+            if (s + 2 < len) load(t + 2 * dir, ca, va, da);
+            step(t + dir, cbk, vb, db);
+        }
+    }
+    __syncthreads();
+    hgs_write_x<T, NT>(buf, ST, chunk, x + base, span, from_zero);
+}
+
+// General variant: tg chunks per workgroup (runtime), any chunk and width;
+// LDS as above with the table's own width w.
 template <typename T>
-void hgs_chunk(const SpOp<T>& A, const int* dpos, const T* d, const T* r, T* x, int chunk, bool backward,
-               bool from_zero, hipStream_t s) {
-    if (A.nr <= 0) return;
-    const int tg = chunk <= HGS_CHUNK_MAX / 2 ? 64 : 32;
-    const long nch = ((long)A.nr + chunk - 1) / chunk;
-    const size_t lds = (size_t)tg * chunk * sizeof(T);
-    k_hgs_chunk<T><<<(unsigned)((nch + tg - 1) / tg), tg, lds, s>>>(A.nr, chunk, A.rp, A.ci, A.v, dpos, d, r, x,
-                                                                      backward ? 1 : 0, from_zero ? 1 : 0);
+__global__ __launch_bounds__(HGS_LDS_NT) void k_hgs_tri_lds(int n, int chunk, int w, int nchp, int tg,
+                                                            const unsigned char* __restrict__ lc,
+                                                            const T* __restrict__ lv, const T* __restrict__ dT,
+                                                            const T* __restrict__ r, T* __restrict__ x,
+                                                            int backward, int from_zero) {
+    extern __shared__ unsigned char hgs_lds[];
+    constexpr int NT = HGS_LDS_NT;
+    const int me = threadIdx.x, st = tg + 1;
+    T* buf = reinterpret_cast<T*>(hgs_lds);
+    T* tv = buf + (size_t)chunk * st;
+    T* td = tv + (size_t)chunk * w * tg;
+    unsigned char* tc = reinterpret_cast<unsigned char*>(td + (size_t)chunk * tg);
+    const int cb = blockIdx.x * tg;
+    const long base = (long)cb * chunk;
+    const int span = (int)min((long)tg * chunk, (long)n - base);
+    hgs_stage_r<T, NT>(buf, st, chunk, r + base, span);
+    // slot q of the workgroup's table = global slot (q / tg) nchp + cb + q % tg
+    const int ts = chunk * w * tg;
+    for (int q0 = me; q0 < ts; q0 += NT * HGS_BATCH) {
+        T v[HGS_BATCH];
+        unsigned char cc[HGS_BATCH];
+#pragma unroll
+        for (int u = 0; u < HGS_BATCH; ++u) {
+            const int q = q0 + u * NT;
+            const size_t o = (size_t)(q / tg) * nchp + cb + q % tg;
+            v[u] = q < ts ? lv[o] : T(0);
+            cc[u] = q < ts ? lc[o] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < HGS_BATCH; ++u) {
+            const int q = q0 + u * NT;
+            if (q < ts) {
+                tv[q] = v[u];
+                tc[q] = cc[u];
+            }
+        }
+    }
+    for (int q0 = me; q0 < chunk * tg; q0 += NT * HGS_BATCH) {
+        T v[HGS_BATCH];
+#pragma unroll
+        for (int u = 0; u < HGS_BATCH; ++u) {
+            const int q = q0 + u * NT;
+            v[u] = q < chunk * tg ? dT[(size_t)(q / tg) * nchp + cb + q % tg] : T(1);
+        }
+#pragma unroll
+        for (int u = 0; u < HGS_BATCH; ++u) {
+            const int q = q0 + u * NT;
+            if (q < chunk * tg) td[q] = v[u];
+        }
+    }
+    __syncthreads();
+    if (me < tg) {
+        const long c0 = (long)(cb + me) * chunk;
+        const int len = c0 < n ? (int)min((long)chunk, (long)n - c0) : 0;
+        for (int s = 0; s < len; ++s) {
+            const int t = backward ? len - 1 - s : s;
+            T acc = buf[t * st + me];
+            for (int k = 0; k < w; ++k) {
+                const int q = (t * w + k) * tg + me;
+                acc -= tv[q] * buf[tc[q] * st + me];
+            }
+            buf[t * st + me] = acc * td[t * tg + me];
+        }
+    }
+    __syncthreads();
+    hgs_write_x<T, NT>(buf, st, chunk, x + base, span, from_zero);
+}
+
+// LDS bytes of k_hgs_tri_lds for tg threads
+template <typename T>
+size_t hgs_lds_bytes(int chunk, int w, int tg) {
+    return (size_t)chunk * (tg + 1) * sizeof(T) + (size_t)chunk * w * tg * (sizeof(T) + 1) +
+           (size_t)chunk * tg * sizeof(T);
+}
+
+template <typename T, int WMAX>
+void hgs_fast_launch(int n, int chunk, int w, int nchp, const unsigned char* lc, const T* lv, const T* dT, const T* r,
+                     T* x, int bw, int fz, hipStream_t s) {
+    constexpr int TG = hgs_fast_tg<T, WMAX>();
+    const long nch = ((long)n + chunk - 1) / chunk;
+    k_hgs_tri_fast<T, WMAX><<<(unsigned)((nch + TG - 1) / TG), HGS_LDS_NT, 0, s>>>(n, chunk, w, nchp, lc, lv, dT, r, x,
+                                                                                  bw, fz);
+}
+
+template <typename T>
+void hgs_tri(int n, int chunk, int w, int nchp, const unsigned char* lc, const T* lv, const T* dT, const T* r, T* x,
+             bool backward, bool from_zero, hipStream_t s) {
+    if (n <= 0) return;
+    if (chunk < 1 || chunk > HGS_CHUNK_MAX || w < 0 || (long)nchp * chunk < n || nchp % 64)
+        throw Error(-1, "hgs_tri: chunk, width or table size out of range");
+    const int grid = nchp / 64;
+    const size_t lds = (size_t)chunk * HGS_LDS_STRIDE * sizeof(T);
+    const int bw = backward ? 1 : 0, fz = from_zero ? 1 : 0;
+    if (grid < HGS_SMALL_GRID && chunk <= HGS_FAST_CHUNK && w <= 32) {
+        if (w <= 4) hgs_fast_launch<T, 4>(n, chunk, w, nchp, lc, lv, dT, r, x, bw, fz, s);
+        else if (w <= 8) hgs_fast_launch<T, 8>(n, chunk, w, nchp, lc, lv, dT, r, x, bw, fz, s);
+        else if (w <= 16) hgs_fast_launch<T, 16>(n, chunk, w, nchp, lc, lv, dT, r, x, bw, fz, s);
+        else hgs_fast_launch<T, 32>(n, chunk, w, nchp, lc, lv, dT, r, x, bw, fz, s);
+        MGR_LAUNCH_CHECK();
+        return;
+    }
+    if (grid < HGS_SMALL_GRID) {
+        // small level with wide rows or long chunks: the general LDS variant
+        // with the widest workgroup that fits
+        const long nch = ((long)n + chunk - 1) / chunk;
+        int tg = 64;
+        while (tg > 1 && hgs_lds_bytes<T>(chunk, w, tg) > HGS_LDS_MAX) tg >>= 1;
+        if (hgs_lds_bytes<T>(chunk, w, tg) <= HGS_LDS_MAX) {
+            k_hgs_tri_lds<T><<<(unsigned)((nch + tg - 1) / tg), HGS_LDS_NT, hgs_lds_bytes<T>(chunk, w, tg), s>>>(
+                n, chunk, w, nchp, tg, lc, lv, dT, r, x, bw, fz);
+            MGR_LAUNCH_CHECK();
+            return;
+        }
+    }
+    if (w <= 4)
+        k_hgs_tri<T, 4><<<grid, 64, lds, s>>>(n, chunk, w, nchp, lc, lv, dT, r, x, bw, fz);
+    else if (w <= 8)
+        k_hgs_tri<T, 8><<<grid, 64, lds, s>>>(n, chunk, w, nchp, lc, lv, dT, r, x, bw, fz);
+    else if (w <= 16)
+        k_hgs_tri<T, 16><<<grid, 64, lds, s>>>(n, chunk, w, nchp, lc, lv, dT, r, x, bw, fz);
+    else
+        k_hgs_tri<T, 0><<<grid, 64, lds, s>>>(n, chunk, w, nchp, lc, lv, dT, r, x, bw, fz);
     MGR_LAUNCH_CHECK();
 }
-template void hgs_chunk<double>(const SpOp<double>&, const int*, const double*, const double*, double*, int, bool,
-                                bool, hipStream_t);
-template void hgs_chunk<float>(const SpOp<float>&, const int*, const float*, const float*, float*, int, bool, bool,
-                               hipStream_t);
+template void hgs_tri<double>(int, int, int, int, const unsigned char*, const double*, const double*,
+                              const double*, double*, bool, bool, hipStream_t);
+template void hgs_tri<float>(int, int, int, int, const unsigned char*, const float*, const float*, const float*,
+                             float*, bool, bool, hipStream_t);
 
 template <typename T>
 void trsv_level(int cnt, const int* rows, const SpOp<T>& A, const T* b, T* x, bool unit, hipStream_t s) {

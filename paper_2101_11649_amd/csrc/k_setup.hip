@@ -2305,6 +2305,76 @@ __global__ __launch_bounds__(TPB) void k_hgs_diag_g(int n, const int* __restrict
     }
 }
 
+// In-chunk entries of row i of the hybrid Gauss-Seidel sweep (columns sorted,
+// diagonal at dpos[i]): below the diagonal down to the chunk start (forward
+// sweeps) and above it up to the chunk end (backward sweeps).
+__device__ inline void hgs_tri_span(int i, int chunk, int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                    int pd, int& lo0, int& nlo, int& nup) {
+    const int c0 = i - i % chunk, c1 = min(n, c0 + chunk);
+    int p = pd;
+    while (p > rp[i] && ci[p - 1] >= c0) --p;
+    lo0 = p;
+    nlo = pd - p;
+    int q = pd + 1;
+    const int pe = rp[i + 1];
+    while (q < pe && ci[q] < c1) ++q;
+    nup = q - pd - 1;
+}
+
+// Widest row of each in-chunk triangle: w[0] = lower, w[1] = upper (two ints
+// of one zeroed slot; integer maxima, so the result is deterministic).
+__global__ void k_hgs_tri_count(int n, int chunk, const int* __restrict__ rp, const int* __restrict__ ci,
+                                const int* __restrict__ dpos, int* __restrict__ w) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int nlo = 0, nup = 0;
+    if (i < n && dpos[i] >= 0) {
+        int lo0;
+        hgs_tri_span(i, chunk, n, rp, ci, dpos[i], lo0, nlo, nup);
+    }
+    nlo = wave_max_int(nlo);
+    nup = wave_max_int(nup);
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        if (nlo > 0) atomicMax(w, nlo);
+        if (nup > 0) atomicMax(w + 1, nup);
+    }
+}
+
+// Slot tables of the in-chunk triangles, slot k of chunk position t of chunk c
+// at (t * W + k) * nchp + c (consecutive chunks adjacent, so the sweep's loads
+// coalesce): the local column (0..chunk-1) and the value, lower entries in
+// column order, then padding (value 0, column t).  dT[t * nchp + c] = 1 / d of
+// that row (1 for rows past n).  One thread per (t, c), c fastest.
+__global__ void k_hgs_tri_fill(int n, int chunk, int nchp, const int* __restrict__ rp, const int* __restrict__ ci,
+                               const double* __restrict__ v, const int* __restrict__ dpos,
+                               const double* __restrict__ d, int wl, unsigned char* __restrict__ lc,
+                               double* __restrict__ lv, int wu, unsigned char* __restrict__ uc,
+                               double* __restrict__ uv, double* __restrict__ dT) {
+    const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (long)nchp * chunk) return;
+    const int t = (int)(q / nchp), c = (int)(q % nchp);
+    const long il = (long)c * chunk + t;
+    int lo0 = 0, nlo = 0, nup = 0, pd = -1;
+    const bool row = il < n;
+    if (row) {
+        pd = dpos[il];
+        if (pd >= 0) hgs_tri_span((int)il, chunk, n, rp, ci, pd, lo0, nlo, nup);
+    }
+    const int c0 = c * chunk;
+    for (int k = 0; k < wl; ++k) {
+        const size_t o = ((size_t)t * wl + k) * nchp + c;
+        const bool e = k < nlo;
+        lc[o] = (unsigned char)(e ? ci[lo0 + k] - c0 : t);
+        lv[o] = e ? v[lo0 + k] : 0.0;
+    }
+    for (int k = 0; k < wu; ++k) {
+        const size_t o = ((size_t)t * wu + k) * nchp + c;
+        const bool e = k < nup;
+        uc[o] = (unsigned char)(e ? ci[pd + 1 + k] - c0 : t);
+        uv[o] = e ? v[pd + 1 + k] : 0.0;
+    }
+    if (dT) dT[(size_t)t * nchp + c] = row ? 1.0 / d[il] : 1.0;
+}
+
 // Scatter of A's entries into the rows of its transpose: row j of the
 // transpose has cnt[j] slots from trp[j]; each entry takes one by decrementing
 // cnt[j] (which ends at zero), so the order inside a row is arbitrary.
@@ -3207,6 +3277,20 @@ void hgs_diag(const DCsr& A, int chunk, double* d, int* flag, hipStream_t s) {
     int G = group_rows(A.max_row);
     MGR_DISPATCH_G4(G, (k_hgs_diag_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, chunk, d,
                                                                               flag)));
+    MGR_LAUNCH_CHECK();
+}
+
+void hgs_tri_count(const DCsr& A, const int* dpos, int chunk, int* w, hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_hgs_tri_count<<<nblk(A.nr), TPB, 0, s>>>(A.nr, chunk, A.rp.p, A.ci.p, dpos, w);
+    MGR_LAUNCH_CHECK();
+}
+
+void hgs_tri_fill(const DCsr& A, const int* dpos, const double* d, int chunk, int nchp, int wl, unsigned char* lc,
+                  double* lv, int wu, unsigned char* uc, double* uv, double* dT, hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_hgs_tri_fill<<<nblk((long)nchp * chunk), TPB, 0, s>>>(A.nr, chunk, nchp, A.rp.p, A.ci.p, A.v.p, dpos, d, wl,
+                                                            lc, lv, wu, uc, uv, dT);
     MGR_LAUNCH_CHECK();
 }
 

@@ -129,6 +129,15 @@ void mp_reach(int n, const int* cfm, const int* wcnt, long long* reach, hipStrea
 // diagonal of the hybrid L1 Gauss-Seidel smoother: a_ii + sum of |a_ij| over the
 // entries of row i outside its chunk of `chunk` consecutive rows
 void hgs_diag(const DCsr& A, int chunk, double* d, int* flag, hipStream_t s);
+// In-chunk triangles of the hybrid Gauss-Seidel sweep (columns sorted, dpos =
+// each row's diagonal position): w[0], w[1] = the most entries of a row below
+// and above its diagonal inside its chunk (w zeroed beforehand); the fill
+// writes slot tables of widths wl and wu for nchp >= ceil(n / chunk) chunks
+// (slot k of position t of chunk c at (t W + k) nchp + c: local column, value;
+// padding has value 0) and dT[t nchp + c] = 1 / d of row c chunk + t (1 past n).
+void hgs_tri_count(const DCsr& A, const int* dpos, int chunk, int* w, hipStream_t s);
+void hgs_tri_fill(const DCsr& A, const int* dpos, const double* d, int chunk, int nchp, int wl, unsigned char* lc,
+                  double* lv, int wu, unsigned char* uc, double* uv, double* dT, hipStream_t s);
 // Composed operators of one L1-Jacobi V(1,1) level (b_c = G b, x = W b + Q x_c):
 // w = 2 D^-1 - D^-1 A D^-1 on A's pattern; out = X - S Y on Y's pattern with
 // S = diag(rs) on the left or diag(cs) on the right; C = [A | B].  *bad is set

@@ -253,6 +253,21 @@ static void make_float(DCsr& A, hipStream_t s) {
 }
 
 // ====================================================================== AMG
+// Slot tables of the in-chunk entries of a hybrid Gauss-Seidel operator on one
+// side of the diagonal (see hgs_tri_fill): w slots per row.
+struct HgsTri {
+    int w = 0;
+    DArr<unsigned char> c;
+    DArr<double> v;
+    DArr<float> vf;
+    void reset() {
+        w = 0;
+        c.reset();
+        v.reset();
+        vf.reset();
+    }
+};
+
 struct AmgLevel {
     int n = 0;
     DCsr A, P, R, AT;        // R = P^T; AT = A^T for the transposed cycle
@@ -267,11 +282,17 @@ struct AmgLevel {
     DArr<float> dinvf;
     DArr<double> rd, td, bd, xd, sd;   // sd = D^-1 b, formed by the restriction from the level above
     DArr<float> rf, tf, bf, xf, sf;
-    // hybrid L1 Gauss-Seidel: chunked L1 diagonal, and the diagonal's position
-    // in each row of A and of A^T
-    DArr<double> dgs;
-    DArr<float> dgsf;
+    // hybrid L1 Gauss-Seidel: chunked L1 diagonal (row order, and in the
+    // chunk-position layout of the slot tables, nchp chunks), the diagonal's
+    // position in each row of A and of A^T, and the in-chunk triangles of A
+    // (lo: forward sweeps, up: backward sweeps) and of A^T; wslot, wslotT:
+    // the pending table widths
+    DArr<double> dgs, dT;
+    DArr<float> dTf;
     DArr<int> dpos, dposT;
+    HgsTri lo, up, loT, upT;
+    int nchp = 0;
+    long long* wslot = nullptr;
 };
 
 struct Amg {
@@ -343,8 +364,9 @@ static void amg_make_tail(Amg& H, hipStream_t s) {
 }
 
 // Hybrid L1 Gauss-Seidel data of every level but the coarsest: the chunked L1
-// diagonal (from the current values) and the diagonal positions (validity read
-// back at the next sync).
+// diagonal (from the current values), the diagonal positions (validity read
+// back at the next sync) and the widths of the in-chunk triangles (read at the
+// next sync by amg_hgs_finish, which makes the slot tables).
 static void amg_hgs_setup(Amg& H, Slots& S) {
     hipStream_t s = S.s;
     for (size_t l = 0; l + 1 < H.lv.size(); ++l) {
@@ -355,7 +377,39 @@ static void amg_hgs_setup(Amg& H, Slots& S) {
             L.dpos.alloc((size_t)L.n + 1, s);
             diag_pos(L.A, L.dpos.p, S.flag(), s);
         }
-        L.dgsf.reset();
+        L.lo.reset();
+        L.up.reset();
+        L.dT.reset();
+        L.dTf.reset();
+        L.wslot = S.take(1);
+        hgs_tri_count(L.A, L.dpos.p, H.chunk, reinterpret_cast<int*>(L.wslot), s);
+    }
+}
+
+static int hgs_nchp(int n, int chunk) { return (int)((((long)n + chunk - 1) / chunk + 63) / 64 * 64); }
+
+// The slot tables of one operator (A, or A^T with its own diagonal positions)
+// from the widths read back in the slot; dT is written when given.
+static void hgs_make_tables(const DCsr& A, const int* dpos, const double* d, int chunk, int nchp, long long wv,
+                            HgsTri& lo, HgsTri& up, double* dT, hipStream_t s) {
+    lo.w = (int)(wv & 0xffffffffLL);
+    up.w = (int)(wv >> 32);
+    const size_t per = (size_t)chunk * nchp;
+    lo.c.alloc(per * lo.w + 1, s);
+    lo.v.alloc(per * lo.w + 1, s);
+    up.c.alloc(per * up.w + 1, s);
+    up.v.alloc(per * up.w + 1, s);
+    hgs_tri_fill(A, dpos, d, chunk, nchp, lo.w, lo.c.p, lo.v.p, up.w, up.c.p, up.v.p, dT, s);
+}
+
+static void amg_hgs_finish(Amg& H, Slots& S) {
+    hipStream_t s = S.s;
+    for (size_t l = 0; l + 1 < H.lv.size(); ++l) {
+        AmgLevel& L = H.lv[l];
+        L.nchp = hgs_nchp(L.n, H.chunk);
+        L.dT.alloc((size_t)H.chunk * L.nchp, s);
+        hgs_make_tables(L.A, L.dpos.p, L.dgs.p, H.chunk, L.nchp, S.val(L.wslot), L.lo, L.up, L.dT.p, s);
+        L.wslot = nullptr;
     }
 }
 
@@ -627,6 +681,7 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
     S.sync("AMG coarsest inverse");
     for (size_t l = 0; l + 1 < H.lv.size(); ++l)
         if (H.lv[l].composed) amg_compose_finish(H.lv[l], S);
+    if (H.smoother == MGR_SMOOTH_HYBRID_GS) amg_hgs_finish(H, S);
     amg_make_tail(H, s);
     H.have_float = false;
     H.have_trans = false;
@@ -645,6 +700,8 @@ static void amg_refresh(Amg& H, DCsr A0, Slots& S) {
         AmgLevel& L = H.lv[k];
         L.AT = DCsr();
         L.dposT.reset();
+        L.loT.reset();
+        L.upT.reset();
         L.G = DCsr(); L.W = DCsr(); L.Q = DCsr(); L.WQ = DCsr(); L.Qt = DCsr(); L.WGt = DCsr();
         L.dinvf.reset();
         DCsr AP, Ac;
@@ -677,6 +734,7 @@ static void amg_refresh(Amg& H, DCsr A0, Slots& S) {
     S.sync("AMG coarsest inverse");
     for (int k = 0; k + 1 < nl; ++k)
         if (H.lv[k].composed) amg_compose_finish(H.lv[k], S);
+    if (H.smoother == MGR_SMOOTH_HYBRID_GS) amg_hgs_finish(H, S);
     amg_make_tail(H, s);
     H.cinvT.reset();
     H.cinvf.reset();
@@ -704,9 +762,15 @@ static void amg_make_float(Amg& H, hipStream_t s) {
             make_float(L.R, s);
             L.dinvf.alloc((size_t)L.n, s);
             to_float(L.dinv.p, L.dinvf.p, L.n, s);
-            if (L.dgs.p) {
-                L.dgsf.alloc((size_t)L.n + 1, s);
-                to_float(L.dgs.p, L.dgsf.p, L.n, s);
+            if (L.dT.p) {
+                const long per = (long)H.chunk * L.nchp;
+                L.dTf.alloc((size_t)per, s);
+                to_float(L.dT.p, L.dTf.p, per, s);
+                for (HgsTri* t : {&L.lo, &L.up, &L.loT, &L.upT}) {
+                    if (!t->v.p) continue;
+                    t->vf.alloc(t->v.n, s);
+                    to_float(t->v.p, t->vf.p, per * t->w, s);
+                }
             }
         }
         if (H.have_trans && L.AT.nr && !L.composed) make_float(L.AT, s);
@@ -764,6 +828,25 @@ static void amg_make_trans(Amg& H, Slots& S) {
             // A^T keeps every diagonal entry of A
             L.dposT.alloc((size_t)L.n + 1, s);
             diag_pos(L.AT, L.dposT.p, S.flag(), s);
+            L.wslot = S.take(1);
+            hgs_tri_count(L.AT, L.dposT.p, H.chunk, reinterpret_cast<int*>(L.wslot), s);
+        }
+    }
+    if (H.smoother == MGR_SMOOTH_HYBRID_GS) {
+        // the transposed sweeps use A's diagonal d, so dT is shared
+        S.sync("hybrid Gauss-Seidel tables of A^T");
+        for (size_t l = 0; l + 1 < H.lv.size(); ++l) {
+            AmgLevel& L = H.lv[l];
+            if (!L.wslot) continue;
+            hgs_make_tables(L.AT, L.dposT.p, L.dgs.p, H.chunk, L.nchp, S.val(L.wslot), L.loT, L.upT, nullptr, s);
+            L.wslot = nullptr;
+            if (H.have_float) {
+                const long per = (long)H.chunk * L.nchp;
+                for (HgsTri* t : {&L.loT, &L.upT}) {
+                    t->vf.alloc(t->v.n, s);
+                    to_float(t->v.p, t->vf.p, per * t->w, s);
+                }
+            }
         }
     }
     int nc = H.nc;
@@ -799,7 +882,8 @@ template <> struct Prec<double> {
     static double* x(AmgLevel& L) { return L.xd.p; }
     static double* sb(AmgLevel& L) { return L.sd.p; }
     static const double* dinv(AmgLevel& L) { return L.dinv.p; }
-    static const double* dgs(AmgLevel& L) { return L.dgs.p; }
+    static const double* dT(AmgLevel& L) { return L.dT.p; }
+    static const double* tv(const HgsTri& t) { return t.v.p; }
     static const double* cinv(Amg& H, bool tr) { return tr ? H.cinvT.p : H.cinv.p; }
     static const double* tail(Amg& H, bool tr) { return tr ? H.tdT.p : H.td.p; }
 };
@@ -810,7 +894,8 @@ template <> struct Prec<float> {
     static float* x(AmgLevel& L) { return L.xf.p; }
     static float* sb(AmgLevel& L) { return L.sf.p; }
     static const float* dinv(AmgLevel& L) { return L.dinvf.p; }
-    static const float* dgs(AmgLevel& L) { return L.dgsf.p; }
+    static const float* dT(AmgLevel& L) { return L.dTf.p; }
+    static const float* tv(const HgsTri& t) { return t.vf.p; }
     static const float* cinv(Amg& H, bool tr) { return tr ? H.cinvTf.p : H.cinvf.p; }
     static const float* tail(Amg& H, bool tr) { return tr ? H.tdTf.p : H.tdf.p; }
 };
@@ -850,13 +935,14 @@ static void amg_vcycle(Amg& H, int k, const T* b, T* x, bool tr, hipStream_t s, 
         // forward sweeps down, backward sweeps up; the transposed cycle runs the
         // same directions on A^T (the transpose of a backward sweep on A is a
         // forward sweep on A^T) with A's row-based diagonal
-        const T* d = Prec<T>::dgs(L);
-        const int* dp = tr ? L.dposT.p : L.dpos.p;
+        const T* dT = Prec<T>::dT(L);
+        const HgsTri& fw = tr ? L.loT : L.lo;
+        const HgsTri& bw = tr ? L.upT : L.up;
         if (npre >= 1) {
-            hgs_chunk<T>(A, dp, d, b, x, H.chunk, false, true, s);
+            hgs_tri<T>(n, H.chunk, fw.w, L.nchp, fw.c.p, Prec<T>::tv(fw), dT, b, x, false, true, s);
             for (int q = 1; q < npre; ++q) {
                 spmv<T, T, T, T, T>(A, x, (const T*)nullptr, INT_MAX, b, t, T(-1), T(1), s);
-                hgs_chunk<T>(A, dp, d, t, x, H.chunk, false, false, s);
+                hgs_tri<T>(n, H.chunk, fw.w, L.nchp, fw.c.p, Prec<T>::tv(fw), dT, t, x, false, false, s);
             }
             spmv<T, T, T, T, T>(A, x, (const T*)nullptr, INT_MAX, b, r, T(-1), T(1), s);
         } else {
@@ -871,7 +957,7 @@ static void amg_vcycle(Amg& H, int k, const T* b, T* x, bool tr, hipStream_t s, 
         spmv<T, T, T, T, T>(view<T>(L.P), xc, (const T*)nullptr, INT_MAX, x, x, T(1), T(1), s);
         for (int q = 0; q < npost; ++q) {
             spmv<T, T, T, T, T>(A, x, (const T*)nullptr, INT_MAX, b, t, T(-1), T(1), s);
-            hgs_chunk<T>(A, dp, d, t, x, H.chunk, true, false, s);
+            hgs_tri<T>(n, H.chunk, bw.w, L.nchp, bw.c.p, Prec<T>::tv(bw), dT, t, x, true, false, s);
         }
         return;
     }
@@ -2114,6 +2200,26 @@ static int do_export(Ctx& c, int kind, int level, int what, int sub, int64_t* si
         if (level != H->tail) throw Error(MGR_ERR_ARG, "level has no dense cycle operator");
         sizes[0] = L.n; sizes[1] = L.n; sizes[2] = (int64_t)L.n * L.n;
         if (b2) MGR_HIP(hipMemcpyAsync(b2, H->td.p, sizeof(double) * L.n * L.n, hipMemcpyDeviceToHost, s));
+        MGR_HIP(hipStreamSynchronize(s));
+        return MGR_OK;
+    }
+    if ((what == 7 || what == 8) && level + 1 < (int)H->lv.size()) {
+        // slot tables of the hybrid Gauss-Seidel sweeps on A (7: forward, the
+        // in-chunk entries left of the diagonal; 8: backward, right of it):
+        // rows = chunk positions x table chunks, cols = slots per row
+        if (H->smoother != MGR_SMOOTH_HYBRID_GS || !L.dT.p) throw Error(MGR_ERR_ARG, "level has no Gauss-Seidel tables");
+        const HgsTri& t = what == 7 ? L.lo : L.up;
+        const long per = (long)H->chunk * L.nchp;
+        sizes[0] = per; sizes[1] = t.w; sizes[2] = per * t.w;
+        const size_t m = (size_t)per * t.w;
+        if (b1 && m) {
+            std::vector<unsigned char> cc(m);
+            MGR_HIP(hipMemcpyAsync(cc.data(), t.c.p, m, hipMemcpyDeviceToHost, s));
+            MGR_HIP(hipStreamSynchronize(s));
+            int* o = (int*)b1;
+            for (size_t q = 0; q < m; ++q) o[q] = cc[q];
+        }
+        if (b2 && m) MGR_HIP(hipMemcpyAsync(b2, t.v.p, sizeof(double) * m, hipMemcpyDeviceToHost, s));
         MGR_HIP(hipStreamSynchronize(s));
         return MGR_OK;
     }

@@ -73,3 +73,57 @@ def test_hybrid_gs_option_errors():
         with pytest.raises(P.MgrError) as e:
             gpu_solver(s, smoother="hybrid-gs", chunk=chunk)
         assert e.value.code == -1
+
+
+def _expected_tables(nr, rp, ci, v, chunk, backward):
+    """Slot tables of the in-chunk entries of a CSR operator, written out row by
+    row on the host: slot k of position t of chunk c at (t W + k) nchp + c."""
+    nch = -(-nr // chunk)
+    nchp = -(-nch // 64) * 64
+    rows = []
+    for i in range(nr):
+        c0 = i - i % chunk
+        c1 = min(nr, c0 + chunk)
+        e = [(j - c0, x) for j, x in zip(ci[rp[i]:rp[i + 1]], v[rp[i]:rp[i + 1]])
+             if (i < j < c1 if backward else c0 <= j < i)]
+        rows.append(e)
+    w = max((len(e) for e in rows), default=0)
+    col = np.zeros(chunk * w * nchp, np.int64)
+    val = np.zeros(chunk * w * nchp)
+    for t in range(chunk):
+        for c in range(nchp):
+            i = c * chunk + t
+            e = rows[i] if i < nr else []
+            for k in range(w):
+                o = (t * w + k) * nchp + c
+                col[o], val[o] = e[k] if k < len(e) else (t, 0.0)
+    return chunk * nchp, w, col, val
+
+
+@pytest.mark.parametrize("name,chunk", [("comp_20x18x10", 7), ("frac_12^3", 32), ("mimetic_9x7x6", 128)])
+def test_hybrid_gs_slot_tables(name, chunk):
+    """The sweep's slot tables hold exactly each row's in-chunk entries (bit-equal
+    values, columns relative to the chunk), then zero padding, for every level of
+    every AMG hierarchy, with ragged last chunks."""
+    s = SMALL[name]()
+    gs = gpu_solver(s, smoother="hybrid-gs", chunk=chunk)
+    hier = [(1, -1, len(gs.info()["amg_levels"]))]
+    for sub in range(len(gs.info()["mgr_levels"])):
+        k = 0
+        while gs.export_sizes(2, k, 1, sub) is not None:
+            k += 1
+        if k:
+            hier.append((2, sub, k))
+    checked = 0
+    for kind, sub, nl in hier:
+        for k in range(nl - 1):
+            nr, _, rp, ci, v = gs.export(kind, k, 1, sub)
+            for what, bw in ((7, False), (8, True)):
+                per, w, col, val = _expected_tables(nr, rp, ci, v, chunk, bw)
+                got = gs.export(kind, k, what, sub)
+                assert (got[0], got[1]) == (per, w), (kind, sub, k, what)
+                assert np.array_equal(got[3], col) and np.array_equal(got[4], val), (kind, sub, k, what)
+                checked += 1
+    say(f"[hgs] {name} chunk {chunk}: {checked} slot tables equal to the host's")
+    assert checked >= 4
+    gs.close()
