@@ -320,7 +320,7 @@ def main():
                     help="timed steps of the fracturing workload, MGR_U and MGR_P (0 = skip)")
     ap.add_argument("--ilu-steps", type=int, default=1,
                     help="timed steps of the headline system with ILU(0) F-relaxation of the components (0 = skip)")
-    ap.add_argument("--frac-variant", default="all", choices=["all", "u", "u_paper_v11", "u_paper_v22", "p"],
+    ap.add_argument("--frac-variant", default="all", choices=["all", "u", "u_paper_v11", "u_paper_v22", "u_paper_sdc_v11", "u_paper_sdc_v22", "p"],
                     help="run one fracturing variant only (profiling runs); 'all' adds the grid sweep")
     ap.add_argument("--no-headline", action="store_true",
                     help="skip the headline workload (profiling runs of the secondaries alone)")
@@ -508,17 +508,20 @@ def main():
                              "pressures -> AMG", 5, reuse=(3, True))
         # the AMG settings of Sec. 4.1 for the mechanics block: one level of aggressive
         # coarsening (multi-pass interpolation) and hybrid L1 Gauss-Seidel, V(1,1)
-        # and V(2,2) (chunks of 32 rows)
-        sfa = dict(sf, levels=[W.level(7, "amg", amg_unknown_based=True, amg_agg_levels=1)])
+        # and V(2,2) (chunks of 32 rows); sdc: built on the separate displacement
+        # component approximation of A_uu (Sec. 4.4)
         frac_paper = {}
-        for nu in (1, 2):
-            if fv not in ("all", f"u_paper_v{nu}{nu}"):
-                continue
-            sfa["solver_opts"] = dict(nu_pre=nu, nu_post=nu, smoother="hybrid-gs", chunk=32)
-            frac_paper[f"v{nu}{nu}"] = secondary(
-                dict(sfa, name=sf["name"] + f"_agg1_hgs_v{nu}{nu}"), args.frac_steps,
-                f"MGR_U, F-relaxation AMG with one aggressive level and hybrid L1 Gauss-Seidel V({nu},{nu})", 5,
-                reuse=(3, True))
+        for sdc in (False, True):
+            for nu in (1, 2):
+                key = ("sdc_" if sdc else "") + f"v{nu}{nu}"
+                if fv not in ("all", "u_paper_" + key):
+                    continue
+                sfa = dict(sf, levels=[W.level(7, "amg", amg_unknown_based=2 if sdc else 1, amg_agg_levels=1)],
+                           solver_opts=dict(nu_pre=nu, nu_post=nu, smoother="hybrid-gs", chunk=32))
+                frac_paper[key] = secondary(
+                    dict(sfa, name=sf["name"] + ("_sdc" if sdc else "") + f"_agg1_hgs_v{nu}{nu}"), args.frac_steps,
+                    "MGR_U, F-relaxation AMG" + (" on the separate-component approximation of A_uu" if sdc else "")
+                    + f" with one aggressive level and hybrid L1 Gauss-Seidel V({nu},{nu})", 5, reuse=(3, True))
         if fv in ("all", "p"):
             sp_ = dict(sf, name=sf["name"] + "_mgr_p", levels=[W.level(1 << 3, "amg")],
                        solver_opts=dict(nu_pre=2, nu_post=2, unknown_based=True))
@@ -526,7 +529,7 @@ def main():
                               "MGR_P: F = fracture pressures (AMG V(2,2) F-relaxation), C = displacements -> "
                               "unknown-based AMG", 5)
             del sp_
-        del sf, sfa
+        del sf
         # iteration counts to 1e-8 against the grid, for each setting
         frac_grid = {} if fv == "all" else None
         for nn, sd in ((12, 5), (18, 6), (30, 7), (48, 8)) if fv == "all" else ():
@@ -537,7 +540,9 @@ def main():
                     ("mgr_u_agg1_hgs_v11", [W.level(7, "amg", amg_unknown_based=True, amg_agg_levels=1)],
                      dict(nu_pre=1, nu_post=1, smoother="hybrid-gs", chunk=32)),
                     ("mgr_u_agg1_hgs_v22", [W.level(7, "amg", amg_unknown_based=True, amg_agg_levels=1)],
-                     dict(nu_pre=2, nu_post=2, smoother="hybrid-gs", chunk=32))):
+                     dict(nu_pre=2, nu_post=2, smoother="hybrid-gs", chunk=32)),
+                    ("mgr_u_sdc_agg1_hgs_v11", [W.level(7, "amg", amg_unknown_based=2, amg_agg_levels=1)],
+                     dict(nu_pre=1, nu_post=1, smoother="hybrid-gs", chunk=32))):
                 g_ = P.Solver(sg["b"], sg["rp"], sg["ci"], sg["vals"], sg["field"], lv, **o)
                 _, [ig] = g_.solve(torch.tensor(sg["rhs"], device="cuda"))
                 row[key] = ig.iterations
@@ -547,7 +552,8 @@ def main():
         if frac_grid is not None:
             frac_grid["96^3"] = {"mgr_u_l1jacobi_v22": frac["fp64"]["iterations"],
                                  "mgr_u_agg1_hgs_v11": frac_paper["v11"]["fp64"]["iterations"],
-                                 "mgr_u_agg1_hgs_v22": frac_paper["v22"]["fp64"]["iterations"]}
+                                 "mgr_u_agg1_hgs_v22": frac_paper["v22"]["fp64"]["iterations"],
+                                 "mgr_u_sdc_agg1_hgs_v11": frac_paper["sdc_v11"]["fp64"]["iterations"]}
 
     # ---- FP64 oracle on the machine's host cores, on the headline workload
     cpu = None

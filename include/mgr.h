@@ -75,6 +75,16 @@ extern "C" {
 #define MGR_SMOOTH_L1_JACOBI 0
 #define MGR_SMOOTH_HYBRID_GS 1
 
+/* The AMG of an MGR_FRELAX_AMG level (mgr_level_opts.amg_unknown_based):
+ * scalar; the unknown approach (strength and interpolation only between
+ * unknowns of one field label); or the unknown approach built on the
+ * separate-component approximation of A_FF, its couplings between unknowns of
+ * different labels dropped (Sec. 4.4: the displacement block's AMG is built
+ * on it, which sparsifies the block), the V-cycle then using that operator. */
+#define MGR_AMG_SCALAR 0
+#define MGR_AMG_UNKNOWN 1
+#define MGR_AMG_SEPARATE 2
+
 typedef struct mgr_ctx *mgr_handle;
 
 /* Block-CSR matrix with b x b row-major dense blocks.  b = 1 is plain CSR.
@@ -95,7 +105,7 @@ typedef struct {
     int32_t sweeps;          /* F-relaxation sweeps (>= 1)                     */
     double omega;            /* F-relaxation weight                            */
     int32_t restrict_type;   /* MGR_RESTRICT_*                                 */
-    int32_t amg_unknown_based; /* MGR_FRELAX_AMG: AMG restricted per field label */
+    int32_t amg_unknown_based; /* MGR_FRELAX_AMG: MGR_AMG_SCALAR, _UNKNOWN or _SEPARATE */
     int32_t amg_agg_levels;  /* MGR_FRELAX_AMG: levels with aggressive coarsening (see mgr_amg_opts) */
 } mgr_level_opts;
 

@@ -296,7 +296,7 @@ class LevelOpts:
     sweeps: int = 1
     omega: float = 1.0
     restrict: str = "injection"
-    amg_unknown_based: bool = False
+    amg_unknown_based: int = 0      # 0 scalar, 1 unknown approach, 2 on the separate-component approximation
     amg_agg_levels: int = 0
 
 

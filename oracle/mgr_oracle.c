@@ -110,6 +110,26 @@ static Csr csr_copy(const Csr *a) {
     return b;
 }
 
+/* The entries a_ij of A with label[i] == label[j] (the separate-component
+ * approximation of a block whose unknowns carry field labels). */
+static Csr csr_same_label(const Csr *a, const int *label) {
+    Csr c;
+    c.nr = a->nr; c.nc = a->nc;
+    c.rp = (int *)xcalloc((size_t)a->nr + 1, sizeof(int));
+    for (int i = 0; i < a->nr; ++i) {
+        int cnt = 0;
+        for (int p = a->rp[i]; p < a->rp[i + 1]; ++p) cnt += label[a->ci[p]] == label[i];
+        c.rp[i + 1] = c.rp[i] + cnt;
+    }
+    int nnz = c.rp[a->nr];
+    c.ci = (int *)xmalloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int));
+    c.v = (double *)xmalloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(double));
+    for (int i = 0, q = 0; i < a->nr; ++i)
+        for (int p = a->rp[i]; p < a->rp[i + 1]; ++p)
+            if (label[a->ci[p]] == label[i]) { c.ci[q] = a->ci[p]; c.v[q] = a->v[p]; ++q; }
+    return c;
+}
+
 /* y = A x, each row summed left to right. */
 static void csr_matvec(const Csr *a, const double *x, double *y) {
     #pragma omp parallel for schedule(static) if (PAR_OK(a->nr))
@@ -1303,21 +1323,26 @@ static int mgr_setup_level(MgrLevel *l, const Csr *a, const int *field, const Le
             status = ilu0_factor(&l->AFF, &l->ilu, &l->ilu_diag);
             if (status != ORC_OK) return status;
         } else if (l->frelax == FRELAX_AMG) {
+            int *flab = (int *)xmalloc((size_t)nF * sizeof(int));
+            for (int k = 0; k < nF; ++k) flab[k] = field[l->fmap[k]];
+            /* the AMG operator: A_FF, or its separate-component approximation
+             * (amg_unknown_based == 2: the couplings between unknowns of
+             * different fields dropped, Sec. 4.4) */
+            Csr aop = lo->amg_unknown_based == 2 ? csr_same_label(&l->AFF, flab) : csr_copy(&l->AFF);
             if (famg_old && keep_famg) {
                 /* A_FF unchanged (the mechanics block between Newton solves, Sec. 3.3) */
                 l->famg = amg_clone(famg_old);
             } else if (famg_old) {
-                status = amg_reuse(&l->AFF, famg_old, &l->famg);
+                status = amg_reuse(&aop, famg_old, &l->famg);
             } else {
                 AmgOpts fo = *ao;
-                fo.unknown_based = lo->amg_unknown_based;
+                fo.unknown_based = lo->amg_unknown_based != 0;
                 fo.agg_levels = lo->amg_agg_levels;
                 fo.seed = amg_seed;
-                int *flab = (int *)xmalloc((size_t)nF * sizeof(int));
-                for (int k = 0; k < nF; ++k) flab[k] = field[l->fmap[k]];
-                status = amg_setup(&l->AFF, flab, &fo, &l->famg);
-                free(flab);
+                status = amg_setup(&aop, flab, &fo, &l->famg);
             }
+            csr_free(&aop);
+            free(flab);
             if (status != ORC_OK) return status;
         } else {
             return ORC_ERR_ARG;

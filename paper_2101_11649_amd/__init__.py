@@ -156,7 +156,7 @@ class SolveInfo:
 def level_opts(fmask, frelax="jacobi", sweeps=1, omega=1.0, restrict="injection", amg_unknown_based=False,
                amg_agg_levels=0):
     return dict(fmask=int(fmask), frelax=frelax, sweeps=int(sweeps), omega=float(omega), restrict=restrict,
-                amg_unknown_based=bool(amg_unknown_based), amg_agg_levels=int(amg_agg_levels))
+                amg_unknown_based=int(amg_unknown_based), amg_agg_levels=int(amg_agg_levels))
 
 
 class Solver:
@@ -165,7 +165,9 @@ class Solver:
     ``b``: block size (1 = CSR); ``rp``, ``ci``, ``vals``: block-CSR arrays (any
     array-like or device tensor; copied by the library); ``field``: field label
     of every scalar unknown; ``levels``: list of dicts (fmask, frelax, sweeps,
-    omega, restrict, amg_unknown_based) -- one per MGR level; ``interp``: AMG
+    omega, restrict, amg_unknown_based: 0 scalar AMG, 1 the unknown approach,
+    2 the unknown approach on the separate-component approximation) -- one per
+    MGR level; ``interp``: AMG
     interpolation, "direct" or "ext+i" (extended+i, distance two);
     ``smoother``: "l1-jacobi" or "hybrid-gs" (hybrid L1 Gauss-Seidel over chunks
     of ``chunk`` rows); ``block``: block-Jacobi group of every unknown;
@@ -242,7 +244,7 @@ class Solver:
         for i, lv in enumerate(self.levels):
             arr[i] = mgr_level_opts(int(lv["fmask"]), FRELAX[lv.get("frelax", "jacobi")], int(lv.get("sweeps", 1)),
                                     float(lv.get("omega", 1.0)), RESTRICT[lv.get("restrict", "injection")],
-                                    int(bool(lv.get("amg_unknown_based", False))),
+                                    int(lv.get("amg_unknown_based", 0)),
                                     int(lv.get("amg_agg_levels", 0)))
         self._check(lib().mgr_setup(self._h, ctypes.byref(A), ctypes.c_void_p(self.field.data_ptr()),
                                     len(self.levels), arr,

@@ -1206,6 +1206,22 @@ __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restri
         a1 = arp[row + 1];
     }
     const int wl = wave_max_int(a1 - a0);
+    if (ADD && valid && a1 == a0) {
+        // no products (e.g. a C row away from every well): the row of C is the
+        // row of D, already in column order; the group leaves together (only
+        // group-local shuffles follow)
+        const int d0 = drp[row], d1 = drp[row + 1];
+        if (!FILL) {
+            if (g.gl == 0) cnt[row] = d1 - d0;
+        } else {
+            const int o = crp[row] - d0;
+            for (int q = d0 + g.gl; q < d1; q += G) {
+                cci[o + q] = dci[q];
+                cv[o + q] = dv[q];
+            }
+        }
+        return;
+    }
     for (int base = 0; base < wl; base += G) {
         // lane t holds entry base + t of the row of A
         int kb0 = 0, kb1 = 0;
@@ -2305,6 +2321,47 @@ __global__ __launch_bounds__(TPB) void k_hgs_diag_g(int n, const int* __restrict
     }
 }
 
+// The entries a_ij with label[i] == label[j] (the separate-component
+// approximation of a block whose unknowns carry field labels): G lanes per
+// row, counts, then the kept entries in their order (ballot compaction).
+template <int G, bool FILL>
+__global__ __launch_bounds__(TPB) void k_label_filter_g(int n, const int* __restrict__ rp,
+                                                        const int* __restrict__ ci, const double* __restrict__ v,
+                                                        const int* __restrict__ label, int* __restrict__ cnt,
+                                                        const int* __restrict__ orp, int* __restrict__ oci,
+                                                        double* __restrict__ ov) {
+    Grp<G> g;
+    const int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    const bool valid = i < n;
+    int p0 = 0, p1 = 0, li = 0, o = 0;
+    if (valid) {
+        p0 = rp[i];
+        p1 = rp[i + 1];
+        li = label[i];
+        if (FILL) o = orp[i];
+    }
+    const int wl = wave_max_int(p1 - p0);
+    int kept = 0;
+    for (int base = 0; base < wl; base += G) {
+        const int p = p0 + base + g.gl;
+        const bool act = p < p1;
+        int j = 0;
+        bool keep = false;
+        if (act) {
+            j = ci[p];
+            keep = label[j] == li;
+        }
+        const unsigned long long bits = g.bits(keep);
+        if (FILL && keep) {
+            const int q = o + kept + g.below(bits);
+            oci[q] = j;
+            ov[q] = v[p];
+        }
+        kept += __popcll(bits);
+    }
+    if (!FILL && valid && g.gl == 0) cnt[i] = kept;
+}
+
 // In-chunk entries of row i of the hybrid Gauss-Seidel sweep (columns sorted,
 // diagonal at dpos[i]): below the diagonal down to the chunk start (forward
 // sweeps) and above it up to the chunk end (backward sweeps).
@@ -3277,6 +3334,22 @@ void hgs_diag(const DCsr& A, int chunk, double* d, int* flag, hipStream_t s) {
     int G = group_rows(A.max_row);
     MGR_DISPATCH_G4(G, (k_hgs_diag_g<GG><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, chunk, d,
                                                                               flag)));
+    MGR_LAUNCH_CHECK();
+}
+
+void label_filter_count(const DCsr& A, const int* label, int* cnt, hipStream_t s) {
+    if (A.nr <= 0) return;
+    int G = group_rows(A.max_row);
+    MGR_DISPATCH_G4(G, (k_label_filter_g<GG, false><<<grid_for(A.nr, GG), TPB, 0, s>>>(
+                           A.nr, A.rp.p, A.ci.p, A.v.p, label, cnt, nullptr, nullptr, nullptr)));
+    MGR_LAUNCH_CHECK();
+}
+
+void label_filter_fill(const DCsr& A, const int* label, DCsr& B, hipStream_t s) {
+    if (A.nr <= 0) return;
+    int G = group_rows(A.max_row);
+    MGR_DISPATCH_G4(G, (k_label_filter_g<GG, true><<<grid_for(A.nr, GG), TPB, 0, s>>>(
+                           A.nr, A.rp.p, A.ci.p, A.v.p, label, nullptr, B.rp.p, B.ci.p, B.v.p)));
     MGR_LAUNCH_CHECK();
 }
 

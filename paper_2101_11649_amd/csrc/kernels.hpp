@@ -129,6 +129,10 @@ void mp_reach(int n, const int* cfm, const int* wcnt, long long* reach, hipStrea
 // diagonal of the hybrid L1 Gauss-Seidel smoother: a_ii + sum of |a_ij| over the
 // entries of row i outside its chunk of `chunk` consecutive rows
 void hgs_diag(const DCsr& A, int chunk, double* d, int* flag, hipStream_t s);
+// B = the entries a_ij of A with label[i] == label[j] (the separate-component
+// approximation), in A's order: row counts, then (B's rows allocated) the fill.
+void label_filter_count(const DCsr& A, const int* label, int* cnt, hipStream_t s);
+void label_filter_fill(const DCsr& A, const int* label, DCsr& B, hipStream_t s);
 // In-chunk triangles of the hybrid Gauss-Seidel sweep (columns sorted, dpos =
 // each row's diagonal position): w[0], w[1] = the most entries of a row below
 // and above its diagonal inside its chunk (w zeroed beforehand); the fill

@@ -1233,23 +1233,36 @@ static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr* A, const int* field
         split_fill(LU, l.iluL, l.iluU, s);
         l.schU = level_schedule(l.iluU, false, S);
     }
-    if (o.frelax == MGR_FRELAX_AMG && lev < (int)c.reuse_famg.size() && c.reuse_famg[lev]) {
-        // setup reuse: the previous hierarchy of this level, kept whole (A_FF
-        // unchanged) or with new Galerkin products
-        l.famg = std::move(c.reuse_famg[lev]);
-        if (!c.reuse_keep_famg) amg_refresh(*l.famg, csr_copy(l.AFF, s), S);
-    } else if (o.frelax == MGR_FRELAX_AMG) {
-        l.famg.reset(new Amg());
-        mgr_amg_opts fo = c.o.amg;
-        fo.unknown_based = o.amg_unknown_based;
-        fo.agg_levels = o.amg_agg_levels;
+    if (o.frelax == MGR_FRELAX_AMG) {
+        // the AMG operator: A_FF, or its separate-component approximation
+        // (MGR_AMG_SEPARATE: the couplings between unknowns of different
+        // fields dropped, Sec. 4.4)
         DArr<int> flab;
         if (o.amg_unknown_based) {
             flab.alloc((size_t)l.nF, s);
             gather_int(l.nF, l.fmap.p, field, flab.p, s);
         }
-        amg_setup(*l.famg, csr_copy(l.AFF, s), o.amg_unknown_based ? flab.p : nullptr, fo,
-                  c.o.amg.seed + 0x1000193ULL * (uint64_t)(lev + 1), S);
+        auto amg_operator = [&]() {
+            if (o.amg_unknown_based != MGR_AMG_SEPARATE) return csr_copy(l.AFF, s);
+            DArr<int> cnt((size_t)l.nF + 1, s);
+            label_filter_count(l.AFF, flab.p, cnt.p, s);
+            DCsr B = csr_from_counts(l.nF, l.nF, cnt.p, S, "separate-component approximation");
+            label_filter_fill(l.AFF, flab.p, B, s);
+            return B;
+        };
+        if (lev < (int)c.reuse_famg.size() && c.reuse_famg[lev]) {
+            // setup reuse: the previous hierarchy of this level, kept whole (A_FF
+            // unchanged) or with new Galerkin products
+            l.famg = std::move(c.reuse_famg[lev]);
+            if (!c.reuse_keep_famg) amg_refresh(*l.famg, amg_operator(), S);
+        } else {
+            l.famg.reset(new Amg());
+            mgr_amg_opts fo = c.o.amg;
+            fo.unknown_based = o.amg_unknown_based != 0;
+            fo.agg_levels = o.amg_agg_levels;
+            amg_setup(*l.famg, amg_operator(), o.amg_unknown_based ? flab.p : nullptr, fo,
+                      c.o.amg.seed + 0x1000193ULL * (uint64_t)(lev + 1), S);
+        }
     }
     // transfer operators and the Petrov-Galerkin coarse operator R A P
     Spgemm jP, jW;
@@ -1998,6 +2011,8 @@ static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nle
         if (lvl[l].restrict_type < 0 || lvl[l].restrict_type > 1) throw Error(MGR_ERR_ARG, "unknown restriction");
         if (lvl[l].f_field_mask == 0) throw Error(MGR_ERR_BAD_LABELS, "empty F-field mask");
         if (lvl[l].amg_agg_levels < 0) throw Error(MGR_ERR_ARG, "amg_agg_levels must be >= 0");
+        if (lvl[l].amg_unknown_based < MGR_AMG_SCALAR || lvl[l].amg_unknown_based > MGR_AMG_SEPARATE)
+            throw Error(MGR_ERR_ARG, "unknown AMG kind of an F-relaxation level");
     }
     c.ready = false;
     c.L.clear();

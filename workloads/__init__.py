@@ -50,7 +50,7 @@ def level(fmask, frelax="jacobi", sweeps=1, omega=1.0, restrict="injection", amg
           amg_agg_levels=0):
     """One MGR reduction level: which fields are F-points and how they are handled."""
     return dict(fmask=int(fmask), frelax=frelax, sweeps=int(sweeps), omega=float(omega), restrict=restrict,
-                amg_unknown_based=bool(amg_unknown_based), amg_agg_levels=int(amg_agg_levels))
+                amg_unknown_based=int(amg_unknown_based), amg_agg_levels=int(amg_agg_levels))
 
 
 def _grid_neighbors(nx, ny, nz):
