@@ -1115,11 +1115,64 @@ struct Ctx {
     static constexpr int HROW = 200;
     double* hpin = nullptr;
     double* hpin_dev = nullptr;  // the same rows as seen by kernels
+    // auxiliary stream (default priority) for setup work off its critical
+    // path -- the copy of the input values, the fused-apply operators R_J and
+    // P_J -- forked from s and joined back into s before the setup returns
+    // (also when it fails); Avin: the input values the setup reads meanwhile
+    // (the caller's array, while the copy is in flight)
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool aux_pending = false;
+    const double* Avin = nullptr;
     ~Ctx() {
+        if (aux) {
+            (void)hipStreamSynchronize(aux);
+            (void)hipStreamDestroy(aux);
+        }
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
         if (hpin) (void)hipHostFree(hpin);
         if (fhist_h) (void)hipHostFree(fhist_h);
     }
 };
+
+// Work enqueued on c.aux after aux_fork runs after everything enqueued on
+// c.s so far; after aux_join, work on c.s runs after everything on c.aux.
+static void aux_fork(Ctx& c) {
+    if (!c.aux) {
+        MGR_HIP(hipStreamCreateWithFlags(&c.aux, hipStreamNonBlocking));
+        MGR_HIP(hipEventCreateWithFlags(&c.ev_fork, hipEventDisableTiming));
+        MGR_HIP(hipEventCreateWithFlags(&c.ev_join, hipEventDisableTiming));
+    }
+    MGR_HIP(hipEventRecord(c.ev_fork, c.s));
+    MGR_HIP(hipStreamWaitEvent(c.aux, c.ev_fork, 0));
+    c.aux_pending = true;
+}
+
+static void aux_join(Ctx& c) {
+    if (!c.aux_pending) return;
+    c.aux_pending = false;
+    MGR_HIP(hipEventRecord(c.ev_join, c.aux));
+    MGR_HIP(hipStreamWaitEvent(c.s, c.ev_join, 0));
+}
+
+// Joins the auxiliary stream at the end of a setup call, however it ends, so
+// that no array of the handle is reused while work on c.aux may still touch it,
+// and forgets the caller's input values.
+struct AuxScope {
+    Ctx& c;
+    ~AuxScope() {
+        if (c.aux_pending) {
+            c.aux_pending = false;
+            (void)hipEventRecord(c.ev_join, c.aux);
+            (void)hipStreamWaitEvent(c.s, c.ev_join, 0);
+        }
+        c.Avin = nullptr;
+    }
+};
+
+// the block values a setup step reads: the caller's while they are being copied
+static const double* in_values(const Ctx& c) { return c.Avin ? c.Avin : c.Av.p; }
 
 static bool fused_ok(const mgr_level_opts& o) {
     return o.sweeps == 1 && o.restrict_type == MGR_RESTRICT_INJECTION &&
@@ -1137,12 +1190,13 @@ static bool fused_ok(const mgr_level_opts& o) {
 static void level_extract_count(Ctx& c, const DCsr* A, const int* isF, const int* lmap, const int* fblk, int* cFF,
                                 int* cFC, int* cCF, int* cCC) {
     if (A) extract_count(*A, isF, lmap, fblk, cFF, cFC, cCF, cCC, c.s);
-    else bsr_extract_count(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, c.Av.p, isF, lmap, fblk, cFF, cFC, cCF, cCC, c.s);
+    else bsr_extract_count(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, in_values(c), isF, lmap, fblk, cFF, cFC, cCF, cCC,
+                           c.s);
 }
 static void level_extract_fill(Ctx& c, const DCsr* A, const int* isF, const int* lmap, const int* fblk, DCsr* FF,
                                DCsr* FC, DCsr* CF, DCsr* CC) {
     if (A) extract_fill(*A, isF, lmap, fblk, FF, FC, CF, CC, c.s);
-    else bsr_extract_fill(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, c.Av.p, isF, lmap, fblk, FF, FC, CF, CC, c.s);
+    else bsr_extract_fill(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, in_values(c), isF, lmap, fblk, FF, FC, CF, CC, c.s);
 }
 
 // The whole of A_FF for a level that kept only its F-relaxation blocks (for
@@ -1299,8 +1353,11 @@ static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr* A, const int* field
     if (l.fused) {
         csr_finish(pR, S);
         csr_finish(pP, S);
-        rj_fill(l.nC, l.W, -o.omega, l.fmap.p, l.cmap.p, l.RJ, s);
-        pj_fill(n, l.nC, l.isF.p, l.lmap.p, l.PF, 1.0, l.M, o.omega, l.fmap.p, l.PJ, s);
+        // R_J and P_J are read only by the apply: filled on the auxiliary
+        // stream while the setup goes on (joined before the setup returns)
+        aux_fork(c);
+        rj_fill(l.nC, l.W, -o.omega, l.fmap.p, l.cmap.p, l.RJ, c.aux);
+        pj_fill(n, l.nC, l.isF.p, l.lmap.p, l.PF, 1.0, l.M, o.omega, l.fmap.p, l.PJ, c.aux);
     }
     if (!fuse_add) {
         Ac = csr_add(l.ACC, T1, S);
@@ -1977,11 +2034,11 @@ static void build_hierarchy(Ctx& c);
 static void expand_input(Ctx& c) {
     hipStream_t s = c.s;
     DArr<int> cnt((size_t)c.n + 1, s);
-    bsr_count(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, c.Av.p, cnt.p, s);
+    bsr_count(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, in_values(c), cnt.p, s);
     Pend pe = csr_begin(c.A0, c.n, c.n, cnt.p, c.slots);
     c.slots.sync("input matrix");
     csr_finish(pe, c.slots);
-    bsr_fill(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, c.Av.p, c.A0, s);
+    bsr_fill(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, in_values(c), c.A0, s);
 }
 
 // The scalar level-0 operator is needed for a plain CSR input (its matvec and
@@ -2029,7 +2086,12 @@ static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nle
     c.Aci.alloc((size_t)c.nnzb, s);
     c.Av.alloc((size_t)c.nnzb * bb, s);
     MGR_HIP(hipMemcpyAsync(c.Aci.p, A->col_idx, sizeof(int) * c.nnzb, hipMemcpyDeviceToDevice, s));
-    MGR_HIP(hipMemcpyAsync(c.Av.p, A->values, sizeof(double) * c.nnzb * bb, hipMemcpyDeviceToDevice, s));
+    // the values (the bulk of the input) are copied on the auxiliary stream
+    // while the setup reads the caller's array
+    AuxScope aux_scope{c};
+    aux_fork(c);
+    MGR_HIP(hipMemcpyAsync(c.Av.p, A->values, sizeof(double) * c.nnzb * bb, hipMemcpyDeviceToDevice, c.aux));
+    c.Avin = A->values;
     if (c.nnzb * bb > INT_MAX) throw Error(MGR_ERR_UNSUPPORTED, "more than 2^31 scalar entries");
     c.field0.alloc((size_t)c.n, s);
     MGR_HIP(hipMemcpyAsync(c.field0.p, field, sizeof(int) * c.n, hipMemcpyDeviceToDevice, s));
@@ -2099,6 +2161,8 @@ static void build_hierarchy(Ctx& c) {
                   c.o.amg.unknown_based ? fld.p : nullptr, c.o.amg, c.o.amg.seed, c.slots);
     }
     c.reuse_famg.clear();
+    aux_join(c);
+    c.Avin = nullptr;
     if (c.o.apply_precision == 32) {
         for (auto& l : c.L) mgr_level_make_float(c, l);
         amg_make_float(c.camg, s);
@@ -2120,7 +2184,10 @@ static void update_values(Ctx& c, const double* values, int flags) {
     if (flags & ~MGR_REUSE_KEEP_FRELAX_AMG) throw Error(MGR_ERR_ARG, "unknown reuse flags");
     c.ready = false;
     long bb = (long)c.b * c.b;
-    MGR_HIP(hipMemcpyAsync(c.Av.p, values, sizeof(double) * c.nnzb * bb, hipMemcpyDeviceToDevice, s));
+    AuxScope aux_scope{c};
+    aux_fork(c);
+    MGR_HIP(hipMemcpyAsync(c.Av.p, values, sizeof(double) * c.nnzb * bb, hipMemcpyDeviceToDevice, c.aux));
+    c.Avin = values;
     prepare_input(c, (int)c.lvl.size());
     c.A0t = DCsr();
     c.ATrp.reset(); c.ATci.reset(); c.ATv.reset();
