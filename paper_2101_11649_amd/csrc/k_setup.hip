@@ -1335,50 +1335,33 @@ __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restri
     }
 }
 
-// C = A B (ADD: C = D + A B) with a lane per entry of a row of A, for rows of
-// A long against those of B (A P in the AMG levels), where the kernel above
-// would take the row's entries one after another.  32 lanes per row take its
-// entries 32 at a time; each lane walks the row of B its entry selects and
-// inserts the columns into the row's LDS hash table (CAS linear probing) in
-// any order: the keys are the output pattern.  The numeric pass numbers every
-// product in the order of A's entries and then B's (the numbers come from a
-// lane prefix sum) and chains it to its slot (an exchange on the slot's list
-// head); each output value is the sum of its slot's products taken in
-// increasing number from 0.0 -- Gustavson's order, so the values equal the
-// other kernels' to the bit; with D, a slot that D's row also holds gets
-// d + that sum (d alone without products).  Rows are written in column order
-// by rank.  The count pass stores the largest number of products of a row in
-// flag[1] (it sizes the numeric pass's list, PMAX >= that number); a full
-// table sets flag[0] (2 in the count pass).
-template <int CAP, int PMAX, bool FILL, bool ADD>
-__global__ __launch_bounds__(TPB) void k_spgemm_lanes(int nr, const int* __restrict__ arp,
-                                                      const int* __restrict__ aci, const double* __restrict__ av,
-                                                      const int* __restrict__ brp, const int* __restrict__ bci,
-                                                      const double* __restrict__ bv, const int* __restrict__ drp,
-                                                      const int* __restrict__ dci, const double* __restrict__ dv,
-                                                      const int* __restrict__ crp, int* __restrict__ cci,
-                                                      double* __restrict__ cv, int* __restrict__ cnt,
-                                                      int* __restrict__ flag) {
+// Symbolic pass of C = A B (ADD: C = D + A B) with a lane per entry of a row
+// of A, for rows of A long against those of B (A P in the AMG levels), where
+// the hashed kernel above would take the row's entries one after another.
+// 32 lanes per row take its entries 32 at a time; each lane walks the row of
+// B its entry selects and inserts the columns into the row's LDS hash table
+// (CAS linear probing) in any order: the keys are the output pattern, the
+// count their number.  A full table sets flag[0] to 2.  (A numeric pass built
+// the same way -- each slot's products chained and summed in Gustavson order
+// -- measured twice as slow as the hashed fill, which walks A's entries in
+// order; the fill stays with that kernel.)
+template <int CAP, bool ADD>
+__global__ __launch_bounds__(TPB) void k_spgemm_lanes_count(int nr, const int* __restrict__ arp,
+                                                            const int* __restrict__ aci,
+                                                            const int* __restrict__ brp,
+                                                            const int* __restrict__ bci,
+                                                            const int* __restrict__ drp,
+                                                            const int* __restrict__ dci, int* __restrict__ cnt,
+                                                            int* __restrict__ flag) {
     constexpr int G = 32, NG = TPB / G, PER = CAP / G;
-    constexpr int PL = FILL ? PMAX : 1, HL = FILL ? CAP : 1, DL = (FILL && ADD) ? CAP : 1;
     __shared__ int keys[NG][CAP];
-    __shared__ int head[NG][HL];
-    __shared__ int pnext[NG][PL];
-    __shared__ double pval[NG][PL];
-    __shared__ double dvs[NG][DL];
-    __shared__ unsigned char hasd[NG][DL];
-    __shared__ int npmax[NG];
     Grp<G> g;
     const int grp = threadIdx.x / G;
     const int row = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
     const bool valid = row < nr;
     int* K = keys[grp];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        K[g.gl + G * u] = -1;
-        if (FILL) head[grp][g.gl + G * u] = -1;
-        if (FILL && ADD) hasd[grp][g.gl + G * u] = 0;
-    }
+    for (int u = 0; u < PER; ++u) K[g.gl + G * u] = -1;
     __syncthreads();
     int a0 = 0, a1 = 0;
     if (valid) {
@@ -1390,98 +1373,30 @@ __global__ __launch_bounds__(TPB) void k_spgemm_lanes(int nr, const int* __restr
         int h = (int)(((unsigned)j * 2654435761u) >> (32 - log2_pow2(CAP)));
         for (int probes = 0;; ++probes) {
             const int old = atomicCAS(&K[h], -1, j);
-            if (old == -1 || old == j) return h;
+            if (old == -1 || old == j) return;
             if (probes + 1 == CAP) {
-                atomicMax(flag, FILL ? 1 : 2);
-                return -1;
+                atomicMax(flag, 2);
+                return;
             }
             h = (h + 1) & (CAP - 1);
         }
     };
-    int np = 0;   // products numbered so far (the same in every lane of the group)
     for (int base = 0; base < wl; base += G) {
         const int e = a0 + base + g.gl;
-        int b0 = 0, len = 0;
-        double a = 0.0;
         if (e < a1) {
             const int k = aci[e];
-            b0 = brp[k];
-            len = brp[k + 1] - b0;
-            if (FILL) a = av[e];
-        }
-        int incl = len;
-        for (int off = 1; off < G; off <<= 1) {
-            const int t = __shfl_up(incl, off, G);
-            if (g.gl >= off) incl += t;
-        }
-        const int tot = __shfl(incl, g.gbase + G - 1, WAVE);
-        const int at = np + incl - len;
-        for (int q = 0; q < len; ++q) {
-            const int h = insert(bci[b0 + q]);
-            const int pn = at + q;
-            if (FILL && h >= 0 && pn < PMAX) {
-                pval[grp][pn] = a * bv[b0 + q];
-                pnext[grp][pn] = atomicExch(&head[grp][h], pn);
-            }
-        }
-        np += tot;
-    }
-    if (FILL && np > PMAX) atomicMax(flag, 1);
-    if (ADD && valid) {
-        for (int q = drp[row] + g.gl; q < drp[row + 1]; q += G) {
-            const int h = insert(dci[q]);
-            if (FILL && h >= 0) {
-                dvs[grp][h] = dv[q];
-                hasd[grp][h] = 1;
-            }
+            const int b0 = brp[k], b1 = brp[k + 1];
+            for (int q = b0; q < b1; ++q) insert(bci[q]);
         }
     }
-    if (!FILL && g.gl == 0) npmax[grp] = np;
+    if (ADD && valid)
+        for (int q = drp[row] + g.gl; q < drp[row + 1]; q += G) insert(dci[q]);
     __syncthreads();
-    if (!FILL) {
-        int mine = 0;
+    int mine = 0;
 #pragma unroll
-        for (int u = 0; u < PER; ++u) mine += K[g.gl + G * u] >= 0 ? 1 : 0;
-        mine = g.sum(mine);
-        if (valid && g.gl == 0) cnt[row] = mine;
-        if (threadIdx.x == 0) {
-            // one atomic per workgroup, and only above the maximum seen so far
-            int m = 0;
-            for (int q = 0; q < NG; ++q) m = max(m, npmax[q]);
-            if (m > __atomic_load_n(flag + 1, __ATOMIC_RELAXED)) atomicMax(flag + 1, m);
-        }
-        return;
-    }
-    if (!valid) return;
-    const int o = crp[row];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int sl = g.gl + G * u;
-        const int key = K[sl];
-        if (key < 0) continue;
-        // the slot's products in increasing number: each pass walks the
-        // chain for the smallest number above the last one taken
-        double acc = 0.0;
-        bool any = false;
-        for (int last = -1;;) {
-            int nx = INT_MAX;
-            for (int p = head[grp][sl]; p >= 0; p = pnext[grp][p])
-                if (p > last && p < nx) nx = p;
-            if (nx == INT_MAX) break;
-            acc = acc + pval[grp][nx];
-            any = true;
-            last = nx;
-        }
-        double val = acc;
-        if (ADD && hasd[grp][sl]) val = any ? dvs[grp][sl] + acc : dvs[grp][sl];
-        int rank = 0;
-        for (int f = 0; f < CAP; ++f) {
-            const int kf = K[f];
-            rank += (kf >= 0 && kf < key) ? 1 : 0;
-        }
-        cci[o + rank] = key;
-        cv[o + rank] = val;
-    }
+    for (int u = 0; u < PER; ++u) mine += K[g.gl + G * u] >= 0 ? 1 : 0;
+    mine = g.sum(mine);
+    if (valid && g.gl == 0) cnt[row] = mine;
 }
 
 // Block extraction (Sec. 2, the partition of eq. (2)): each row i goes to
@@ -3216,58 +3131,27 @@ static void spgemm_hash_launch(const DCsr& A, const DCsr& B, const DCsr* D, int 
     MGR_LAUNCH_CHECK();
 }
 
-constexpr bool SPGEMM_LANES_FILL = false;
-
-// The lane-per-entry kernel: rows of A of 24 entries or more and at least
-// twice as long as those of B (shorter rows keep more lanes busy in the
-// kernels above: measured on the MGR products A_CF M, A_CC + A_CF P_F).
+// The lane-per-entry symbolic kernel: rows of A of 24 entries or more and at
+// least twice as long as those of B (shorter rows keep more lanes busy in the
+// hashed kernel: measured on the MGR products A_CF M, A_CC + A_CF P_F).
 static bool lanes_ok(const DCsr& A, const DCsr& B) {
     return A.nr > 0 && A.max_row >= 24 && B.max_row >= 0 && 2 * B.max_row <= A.max_row;
 }
 
-// tables of cap slots (32..512) in the count pass; in the numeric pass the
-// instantiated pairs of table and product list (the eight groups of a
-// workgroup within 64 KB of LDS, D's values included)
-static bool lanes_fill_ok(int cap, int pmax) {
-    return (pmax <= 128 && cap <= 256) || (pmax <= 256 && cap <= 128) || (pmax <= 512 && cap <= 64);
-}
-
-template <bool FILL, bool ADD>
-static void spgemm_lanes_launch(const DCsr& A, const DCsr& B, const DCsr* D, int cap, int pmax, const int* crp,
-                                int* cci, double* cv, int* cnt, int* flag, hipStream_t s) {
+template <bool ADD>
+static void spgemm_lanes_count(const DCsr& A, const DCsr& B, const DCsr* D, int cap, int* cnt, int* flag,
+                               hipStream_t s) {
     const int* drp = ADD ? D->rp.p : nullptr;
     const int* dci = ADD ? D->ci.p : nullptr;
-    const double* dvv = ADD ? D->v.p : nullptr;
     const int grid = grid_for(A.nr, 32);
-#define MGR_LANES(CC, PP)                                                                                          \
-    k_spgemm_lanes<CC, PP, FILL, ADD><<<grid, TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p, B.ci.p, B.v.p, drp, \
-                                                          dci, dvv, crp, cci, cv, cnt, flag)
-    if (!FILL) {
-        switch (cap) {
-            case 32: MGR_LANES(32, 1); break;
-            case 64: MGR_LANES(64, 1); break;
-            case 128: MGR_LANES(128, 1); break;
-            case 256: MGR_LANES(256, 1); break;
-            default: MGR_LANES(512, 1); break;
-        }
-    } else if (pmax <= 128) {
-        switch (cap) {
-            case 32: MGR_LANES(32, 128); break;
-            case 64: MGR_LANES(64, 128); break;
-            case 128: MGR_LANES(128, 128); break;
-            default: MGR_LANES(256, 128); break;
-        }
-    } else if (pmax <= 256) {
-        switch (cap) {
-            case 32: MGR_LANES(32, 256); break;
-            case 64: MGR_LANES(64, 256); break;
-            default: MGR_LANES(128, 256); break;
-        }
-    } else {
-        switch (cap) {
-            case 32: MGR_LANES(32, 512); break;
-            default: MGR_LANES(64, 512); break;
-        }
+#define MGR_LANES(CC) \
+    k_spgemm_lanes_count<CC, ADD><<<grid, TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, B.rp.p, B.ci.p, drp, dci, cnt, flag)
+    switch (cap) {
+        case 32: MGR_LANES(32); break;
+        case 64: MGR_LANES(64); break;
+        case 128: MGR_LANES(128); break;
+        case 256: MGR_LANES(256); break;
+        default: MGR_LANES(512); break;
     }
 #undef MGR_LANES
     MGR_LAUNCH_CHECK();
@@ -3289,7 +3173,7 @@ void spgemm_count(const DCsr& A, const DCsr& B, int max_row, int* cnt, int* flag
         if (bound <= 256 || (loose && bound <= SPGEMM_HASH_LOOSE)) {
             const int cap = pow2_at_least(bound < 512 ? bound : 512, 32);
             if (lanes_ok(A, B))
-                spgemm_lanes_launch<false, false>(A, B, nullptr, cap, 0, nullptr, nullptr, nullptr, cnt, flag, s);
+                spgemm_lanes_count<false>(A, B, nullptr, cap, cnt, flag, s);
             else
                 spgemm_hash_launch<false, false>(A, B, nullptr, cap, nullptr, nullptr, nullptr, cnt, flag, s);
             return;
@@ -3298,16 +3182,12 @@ void spgemm_count(const DCsr& A, const DCsr& B, int max_row, int* cnt, int* flag
     spgemm_launch<false>(A, B, max_row, nullptr, nullptr, nullptr, cnt, flag, s);
 }
 
-void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, int* flag, hipStream_t s, int pmax) {
+void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, int* flag, hipStream_t s) {
     // hashed rows when the right factor is too wide for the dense LDS row and the
     // output rows (known from the symbolic pass) fit a table of at most 512 slots
     if (!spgemm_dense_ok(A, B) && A.nr > 0 && C.max_row >= 0 && C.max_row <= 256 && B.max_row >= 0) {
         const int cap = pow2_at_least(2L * C.max_row, 32);
-        const int pm = pow2_at_least(pmax, 128);
-        if (SPGEMM_LANES_FILL && pmax > 0 && lanes_ok(A, B) && lanes_fill_ok(cap, pm))
-            spgemm_lanes_launch<true, false>(A, B, nullptr, cap, pm, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s);
-        else
-            spgemm_hash_launch<true, false>(A, B, nullptr, cap, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s);
+        spgemm_hash_launch<true, false>(A, B, nullptr, cap, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s);
         return;
     }
     spgemm_launch<true>(A, B, max_row, C.rp.p, C.ci.p, C.v.p, nullptr, nullptr, s);
@@ -3324,19 +3204,15 @@ void spgemm_add_count(const DCsr& A, const DCsr& B, const DCsr& D, int* cnt, int
     const long bound = (long)A.max_row * B.max_row + D.max_row;
     const int cap = pow2_at_least(bound, 32);
     if (lanes_ok(A, B))
-        spgemm_lanes_launch<false, true>(A, B, &D, cap, 0, nullptr, nullptr, nullptr, cnt, flag, s);
+        spgemm_lanes_count<true>(A, B, &D, cap, cnt, flag, s);
     else
         spgemm_hash_launch<false, true>(A, B, &D, cap, nullptr, nullptr, nullptr, cnt, flag, s);
 }
 
-void spgemm_add_fill(const DCsr& A, const DCsr& B, const DCsr& D, DCsr& C, int* flag, hipStream_t s, int pmax) {
+void spgemm_add_fill(const DCsr& A, const DCsr& B, const DCsr& D, DCsr& C, int* flag, hipStream_t s) {
     if (A.nr <= 0) return;
     const int cap = pow2_at_least(2L * C.max_row, 32);
-    const int pm = pow2_at_least(pmax, 128);
-    if (SPGEMM_LANES_FILL && pmax > 0 && lanes_ok(A, B) && lanes_fill_ok(cap, pm))
-        spgemm_lanes_launch<true, true>(A, B, &D, cap, pm, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s);
-    else
-        spgemm_hash_launch<true, true>(A, B, &D, cap, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s);
+    spgemm_hash_launch<true, true>(A, B, &D, cap, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s);
 }
 
 static int add_group(const DCsr& A, const DCsr& B) {

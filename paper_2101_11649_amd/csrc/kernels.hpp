@@ -66,20 +66,16 @@ void frelax_fill(int nb, const int* bstart, const DCsr& AFF, DCsr& M, int* flag,
 // sets *flag to 2, and the count must then be made again without `loose`.
 constexpr int SPGEMM_DENSE_COLS = 4096;
 constexpr long SPGEMM_HASH_LOOSE = 2048;
-// flag[1] (a second int in device memory, zero beforehand) receives the
-// largest number of products of a row when the lane-per-entry variant counted
-// (rows of A at least twice as long as those of B), to be passed to the fill.
 void spgemm_count(const DCsr& A, const DCsr& B, int max_row, int* cnt, int* flag, hipStream_t s, bool loose = false);
 // C's row pointers and max_row come from the counts; a failure of the hashed
-// variant (a full table) sets *flag (an int in device memory).  pmax: the
-// count's flag[1] (0: unknown).
-void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, int* flag, hipStream_t s, int pmax = 0);
+// variant (a full table) sets *flag (an int in device memory).
+void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, int* flag, hipStream_t s);
 // C = D + A B in one hashed product (D has A's rows and B's columns), when
 // every row of C is bounded by maxrow(A) maxrow(B) + maxrow(D) <= 256; the
 // values are those of the product followed by a separate sparse add.
 bool spgemm_add_fusable(const DCsr& A, const DCsr& B, const DCsr& D);
 void spgemm_add_count(const DCsr& A, const DCsr& B, const DCsr& D, int* cnt, int* flag, hipStream_t s);
-void spgemm_add_fill(const DCsr& A, const DCsr& B, const DCsr& D, DCsr& C, int* flag, hipStream_t s, int pmax = 0);
+void spgemm_add_fill(const DCsr& A, const DCsr& B, const DCsr& D, DCsr& C, int* flag, hipStream_t s);
 void add_count(const DCsr& A, const DCsr& B, int* cnt, hipStream_t s);
 void add_fill(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s);
 void negate(double* v, long n, hipStream_t s);

@@ -148,7 +148,7 @@ static void spgemm_recount(Spgemm& j, hipStream_t s) {
     long long h[3] = {0, 0, 0};
     MGR_HIP(hipMemcpyAsync(h, t.p, sizeof(h), hipMemcpyDeviceToHost, s));
     MGR_HIP(hipStreamSynchronize(s));
-    if ((h[0] & 0xffffffffLL) != 0) throw Error(MGR_ERR_ARG, "internal: spgemm row longer than its recorded length");
+    if (h[0] != 0) throw Error(MGR_ERR_ARG, "internal: spgemm row longer than its recorded length");
     if (h[1] > INT_MAX) throw Error(MGR_ERR_UNSUPPORTED, "operator exceeds the int32 index range");
     C.nnz = (long)h[1];
     C.max_row = (int)h[2];
@@ -170,20 +170,15 @@ static void spgemm_add_begin(Spgemm& j, const DCsr& A, const DCsr& B, const DCsr
 }
 
 static void spgemm_finish(Spgemm& j, Slots& S) {
-    // the slot holds the count's table-overflow flag (low int) and the most
-    // products of a row (high int, from the lane-per-entry variant, else 0)
     const long long v = S.val(j.lr);
-    const int fl = (int)(v & 0xffffffffLL);
-    int pmax = (int)((unsigned long long)v >> 32);
-    if (fl == 2 && !j.D) {
+    if (v == 2 && !j.D) {
         spgemm_recount(j, S.s);
-        pmax = 0;
     } else {
-        if (fl != 0) throw Error(MGR_ERR_ARG, "internal: spgemm row longer than its recorded length");
+        if (v != 0) throw Error(MGR_ERR_ARG, "internal: spgemm row longer than its recorded length");
         csr_finish(j.pend, S);
     }
-    if (j.D) spgemm_add_fill(*j.A, *j.B, *j.D, *j.C, S.flag(), S.s, pmax);
-    else spgemm_fill(*j.A, *j.B, j.A->max_row, *j.C, S.flag(), S.s, pmax);
+    if (j.D) spgemm_add_fill(*j.A, *j.B, *j.D, *j.C, S.flag(), S.s);
+    else spgemm_fill(*j.A, *j.B, j.A->max_row, *j.C, S.flag(), S.s);
     j.cnt.reset();
 }
 
