@@ -1507,14 +1507,16 @@ struct BsrBlock {
 template <int B>
 __device__ inline void bsr_row_counts(const BsrBlock<B>& k, int I, int r, int ffb, const int* __restrict__ fblk,
                                       int& nf, int& nc) {
+    // both counters updated by selects: a branch choosing which one to bump
+    // had the compiler index a two-element array in scratch memory
     nf = 0;
     nc = 0;
 #pragma unroll
     for (int c = 0; c < B; ++c) {
         const bool keep = k.a[r][c] != 0.0 || (k.J == I && c == r);
-        if (!keep) continue;
-        if (k.cf[c]) nf += (ffb < 0 || fblk[k.cl[c]] == ffb) ? 1 : 0;
-        else ++nc;
+        const bool inb = ffb < 0 || (k.cf[c] && fblk[k.cl[c]] == ffb);
+        nf += (keep && k.cf[c] && inb) ? 1 : 0;
+        nc += (keep && !k.cf[c]) ? 1 : 0;
     }
 }
 
@@ -1621,15 +1623,13 @@ __global__ __launch_bounds__(TPB) void k_bsr_extract_fill_g(int nbr, const int* 
 #pragma unroll
                 for (int cc = 0; cc < B; ++cc) {
                     const double a = k.a[r][cc];
-                    if (!(a != 0.0 || (k.J == I && cc == r))) continue;
-                    if (k.cf[cc]) {
-                        if (ffb[r] >= 0 && fblk[k.cl[cc]] != ffb[r]) continue;
-                        if (cF[r]) { cF[r][wf] = k.cl[cc]; vF[r][wf] = a; }
-                        ++wf;
-                    } else {
-                        if (cC[r]) { cC[r][wc] = k.cl[cc]; vC[r][wc] = a; }
-                        ++wc;
-                    }
+                    const bool keep = a != 0.0 || (k.J == I && cc == r);
+                    const bool inb = ffb[r] < 0 || (k.cf[cc] && fblk[k.cl[cc]] == ffb[r]);
+                    const bool tf = keep && k.cf[cc] && inb, tc = keep && !k.cf[cc];
+                    if (tf && cF[r]) { cF[r][wf] = k.cl[cc]; vF[r][wf] = a; }
+                    if (tc && cC[r]) { cC[r][wc] = k.cl[cc]; vC[r][wc] = a; }
+                    wf += tf ? 1 : 0;
+                    wc += tc ? 1 : 0;
                 }
             }
             oF[r] += __shfl(fi, g.gbase + G - 1, WAVE);
