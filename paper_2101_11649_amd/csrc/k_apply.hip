@@ -38,33 +38,45 @@ __device__ inline T group_sum(T v, int G) {
 //   SpmvOp     y = alpha * A [x | x2] + beta * w   (w may alias y)
 //   JacobiOp   y = x + dinv .* (b - A x)          (one L1-Jacobi sweep, out of place)
 //   PreOp      x = dinv .* b,  r = b - A x        (first sweep from zero + residual)
+// Every operation splits its row epilogue in two: pre(r) loads the vectors the
+// epilogue reads (issued by the kernels before their gathers, so those loads
+// overlap the row's products instead of following them), fin(r, s, p) forms
+// and stores the row's results; done(r, s) = fin(r, s, pre(r)).
 template <typename MT, typename XT, typename X2T, typename YT, typename WT>
 struct SpmvOp {
     const XT* x; const X2T* x2; int split; const WT* w; YT* y; MT alpha, beta;
+    struct Pre { MT w; };
     __device__ MT xval(int c) const { return (c < split) ? (MT)x[c] : (MT)x2[c - split]; }
-    __device__ void done(int r, MT s) const {
+    __device__ Pre pre(int r) const { return Pre{w ? (MT)w[r] : MT(0)}; }
+    __device__ void fin(int r, MT s, const Pre& p) const {
         MT o = alpha * s;
-        if (w) o += beta * (MT)w[r];
+        if (w) o += beta * p.w;
         y[r] = (YT)o;
     }
+    __device__ void done(int r, MT s) const { fin(r, s, pre(r)); }
 };
 
 template <typename T>
 struct JacobiOp {
     const T* dinv; const T* b; const T* x; T* y;
+    struct Pre { T d, b, x; };
     __device__ T xval(int c) const { return x[c]; }
-    __device__ void done(int r, T s) const { y[r] = x[r] + dinv[r] * (b[r] - s); }
+    __device__ Pre pre(int r) const { return Pre{dinv[r], b[r], x[r]}; }
+    __device__ void fin(int r, T s, const Pre& p) const { y[r] = p.x + p.d * (p.b - s); }
+    __device__ void done(int r, T s) const { fin(r, s, pre(r)); }
 };
 
 template <typename T>
 struct PreOp {
     const T* dinv; const T* b; T* x; T* r_;
+    struct Pre { T d, b; };
     __device__ T xval(int c) const { return dinv[c] * b[c]; }
-    __device__ void done(int r, T s) const {
-        T bi = b[r];
-        x[r] = dinv[r] * bi;
-        r_[r] = bi - s;
+    __device__ Pre pre(int r) const { return Pre{dinv[r], b[r]}; }
+    __device__ void fin(int r, T s, const Pre& p) const {
+        x[r] = p.d * p.b;
+        r_[r] = p.b - s;
     }
+    __device__ void done(int r, T s) const { fin(r, s, pre(r)); }
 };
 
 // RestrictOp  y = A x  and  yd = dsc .* y  (the next level's D^-1 b); x may be
@@ -72,22 +84,28 @@ struct PreOp {
 template <typename T, typename XT>
 struct RestrictOp {
     const XT* x; const T* dsc; T* y; T* yd;
+    struct Pre { T d; };
     __device__ T xval(int c) const { return (T)x[c]; }
-    __device__ void done(int r, T s) const {
+    __device__ Pre pre(int r) const { return Pre{dsc[r]}; }
+    __device__ void fin(int r, T s, const Pre& p) const {
         y[r] = s;
-        yd[r] = dsc[r] * s;
+        yd[r] = p.d * s;
     }
+    __device__ void done(int r, T s) const { fin(r, s, pre(r)); }
 };
 
 // PreOpD  x = bd,  r = b - A bd  with bd = dinv .* b already formed
 template <typename T>
 struct PreOpD {
     const T* bd; const T* b; T* x; T* r_;
+    struct Pre { T bd, b; };
     __device__ T xval(int c) const { return bd[c]; }
-    __device__ void done(int r, T s) const {
-        x[r] = bd[r];
-        r_[r] = b[r] - s;
+    __device__ Pre pre(int r) const { return Pre{bd[r], b[r]}; }
+    __device__ void fin(int r, T s, const Pre& p) const {
+        x[r] = p.bd;
+        r_[r] = p.b - s;
     }
+    __device__ void done(int r, T s) const { fin(r, s, pre(r)); }
 };
 
 template <typename MT, int TAG, class Op>
@@ -101,6 +119,18 @@ __global__ __launch_bounds__(TPB) void k_spmv_stream(const int* __restrict__ blk
     const int p0 = rp[r0], p1 = rp[r1];
     const int nnz = p1 - p0;
     if (nnz <= SPMV_LDS) {
+        // the epilogue inputs of the (first) row this thread finishes, loaded
+        // with the entries
+        const int nrows = r1 - r0;
+        int G = 64;
+        while (G > 1 && G * nrows > TPB) G >>= 1;
+        const int rl = tid / G, lane = tid & (G - 1);
+        typename Op::Pre pre{};
+        if (nrows > TPB / 4) {
+            if (r0 + tid < r1) pre = op.pre(r0 + tid);
+        } else if (rl < nrows && lane == 0) {
+            pre = op.pre(r0 + rl);
+        }
         // issue every index and value load of this thread before the gathers
         constexpr int PER = SPMV_LDS / TPB;
         int cc[PER];
@@ -116,18 +146,15 @@ __global__ __launch_bounds__(TPB) void k_spmv_stream(const int* __restrict__ blk
             if (q < nnz) sh[q] = vv[t] * op.xval(cc[t]);
         }
         __syncthreads();
-        const int nrows = r1 - r0;
         if (nrows > TPB / 4) {
             for (int r = r0 + tid; r < r1; r += TPB) {
                 MT s = MT(0);
                 int qe = rp[r + 1] - p0;
                 for (int q = rp[r] - p0; q < qe; ++q) s += sh[q];
-                op.done(r, s);
+                if (r == r0 + tid) op.fin(r, s, pre);
+                else op.done(r, s);
             }
         } else {
-            int G = 64;
-            while (G > 1 && G * nrows > TPB) G >>= 1;
-            int rl = tid / G, lane = tid & (G - 1);
             int r = r0 + rl;
             MT s = MT(0);
             if (rl < nrows) {
@@ -135,7 +162,7 @@ __global__ __launch_bounds__(TPB) void k_spmv_stream(const int* __restrict__ blk
                 for (int q = rp[r] - p0 + lane; q < qe; q += G) s += sh[q];
             }
             for (int off = G >> 1; off > 0; off >>= 1) s += __shfl_xor(s, off, WAVE);
-            if (rl < nrows && lane == 0) op.done(r, s);
+            if (rl < nrows && lane == 0) op.fin(r, s, pre);
         }
         return;
     }
@@ -679,6 +706,7 @@ __global__ __launch_bounds__(TPB) void k_spmv_ell(int nr, int w, const int* __re
     const int sw = min(esw[blockIdx.x], w);
     if (r >= nr) return;
     const long base = (long)blockIdx.x * w * TPB + threadIdx.x;
+    const typename Op::Pre pre = op.pre(r);
     int c[WMAX];
     MT a[WMAX];
 #pragma unroll
@@ -691,7 +719,7 @@ __global__ __launch_bounds__(TPB) void k_spmv_ell(int nr, int w, const int* __re
 #pragma unroll
     for (int k = 0; k < WMAX; ++k)
         if (k < sw) s += a[k] * op.xval(c[k]);
-    op.done(r, s);
+    op.fin(r, s, pre);
 }
 
 // esw[slice] = the longest row of the slice's TPB rows
