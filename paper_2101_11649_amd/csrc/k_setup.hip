@@ -1184,7 +1184,7 @@ __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restri
                                                      const int* __restrict__ dci, const double* __restrict__ dv,
                                                      const int* __restrict__ crp, int* __restrict__ cci,
                                                      double* __restrict__ cv, int* __restrict__ cnt,
-                                                     int* __restrict__ flag) {
+                                                     int* __restrict__ flag, int lo, int hi) {
     constexpr int NG = TPB / G;
     constexpr int PER = CAP / G;
     __shared__ int keys[NG][CAP];
@@ -1192,7 +1192,12 @@ __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restri
     Grp<G> g;
     const int grp = threadIdx.x / G;
     const int row = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
-    const bool valid = row < nr;
+    bool valid = row < nr;
+    if (FILL && valid) {
+        // this launch takes the rows of C with lo < length <= hi
+        const int cl = crp[row + 1] - crp[row];
+        valid = cl > lo && cl <= hi;
+    }
     int* K = keys[grp];
     double* Vs = vals[grp];
 #pragma unroll
@@ -1335,6 +1340,184 @@ __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restri
     }
 }
 
+// Products with the block-diagonal F-relaxation operator M, whose blocks of at
+// most four F-points store, in every row, the block's columns in order (a
+// larger, failed block keeps one diagonal entry per row).  M's layout is
+// known: row s0 + r of a block of bs <= 4 rows starts at mrp[s0] + r bs and
+// holds columns s0 .. s0 + bs - 1; a failed block's row holds its diagonal.
+//
+// Symbolic pass of M B (P_F = -M A_FC), G lanes per block: every row of a
+// block has the same pattern, the union of B's rows s0 .. s0 + bs - 1, formed
+// once in an LDS hash table.  A failed block's rows are taken one by one.
+// At most BDL_STAGE entries of B per block.
+constexpr int BDL_STAGE = 64, BDL_CAP = 128;
+
+template <int G>
+__global__ __launch_bounds__(TPB) void k_bdiag_left_count(int nb, const int* __restrict__ bstart,
+                                                          const int* __restrict__ brp, const int* __restrict__ bci,
+                                                          int* __restrict__ cnt, int* __restrict__ flag) {
+    constexpr int NG = TPB / G, PER = BDL_CAP / G;
+    __shared__ int keys[NG][BDL_CAP];
+    Grp<G> g;
+    const int grp = threadIdx.x / G;
+    const int b = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    int s0 = 0, bs = 0;
+    if (b < nb) {
+        s0 = bstart[b];
+        bs = bstart[b + 1] - s0;
+    }
+    const bool whole = bs <= 4;
+    const int nsets = whole ? (bs > 0 ? 1 : 0) : bs;
+    const int nsub = wave_max_int(nsets);
+    int* K = keys[grp];
+    for (int sub = 0; sub < nsub; ++sub) {
+        const bool act = sub < nsets;
+        const int r0 = whole ? s0 : s0 + sub, nrow = whole ? bs : 1, nk = act ? nrow : 0;
+        int rb[5];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) rb[t] = (act && t <= nk) ? brp[r0 + t] : 0;
+        int bk0[4] = {0, 0, 0, 0}, bkl[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (t < nk) {
+                bk0[t] = rb[t];
+                bkl[t] = rb[t + 1] - rb[t];
+            }
+        int total = bkl[0] + bkl[1] + bkl[2] + bkl[3];
+        if (total > BDL_STAGE) {
+            if (g.gl == 0) atomicMax(flag, 1);
+            total = 0;
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) K[g.gl + G * u] = -1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        for (int e = g.gl; e < total; e += G) {
+            // entry e of the concatenated rows: row t, position q
+            int q = e, t = 0, base = bk0[0];
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const bool adv = t == u && q >= bkl[u];
+                q = adv ? q - bkl[u] : q;
+                base = adv ? bk0[u + 1] : base;
+                t = adv ? u + 1 : t;
+            }
+            const int j = bci[base + q];
+            // at most BDL_STAGE distinct keys in BDL_CAP slots: a slot is found
+            int h = (int)(((unsigned)j * 2654435761u) >> (32 - log2_pow2(BDL_CAP)));
+            for (int probes = 0; probes < BDL_CAP; ++probes) {
+                const int old = atomicCAS(&K[h], -1, j);
+                if (old == -1 || old == j) break;
+                h = (h + 1) & (BDL_CAP - 1);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        int mine = 0;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) mine += K[g.gl + G * u] >= 0 ? 1 : 0;
+        const int L = g.sum(mine);
+        if (act)
+            for (int r = g.gl; r < nrow; r += G) cnt[r0 + r] = L;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// C = A M with M on the right (W = A_CF M), 32 lanes per row of A (rows of at
+// most 32 entries, columns ascending): lane e holds entry e.  A block's columns
+// are a range of indices, so its entries in the row are consecutive: a run of
+// entries whose M rows start at the same column and have the same length.  A
+// run contributes exactly its block's columns, and the run's first lane sums
+// the run's products for each of them in entry order (M's rows hold
+// consecutive columns, the first of them the block's).  A group takes BDR_ROWS
+// consecutive rows, with the loads of all of them issued before any is used.
+constexpr int BDR_ROWS = 4;
+
+template <bool FILL>
+__global__ __launch_bounds__(TPB) void k_bdiag_right(int nr, const int* __restrict__ arp,
+                                                     const int* __restrict__ aci, const double* __restrict__ av,
+                                                     const int* __restrict__ mrp, const int* __restrict__ mci,
+                                                     const double* __restrict__ mv, const int* __restrict__ crp,
+                                                     int* __restrict__ cci, double* __restrict__ cv,
+                                                     int* __restrict__ cnt, int* __restrict__ flag) {
+    constexpr int G = 32, R = BDR_ROWS;
+    Grp<G> g;
+    const int row0 = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G) * R;
+    int rpv[R + 1];
+#pragma unroll
+    for (int r = 0; r <= R; ++r) rpv[r] = row0 + r <= nr ? arp[row0 + r] : 0;
+    int len[R], k[R], m0[R], ml[R], first[R];
+    double a[R], mvv[R][4];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        len[r] = row0 + r < nr ? rpv[r + 1] - rpv[r] : 0;
+        if (len[r] > G) {
+            if (g.gl == 0) atomicMax(flag, 1);
+            len[r] = 0;
+        }
+        k[r] = g.gl < len[r] ? aci[rpv[r] + g.gl] : -1;
+        if (FILL) a[r] = g.gl < len[r] ? av[rpv[r] + g.gl] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        m0[r] = k[r] >= 0 ? mrp[k[r]] : 0;
+        ml[r] = k[r] >= 0 ? min(mrp[k[r] + 1] - m0[r], 4) : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        first[r] = k[r] >= 0 ? mci[m0[r]] : -1;
+        if (FILL)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) mvv[r][t] = t < ml[r] ? mv[m0[r] + t] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool act = k[r] >= 0;
+        const int pk = __shfl_up(k[r], 1, G), pf = __shfl_up(first[r], 1, G), pl = __shfl_up(ml[r], 1, G);
+        if (act && g.gl > 0 && pk >= k[r]) atomicMax(flag, 1);   // columns not ascending
+        const bool head = act && (g.gl == 0 || pf != first[r] || pl != ml[r]);
+        const int contrib = head ? ml[r] : 0;
+        int incl = contrib;
+        for (int off = 1; off < G; off <<= 1) {
+            const int tt = __shfl_up(incl, off, G);
+            if (g.gl >= off) incl += tt;
+        }
+        if (!FILL) {
+            const int tot = __shfl(incl, g.gbase + G - 1, WAVE);
+            if (row0 + r < nr && g.gl == 0) cnt[row0 + r] = tot;
+            continue;
+        }
+        double p[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) p[t] = a[r] * mvv[r][t];
+        // the run ends at the next head (or the row's end)
+        const unsigned long long later = g.bits(head) & ~((2ULL << g.gl) - 1ULL);
+        const int runlen = later ? __ffsll((long long)later) - 1 - g.gl : len[r] - g.gl;
+        double acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = 0.0 + p[t];
+#pragma unroll
+        for (int u = 1; u < 4; ++u) {
+            const int src = g.gbase + min(g.gl + u, G - 1);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const double q = __shfl(p[t], src, WAVE);
+                if (u < runlen) acc[t] = acc[t] + q;
+            }
+        }
+        if (head) {
+            const int o = crp[row0 + r] + incl - contrib;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                if (t < ml[r]) {
+                    cci[o + t] = first[r] + t;
+                    cv[o + t] = acc[t];
+                }
+        }
+    }
+}
+
 // Symbolic pass of C = A B (ADD: C = D + A B) with a lane per entry of a row
 // of A, for rows of A long against those of B (A P in the AMG levels), where
 // the hashed kernel above would take the row's entries one after another.
@@ -1405,6 +1588,11 @@ __global__ __launch_bounds__(TPB) void k_spgemm_lanes_count(int nr, const int* _
 // only the columns of its own block: the part of A_FF that M is formed from
 // (the one-sweep apply never reads the rest).  A null output array skips that
 // output (the count stays to be written).
+// Both kernels issue the index loads of EX_BATCH chunks of G entries, then
+// the flag gathers of all of them, before using any (rows of up to
+// EX_BATCH * G entries in one round of dependent loads).
+constexpr int EX_BATCH = 4;
+
 template <int G>
 __global__ __launch_bounds__(TPB) void k_extract_count_g(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                          const int* __restrict__ isF, const int* __restrict__ lmap,
@@ -1416,10 +1604,19 @@ __global__ __launch_bounds__(TPB) void k_extract_count_g(int n, const int* __res
     if (i < n) {
         const bool rowF = isF[i] != 0;
         const int fi = (rowF && fblk) ? fblk[lmap[i]] : -1;
-        for (int p = rp[i] + g.gl; p < rp[i + 1]; p += G) {
-            const int j = ci[p];
-            if (isF[j]) f += (fi < 0 || fblk[lmap[j]] == fi) ? 1 : 0;
-            else ++c;
+        const int pe = rp[i + 1];
+        for (int p = rp[i] + g.gl; p < pe; p += G * EX_BATCH) {
+            int jj[EX_BATCH], fl[EX_BATCH];
+#pragma unroll
+            for (int u = 0; u < EX_BATCH; ++u) jj[u] = p + u * G < pe ? ci[p + u * G] : -1;
+#pragma unroll
+            for (int u = 0; u < EX_BATCH; ++u) fl[u] = jj[u] >= 0 ? isF[jj[u]] : 0;
+#pragma unroll
+            for (int u = 0; u < EX_BATCH; ++u) {
+                if (jj[u] < 0) continue;
+                if (fl[u]) f += (fi < 0 || fblk[lmap[jj[u]]] == fi) ? 1 : 0;
+                else ++c;
+            }
         }
     }
     f = g.sum(f);
@@ -1459,36 +1656,101 @@ __global__ __launch_bounds__(TPB) void k_extract_fill_g(int n, const int* __rest
             if (ciCC) { oC = rpCC[l]; cC = ciCC; vC = vCC; }
         }
     }
-    for (int base = 0; base < maxlen; base += G) {
-        int q = base + g.gl;
-        bool act = q < len;
-        int j = act ? ci[p0 + q] : 0;
-        bool f = act && isF[j] && (fi < 0 || fblk[lmap[j]] == fi);
-        bool c = act && !isF[j];
-        unsigned long long bf = g.bits(f), bc = g.bits(c);
-        if (f && cF) { int o = oF + g.below(bf); cF[o] = lmap[j]; vF[o] = v[p0 + q]; }
-        if (c && cC) { int o = oC + g.below(bc); cC[o] = lmap[j]; vC[o] = v[p0 + q]; }
-        oF += __popcll(bf);
-        oC += __popcll(bc);
+    for (int base = 0; base < maxlen; base += G * EX_BATCH) {
+        int jj[EX_BATCH], fl[EX_BATCH], lj[EX_BATCH];
+        double vv[EX_BATCH];
+#pragma unroll
+        for (int u = 0; u < EX_BATCH; ++u) {
+            const int q = base + u * G + g.gl;
+            jj[u] = q < len ? ci[p0 + q] : -1;
+            vv[u] = q < len ? v[p0 + q] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < EX_BATCH; ++u) {
+            fl[u] = jj[u] >= 0 ? isF[jj[u]] : 0;
+            lj[u] = jj[u] >= 0 ? lmap[jj[u]] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < EX_BATCH; ++u) {
+            const bool act = jj[u] >= 0;
+            const bool f = act && fl[u] && (fi < 0 || fblk[lj[u]] == fi);
+            const bool c = act && !fl[u];
+            const unsigned long long bf = g.bits(f), bc = g.bits(c);
+            if (f && cF) { int o = oF + g.below(bf); cF[o] = lj[u]; vF[o] = vv[u]; }
+            if (c && cC) { int o = oC + g.below(bc); cC[o] = lj[u]; vC[o] = vv[u]; }
+            oF += __popcll(bf);
+            oC += __popcll(bc);
+        }
     }
 }
 
 // The same extraction straight from the block-CSR input (b = B): G lanes per
-// block row, one block per lane at a time (its B x B values in one contiguous
-// load, the F flags of its B columns together), so that the block values are
-// read once for the B scalar rows.  Entry (r, c) of block (I, J) is entry
+// scalar row i = I B + r, one block of the block row per lane at a time (row r
+// of its B x B values in one contiguous load, the F flags of its B columns
+// together).  The B groups of one block row sit in the same wavefront, so each
+// block's values come from memory once.  Entry (r, c) of block (I, J) is entry
 // (I B + r, J B + c) of the scalar operator unless it is an exact zero off the
 // diagonal (the scalar operator of the input leaves those out).  Lanes hold
 // consecutive blocks, so the per-lane counts scanned in lane order place the
-// entries in column order.
+// entries in column order.  (A group per block row, holding whole blocks, took
+// 114 registers and half the occupancy.)  With vcopy, the values read are also
+// stored there (the library's copy of the input, made in the same pass).
+template <int B>
+struct BsrRowPart {
+    double a[B];    // row r of the block
+    bool cf[B];     // column J B + c is an F-point
+    int cl[B];      // its local index
+    unsigned mf = 0, mc = 0;   // bit c: a kept F entry (in A_FF's block when ffb >= 0) / a kept C entry
+    __device__ void load(int p, int I, int r, int ffb, const int* __restrict__ bci, const double* __restrict__ bv,
+                         const int* __restrict__ isF, const int* __restrict__ lmap, const int* __restrict__ fblk,
+                         double* __restrict__ vcopy) {
+        const int J = bci[p];
+        const double* src = bv + ((long)p * B + r) * B;
+#pragma unroll
+        for (int c = 0; c < B; ++c) a[c] = src[c];
+        if (vcopy)
+#pragma unroll
+            for (int c = 0; c < B; ++c) vcopy[((long)p * B + r) * B + c] = a[c];
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+            cf[c] = isF[J * B + c] != 0;
+            cl[c] = lmap[J * B + c];
+        }
+        int fb[B];
+#pragma unroll
+        for (int c = 0; c < B; ++c) fb[c] = (ffb >= 0 && cf[c]) ? fblk[cl[c]] : -1;
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+            const bool keep = a[c] != 0.0 || (J == I && c == r);
+            const bool inb = ffb < 0 || fb[c] == ffb;
+            mf |= (keep && cf[c] && inb) ? 1u << c : 0u;
+            mc |= (keep && !cf[c]) ? 1u << c : 0u;
+        }
+    }
+};
+
+template <int G>
+__device__ inline int group_scan_incl(int v, int gl) {
+#pragma unroll
+    for (int off = 1; off < G; off <<= 1) {
+        const int t = __shfl_up(v, off, G);
+        if (gl >= off) v += t;
+    }
+    return v;
+}
+
+// The symbolic pass keeps a group per block row (whole blocks per lane, the
+// counts of the B rows together): it holds fewer registers than the numeric
+// pass, and a quarter of the wavefronts of a group per scalar row ran faster.
 template <int B>
 struct BsrBlock {
     double a[B][B];
     int J;
     bool cf[B];     // column J B + c is an F-point
     int cl[B];      // its local index
+    int fb[B];      // its F-relaxation block (with fblk; else -1)
     __device__ void load(int p, const int* __restrict__ bci, const double* __restrict__ bv,
-                         const int* __restrict__ isF, const int* __restrict__ lmap) {
+                         const int* __restrict__ isF, const int* __restrict__ lmap, const int* __restrict__ fblk) {
         J = bci[p];
         const double* src = bv + (long)p * B * B;
 #pragma unroll
@@ -1500,35 +1762,22 @@ struct BsrBlock {
             cf[c] = isF[J * B + c] != 0;
             cl[c] = lmap[J * B + c];
         }
+#pragma unroll
+        for (int c = 0; c < B; ++c) fb[c] = (fblk && cf[c]) ? fblk[cl[c]] : -1;
+    }
+    // kept F entries of row r (in A_FF's block when ffb >= 0) and kept C entries
+    __device__ void row_counts(int I, int r, int ffb, int& nf, int& nc) const {
+        nf = 0;
+        nc = 0;
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+            const bool keep = a[r][c] != 0.0 || (J == I && c == r);
+            const bool inb = ffb < 0 || fb[c] == ffb;
+            nf += (keep && cf[c] && inb) ? 1 : 0;
+            nc += (keep && !cf[c]) ? 1 : 0;
+        }
     }
 };
-
-// row r of this lane's block: kept F (in A_FF's block when ffb >= 0) and C entries
-template <int B>
-__device__ inline void bsr_row_counts(const BsrBlock<B>& k, int I, int r, int ffb, const int* __restrict__ fblk,
-                                      int& nf, int& nc) {
-    // both counters updated by selects: a branch choosing which one to bump
-    // had the compiler index a two-element array in scratch memory
-    nf = 0;
-    nc = 0;
-#pragma unroll
-    for (int c = 0; c < B; ++c) {
-        const bool keep = k.a[r][c] != 0.0 || (k.J == I && c == r);
-        const bool inb = ffb < 0 || (k.cf[c] && fblk[k.cl[c]] == ffb);
-        nf += (keep && k.cf[c] && inb) ? 1 : 0;
-        nc += (keep && !k.cf[c]) ? 1 : 0;
-    }
-}
-
-template <int G>
-__device__ inline int group_scan_incl(int v, int gl) {
-#pragma unroll
-    for (int off = 1; off < G; off <<= 1) {
-        const int t = __shfl_up(v, off, G);
-        if (gl >= off) v += t;
-    }
-    return v;
-}
 
 template <int G, int B>
 __global__ __launch_bounds__(TPB) void k_bsr_extract_count_g(int nbr, const int* __restrict__ brp,
@@ -1548,11 +1797,11 @@ __global__ __launch_bounds__(TPB) void k_bsr_extract_count_g(int nbr, const int*
     if (valid) {
         BsrBlock<B> k;
         for (int p = brp[I] + g.gl; p < brp[I + 1]; p += G) {
-            k.load(p, bci, bv, isF, lmap);
+            k.load(p, bci, bv, isF, lmap, fblk);
 #pragma unroll
             for (int r = 0; r < B; ++r) {
                 int f, c;
-                bsr_row_counts<B>(k, I, r, ffb[r], fblk, f, c);
+                k.row_counts(I, r, ffb[r], f, c);
                 nf[r] += f;
                 nc[r] += c;
             }
@@ -1581,60 +1830,47 @@ __global__ __launch_bounds__(TPB) void k_bsr_extract_fill_g(int nbr, const int* 
                                                             const int* __restrict__ rpFF, int* ciFF, double* vFF,
                                                             const int* __restrict__ rpFC, int* ciFC, double* vFC,
                                                             const int* __restrict__ rpCF, int* ciCF, double* vCF,
-                                                            const int* __restrict__ rpCC, int* ciCC, double* vCC) {
+                                                            const int* __restrict__ rpCC, int* ciCC, double* vCC,
+                                                            double* __restrict__ vcopy) {
     Grp<G> g;
-    const int I = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
-    const bool valid = I < nbr;
+    const int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
+    const bool valid = i < nbr * B;
+    const int I = i / B, r = i - I * B;
     const int p0 = valid ? brp[I] : 0, nb = valid ? brp[I + 1] - p0 : 0;
-    int maxnb = nb;
-    for (int off = WAVE / 2; off > 0; off >>= 1) maxnb = max(maxnb, __shfl_xor(maxnb, off, WAVE));
-    int ffb[B], oF[B], oC[B];
-    int* cF[B];
-    int* cC[B];
-    double* vF[B];
-    double* vC[B];
-#pragma unroll
-    for (int r = 0; r < B; ++r) {
-        ffb[r] = -1; oF[r] = oC[r] = 0;
-        cF[r] = cC[r] = nullptr; vF[r] = vC[r] = nullptr;
-        if (!valid) continue;
-        const int i = I * B + r, l = lmap[i];
+    const int maxnb = wave_max_int(nb);
+    int oF = 0, oC = 0, ffb = -1;
+    int* cF = nullptr;
+    int* cC = nullptr;
+    double* vF = nullptr;
+    double* vC = nullptr;
+    if (valid) {
+        const int l = lmap[i];
         if (isF[i]) {
-            if (ciFF) { oF[r] = rpFF[l]; cF[r] = ciFF; vF[r] = vFF; }
-            if (ciFC) { oC[r] = rpFC[l]; cC[r] = ciFC; vC[r] = vFC; }
-            if (fblk) ffb[r] = fblk[l];
+            if (ciFF) { oF = rpFF[l]; cF = ciFF; vF = vFF; }
+            if (ciFC) { oC = rpFC[l]; cC = ciFC; vC = vFC; }
+            if (fblk) ffb = fblk[l];
         } else {
-            if (ciCF) { oF[r] = rpCF[l]; cF[r] = ciCF; vF[r] = vCF; }
-            if (ciCC) { oC[r] = rpCC[l]; cC[r] = ciCC; vC[r] = vCC; }
+            if (ciCF) { oF = rpCF[l]; cF = ciCF; vF = vCF; }
+            if (ciCC) { oC = rpCC[l]; cC = ciCC; vC = vCC; }
         }
     }
     for (int base = 0; base < maxnb; base += G) {
         const int q = base + g.gl;
-        const bool act = q < nb;
-        BsrBlock<B> k;
-        if (act) k.load(p0 + q, bci, bv, isF, lmap);
+        BsrRowPart<B> k;
+        if (q < nb) k.load(p0 + q, I, r, ffb, bci, bv, isF, lmap, fblk, vcopy);
+        const int f = __popc(k.mf), c = __popc(k.mc);
+        const int fi = group_scan_incl<G>(f, g.gl), ci = group_scan_incl<G>(c, g.gl);
+        int wf = oF + fi - f, wc = oC + ci - c;
 #pragma unroll
-        for (int r = 0; r < B; ++r) {
-            int f = 0, c = 0;
-            if (act) bsr_row_counts<B>(k, I, r, ffb[r], fblk, f, c);
-            const int fi = group_scan_incl<G>(f, g.gl), ci = group_scan_incl<G>(c, g.gl);
-            int wf = oF[r] + fi - f, wc = oC[r] + ci - c;
-            if (act) {
-#pragma unroll
-                for (int cc = 0; cc < B; ++cc) {
-                    const double a = k.a[r][cc];
-                    const bool keep = a != 0.0 || (k.J == I && cc == r);
-                    const bool inb = ffb[r] < 0 || (k.cf[cc] && fblk[k.cl[cc]] == ffb[r]);
-                    const bool tf = keep && k.cf[cc] && inb, tc = keep && !k.cf[cc];
-                    if (tf && cF[r]) { cF[r][wf] = k.cl[cc]; vF[r][wf] = a; }
-                    if (tc && cC[r]) { cC[r][wc] = k.cl[cc]; vC[r][wc] = a; }
-                    wf += tf ? 1 : 0;
-                    wc += tc ? 1 : 0;
-                }
-            }
-            oF[r] += __shfl(fi, g.gbase + G - 1, WAVE);
-            oC[r] += __shfl(ci, g.gbase + G - 1, WAVE);
+        for (int cc = 0; cc < B; ++cc) {
+            const bool tf = (k.mf >> cc) & 1u, tc = (k.mc >> cc) & 1u;
+            if (tf && cF) { cF[wf] = k.cl[cc]; vF[wf] = k.a[cc]; }
+            if (tc && cC) { cC[wc] = k.cl[cc]; vC[wc] = k.a[cc]; }
+            wf += tf ? 1 : 0;
+            wc += tc ? 1 : 0;
         }
+        oF += __shfl(fi, g.gbase + G - 1, WAVE);
+        oC += __shfl(ci, g.gbase + G - 1, WAVE);
     }
 }
 
@@ -3019,12 +3255,14 @@ void bsr_extract_count(int b, int nbr, long nnzb, const int* brp, const int* bci
 }
 
 void bsr_extract_fill(int b, int nbr, long nnzb, const int* brp, const int* bci, const double* bv, const int* isF,
-                      const int* lmap, const int* fblk, DCsr* FF, DCsr* FC, DCsr* CF, DCsr* CC, hipStream_t s) {
+                      const int* lmap, const int* fblk, DCsr* FF, DCsr* FC, DCsr* CF, DCsr* CC, double* vcopy,
+                      hipStream_t s) {
     if (nbr <= 0) return;
     const int G = bsr_group(nbr, nnzb);
-    MGR_DISPATCH_B(b, MGR_DISPATCH_G4(G, (k_bsr_extract_fill_g<GG, BB><<<grid_for(nbr, GG), TPB, 0, s>>>(
+    MGR_DISPATCH_B(b, MGR_DISPATCH_G4(G, (k_bsr_extract_fill_g<GG, BB><<<grid_for((long)nbr * BB, GG), TPB, 0, s>>>(
                                              nbr, brp, bci, bv, isF, lmap, fblk, orp(FF), oci(FF), ov(FF), orp(FC),
-                                             oci(FC), ov(FC), orp(CF), oci(CF), ov(CF), orp(CC), oci(CC), ov(CC)))));
+                                             oci(FC), ov(FC), orp(CF), oci(CF), ov(CF), orp(CC), oci(CC), ov(CC),
+                                             vcopy))));
     MGR_LAUNCH_CHECK();
 }
 
@@ -3104,22 +3342,28 @@ static bool spgemm_dense_ok(const DCsr& A, const DCsr& B) {
 
 // Hashed rows with tables of cap slots (cap >= 32, a power of two <= 512);
 // with D, C = D + A B.
+// lanes per row of A: enough for the rows of B, and for TPB / G tables of cap
+// slots to take at most 64 KB of LDS
+static int hash_group(const DCsr& B, int cap) {
+    int gb = 4;
+    while (gb < B.max_row && gb < 32) gb <<= 1;
+    int gl = (int)((long)cap * 12 * TPB / 65536);
+    int G = gb;
+    while (G < gl) G <<= 1;
+    return G > 32 ? 32 : G;
+}
+
 template <bool FILL, bool ADD>
 static void spgemm_hash_launch(const DCsr& A, const DCsr& B, const DCsr* D, int cap, const int* crp, int* cci,
-                               double* cv, int* cnt, int* flag, hipStream_t s) {
+                               double* cv, int* cnt, int* flag, hipStream_t s, int lo = -1, int hi = INT_MAX) {
     const int* drp = ADD ? D->rp.p : nullptr;
     const int* dci = ADD ? D->ci.p : nullptr;
     const double* dvv = ADD ? D->v.p : nullptr;
-    int gb = 4;
-    while (gb < B.max_row && gb < 32) gb <<= 1;
-    int gl = (int)((long)cap * 12 * TPB / 65536);   // LDS: TPB / G tables of cap slots
-    int G = gb;
-    while (G < gl) G <<= 1;
-    if (G > 32) G = 32;
+    const int G = hash_group(B, cap);
 #define MGR_HASH(GG, CC)                                                                                          \
     k_spgemm_hash<GG, CC, FILL, ADD><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p,     \
                                                                        B.ci.p, B.v.p, drp, dci, dvv, crp, cci, cv, \
-                                                                       cnt, flag)
+                                                                       cnt, flag, lo, hi)
     switch (cap) {
         case 32: if (G <= 4) MGR_HASH(4, 32); else if (G == 8) MGR_HASH(8, 32); else if (G == 16) MGR_HASH(16, 32); else MGR_HASH(32, 32); break;
         case 64: if (G <= 4) MGR_HASH(4, 64); else if (G == 8) MGR_HASH(8, 64); else if (G == 16) MGR_HASH(16, 64); else MGR_HASH(32, 64); break;
@@ -3157,6 +3401,55 @@ static void spgemm_lanes_count(const DCsr& A, const DCsr& B, const DCsr* D, int 
     MGR_LAUNCH_CHECK();
 }
 
+bool bdiag_left_ok(const DCsr& M, const DCsr& B) {
+    return M.max_row >= 0 && M.max_row <= 4 && B.max_row >= 0 && 4 * B.max_row <= BDL_STAGE;
+}
+// rows of A of 8 entries or more on average: a mostly empty A (A_CF of a
+// level whose few F-points couple to few C-points) keeps the hashed product,
+// whose small lane groups skip empty rows at less cost
+bool bdiag_right_ok(const DCsr& A, const DCsr& M) {
+    return A.max_row >= 0 && A.max_row <= 32 && M.max_row >= 0 && M.max_row <= 4 && A.nnz >= 8L * A.nr;
+}
+
+void bdiag_left_count(int nb, const int* bstart, const DCsr& B, int* cnt, int* flag, hipStream_t s) {
+    if (nb <= 0) return;
+    k_bdiag_left_count<16><<<grid_for(nb, 16), TPB, 0, s>>>(nb, bstart, B.rp.p, B.ci.p, cnt, flag);
+    MGR_LAUNCH_CHECK();
+}
+void bdiag_right_count(const DCsr& A, const DCsr& M, int* cnt, int* flag, hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_bdiag_right<false><<<grid_for((A.nr + BDR_ROWS - 1) / BDR_ROWS, 32), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, M.rp.p, M.ci.p, M.v.p,
+                                                            nullptr, nullptr, nullptr, cnt, flag);
+    MGR_LAUNCH_CHECK();
+}
+void bdiag_right_fill(const DCsr& A, const DCsr& M, DCsr& C, int* flag, hipStream_t s) {
+    if (A.nr <= 0) return;
+    k_bdiag_right<true><<<grid_for((A.nr + BDR_ROWS - 1) / BDR_ROWS, 32), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, M.rp.p, M.ci.p, M.v.p,
+                                                           C.rp.p, C.ci.p, C.v.p, nullptr, flag);
+    MGR_LAUNCH_CHECK();
+}
+
+// Numeric hashed pass.  Where the tables of a workgroup take 40 KB of LDS or
+// more, the LDS bounds the rows in flight per CU; on a large product whose
+// average row is at most a sixth of cap (the longest rows of a Galerkin
+// product sit next to wells or boundaries), the rows of at most a quarter of
+// cap entries then take tables of half the size in a first launch, the rest
+// a second one (measured: the level-0 A P of the pressure AMG, 864 -> 565 +
+// 99 us; on small levels, with smaller tables or longer average rows the
+// second launch costs more than it saves).
+template <bool ADD>
+static void spgemm_fill_split(const DCsr& A, const DCsr& B, const DCsr* D, DCsr& C, int cap, int* flag,
+                              hipStream_t s) {
+    const long lds = (long)(TPB / hash_group(B, cap)) * cap * 12;
+    const bool short_rows = C.nr > 0 && 6 * C.nnz <= (long)C.nr * cap;   // average row <= cap / 6
+    if (cap >= 64 && lds >= 40960 && A.nr >= 262144 && short_rows) {
+        spgemm_hash_launch<true, ADD>(A, B, D, cap / 2, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s, -1, cap / 4);
+        spgemm_hash_launch<true, ADD>(A, B, D, cap, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s, cap / 4, INT_MAX);
+    } else {
+        spgemm_hash_launch<true, ADD>(A, B, D, cap, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s);
+    }
+}
+
 static int pow2_at_least(long v, int lo) {
     int c = lo;
     while (c < v) c <<= 1;
@@ -3187,7 +3480,7 @@ void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, int* flag, 
     // output rows (known from the symbolic pass) fit a table of at most 512 slots
     if (!spgemm_dense_ok(A, B) && A.nr > 0 && C.max_row >= 0 && C.max_row <= 256 && B.max_row >= 0) {
         const int cap = pow2_at_least(2L * C.max_row, 32);
-        spgemm_hash_launch<true, false>(A, B, nullptr, cap, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s);
+        spgemm_fill_split<false>(A, B, nullptr, C, cap, flag, s);
         return;
     }
     spgemm_launch<true>(A, B, max_row, C.rp.p, C.ci.p, C.v.p, nullptr, nullptr, s);
@@ -3198,11 +3491,12 @@ bool spgemm_add_fusable(const DCsr& A, const DCsr& B, const DCsr& D) {
            (long)A.max_row * B.max_row + D.max_row <= 256;
 }
 
-void spgemm_add_count(const DCsr& A, const DCsr& B, const DCsr& D, int* cnt, int* flag, hipStream_t s) {
+void spgemm_add_count(const DCsr& A, const DCsr& B, const DCsr& D, int* cnt, int* flag, hipStream_t s, bool loose) {
     if (!spgemm_add_fusable(A, B, D)) throw Error(-1, "spgemm_add: rows may exceed 256 entries");
     if (A.nr <= 0) return;
     const long bound = (long)A.max_row * B.max_row + D.max_row;
-    const int cap = pow2_at_least(bound, 32);
+    int cap = pow2_at_least(bound, 32);
+    if (loose && cap > SPGEMM_ADD_LOOSE_CAP) cap = SPGEMM_ADD_LOOSE_CAP;
     if (lanes_ok(A, B))
         spgemm_lanes_count<true>(A, B, &D, cap, cnt, flag, s);
     else
@@ -3212,7 +3506,7 @@ void spgemm_add_count(const DCsr& A, const DCsr& B, const DCsr& D, int* cnt, int
 void spgemm_add_fill(const DCsr& A, const DCsr& B, const DCsr& D, DCsr& C, int* flag, hipStream_t s) {
     if (A.nr <= 0) return;
     const int cap = pow2_at_least(2L * C.max_row, 32);
-    spgemm_hash_launch<true, true>(A, B, &D, cap, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s);
+    spgemm_fill_split<true>(A, B, &D, C, cap, flag, s);
 }
 
 static int add_group(const DCsr& A, const DCsr& B) {

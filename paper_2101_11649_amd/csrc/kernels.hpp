@@ -47,8 +47,10 @@ void extract_fill(const DCsr& A, const int* isF, const int* lmap, const int* fbl
                   DCsr* CC, hipStream_t s);
 void bsr_extract_count(int b, int nbr, long nnzb, const int* brp, const int* bci, const double* bv, const int* isF,
                        const int* lmap, const int* fblk, int* cFF, int* cFC, int* cCF, int* cCC, hipStream_t s);
+// With vcopy (nnzb b^2 values), the block values are also copied there.
 void bsr_extract_fill(int b, int nbr, long nnzb, const int* brp, const int* bci, const double* bv, const int* isF,
-                      const int* lmap, const int* fblk, DCsr* FF, DCsr* FC, DCsr* CF, DCsr* CC, hipStream_t s);
+                      const int* lmap, const int* fblk, DCsr* FF, DCsr* FC, DCsr* CF, DCsr* CC, double* vcopy,
+                      hipStream_t s);
 
 // F-relaxation operator: blocks = runs of consecutive F-points with equal block id
 // (Jacobi: every point its own block).  bstart gets nb+1 entries.
@@ -74,8 +76,25 @@ void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, int* flag, 
 // every row of C is bounded by maxrow(A) maxrow(B) + maxrow(D) <= 256; the
 // values are those of the product followed by a separate sparse add.
 bool spgemm_add_fusable(const DCsr& A, const DCsr& B, const DCsr& D);
-void spgemm_add_count(const DCsr& A, const DCsr& B, const DCsr& D, int* cnt, int* flag, hipStream_t s);
+// With `loose`, the rows are counted in tables of at most SPGEMM_ADD_LOOSE_CAP
+// slots (the bound maxrow(A) maxrow(B) + maxrow(D) is far above the rows of
+// a Galerkin product of stencil operators); a full table sets *flag to 2, and
+// the count must then be made again without `loose`.
+constexpr int SPGEMM_ADD_LOOSE_CAP = 64;
+void spgemm_add_count(const DCsr& A, const DCsr& B, const DCsr& D, int* cnt, int* flag, hipStream_t s,
+                      bool loose = false);
 void spgemm_add_fill(const DCsr& A, const DCsr& B, const DCsr& D, DCsr& C, int* flag, hipStream_t s);
+// Products with the block-diagonal F-relaxation operator M (blocks of at most
+// four rows over [bstart[t], bstart[t+1]), each row storing its block's
+// columns; a failed larger block one diagonal entry per row), with the
+// pattern (and values) of the general product.  Left: the row counts of M B
+// (B's rows of at most 16 entries).  Right: C = A M (A's rows of at most 32
+// entries, columns ascending).  A violated bound sets *flag to 1.
+bool bdiag_left_ok(const DCsr& M, const DCsr& B);
+bool bdiag_right_ok(const DCsr& A, const DCsr& M);
+void bdiag_left_count(int nb, const int* bstart, const DCsr& B, int* cnt, int* flag, hipStream_t s);
+void bdiag_right_count(const DCsr& A, const DCsr& M, int* cnt, int* flag, hipStream_t s);
+void bdiag_right_fill(const DCsr& A, const DCsr& M, DCsr& C, int* flag, hipStream_t s);
 void add_count(const DCsr& A, const DCsr& B, int* cnt, hipStream_t s);
 void add_fill(const DCsr& A, const DCsr& B, DCsr& C, hipStream_t s);
 void negate(double* v, long n, hipStream_t s);

@@ -115,6 +115,7 @@ struct Spgemm {
     const DCsr* B = nullptr;
     const DCsr* D = nullptr;  // C = D + A B when set
     DCsr* C = nullptr;
+    int bdiag = 0;            // symbolic pass by the block kernels: 1 for M B, 2 for A M
     DArr<int> cnt;
     long long* lr = nullptr;
     Pend pend;
@@ -132,14 +133,16 @@ static void spgemm_begin(Spgemm& j, const DCsr& A, const DCsr& B, DCsr& C, Slots
     j.pend = csr_begin(C, A.nr, B.nc, j.cnt.p, S);
 }
 
-// A row overflowed its hash table in the symbolic pass: count again with the
-// merging kernels and size C from a read of its own (not through the slots,
-// whose other pending values the caller has yet to use).
+// A row overflowed its hash table in the symbolic pass: count again with
+// tables sized for the bound (or the merging kernels) and size C from a read
+// of its own (not through the slots, whose other pending values the caller
+// has yet to use).
 static void spgemm_recount(Spgemm& j, hipStream_t s) {
     DCsr& C = *j.C;
     DArr<long long> t(3, s);
     fill_ll(t.p, 0, 3, s);
-    spgemm_count(*j.A, *j.B, j.A->max_row, j.cnt.p, reinterpret_cast<int*>(t.p), s, false);
+    if (j.D) spgemm_add_count(*j.A, *j.B, *j.D, j.cnt.p, reinterpret_cast<int*>(t.p), s, false);
+    else spgemm_count(*j.A, *j.B, j.A->max_row, j.cnt.p, reinterpret_cast<int*>(t.p), s, false);
     C = DCsr();
     C.nr = j.A->nr;
     C.nc = j.B->nc;
@@ -165,13 +168,37 @@ static void spgemm_add_begin(Spgemm& j, const DCsr& A, const DCsr& B, const DCsr
     j.C = &C;
     j.cnt.alloc((size_t)A.nr + 1, S.s);
     j.lr = S.take(1);
-    spgemm_add_count(A, B, D, j.cnt.p, reinterpret_cast<int*>(j.lr), S.s);
+    spgemm_add_count(A, B, D, j.cnt.p, reinterpret_cast<int*>(j.lr), S.s, true);
+    j.pend = csr_begin(C, A.nr, B.nc, j.cnt.p, S);
+}
+
+// The transfer products with the block-diagonal M (side 1: M A_FC, counted by
+// blocks and filled by the hashed kernel; side 2: A_CF M, by rows and runs).
+static void bdiag_begin(Spgemm& j, int side, const DCsr& A, const DCsr& B, DCsr& C, int nb, const int* bstart,
+                        Slots& S) {
+    if (A.nc != B.nr) throw Error(MGR_ERR_ARG, "spgemm: inner dimensions differ");
+    j.A = &A;
+    j.B = &B;
+    j.C = &C;
+    j.bdiag = side;
+    j.cnt.alloc((size_t)A.nr + 1, S.s);
+    j.lr = S.take(1);
+    if (side == 1) bdiag_left_count(nb, bstart, B, j.cnt.p, reinterpret_cast<int*>(j.lr), S.s);
+    else bdiag_right_count(A, B, j.cnt.p, reinterpret_cast<int*>(j.lr), S.s);
     j.pend = csr_begin(C, A.nr, B.nc, j.cnt.p, S);
 }
 
 static void spgemm_finish(Spgemm& j, Slots& S) {
     const long long v = S.val(j.lr);
-    if (v == 2 && !j.D) {
+    if (j.bdiag) {
+        if (v != 0) throw Error(MGR_ERR_ARG, "internal: block-diagonal product outside its row bounds");
+        csr_finish(j.pend, S);
+        if (j.bdiag == 1) spgemm_fill(*j.A, *j.B, j.A->max_row, *j.C, S.flag(), S.s);
+        else bdiag_right_fill(*j.A, *j.B, *j.C, S.flag(), S.s);
+        j.cnt.reset();
+        return;
+    }
+    if (v == 2) {
         spgemm_recount(j, S.s);
     } else {
         if (v != 0) throw Error(MGR_ERR_ARG, "internal: spgemm row longer than its recorded length");
@@ -1124,6 +1151,9 @@ struct Ctx {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool aux_pending = false;
     const double* Avin = nullptr;
+    // the copy of the input values is made by the first block extraction (a
+    // block input with MGR levels) instead of a separate copy
+    bool copy_in_extract = false;
     ~Ctx() {
         if (aux) {
             (void)hipStreamSynchronize(aux);
@@ -1168,6 +1198,7 @@ struct AuxScope {
             (void)hipStreamWaitEvent(c.s, c.ev_join, 0);
         }
         c.Avin = nullptr;
+        c.copy_in_extract = false;
     }
 };
 
@@ -1195,8 +1226,18 @@ static void level_extract_count(Ctx& c, const DCsr* A, const int* isF, const int
 }
 static void level_extract_fill(Ctx& c, const DCsr* A, const int* isF, const int* lmap, const int* fblk, DCsr* FF,
                                DCsr* FC, DCsr* CF, DCsr* CC) {
-    if (A) extract_fill(*A, isF, lmap, fblk, FF, FC, CF, CC, c.s);
-    else bsr_extract_fill(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, in_values(c), isF, lmap, fblk, FF, FC, CF, CC, c.s);
+    if (A) {
+        extract_fill(*A, isF, lmap, fblk, FF, FC, CF, CC, c.s);
+        return;
+    }
+    // the first extraction of a setup also makes the library's copy of the
+    // input values (every block is read here anyway); later steps read it
+    double* vcopy = c.copy_in_extract ? c.Av.p : nullptr;
+    bsr_extract_fill(c.b, c.nbr, c.nnzb, c.Arp.p, c.Aci.p, in_values(c), isF, lmap, fblk, FF, FC, CF, CC, vcopy, c.s);
+    if (vcopy) {
+        c.copy_in_extract = false;
+        c.Avin = nullptr;
+    }
 }
 
 // The whole of A_FF for a level that kept only its F-relaxation blocks (for
@@ -1320,8 +1361,11 @@ static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr* A, const int* field
     }
     // transfer operators and the Petrov-Galerkin coarse operator R A P
     Spgemm jP, jW;
-    spgemm_begin(jP, l.M, l.AFC, l.PF, S);
-    spgemm_begin(jW, l.ACF, l.M, l.W, S);
+    const bool bdl = bdiag_left_ok(l.M, l.AFC), bdr = bdiag_right_ok(l.ACF, l.M);
+    if (bdl) bdiag_begin(jP, 1, l.M, l.AFC, l.PF, (int)nb, bstart.p, S);
+    else spgemm_begin(jP, l.M, l.AFC, l.PF, S);
+    if (bdr) bdiag_begin(jW, 2, l.ACF, l.M, l.W, 0, nullptr, S);
+    else spgemm_begin(jW, l.ACF, l.M, l.W, S);
     S.sync("MGR transfer operators");
     spgemm_finish(jP, S);
     negate(l.PF.v.p, l.PF.nnz, s);
@@ -2045,6 +2089,20 @@ static void expand_input(Ctx& c) {
 // first level) and for an AMG without MGR levels; the first MGR level of a
 // block input is extracted from the blocks directly, and then only the label
 // histogram (which sizes the levels) has to reach the host.
+// The library's copy of the input values (c.Av): a block input with MGR
+// levels gets it from its first block extraction (which reads every block);
+// otherwise a copy on the auxiliary stream.  Until then setup steps read the
+// caller's array.
+static void copy_input_values(Ctx& c, const double* values, int nlevels) {
+    c.Avin = values;
+    if (c.b > 1 && nlevels > 0) {
+        c.copy_in_extract = true;
+        return;
+    }
+    aux_fork(c);
+    MGR_HIP(hipMemcpyAsync(c.Av.p, values, sizeof(double) * c.nnzb * c.b * c.b, hipMemcpyDeviceToDevice, c.aux));
+}
+
 static void prepare_input(Ctx& c, int nlevels) {
     if (c.b == 1 || nlevels == 0) {
         expand_input(c);
@@ -2086,12 +2144,11 @@ static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nle
     c.Aci.alloc((size_t)c.nnzb, s);
     c.Av.alloc((size_t)c.nnzb * bb, s);
     MGR_HIP(hipMemcpyAsync(c.Aci.p, A->col_idx, sizeof(int) * c.nnzb, hipMemcpyDeviceToDevice, s));
-    // the values (the bulk of the input) are copied on the auxiliary stream
-    // while the setup reads the caller's array
+    // the values (the bulk of the input) are copied by the first block
+    // extraction, or else on the auxiliary stream, while the setup reads the
+    // caller's array
     AuxScope aux_scope{c};
-    aux_fork(c);
-    MGR_HIP(hipMemcpyAsync(c.Av.p, A->values, sizeof(double) * c.nnzb * bb, hipMemcpyDeviceToDevice, c.aux));
-    c.Avin = A->values;
+    copy_input_values(c, A->values, nlevels);
     if (c.nnzb * bb > INT_MAX) throw Error(MGR_ERR_UNSUPPORTED, "more than 2^31 scalar entries");
     c.field0.alloc((size_t)c.n, s);
     MGR_HIP(hipMemcpyAsync(c.field0.p, field, sizeof(int) * c.n, hipMemcpyDeviceToDevice, s));
@@ -2183,11 +2240,8 @@ static void update_values(Ctx& c, const double* values, int flags) {
     if (!values) throw Error(MGR_ERR_ARG, "null values");
     if (flags & ~MGR_REUSE_KEEP_FRELAX_AMG) throw Error(MGR_ERR_ARG, "unknown reuse flags");
     c.ready = false;
-    long bb = (long)c.b * c.b;
     AuxScope aux_scope{c};
-    aux_fork(c);
-    MGR_HIP(hipMemcpyAsync(c.Av.p, values, sizeof(double) * c.nnzb * bb, hipMemcpyDeviceToDevice, c.aux));
-    c.Avin = values;
+    copy_input_values(c, values, (int)c.lvl.size());
     prepare_input(c, (int)c.lvl.size());
     c.A0t = DCsr();
     c.ATrp.reset(); c.ATci.reset(); c.ATv.reset();
