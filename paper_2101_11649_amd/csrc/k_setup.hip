@@ -1184,7 +1184,7 @@ __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restri
                                                      const int* __restrict__ dci, const double* __restrict__ dv,
                                                      const int* __restrict__ crp, int* __restrict__ cci,
                                                      double* __restrict__ cv, int* __restrict__ cnt,
-                                                     int* __restrict__ flag, int lo, int hi) {
+                                                     int* __restrict__ flag, int lo, int hi, double sgn) {
     constexpr int NG = TPB / G;
     constexpr int PER = CAP / G;
     __shared__ int keys[NG][CAP];
@@ -1335,7 +1335,7 @@ __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restri
             int rank = 0;
             for (int f = 0; f < L; ++f) rank += (K[f] < key) ? 1 : 0;
             cci[o + rank] = key;
-            cv[o + rank] = Vs[e];
+            cv[o + rank] = sgn * Vs[e];
         }
     }
 }
@@ -2897,9 +2897,13 @@ __global__ void k_pj_count(int n, const int* __restrict__ isF, const int* __rest
     len[g] = (yrp[k + 1] - yrp[k]) + (mrp[k + 1] - mrp[k]);
 }
 
-// Lane-group versions of the two fills above.  In a row of R the unit entry
-// goes before the first column above g, so entry p of X lands at
-// (p - row start) + (col > g) and the unit after the columns below g.
+// Lane-group versions of the two fills above, each lane taking FILL_BATCH
+// entries of its row with every load of the batch issued before any is used
+// (a row's loads form a chain of three or four dependent steps).  In a row of
+// R the unit entry goes before the first column above g, so entry p of X lands
+// at (p - row start) + (col > g) and the unit after the columns below g.
+constexpr int FILL_BATCH = 4;
+
 template <int G>
 __global__ __launch_bounds__(TPB) void k_rj_fill_g(int nC, const int* __restrict__ xrp, const int* __restrict__ xci,
                                                    const double* __restrict__ xv, double scale,
@@ -2918,17 +2922,28 @@ __global__ __launch_bounds__(TPB) void k_rj_fill_g(int nC, const int* __restrict
     }
     const int wl = wave_max_int(len);
     int nless = 0;
-    for (int base = 0; base < wl; base += G) {
-        const int q = base + g.gl;
-        const bool act = q < len;
-        int col = 0;
-        if (act) {
-            col = fmap[xci[p0 + q]];
-            int pos = o + q + (col > gc ? 1 : 0);
-            rci[pos] = col;
-            rv[pos] = scale * xv[p0 + q];
+    for (int base = 0; base < wl; base += G * FILL_BATCH) {
+        int col[FILL_BATCH];
+        double val[FILL_BATCH];
+#pragma unroll
+        for (int u = 0; u < FILL_BATCH; ++u) {
+            const int q = base + u * G + g.gl;
+            col[u] = q < len ? xci[p0 + q] : -1;
+            val[u] = q < len ? xv[p0 + q] : 0.0;
         }
-        nless += __popcll(g.bits(act && col < gc));
+#pragma unroll
+        for (int u = 0; u < FILL_BATCH; ++u) col[u] = col[u] >= 0 ? fmap[col[u]] : -1;
+#pragma unroll
+        for (int u = 0; u < FILL_BATCH; ++u) {
+            const int q = base + u * G + g.gl;
+            const bool act = q < len;
+            if (act) {
+                const int pos = o + q + (col[u] > gc ? 1 : 0);
+                rci[pos] = col[u];
+                rv[pos] = scale * val[u];
+            }
+            nless += __popcll(g.bits(act && col[u] < gc));
+        }
     }
     if (valid && g.gl == 0) {
         rci[o + nless] = gc;
@@ -2954,15 +2969,32 @@ __global__ __launch_bounds__(TPB) void k_pj_fill_g(int n, int nC, const int* __r
         if (g.gl == 0) { pci[o] = k; pv[o] = 1.0; }
         return;
     }
+    // the row is [Y row k | M row k]: entry q < ylen from Y, the rest from M
     const int y0 = yrp[k], ylen = yrp[k + 1] - y0;
-    for (int q = g.gl; q < ylen; q += G) {
-        pci[o + q] = yci[y0 + q];
-        pv[o + q] = yscale * yv[y0 + q];
-    }
-    const int m0 = mrp[k], mlen = mrp[k + 1] - m0;
-    for (int q = g.gl; q < mlen; q += G) {
-        pci[o + ylen + q] = nC + fmap[mci[m0 + q]];
-        pv[o + ylen + q] = mscale * mv[m0 + q];
+    const int m0 = mrp[k], len = ylen + mrp[k + 1] - m0;
+    for (int base = 0; base < len; base += G * FILL_BATCH) {
+        int col[FILL_BATCH];
+        double val[FILL_BATCH];
+#pragma unroll
+        for (int u = 0; u < FILL_BATCH; ++u) {
+            const int q = base + u * G + g.gl;
+            const bool iny = q < ylen, inm = !iny && q < len;
+            col[u] = iny ? yci[y0 + q] : (inm ? mci[m0 + q - ylen] : -1);
+            val[u] = iny ? yscale * yv[y0 + q] : (inm ? mscale * mv[m0 + q - ylen] : 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < FILL_BATCH; ++u) {
+            const int q = base + u * G + g.gl;
+            if (q >= ylen && q < len) col[u] = nC + fmap[col[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < FILL_BATCH; ++u) {
+            const int q = base + u * G + g.gl;
+            if (q < len) {
+                pci[o + q] = col[u];
+                pv[o + q] = val[u];
+            }
+        }
     }
 }
 
@@ -3355,7 +3387,8 @@ static int hash_group(const DCsr& B, int cap) {
 
 template <bool FILL, bool ADD>
 static void spgemm_hash_launch(const DCsr& A, const DCsr& B, const DCsr* D, int cap, const int* crp, int* cci,
-                               double* cv, int* cnt, int* flag, hipStream_t s, int lo = -1, int hi = INT_MAX) {
+                               double* cv, int* cnt, int* flag, hipStream_t s, int lo = -1, int hi = INT_MAX,
+                               double sgn = 1.0) {
     const int* drp = ADD ? D->rp.p : nullptr;
     const int* dci = ADD ? D->ci.p : nullptr;
     const double* dvv = ADD ? D->v.p : nullptr;
@@ -3363,7 +3396,7 @@ static void spgemm_hash_launch(const DCsr& A, const DCsr& B, const DCsr* D, int 
 #define MGR_HASH(GG, CC)                                                                                          \
     k_spgemm_hash<GG, CC, FILL, ADD><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p,     \
                                                                        B.ci.p, B.v.p, drp, dci, dvv, crp, cci, cv, \
-                                                                       cnt, flag, lo, hi)
+                                                                       cnt, flag, lo, hi, sgn)
     switch (cap) {
         case 32: if (G <= 4) MGR_HASH(4, 32); else if (G == 8) MGR_HASH(8, 32); else if (G == 16) MGR_HASH(16, 32); else MGR_HASH(32, 32); break;
         case 64: if (G <= 4) MGR_HASH(4, 64); else if (G == 8) MGR_HASH(8, 64); else if (G == 16) MGR_HASH(16, 64); else MGR_HASH(32, 64); break;
@@ -3418,14 +3451,16 @@ void bdiag_left_count(int nb, const int* bstart, const DCsr& B, int* cnt, int* f
 }
 void bdiag_right_count(const DCsr& A, const DCsr& M, int* cnt, int* flag, hipStream_t s) {
     if (A.nr <= 0) return;
-    k_bdiag_right<false><<<grid_for((A.nr + BDR_ROWS - 1) / BDR_ROWS, 32), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, M.rp.p, M.ci.p, M.v.p,
-                                                            nullptr, nullptr, nullptr, cnt, flag);
+    const int grid = grid_for((A.nr + BDR_ROWS - 1) / BDR_ROWS, 32);
+    k_bdiag_right<false><<<grid, TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, M.rp.p, M.ci.p, M.v.p, nullptr, nullptr,
+                                               nullptr, cnt, flag);
     MGR_LAUNCH_CHECK();
 }
 void bdiag_right_fill(const DCsr& A, const DCsr& M, DCsr& C, int* flag, hipStream_t s) {
     if (A.nr <= 0) return;
-    k_bdiag_right<true><<<grid_for((A.nr + BDR_ROWS - 1) / BDR_ROWS, 32), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, M.rp.p, M.ci.p, M.v.p,
-                                                           C.rp.p, C.ci.p, C.v.p, nullptr, flag);
+    const int grid = grid_for((A.nr + BDR_ROWS - 1) / BDR_ROWS, 32);
+    k_bdiag_right<true><<<grid, TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, M.rp.p, M.ci.p, M.v.p, C.rp.p, C.ci.p,
+                                              C.v.p, nullptr, flag);
     MGR_LAUNCH_CHECK();
 }
 
@@ -3439,14 +3474,15 @@ void bdiag_right_fill(const DCsr& A, const DCsr& M, DCsr& C, int* flag, hipStrea
 // second launch costs more than it saves).
 template <bool ADD>
 static void spgemm_fill_split(const DCsr& A, const DCsr& B, const DCsr* D, DCsr& C, int cap, int* flag,
-                              hipStream_t s) {
+                              hipStream_t s, double sgn = 1.0) {
     const long lds = (long)(TPB / hash_group(B, cap)) * cap * 12;
     const bool short_rows = C.nr > 0 && 6 * C.nnz <= (long)C.nr * cap;   // average row <= cap / 6
     if (cap >= 64 && lds >= 40960 && A.nr >= 262144 && short_rows) {
-        spgemm_hash_launch<true, ADD>(A, B, D, cap / 2, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s, -1, cap / 4);
-        spgemm_hash_launch<true, ADD>(A, B, D, cap, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s, cap / 4, INT_MAX);
+        spgemm_hash_launch<true, ADD>(A, B, D, cap / 2, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s, -1, cap / 4, sgn);
+        spgemm_hash_launch<true, ADD>(A, B, D, cap, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s, cap / 4, INT_MAX,
+                                      sgn);
     } else {
-        spgemm_hash_launch<true, ADD>(A, B, D, cap, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s);
+        spgemm_hash_launch<true, ADD>(A, B, D, cap, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s, -1, INT_MAX, sgn);
     }
 }
 
@@ -3475,15 +3511,16 @@ void spgemm_count(const DCsr& A, const DCsr& B, int max_row, int* cnt, int* flag
     spgemm_launch<false>(A, B, max_row, nullptr, nullptr, nullptr, cnt, flag, s);
 }
 
-void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, int* flag, hipStream_t s) {
+void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, int* flag, hipStream_t s, bool neg) {
     // hashed rows when the right factor is too wide for the dense LDS row and the
     // output rows (known from the symbolic pass) fit a table of at most 512 slots
     if (!spgemm_dense_ok(A, B) && A.nr > 0 && C.max_row >= 0 && C.max_row <= 256 && B.max_row >= 0) {
         const int cap = pow2_at_least(2L * C.max_row, 32);
-        spgemm_fill_split<false>(A, B, nullptr, C, cap, flag, s);
+        spgemm_fill_split<false>(A, B, nullptr, C, cap, flag, s, neg ? -1.0 : 1.0);
         return;
     }
     spgemm_launch<true>(A, B, max_row, C.rp.p, C.ci.p, C.v.p, nullptr, nullptr, s);
+    if (neg) negate(C.v.p, C.nnz, s);
 }
 
 bool spgemm_add_fusable(const DCsr& A, const DCsr& B, const DCsr& D) {
@@ -3846,7 +3883,7 @@ void rj_count(int nC, const DCsr& X, int* len, hipStream_t s) {
 
 void rj_fill(int nC, const DCsr& X, double scale, const int* fmap, const int* cmap, DCsr& R, hipStream_t s) {
     if (nC <= 0) return;
-    int G = group_for(X.max_row);
+    int G = group_for((X.max_row + FILL_BATCH - 1) / FILL_BATCH);
     MGR_DISPATCH_G4(G, (k_rj_fill_g<GG><<<grid_for(nC, GG), TPB, 0, s>>>(nC, X.rp.p, X.ci.p, X.v.p, scale, fmap,
                                                                           cmap, R.rp.p, R.ci.p, R.v.p)));
     MGR_LAUNCH_CHECK();
@@ -3861,7 +3898,7 @@ void pj_count(int n, const int* isF, const int* lmap, const DCsr& Y, const DCsr&
 void pj_fill(int n, int nC, const int* isF, const int* lmap, const DCsr& Y, double yscale, const DCsr& M,
              double mscale, const int* fmap, DCsr& P, hipStream_t s) {
     if (n <= 0) return;
-    int G = group_for(Y.max_row < 0 || M.max_row < 0 ? -1 : Y.max_row + M.max_row);
+    int G = group_for(Y.max_row < 0 || M.max_row < 0 ? -1 : (Y.max_row + M.max_row + FILL_BATCH - 1) / FILL_BATCH);
     MGR_DISPATCH_G4(G, (k_pj_fill_g<GG><<<grid_for(n, GG), TPB, 0, s>>>(n, nC, isF, lmap, Y.rp.p, Y.ci.p, Y.v.p,
                                                                          yscale, M.rp.p, M.ci.p, M.v.p, mscale,
                                                                          fmap, P.rp.p, P.ci.p, P.v.p)));

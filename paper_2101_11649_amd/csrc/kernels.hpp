@@ -70,8 +70,9 @@ constexpr int SPGEMM_DENSE_COLS = 4096;
 constexpr long SPGEMM_HASH_LOOSE = 2048;
 void spgemm_count(const DCsr& A, const DCsr& B, int max_row, int* cnt, int* flag, hipStream_t s, bool loose = false);
 // C's row pointers and max_row come from the counts; a failure of the hashed
-// variant (a full table) sets *flag (an int in device memory).
-void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, int* flag, hipStream_t s);
+// variant (a full table) sets *flag (an int in device memory).  With neg,
+// C = -A B (each value the negated sum).
+void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, int* flag, hipStream_t s, bool neg = false);
 // C = D + A B in one hashed product (D has A's rows and B's columns), when
 // every row of C is bounded by maxrow(A) maxrow(B) + maxrow(D) <= 256; the
 // values are those of the product followed by a separate sparse add.

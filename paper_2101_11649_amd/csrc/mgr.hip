@@ -12,6 +12,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -54,6 +55,9 @@ struct Slots {
         return p;
     }
     int* flag() { return reinterpret_cast<int*>(d.p + FLAG); }
+    // called by the AMG setup at the start of each level with its size (work
+    // held back for the small levels, whose kernels leave the GPU mostly idle)
+    std::function<void(int)> level_hook;
     // Reads every slot back; the value slots are then cleared on the stream, so
     // slots handed out by take() start at zero.
     void sync(const char* what) {
@@ -116,6 +120,7 @@ struct Spgemm {
     const DCsr* D = nullptr;  // C = D + A B when set
     DCsr* C = nullptr;
     int bdiag = 0;            // symbolic pass by the block kernels: 1 for M B, 2 for A M
+    bool neg = false;         // C = -A B
     DArr<int> cnt;
     long long* lr = nullptr;
     Pend pend;
@@ -188,25 +193,43 @@ static void bdiag_begin(Spgemm& j, int side, const DCsr& A, const DCsr& B, DCsr&
     j.pend = csr_begin(C, A.nr, B.nc, j.cnt.p, S);
 }
 
-static void spgemm_finish(Spgemm& j, Slots& S) {
+// After the sync that read the job's slot: C's row pointers and arrays
+// (spgemm_alloc), then the numeric pass on stream st (spgemm_fillpass), which
+// may be another stream than the slots' when C is read only there.
+static void spgemm_alloc(Spgemm& j, Slots& S) {
     const long long v = S.val(j.lr);
     if (j.bdiag) {
         if (v != 0) throw Error(MGR_ERR_ARG, "internal: block-diagonal product outside its row bounds");
         csr_finish(j.pend, S);
-        if (j.bdiag == 1) spgemm_fill(*j.A, *j.B, j.A->max_row, *j.C, S.flag(), S.s);
-        else bdiag_right_fill(*j.A, *j.B, *j.C, S.flag(), S.s);
-        j.cnt.reset();
-        return;
-    }
-    if (v == 2) {
+    } else if (v == 2) {
         spgemm_recount(j, S.s);
     } else {
         if (v != 0) throw Error(MGR_ERR_ARG, "internal: spgemm row longer than its recorded length");
         csr_finish(j.pend, S);
     }
-    if (j.D) spgemm_add_fill(*j.A, *j.B, *j.D, *j.C, S.flag(), S.s);
-    else spgemm_fill(*j.A, *j.B, j.A->max_row, *j.C, S.flag(), S.s);
     j.cnt.reset();
+}
+
+struct FillPass {
+    const DCsr* A = nullptr;
+    const DCsr* B = nullptr;
+    const DCsr* D = nullptr;
+    DCsr* C = nullptr;
+    int bdiag = 0;
+    bool neg = false;
+    void run(int* flag, hipStream_t st) const {
+        if (bdiag == 2) bdiag_right_fill(*A, *B, *C, flag, st);
+        else if (D) spgemm_add_fill(*A, *B, *D, *C, flag, st);
+        else spgemm_fill(*A, *B, A->max_row, *C, flag, st, neg);
+    }
+};
+static FillPass fill_pass(const Spgemm& j) { return FillPass{j.A, j.B, j.D, j.C, j.bdiag, j.neg}; }
+
+static void spgemm_fillpass(const Spgemm& j, Slots& S, hipStream_t st) { fill_pass(j).run(S.flag(), st); }
+
+static void spgemm_finish(Spgemm& j, Slots& S) {
+    spgemm_alloc(j, S);
+    spgemm_fillpass(j, S, S.s);
 }
 
 static DCsr spgemm(const DCsr& A, const DCsr& B, Slots& S) {
@@ -277,6 +300,13 @@ static void make_float(DCsr& A, hipStream_t s) {
     if (A.vf.p || A.nr == 0) return;
     A.vf.alloc((size_t)(A.nnz > 0 ? A.nnz : 1), s);
     to_float(A.v.p, A.vf.p, A.nnz, s);
+}
+
+// The same, converted on stream run (the array taken on stream s, which owns it).
+static void make_float_on(DCsr& A, hipStream_t s, hipStream_t run) {
+    if (A.vf.p || A.nr == 0) return;
+    A.vf.alloc((size_t)(A.nnz > 0 ? A.nnz : 1), s);
+    to_float(A.v.p, A.vf.p, A.nnz, run);
 }
 
 // ====================================================================== AMG
@@ -584,6 +614,7 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
         AmgLevel& L = H.lv[k];
         const DCsr& A = L.A;
         int n = A.nr;
+        if (S.level_hook) S.level_hook(n);
         if (n <= o.max_coarse || k + 1 >= o.max_levels) break;
         size_t nz = (size_t)(A.nnz > 0 ? A.nnz : 1);
         DArr<unsigned char> strong(nz, s);
@@ -725,6 +756,7 @@ static void amg_refresh(Amg& H, DCsr A0, Slots& S) {
     const int nl = (int)H.lv.size();
     for (int k = 0; k + 1 < nl; ++k) {
         AmgLevel& L = H.lv[k];
+        if (S.level_hook) S.level_hook(L.n);
         L.AT = DCsr();
         L.dposT.reset();
         L.loT.reset();
@@ -770,37 +802,40 @@ static void amg_refresh(Amg& H, DCsr A0, Slots& S) {
     H.have_trans = false;
 }
 
-static void amg_make_float(Amg& H, hipStream_t s) {
+// FP32 copies of the hierarchy: arrays taken on stream s, converted on run
+// (s when null)
+static void amg_make_float(Amg& H, hipStream_t s, hipStream_t run = nullptr) {
     if (H.have_float) return;
+    if (!run) run = s;
     for (size_t l = 0; l < H.lv.size(); ++l) {
         AmgLevel& L = H.lv[l];
         if (L.composed) {
-            make_float(L.G, s);
-            make_float(L.WQ, s);
+            make_float_on(L.G, s, run);
+            make_float_on(L.WQ, s, run);
             if (H.have_trans) {
-                make_float(L.Qt, s);
-                make_float(L.WGt, s);
+                make_float_on(L.Qt, s, run);
+                make_float_on(L.WGt, s, run);
             }
         } else {
-            make_float(L.A, s);
+            make_float_on(L.A, s, run);
         }
         if (l + 1 < H.lv.size() && !L.composed) {
-            make_float(L.P, s);
-            make_float(L.R, s);
+            make_float_on(L.P, s, run);
+            make_float_on(L.R, s, run);
             L.dinvf.alloc((size_t)L.n, s);
-            to_float(L.dinv.p, L.dinvf.p, L.n, s);
+            to_float(L.dinv.p, L.dinvf.p, L.n, run);
             if (L.dT.p) {
                 const long per = (long)H.chunk * L.nchp;
                 L.dTf.alloc((size_t)per, s);
-                to_float(L.dT.p, L.dTf.p, per, s);
+                to_float(L.dT.p, L.dTf.p, per, run);
                 for (HgsTri* t : {&L.lo, &L.up, &L.loT, &L.upT}) {
                     if (!t->v.p) continue;
                     t->vf.alloc(t->v.n, s);
-                    to_float(t->v.p, t->vf.p, per * t->w, s);
+                    to_float(t->v.p, t->vf.p, per * t->w, run);
                 }
             }
         }
-        if (H.have_trans && L.AT.nr && !L.composed) make_float(L.AT, s);
+        if (H.have_trans && L.AT.nr && !L.composed) make_float_on(L.AT, s, run);
         L.rf.alloc((size_t)L.n + 1, s);
         L.tf.alloc((size_t)L.n + 1, s);
         L.sf.alloc((size_t)L.n + 1, s);
@@ -811,18 +846,18 @@ static void amg_make_float(Amg& H, hipStream_t s) {
     }
     long nn = (long)H.nc * H.nc;
     H.cinvf.alloc((size_t)nn + 1, s);
-    to_float(H.cinv.p, H.cinvf.p, nn, s);
+    to_float(H.cinv.p, H.cinvf.p, nn, run);
     if (H.have_trans) {
         H.cinvTf.alloc((size_t)nn + 1, s);
-        to_float(H.cinvT.p, H.cinvTf.p, nn, s);
+        to_float(H.cinvT.p, H.cinvTf.p, nn, run);
     }
     if (H.tail >= 0) {
         const long tn = (long)H.lv[H.tail].n * H.lv[H.tail].n;
         H.tdf.alloc((size_t)tn + 1, s);
-        to_float(H.td.p, H.tdf.p, tn, s);
+        to_float(H.td.p, H.tdf.p, tn, run);
         if (H.have_trans) {
             H.tdTf.alloc((size_t)tn + 1, s);
-            to_float(H.tdT.p, H.tdTf.p, tn, s);
+            to_float(H.tdT.p, H.tdTf.p, tn, run);
         }
     }
     H.have_float = true;
@@ -1154,6 +1189,10 @@ struct Ctx {
     // the copy of the input values is made by the first block extraction (a
     // block input with MGR levels) instead of a separate copy
     bool copy_in_extract = false;
+    // setup work for the auxiliary stream held back until the coarse AMG
+    // reaches its smaller levels, one piece per level (run_deferred)
+    std::vector<std::function<void()>> deferred;
+    size_t deferred_next = 0;
     ~Ctx() {
         if (aux) {
             (void)hipStreamSynchronize(aux);
@@ -1199,8 +1238,25 @@ struct AuxScope {
         }
         c.Avin = nullptr;
         c.copy_in_extract = false;
+        c.deferred.clear();
+        c.deferred_next = 0;
+        c.slots.level_hook = nullptr;
     }
 };
+
+// Held-back work, on the auxiliary stream after everything enqueued so far:
+// the next `pieces` pieces (all with pieces < 0).  Spread over the AMG's
+// smaller levels, whose own kernels are latency-bound, it slows them less
+// than all at once.
+static void run_deferred(Ctx& c, int pieces = -1) {
+    if (c.deferred_next >= c.deferred.size()) return;
+    aux_fork(c);
+    for (; c.deferred_next < c.deferred.size() && pieces != 0; --pieces) c.deferred[c.deferred_next++]();
+    if (c.deferred_next >= c.deferred.size()) {
+        c.deferred.clear();
+        c.deferred_next = 0;
+    }
+}
 
 // the block values a setup step reads: the caller's while they are being copied
 static const double* in_values(const Ctx& c) { return c.Avin ? c.Avin : c.Av.p; }
@@ -1364,12 +1420,16 @@ static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr* A, const int* field
     const bool bdl = bdiag_left_ok(l.M, l.AFC), bdr = bdiag_right_ok(l.ACF, l.M);
     if (bdl) bdiag_begin(jP, 1, l.M, l.AFC, l.PF, (int)nb, bstart.p, S);
     else spgemm_begin(jP, l.M, l.AFC, l.PF, S);
+    jP.neg = true;
     if (bdr) bdiag_begin(jW, 2, l.ACF, l.M, l.W, 0, nullptr, S);
     else spgemm_begin(jW, l.ACF, l.M, l.W, S);
     S.sync("MGR transfer operators");
     spgemm_finish(jP, S);
-    negate(l.PF.v.p, l.PF.nnz, s);
-    spgemm_finish(jW, S);
+    // with the fused apply, W = A_CF M is read only by R_J's fill: its own
+    // numeric pass goes to the auxiliary stream with it
+    l.fused = fused_ok(o);
+    spgemm_alloc(jW, S);
+    if (!l.fused) spgemm_fillpass(jW, S, s);
     if (o.restrict_type == MGR_RESTRICT_JACOBI) {
         l.RF = csr_copy(l.W, s);
         negate(l.RF.v.p, l.RF.nnz, s);
@@ -1381,7 +1441,6 @@ static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr* A, const int* field
     if (fuse_add) spgemm_add_begin(j1, l.ACF, l.PF, l.ACC, Ac, S);
     else spgemm_begin(j1, l.ACF, l.PF, T1, S);
     // fused one-sweep apply: r_c = [-omega A_CF M | I] v ; z = [P_F | omega M] [e_c ; v]
-    l.fused = fused_ok(o);
     DArr<int> lenR, lenP;
     Pend pR, pP;
     if (l.fused) {
@@ -1397,11 +1456,22 @@ static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr* A, const int* field
     if (l.fused) {
         csr_finish(pR, S);
         csr_finish(pP, S);
-        // R_J and P_J are read only by the apply: filled on the auxiliary
-        // stream while the setup goes on (joined before the setup returns)
-        aux_fork(c);
-        rj_fill(l.nC, l.W, -o.omega, l.fmap.p, l.cmap.p, l.RJ, c.aux);
-        pj_fill(n, l.nC, l.isF.p, l.lmap.p, l.PF, 1.0, l.M, o.omega, l.fmap.p, l.PJ, c.aux);
+        // R_J and P_J (and W, read only by R_J's fill) are read only by the
+        // apply: filled on the auxiliary stream once the coarse AMG reaches
+        // its small levels (on the busy large levels the two streams would
+        // only share the bandwidth), joined before the setup returns
+        const FillPass wfill = fill_pass(jW);
+        const double om = o.omega;
+        const bool f32 = c.o.apply_precision == 32;
+        c.deferred.push_back([&c, wfill]() { wfill.run(c.slots.flag(), c.aux); });
+        c.deferred.push_back([&c, &l, om, f32]() {
+            rj_fill(l.nC, l.W, -om, l.fmap.p, l.cmap.p, l.RJ, c.aux);
+            if (f32) make_float_on(l.RJ, c.s, c.aux);   // the FP32 apply's copy
+        });
+        c.deferred.push_back([&c, &l, om, n, f32]() {
+            pj_fill(n, l.nC, l.isF.p, l.lmap.p, l.PF, 1.0, l.M, om, l.fmap.p, l.PJ, c.aux);
+            if (f32) make_float_on(l.PJ, c.s, c.aux);
+        });
     }
     if (!fuse_add) {
         Ac = csr_add(l.ACC, T1, S);
@@ -1467,27 +1537,31 @@ static void mgr_level_make_trans(Ctx& c, MgrLevel& l) {
     l.have_trans = true;
 }
 
-static void mgr_level_make_float(Ctx& c, MgrLevel& l) {
+// the level's FP32 copies, converted on stream run (c.s when null)
+static void mgr_level_make_float(Ctx& c, MgrLevel& l, hipStream_t run = nullptr) {
     if (l.have_float) return;
     hipStream_t s = c.s;
+    if (!run) run = s;
     if (l.fused) {
-        make_float(l.RJ, s); make_float(l.PJ, s);
-        if (l.have_trans) { make_float(l.RJt, s); make_float(l.PJt, s); }
+        make_float_on(l.RJ, s, run); make_float_on(l.PJ, s, run);
+        if (l.have_trans) { make_float_on(l.RJt, s, run); make_float_on(l.PJt, s, run); }
     } else {
-        make_float(l.AFF, s); make_float(l.ACF, s); make_float(l.PF, s); make_float(l.M, s);
-        if (l.RF.nr) make_float(l.RF, s);
-        if (l.iluL.nr) { make_float(l.iluL, s); make_float(l.iluU, s); }
-        if (l.have_trans && l.iluLt.nr) { make_float(l.iluLt, s); make_float(l.iluUt, s); }
+        make_float_on(l.AFF, s, run); make_float_on(l.ACF, s, run);
+        make_float_on(l.PF, s, run); make_float_on(l.M, s, run);
+        if (l.RF.nr) make_float_on(l.RF, s, run);
+        if (l.iluL.nr) { make_float_on(l.iluL, s, run); make_float_on(l.iluU, s, run); }
+        if (l.have_trans && l.iluLt.nr) { make_float_on(l.iluLt, s, run); make_float_on(l.iluUt, s, run); }
         if (l.have_trans) {
-            make_float(l.AFFt, s); make_float(l.ACFt, s); make_float(l.PFt, s); make_float(l.Mt, s);
-            if (l.RFt.nr) make_float(l.RFt, s);
+            make_float_on(l.AFFt, s, run); make_float_on(l.ACFt, s, run);
+            make_float_on(l.PFt, s, run); make_float_on(l.Mt, s, run);
+            if (l.RFt.nr) make_float_on(l.RFt, s, run);
         }
         l.vFf.alloc((size_t)l.nF + 1, s); l.vCf.alloc((size_t)l.nC + 1, s);
         l.zFf.alloc((size_t)l.nF + 1, s); l.rFf.alloc((size_t)l.nF + 1, s); l.tFf.alloc((size_t)l.nF + 1, s);
     }
     l.rcf.alloc((size_t)l.nC + 1, s);
     l.ecf.alloc((size_t)l.nC + 1, s);
-    if (l.famg) amg_make_float(*l.famg, s);
+    if (l.famg) amg_make_float(*l.famg, s, run);
     l.have_float = true;
 }
 
@@ -2168,6 +2242,9 @@ static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nle
     build_hierarchy(c);
 }
 
+// coarse-AMG level size from which the held-back auxiliary-stream work runs
+constexpr int AUX_DEFER_ROWS = 400000;
+
 // The MGR levels and the coarse AMG on the current input (c.A0, c.field0, c.lvl);
 // AMG hierarchies found in c.reuse_* are reused instead of coarsened again.
 static void build_hierarchy(Ctx& c) {
@@ -2209,6 +2286,9 @@ static void build_hierarchy(Ctx& c) {
             cur = &next;
         }
     }
+    c.slots.level_hook = [&c](int n) {
+        if (n <= AUX_DEFER_ROWS) run_deferred(c, 1);
+    };
     if (c.reuse_camg) {
         c.camg = std::move(*c.reuse_camg);
         c.reuse_camg.reset();
@@ -2217,14 +2297,18 @@ static void build_hierarchy(Ctx& c) {
         amg_setup(c.camg, nlevels > 0 ? std::move(next) : csr_copy(c.A0, s),
                   c.o.amg.unknown_based ? fld.p : nullptr, c.o.amg, c.o.amg.seed, c.slots);
     }
+    c.slots.level_hook = nullptr;
+    run_deferred(c);
     c.reuse_famg.clear();
-    aux_join(c);
     c.Avin = nullptr;
     if (c.o.apply_precision == 32) {
-        for (auto& l : c.L) mgr_level_make_float(c, l);
-        amg_make_float(c.camg, s);
+        // the FP32 copies on the auxiliary stream, beside the sliced-ELL sizing
+        aux_fork(c);
+        for (auto& l : c.L) mgr_level_make_float(c, l, c.aux);
+        amg_make_float(c.camg, s, c.aux);
     }
     prepare_ell(c);
+    aux_join(c);
     MGR_HIP(hipStreamSynchronize(s));
     c.ready = true;
 }
