@@ -2897,7 +2897,8 @@ __global__ void k_pj_count(int n, const int* __restrict__ isF, const int* __rest
     len[g] = (yrp[k + 1] - yrp[k]) + (mrp[k + 1] - mrp[k]);
 }
 
-// Lane-group versions of the two fills above, each lane taking FILL_BATCH
+// Lane-group versions of the two fills above (with the FP32 copy of the values
+// too when the output has one allocated), each lane taking FILL_BATCH
 // entries of its row with every load of the batch issued before any is used
 // (a row's loads form a chain of three or four dependent steps).  In a row of
 // R the unit entry goes before the first column above g, so entry p of X lands
@@ -2909,7 +2910,7 @@ __global__ __launch_bounds__(TPB) void k_rj_fill_g(int nC, const int* __restrict
                                                    const double* __restrict__ xv, double scale,
                                                    const int* __restrict__ fmap, const int* __restrict__ cmap,
                                                    const int* __restrict__ rrp, int* __restrict__ rci,
-                                                   double* __restrict__ rv) {
+                                                   double* __restrict__ rv, float* __restrict__ rvf) {
     Grp<G> g;
     const int i = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
     const bool valid = i < nC;
@@ -2939,8 +2940,10 @@ __global__ __launch_bounds__(TPB) void k_rj_fill_g(int nC, const int* __restrict
             const bool act = q < len;
             if (act) {
                 const int pos = o + q + (col[u] > gc ? 1 : 0);
+                const double x = scale * val[u];
                 rci[pos] = col[u];
-                rv[pos] = scale * val[u];
+                rv[pos] = x;
+                if (rvf) rvf[pos] = (float)x;
             }
             nless += __popcll(g.bits(act && col[u] < gc));
         }
@@ -2948,6 +2951,7 @@ __global__ __launch_bounds__(TPB) void k_rj_fill_g(int nC, const int* __restrict
     if (valid && g.gl == 0) {
         rci[o + nless] = gc;
         rv[o + nless] = 1.0;
+        if (rvf) rvf[o + nless] = 1.0f;
     }
 }
 
@@ -2959,14 +2963,18 @@ __global__ __launch_bounds__(TPB) void k_pj_fill_g(int n, int nC, const int* __r
                                                    const int* __restrict__ mci, const double* __restrict__ mv,
                                                    double mscale, const int* __restrict__ fmap,
                                                    const int* __restrict__ prp, int* __restrict__ pci,
-                                                   double* __restrict__ pv) {
+                                                   double* __restrict__ pv, float* __restrict__ pvf) {
     Grp<G> g;
     const int r = (int)(((long)blockIdx.x * TPB + threadIdx.x) / G);
     if (r >= n) return;
     const int o = prp[r];
     const int k = lmap[r];
     if (!isF[r]) {
-        if (g.gl == 0) { pci[o] = k; pv[o] = 1.0; }
+        if (g.gl == 0) {
+            pci[o] = k;
+            pv[o] = 1.0;
+            if (pvf) pvf[o] = 1.0f;
+        }
         return;
     }
     // the row is [Y row k | M row k]: entry q < ylen from Y, the rest from M
@@ -2993,6 +3001,7 @@ __global__ __launch_bounds__(TPB) void k_pj_fill_g(int n, int nC, const int* __r
             if (q < len) {
                 pci[o + q] = col[u];
                 pv[o + q] = val[u];
+                if (pvf) pvf[o + q] = (float)val[u];
             }
         }
     }
@@ -3885,7 +3894,7 @@ void rj_fill(int nC, const DCsr& X, double scale, const int* fmap, const int* cm
     if (nC <= 0) return;
     int G = group_for((X.max_row + FILL_BATCH - 1) / FILL_BATCH);
     MGR_DISPATCH_G4(G, (k_rj_fill_g<GG><<<grid_for(nC, GG), TPB, 0, s>>>(nC, X.rp.p, X.ci.p, X.v.p, scale, fmap,
-                                                                          cmap, R.rp.p, R.ci.p, R.v.p)));
+                                                                          cmap, R.rp.p, R.ci.p, R.v.p, R.vf.p)));
     MGR_LAUNCH_CHECK();
 }
 
@@ -3901,7 +3910,7 @@ void pj_fill(int n, int nC, const int* isF, const int* lmap, const DCsr& Y, doub
     int G = group_for(Y.max_row < 0 || M.max_row < 0 ? -1 : (Y.max_row + M.max_row + FILL_BATCH - 1) / FILL_BATCH);
     MGR_DISPATCH_G4(G, (k_pj_fill_g<GG><<<grid_for(n, GG), TPB, 0, s>>>(n, nC, isF, lmap, Y.rp.p, Y.ci.p, Y.v.p,
                                                                          yscale, M.rp.p, M.ci.p, M.v.p, mscale,
-                                                                         fmap, P.rp.p, P.ci.p, P.v.p)));
+                                                                         fmap, P.rp.p, P.ci.p, P.v.p, P.vf.p)));
     MGR_LAUNCH_CHECK();
 }
 

@@ -190,7 +190,8 @@ void ilu_level(int cnt, const int* rows, DCsr& LU, const int* dpos, int* flag, h
 void split_count(const DCsr& A, int* nl, int* nu, hipStream_t s);
 void split_fill(const DCsr& A, DCsr& L, DCsr& U, hipStream_t s);
 
-// MGR apply operators of the fused one-sweep path
+// MGR apply operators of the fused one-sweep path (the fills also write the
+// FP32 copy of the values when R.vf / P.vf is allocated)
 void rj_count(int nC, const DCsr& X, int* len, hipStream_t s);
 void rj_fill(int nC, const DCsr& X, double scale, const int* fmap, const int* cmap, DCsr& R, hipStream_t s);
 void pj_count(int n, const int* isF, const int* lmap, const DCsr& Y, const DCsr& M, int* len, hipStream_t s);

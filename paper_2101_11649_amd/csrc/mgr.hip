@@ -1131,6 +1131,7 @@ struct MgrLevel {
     // level vectors: coarse input / output (the next level's v and z)
     DArr<double> rcd, ecd, vFd, vCd, zFd, rFd, tFd;
     DArr<float> rcf, ecf, vFf, vCf, zFf, rFf, tFf;
+    DArr<float> vinf;   // FP32 apply, first fused level: the input v in FP32
 };
 
 struct Ctx {
@@ -1464,13 +1465,14 @@ static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr* A, const int* field
         const double om = o.omega;
         const bool f32 = c.o.apply_precision == 32;
         c.deferred.push_back([&c, wfill]() { wfill.run(c.slots.flag(), c.aux); });
+        // (with the FP32 apply, the fills write its FP32 copies too)
         c.deferred.push_back([&c, &l, om, f32]() {
+            if (f32) l.RJ.vf.alloc((size_t)(l.RJ.nnz > 0 ? l.RJ.nnz : 1), c.s);
             rj_fill(l.nC, l.W, -om, l.fmap.p, l.cmap.p, l.RJ, c.aux);
-            if (f32) make_float_on(l.RJ, c.s, c.aux);   // the FP32 apply's copy
         });
         c.deferred.push_back([&c, &l, om, n, f32]() {
+            if (f32) l.PJ.vf.alloc((size_t)(l.PJ.nnz > 0 ? l.PJ.nnz : 1), c.s);
             pj_fill(n, l.nC, l.isF.p, l.lmap.p, l.PF, 1.0, l.M, om, l.fmap.p, l.PJ, c.aux);
-            if (f32) make_float_on(l.PJ, c.s, c.aux);
         });
     }
     if (!fuse_add) {
@@ -1561,6 +1563,7 @@ static void mgr_level_make_float(Ctx& c, MgrLevel& l, hipStream_t run = nullptr)
     }
     l.rcf.alloc((size_t)l.nC + 1, s);
     l.ecf.alloc((size_t)l.nC + 1, s);
+    if (l.fused && &l == &c.L.front()) l.vinf.alloc((size_t)l.n + 1, s);
     if (l.famg) amg_make_float(*l.famg, s, run);
     l.have_float = true;
 }
@@ -1620,6 +1623,28 @@ static const T* amg_first_dinv(Ctx& c, bool tr) {
     return Prec<T>::dinv(H.lv[0]);
 }
 
+// The one-sweep level: r_c = R_J v, the coarse solve, z = P_J [e_c ; v];
+// XT is the type the transfers read v in, ZT the type of z.
+template <typename T, typename XT, typename ZT>
+static void fused_level_apply(Ctx& c, int lev, MgrLevel& l, const XT* v, ZT* z, bool tr) {
+    hipStream_t s = c.s;
+    T* rc = LV<T>::rc(l);
+    T* ec = LV<T>::ec(l);
+    SpOp<T> R = view<T>(tr ? l.RJt : l.RJ);
+    SpOp<T> P = view<T>(tr ? l.PJt : l.PJ);
+    const T* d0 = (lev + 1 == (int)c.L.size()) ? amg_first_dinv<T>(c, tr) : nullptr;
+    if (d0) {
+        // the coarse AMG's first pre-smoothing gathers D^-1 r_c formed here
+        T* sc = Prec<T>::sb(c.camg.lv[0]);
+        restrict_scaled<T, XT>(R, v, d0, rc, sc, s);
+        mgr_apply_rec<T>(c, lev + 1, rc, ec, tr, sc);
+    } else {
+        spmv<T, XT, XT, T, T>(R, v, (const XT*)nullptr, INT_MAX, (const T*)nullptr, rc, T(1), T(0), s);
+        mgr_apply_rec<T>(c, lev + 1, rc, ec, tr);
+    }
+    spmv<T, T, XT, ZT, ZT>(P, ec, v, l.nC, (const ZT*)nullptr, z, T(1), T(0), s);
+}
+
 // Algorithm 1 at level `lev` with working precision T; VT is the type of v and
 // z at this level (FP64 at level 0, T below).
 template <typename T, typename VT>
@@ -1629,19 +1654,18 @@ static void mgr_level_apply(Ctx& c, int lev, const VT* v, VT* z, bool tr) {
     T* rc = LV<T>::rc(l);
     T* ec = LV<T>::ec(l);
     if (l.fused) {
-        SpOp<T> R = view<T>(tr ? l.RJt : l.RJ);
-        SpOp<T> P = view<T>(tr ? l.PJt : l.PJ);
-        const T* d0 = (lev + 1 == (int)c.L.size()) ? amg_first_dinv<T>(c, tr) : nullptr;
-        if (d0) {
-            // the coarse AMG's first pre-smoothing gathers D^-1 r_c formed here
-            T* sc = Prec<T>::sb(c.camg.lv[0]);
-            restrict_scaled<T, VT>(R, v, d0, rc, sc, s);
-            mgr_apply_rec<T>(c, lev + 1, rc, ec, tr, sc);
-        } else {
-            spmv<T, VT, VT, T, T>(R, v, (const VT*)nullptr, INT_MAX, (const T*)nullptr, rc, T(1), T(0), s);
-            mgr_apply_rec<T>(c, lev + 1, rc, ec, tr);
+        if constexpr (std::is_same_v<T, float> && std::is_same_v<VT, double>) {
+            if (l.vinf.p) {
+                // the FP32 transfers read each value of v rounded to FP32:
+                // rounded once here, both read FP32 columns (the same values;
+                // one column type lets the interpolation issue one load per
+                // entry instead of one per source)
+                copy<double, float>(l.n, v, l.vinf.p, s);
+                fused_level_apply<T, float, VT>(c, lev, l, l.vinf.p, z, tr);
+                return;
+            }
         }
-        spmv<T, T, VT, VT, VT>(P, ec, v, l.nC, (const VT*)nullptr, z, T(1), T(0), s);
+        fused_level_apply<T, VT, VT>(c, lev, l, v, z, tr);
         return;
     }
     T* vF = LV<T>::vF(l);
@@ -1770,7 +1794,7 @@ template <typename F>
 static void for_each_work(Ctx& c, F&& f) {
     for (auto& l : c.L) {
         f(l.rcd); f(l.ecd); f(l.vFd); f(l.vCd); f(l.zFd); f(l.rFd); f(l.tFd);
-        f(l.rcf); f(l.ecf); f(l.vFf); f(l.vCf); f(l.zFf); f(l.rFf); f(l.tFf);
+        f(l.rcf); f(l.ecf); f(l.vFf); f(l.vCf); f(l.zFf); f(l.rFf); f(l.tFf); f(l.vinf);
         if (l.famg) for_each_work(*l.famg, f);
     }
     for_each_work(c.camg, f);
