@@ -3542,7 +3542,11 @@ void spgemm_add_count(const DCsr& A, const DCsr& B, const DCsr& D, int* cnt, int
     if (A.nr <= 0) return;
     const long bound = (long)A.max_row * B.max_row + D.max_row;
     int cap = pow2_at_least(bound, 32);
-    if (loose && cap > SPGEMM_ADD_LOOSE_CAP) cap = SPGEMM_ADD_LOOSE_CAP;
+    if (loose) {
+        // a row of C holds D's row: tables of at least twice that
+        const int lc = std::max(SPGEMM_ADD_LOOSE_CAP, pow2_at_least(2L * D.max_row, 32));
+        cap = std::min(cap, lc);
+    }
     if (lanes_ok(A, B))
         spgemm_lanes_count<true>(A, B, &D, cap, cnt, flag, s);
     else

@@ -77,10 +77,11 @@ void spgemm_fill(const DCsr& A, const DCsr& B, int max_row, DCsr& C, int* flag, 
 // every row of C is bounded by maxrow(A) maxrow(B) + maxrow(D) <= 256; the
 // values are those of the product followed by a separate sparse add.
 bool spgemm_add_fusable(const DCsr& A, const DCsr& B, const DCsr& D);
-// With `loose`, the rows are counted in tables of at most SPGEMM_ADD_LOOSE_CAP
-// slots (the bound maxrow(A) maxrow(B) + maxrow(D) is far above the rows of
-// a Galerkin product of stencil operators); a full table sets *flag to 2, and
-// the count must then be made again without `loose`.
+// With `loose`, the rows are counted in tables of at most the larger of
+// SPGEMM_ADD_LOOSE_CAP slots and twice D's longest row (the bound maxrow(A)
+// maxrow(B) + maxrow(D) is far above the rows of a Galerkin product of stencil
+// operators); a full table sets *flag to 2, and the count must then be made
+// again without `loose`.
 constexpr int SPGEMM_ADD_LOOSE_CAP = 64;
 void spgemm_add_count(const DCsr& A, const DCsr& B, const DCsr& D, int* cnt, int* flag, hipStream_t s,
                       bool loose = false);
