@@ -30,18 +30,27 @@ namespace mgr {
 // Device-produced values the host needs during setup (prefix-sum totals,
 // longest rows, counters, error flags) land in a small slot array that is read
 // back with ONE pinned copy per sync point, so a whole setup needs a few tens of
-// host synchronisations instead of one per scan.
+// host synchronisations instead of one per scan.  The slots of one sync period
+// form a region; each sync moves on to the next region, zeroed in advance
+// with all the others, instead of clearing the region it read with a kernel of
+// its own (a launch per sync saved).
 struct Slots {
-    static constexpr int N = 64;
-    static constexpr int FLAG = N - 1;   // int error flag kept in the last slot
+    static constexpr int N = 64;           // slots per region
+    static constexpr int FLAG = N - 1;     // int error flag kept in the last slot
+    static constexpr int REGIONS = 64;     // regions zeroed together
     DArr<long long> d;
     long long* h = nullptr;
+    long long* cur = nullptr;    // the region slots are taken from
+    long long* read = nullptr;   // the region the last sync read into h
+    int region = 0;
     int next = 0;
     hipStream_t s = nullptr;
     void init(hipStream_t st) {
         s = st;
-        d.alloc(N, s);
-        fill_ll(d.p, 0, N, s);
+        d.alloc((size_t)N * REGIONS, s);
+        fill_ll(d.p, 0, (long)N * REGIONS, s);
+        cur = read = d.p;
+        region = 0;
         MGR_HIP(hipHostMalloc(reinterpret_cast<void**>(&h), sizeof(long long) * N, hipHostMallocDefault));
         std::memset(h, 0, sizeof(long long) * N);
     }
@@ -50,24 +59,29 @@ struct Slots {
     }
     long long* take(int k) {
         if (next + k > FLAG) throw Error(MGR_ERR_ARG, "internal: too many pending setup values");
-        long long* p = d.p + next;
+        long long* p = cur + next;
         next += k;
         return p;
     }
-    int* flag() { return reinterpret_cast<int*>(d.p + FLAG); }
+    int* flag() { return reinterpret_cast<int*>(cur + FLAG); }
     // called by the AMG setup at the start of each level with its size (work
     // held back for the small levels, whose kernels leave the GPU mostly idle)
     std::function<void(int)> level_hook;
-    // Reads every slot back; the value slots are then cleared on the stream, so
-    // slots handed out by take() start at zero.
+    // Reads the region back; slots taken afterwards come from the next region
+    // (zero).  When the regions run out they are all zeroed again, on the
+    // stream, which the sync has just drained.
     void sync(const char* what) {
-        MGR_HIP(hipMemcpyAsync(h, d.p, sizeof(long long) * N, hipMemcpyDeviceToHost, s));
+        MGR_HIP(hipMemcpyAsync(h, cur, sizeof(long long) * N, hipMemcpyDeviceToHost, s));
         MGR_HIP(hipStreamSynchronize(s));
-        if (next > 0) fill_ll(d.p, 0, next, s);
+        read = cur;
+        if (++region == REGIONS) {
+            fill_ll(d.p, 0, (long)N * REGIONS, s);
+            region = 0;
+        }
+        cur = d.p + (long)region * N;
         next = 0;
         int f = (int)(h[FLAG] & 0xffffffffLL);
         if (f != 0) {
-            fill_ll(d.p + FLAG, 0, 1, s);
             std::string m = std::string(what) + ": ";
             if (f == 3) throw Error(MGR_ERR_ZERO_PIVOT, m + "zero or non-finite pivot");
             if (f == 5) throw Error(MGR_ERR_BAD_LABELS, m + "field label outside [0, 32)");
@@ -75,7 +89,13 @@ struct Slots {
                         m + "unsupported input (row too long, block larger than 4, or a_ii <= 0)");
         }
     }
-    long long val(const long long* p) const { return h[p - d.p]; }
+    // a slot's value, read back by the sync after it was taken (a slot read
+    // after a later sync is an error in the caller's sequencing)
+    long long val(const long long* p) const {
+        const long i = p - read;
+        if (i < 0 || i >= N) throw Error(MGR_ERR_ARG, "internal: setup value read after a later sync");
+        return h[i];
+    }
 };
 
 // Two-phase construction from row counts: begin() scans asynchronously, the
@@ -470,9 +490,13 @@ static void amg_hgs_finish(Amg& H, Slots& S) {
     }
 }
 
+constexpr int PMIS_SMALL_N = 8192;
+
 // PMIS to completion on a strength graph (srp, sci) with measures lam and the
 // random stream of `level`; cf gets +1 = C / -1 = F.  Host checks every four
-// rounds (after a first batch of eight).
+// rounds, after a first batch of eight (four on levels of at most
+// PMIS_SMALL_N points, which finish in about three rounds: rounds after the
+// last undecided point is settled change nothing, so the split is the same).
 static void pmis_run(int n, const int* srp, const int* sci, const int* lam, uint64_t seed, int level, DArr<int>& cf,
                      int avg_row, Slots& S) {
     hipStream_t s = S.s;
@@ -482,7 +506,7 @@ static void pmis_run(int n, const int* srp, const int* sci, const int* lam, uint
     cf.alloc((size_t)n + 1, s);
     pmis_init(n, lam, seed, level, w.p, cf.p, s);
     fill_bytes(bt.p, 0, n, s);
-    for (int total = 0, batch = 8;; total += batch, batch = 4) {
+    for (int total = 0, batch = n <= PMIS_SMALL_N ? 4 : 8;; total += batch, batch = 4) {
         if (total > 100000) throw Error(MGR_ERR_UNSUPPORTED, "PMIS did not terminate");
         long long* und = S.take(1);
         for (int r = 0; r < batch; ++r) {
@@ -886,15 +910,19 @@ static void amg_make_trans(Amg& H, Slots& S) {
         }
         L.AT = csr_transpose(L.A, S);
         if (H.have_float) make_float(L.AT, s);
-        if (H.smoother == MGR_SMOOTH_HYBRID_GS) {
+    }
+    if (H.smoother == MGR_SMOOTH_HYBRID_GS) {
+        // the widths of every level counted after the last transpose's sync,
+        // so that one sync reads them all
+        for (size_t l = 0; l + 1 < H.lv.size(); ++l) {
+            AmgLevel& L = H.lv[l];
+            if (L.composed) continue;
             // A^T keeps every diagonal entry of A
             L.dposT.alloc((size_t)L.n + 1, s);
             diag_pos(L.AT, L.dposT.p, S.flag(), s);
             L.wslot = S.take(1);
             hgs_tri_count(L.AT, L.dposT.p, H.chunk, reinterpret_cast<int*>(L.wslot), s);
         }
-    }
-    if (H.smoother == MGR_SMOOTH_HYBRID_GS) {
         // the transposed sweeps use A's diagonal d, so dT is shared
         S.sync("hybrid Gauss-Seidel tables of A^T");
         for (size_t l = 0; l + 1 < H.lv.size(); ++l) {
