@@ -218,7 +218,7 @@ int mgr_apply(mgr_handle h, const double *r, double *z);
  * operators, so the same result), for callers that cannot allocate device
  * memory: code under HIP graph capture, tight serving loops, harnesses that
  * forbid allocation.  It calls no allocating routine: its work vectors live in
- * one static device array per GPU of MGR_NOALLOC_SCRATCH_BYTES (64 MiB), held
+ * one static device array per GPU of MGR_NOALLOC_SCRATCH_BYTES (128 MiB), held
  * from the library's first handle on that GPU until the process ends.  Every
  * call on a GPU shares that array, so calls that overlap on one GPU (other
  * streams, other handles, other threads) race; the array keeps the last call's
@@ -229,7 +229,7 @@ int mgr_apply(mgr_handle h, const double *r, double *z);
  * may not alias.  Asynchronous.  Errors: ARG (no setup, no earlier apply, null
  * vector), UNSUPPORTED (the hierarchy's work vectors, each rounded up to 256
  * bytes, exceed the scratch size). */
-#define MGR_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define MGR_NOALLOC_SCRATCH_BYTES (128u << 20)
 int mgr_apply_noalloc(mgr_handle h, const double *r, double *z);
 
 /* z = M^{-T} r, the exact transpose of mgr_apply (requires sweeps == 1 on

@@ -69,3 +69,27 @@ def test_noalloc_needs_setup_and_a_first_apply():
         assert P.lib().mgr_apply_noalloc(g._h, None, ctypes.c_void_p(z.data_ptr())) == -1
     finally:
         g.close()
+
+
+def test_noalloc_at_full_size():
+    """The compositional 128 x 128 x 64 system (4,194,368 unknowns): its work
+    vectors (73.5 MB in FP64) fit the scratch array, in both apply precisions."""
+    import torch
+
+    import paper_2101_11649_amd as P
+    import workloads as W
+    s = W.compositional_wells(seed=2)
+    vals = torch.tensor(s["vals"], device="cuda")
+    v = torch.tensor(np.random.default_rng(8).standard_normal(s["n"]), device="cuda")
+    for precision in (64, 32):
+        g = P.Solver(s["b"], s["rp"], s["ci"], vals, s["field"], s["levels"], precision=precision)
+        try:
+            zref = g.apply(v)
+            z = torch.full_like(v, float("nan"))
+            rc = _noalloc(P, g, v, z)
+            assert rc == 0, P.lib().mgr_last_error(g._h)
+            torch.cuda.synchronize()
+            say(f"compositional 128x128x64 fp{precision}: noalloc vs apply identical")
+            assert torch.equal(z, zref)
+        finally:
+            g.close()
