@@ -261,14 +261,19 @@ def apply_launches(solver, precision, nu_pre=1, nu_post=1, levels=None, smoother
             first_plain = len(amg) >= 2 and solver.export_sizes(1, 0, 4) is None \
                 and solver.export_sizes(1, 0, 6) is None and nu_pre >= 1 and not gs
             scaled = (l + 1 == len(mgr)) and first_plain
-            out.append((f"MGR{l} restriction R_J", sp(nC, rj[2]) + n * vs + (3 if scaled else 1) * nC * s))
+            # the FP32 apply converts the FP64 input once; both transfers then read it in FP32
+            conv = l == 0 and s == 4
+            xs = s if conv else vs
+            if conv:
+                out.append((f"MGR{l} input to FP32", n * 8 + n * 4))
+            out.append((f"MGR{l} restriction R_J", sp(nC, rj[2]) + n * xs + (3 if scaled else 1) * nC * s))
             if l + 1 < len(mgr):
                 if not mgr_level(l + 1):
                     return False
             else:
                 amg_cycle(1, -1, amg, 0, "AMG")
             pj = solver.export_sizes(0, l, 7)[2]
-            out.append((f"MGR{l} interpolation P_J", sp(n, pj) + nC * s + 2 * n * vs))
+            out.append((f"MGR{l} interpolation P_J", sp(n, pj) + nC * s + n * xs + n * vs))
             return True
         fr = lo.get("frelax", "jacobi")
         if fr == "ilu0":
