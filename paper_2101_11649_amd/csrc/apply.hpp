@@ -26,6 +26,7 @@ struct SpOp {
     const int* ci = nullptr;
     const T* v = nullptr;
     const int* blk = nullptr;  // row-block boundaries (nblk + 1)
+    const int* bpos = nullptr; // their entry offsets
     int nblk = 0;
     const int* eci = nullptr;  // sliced ELL copy, if any (see DCsr)
     const int* esw = nullptr;
@@ -35,7 +36,7 @@ struct SpOp {
 
 // number of row blocks of an operator with nnz entries, and their boundaries
 int rowblock_count(int nr, long nnz);
-void rowblocks(int nr, long nnz, const int* rp, int* blk, hipStream_t s);
+void rowblocks(int nr, long nnz, const int* rp, int* blk, int* bpos, hipStream_t s);
 
 template <typename T>
 inline SpOp<T> view(const DCsr& A);
@@ -110,7 +111,8 @@ inline void ensure_rowblocks(const DCsr& A) {
     DCsr& M = const_cast<DCsr&>(A);
     M.nblk = rowblock_count(M.nr, M.nnz);
     M.blk.alloc((size_t)M.nblk + 1, M.rp.s);
-    rowblocks(M.nr, M.nnz, M.rp.p, M.blk.p, M.rp.s);
+    M.bpos.alloc((size_t)M.nblk + 1, M.rp.s);
+    rowblocks(M.nr, M.nnz, M.rp.p, M.blk.p, M.bpos.p, M.rp.s);
 }
 
 template <>
@@ -118,7 +120,7 @@ inline SpOp<double> view<double>(const DCsr& A) {
     ensure_rowblocks(A);
     SpOp<double> o;
     o.nr = A.nr; o.nc = A.nc; o.nnz = A.nnz; o.rp = A.rp.p; o.ci = A.ci.p; o.v = A.v.p;
-    o.blk = A.blk.p; o.nblk = A.nblk;
+    o.blk = A.blk.p; o.bpos = A.bpos.p; o.nblk = A.nblk;
     ensure_ell(A, false);
     if (A.ev.p) { o.eci = A.eci.p; o.esw = A.esw.p; o.ev = A.ev.p; o.ew = A.ew; }
     return o;
@@ -128,7 +130,7 @@ inline SpOp<float> view<float>(const DCsr& A) {
     ensure_rowblocks(A);
     SpOp<float> o;
     o.nr = A.nr; o.nc = A.nc; o.nnz = A.nnz; o.rp = A.rp.p; o.ci = A.ci.p; o.v = A.vf.p;
-    o.blk = A.blk.p; o.nblk = A.nblk;
+    o.blk = A.blk.p; o.bpos = A.bpos.p; o.nblk = A.nblk;
     ensure_ell(A, true);
     if (A.evf.p) { o.eci = A.eci.p; o.esw = A.esw.p; o.ev = A.evf.p; o.ew = A.ew; }
     return o;

@@ -162,6 +162,7 @@ struct DCsr {
     DArr<double> v;
     DArr<float> vf;
     DArr<int> blk;   // row-block boundaries of the CSR-stream SpMV
+    DArr<int> bpos;  // the entry offset of each boundary (rp[blk[b]])
     int nblk = 0;
     // sliced ELL copy for SpMVs on operators with short, fairly uniform rows:
     // slices of one workgroup's rows, each slot-major with the slice's own
@@ -183,6 +184,7 @@ struct DCsr {
         v.alloc((size_t)(nz > 0 ? nz : 1), s);
         vf.reset();
         blk.reset();
+        bpos.reset();
         nblk = 0;
         eci.reset();
         esw.reset();

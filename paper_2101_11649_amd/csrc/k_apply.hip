@@ -109,14 +109,16 @@ struct PreOpD {
 };
 
 template <typename MT, int TAG, class Op>
-__global__ __launch_bounds__(TPB) void k_spmv_stream(const int* __restrict__ blk, const int* __restrict__ rp,
-                                                     const int* __restrict__ ci, const MT* __restrict__ v, Op op) {
+__global__ __launch_bounds__(TPB) void k_spmv_stream(const int* __restrict__ blk, const int* __restrict__ bpos,
+                                                     const int* __restrict__ rp, const int* __restrict__ ci,
+                                                     const MT* __restrict__ v, Op op) {
     __shared__ MT sh[SPMV_LDS];
     __shared__ MT red[TPB / WAVE];
     const int tid = threadIdx.x;
+    // the block's rows and entries, four independent loads
     const int r0 = blk[blockIdx.x], r1 = blk[blockIdx.x + 1];
+    const int p0 = bpos[blockIdx.x], p1 = bpos[blockIdx.x + 1];
     if (r0 >= r1) return;
-    const int p0 = rp[r0], p1 = rp[r1];
     const int nnz = p1 - p0;
     if (nnz <= SPMV_LDS) {
         // the epilogue inputs of the (first) row this thread finishes, loaded
@@ -198,10 +200,15 @@ __global__ __launch_bounds__(TPB) void k_spmv_stream(const int* __restrict__ blk
     }
 }
 
-__global__ void k_rowblocks(int nr, int nb, const int* __restrict__ rp, int* __restrict__ blk) {
+__global__ void k_rowblocks(int nr, int nb, const int* __restrict__ rp, int* __restrict__ blk,
+                            int* __restrict__ bpos) {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b > nb) return;
-    if (b == nb) { blk[b] = nr; return; }
+    if (b == nb) {
+        blk[b] = nr;
+        bpos[b] = rp[nr];
+        return;
+    }
     long target = (long)b * SPMV_CHUNK;
     int lo = 0, hi = nr;  // first row r in [0, nr] with cost(r) >= target
     while (lo < hi) {
@@ -210,6 +217,7 @@ __global__ void k_rowblocks(int nr, int nb, const int* __restrict__ rp, int* __r
         else hi = mid;
     }
     blk[b] = lo;
+    bpos[b] = rp[lo];
 }
 
 // Block-CSR SpMV, b x b row-major blocks, G lanes per block row:
@@ -852,7 +860,7 @@ static void launch_rows(const SpOp<MT>& A, const Op& op, hipStream_t s) {
     if (A.ew > 0 && A.eci && A.ev && A.esw)
         k_spmv_ell<MT, TAG, ELL_MAX_W, Op><<<nblk(A.nr), TPB, 0, s>>>(A.nr, A.ew, A.esw, A.eci, A.ev, op);
     else
-        k_spmv_stream<MT, TAG><<<A.nblk, TPB, 0, s>>>(A.blk, A.rp, A.ci, A.v, op);
+        k_spmv_stream<MT, TAG><<<A.nblk, TPB, 0, s>>>(A.blk, A.bpos, A.rp, A.ci, A.v, op);
 }
 
 int rowblock_count(int nr, long nnz) {
@@ -860,9 +868,9 @@ int rowblock_count(int nr, long nnz) {
     return cost > 0 ? (int)((cost + SPMV_CHUNK - 1) / SPMV_CHUNK) : 1;
 }
 
-void rowblocks(int nr, long nnz, const int* rp, int* blk, hipStream_t s) {
+void rowblocks(int nr, long nnz, const int* rp, int* blk, int* bpos, hipStream_t s) {
     int nb = rowblock_count(nr, nnz);
-    k_rowblocks<<<nblk(nb + 1), TPB, 0, s>>>(nr, nb, rp, blk);
+    k_rowblocks<<<nblk(nb + 1), TPB, 0, s>>>(nr, nb, rp, blk, bpos);
     MGR_LAUNCH_CHECK();
 }
 
