@@ -1184,7 +1184,8 @@ __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restri
                                                      const int* __restrict__ dci, const double* __restrict__ dv,
                                                      const int* __restrict__ crp, int* __restrict__ cci,
                                                      double* __restrict__ cv, int* __restrict__ cnt,
-                                                     int* __restrict__ flag, int lo, int hi, double sgn) {
+                                                     int* __restrict__ flag, int lo, int hi, double sgn,
+                                                     const int* __restrict__ brep) {
     constexpr int NG = TPB / G;
     constexpr int PER = CAP / G;
     __shared__ int keys[NG][CAP];
@@ -1232,10 +1233,17 @@ __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restri
         int kb0 = 0, kb1 = 0;
         double ka = 0.0;
         if (a0 + base + g.gl < a1) {
-            int k = aci[a0 + base + g.gl];
-            kb0 = brp[k];
-            kb1 = brp[k + 1];
-            if (FILL) ka = av[a0 + base + g.gl];
+            const int q = a0 + base + g.gl;
+            int k = aci[q];
+            // symbolic pass with brep: rows of B with equal brep have equal
+            // patterns, so an entry whose predecessor in A's row selects such
+            // a row adds no column (an empty row of B instead)
+            const bool same = !FILL && brep && q > a0 && brep[aci[q - 1]] == brep[k];
+            if (!same) {
+                kb0 = brp[k];
+                kb1 = brp[k + 1];
+            }
+            if (FILL) ka = av[q];
         }
         const int lim = min(G, wl - base);   // the same for the whole wavefront
         // The first G entries of the rows of B that the next D entries of A
@@ -3397,7 +3405,7 @@ static int hash_group(const DCsr& B, int cap) {
 template <bool FILL, bool ADD>
 static void spgemm_hash_launch(const DCsr& A, const DCsr& B, const DCsr* D, int cap, const int* crp, int* cci,
                                double* cv, int* cnt, int* flag, hipStream_t s, int lo = -1, int hi = INT_MAX,
-                               double sgn = 1.0) {
+                               double sgn = 1.0, const int* brep = nullptr) {
     const int* drp = ADD ? D->rp.p : nullptr;
     const int* dci = ADD ? D->ci.p : nullptr;
     const double* dvv = ADD ? D->v.p : nullptr;
@@ -3405,7 +3413,7 @@ static void spgemm_hash_launch(const DCsr& A, const DCsr& B, const DCsr* D, int 
 #define MGR_HASH(GG, CC)                                                                                          \
     k_spgemm_hash<GG, CC, FILL, ADD><<<grid_for(A.nr, GG), TPB, 0, s>>>(A.nr, A.rp.p, A.ci.p, A.v.p, B.rp.p,     \
                                                                        B.ci.p, B.v.p, drp, dci, dvv, crp, cci, cv, \
-                                                                       cnt, flag, lo, hi, sgn)
+                                                                       cnt, flag, lo, hi, sgn, brep)
     switch (cap) {
         case 32: if (G <= 4) MGR_HASH(4, 32); else if (G == 8) MGR_HASH(8, 32); else if (G == 16) MGR_HASH(16, 32); else MGR_HASH(32, 32); break;
         case 64: if (G <= 4) MGR_HASH(4, 64); else if (G == 8) MGR_HASH(8, 64); else if (G == 16) MGR_HASH(16, 64); else MGR_HASH(32, 64); break;
@@ -3537,7 +3545,8 @@ bool spgemm_add_fusable(const DCsr& A, const DCsr& B, const DCsr& D) {
            (long)A.max_row * B.max_row + D.max_row <= 256;
 }
 
-void spgemm_add_count(const DCsr& A, const DCsr& B, const DCsr& D, int* cnt, int* flag, hipStream_t s, bool loose) {
+void spgemm_add_count(const DCsr& A, const DCsr& B, const DCsr& D, int* cnt, int* flag, hipStream_t s, bool loose,
+                      const int* brep) {
     if (!spgemm_add_fusable(A, B, D)) throw Error(-1, "spgemm_add: rows may exceed 256 entries");
     if (A.nr <= 0) return;
     const long bound = (long)A.max_row * B.max_row + D.max_row;
@@ -3547,10 +3556,11 @@ void spgemm_add_count(const DCsr& A, const DCsr& B, const DCsr& D, int* cnt, int
         const int lc = std::max(SPGEMM_ADD_LOOSE_CAP, pow2_at_least(2L * D.max_row, 32));
         cap = std::min(cap, lc);
     }
-    if (lanes_ok(A, B))
+    if (lanes_ok(A, B) && !brep)
         spgemm_lanes_count<true>(A, B, &D, cap, cnt, flag, s);
     else
-        spgemm_hash_launch<false, true>(A, B, &D, cap, nullptr, nullptr, nullptr, cnt, flag, s);
+        spgemm_hash_launch<false, true>(A, B, &D, cap, nullptr, nullptr, nullptr, cnt, flag, s, -1, INT_MAX, 1.0,
+                                        brep);
 }
 
 void spgemm_add_fill(const DCsr& A, const DCsr& B, const DCsr& D, DCsr& C, int* flag, hipStream_t s) {

@@ -184,8 +184,10 @@ static void spgemm_recount(Spgemm& j, hipStream_t s) {
     C.v.alloc((size_t)(C.nnz > 0 ? C.nnz : 1), s);
 }
 
-// C = D + A B in one hashed product (requires spgemm_add_fusable(A, B, D)).
-static void spgemm_add_begin(Spgemm& j, const DCsr& A, const DCsr& B, const DCsr& D, DCsr& C, Slots& S) {
+// C = D + A B in one hashed product (requires spgemm_add_fusable(A, B, D));
+// brep as for spgemm_add_count.
+static void spgemm_add_begin(Spgemm& j, const DCsr& A, const DCsr& B, const DCsr& D, DCsr& C, Slots& S,
+                             const int* brep = nullptr) {
     if (A.nc != B.nr) throw Error(MGR_ERR_ARG, "spgemm: inner dimensions differ");
     j.A = &A;
     j.B = &B;
@@ -193,7 +195,7 @@ static void spgemm_add_begin(Spgemm& j, const DCsr& A, const DCsr& B, const DCsr
     j.C = &C;
     j.cnt.alloc((size_t)A.nr + 1, S.s);
     j.lr = S.take(1);
-    spgemm_add_count(A, B, D, j.cnt.p, reinterpret_cast<int*>(j.lr), S.s, true);
+    spgemm_add_count(A, B, D, j.cnt.p, reinterpret_cast<int*>(j.lr), S.s, true, brep);
     j.pend = csr_begin(C, A.nr, B.nc, j.cnt.p, S);
 }
 
@@ -1467,7 +1469,9 @@ static DCsr mgr_setup_level(Ctx& c, MgrLevel& l, const DCsr* A, const int* field
     const bool fuse_add = spgemm_add_fusable(l.ACF, l.PF, l.ACC);
     DCsr T1, Ac;
     Spgemm j1;
-    if (fuse_add) spgemm_add_begin(j1, l.ACF, l.PF, l.ACC, Ac, S);
+    // the rows of P_F of one F-relaxation block share their pattern (a failed
+    // block has stopped the setup at the block extraction's sync)
+    if (fuse_add) spgemm_add_begin(j1, l.ACF, l.PF, l.ACC, Ac, S, bnum.p);
     else spgemm_begin(j1, l.ACF, l.PF, T1, S);
     // fused one-sweep apply: r_c = [-omega A_CF M | I] v ; z = [P_F | omega M] [e_c ; v]
     DArr<int> lenR, lenP;
