@@ -1228,18 +1228,24 @@ __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restri
         }
         return;
     }
+    // numeric pass with brep: the slot this lane's first column went to in
+    // the previous entry of A (the same column when both select rows of B of
+    // one pattern)
+    int hprev = -1;
     for (int base = 0; base < wl; base += G) {
         // lane t holds entry base + t of the row of A
         int kb0 = 0, kb1 = 0;
         double ka = 0.0;
+        bool same = false;
         if (a0 + base + g.gl < a1) {
             const int q = a0 + base + g.gl;
             int k = aci[q];
-            // symbolic pass with brep: rows of B with equal brep have equal
-            // patterns, so an entry whose predecessor in A's row selects such
-            // a row adds no column (an empty row of B instead)
-            const bool same = !FILL && brep && q > a0 && brep[aci[q - 1]] == brep[k];
-            if (!same) {
+            // with brep, rows of B with equal brep have equal patterns: an
+            // entry whose predecessor in A's row selects such a row adds no
+            // column (the symbolic pass takes an empty row of B instead; the
+            // numeric pass finds its slots where the predecessor put them)
+            same = brep && q > a0 && brep[aci[q - 1]] == brep[k];
+            if (FILL || !same) {
                 kb0 = brp[k];
                 kb1 = brp[k + 1];
             }
@@ -1268,20 +1274,29 @@ __global__ __launch_bounds__(TPB) void k_spgemm_hash(int nr, const int* __restri
                 if (t0 + d >= lim) break;
                 const int b0 = __shfl(kb0, g.gbase + t0 + d, WAVE), b1 = __shfl(kb1, g.gbase + t0 + d, WAVE);
                 const double a = __shfl(ka, g.gbase + t0 + d, WAVE);
+                const bool sd = FILL && brep && __shfl((int)same, g.gbase + t0 + d, WAVE) != 0;
                 for (int q = b0 + g.gl; q < b1; q += G) {
-                    const int j = (q == b0 + g.gl) ? hj[d] : bci[q];
-                    const double prod = FILL ? a * ((q == b0 + g.gl) ? hv[d] : bv[q]) : 0.0;
-                    // multiplicative hash: the top log2(CAP) bits of j * 2654435761
-                    int h = (int)(((unsigned)j * 2654435761u) >> (32 - log2_pow2(CAP)));
-                    int probes = 0;
-                    for (;;) {
-                        int old = atomicCAS(&K[h], -1, j);
-                        if (old == -1 || old == j) break;
-                        h = (h + 1) & (CAP - 1);
-                        if (++probes == CAP) { atomicMax(flag, FILL ? 1 : 2); h = -1; break; }
+                    const bool first = q == b0 + g.gl;
+                    const int j = first ? hj[d] : bci[q];
+                    const double prod = FILL ? a * (first ? hv[d] : bv[q]) : 0.0;
+                    int h;
+                    if (first && sd && hprev >= 0) {
+                        h = hprev;
+                    } else {
+                        // multiplicative hash: the top log2(CAP) bits of j * 2654435761
+                        h = (int)(((unsigned)j * 2654435761u) >> (32 - log2_pow2(CAP)));
+                        int probes = 0;
+                        for (;;) {
+                            int old = atomicCAS(&K[h], -1, j);
+                            if (old == -1 || old == j) break;
+                            h = (h + 1) & (CAP - 1);
+                            if (++probes == CAP) { atomicMax(flag, FILL ? 1 : 2); h = -1; break; }
+                        }
                     }
                     if (FILL && h >= 0) Vs[h] = Vs[h] + prod;
+                    if (first) hprev = h;
                 }
+                if (FILL && brep && b0 + g.gl >= b1) hprev = -1;
             }
         }
     }
@@ -3491,15 +3506,17 @@ void bdiag_right_fill(const DCsr& A, const DCsr& M, DCsr& C, int* flag, hipStrea
 // second launch costs more than it saves).
 template <bool ADD>
 static void spgemm_fill_split(const DCsr& A, const DCsr& B, const DCsr* D, DCsr& C, int cap, int* flag,
-                              hipStream_t s, double sgn = 1.0) {
+                              hipStream_t s, double sgn = 1.0, const int* brep = nullptr) {
     const long lds = (long)(TPB / hash_group(B, cap)) * cap * 12;
     const bool short_rows = C.nr > 0 && 6 * C.nnz <= (long)C.nr * cap;   // average row <= cap / 6
     if (cap >= 64 && lds >= 40960 && A.nr >= 262144 && short_rows) {
-        spgemm_hash_launch<true, ADD>(A, B, D, cap / 2, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s, -1, cap / 4, sgn);
+        spgemm_hash_launch<true, ADD>(A, B, D, cap / 2, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s, -1, cap / 4, sgn,
+                                      brep);
         spgemm_hash_launch<true, ADD>(A, B, D, cap, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s, cap / 4, INT_MAX,
-                                      sgn);
+                                      sgn, brep);
     } else {
-        spgemm_hash_launch<true, ADD>(A, B, D, cap, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s, -1, INT_MAX, sgn);
+        spgemm_hash_launch<true, ADD>(A, B, D, cap, C.rp.p, C.ci.p, C.v.p, nullptr, flag, s, -1, INT_MAX, sgn,
+                                      brep);
     }
 }
 
@@ -3563,10 +3580,11 @@ void spgemm_add_count(const DCsr& A, const DCsr& B, const DCsr& D, int* cnt, int
                                         brep);
 }
 
-void spgemm_add_fill(const DCsr& A, const DCsr& B, const DCsr& D, DCsr& C, int* flag, hipStream_t s) {
+void spgemm_add_fill(const DCsr& A, const DCsr& B, const DCsr& D, DCsr& C, int* flag, hipStream_t s,
+                     const int* brep) {
     if (A.nr <= 0) return;
     const int cap = pow2_at_least(2L * C.max_row, 32);
-    spgemm_fill_split<true>(A, B, &D, C, cap, flag, s);
+    spgemm_fill_split<true>(A, B, &D, C, cap, flag, s, 1.0, brep);
 }
 
 static int add_group(const DCsr& A, const DCsr& B) {

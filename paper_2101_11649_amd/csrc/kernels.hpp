@@ -86,10 +86,12 @@ constexpr int SPGEMM_ADD_LOOSE_CAP = 64;
 // With brep (one int per row of B), rows of B with equal brep must have equal
 // patterns (the rows of P_F = -M A_FC of one F-relaxation block): the count
 // then inserts the pattern of a run of such rows selected by consecutive
-// entries of a row of A once.
+// entries of a row of A once, and the numeric pass finds such a row's slots
+// where the previous entry put them.
 void spgemm_add_count(const DCsr& A, const DCsr& B, const DCsr& D, int* cnt, int* flag, hipStream_t s,
                       bool loose = false, const int* brep = nullptr);
-void spgemm_add_fill(const DCsr& A, const DCsr& B, const DCsr& D, DCsr& C, int* flag, hipStream_t s);
+void spgemm_add_fill(const DCsr& A, const DCsr& B, const DCsr& D, DCsr& C, int* flag, hipStream_t s,
+                     const int* brep = nullptr);
 // Products with the block-diagonal F-relaxation operator M (blocks of at most
 // four rows over [bstart[t], bstart[t+1]), each row storing its block's
 // columns; a failed larger block one diagonal entry per row), with the

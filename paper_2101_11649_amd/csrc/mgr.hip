@@ -141,6 +141,7 @@ struct Spgemm {
     DCsr* C = nullptr;
     int bdiag = 0;            // symbolic pass by the block kernels: 1 for M B, 2 for A M
     bool neg = false;         // C = -A B
+    const int* brep = nullptr;   // rows of B with equal brep share a pattern (C = D + A B)
     DArr<int> cnt;
     long long* lr = nullptr;
     Pend pend;
@@ -195,6 +196,7 @@ static void spgemm_add_begin(Spgemm& j, const DCsr& A, const DCsr& B, const DCsr
     j.C = &C;
     j.cnt.alloc((size_t)A.nr + 1, S.s);
     j.lr = S.take(1);
+    j.brep = brep;
     spgemm_add_count(A, B, D, j.cnt.p, reinterpret_cast<int*>(j.lr), S.s, true, brep);
     j.pend = csr_begin(C, A.nr, B.nc, j.cnt.p, S);
 }
@@ -239,13 +241,14 @@ struct FillPass {
     DCsr* C = nullptr;
     int bdiag = 0;
     bool neg = false;
+    const int* brep = nullptr;
     void run(int* flag, hipStream_t st) const {
         if (bdiag == 2) bdiag_right_fill(*A, *B, *C, flag, st);
-        else if (D) spgemm_add_fill(*A, *B, *D, *C, flag, st);
+        else if (D) spgemm_add_fill(*A, *B, *D, *C, flag, st, brep);
         else spgemm_fill(*A, *B, A->max_row, *C, flag, st, neg);
     }
 };
-static FillPass fill_pass(const Spgemm& j) { return FillPass{j.A, j.B, j.D, j.C, j.bdiag, j.neg}; }
+static FillPass fill_pass(const Spgemm& j) { return FillPass{j.A, j.B, j.D, j.C, j.bdiag, j.neg, j.brep}; }
 
 static void spgemm_fillpass(const Spgemm& j, Slots& S, hipStream_t st) { fill_pass(j).run(S.flag(), st); }
 
