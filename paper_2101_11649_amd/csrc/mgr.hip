@@ -673,8 +673,9 @@ static void amg_setup(Amg& H, DCsr A0, const int* label0, const mgr_amg_opts& o,
         Pend pp;
         long long* sc = nullptr;
         // seven rounds usually decide every point: a first batch of eight rarely
-        // needs a second (each batch costs a sync and a speculative P count)
-        int batch = 8;
+        // needs a second (each batch costs a sync and a speculative P count);
+        // levels of at most PMIS_SMALL_N points take about three, so four
+        int batch = n <= PMIS_SMALL_N ? 4 : 8;
         // strong rows hold about half of a row of A
         const int avg_row = (int)((A.nnz + 2L * n - 1) / (2L * n));
         for (int total = 0;; total += batch, batch = 4) {
