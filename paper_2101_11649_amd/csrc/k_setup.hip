@@ -191,6 +191,24 @@ __global__ void k_to_float(const double* __restrict__ s, float* __restrict__ d, 
     if (i < n) d[i] = (float)s[i];
 }
 
+// Several arrays converted by one launch: segment q owns the blocks from
+// boff[q] on, each block TPB * F32_PER consecutive elements of it.
+constexpr int F32_PER = 4;
+__global__ __launch_bounds__(TPB) void k_to_float_batch(F32Segs sg) {
+    const int b = blockIdx.x;
+    int q = 0;
+    while (q + 1 < sg.k && sg.boff[q + 1] <= b) ++q;
+    const double* __restrict__ src = sg.src[q];
+    float* __restrict__ dst = sg.dst[q];
+    const long n = sg.n[q];
+    const long base = (long)(b - sg.boff[q]) * TPB * F32_PER + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < F32_PER; ++j) {
+        const long i = base + (long)j * TPB;
+        if (i < n) dst[i] = (float)src[i];
+    }
+}
+
 __global__ void k_negate(double* v, long n) {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) v[i] = -v[i];
@@ -3207,6 +3225,26 @@ void fill_int(int* p, int v, long n, hipStream_t s) {
 void to_float(const double* src, float* dst, long n, hipStream_t s) {
     if (n <= 0) return;
     k_to_float<<<nblk(n), TPB, 0, s>>>(src, dst, n);
+    MGR_LAUNCH_CHECK();
+}
+
+void to_float_batch(int k, const double* const* src, float* const* dst, const long* n, hipStream_t s) {
+    if (k <= 0) return;
+    if (k > F32_SEGS) throw Error(MGR_ERR_ARG, "internal: too many FP32 conversion segments");
+    F32Segs sg{};
+    sg.k = k;
+    long blocks = 0;
+    for (int q = 0; q < k; ++q) {
+        sg.src[q] = src[q];
+        sg.dst[q] = dst[q];
+        sg.n[q] = n[q];
+        sg.boff[q] = (int)blocks;
+        blocks += (n[q] + (long)TPB * F32_PER - 1) / ((long)TPB * F32_PER);
+    }
+    sg.boff[k] = (int)blocks;
+    if (blocks <= 0) return;
+    if (blocks > INT_MAX) throw Error(MGR_ERR_UNSUPPORTED, "FP32 conversion too large");
+    k_to_float_batch<<<(unsigned)blocks, TPB, 0, s>>>(sg);
     MGR_LAUNCH_CHECK();
 }
 

@@ -206,6 +206,17 @@ void pj_fill(int n, int nC, const int* isF, const int* lmap, const DCsr& Y, doub
              double mscale, const int* fmap, DCsr& P, hipStream_t s);
 
 void to_float(const double* src, float* dst, long n, hipStream_t s);
+// k (at most F32_SEGS) conversions dst[q][i] = (float)src[q][i], i < n[q], in
+// one launch (segments with n[q] <= 0 take no blocks)
+constexpr int F32_SEGS = 32;
+struct F32Segs {
+    const double* src[F32_SEGS];
+    float* dst[F32_SEGS];
+    long n[F32_SEGS];
+    int boff[F32_SEGS + 1];
+    int k;
+};
+void to_float_batch(int k, const double* const* src, float* const* dst, const long* n, hipStream_t s);
 void fill_int(int* p, int v, long n, hipStream_t s);
 void fill_bytes(unsigned char* p, unsigned char v, long n, hipStream_t s);
 

@@ -327,11 +327,34 @@ static void make_float(DCsr& A, hipStream_t s) {
     to_float(A.v.p, A.vf.p, A.nnz, s);
 }
 
-// The same, converted on stream run (the array taken on stream s, which owns it).
-static void make_float_on(DCsr& A, hipStream_t s, hipStream_t run) {
+// FP32 conversions gathered and issued F32_SEGS arrays per launch (a
+// hierarchy's small operators would each cost a dependent launch otherwise);
+// the destinations are taken on the owning stream, flush converts on `run`.
+struct F32Batch {
+    std::vector<const double*> src;
+    std::vector<float*> dst;
+    std::vector<long> n;
+    void add(const double* a, float* b, long k) {
+        if (k <= 0) return;
+        src.push_back(a);
+        dst.push_back(b);
+        n.push_back(k);
+    }
+    void flush(hipStream_t run) {
+        for (size_t i = 0; i < src.size(); i += F32_SEGS) {
+            const int k = (int)std::min(src.size() - i, (size_t)F32_SEGS);
+            to_float_batch(k, src.data() + i, dst.data() + i, n.data() + i, run);
+        }
+        src.clear();
+        dst.clear();
+        n.clear();
+    }
+};
+
+static void make_float_on(DCsr& A, hipStream_t s, F32Batch& fb) {
     if (A.vf.p || A.nr == 0) return;
     A.vf.alloc((size_t)(A.nnz > 0 ? A.nnz : 1), s);
-    to_float(A.v.p, A.vf.p, A.nnz, run);
+    fb.add(A.v.p, A.vf.p, A.nnz);
 }
 
 // ====================================================================== AMG
@@ -834,38 +857,37 @@ static void amg_refresh(Amg& H, DCsr A0, Slots& S) {
 
 // FP32 copies of the hierarchy: arrays taken on stream s, converted on run
 // (s when null)
-static void amg_make_float(Amg& H, hipStream_t s, hipStream_t run = nullptr) {
+static void amg_make_float(Amg& H, hipStream_t s, F32Batch& fb) {
     if (H.have_float) return;
-    if (!run) run = s;
     for (size_t l = 0; l < H.lv.size(); ++l) {
         AmgLevel& L = H.lv[l];
         if (L.composed) {
-            make_float_on(L.G, s, run);
-            make_float_on(L.WQ, s, run);
+            make_float_on(L.G, s, fb);
+            make_float_on(L.WQ, s, fb);
             if (H.have_trans) {
-                make_float_on(L.Qt, s, run);
-                make_float_on(L.WGt, s, run);
+                make_float_on(L.Qt, s, fb);
+                make_float_on(L.WGt, s, fb);
             }
         } else {
-            make_float_on(L.A, s, run);
+            make_float_on(L.A, s, fb);
         }
         if (l + 1 < H.lv.size() && !L.composed) {
-            make_float_on(L.P, s, run);
-            make_float_on(L.R, s, run);
+            make_float_on(L.P, s, fb);
+            make_float_on(L.R, s, fb);
             L.dinvf.alloc((size_t)L.n, s);
-            to_float(L.dinv.p, L.dinvf.p, L.n, run);
+            fb.add(L.dinv.p, L.dinvf.p, L.n);
             if (L.dT.p) {
                 const long per = (long)H.chunk * L.nchp;
                 L.dTf.alloc((size_t)per, s);
-                to_float(L.dT.p, L.dTf.p, per, run);
+                fb.add(L.dT.p, L.dTf.p, per);
                 for (HgsTri* t : {&L.lo, &L.up, &L.loT, &L.upT}) {
                     if (!t->v.p) continue;
                     t->vf.alloc(t->v.n, s);
-                    to_float(t->v.p, t->vf.p, per * t->w, run);
+                    fb.add(t->v.p, t->vf.p, per * t->w);
                 }
             }
         }
-        if (H.have_trans && L.AT.nr && !L.composed) make_float_on(L.AT, s, run);
+        if (H.have_trans && L.AT.nr && !L.composed) make_float_on(L.AT, s, fb);
         L.rf.alloc((size_t)L.n + 1, s);
         L.tf.alloc((size_t)L.n + 1, s);
         L.sf.alloc((size_t)L.n + 1, s);
@@ -876,18 +898,18 @@ static void amg_make_float(Amg& H, hipStream_t s, hipStream_t run = nullptr) {
     }
     long nn = (long)H.nc * H.nc;
     H.cinvf.alloc((size_t)nn + 1, s);
-    to_float(H.cinv.p, H.cinvf.p, nn, run);
+    fb.add(H.cinv.p, H.cinvf.p, nn);
     if (H.have_trans) {
         H.cinvTf.alloc((size_t)nn + 1, s);
-        to_float(H.cinvT.p, H.cinvTf.p, nn, run);
+        fb.add(H.cinvT.p, H.cinvTf.p, nn);
     }
     if (H.tail >= 0) {
         const long tn = (long)H.lv[H.tail].n * H.lv[H.tail].n;
         H.tdf.alloc((size_t)tn + 1, s);
-        to_float(H.td.p, H.tdf.p, tn, run);
+        fb.add(H.td.p, H.tdf.p, tn);
         if (H.have_trans) {
             H.tdTf.alloc((size_t)tn + 1, s);
-            to_float(H.tdT.p, H.tdTf.p, tn, run);
+            fb.add(H.tdT.p, H.tdTf.p, tn);
         }
     }
     H.have_float = true;
@@ -1576,23 +1598,22 @@ static void mgr_level_make_trans(Ctx& c, MgrLevel& l) {
 }
 
 // the level's FP32 copies, converted on stream run (c.s when null)
-static void mgr_level_make_float(Ctx& c, MgrLevel& l, hipStream_t run = nullptr) {
+static void mgr_level_make_float(Ctx& c, MgrLevel& l, F32Batch& fb) {
     if (l.have_float) return;
     hipStream_t s = c.s;
-    if (!run) run = s;
     if (l.fused) {
-        make_float_on(l.RJ, s, run); make_float_on(l.PJ, s, run);
-        if (l.have_trans) { make_float_on(l.RJt, s, run); make_float_on(l.PJt, s, run); }
+        make_float_on(l.RJ, s, fb); make_float_on(l.PJ, s, fb);
+        if (l.have_trans) { make_float_on(l.RJt, s, fb); make_float_on(l.PJt, s, fb); }
     } else {
-        make_float_on(l.AFF, s, run); make_float_on(l.ACF, s, run);
-        make_float_on(l.PF, s, run); make_float_on(l.M, s, run);
-        if (l.RF.nr) make_float_on(l.RF, s, run);
-        if (l.iluL.nr) { make_float_on(l.iluL, s, run); make_float_on(l.iluU, s, run); }
-        if (l.have_trans && l.iluLt.nr) { make_float_on(l.iluLt, s, run); make_float_on(l.iluUt, s, run); }
+        make_float_on(l.AFF, s, fb); make_float_on(l.ACF, s, fb);
+        make_float_on(l.PF, s, fb); make_float_on(l.M, s, fb);
+        if (l.RF.nr) make_float_on(l.RF, s, fb);
+        if (l.iluL.nr) { make_float_on(l.iluL, s, fb); make_float_on(l.iluU, s, fb); }
+        if (l.have_trans && l.iluLt.nr) { make_float_on(l.iluLt, s, fb); make_float_on(l.iluUt, s, fb); }
         if (l.have_trans) {
-            make_float_on(l.AFFt, s, run); make_float_on(l.ACFt, s, run);
-            make_float_on(l.PFt, s, run); make_float_on(l.Mt, s, run);
-            if (l.RFt.nr) make_float_on(l.RFt, s, run);
+            make_float_on(l.AFFt, s, fb); make_float_on(l.ACFt, s, fb);
+            make_float_on(l.PFt, s, fb); make_float_on(l.Mt, s, fb);
+            if (l.RFt.nr) make_float_on(l.RFt, s, fb);
         }
         l.vFf.alloc((size_t)l.nF + 1, s); l.vCf.alloc((size_t)l.nC + 1, s);
         l.zFf.alloc((size_t)l.nF + 1, s); l.rFf.alloc((size_t)l.nF + 1, s); l.tFf.alloc((size_t)l.nF + 1, s);
@@ -1600,7 +1621,7 @@ static void mgr_level_make_float(Ctx& c, MgrLevel& l, hipStream_t run = nullptr)
     l.rcf.alloc((size_t)l.nC + 1, s);
     l.ecf.alloc((size_t)l.nC + 1, s);
     if (l.fused && &l == &c.L.front()) l.vinf.alloc((size_t)l.n + 1, s);
-    if (l.famg) amg_make_float(*l.famg, s, run);
+    if (l.famg) amg_make_float(*l.famg, s, fb);
     l.have_float = true;
 }
 
@@ -1771,8 +1792,10 @@ static void mgr_apply_top(Ctx& c, const double* v, double* z, bool tr) {
     }
     bool f32 = (c.o.apply_precision == 32);
     if (f32) {
-        for (auto& l : c.L) mgr_level_make_float(c, l);
-        amg_make_float(c.camg, c.s);
+        F32Batch fb;
+        for (auto& l : c.L) mgr_level_make_float(c, l, fb);
+        amg_make_float(c.camg, c.s, fb);
+        fb.flush(c.s);
     }
     if (c.L.empty()) {
         // no reduction level: the preconditioner is the AMG cycle on A itself
@@ -2364,8 +2387,10 @@ static void build_hierarchy(Ctx& c) {
     if (c.o.apply_precision == 32) {
         // the FP32 copies on the auxiliary stream, beside the sliced-ELL sizing
         aux_fork(c);
-        for (auto& l : c.L) mgr_level_make_float(c, l, c.aux);
-        amg_make_float(c.camg, s, c.aux);
+        F32Batch fb;
+        for (auto& l : c.L) mgr_level_make_float(c, l, fb);
+        amg_make_float(c.camg, s, fb);
+        fb.flush(c.aux);
     }
     prepare_ell(c);
     aux_join(c);
