@@ -116,6 +116,10 @@ __global__ void k_scan_apply(const int* __restrict__ in, int n, const long long*
 
 // Whole scan in one workgroup for n <= SCAN_SMALL: thread t owns up to 16
 // consecutive inputs; wavefront scans, then a scan of the 16 wave totals.
+// Chunks of more than one input are rounded up to a multiple of four and,
+// with both arrays 16-byte aligned, read and written four at a time: the
+// whole scan runs on one CU, whose memory pipeline otherwise takes every
+// input (64 bytes apart across a wavefront) as a load of its own.
 constexpr int SCAN_SMALL = 1024 * 16;
 
 __global__ __launch_bounds__(1024) void k_scan_small(const int* __restrict__ in, int n, int* __restrict__ out,
@@ -123,15 +127,34 @@ __global__ __launch_bounds__(1024) void k_scan_small(const int* __restrict__ in,
     __shared__ long long wsum[16];
     __shared__ int wmax[16];
     const int t = threadIdx.x, lane = t & (WAVE - 1), wid = t / WAVE;
-    const int chunk = (n + 1023) / 1024;
+    int chunk = (n + 1023) / 1024;
+    if (chunk > 1) chunk = (chunk + 3) & ~3;
+    const bool vec = (chunk & 3) == 0 && ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
     const int b0 = t * chunk;
     int v[16];
     long long sum = 0;
     int m = 0;
+    if (vec) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = b0 + 4 * q;
+            if (4 * q < chunk && i + 3 < n) {
+                const int4 x = *reinterpret_cast<const int4*>(in + i);
+                v[4 * q] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[4 * q + j] = (4 * q < chunk && i + j < n) ? in[i + j] : 0;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = b0 + u;
+            v[u] = (u < chunk && i < n) ? in[i] : 0;
+        }
+    }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-        int i = b0 + u;
-        v[u] = (u < chunk && i < n) ? in[i] : 0;
         sum += v[u];
         m = max(m, v[u]);
     }
@@ -157,11 +180,31 @@ __global__ __launch_bounds__(1024) void k_scan_small(const int* __restrict__ in,
     }
     __syncthreads();
     long long run = (wid ? wsum[wid - 1] : 0) + inc - sum;
+    if (vec) {
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-        int i = b0 + u;
-        if (u < chunk && i < n) out[i] = (int)run;
-        run += v[u];
+        for (int q = 0; q < 4; ++q) {
+            const int i = b0 + 4 * q;
+            int o[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                o[j] = (int)run;
+                run += v[4 * q + j];
+            }
+            if (4 * q < chunk && i + 3 < n) {
+                *reinterpret_cast<int4*>(out + i) = make_int4(o[0], o[1], o[2], o[3]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (4 * q < chunk && i + j < n) out[i + j] = o[j];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            int i = b0 + u;
+            if (u < chunk && i < n) out[i] = (int)run;
+            run += v[u];
+        }
     }
     if (t == 0) {
         long long total = wsum[15];
