@@ -20,6 +20,7 @@ constexpr int TPB = 256;
 constexpr int WAVE = 64;
 constexpr int SCAN_T = 256;
 constexpr int SCAN_I = 8;
+static_assert(SCAN_I % 4 == 0, "scan runs are moved in 16-byte vectors");
 constexpr int SCAN_B = SCAN_T * SCAN_I;
 
 inline int nblk(long n, int t = TPB) { return (int)((n + t - 1) / t); }
@@ -90,14 +91,28 @@ __global__ void k_scan_apply(const int* __restrict__ in, int n, const long long*
             if (slot) { slot[0] = total; slot[1] = tm; }
         }
     }
+    // each thread's SCAN_I consecutive inputs, in 16-byte loads where the
+    // arrays are aligned and the run is whole
     int base = blockIdx.x * SCAN_B + tid * SCAN_I;
+    const bool vec = base + SCAN_I - 1 < n &&
+                     ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
     int v[SCAN_I];
     int s = 0;
-    for (int t = 0; t < SCAN_I; ++t) {
-        int i = base + t;
-        v[t] = (i < n) ? in[i] : 0;
-        s += v[t];
+    if (vec) {
+#pragma unroll
+        for (int q = 0; q < SCAN_I / 4; ++q) {
+            const int4 x = *reinterpret_cast<const int4*>(in + base + 4 * q);
+            v[4 * q] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < SCAN_I; ++t) {
+            int i = base + t;
+            v[t] = (i < n) ? in[i] : 0;
+        }
     }
+#pragma unroll
+    for (int t = 0; t < SCAN_I; ++t) s += v[t];
     sh[tid] = s;
     __syncthreads();
     for (int off = 1; off < SCAN_T; off <<= 1) {
@@ -107,36 +122,53 @@ __global__ void k_scan_apply(const int* __restrict__ in, int n, const long long*
         __syncthreads();
     }
     long long off = boff + (tid ? sh[tid - 1] : 0);
-    for (int t = 0; t < SCAN_I; ++t) {
-        int i = base + t;
-        if (i < n) out[i] = (int)off;
-        off += v[t];
+    if (vec) {
+#pragma unroll
+        for (int q = 0; q < SCAN_I / 4; ++q) {
+            int o[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                o[j] = (int)off;
+                off += v[4 * q + j];
+            }
+            *reinterpret_cast<int4*>(out + base + 4 * q) = make_int4(o[0], o[1], o[2], o[3]);
+        }
+    } else {
+        for (int t = 0; t < SCAN_I; ++t) {
+            int i = base + t;
+            if (i < n) out[i] = (int)off;
+            off += v[t];
+        }
     }
 }
 
-// Whole scan in one workgroup for n <= SCAN_SMALL: thread t owns up to 16
-// consecutive inputs; wavefront scans, then a scan of the 16 wave totals.
-// Chunks of more than one input are rounded up to a multiple of four and,
-// with both arrays 16-byte aligned, read and written four at a time: the
-// whole scan runs on one CU, whose memory pipeline otherwise takes every
-// input (64 bytes apart across a wavefront) as a load of its own.
-constexpr int SCAN_SMALL = 1024 * 16;
+// Whole scan in one workgroup of SCAN_SMALL_T threads for n <= SCAN_SMALL:
+// thread t owns a run of up to SCAN_SMALL_CH consecutive inputs (rounded up
+// to a multiple of four and, with both arrays 16-byte aligned, read and
+// written four at a time); wavefront scans, then a scan of the wave totals.
+// A workgroup no larger than the setup's other kernels' gets a CU while an
+// auxiliary-stream kernel fills the GPU (a 1024-thread one waited up to
+// 0.23 ms for sixteen free wave slots on one CU).
+constexpr int SCAN_SMALL_T = 256;
+constexpr int SCAN_SMALL_CH = 64;
+constexpr int SCAN_SMALL = SCAN_SMALL_T * SCAN_SMALL_CH;
+constexpr int SCAN_SMALL_W = SCAN_SMALL_T / WAVE;
 
-__global__ __launch_bounds__(1024) void k_scan_small(const int* __restrict__ in, int n, int* __restrict__ out,
-                                                     long long* __restrict__ slot) {
-    __shared__ long long wsum[16];
-    __shared__ int wmax[16];
+__global__ __launch_bounds__(SCAN_SMALL_T) void k_scan_small(const int* __restrict__ in, int n,
+                                                             int* __restrict__ out, long long* __restrict__ slot) {
+    __shared__ long long wsum[SCAN_SMALL_W];
+    __shared__ int wmax[SCAN_SMALL_W];
     const int t = threadIdx.x, lane = t & (WAVE - 1), wid = t / WAVE;
-    int chunk = (n + 1023) / 1024;
+    int chunk = (n + SCAN_SMALL_T - 1) / SCAN_SMALL_T;
     if (chunk > 1) chunk = (chunk + 3) & ~3;
     const bool vec = (chunk & 3) == 0 && ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
     const int b0 = t * chunk;
-    int v[16];
+    int v[SCAN_SMALL_CH];
     long long sum = 0;
     int m = 0;
     if (vec) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < SCAN_SMALL_CH / 4; ++q) {
             const int i = b0 + 4 * q;
             if (4 * q < chunk && i + 3 < n) {
                 const int4 x = *reinterpret_cast<const int4*>(in + i);
@@ -148,13 +180,13 @@ __global__ __launch_bounds__(1024) void k_scan_small(const int* __restrict__ in,
         }
     } else {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
+        for (int u = 0; u < SCAN_SMALL_CH; ++u) {
             const int i = b0 + u;
             v[u] = (u < chunk && i < n) ? in[i] : 0;
         }
     }
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < SCAN_SMALL_CH; ++u) {
         sum += v[u];
         m = max(m, v[u]);
     }
@@ -167,22 +199,19 @@ __global__ __launch_bounds__(1024) void k_scan_small(const int* __restrict__ in,
     if (lane == WAVE - 1) wsum[wid] = inc;
     if (lane == 0) wmax[wid] = m;
     __syncthreads();
-    if (wid == 0) {
-        long long x = lane < 16 ? wsum[lane] : 0;
-        int y = lane < 16 ? wmax[lane] : 0;
-        for (int off = 1; off < 16; off <<= 1) {
-            long long o = __shfl_up(x, off, WAVE);
-            if (lane >= off) x += o;
-        }
-        for (int off = 8; off > 0; off >>= 1) y = max(y, __shfl_xor(y, off, WAVE));
-        if (lane < 16) wsum[lane] = x;
-        if (lane == 0) wmax[0] = y;
+    // the waves before this one, and (thread 0) the total and the maximum
+    long long before = 0, total = 0;
+    int mx = 0;
+#pragma unroll
+    for (int q = 0; q < SCAN_SMALL_W; ++q) {
+        if (q < wid) before += wsum[q];
+        total += wsum[q];
+        mx = max(mx, wmax[q]);
     }
-    __syncthreads();
-    long long run = (wid ? wsum[wid - 1] : 0) + inc - sum;
+    long long run = before + inc - sum;
     if (vec) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < SCAN_SMALL_CH / 4; ++q) {
             const int i = b0 + 4 * q;
             int o[4];
 #pragma unroll
@@ -200,16 +229,15 @@ __global__ __launch_bounds__(1024) void k_scan_small(const int* __restrict__ in,
         }
     } else {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
+        for (int u = 0; u < SCAN_SMALL_CH; ++u) {
             int i = b0 + u;
             if (u < chunk && i < n) out[i] = (int)run;
             run += v[u];
         }
     }
     if (t == 0) {
-        long long total = wsum[15];
         out[n] = (total > INT_MAX) ? INT_MAX : (int)total;
-        if (slot) { slot[0] = total; slot[1] = wmax[0]; }
+        if (slot) { slot[0] = total; slot[1] = mx; }
     }
 }
 
@@ -3219,7 +3247,7 @@ static int grid_for(long rows, int G) { return (int)((rows * G + TPB - 1) / TPB)
 
 void scan_async(const int* in, int* out, int n, long long* slot, hipStream_t s) {
     if (n <= SCAN_SMALL) {
-        k_scan_small<<<1, 1024, 0, s>>>(in, n < 0 ? 0 : n, out, slot);
+        k_scan_small<<<1, SCAN_SMALL_T, 0, s>>>(in, n < 0 ? 0 : n, out, slot);
         MGR_LAUNCH_CHECK();
         return;
     }
