@@ -2326,7 +2326,9 @@ static void setup(Ctx& c, const mgr_matrix* A, const int32_t* field, int32_t nle
 }
 
 // coarse-AMG level size from which the held-back auxiliary-stream work runs
-constexpr int AUX_DEFER_ROWS = 400000;
+// (one piece per level; on larger levels the pieces slow the level's own
+// bandwidth-bound kernels more than they gain)
+constexpr int AUX_DEFER_ROWS = 20000;
 
 // The MGR levels and the coarse AMG on the current input (c.A0, c.field0, c.lvl);
 // AMG hierarchies found in c.reuse_* are reused instead of coarsened again.
